@@ -1,0 +1,245 @@
+"""ctypes wrapper of the FP64 CPU oracle (``cutcell_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the package smoke check and by the CPU-baseline
+leg of the benchmark.  It never touches the HIP library.  Arrays are numpy float64 / int8 / int32 on
+the unpadded ``(nx, ny, nz)`` layout, k fastest.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "cutcell_oracle.c")
+LIB = os.path.join(HERE, "libcutcell_oracle.so")
+
+SOLID, OPEN, ABSORBED, ORPHAN = 0, 1, 2, 3
+NONE, ZP, XM, XP, YM, YP = 0, 1, 2, 3, 4, 5
+GROUND, PRED, MFACE = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: no FMA contraction, no fast-math, OpenMP."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                               "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("nsub", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double)]
+
+
+class _Phys(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("g", "rd", "cp", "p0", "theta0", "bvn", "u0", "v0")]
+
+
+_DP = C.POINTER(C.c_double)
+_I8 = C.POINTER(C.c_int8)
+_I32 = C.POINTER(C.c_int32)
+_I64 = C.POINTER(C.c_int64)
+
+
+class _Geom(C.Structure):
+    _fields_ = [("H", _DP), ("V", _DP), ("Ax", _DP), ("Ay", _DP), ("Az", _DP), ("hc", _DP),
+                ("gx", _DP), ("gy", _DP), ("nrm", _DP), ("cls", _I8), ("dir", _I8), ("vcls", _I8),
+                ("master", _I32), ("Vgroup", _DP)]
+
+
+class _State(C.Structure):
+    _fields_ = [(n, _DP) for n in ("rho", "rth", "mu", "mv", "mw")]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        L = C.CDLL(LIB)
+        G, P, GM, S = C.POINTER(_Grid), C.POINTER(_Phys), C.POINTER(_Geom), C.POINTER(_State)
+        L.or_base_state.argtypes = [P, C.c_int, C.c_double, _DP, _DP, _DP, _DP]
+        L.or_geometry.argtypes = [G, GM]
+        L.or_merge.argtypes = [G, GM, _I64]
+        L.or_merge_direction.argtypes = [C.c_double, C.c_double]
+        L.or_merge_direction.restype = C.c_int
+        L.or_init_state.argtypes = [G, P, GM, _DP, _DP, _DP, _DP, _DP, S, _I64]
+        L.or_diagnose.argtypes = [G, P, GM, _DP, _DP, _DP, S, _I64]
+        L.or_boundary_velocity.argtypes = [G, P, GM, _DP, _DP, _DP, S, _DP, _I8]
+        L.or_boundary_velocity.restype = C.c_int64
+        L.or_tendency.argtypes = [G, P, GM, _DP, _DP, _DP, S, S]
+        L.or_tendency_points.argtypes = [G, P, GM, _DP, _DP, _DP, S, _I64, C.c_int64, _DP]
+        L.or_rk_stage.argtypes = [G, P, GM, _DP, _DP, _DP, S, S, S, C.c_double, _I64]
+        L.or_reduce.argtypes = [G, P, GM, _DP, _DP, _DP, S, _DP]
+        L.or_run.argtypes = [G, P, GM, _DP, _DP, _DP, S, S, S, C.c_double, C.c_int, _I64]
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_set_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray, t=_DP):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(t)
+
+
+FIELDS = ("rho", "rth", "mu", "mv", "mw")
+
+
+class State:
+    """Five prognostic arrays: rho', (rho theta)' at cells, and the momentum (rho u, rho v, rho w) at
+    predicted lattice points (velocity itself at diagnosed points)."""
+
+    def __init__(self, shape, arrays: Optional[dict] = None):
+        self.a = {f: (np.ascontiguousarray(arrays[f], dtype=np.float64).copy() if arrays else
+                      np.zeros(shape)) for f in FIELDS}
+
+    def c(self) -> _State:
+        return _State(*[_p(self.a[f]) for f in FIELDS])
+
+    def copy(self) -> "State":
+        s = State(None, self.a)
+        return s
+
+    def __getitem__(self, k):
+        return self.a[k]
+
+
+def set_threads(n: int) -> int:
+    """Set the OpenMP thread count of the oracle; returns the count now in effect."""
+    return lib().or_set_threads(n)
+
+
+def merge_direction(gx: float, gy: float) -> int:
+    return lib().or_merge_direction(gx, gy)
+
+
+class Oracle:
+    """Oracle bound to one uniform-grid configuration (``workloads.Config``)."""
+
+    def __init__(self, cfg, H: Optional[np.ndarray] = None):
+        from paper_1509_02572_amd import workloads
+        self.cfg = cfg
+        self.H = np.ascontiguousarray(workloads.terrain(cfg) if H is None else H, dtype=np.float64)
+        nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
+        self.shape = (nx, ny, nz)
+        self.grid = _Grid(nx, ny, nz, cfg.nsub, cfg.dx, cfg.dy, cfg.dz)
+        self.phys = _Phys(cfg.g, cfg.rd, cfg.cp, cfg.p0, cfg.theta0, cfg.bvn, cfg.u0, cfg.v0)
+        self.rhob, self.rthb, self.pb, self.thb = (np.zeros(nz) for _ in range(4))
+        lib().or_base_state(C.byref(self.phys), nz, cfg.dz, _p(self.rhob), _p(self.rthb), _p(self.pb),
+                            _p(self.thb))
+        sh3, sh2 = self.shape, (nx, ny)
+        self.V, self.Ax, self.Ay, self.Az = (np.zeros(sh3) for _ in range(4))
+        self.hc, self.gx, self.gy = (np.zeros(sh2) for _ in range(3))
+        self.nrm = np.zeros((3, nx, ny))
+        self.cls = np.zeros(sh3, np.int8)
+        self.dir = np.zeros(sh3, np.int8)
+        self.vcls = np.zeros(sh3, np.int8)
+        self.master = np.zeros(sh3, np.int32)
+        self.Vgroup = np.zeros(sh3)
+        self.counts = np.zeros(2, np.int64)  # [unmergeable, no nearest plane]
+        self._geom = _Geom(_p(self.H), _p(self.V), _p(self.Ax), _p(self.Ay), _p(self.Az), _p(self.hc),
+                           _p(self.gx), _p(self.gy), _p(self.nrm), _p(self.cls, _I8), _p(self.dir, _I8),
+                           _p(self.vcls, _I8), _p(self.master, _I32), _p(self.Vgroup))
+        self.have_geometry = False
+        self.have_merge = False
+
+    # -- setup ---------------------------------------------------------------------------------
+    def geometry(self) -> "Oracle":
+        lib().or_geometry(C.byref(self.grid), C.byref(self._geom))
+        self.have_geometry = True
+        return self
+
+    def merge(self) -> "Oracle":
+        if not self.have_geometry:
+            self.geometry()
+        lib().or_merge(C.byref(self.grid), C.byref(self._geom), _p(self.counts, _I64))
+        self.have_merge = True
+        return self
+
+    def _ready(self):
+        if not self.have_merge:
+            self.merge()
+
+    def _args(self):
+        return (C.byref(self.grid), C.byref(self.phys), C.byref(self._geom), _p(self.rhob),
+                _p(self.rthb), _p(self.pb))
+
+    def init_state(self, noise: Optional[np.ndarray] = None) -> State:
+        self._ready()
+        q = State(self.shape)
+        nz_ptr = _p(np.ascontiguousarray(noise, dtype=np.float64)) if noise is not None else None
+        keep = noise
+        cq = q.c()
+        lib().or_init_state(C.byref(self.grid), C.byref(self.phys), C.byref(self._geom), _p(self.rhob),
+                            _p(self.rthb), _p(self.pb), _p(self.thb), nz_ptr, C.byref(cq),
+                            _p(self.counts, _I64))
+        del keep
+        return q
+
+    # -- hot path ------------------------------------------------------------------------------
+    def diagnose(self, q: State) -> State:
+        self._ready()
+        cq = q.c()
+        lib().or_diagnose(*self._args(), C.byref(cq), _p(self.counts, _I64))
+        return q
+
+    def boundary_velocity(self, q: State):
+        """(u_B[nx, ny, 3], no-plane flag[nx, ny]) for the current state."""
+        self._ready()
+        ub = np.zeros((self.cfg.nx, self.cfg.ny, 3))
+        fl = np.zeros((self.cfg.nx, self.cfg.ny), np.int8)
+        cq = q.c()
+        lib().or_boundary_velocity(*self._args(), C.byref(cq), _p(ub), _p(fl, _I8))
+        return ub, fl
+
+    def tendency(self, q: State) -> State:
+        self._ready()
+        dq = State(self.shape)
+        cq, cd = q.c(), dq.c()
+        lib().or_tendency(*self._args(), C.byref(cq), C.byref(cd))
+        return dq
+
+    def tendency_points(self, q: State, pts: np.ndarray) -> np.ndarray:
+        self._ready()
+        pts = np.ascontiguousarray(pts, dtype=np.int64)
+        out = np.zeros((len(pts), 5))
+        cq = q.c()
+        lib().or_tendency_points(*self._args(), C.byref(cq), _p(pts, _I64), len(pts), _p(out))
+        return out
+
+    def rk_stage(self, qn: State, qs: State, cdt: float) -> State:
+        self._ready()
+        out = State(self.shape)
+        a, b, c = qn.c(), qs.c(), out.c()
+        lib().or_rk_stage(*self._args(), C.byref(a), C.byref(b), C.byref(c), cdt, _p(self.counts, _I64))
+        return out
+
+    def step(self, q: State, dt: float) -> State:
+        q1 = self.rk_stage(q, q, dt / 3.0)
+        q2 = self.rk_stage(q, q1, dt / 2.0)
+        return self.rk_stage(q, q2, dt)
+
+    def run(self, q: State, dt: float, nsteps: int) -> State:
+        self._ready()
+        q = q.copy()
+        s1, s2 = State(self.shape), State(self.shape)
+        a, b, c = q.c(), s1.c(), s2.c()
+        lib().or_run(*self._args(), C.byref(a), C.byref(b), C.byref(c), dt, nsteps, _p(self.counts, _I64))
+        return q
+
+    def reduce(self, q: State) -> np.ndarray:
+        self._ready()
+        out = np.zeros(4)
+        cq = q.c()
+        lib().or_reduce(*self._args(), C.byref(cq), _p(out))
+        return out
