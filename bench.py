@@ -1,0 +1,165 @@
+"""Benchmark of the cut-cell Runge-Kutta stage on one MI355X.
+
+Workload: the 256 x 256 x 128 bell-hill domain (dx = dy = 100 m, dz = 50 m, h0 = 400 m, a = 2 km,
+theta' noise from seed 0, dt = 0.05 s).  A "step" is one three-stage Runge-Kutta step: per stage the
+fused tendency+update kernel and the velocity-diagnostic kernel.  The metric is interior
+cell-updates per second per stage (nx*ny*nz cells x 3 stages per step), for the FP32 perturbation
+form (headline) and the plain FP64 path (reported beside it).
+
+The roofline object describes the dominant kernel (the fused update): algorithmic bytes per launch
+(5 fields read and written per cell, plus q_n read in stages 2 and 3) over the launch duration
+measured with HIP events on the launch stream, against the 8 TB/s HBM peak.  Measured HBM traffic
+comes from a committed rocprofv3 counter summary when it was taken on the current kernel source.
+The CPU baseline times the FP64 oracle on this machine's host cores on one step of the workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f32|f64] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_bell256.json")
+STAGE_SRC = os.path.join(ROOT, "paper_1509_02572_amd", "csrc", "cc_stage.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(STAGE_SRC, "rb").read()).hexdigest()[:16]
+
+
+def run_gpu(cfg, prec: str, steps: int, warmup: int):
+    import torch
+    from paper_1509_02572_amd import cutcell as CC
+    from paper_1509_02572_amd import workloads as W
+
+    dom = CC.Domain(cfg, prec, "cuda:0")
+    q = dom.init_state(W.theta_noise(cfg))
+    a, b, c = q, dom.new_state(), dom.new_state()
+    dt = cfg.dt
+    esz = 8 if prec == "f64" else 4
+    ncell = cfg.nx * cfg.ny * cfg.nz
+    stream = torch.cuda.current_stream()
+
+    def step(a, b, c, ev=None):
+        # stage s: update kernel (timed with events when ev is given) + diagnostics
+        for s, (qs, qo, cdt) in enumerate(((a, b, dt / 3.0), (b, c, dt / 2.0), (c, b, dt))):
+            if ev is not None:
+                ev.append((torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True), s))
+                ev[-1][0].record(stream)
+            dom.rk_update(a, qs, qo, cdt)
+            if ev is not None:
+                ev[-1][1].record(stream)
+            dom.diagnose(qo)
+        return b, a, c
+
+    for _ in range(warmup):
+        a, b, c = step(a, b, c)
+    torch.cuda.synchronize()
+    ev = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a, b, c = step(a, b, c, ev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = dom.check()
+    if st[:5].any():
+        raise RuntimeError(f"device status counters set: {st}")
+    secs = t1 - t0
+    upd_ms = [e0.elapsed_time(e1) for e0, e1, _ in ev]
+    # algorithmic bytes: stage 1 reads q_s (= q_n) and writes q_out; stages 2-3 also read q_n
+    bytes_per = [ncell * 5 * esz * (2 if s == 0 else 3) for _, _, s in ev]
+    avg_ms = sum(upd_ms) / len(upd_ms)
+    avg_bytes = sum(bytes_per) / len(bytes_per)
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": f"k_stage_general<{'double' if prec == 'f64' else 'float'},0>",
+            "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(avg_bytes)}
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        ent = tr.get(prec)
+        if ent and tr.get("kernel_source_sha256_16") == kernel_hash():
+            roof["traffic"] = ent["hbm_bytes_per_launch"]
+    value = ncell * 3 * steps / secs
+    red = dom.reduce(a)
+    return {"value": value, "ms_per_step": secs / steps * 1e3, "roofline": roof,
+            "mass_total": float(red[2]), "mass_pert": float(red[0])}
+
+
+def run_cpu_baseline(cfg):
+    """FP64 oracle on the host cores: one full step (three stages) of the same workload."""
+    from oracle import oracle as O
+    from paper_1509_02572_amd import workloads as W
+    O.build(force=False)
+    o = O.Oracle(cfg).merge()
+    q = o.init_state(W.theta_noise(cfg))
+    threads = O.set_threads(0)
+    t0 = time.perf_counter()
+    o.run(q, cfg.dt, 1)
+    secs = time.perf_counter() - t0
+    n = cfg.nx * cfg.ny * cfg.nz
+    return {"value": n * 3 / secs, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 RK step (3 stages) of the {cfg.nx}x{cfg.ny}x{cfg.nz} workload, FP64, "
+                      f"{secs:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the cut-cell stage is measured on a single MI355X); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    from paper_1509_02572_amd import workloads as W
+    cfg = W.get("bell256")
+    other = "f64" if args.prec == "f32" else "f32"
+    log(f"bench: {cfg.name} {cfg.nx}x{cfg.ny}x{cfg.nz} prec={args.prec} steps={args.steps} warmup={args.warmup}")
+    head = run_gpu(cfg, args.prec, args.steps, args.warmup)
+    log(f"bench: {args.prec} {head['value']:.4g} cell-updates/s, {head['ms_per_step']:.3f} ms/step")
+    side = run_gpu(cfg, other, args.steps, args.warmup)
+    log(f"bench: {other} {side['value']:.4g} cell-updates/s, {side['ms_per_step']:.3f} ms/step")
+    f64 = head if args.prec == "f64" else side
+    out = {
+        "metric": "cell-updates/s per RK stage",
+        "value": head["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.prec == "f32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "bell256: 256x256x128 cells, dx=dy=100 m, dz=50 m, bell hill h0=400 m "
+                               "a=2 km, N=0.01 1/s, U=10 m/s, theta' noise N(0,0.01 K) seed 0, dt=0.05 s",
+                   "precision": "FP32 perturbation (FP64 base state and sums)" if args.prec == "f32" else "FP64",
+                   "cells": cfg.nx * cfg.ny * cfg.nz, "stages_per_step": 3},
+        "roofline": head["roofline"],
+        other: {"value": side["value"], "ms_per_step": side["ms_per_step"], "roofline": side["roofline"]},
+        "speedup_vs_fp64": head["value"] / f64["value"],
+    }
+    if not args.no_cpu:
+        log("bench: timing the CPU oracle baseline")
+        out["cpu_baseline"] = run_cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * cutcell.h -- C ABI of libcutcell.so, the MI355X (gfx950) implementation of the explicit
+ * finite-volume cut-cell stage of Yamazaki, Satomura & Nikiforakis, "3D cut-cell modelling for
+ * high-resolution atmospheric simulations" (arXiv:1509.02572).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * Memory.  Every array pointer is DEVICE memory allocated and owned by the caller; the library never
+ * allocates or frees on these paths and keeps no global state apart from a thread-local last-error
+ * string.  Calls are ordered on the caller's HIP stream (`stream`, a hipStream_t; NULL = the default
+ * stream) and return as soon as their kernels are enqueued.
+ *
+ * Layout.  Cell (i,j,k), 0<=i<nx, 0<=j<ny, 0<=k<nz, spans [i dx,(i+1)dx] x [j dy,(j+1)dy] x
+ * [k dz,(k+1)dz].  Every 3-D array is structure-of-arrays, k fastest, index ((i*ny + j)*nzs + k) with
+ * the padded stride nzs >= nz; slots k >= nz are never read or written.  Lattice point (I,J,K) is the
+ * cell corner (I dx, J dy, K dz) (velocity point of the semi-staggered arrangement, Sec. 2.3) and
+ * uses the index of cell (I,J,K); the lid row K = nz is not stored.  Column and corner arrays are
+ * [nx*ny], index (i*ny + j).  x and y are periodic.
+ *
+ * Precision.  CC_F64: every field is double and holds the paper's variables: rho', (rho theta)' at
+ * cells, the momentum (rho u, rho v, rho w) at predicted lattice points and the diagnosed velocity
+ * (u, v, w) at all other lattice points.  CC_F32_PERT: every state field is float and holds
+ * perturbations: rho', (rho theta)', the momentum perturbation rho u - rhobar_c(K) (u0, v0, 0) at
+ * predicted points (rhobar_c(K) = mean of the base density of levels K-1 and K) and the velocity
+ * perturbation u - (u0, v0, 0) at diagnosed points.  Base state, geometry and reductions stay double.
+ *
+ * Errors.  Argument errors found on the host (null pointer, bad sizes, nsub not a power of two, nz<3)
+ * return CC_EINVAL and launch nothing.  HIP launch failures return CC_EDEVICE.  Conditions found on
+ * the device are counted into the caller's int64 status array `dev_status[CC_NSTATUS]` (never reset
+ * by the library): [0] unmergeable cells, [1] corners without a nearest plane, [2] non-finite values,
+ * [3] terrain corners outside [0, (nz-2) dz], [4] merged groups larger than CC_MAX_GROUP.  The
+ * caller synchronises and checks them (cutcell_check_status).  No exception crosses the ABI.
+ * Calls are reentrant for distinct streams and buffers; calls sharing output buffers race.
+ */
+#ifndef CUTCELL_H
+#define CUTCELL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *cc_stream_t; /* hipStream_t */
+
+typedef enum {
+    CC_OK = 0,
+    CC_EINVAL = 1,
+    CC_EDEVICE = 2,
+    CC_EUNMERGEABLE = 3,
+    CC_ENOPLANE = 4,
+    CC_ENONFINITE = 5,
+    CC_ETERRAIN = 6
+} cc_status;
+
+typedef enum { CC_F64 = 0, CC_F32_PERT = 1 } cc_prec;
+
+#define CC_NSTATUS 8
+#define CC_MAX_GROUP 32
+
+/* cell classes (cls), merge directions (dir) and lattice-point classes (vcls) */
+enum { CC_SOLID = 0, CC_OPEN = 1, CC_ABSORBED = 2, CC_ORPHAN = 3 };
+enum { CC_DIR_NONE = 0, CC_DIR_ZP = 1, CC_DIR_XM = 2, CC_DIR_XP = 3, CC_DIR_YM = 4, CC_DIR_YP = 5 };
+enum { CC_GROUND = 0, CC_PRED = 1, CC_MFACE = 2 };
+
+typedef struct {
+    int32_t nx, ny, nz, nzs; /* cells; padded k stride (nzs >= nz) */
+    double dx, dy, dz;       /* spacings [m] */
+    int32_t nsub;            /* sub-columns per cell edge for volumes/apertures, power of two */
+    int32_t reserved;
+} cc_grid;
+
+typedef struct {
+    double g, rd, cp, p0; /* gravity, gas constant, specific heat at constant pressure, p_ref */
+    double theta0, bvn;   /* sea-level potential temperature [K], Brunt-Vaisala frequency [1/s] */
+    double u0, v0;        /* uniform inflow (reference velocity of the perturbation form) */
+} cc_phys;
+
+/* Geometry and merge map (device arrays, caller-allocated). */
+typedef struct {
+    const double *H;          /* [nx*ny] terrain height at corner (I,J), input */
+    double *V;                /* [cells] volume fraction in [0,1] */
+    double *Ax, *Ay, *Az;     /* [cells] open fraction of the faces x = i dx, y = j dy, z = k dz */
+    double *col;              /* [3][nx*ny] column centre height hc, gradients gx, gy */
+    double *nrm;              /* [3][nx*ny] unit terrain normal at corner (I,J) */
+    int8_t *cls, *dir, *vcls; /* [cells] */
+    int32_t *master;          /* [cells] linear index of the group master, -1 for solid cells */
+    int32_t *gnext;           /* [cells] next member of the master's group (increasing index), -1 */
+    double *Vgroup;           /* [cells] group volume fraction, valid at masters */
+    int32_t *colk;            /* [2][nx*ny] per column: first k of the regular interior; 1 + top k
+                                 of any diagnosed lattice point, absorbed or solid cell */
+} cc_geom;
+
+/* Five prognostic fields; element type double (CC_F64) or float (CC_F32_PERT). */
+typedef struct {
+    void *rho, *rth, *mu, *mv, *mw;
+} cc_state;
+
+const char *cutcell_version(void);
+const char *cutcell_last_error(void);
+
+/* Base state on cell centres z_k = (k+1/2) dz (Sec. 2.1 hydrostatic reference; constant N and
+ * theta0 at z = 0, surface pressure p0, Sec. 3).  base: [4*nz] doubles = rhobar, (rho theta)bar,
+ * pbar, thetabar; pbar follows from (rho theta)bar through the equation of state. */
+cc_status cutcell_base_state(const cc_grid *grid, const cc_phys *phys, double *base, cc_stream_t stream);
+
+/* Cut-cell geometry (Sec. 2.3): bilinear terrain per column (eq. bilin) from the corner heights H,
+ * cell volume fractions V and face apertures Ax/Ay/Az from nsub x nsub narrow sub-columns, column
+ * gradients (eqs. xgrad, ygrad) and the unit terrain normal at every corner from centred gradients
+ * of the column-centre heights (Sec. 2.4).  A face touching a cell with V = 0 is closed.  Writes
+ * V, Ax, Ay, Az, col, nrm of `geom`; counts terrain outside [0,(nz-2)dz] into dev_status[3]. */
+cc_status cutcell_geometry(const cc_grid *grid, cc_geom *geom, int64_t *dev_status, cc_stream_t stream);
+
+/* Cell merging (Sec. 2.3, Fig. 6): a cell with V > 0 merges when its centre is below the column's
+ * centre height or V < 1/2; direction from the column gradients (vertical if |gx|,|gy| <= 1, else
+ * towards lower terrain, x preferred on ties).  Chains of targets that must merge themselves are
+ * followed up to 8 hops to the master.  Also classifies lattice points (predicted when all eight
+ * surrounding cells are available, Sec. 2.4) and fills gnext, Vgroup and colk.  Needs V, Az.. and
+ * col from cutcell_geometry.  Unmergeable cells become their own master (CC_ORPHAN) and are counted
+ * into dev_status[0]. */
+cc_status cutcell_merge_map(const cc_grid *grid, cc_geom *geom, int64_t *dev_status, cc_stream_t stream);
+
+/* Initial state: theta' (nullable, cell layout, double) applied at constant pressure to group
+ * masters, (rho theta)' = 0, uniform inflow (u0, v0, 0) as momentum at predicted points, then one
+ * velocity-diagnostic pass.  Writes every slot k < nz of q. */
+cc_status cutcell_init_state(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                             const double *base, cc_prec prec, const double *theta_noise, cc_state *q,
+                             int64_t *dev_status, cc_stream_t stream);
+
+/* Velocity diagnostics (Sec. 2.4, three-step procedure, steps 2-3): boundary velocity at every
+ * corner from the nearest plane of predicted points and the free-slip projection (eq. 33),
+ * merged-face points by linear interpolation towards the lowest predicted point above, points on or
+ * below the terrain take the boundary velocity; absorbed cells mirror their master's scalars and
+ * solid cells are zeroed.  Updates q in place. */
+cc_status cutcell_diagnose(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                           const double *base, cc_prec prec, cc_state *q, int64_t *dev_status,
+                           cc_stream_t stream);
+
+/* Tendency L(q) (Sec. 2.4): scalar fluxes with apertures over the whole merged group divided by the
+ * group volume (eqs. gauss_m, gauss_d, fvm_d and the merged-cell face split), momentum, pressure
+ * gradient and buoyancy at predicted points (eqs. momentum_u_d, _v_d, _w_d).  dqdt: same element
+ * type as q; scalars at group masters, momentum at predicted points, zero elsewhere. */
+cc_status cutcell_tendency(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                           const double *base, cc_prec prec, const cc_state *q, cc_state *dqdt,
+                           cc_stream_t stream);
+
+/* One explicit Runge-Kutta stage q_out = q_n + stage_dt * L(q_s) (three-stage scheme of Wicker &
+ * Skamarock with stage_dt = dt/3, dt/2, dt; it replaces the paper's leap-frog, Sec. 2.2), followed
+ * by the velocity diagnostics of q_out.  q_n may equal q_s; q_out must differ from both.  Non-finite
+ * updated values are counted into dev_status[2]. */
+cc_status cutcell_rk_stage(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                           const double *base, cc_prec prec, const cc_state *q_n, const cc_state *q_s,
+                           cc_state *q_out, double stage_dt, int64_t *dev_status, cc_stream_t stream);
+
+/* The update half of cutcell_rk_stage alone: q_out = q_n + stage_dt * L(q_s) at group masters
+ * and predicted points, solid cells zeroed.  Absorbed cells and diagnosed lattice points of q_out
+ * are left for a following cutcell_diagnose(q_out), which completes the stage (used to time the
+ * fused update kernel separately). */
+cc_status cutcell_rk_update(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                            const double *base, cc_prec prec, const cc_state *q_n, const cc_state *q_s,
+                            cc_state *q_out, double stage_dt, int64_t *dev_status, cc_stream_t stream);
+
+/* Conservation sums (FP64, deterministic order): out[4] = { M' = sum Vgroup dV rho',
+ * Theta' = sum Vgroup dV (rho theta)', M_total (with the base density at each master's level),
+ * E = internal + potential energy of the groups + kinetic energy at predicted points }.  Mass is
+ * conserved (Sec. 2.4); E is reported only.  workspace: cutcell_reduce_workspace() bytes. */
+size_t cutcell_reduce_workspace(const cc_grid *grid);
+cc_status cutcell_reduce(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                         const double *base, cc_prec prec, const cc_state *q, void *workspace,
+                         double *out, cc_stream_t stream);
+
+/* Host helper: copies dev_status to the host (synchronising `stream`) and maps the first non-zero
+ * counter to its status code. */
+cc_status cutcell_check_status(const int64_t *dev_status, int64_t *host_copy, cc_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CUTCELL_H */

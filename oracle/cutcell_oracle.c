@@ -429,6 +429,7 @@ static int plane_family(const or_ctx *x, int fam, int I, int J, double ut[3])
     size_t nc = (size_t)g->nx * g->ny, hc = hidx(g, I, J);
     double n0 = x->G->nrm[hc], n1 = x->G->nrm[nc + hc], n2 = x->G->nrm[2 * nc + hc];
     double h = x->G->H[hc];
+    if (!(h >= 0.0 && h < (double)g->nz * g->dz)) return 0; /* terrain outside the column */
     double bx = (double)I * g->dx, by = (double)J * g->dy;
     for (int m = 0; m < 3; ++m) {
         int P[4][3], ia, ib;
@@ -587,8 +588,10 @@ void or_init_state(const or_grid *g, const or_phys *ph, const or_geom *G, const 
                 q->rth[c] = 0.0;
                 q->rho[c] = 0.0;
                 if (G->cls[c] == OR_OPEN || G->cls[c] == OR_ORPHAN) {
+                    /* rho' = (rho theta)bar/(thetabar + theta') - rhobar, written without the
+                     * cancellation: rhobar = (rho theta)bar / thetabar */
                     double thp = noise ? noise[c] : 0.0;
-                    q->rho[c] = rthb[k] / (thb[k] + thp) - rhob[k];
+                    q->rho[c] = thp != 0.0 ? -(rhob[k] * thp) / (thb[k] + thp) : 0.0;
                 }
                 q->mu[c] = 0.0; q->mv[c] = 0.0; q->mw[c] = 0.0;
             }

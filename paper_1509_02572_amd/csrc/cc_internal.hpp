@@ -1,0 +1,69 @@
+// Internal declarations shared by the HIP translation units of libcutcell (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+
+#include "cutcell.h"
+
+namespace cc {
+
+// Grid description passed by value to every kernel.
+struct Dims {
+    int nx, ny, nz, nzs;
+    double dx, dy, dz;
+    int nsub;
+};
+
+__host__ __device__ __forceinline__ int wrap(int a, int n)
+{
+    a %= n;
+    return a < 0 ? a + n : a;
+}
+// linear index of cell / lattice point (i,j,k) with periodic i and j (k must be in range)
+__host__ __device__ __forceinline__ int64_t cidx(const Dims &d, int i, int j, int k)
+{
+    return ((int64_t)wrap(i, d.nx) * d.ny + wrap(j, d.ny)) * d.nzs + k;
+}
+__host__ __device__ __forceinline__ int64_t hidx(const Dims &d, int i, int j)
+{
+    return (int64_t)wrap(i, d.nx) * d.ny + wrap(j, d.ny);
+}
+// inverse of cidx for an in-range linear index
+__host__ __device__ __forceinline__ void unidx(const Dims &d, int64_t c, int &i, int &j, int &k)
+{
+    k = (int)(c % d.nzs);
+    int64_t col = c / d.nzs;
+    j = (int)(col % d.ny);
+    i = (int)(col / d.ny);
+}
+
+// status counters (see cutcell.h)
+enum { ST_UNMERGEABLE = 0, ST_NOPLANE = 1, ST_NONFINITE = 2, ST_TERRAIN = 3, ST_GROUPSIZE = 4 };
+
+__device__ __forceinline__ void count_status(int64_t *st, int which, int64_t n = 1)
+{
+    if (st) atomicAdd(reinterpret_cast<unsigned long long *>(st + which), (unsigned long long)n);
+}
+
+void set_error(const char *fmt, ...);
+cc_status launch_status(const char *what);
+Dims dims_of(const cc_grid *g);
+// host-side argument checks; on failure set the error text and return false
+bool check_grid(const cc_grid *g);
+bool check_ptrs(const char *what, int n, const void *const *ptrs);
+
+inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+}  // namespace cc
+
+#define CC_REQUIRE(cond, ...)                  \
+    do {                                       \
+        if (!(cond)) {                         \
+            ::cc::set_error(__VA_ARGS__);      \
+            return CC_EINVAL;                  \
+        }                                      \
+    } while (0)

@@ -1,0 +1,697 @@
+// The cut-cell stage: tendencies, the explicit RK stage update, the velocity diagnostics, the
+// initial state and the conservation sums (Sec. 2.4 of the paper), for both storage precisions.
+//
+// Precision forms
+//   double : the paper's variables; reference velocity (ux, vy) = 0.
+//   float  : perturbation form.  Momentum is stored as m' = rho u - rhobar_c(K) (ux, vy, 0) and
+//            diagnosed velocities as u - (ux, vy, 0).  Fluxes are split into the part carried by
+//            the base state and the uniform reference flow, which is evaluated in double (it is a
+//            static quantity that cancels exactly on regular cells), and the perturbation part,
+//            evaluated and accumulated in float.  Base state, group volumes and sums stay double.
+#include "cc_internal.hpp"
+
+namespace cc {
+
+template <typename T>
+struct SIn {
+    const T *rho, *rth, *mu, *mv, *mw;
+};
+template <typename T>
+struct SOut {
+    T *rho, *rth, *mu, *mv, *mw;
+};
+
+struct Geo {
+    const double *H, *V, *Ax, *Ay, *Az, *nrm, *Vgroup;
+    const int8_t *cls, *vcls;
+    const int32_t *master, *gnext, *colk;
+};
+
+struct Phy {
+    const double *rhob, *rthb, *pb, *thb;  // base state at cell centres [nz]
+    double g, gam, ux, vy, dV;
+};
+
+template <typename T>
+struct Compute;
+template <>
+struct Compute<double> {
+    using R = double;
+};
+template <>
+struct Compute<float> {
+    using R = float;
+};
+
+__device__ __forceinline__ double expm1_r(double x) { return expm1(x); }
+__device__ __forceinline__ float expm1_r(float x) { return expm1f(x); }
+__device__ __forceinline__ double log1p_r(double x) { return log1p(x); }
+__device__ __forceinline__ float log1p_r(float x) { return log1pf(x); }
+
+// p' from (rho theta)' through the ideal-gas equation of state (Sec. 2.1):
+// p = p0 (R rho theta / p0)^(cp/cv)  =>  p' = pbar ((1 + rth'/rthbar)^gamma - 1)
+template <typename R>
+__device__ __forceinline__ R eos_pprime(R rthp, double rthb, double pb, double gam)
+{
+    return (R)pb * expm1_r((R)gam * log1p_r(rthp / (R)rthb));
+}
+
+// Velocity (perturbation from the reference flow) at lattice point (I,J,K).
+// Predicted points divide the momentum by the mean of the eight surrounding cell densities;
+// diagnosed points store the velocity; the rigid lid (K = nz) has w = 0 and copies (u, v) of the
+// level below.
+template <typename T, typename R = typename Compute<T>::R>
+__device__ __forceinline__ void lat_vel(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &q,
+                                        int I, int J, int K, R u[3])
+{
+    bool lid = K >= d.nz;
+    if (lid) K = d.nz - 1;
+    int64_t p = cidx(d, I, J, K);
+    if (G.vcls[p] == CC_PRED) {
+        int64_t c00 = cidx(d, I - 1, J - 1, K - 1), c10 = cidx(d, I, J - 1, K - 1);
+        int64_t c01 = cidx(d, I - 1, J, K - 1), c11 = cidx(d, I, J, K - 1);
+        R s = (((R)q.rho[c00] + (R)q.rho[c10]) + ((R)q.rho[c01] + (R)q.rho[c11])) +
+              (((R)q.rho[c00 + 1] + (R)q.rho[c10 + 1]) + ((R)q.rho[c01 + 1] + (R)q.rho[c11 + 1]));
+        R rpc = s * (R)0.125;
+        R rc = (R)(0.5 * (P.rhob[K - 1] + P.rhob[K])) + rpc;
+        u[0] = ((R)q.mu[p] - rpc * (R)P.ux) / rc;
+        u[1] = ((R)q.mv[p] - rpc * (R)P.vy) / rc;
+        u[2] = (R)q.mw[p] / rc;
+    } else {
+        u[0] = (R)q.mu[p];
+        u[1] = (R)q.mv[p];
+        u[2] = (R)q.mw[p];
+    }
+    if (lid) u[2] = (R)0;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Scalar tendency of a merged group (Sec. 2.4): the surface integral over every external face of
+// every member (a face split among several neighbours contributes one sub-face per neighbour, with
+// its own aperture), face scalar = mean of the two exchanging groups, face normal velocity = mean
+// of the four corner velocities (eqs. ux1-ux3), zero flux through closed faces (terrain, ground,
+// rigid lid).  Returns d(rho')/dt and d(rho theta)'/dt of master c.
+// ------------------------------------------------------------------------------------------------
+template <typename T, typename R = typename Compute<T>::R>
+__device__ void group_scalar_tendency(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &q,
+                                      int64_t c, double L[2])
+{
+    double rb0 = 0.0, rb1 = 0.0;  // base-state / reference-flow part (double)
+    R rp0 = (R)0, rp1 = (R)0;     // perturbation part
+    int kc = (int)(c % d.nzs);
+    int64_t mem = c;
+    for (int guard = 0; mem >= 0 && guard <= CC_MAX_GROUP; ++guard) {
+        int i, j, k;
+        unidx(d, mem, i, j, k);
+        for (int f = 0; f < 6; ++f) {
+            int axis = f >> 1, plus = f & 1;
+            int fi = i, fj = j, fk = k, ni = i, nj = j, nk = k;
+            if (axis == 0) { if (plus) { fi = i + 1; ni = i + 1; } else ni = i - 1; }
+            else if (axis == 1) { if (plus) { fj = j + 1; nj = j + 1; } else nj = j - 1; }
+            else {
+                if (plus) { fk = k + 1; nk = k + 1; } else nk = k - 1;
+                if (nk < 0 || nk >= d.nz) continue;
+            }
+            int64_t fu = cidx(d, fi, fj, fk);
+            double A = axis == 0 ? G.Ax[fu] : (axis == 1 ? G.Ay[fu] : G.Az[fu]);
+            if (A == 0.0) continue;
+            int32_t mn = G.master[cidx(d, ni, nj, nk)];
+            if (mn == (int32_t)c || mn < 0) continue;  // internal face of the group
+            R a[3], b[3], e[3], h[3];
+            double S, Un;
+            if (axis == 0) {
+                lat_vel<T>(d, G, P, q, fi, fj, fk, a); lat_vel<T>(d, G, P, q, fi, fj + 1, fk, b);
+                lat_vel<T>(d, G, P, q, fi, fj, fk + 1, e); lat_vel<T>(d, G, P, q, fi, fj + 1, fk + 1, h);
+                S = d.dy * d.dz; Un = P.ux;
+            } else if (axis == 1) {
+                lat_vel<T>(d, G, P, q, fi, fj, fk, a); lat_vel<T>(d, G, P, q, fi + 1, fj, fk, b);
+                lat_vel<T>(d, G, P, q, fi, fj, fk + 1, e); lat_vel<T>(d, G, P, q, fi + 1, fj, fk + 1, h);
+                S = d.dz * d.dx; Un = P.vy;
+            } else {
+                lat_vel<T>(d, G, P, q, fi, fj, fk, a); lat_vel<T>(d, G, P, q, fi + 1, fj, fk, b);
+                lat_vel<T>(d, G, P, q, fi, fj + 1, fk, e); lat_vel<T>(d, G, P, q, fi + 1, fj + 1, fk, h);
+                S = d.dx * d.dy; Un = 0.0;
+            }
+            R un = (R)0.25 * ((a[axis] + b[axis]) + (e[axis] + h[axis]));
+            int64_t mlo = plus ? c : (int64_t)mn, mup = plus ? (int64_t)mn : c;
+            int klo = plus ? kc : (int)(mn % d.nzs), kup = plus ? (int)(mn % d.nzs) : kc;
+            double pb0 = 0.5 * (P.rhob[klo] + P.rhob[kup]);
+            double pb1 = 0.5 * (P.rthb[klo] + P.rthb[kup]);
+            R pp0 = (R)0.5 * ((R)q.rho[mlo] + (R)q.rho[mup]);
+            R pp1 = (R)0.5 * ((R)q.rth[mlo] + (R)q.rth[mup]);
+            R AS = (R)(A * S);
+            R unt = un + (R)Un;
+            R f0 = ((R)pb0 * un + pp0 * unt) * AS;
+            R f1 = ((R)pb1 * un + pp1 * unt) * AS;
+            double g0 = pb0 * Un * A * S, g1 = pb1 * Un * A * S;
+            if (plus) { rp0 += f0; rp1 += f1; rb0 += g0; rb1 += g1; }
+            else { rp0 -= f0; rp1 -= f1; rb0 -= g0; rb1 -= g1; }
+        }
+        mem = G.gnext[mem];
+    }
+    double vol = G.Vgroup[c] * P.dV;
+    L[0] = -(rb0 + (double)rp0) / vol;
+    L[1] = -(rb1 + (double)rp1) / vol;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Momentum tendency at a predicted point (eqs. momentum_u_d, momentum_v_d, momentum_w_d): advection
+// through the six faces of the rectangular velocity cell (face density = mean of the four cell
+// densities on the face, velocities averaged along the face normal), second-order pressure
+// gradient of p' and buoyancy -rho' g.  In the perturbation form the base-state/reference-flow
+// product rhobar U0 M0 cancels identically between opposite faces and is left out.
+// ------------------------------------------------------------------------------------------------
+template <typename T, typename R = typename Compute<T>::R>
+__device__ void momentum_tendency(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &q, int i,
+                                  int j, int k, R L[3])
+{
+    R u[7][3];
+    lat_vel<T>(d, G, P, q, i, j, k, u[0]);
+    lat_vel<T>(d, G, P, q, i - 1, j, k, u[1]);
+    lat_vel<T>(d, G, P, q, i + 1, j, k, u[2]);
+    lat_vel<T>(d, G, P, q, i, j - 1, k, u[3]);
+    lat_vel<T>(d, G, P, q, i, j + 1, k, u[4]);
+    lat_vel<T>(d, G, P, q, i, j, k - 1, u[5]);
+    lat_vel<T>(d, G, P, q, i, j, k + 1, u[6]);
+    R rp[8], pp[8];  // bit0: i-1/i, bit1: j-1/j, bit2: k-1/k
+    for (int s = 0; s < 8; ++s) {
+        int kk = k - 1 + (s >> 2);
+        int64_t cc = cidx(d, i - 1 + (s & 1), j - 1 + ((s >> 1) & 1), kk);
+        rp[s] = (R)q.rho[cc];
+        pp[s] = eos_pprime<R>((R)q.rth[cc], P.rthb[kk], P.pb[kk], P.gam);
+    }
+    R q4 = (R)0.25;
+    R rxm = q4 * ((rp[0] + rp[2]) + (rp[4] + rp[6])), rxp = q4 * ((rp[1] + rp[3]) + (rp[5] + rp[7]));
+    R rym = q4 * ((rp[0] + rp[1]) + (rp[4] + rp[5])), ryp = q4 * ((rp[2] + rp[3]) + (rp[6] + rp[7]));
+    R rzm = q4 * ((rp[0] + rp[1]) + (rp[2] + rp[3])), rzp = q4 * ((rp[4] + rp[5]) + (rp[6] + rp[7]));
+    R pxm = q4 * ((pp[0] + pp[2]) + (pp[4] + pp[6])), pxp = q4 * ((pp[1] + pp[3]) + (pp[5] + pp[7]));
+    R pym = q4 * ((pp[0] + pp[1]) + (pp[4] + pp[5])), pyp = q4 * ((pp[2] + pp[3]) + (pp[6] + pp[7]));
+    R pzm = q4 * ((pp[0] + pp[1]) + (pp[2] + pp[3])), pzp = q4 * ((pp[4] + pp[5]) + (pp[6] + pp[7]));
+    R r8 = (R)0.125 * (((rp[0] + rp[1]) + (rp[2] + rp[3])) + ((rp[4] + rp[5]) + (rp[6] + rp[7])));
+    R rbc = (R)(0.5 * (P.rhob[k - 1] + P.rhob[k]));
+    R rbzm = (R)P.rhob[k - 1], rbzp = (R)P.rhob[k];
+    R Ux = (R)P.ux, Vy = (R)P.vy, h = (R)0.5;
+    for (int c = 0; c < 3; ++c) {
+        R M0 = c == 0 ? Ux : (c == 1 ? Vy : (R)0);
+        R ub, mb;
+        ub = h * (u[0][0] + u[2][0]); mb = h * (u[0][c] + u[2][c]);
+        R fxp = rbc * (Ux * mb + ub * M0 + ub * mb) + rxp * (Ux + ub) * (M0 + mb);
+        ub = h * (u[1][0] + u[0][0]); mb = h * (u[1][c] + u[0][c]);
+        R fxm = rbc * (Ux * mb + ub * M0 + ub * mb) + rxm * (Ux + ub) * (M0 + mb);
+        ub = h * (u[0][1] + u[4][1]); mb = h * (u[0][c] + u[4][c]);
+        R fyp = rbc * (Vy * mb + ub * M0 + ub * mb) + ryp * (Vy + ub) * (M0 + mb);
+        ub = h * (u[3][1] + u[0][1]); mb = h * (u[3][c] + u[0][c]);
+        R fym = rbc * (Vy * mb + ub * M0 + ub * mb) + rym * (Vy + ub) * (M0 + mb);
+        ub = h * (u[0][2] + u[6][2]); mb = h * (u[0][c] + u[6][c]);
+        R fzp = (rbzp + rzp) * ub * (M0 + mb);
+        ub = h * (u[5][2] + u[0][2]); mb = h * (u[5][c] + u[0][c]);
+        R fzm = (rbzm + rzm) * ub * (M0 + mb);
+        R adv = (fxp - fxm) / (R)d.dx + (fyp - fym) / (R)d.dy + (fzp - fzm) / (R)d.dz;
+        R pgf = c == 0 ? (pxp - pxm) / (R)d.dx : (c == 1 ? (pyp - pym) / (R)d.dy : (pzp - pzm) / (R)d.dz);
+        R buoy = c == 2 ? (R)P.g * r8 : (R)0;
+        L[c] = -adv - pgf - buoy;
+    }
+}
+
+// General path: one thread per cell / lattice index (i,j,k).  MODE 0: q_out = q_n + cdt L(q_s);
+// MODE 1: dq = L(q_s) (zero where no equation is solved).  Solid cells are zeroed; absorbed cells
+// and diagnosed lattice points are written by the diagnostic pass that follows.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_stage_general(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn,
+                                                       SOut<T> qo, double cdt, int64_t *st)
+{
+    using R = typename Compute<T>::R;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)d.nx * d.ny * d.nz) return;
+    int k = (int)(t % d.nz);
+    int64_t colI = t / d.nz;
+    int j = (int)(colI % d.ny), i = (int)(colI / d.ny);
+    int64_t c = cidx(d, i, j, k);
+    int8_t cl = G.cls[c];
+    bool bad = false;
+    if (cl == CC_OPEN || cl == CC_ORPHAN) {
+        double L[2];
+        group_scalar_tendency<T>(d, G, P, qs, c, L);
+        if (MODE == 0) {
+            T a = (T)((double)qn.rho[c] + cdt * L[0]);
+            T b = (T)((double)qn.rth[c] + cdt * L[1]);
+            bad = !isfinite(a) || !isfinite(b);
+            qo.rho[c] = a;
+            qo.rth[c] = b;
+        } else {
+            qo.rho[c] = (T)L[0];
+            qo.rth[c] = (T)L[1];
+        }
+    } else if (cl == CC_SOLID || MODE == 1) {
+        qo.rho[c] = (T)0;
+        qo.rth[c] = (T)0;
+    }
+    if (G.vcls[c] == CC_PRED) {
+        R L[3];
+        momentum_tendency<T>(d, G, P, qs, i, j, k, L);
+        if (MODE == 0) {
+            R cd = (R)cdt;
+            T a = (T)((R)qn.mu[c] + cd * L[0]);
+            T b = (T)((R)qn.mv[c] + cd * L[1]);
+            T e = (T)((R)qn.mw[c] + cd * L[2]);
+            bad = bad || !isfinite(a) || !isfinite(b) || !isfinite(e);
+            qo.mu[c] = a; qo.mv[c] = b; qo.mw[c] = e;
+        } else {
+            qo.mu[c] = (T)L[0]; qo.mv[c] = (T)L[1]; qo.mw[c] = (T)L[2];
+        }
+    } else if (MODE == 1) {
+        qo.mu[c] = (T)0; qo.mv[c] = (T)0; qo.mw[c] = (T)0;
+    }
+    if (bad) count_status(st, ST_NONFINITE);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Velocity diagnostics (Sec. 2.4).  The plane search takes integer decisions (which plane, which
+// face, which corners carry weight) from floating-point positions, so it is evaluated without FMA
+// contraction in the written order.
+// ------------------------------------------------------------------------------------------------
+
+// Try the first three lattice planes of one family (0: x = const, 1: y = const, 2: z = const) beyond
+// the terrain point B along the normal line; on each plane the intersection falls in a face of four
+// lattice points (located with floor); the first plane whose corners with non-zero bilinear weight
+// are all predicted gives the interpolated velocity (the paper's u_N).
+template <typename T, typename R = typename Compute<T>::R>
+__device__ bool plane_family(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &q, int fam,
+                             int I, int J, R ut[3])
+{
+#pragma clang fp contract(off)
+    int64_t nc = (int64_t)d.nx * d.ny, hc = hidx(d, I, J);
+    double n0 = G.nrm[hc], n1 = G.nrm[nc + hc], n2 = G.nrm[2 * nc + hc];
+    double hh = G.H[hc];
+    if (!(hh >= 0.0 && hh < (double)d.nz * d.dz)) return false;  // terrain outside the column
+    double bx = (double)I * d.dx, by = (double)J * d.dy;
+    for (int m = 0; m < 3; ++m) {
+        int P4[4][3];
+        int ia, ib;
+        double a, b;
+        if (fam == 2) {
+            int K0 = (int)floor(hh / d.dz) + 1;
+            while (K0 > 0 && (double)(K0 - 1) * d.dz > hh) --K0;
+            while ((double)K0 * d.dz <= hh) ++K0;
+            int K = K0 + m;
+            if (K > d.nz - 1) return false;
+            double t = ((double)K * d.dz - hh) / n2;
+            double fx = (bx + t * n0) / d.dx, fy = (by + t * n1) / d.dy;
+            ia = (int)floor(fx); ib = (int)floor(fy);
+            a = fx - (double)ia; b = fy - (double)ib;
+            P4[0][0] = ia; P4[0][1] = ib; P4[0][2] = K;
+            P4[1][0] = ia + 1; P4[1][1] = ib; P4[1][2] = K;
+            P4[2][0] = ia; P4[2][1] = ib + 1; P4[2][2] = K;
+            P4[3][0] = ia + 1; P4[3][1] = ib + 1; P4[3][2] = K;
+        } else {
+            double nn = fam == 0 ? n0 : n1;
+            if (nn == 0.0) return false;
+            int step = (m + 1) * (nn > 0.0 ? 1 : -1);
+            double t = fam == 0 ? ((double)step * d.dx) / nn : ((double)step * d.dy) / nn;
+            double fa = fam == 0 ? (by + t * n1) / d.dy : (bx + t * n0) / d.dx;
+            double fz = (hh + t * n2) / d.dz;
+            ia = (int)floor(fa); ib = (int)floor(fz);
+            a = fa - (double)ia; b = fz - (double)ib;
+            if (ib < 0 || ib + 1 > d.nz - 1) continue;
+            for (int s = 0; s < 4; ++s) {
+                int pa = ia + (s & 1), pz = ib + (s >> 1);
+                if (fam == 0) { P4[s][0] = I + step; P4[s][1] = pa; }
+                else { P4[s][0] = pa; P4[s][1] = J + step; }
+                P4[s][2] = pz;
+            }
+        }
+        double w[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
+        bool ok = true;
+        for (int s = 0; s < 4 && ok; ++s)
+            if (w[s] != 0.0) ok = G.vcls[cidx(d, P4[s][0], P4[s][1], P4[s][2])] == CC_PRED;
+        if (!ok) continue;
+        R acc[3] = {(R)0, (R)0, (R)0};
+        for (int s = 0; s < 4; ++s) {
+            if (w[s] == 0.0) continue;
+            R v[3];
+            lat_vel<T>(d, G, P, q, P4[s][0], P4[s][1], P4[s][2], v);
+            for (int cc = 0; cc < 3; ++cc) acc[cc] += (R)w[s] * v[cc];
+        }
+        ut[0] = acc[0]; ut[1] = acc[1]; ut[2] = acc[2];
+        return true;
+    }
+    return false;
+}
+
+// one thread per column corner (I,J): boundary velocity (free-slip projection of the nearest-plane
+// mean, eq. 33), then every diagnosed lattice point and absorbed/solid cell of the column
+template <typename T>
+__global__ void __launch_bounds__(256) k_diagnose(Dims d, Geo G, Phy P, SOut<T> qw, int64_t *st)
+{
+    using R = typename Compute<T>::R;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t nc = (int64_t)d.nx * d.ny;
+    if (t >= nc) return;
+    int I = (int)(t / d.ny), J = (int)(t % d.ny);
+    SIn<T> q{qw.rho, qw.rth, qw.mu, qw.mv, qw.mw};
+    double n0 = G.nrm[t], n1 = G.nrm[nc + t], n2 = G.nrm[2 * nc + t];
+    int dom = (fabs(n2) >= fabs(n0) && fabs(n2) >= fabs(n1)) ? 2 : (fabs(n0) >= fabs(n1) ? 0 : 1);
+    R ut[3];
+    bool ok = plane_family<T>(d, G, P, q, dom, I, J, ut);
+    const int order[3] = {2, 0, 1};
+    for (int f = 0; f < 3 && !ok; ++f)
+        if (order[f] != dom) ok = plane_family<T>(d, G, P, q, order[f], I, J, ut);
+    if (!ok) {  // no usable plane: u~ = 0 (as a perturbation: minus the reference flow)
+        ut[0] = -(R)P.ux; ut[1] = -(R)P.vy; ut[2] = (R)0;
+        count_status(st, ST_NOPLANE);
+    }
+    R dn = (ut[0] + (R)P.ux) * (R)n0 + (ut[1] + (R)P.vy) * (R)n1 + ut[2] * (R)n2;
+    R ub[3] = {ut[0] - dn * (R)n0, ut[1] - dn * (R)n1, ut[2] - dn * (R)n2};
+    double hh = G.H[t];
+    int ktop = G.colk[nc + t];
+    int64_t base = cidx(d, I, J, 0);
+    for (int K = 0; K < ktop; ++K) {
+        int64_t p = base + K;
+        int8_t vc = G.vcls[p];
+        if (vc != CC_PRED) {
+            R u[3] = {ub[0], ub[1], ub[2]};
+            if (vc == CC_MFACE) {
+                int kp = -1;
+                for (int kk = K + 1; kk <= K + 8 && kk < d.nz; ++kk)
+                    if (G.vcls[base + kk] == CC_PRED) { kp = kk; break; }
+                if (kp >= 0) {
+                    double gm = ((double)K * d.dz - hh) / ((double)kp * d.dz - hh);
+                    R v[3];
+                    lat_vel<T>(d, G, P, q, I, J, kp, v);
+                    for (int cc = 0; cc < 3; ++cc) u[cc] = v[cc] * (R)gm + ub[cc] * (R)(1.0 - gm);
+                }
+            }
+            qw.mu[p] = (T)u[0]; qw.mv[p] = (T)u[1]; qw.mw[p] = (T)u[2];
+        }
+        int8_t cl = G.cls[p];
+        if (cl == CC_SOLID) { qw.rho[p] = (T)0; qw.rth[p] = (T)0; }
+        else if (cl == CC_ABSORBED) {
+            int64_t m = G.master[p];
+            qw.rho[p] = qw.rho[m];
+            qw.rth[p] = qw.rth[m];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Initial state: theta' at constant pressure on group masters, (rho theta)' = 0, inflow (u0, v0, 0)
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_init_cells(Dims d, Geo G, Phy P, const double *noise, SOut<T> q)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)d.nx * d.ny * d.nz) return;
+    int k = (int)(t % d.nz);
+    int64_t colI = t / d.nz;
+    int64_t c = colI * d.nzs + k;
+    int8_t cl = G.cls[c];
+    double r = 0.0;
+    if (cl == CC_OPEN || cl == CC_ORPHAN) {
+        // rho' = (rho theta)bar/(thetabar + theta') - rhobar without the cancellation
+        double thp = noise ? noise[c] : 0.0;
+        r = thp != 0.0 ? -(P.rhob[k] * thp) / (P.thb[k] + thp) : 0.0;
+    }
+    q.rho[c] = (T)r;
+    q.rth[c] = (T)0;
+    q.mu[c] = (T)0; q.mv[c] = (T)0; q.mw[c] = (T)0;
+}
+
+// perturbation form: m' = rho_c U0 - rhobar_c U0 = rho'_c (u0, v0, 0)
+__global__ void k_init_momentum_pert(Dims d, Geo G, Phy P, SOut<float> q)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)d.nx * d.ny * d.nz) return;
+    int K = (int)(t % d.nz);
+    int64_t colI = t / d.nz;
+    int J = (int)(colI % d.ny), I = (int)(colI / d.ny);
+    int64_t p = cidx(d, I, J, K);
+    if (G.vcls[p] != CC_PRED) return;
+    double sp = 0.0;
+    for (int s = 0; s < 8; ++s)
+        sp += (double)q.rho[cidx(d, I - 1 + (s & 1), J - 1 + ((s >> 1) & 1), K - 1 + (s >> 2))];
+    double rpc = 0.125 * sp;
+    q.mu[p] = (float)(rpc * P.ux);
+    q.mv[p] = (float)(rpc * P.vy);
+    q.mw[p] = 0.0f;
+}
+
+// paper variables: momentum = mean of the eight surrounding cell densities x (u0, v0, 0)
+__global__ void k_init_momentum_full(Dims d, Geo G, Phy P, double u0, double v0, SOut<double> q)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)d.nx * d.ny * d.nz) return;
+    int K = (int)(t % d.nz);
+    int64_t colI = t / d.nz;
+    int J = (int)(colI % d.ny), I = (int)(colI / d.ny);
+    int64_t p = cidx(d, I, J, K);
+    if (G.vcls[p] != CC_PRED) return;
+    auto rt = [&](int a, int b, int kk) { return P.rhob[kk] + q.rho[cidx(d, I + a, J + b, kk)]; };
+    double s0 = (rt(-1, -1, K - 1) + rt(0, -1, K - 1)) + (rt(-1, 0, K - 1) + rt(0, 0, K - 1));
+    double s1 = (rt(-1, -1, K) + rt(0, -1, K)) + (rt(-1, 0, K) + rt(0, 0, K));
+    double rc = 0.125 * (s0 + s1);
+    q.mu[p] = rc * u0;
+    q.mv[p] = rc * v0;
+    q.mw[p] = 0.0;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Conservation sums: fixed grid, fixed per-thread order, fixed tree -> bitwise reproducible.
+// ------------------------------------------------------------------------------------------------
+constexpr int RED_BLOCKS = 1024, RED_THREADS = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_partial(Dims d, Geo G, Phy P, SIn<T> q,
+                                                                double *part)
+{
+    using R = typename Compute<T>::R;
+    __shared__ double sh[4][RED_THREADS];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t n = (int64_t)d.nx * d.ny * d.nz;
+    for (int64_t t = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; t < n;
+         t += (int64_t)RED_BLOCKS * RED_THREADS) {
+        int k = (int)(t % d.nz);
+        int64_t colI = t / d.nz;
+        int j = (int)(colI % d.ny), i = (int)(colI / d.ny);
+        int64_t c = colI * d.nzs + k;
+        int8_t cl = G.cls[c];
+        if (cl == CC_OPEN || cl == CC_ORPHAN) {
+            double vg = G.Vgroup[c] * P.dV;
+            double rp = (double)q.rho[c], tp = (double)q.rth[c];
+            double rho = P.rhob[k] + rp;
+            double p = P.pb[k] + P.pb[k] * expm1(P.gam * log1p(tp / P.rthb[k]));
+            double z = ((double)k + 0.5) * d.dz;
+            acc[0] += vg * rp;
+            acc[1] += vg * tp;
+            acc[2] += vg * rho;
+            acc[3] += vg * (p / (P.gam - 1.0) + rho * P.g * z);
+        }
+        if (G.vcls[c] == CC_PRED) {
+            R u[3];
+            lat_vel<T>(d, G, P, q, i, j, k, u);
+            double rpc = 0.0;
+            for (int s = 0; s < 8; ++s)
+                rpc += (double)q.rho[cidx(d, i - 1 + (s & 1), j - 1 + ((s >> 1) & 1), k - 1 + (s >> 2))];
+            double rc = 0.5 * (P.rhob[k - 1] + P.rhob[k]) + 0.125 * rpc;
+            double uu = (double)u[0] + P.ux, vv = (double)u[1] + P.vy, ww = (double)u[2];
+            acc[3] += P.dV * 0.5 * rc * (uu * uu + vv * vv + ww * ww);
+        }
+    }
+    for (int a = 0; a < 4; ++a) sh[a][threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int a = 0; a < 4; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[(int64_t)blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double *part, double *out)
+{
+    __shared__ double sh[4][RED_THREADS];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < RED_BLOCKS; b += RED_THREADS)
+        for (int a = 0; a < 4; ++a) acc[a] += part[b * 4 + a];
+    for (int a = 0; a < 4; ++a) sh[a][threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int a = 0; a < 4; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// ------------------------------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------------------------------
+static bool make_views(const char *what, const cc_grid *grid, const cc_phys *phys, const cc_geom *g,
+                       const double *base, cc_prec prec, Dims &d, Geo &G, Phy &P)
+{
+    if (!check_grid(grid)) return false;
+    if (!phys || !g || !base) { set_error("%s: null argument", what); return false; }
+    const void *p[] = {g->H, g->V, g->Ax, g->Ay, g->Az, g->nrm, g->Vgroup, g->cls, g->vcls,
+                       g->master, g->gnext, g->colk};
+    if (!check_ptrs(what, 12, p)) return false;
+    if (prec != CC_F64 && prec != CC_F32_PERT) { set_error("%s: unknown precision %d", what, (int)prec); return false; }
+    d = dims_of(grid);
+    G = Geo{g->H, g->V, g->Ax, g->Ay, g->Az, g->nrm, g->Vgroup, g->cls, g->vcls, g->master, g->gnext, g->colk};
+    double cv = phys->cp - phys->rd;
+    P.rhob = base; P.rthb = base + d.nz; P.pb = base + 2 * d.nz; P.thb = base + 3 * d.nz;
+    P.g = phys->g;
+    P.gam = phys->cp / cv;
+    P.ux = prec == CC_F32_PERT ? phys->u0 : 0.0;
+    P.vy = prec == CC_F32_PERT ? phys->v0 : 0.0;
+    P.dV = d.dx * d.dy * d.dz;
+    return true;
+}
+
+static bool state_ok(const char *what, const cc_state *q)
+{
+    if (!q) { set_error("%s: null state", what); return false; }
+    const void *p[] = {q->rho, q->rth, q->mu, q->mv, q->mw};
+    return check_ptrs(what, 5, p);
+}
+
+template <typename T>
+static SIn<T> sin_of(const cc_state *q)
+{
+    return SIn<T>{(const T *)q->rho, (const T *)q->rth, (const T *)q->mu, (const T *)q->mv, (const T *)q->mw};
+}
+template <typename T>
+static SOut<T> sout_of(cc_state *q)
+{
+    return SOut<T>{(T *)q->rho, (T *)q->rth, (T *)q->mu, (T *)q->mv, (T *)q->mw};
+}
+
+template <typename T>
+static void launch_diagnose(const Dims &d, const Geo &G, const Phy &P, cc_state *q, int64_t *st, hipStream_t s)
+{
+    int64_t nc = (int64_t)d.nx * d.ny;
+    hipLaunchKernelGGL(k_diagnose<T>, dim3(blocks_for(nc, 256)), dim3(256), 0, s, d, G, P, sout_of<T>(q), st);
+}
+
+template <typename T, int MODE>
+static void launch_stage(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
+                         cc_state *qo, double cdt, int64_t *st, hipStream_t s)
+{
+    int64_t n = (int64_t)d.nx * d.ny * d.nz;
+    hipLaunchKernelGGL((k_stage_general<T, MODE>), dim3(blocks_for(n, 256)), dim3(256), 0, s, d, G, P,
+                       sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, st);
+}
+
+}  // namespace cc
+
+using namespace cc;
+
+extern "C" cc_status cutcell_init_state(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                                        const double *base, cc_prec prec, const double *noise,
+                                        cc_state *q, int64_t *st, cc_stream_t stream)
+{
+    Dims d; Geo G; Phy P;
+    if (!make_views("cutcell_init_state", grid, phys, geom, base, prec, d, G, P)) return CC_EINVAL;
+    if (!state_ok("cutcell_init_state", q)) return CC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int64_t n = (int64_t)d.nx * d.ny * d.nz;
+    dim3 gb(blocks_for(n, 256)), tb(256);
+    if (prec == CC_F64) {
+        hipLaunchKernelGGL(k_init_cells<double>, gb, tb, 0, s, d, G, P, noise, sout_of<double>(q));
+        hipLaunchKernelGGL(k_init_momentum_full, gb, tb, 0, s, d, G, P, phys->u0, phys->v0, sout_of<double>(q));
+        launch_diagnose<double>(d, G, P, q, st, s);
+    } else {
+        hipLaunchKernelGGL(k_init_cells<float>, gb, tb, 0, s, d, G, P, noise, sout_of<float>(q));
+        hipLaunchKernelGGL(k_init_momentum_pert, gb, tb, 0, s, d, G, P, sout_of<float>(q));
+        launch_diagnose<float>(d, G, P, q, st, s);
+    }
+    return launch_status("cutcell_init_state");
+}
+
+extern "C" cc_status cutcell_diagnose(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                                      const double *base, cc_prec prec, cc_state *q, int64_t *st,
+                                      cc_stream_t stream)
+{
+    Dims d; Geo G; Phy P;
+    if (!make_views("cutcell_diagnose", grid, phys, geom, base, prec, d, G, P)) return CC_EINVAL;
+    if (!state_ok("cutcell_diagnose", q)) return CC_EINVAL;
+    if (prec == CC_F64) launch_diagnose<double>(d, G, P, q, st, (hipStream_t)stream);
+    else launch_diagnose<float>(d, G, P, q, st, (hipStream_t)stream);
+    return launch_status("cutcell_diagnose");
+}
+
+extern "C" cc_status cutcell_tendency(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                                      const double *base, cc_prec prec, const cc_state *q, cc_state *dq,
+                                      cc_stream_t stream)
+{
+    Dims d; Geo G; Phy P;
+    if (!make_views("cutcell_tendency", grid, phys, geom, base, prec, d, G, P)) return CC_EINVAL;
+    if (!state_ok("cutcell_tendency", q) || !state_ok("cutcell_tendency", dq)) return CC_EINVAL;
+    CC_REQUIRE(q->rho != dq->rho, "cutcell_tendency: output aliases input");
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == CC_F64) launch_stage<double, 1>(d, G, P, q, q, dq, 0.0, nullptr, s);
+    else launch_stage<float, 1>(d, G, P, q, q, dq, 0.0, nullptr, s);
+    return launch_status("cutcell_tendency");
+}
+
+extern "C" cc_status cutcell_rk_stage(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                                      const double *base, cc_prec prec, const cc_state *qn,
+                                      const cc_state *qs, cc_state *qo, double cdt, int64_t *st,
+                                      cc_stream_t stream)
+{
+    Dims d; Geo G; Phy P;
+    if (!make_views("cutcell_rk_stage", grid, phys, geom, base, prec, d, G, P)) return CC_EINVAL;
+    if (!state_ok("cutcell_rk_stage", qn) || !state_ok("cutcell_rk_stage", qs) || !state_ok("cutcell_rk_stage", qo))
+        return CC_EINVAL;
+    CC_REQUIRE(qo->rho != qs->rho && qo->rho != qn->rho && qo->mu != qs->mu && qo->mu != qn->mu,
+               "cutcell_rk_stage: q_out must not alias q_n or q_s");
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == CC_F64) {
+        launch_stage<double, 0>(d, G, P, qs, qn, qo, cdt, st, s);
+        launch_diagnose<double>(d, G, P, qo, st, s);
+    } else {
+        launch_stage<float, 0>(d, G, P, qs, qn, qo, cdt, st, s);
+        launch_diagnose<float>(d, G, P, qo, st, s);
+    }
+    return launch_status("cutcell_rk_stage");
+}
+
+extern "C" cc_status cutcell_rk_update(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                                       const double *base, cc_prec prec, const cc_state *qn,
+                                       const cc_state *qs, cc_state *qo, double cdt, int64_t *st,
+                                       cc_stream_t stream)
+{
+    Dims d; Geo G; Phy P;
+    if (!make_views("cutcell_rk_update", grid, phys, geom, base, prec, d, G, P)) return CC_EINVAL;
+    if (!state_ok("cutcell_rk_update", qn) || !state_ok("cutcell_rk_update", qs) || !state_ok("cutcell_rk_update", qo))
+        return CC_EINVAL;
+    CC_REQUIRE(qo->rho != qs->rho && qo->rho != qn->rho && qo->mu != qs->mu && qo->mu != qn->mu,
+               "cutcell_rk_update: q_out must not alias q_n or q_s");
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == CC_F64) launch_stage<double, 0>(d, G, P, qs, qn, qo, cdt, st, s);
+    else launch_stage<float, 0>(d, G, P, qs, qn, qo, cdt, st, s);
+    return launch_status("cutcell_rk_update");
+}
+
+extern "C" size_t cutcell_reduce_workspace(const cc_grid *)
+{
+    return sizeof(double) * 4 * RED_BLOCKS;
+}
+
+extern "C" cc_status cutcell_reduce(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                                    const double *base, cc_prec prec, const cc_state *q, void *ws,
+                                    double *out, cc_stream_t stream)
+{
+    Dims d; Geo G; Phy P;
+    if (!make_views("cutcell_reduce", grid, phys, geom, base, prec, d, G, P)) return CC_EINVAL;
+    if (!state_ok("cutcell_reduce", q)) return CC_EINVAL;
+    CC_REQUIRE(ws && out, "cutcell_reduce: null workspace or output");
+    hipStream_t s = (hipStream_t)stream;
+    double *part = (double *)ws;
+    if (prec == CC_F64)
+        hipLaunchKernelGGL(k_reduce_partial<double>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, d, G, P,
+                           sin_of<double>(q), part);
+    else
+        hipLaunchKernelGGL(k_reduce_partial<float>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, d, G, P,
+                           sin_of<float>(q), part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, part, out);
+    return launch_status("cutcell_reduce");
+}

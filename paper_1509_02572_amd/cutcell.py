@@ -1,0 +1,310 @@
+"""Python binding of libcutcell.so (C ABI in include/cutcell.h).
+
+Argument marshalling only: every step of the cut-cell stage runs in the library's HIP kernels.
+PyTorch provides device memory and the stream.  The functions below carry the same names as the C
+entry points and take torch tensors; ``Domain`` allocates the arrays of one uniform grid and chains
+the calls of a Runge-Kutta step.  Importing this module on a machine without the built library, or
+calling it without a HIP device, raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libcutcell.so")
+
+CC_OK, CC_EINVAL, CC_EDEVICE, CC_EUNMERGEABLE, CC_ENOPLANE, CC_ENONFINITE, CC_ETERRAIN = range(7)
+CC_F64, CC_F32_PERT = 0, 1
+CC_NSTATUS = 8
+SOLID, OPEN, ABSORBED, ORPHAN = 0, 1, 2, 3
+GROUND, PRED, MFACE = 0, 1, 2
+STATUS_NAMES = ("unmergeable", "noplane", "nonfinite", "terrain", "groupsize")
+
+
+class cc_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("nzs", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("nsub", C.c_int32), ("reserved", C.c_int32)]
+
+
+class cc_phys(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("g", "rd", "cp", "p0", "theta0", "bvn", "u0", "v0")]
+
+
+class cc_geom(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("H", "V", "Ax", "Ay", "Az", "col", "nrm", "cls", "dir",
+                                           "vcls", "master", "gnext", "Vgroup", "colk")]
+
+
+class cc_state(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("rho", "rth", "mu", "mv", "mw")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcutcell.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"libcutcell.so not built at {LIBPATH}; run __graft_entry__.build()")
+        L = C.CDLL(LIBPATH)
+        G, P, GM, S = C.POINTER(cc_grid), C.POINTER(cc_phys), C.POINTER(cc_geom), C.POINTER(cc_state)
+        vp, i64p = C.c_void_p, C.c_void_p
+        L.cutcell_version.restype = C.c_char_p
+        L.cutcell_last_error.restype = C.c_char_p
+        L.cutcell_base_state.argtypes = [G, P, vp, vp]
+        L.cutcell_geometry.argtypes = [G, GM, i64p, vp]
+        L.cutcell_merge_map.argtypes = [G, GM, i64p, vp]
+        L.cutcell_init_state.argtypes = [G, P, GM, vp, C.c_int, vp, S, i64p, vp]
+        L.cutcell_diagnose.argtypes = [G, P, GM, vp, C.c_int, S, i64p, vp]
+        L.cutcell_tendency.argtypes = [G, P, GM, vp, C.c_int, S, S, vp]
+        L.cutcell_rk_stage.argtypes = [G, P, GM, vp, C.c_int, S, S, S, C.c_double, i64p, vp]
+        L.cutcell_rk_update.argtypes = [G, P, GM, vp, C.c_int, S, S, S, C.c_double, i64p, vp]
+        L.cutcell_reduce_workspace.argtypes = [G]
+        L.cutcell_reduce_workspace.restype = C.c_size_t
+        L.cutcell_reduce.argtypes = [G, P, GM, vp, C.c_int, S, vp, vp, vp]
+        L.cutcell_check_status.argtypes = [vp, vp, vp]
+        for name in ("cutcell_base_state", "cutcell_geometry", "cutcell_merge_map", "cutcell_init_state",
+                     "cutcell_diagnose", "cutcell_tendency", "cutcell_rk_stage", "cutcell_rk_update", "cutcell_reduce",
+                     "cutcell_check_status"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check(rc: int, what: str):
+    if rc != CC_OK:
+        raise RuntimeError(f"{what} failed ({rc}): {lib().cutcell_last_error().decode()}")
+
+
+def version() -> str:
+    return lib().cutcell_version().decode()
+
+
+# ------------------------------------------------------------------------------------------------
+# entry points with the C names (torch tensors in, status checked)
+# ------------------------------------------------------------------------------------------------
+
+def cutcell_base_state(grid: cc_grid, phys: cc_phys, base: torch.Tensor, stream=None):
+    _check(lib().cutcell_base_state(C.byref(grid), C.byref(phys), _ptr(base), _stream(stream)),
+           "cutcell_base_state")
+
+
+def cutcell_geometry(grid: cc_grid, geom: cc_geom, status: torch.Tensor, stream=None):
+    _check(lib().cutcell_geometry(C.byref(grid), C.byref(geom), _ptr(status), _stream(stream)),
+           "cutcell_geometry")
+
+
+def cutcell_merge_map(grid: cc_grid, geom: cc_geom, status: torch.Tensor, stream=None):
+    _check(lib().cutcell_merge_map(C.byref(grid), C.byref(geom), _ptr(status), _stream(stream)),
+           "cutcell_merge_map")
+
+
+def cutcell_init_state(grid, phys, geom, base, prec, noise, q: cc_state, status, stream=None):
+    _check(lib().cutcell_init_state(C.byref(grid), C.byref(phys), C.byref(geom), _ptr(base), prec,
+                                    _ptr(noise), C.byref(q), _ptr(status), _stream(stream)),
+           "cutcell_init_state")
+
+
+def cutcell_diagnose(grid, phys, geom, base, prec, q: cc_state, status, stream=None):
+    _check(lib().cutcell_diagnose(C.byref(grid), C.byref(phys), C.byref(geom), _ptr(base), prec,
+                                  C.byref(q), _ptr(status), _stream(stream)), "cutcell_diagnose")
+
+
+def cutcell_tendency(grid, phys, geom, base, prec, q: cc_state, dq: cc_state, stream=None):
+    _check(lib().cutcell_tendency(C.byref(grid), C.byref(phys), C.byref(geom), _ptr(base), prec,
+                                  C.byref(q), C.byref(dq), _stream(stream)), "cutcell_tendency")
+
+
+def cutcell_rk_stage(grid, phys, geom, base, prec, qn: cc_state, qs: cc_state, qo: cc_state,
+                     stage_dt: float, status, stream=None):
+    _check(lib().cutcell_rk_stage(C.byref(grid), C.byref(phys), C.byref(geom), _ptr(base), prec,
+                                  C.byref(qn), C.byref(qs), C.byref(qo), stage_dt, _ptr(status),
+                                  _stream(stream)), "cutcell_rk_stage")
+
+
+def cutcell_rk_update(grid, phys, geom, base, prec, qn: cc_state, qs: cc_state, qo: cc_state,
+                      stage_dt: float, status, stream=None):
+    _check(lib().cutcell_rk_update(C.byref(grid), C.byref(phys), C.byref(geom), _ptr(base), prec,
+                                   C.byref(qn), C.byref(qs), C.byref(qo), stage_dt, _ptr(status),
+                                   _stream(stream)), "cutcell_rk_update")
+
+
+def cutcell_reduce(grid, phys, geom, base, prec, q: cc_state, workspace, out, stream=None):
+    _check(lib().cutcell_reduce(C.byref(grid), C.byref(phys), C.byref(geom), _ptr(base), prec,
+                                C.byref(q), _ptr(workspace), _ptr(out), _stream(stream)), "cutcell_reduce")
+
+
+def cutcell_check_status(status: torch.Tensor, stream=None) -> (int, np.ndarray):
+    host = np.zeros(CC_NSTATUS, np.int64)
+    rc = lib().cutcell_check_status(_ptr(status), host.ctypes.data_as(C.c_void_p), _stream(stream))
+    return rc, host
+
+
+# ------------------------------------------------------------------------------------------------
+# Domain: the arrays of one uniform grid on one device
+# ------------------------------------------------------------------------------------------------
+FIELDS = ("rho", "rth", "mu", "mv", "mw")
+
+
+def default_nzs(nz: int) -> int:
+    return (nz + 15) // 16 * 16
+
+
+class State:
+    """Five device arrays of one state (double: paper variables; float: perturbation form)."""
+
+    def __init__(self, n: int, dtype, device):
+        self.t = {f: torch.zeros(n, dtype=dtype, device=device) for f in FIELDS}
+        self.c = cc_state(*[_ptr(self.t[f]) for f in FIELDS])
+
+    def __getitem__(self, f):
+        return self.t[f]
+
+
+class Domain:
+    """Grid, geometry, merge map and base state of one configuration on ``device``.
+
+    ``prec`` is ``"f64"`` (paper variables in double) or ``"f32"`` (float perturbation form)."""
+
+    def __init__(self, cfg, prec: str = "f64", device: str = "cuda:0", nzs: Optional[int] = None,
+                 H: Optional[np.ndarray] = None):
+        from . import workloads
+        if not torch.cuda.is_available():
+            raise RuntimeError("libcutcell needs a HIP device")
+        self.cfg = cfg
+        self.dev = torch.device(device)
+        self.prec = CC_F64 if prec == "f64" else CC_F32_PERT
+        self.dtype = torch.float64 if self.prec == CC_F64 else torch.float32
+        nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
+        self.nzs = nzs or default_nzs(nz)
+        self.n = nx * ny * self.nzs
+        self.grid = cc_grid(nx, ny, nz, self.nzs, cfg.dx, cfg.dy, cfg.dz, cfg.nsub, 0)
+        self.phys = cc_phys(cfg.g, cfg.rd, cfg.cp, cfg.p0, cfg.theta0, cfg.bvn, cfg.u0, cfg.v0)
+        Hn = workloads.terrain(cfg) if H is None else H
+        d, f64, i8, i32 = self.dev, torch.float64, torch.int8, torch.int32
+        nc = nx * ny
+        self.g: Dict[str, torch.Tensor] = {
+            "H": torch.from_numpy(np.ascontiguousarray(Hn, dtype=np.float64).ravel()).to(d),
+            "V": torch.zeros(self.n, dtype=f64, device=d), "Ax": torch.zeros(self.n, dtype=f64, device=d),
+            "Ay": torch.zeros(self.n, dtype=f64, device=d), "Az": torch.zeros(self.n, dtype=f64, device=d),
+            "col": torch.zeros(3 * nc, dtype=f64, device=d), "nrm": torch.zeros(3 * nc, dtype=f64, device=d),
+            "cls": torch.zeros(self.n, dtype=i8, device=d), "dir": torch.zeros(self.n, dtype=i8, device=d),
+            "vcls": torch.zeros(self.n, dtype=i8, device=d), "master": torch.zeros(self.n, dtype=i32, device=d),
+            "gnext": torch.zeros(self.n, dtype=i32, device=d), "Vgroup": torch.zeros(self.n, dtype=f64, device=d),
+            "colk": torch.zeros(2 * nc, dtype=i32, device=d),
+        }
+        self.geom = cc_geom(*[_ptr(self.g[k]) for k in ("H", "V", "Ax", "Ay", "Az", "col", "nrm", "cls",
+                                                         "dir", "vcls", "master", "gnext", "Vgroup", "colk")])
+        self.base = torch.zeros(4 * nz, dtype=f64, device=d)
+        self.status = torch.zeros(CC_NSTATUS, dtype=torch.int64, device=d)
+        self.ws = torch.zeros(lib().cutcell_reduce_workspace(C.byref(self.grid)) // 8 + 1, dtype=f64, device=d)
+        self.red = torch.zeros(4, dtype=f64, device=d)
+        cutcell_base_state(self.grid, self.phys, self.base)
+        cutcell_geometry(self.grid, self.geom, self.status)
+        cutcell_merge_map(self.grid, self.geom, self.status)
+
+    # -- states -------------------------------------------------------------------------------
+    def new_state(self) -> State:
+        return State(self.n, self.dtype, self.dev)
+
+    def pad(self, a: np.ndarray) -> torch.Tensor:
+        """(nx, ny, nz) host array -> padded device vector of the state layout (double)."""
+        cfg = self.cfg
+        out = np.zeros((cfg.nx, cfg.ny, self.nzs))
+        out[:, :, :cfg.nz] = a
+        return torch.from_numpy(out.ravel()).to(self.dev)
+
+    def unpad(self, t: torch.Tensor) -> np.ndarray:
+        cfg = self.cfg
+        return t.detach().cpu().numpy().reshape(cfg.nx, cfg.ny, self.nzs)[:, :, :cfg.nz].copy()
+
+    def init_state(self, noise: Optional[np.ndarray] = None) -> State:
+        q = self.new_state()
+        nt = self.pad(noise) if noise is not None else None
+        cutcell_init_state(self.grid, self.phys, self.geom, self.base, self.prec, nt, q.c, self.status)
+        return q
+
+    # -- hot path -----------------------------------------------------------------------------
+    def diagnose(self, q: State):
+        cutcell_diagnose(self.grid, self.phys, self.geom, self.base, self.prec, q.c, self.status)
+
+    def tendency(self, q: State) -> State:
+        dq = self.new_state()
+        cutcell_tendency(self.grid, self.phys, self.geom, self.base, self.prec, q.c, dq.c)
+        return dq
+
+    def rk_stage(self, qn: State, qs: State, qo: State, stage_dt: float):
+        cutcell_rk_stage(self.grid, self.phys, self.geom, self.base, self.prec, qn.c, qs.c, qo.c,
+                         stage_dt, self.status)
+
+    def rk_update(self, qn: State, qs: State, qo: State, stage_dt: float):
+        cutcell_rk_update(self.grid, self.phys, self.geom, self.base, self.prec, qn.c, qs.c, qo.c,
+                          stage_dt, self.status)
+
+    def step(self, q: State, s1: State, s2: State, dt: float):
+        """One three-stage step; the new state is left in ``s1`` (returns (s1, q, s2) rotated so
+        that the first element is the new state)."""
+        self.rk_stage(q, q, s1, dt / 3.0)
+        self.rk_stage(q, s1, s2, dt / 2.0)
+        self.rk_stage(q, s2, s1, dt)
+        return s1, q, s2
+
+    def run(self, q: State, dt: float, nsteps: int) -> State:
+        a, b, c = q, self.new_state(), self.new_state()
+        for _ in range(nsteps):
+            a, b, c = self.step(a, b, c, dt)
+        return a
+
+    def reduce(self, q: State) -> np.ndarray:
+        cutcell_reduce(self.grid, self.phys, self.geom, self.base, self.prec, q.c, self.ws, self.red)
+        return self.red.cpu().numpy().copy()
+
+    def check(self) -> np.ndarray:
+        rc, host = cutcell_check_status(self.status)
+        return host
+
+    # -- host views ---------------------------------------------------------------------------
+    def geometry_numpy(self) -> Dict[str, np.ndarray]:
+        cfg = self.cfg
+        out = {}
+        for k in ("V", "Ax", "Ay", "Az", "cls", "dir", "vcls", "master", "gnext", "Vgroup"):
+            out[k] = self.unpad(self.g[k])
+        nc = cfg.nx * cfg.ny
+        col = self.g["col"].cpu().numpy().reshape(3, cfg.nx, cfg.ny)
+        out["hc"], out["gx"], out["gy"] = col[0].copy(), col[1].copy(), col[2].copy()
+        out["nrm"] = self.g["nrm"].cpu().numpy().reshape(3, cfg.nx, cfg.ny).copy()
+        out["colk"] = self.g["colk"].cpu().numpy().reshape(2, cfg.nx, cfg.ny).copy()
+        m = out["master"].astype(np.int64)
+        ok = m >= 0  # padded linear index -> unpadded linear index
+        mm = m[ok]
+        k = mm % self.nzs
+        col_ = mm // self.nzs
+        m[ok] = col_ * cfg.nz + k
+        out["master"] = m.astype(np.int32)
+        return out
+
+    def state_numpy(self, q: State) -> Dict[str, np.ndarray]:
+        return {f: self.unpad(q.t[f]).astype(np.float64) for f in FIELDS}

@@ -1,0 +1,306 @@
+"""GPU (HIP, through the C ABI) versus the FP64 CPU oracle.
+
+Bars: classification and merge map bit-exact; geometry bit-exact; FP64 state within 1e-12 relative
+(per field, L-infinity over the points where the field is defined) after 100 steps; FP32
+perturbation form within 1e-5 relative (per field, L2) after 100 steps with mass conserved to
+1e-12 of the total mass.  Large configurations are compared on sampled points.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1509_02572_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CC = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    global CC
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1509_02572_amd import cutcell
+    CC = cutcell
+    CC.lib()
+    O.build(force=False)
+
+
+def _ragged():
+    hills = [(350.0, 600.0, 900.0, 1100.0), (250.0, 400.0, 2600.0, 500.0)]
+    return W.Config("ragged", 37, 29, 23, 100.0, 100.0, 50.0, W.Hill("gauss", extra=hills), u0=7.0,
+                    v0=2.5, bvn=0.012, dt=0.05)
+
+
+def _steep_random():
+    for seed in range(1, 200):
+        H = W.random_corners(6, 6, 6, 100.0, seed, 0.05, 0.6)
+        cfg = W.Config("rand", 6, 6, 6, 100.0, 100.0, 100.0, W.Hill("flat"), H=H, u0=3.0, v0=-2.0, dt=0.02)
+        o = O.Oracle(cfg).merge()
+        d = np.bincount(o.dir.ravel(), minlength=6)
+        if o.counts[0] == 0 and d[2:].sum() > 0:
+            return cfg
+    raise RuntimeError
+
+
+SMALL = {
+    "bell32": lambda: W.get("bell32"),
+    "hemi_tiny": lambda: W.get("hemi_tiny"),
+    "bell_small": lambda: W.get("bell_small"),
+    "ragged": _ragged,
+    "steep_random": _steep_random,
+}
+
+
+def _masters(o):
+    return (o.cls == O.OPEN) | (o.cls == O.ORPHAN)
+
+
+def _compare_state(o, got, ref, tol, what=""):
+    """L-infinity relative error per field over the points where it is defined."""
+    nonsolid = o.cls != O.SOLID
+    pred = o.vcls == O.PRED
+    errs = {}
+    for f in ("rho", "rth"):
+        scale = max(np.abs(ref[f][nonsolid]).max(), 1e-300)
+        errs[f] = np.abs(got[f] - ref[f])[nonsolid].max() / scale
+    for f in ("mu", "mv", "mw"):
+        for name, m in (("pred", pred), ("diag", ~pred)):
+            if not m.any():
+                continue
+            scale = max(np.abs(ref[f][m]).max(), 1e-300)
+            errs[f + "_" + name] = np.abs(got[f] - ref[f])[m].max() / scale
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"{what}: {bad} (all: {errs})"
+    return errs
+
+
+# ------------------------------------------------------------------------------------------------
+# geometry and merge map: bit-exact
+# ------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_geometry_and_merge_map_bitexact(name):
+    cfg = SMALL[name]()
+    print(f"case {name} {cfg.nx}x{cfg.ny}x{cfg.nz}", flush=True)
+    o = O.Oracle(cfg).merge()
+    dom = CC.Domain(cfg, "f64")
+    g = dom.geometry_numpy()
+    for k in ("V", "Ax", "Ay", "Az", "hc", "gx", "gy", "cls", "dir", "vcls", "master", "Vgroup"):
+        assert np.array_equal(g[k], getattr(o, k)), k
+    assert np.abs(g["nrm"] - o.nrm).max() <= 2e-16
+    st = dom.check()
+    assert st[0] == o.counts[0] and not st[3:5].any()
+
+
+@pytest.mark.parametrize("name", ["bell256", "hemi512"])
+def test_full_size_geometry_and_merge_map_bitexact(name):
+    cfg = W.get(name)
+    print(f"case {name} {cfg.nx}x{cfg.ny}x{cfg.nz}", flush=True)
+    o = O.Oracle(cfg).merge()
+    dom = CC.Domain(cfg, "f64")
+    g = dom.geometry_numpy()
+    for k in ("V", "Ax", "Ay", "Az", "cls", "dir", "vcls", "master", "Vgroup"):
+        assert np.array_equal(g[k], getattr(o, k)), k
+    assert o.counts[0] == 0 and not dom.check()[:5].any()
+
+
+# ------------------------------------------------------------------------------------------------
+# FP64: initial state, tendency and 100-step parity
+# ------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_f64_initial_state_and_tendency(name):
+    cfg = SMALL[name]()
+    print(f"case {name}", flush=True)
+    o = O.Oracle(cfg).merge()
+    dom = CC.Domain(cfg, "f64")
+    noise = W.theta_noise(cfg.replace(noise_sigma=0.01, seed=3))
+    q = dom.init_state(noise)
+    q0 = o.init_state(noise)
+    _compare_state(o, dom.state_numpy(q), q0.a, 1e-13, "init")
+    # tendency of a random state whose diagnosed points are filled by each side's own diagnostics
+    rs = W.random_state(cfg, 17)
+    qo = O.State(None, rs)
+    o.diagnose(qo)
+    qg = dom.new_state()
+    for f in O.FIELDS:
+        qg.t[f].copy_(dom.pad(rs[f]))
+    dom.diagnose(qg)
+    _compare_state(o, dom.state_numpy(qg), qo.a, 1e-13, "diagnose")
+    dref = o.tendency(qo)
+    dgot = dom.state_numpy(dom.tendency(qg))
+    pred, mast = o.vcls == O.PRED, _masters(o)
+    for f, m in (("rho", mast), ("rth", mast), ("mu", pred), ("mv", pred), ("mw", pred)):
+        scale = np.abs(dref[f][m]).max()
+        assert np.abs(dgot[f] - dref[f])[m].max() <= 1e-12 * scale, f
+        assert not dgot[f][~m].any(), f
+
+
+@pytest.mark.parametrize("name,steps", [("bell32", 100), ("hemi_tiny", 100), ("bell_small", 100),
+                                        ("ragged", 100), ("steep_random", 100)])
+def test_f64_state_parity_after_steps(name, steps):
+    cfg = SMALL[name]()
+    print(f"case {name} steps {steps}", flush=True)
+    o = O.Oracle(cfg).merge()
+    noise = W.theta_noise(cfg.replace(noise_sigma=0.01, seed=1))
+    ref = o.run(o.init_state(noise), cfg.dt, steps)
+    dom = CC.Domain(cfg, "f64")
+    got = dom.run(dom.init_state(noise), cfg.dt, steps)
+    torch.cuda.synchronize()
+    _compare_state(o, dom.state_numpy(got), ref.a, 1e-12, name)
+    st = dom.check()
+    assert st[0] == o.counts[0] and st[1] == 0 and st[2] == 0
+    # conservation sums agree with the oracle's
+    rg, ro = dom.reduce(got), o.reduce(ref)
+    assert abs(rg[0] - ro[0]) <= 1e-12 * ro[2] and abs(rg[2] - ro[2]) <= 1e-12 * ro[2]
+    assert abs(rg[3] - ro[3]) <= 1e-12 * abs(ro[3])
+
+
+def test_f64_mass_conservation_and_determinism():
+    cfg = W.get("bell_small")
+    dom = CC.Domain(cfg, "f64")
+    noise = W.theta_noise(cfg)
+    q = dom.init_state(noise)
+    r0 = dom.reduce(q)
+    a = dom.run(q, cfg.dt, 50)
+    b = dom.run(q, cfg.dt, 50)
+    r1 = dom.reduce(a)
+    assert abs(r1[0] - r0[0]) <= 1e-12 * r0[2]
+    assert abs(r1[1] - r0[1]) <= 1e-12 * r0[2] * 300
+    for f in CC.FIELDS:
+        assert torch.equal(a.t[f], b.t[f]), f
+
+
+def test_rest_stays_at_rest_on_gpu():
+    cfg = W.get("hemi_tiny").replace(u0=0.0, v0=0.0)
+    o = O.Oracle(cfg).merge()
+    from tests.test_oracle_pins import _hydrostatic_state
+    q = _hydrostatic_state(o)
+    dom = CC.Domain(cfg, "f64")
+    qg = dom.new_state()
+    for f in O.FIELDS:
+        qg.t[f].copy_(dom.pad(q[f]))
+    dom.diagnose(qg)
+    out = dom.state_numpy(dom.run(qg, cfg.dt, 100))
+    for f in ("mu", "mv", "mw"):
+        assert np.abs(out[f]).max() <= 1e-10, f
+
+
+# ------------------------------------------------------------------------------------------------
+# FP32 perturbation form against the FP64 oracle
+# ------------------------------------------------------------------------------------------------
+
+def _full_from_pert(o, got):
+    """Convert the float perturbation state to the paper's variables with the oracle's base state."""
+    cfg = o.cfg
+    pred = o.vcls == O.PRED
+    rbc = np.zeros(cfg.nz)
+    rbc[1:] = 0.5 * (o.rhob[:-1] + o.rhob[1:])
+    out = dict(got)
+    for f, u in (("mu", cfg.u0), ("mv", cfg.v0)):
+        full = got[f] + u
+        full[pred] = got[f][pred] + (rbc[None, None, :] * u * np.ones(o.shape))[pred]
+        out[f] = full
+    return out
+
+
+@pytest.mark.parametrize("name", ["bell_small", "hemi_tiny", "ragged"])
+def test_f32_perturbation_error_after_100_steps(name):
+    cfg = SMALL[name]()
+    print(f"case {name}", flush=True)
+    o = O.Oracle(cfg).merge()
+    noise = W.theta_noise(cfg.replace(noise_sigma=0.01, seed=1))
+    ref = o.run(o.init_state(noise), cfg.dt, 100)
+    dom = CC.Domain(cfg, "f32")
+    q = dom.init_state(noise)
+    r0 = dom.reduce(q)
+    got = dom.run(q, cfg.dt, 100)
+    r1 = dom.reduce(got)
+    g = _full_from_pert(o, dom.state_numpy(got))
+    nonsolid, pred = o.cls != O.SOLID, o.vcls == O.PRED
+    errs = {}
+    for f, m in (("rho", nonsolid), ("rth", nonsolid), ("mu", pred), ("mv", pred), ("mw", pred),
+                 ("mu", ~pred), ("mw", ~pred)):
+        e = np.linalg.norm((g[f] - ref[f])[m]) / np.linalg.norm(ref[f][m])
+        errs[f + ("" if m is nonsolid or m is pred else "_diag")] = e
+    print("f32 errors", name, errs, flush=True)
+    for k, e in errs.items():
+        assert e <= 1e-5, (k, errs)
+    # mass is still conserved to 1e-12 of the total mass
+    assert abs(r1[0] - r0[0]) <= 1e-12 * r0[2]
+
+
+# ------------------------------------------------------------------------------------------------
+# full-size configurations: one stage of the timed path on sampled points
+# ------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,prec", [("bell256", "f64"), ("hemi512", "f64"), ("bell256", "f32"),
+                                       ("hemi512", "f32")])
+def test_full_size_stage_on_sampled_points(name, prec):
+    cfg = W.get(name)
+    print(f"case {name} {prec}", flush=True)
+    o = O.Oracle(cfg).merge()
+    noise = W.theta_noise(cfg)
+    q0 = o.init_state(noise)
+    rng = np.random.Generator(np.random.PCG64(5))
+    # sample the cut band densely and the rest uniformly
+    band = np.flatnonzero(((o.V > 0) & (o.V < 1)).ravel() | (o.vcls != O.PRED).ravel() & (o.cls != O.SOLID).ravel())
+    pts = np.concatenate([rng.choice(band, min(4000, band.size), replace=False),
+                          rng.integers(0, o.V.size, 4000)])
+    L = o.tendency_points(q0, pts)
+    cdt = cfg.dt / 3.0
+    dom = CC.Domain(cfg, prec)
+    qn = dom.init_state(noise)
+    qo = dom.new_state()
+    dom.rk_stage(qn, qn, qo, cdt)
+    got = dom.state_numpy(qo)
+    if prec == "f32":
+        got = _full_from_pert(o, got)
+    mast = _masters(o).ravel()[pts]
+    pred = (o.vcls == O.PRED).ravel()[pts]
+    tol = 1e-12 if prec == "f64" else 1e-5
+    for t, (f, m) in enumerate((("rho", mast), ("rth", mast), ("mu", pred), ("mv", pred), ("mw", pred))):
+        ref = q0[f].ravel()[pts] + cdt * L[:, t]
+        g = got[f].ravel()[pts]
+        scale = max(np.abs(ref[m]).max(), 1e-300)
+        err = np.abs(g - ref)[m].max() / scale
+        print(f"  {f}: rel err {err:.3e}", flush=True)
+        assert err <= tol, (f, err)
+    assert not dom.check()[:5].any()
+
+
+# ------------------------------------------------------------------------------------------------
+# error paths (forced from the host; every kernel exits normally)
+# ------------------------------------------------------------------------------------------------
+
+def test_error_paths():
+    # v-shaped valley: unmergeable cells are counted, as in the oracle
+    nx, ny, nz, d = 8, 4, 8, 100.0
+    I = np.arange(nx)[:, None] + 0 * np.arange(ny)[None, :]
+    H = np.minimum(20.0 + 3.0 * d * np.abs(I - 4).astype(float), 0.6 * nz * d)
+    cfg = W.Config("vvalley", nx, ny, nz, d, d, d, W.Hill("flat"), H=H)
+    o = O.Oracle(cfg).merge()
+    dom = CC.Domain(cfg, "f64")
+    rc, host = CC.cutcell_check_status(dom.status)
+    assert rc == CC.CC_EUNMERGEABLE and host[0] == o.counts[0] > 0
+    assert np.array_equal(dom.geometry_numpy()["cls"], o.cls)
+    # a non-finite value in the state is reported after a stage
+    cfg = W.get("bell32")
+    dom = CC.Domain(cfg, "f64")
+    q = dom.init_state()
+    q.t["rth"][dom.nzs * 40 + 10] = float("nan")
+    s = dom.new_state()
+    dom.rk_stage(q, q, s, cfg.dt)
+    rc, host = CC.cutcell_check_status(dom.status)
+    assert rc == CC.CC_ENONFINITE and host[2] > 0
+    # terrain above the allowed band is reported by the geometry call
+    H = W.terrain(cfg).copy()
+    H[3, 3] = cfg.nz * cfg.dz
+    dom = CC.Domain(cfg.replace(H=H), "f64")
+    rc, host = CC.cutcell_check_status(dom.status)
+    assert host[3] == 1
+    # host-side argument errors
+    with pytest.raises(RuntimeError, match="alias"):
+        dom.rk_stage(q, q, q, 0.1)
