@@ -92,9 +92,15 @@ typedef struct {
                                  of any diagnosed lattice point, absorbed or solid cell */
 } cc_geom;
 
-/* Five prognostic fields; element type double (CC_F64) or float (CC_F32_PERT). */
+/* Five prognostic fields; element type double (CC_F64) or float (CC_F32_PERT).
+ * rho_lo, rth_lo (CC_F32_PERT only, float, nullable): low-order parts of rho' and (rho theta)'.  The
+ * value of the state is rho + rho_lo; the stage that completes a time step adds q_n's low-order part
+ * and stores the rounding remainder of its float result in q_out's, so the cell masses change only
+ * by the FP64 rounding of the flux sums (mass and Theta' stay conserved with float storage).  With
+ * null pointers the float state is rounded plainly.  Ignored by CC_F64. */
 typedef struct {
     void *rho, *rth, *mu, *mv, *mw;
+    void *rho_lo, *rth_lo;
 } cc_state;
 
 const char *cutcell_version(void);
@@ -148,10 +154,12 @@ cc_status cutcell_tendency(const cc_grid *grid, const cc_phys *phys, const cc_ge
 /* One explicit Runge-Kutta stage q_out = q_n + stage_dt * L(q_s) (three-stage scheme of Wicker &
  * Skamarock with stage_dt = dt/3, dt/2, dt; it replaces the paper's leap-frog, Sec. 2.2), followed
  * by the velocity diagnostics of q_out.  q_n may equal q_s; q_out must differ from both.  Non-finite
- * updated values are counted into dev_status[2]. */
+ * updated values are counted into dev_status[2].  final_stage != 0 marks the stage that completes a
+ * time step (the only one that reads q_n's and writes q_out's low-order parts, CC_F32_PERT). */
 cc_status cutcell_rk_stage(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
                            const double *base, cc_prec prec, const cc_state *q_n, const cc_state *q_s,
-                           cc_state *q_out, double stage_dt, int64_t *dev_status, cc_stream_t stream);
+                           cc_state *q_out, double stage_dt, int32_t final_stage, int64_t *dev_status,
+                           cc_stream_t stream);
 
 /* The update half of cutcell_rk_stage alone: q_out = q_n + stage_dt * L(q_s) at group masters
  * and predicted points, solid cells zeroed.  Absorbed cells and diagnosed lattice points of q_out
@@ -159,7 +167,8 @@ cc_status cutcell_rk_stage(const cc_grid *grid, const cc_phys *phys, const cc_ge
  * fused update kernel separately). */
 cc_status cutcell_rk_update(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
                             const double *base, cc_prec prec, const cc_state *q_n, const cc_state *q_s,
-                            cc_state *q_out, double stage_dt, int64_t *dev_status, cc_stream_t stream);
+                            cc_state *q_out, double stage_dt, int32_t final_stage, int64_t *dev_status,
+                            cc_stream_t stream);
 
 /* Conservation sums (FP64, deterministic order): out[4] = { M' = sum Vgroup dV rho',
  * Theta' = sum Vgroup dV (rho theta)', M_total (with the base density at each master's level),

@@ -15,10 +15,12 @@ namespace cc {
 template <typename T>
 struct SIn {
     const T *rho, *rth, *mu, *mv, *mw;
+    const T *rho_lo, *rth_lo;  // low-order parts (float form, nullable)
 };
 template <typename T>
 struct SOut {
     T *rho, *rth, *mu, *mv, *mw;
+    T *rho_lo, *rth_lo;
 };
 
 struct Geo {
@@ -218,7 +220,8 @@ __device__ void momentum_tendency(const Dims &d, const Geo &G, const Phy &P, con
 // and diagnosed lattice points are written by the diagnostic pass that follows.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(256) k_stage_general(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn,
-                                                       SOut<T> qo, double cdt, int64_t *st)
+                                                       SOut<T> qo, double cdt, int final_stage,
+                                                       int64_t *st)
 {
     using R = typename Compute<T>::R;
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -233,11 +236,18 @@ __global__ void __launch_bounds__(256) k_stage_general(Dims d, Geo G, Phy P, SIn
         double L[2];
         group_scalar_tendency<T>(d, G, P, qs, c, L);
         if (MODE == 0) {
-            T a = (T)((double)qn.rho[c] + cdt * L[0]);
-            T b = (T)((double)qn.rth[c] + cdt * L[1]);
+            double x0 = (double)qn.rho[c], x1 = (double)qn.rth[c];
+            if (final_stage && qn.rho_lo) { x0 += (double)qn.rho_lo[c]; x1 += (double)qn.rth_lo[c]; }
+            x0 += cdt * L[0];
+            x1 += cdt * L[1];
+            T a = (T)x0, b = (T)x1;
             bad = !isfinite(a) || !isfinite(b);
             qo.rho[c] = a;
             qo.rth[c] = b;
+            if (final_stage && qo.rho_lo) {  // compensated storage: keep the rounding remainder
+                qo.rho_lo[c] = (T)(x0 - (double)a);
+                qo.rth_lo[c] = (T)(x1 - (double)b);
+            }
         } else {
             qo.rho[c] = (T)L[0];
             qo.rth[c] = (T)L[1];
@@ -245,6 +255,7 @@ __global__ void __launch_bounds__(256) k_stage_general(Dims d, Geo G, Phy P, SIn
     } else if (cl == CC_SOLID || MODE == 1) {
         qo.rho[c] = (T)0;
         qo.rth[c] = (T)0;
+        if (MODE == 0 && final_stage && qo.rho_lo) { qo.rho_lo[c] = (T)0; qo.rth_lo[c] = (T)0; }
     }
     if (G.vcls[c] == CC_PRED) {
         R L[3];
@@ -348,7 +359,7 @@ __global__ void __launch_bounds__(256) k_diagnose(Dims d, Geo G, Phy P, SOut<T> 
     int64_t nc = (int64_t)d.nx * d.ny;
     if (t >= nc) return;
     int I = (int)(t / d.ny), J = (int)(t % d.ny);
-    SIn<T> q{qw.rho, qw.rth, qw.mu, qw.mv, qw.mw};
+    SIn<T> q{qw.rho, qw.rth, qw.mu, qw.mv, qw.mw, qw.rho_lo, qw.rth_lo};
     double n0 = G.nrm[t], n1 = G.nrm[nc + t], n2 = G.nrm[2 * nc + t];
     int dom = (fabs(n2) >= fabs(n0) && fabs(n2) >= fabs(n1)) ? 2 : (fabs(n0) >= fabs(n1) ? 0 : 1);
     R ut[3];
@@ -384,11 +395,14 @@ __global__ void __launch_bounds__(256) k_diagnose(Dims d, Geo G, Phy P, SOut<T> 
             qw.mu[p] = (T)u[0]; qw.mv[p] = (T)u[1]; qw.mw[p] = (T)u[2];
         }
         int8_t cl = G.cls[p];
-        if (cl == CC_SOLID) { qw.rho[p] = (T)0; qw.rth[p] = (T)0; }
-        else if (cl == CC_ABSORBED) {
+        if (cl == CC_SOLID) {
+            qw.rho[p] = (T)0; qw.rth[p] = (T)0;
+            if (qw.rho_lo) { qw.rho_lo[p] = (T)0; qw.rth_lo[p] = (T)0; }
+        } else if (cl == CC_ABSORBED) {
             int64_t m = G.master[p];
             qw.rho[p] = qw.rho[m];
             qw.rth[p] = qw.rth[m];
+            if (qw.rho_lo) { qw.rho_lo[p] = qw.rho_lo[m]; qw.rth_lo[p] = qw.rth_lo[m]; }
         }
     }
 }
@@ -413,6 +427,7 @@ __global__ void k_init_cells(Dims d, Geo G, Phy P, const double *noise, SOut<T> 
     }
     q.rho[c] = (T)r;
     q.rth[c] = (T)0;
+    if (q.rho_lo) { q.rho_lo[c] = (T)(r - (double)(T)r); q.rth_lo[c] = (T)0; }
     q.mu[c] = (T)0; q.mv[c] = (T)0; q.mw[c] = (T)0;
 }
 
@@ -477,6 +492,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_partial(Dims d, Geo G, P
         if (cl == CC_OPEN || cl == CC_ORPHAN) {
             double vg = G.Vgroup[c] * P.dV;
             double rp = (double)q.rho[c], tp = (double)q.rth[c];
+            if (q.rho_lo) { rp += (double)q.rho_lo[c]; tp += (double)q.rth_lo[c]; }
             double rho = P.rhob[k] + rp;
             double p = P.pb[k] + P.pb[k] * expm1(P.gam * log1p(tp / P.rthb[k]));
             double z = ((double)k + 0.5) * d.dz;
@@ -556,12 +572,16 @@ static bool state_ok(const char *what, const cc_state *q)
 template <typename T>
 static SIn<T> sin_of(const cc_state *q)
 {
-    return SIn<T>{(const T *)q->rho, (const T *)q->rth, (const T *)q->mu, (const T *)q->mv, (const T *)q->mw};
+    bool lo = sizeof(T) == 4 && q->rho_lo && q->rth_lo;
+    return SIn<T>{(const T *)q->rho, (const T *)q->rth, (const T *)q->mu, (const T *)q->mv, (const T *)q->mw,
+                  lo ? (const T *)q->rho_lo : nullptr, lo ? (const T *)q->rth_lo : nullptr};
 }
 template <typename T>
 static SOut<T> sout_of(cc_state *q)
 {
-    return SOut<T>{(T *)q->rho, (T *)q->rth, (T *)q->mu, (T *)q->mv, (T *)q->mw};
+    bool lo = sizeof(T) == 4 && q->rho_lo && q->rth_lo;
+    return SOut<T>{(T *)q->rho, (T *)q->rth, (T *)q->mu, (T *)q->mv, (T *)q->mw,
+                   lo ? (T *)q->rho_lo : nullptr, lo ? (T *)q->rth_lo : nullptr};
 }
 
 template <typename T>
@@ -573,11 +593,11 @@ static void launch_diagnose(const Dims &d, const Geo &G, const Phy &P, cc_state 
 
 template <typename T, int MODE>
 static void launch_stage(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
-                         cc_state *qo, double cdt, int64_t *st, hipStream_t s)
+                         cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
 {
     int64_t n = (int64_t)d.nx * d.ny * d.nz;
     hipLaunchKernelGGL((k_stage_general<T, MODE>), dim3(blocks_for(n, 256)), dim3(256), 0, s, d, G, P,
-                       sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, st);
+                       sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, st);
 }
 
 }  // namespace cc
@@ -627,15 +647,15 @@ extern "C" cc_status cutcell_tendency(const cc_grid *grid, const cc_phys *phys, 
     if (!state_ok("cutcell_tendency", q) || !state_ok("cutcell_tendency", dq)) return CC_EINVAL;
     CC_REQUIRE(q->rho != dq->rho, "cutcell_tendency: output aliases input");
     hipStream_t s = (hipStream_t)stream;
-    if (prec == CC_F64) launch_stage<double, 1>(d, G, P, q, q, dq, 0.0, nullptr, s);
-    else launch_stage<float, 1>(d, G, P, q, q, dq, 0.0, nullptr, s);
+    if (prec == CC_F64) launch_stage<double, 1>(d, G, P, q, q, dq, 0.0, 0, nullptr, s);
+    else launch_stage<float, 1>(d, G, P, q, q, dq, 0.0, 0, nullptr, s);
     return launch_status("cutcell_tendency");
 }
 
 extern "C" cc_status cutcell_rk_stage(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
                                       const double *base, cc_prec prec, const cc_state *qn,
-                                      const cc_state *qs, cc_state *qo, double cdt, int64_t *st,
-                                      cc_stream_t stream)
+                                      const cc_state *qs, cc_state *qo, double cdt, int32_t final_stage,
+                                      int64_t *st, cc_stream_t stream)
 {
     Dims d; Geo G; Phy P;
     if (!make_views("cutcell_rk_stage", grid, phys, geom, base, prec, d, G, P)) return CC_EINVAL;
@@ -645,10 +665,10 @@ extern "C" cc_status cutcell_rk_stage(const cc_grid *grid, const cc_phys *phys, 
                "cutcell_rk_stage: q_out must not alias q_n or q_s");
     hipStream_t s = (hipStream_t)stream;
     if (prec == CC_F64) {
-        launch_stage<double, 0>(d, G, P, qs, qn, qo, cdt, st, s);
+        launch_stage<double, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
         launch_diagnose<double>(d, G, P, qo, st, s);
     } else {
-        launch_stage<float, 0>(d, G, P, qs, qn, qo, cdt, st, s);
+        launch_stage<float, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
         launch_diagnose<float>(d, G, P, qo, st, s);
     }
     return launch_status("cutcell_rk_stage");
@@ -656,8 +676,8 @@ extern "C" cc_status cutcell_rk_stage(const cc_grid *grid, const cc_phys *phys, 
 
 extern "C" cc_status cutcell_rk_update(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
                                        const double *base, cc_prec prec, const cc_state *qn,
-                                       const cc_state *qs, cc_state *qo, double cdt, int64_t *st,
-                                       cc_stream_t stream)
+                                       const cc_state *qs, cc_state *qo, double cdt, int32_t final_stage,
+                                       int64_t *st, cc_stream_t stream)
 {
     Dims d; Geo G; Phy P;
     if (!make_views("cutcell_rk_update", grid, phys, geom, base, prec, d, G, P)) return CC_EINVAL;
@@ -666,8 +686,8 @@ extern "C" cc_status cutcell_rk_update(const cc_grid *grid, const cc_phys *phys,
     CC_REQUIRE(qo->rho != qs->rho && qo->rho != qn->rho && qo->mu != qs->mu && qo->mu != qn->mu,
                "cutcell_rk_update: q_out must not alias q_n or q_s");
     hipStream_t s = (hipStream_t)stream;
-    if (prec == CC_F64) launch_stage<double, 0>(d, G, P, qs, qn, qo, cdt, st, s);
-    else launch_stage<float, 0>(d, G, P, qs, qn, qo, cdt, st, s);
+    if (prec == CC_F64) launch_stage<double, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
+    else launch_stage<float, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
     return launch_status("cutcell_rk_update");
 }
 

@@ -42,7 +42,7 @@ class cc_geom(C.Structure):
 
 
 class cc_state(C.Structure):
-    _fields_ = [(n, C.c_void_p) for n in ("rho", "rth", "mu", "mv", "mw")]
+    _fields_ = [(n, C.c_void_p) for n in ("rho", "rth", "mu", "mv", "mw", "rho_lo", "rth_lo")]
 
 
 _lib = None
@@ -65,8 +65,8 @@ def lib():
         L.cutcell_init_state.argtypes = [G, P, GM, vp, C.c_int, vp, S, i64p, vp]
         L.cutcell_diagnose.argtypes = [G, P, GM, vp, C.c_int, S, i64p, vp]
         L.cutcell_tendency.argtypes = [G, P, GM, vp, C.c_int, S, S, vp]
-        L.cutcell_rk_stage.argtypes = [G, P, GM, vp, C.c_int, S, S, S, C.c_double, i64p, vp]
-        L.cutcell_rk_update.argtypes = [G, P, GM, vp, C.c_int, S, S, S, C.c_double, i64p, vp]
+        L.cutcell_rk_stage.argtypes = [G, P, GM, vp, C.c_int, S, S, S, C.c_double, C.c_int32, i64p, vp]
+        L.cutcell_rk_update.argtypes = [G, P, GM, vp, C.c_int, S, S, S, C.c_double, C.c_int32, i64p, vp]
         L.cutcell_reduce_workspace.argtypes = [G]
         L.cutcell_reduce_workspace.restype = C.c_size_t
         L.cutcell_reduce.argtypes = [G, P, GM, vp, C.c_int, S, vp, vp, vp]
@@ -139,17 +139,17 @@ def cutcell_tendency(grid, phys, geom, base, prec, q: cc_state, dq: cc_state, st
 
 
 def cutcell_rk_stage(grid, phys, geom, base, prec, qn: cc_state, qs: cc_state, qo: cc_state,
-                     stage_dt: float, status, stream=None):
+                     stage_dt: float, final_stage: bool, status, stream=None):
     _check(lib().cutcell_rk_stage(C.byref(grid), C.byref(phys), C.byref(geom), _ptr(base), prec,
-                                  C.byref(qn), C.byref(qs), C.byref(qo), stage_dt, _ptr(status),
-                                  _stream(stream)), "cutcell_rk_stage")
+                                  C.byref(qn), C.byref(qs), C.byref(qo), stage_dt, int(final_stage),
+                                  _ptr(status), _stream(stream)), "cutcell_rk_stage")
 
 
 def cutcell_rk_update(grid, phys, geom, base, prec, qn: cc_state, qs: cc_state, qo: cc_state,
-                      stage_dt: float, status, stream=None):
+                      stage_dt: float, final_stage: bool, status, stream=None):
     _check(lib().cutcell_rk_update(C.byref(grid), C.byref(phys), C.byref(geom), _ptr(base), prec,
-                                   C.byref(qn), C.byref(qs), C.byref(qo), stage_dt, _ptr(status),
-                                   _stream(stream)), "cutcell_rk_update")
+                                   C.byref(qn), C.byref(qs), C.byref(qo), stage_dt, int(final_stage),
+                                   _ptr(status), _stream(stream)), "cutcell_rk_update")
 
 
 def cutcell_reduce(grid, phys, geom, base, prec, q: cc_state, workspace, out, stream=None):
@@ -174,11 +174,16 @@ def default_nzs(nz: int) -> int:
 
 
 class State:
-    """Five device arrays of one state (double: paper variables; float: perturbation form)."""
+    """Device arrays of one state (double: paper variables; float: perturbation form with the
+    low-order parts of rho' and (rho theta)')."""
 
     def __init__(self, n: int, dtype, device):
         self.t = {f: torch.zeros(n, dtype=dtype, device=device) for f in FIELDS}
-        self.c = cc_state(*[_ptr(self.t[f]) for f in FIELDS])
+        if dtype == torch.float32:
+            self.t["rho_lo"] = torch.zeros(n, dtype=dtype, device=device)
+            self.t["rth_lo"] = torch.zeros(n, dtype=dtype, device=device)
+        self.c = cc_state(*[_ptr(self.t[f]) for f in FIELDS], _ptr(self.t.get("rho_lo")),
+                          _ptr(self.t.get("rth_lo")))
 
     def __getitem__(self, f):
         return self.t[f]
@@ -256,20 +261,20 @@ class Domain:
         cutcell_tendency(self.grid, self.phys, self.geom, self.base, self.prec, q.c, dq.c)
         return dq
 
-    def rk_stage(self, qn: State, qs: State, qo: State, stage_dt: float):
+    def rk_stage(self, qn: State, qs: State, qo: State, stage_dt: float, final_stage: bool = False):
         cutcell_rk_stage(self.grid, self.phys, self.geom, self.base, self.prec, qn.c, qs.c, qo.c,
-                         stage_dt, self.status)
+                         stage_dt, final_stage, self.status)
 
-    def rk_update(self, qn: State, qs: State, qo: State, stage_dt: float):
+    def rk_update(self, qn: State, qs: State, qo: State, stage_dt: float, final_stage: bool = False):
         cutcell_rk_update(self.grid, self.phys, self.geom, self.base, self.prec, qn.c, qs.c, qo.c,
-                          stage_dt, self.status)
+                          stage_dt, final_stage, self.status)
 
     def step(self, q: State, s1: State, s2: State, dt: float):
         """One three-stage step; the new state is left in ``s1`` (returns (s1, q, s2) rotated so
         that the first element is the new state)."""
         self.rk_stage(q, q, s1, dt / 3.0)
         self.rk_stage(q, s1, s2, dt / 2.0)
-        self.rk_stage(q, s2, s1, dt)
+        self.rk_stage(q, s2, s1, dt, final_stage=True)
         return s1, q, s2
 
     def run(self, q: State, dt: float, nsteps: int) -> State:
@@ -307,4 +312,9 @@ class Domain:
         return out
 
     def state_numpy(self, q: State) -> Dict[str, np.ndarray]:
-        return {f: self.unpad(q.t[f]).astype(np.float64) for f in FIELDS}
+        """Host copy in double; the float form's low-order parts are added to rho', (rho theta)'."""
+        out = {f: self.unpad(q.t[f]).astype(np.float64) for f in FIELDS}
+        if "rho_lo" in q.t:
+            out["rho"] += self.unpad(q.t["rho_lo"]).astype(np.float64)
+            out["rth"] += self.unpad(q.t["rth_lo"]).astype(np.float64)
+        return out
