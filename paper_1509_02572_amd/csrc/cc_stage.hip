@@ -7,7 +7,9 @@
 //            diagnosed velocities as u - (ux, vy, 0).  Fluxes are split into the part carried by
 //            the base state and the uniform reference flow, which is evaluated in double (it is a
 //            static quantity that cancels exactly on regular cells), and the perturbation part,
-//            evaluated and accumulated in float.  Base state, group volumes and sums stay double.
+//            evaluated in float (momentum fluxes also accumulated in float; the few scalar face
+//            fluxes of a cell are summed in double so that their cancellation between neighbours
+//            is exact).  Base state, group volumes and global sums stay double.
 #include "cc_internal.hpp"
 
 namespace cc {
@@ -98,8 +100,11 @@ template <typename T, typename R = typename Compute<T>::R>
 __device__ void group_scalar_tendency(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &q,
                                       int64_t c, double L[2])
 {
-    double rb0 = 0.0, rb1 = 0.0;  // base-state / reference-flow part (double)
-    R rp0 = (R)0, rp1 = (R)0;     // perturbation part
+    double rb0 = 0.0, rb1 = 0.0;  // base-state / reference-flow part
+    // perturbation part: each face flux is evaluated in R; the per-group sum of those fluxes is
+    // formed in double, where a sum of a few floats is exact, so a face contributes exactly
+    // opposite amounts to its two groups and mass is conserved to FP64 rounding
+    double rp0 = 0.0, rp1 = 0.0;
     int kc = (int)(c % d.nzs);
     int64_t mem = c;
     for (int guard = 0; mem >= 0 && guard <= CC_MAX_GROUP; ++guard) {
@@ -146,14 +151,14 @@ __device__ void group_scalar_tendency(const Dims &d, const Geo &G, const Phy &P,
             R f0 = ((R)pb0 * un + pp0 * unt) * AS;
             R f1 = ((R)pb1 * un + pp1 * unt) * AS;
             double g0 = pb0 * Un * A * S, g1 = pb1 * Un * A * S;
-            if (plus) { rp0 += f0; rp1 += f1; rb0 += g0; rb1 += g1; }
-            else { rp0 -= f0; rp1 -= f1; rb0 -= g0; rb1 -= g1; }
+            if (plus) { rp0 += (double)f0; rp1 += (double)f1; rb0 += g0; rb1 += g1; }
+            else { rp0 -= (double)f0; rp1 -= (double)f1; rb0 -= g0; rb1 -= g1; }
         }
         mem = G.gnext[mem];
     }
     double vol = G.Vgroup[c] * P.dV;
-    L[0] = -(rb0 + (double)rp0) / vol;
-    L[1] = -(rb1 + (double)rp1) / vol;
+    L[0] = -(rb0 + rp0) / vol;
+    L[1] = -(rb1 + rp1) / vol;
 }
 
 // ------------------------------------------------------------------------------------------------
