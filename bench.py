@@ -85,7 +85,7 @@ def run_gpu(cfg, prec: str, steps: int, warmup: int):
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"k_stage_general<{'double' if prec == 'f64' else 'float'},0>",
+            "kernel": f"k_stage_tiled<{'double' if prec == 'f64' else 'float'},0>",
             "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(avg_bytes)}
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))

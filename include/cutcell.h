@@ -88,8 +88,9 @@ typedef struct {
     int32_t *master;          /* [cells] linear index of the group master, -1 for solid cells */
     int32_t *gnext;           /* [cells] next member of the master's group (increasing index), -1 */
     double *Vgroup;           /* [cells] group volume fraction, valid at masters */
-    int32_t *colk;            /* [2][nx*ny] per column: first k of the regular interior; 1 + top k
-                                 of any diagnosed lattice point, absorbed or solid cell */
+    int32_t *colk;            /* [3][nx*ny] per column: first k of the regular cell interior; 1 + top
+                                 K of a lattice point that is not predicted; 1 + top level of any
+                                 diagnosed point, absorbed or solid cell */
 } cc_geom;
 
 /* Five prognostic fields; element type double (CC_F64) or float (CC_F32_PERT).

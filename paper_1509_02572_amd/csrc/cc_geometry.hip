@@ -358,10 +358,12 @@ __global__ void k_lattice_class(Dims d, const double *__restrict__ H, const int8
     vcls[p] = all ? CC_PRED : CC_MFACE;
 }
 
-// per column: colk[0] = first k from which every thread index (i,j,k) is regular (a single-cell
-// available group with V = 1, six open faces, available neighbours, and predicted points at its
-// corners and around its lattice point); colk[1] = 1 + top k of any diagnosed lattice point,
-// absorbed or solid cell.
+// Per-column thresholds used by the stage kernels to skip geometry and class reads away from the
+// terrain:
+//   colk[0] (cell band): from this k up every cell is a single-cell available group with V = 1,
+//           six open faces (k >= 1) and available neighbours;
+//   colk[1] (lattice band): 1 + the top level K < nz of a lattice point that is not predicted;
+//   colk[2] (diagnostic top): max(colk[1], 1 + top k of an absorbed or solid cell).
 __global__ void k_column_bands(Dims d, const double *__restrict__ V, const double *__restrict__ Ax,
                                const double *__restrict__ Ay, const double *__restrict__ Az,
                                const int8_t *__restrict__ cls, const int32_t *__restrict__ gnext,
@@ -371,29 +373,23 @@ __global__ void k_column_bands(Dims d, const double *__restrict__ V, const doubl
     int64_t nc = (int64_t)d.nx * d.ny;
     if (t >= nc) return;
     int i = (int)(t / d.ny), j = (int)(t % d.ny);
-    int kfast = 0, kdiag = 0;
+    int kcell = 0, klat = 0, kdiag = 0;
     for (int k = 0; k < d.nz; ++k) {
         int64_t c = cidx(d, i, j, k);
-        int8_t vc = vcls[c], cl = cls[c];
-        if (vc != CC_PRED || cl == CC_ABSORBED || cl == CC_SOLID) kdiag = k + 1;
-        bool sp = cl != CC_OPEN || gnext[c] != -1 || V[c] != 1.0 || vc != CC_PRED;
+        int8_t cl = cls[c];
+        if (vcls[c] != CC_PRED) klat = k + 1;
+        if (cl == CC_ABSORBED || cl == CC_SOLID) kdiag = k + 1;
+        bool sp = k == 0 || cl != CC_OPEN || gnext[c] != -1 || V[c] != 1.0;
         sp = sp || Ax[c] != 1.0 || Ax[cidx(d, i + 1, j, k)] != 1.0 || Ay[c] != 1.0 ||
              Ay[cidx(d, i, j + 1, k)] != 1.0 || Az[c] != 1.0 || (k + 1 < d.nz && Az[c + 1] != 1.0);
         sp = sp || cls[cidx(d, i - 1, j, k)] != CC_OPEN || cls[cidx(d, i + 1, j, k)] != CC_OPEN ||
              cls[cidx(d, i, j - 1, k)] != CC_OPEN || cls[cidx(d, i, j + 1, k)] != CC_OPEN ||
-             (k > 0 && cls[c - 1] != CC_OPEN) || (k + 1 < d.nz && cls[c + 1] != CC_OPEN);
-        for (int q = 0; q < 8 && !sp; ++q) {  // the cell's corners
-            int K = k + (q >> 2);
-            if (K >= d.nz) continue;
-            sp = vcls[cidx(d, i + (q & 1), j + ((q >> 1) & 1), K)] != CC_PRED;
-        }
-        sp = sp || vcls[cidx(d, i - 1, j, k)] != CC_PRED || vcls[cidx(d, i + 1, j, k)] != CC_PRED ||
-             vcls[cidx(d, i, j - 1, k)] != CC_PRED || vcls[cidx(d, i, j + 1, k)] != CC_PRED ||
-             (k == 0 || vcls[c - 1] != CC_PRED) || (k + 1 < d.nz && vcls[c + 1] != CC_PRED);
-        if (sp) kfast = k + 1;
+             cls[c - 1] != CC_OPEN || (k + 1 < d.nz && cls[c + 1] != CC_OPEN);
+        if (sp) kcell = k + 1;
     }
-    colk[t] = kfast;
-    colk[nc + t] = kdiag;
+    colk[t] = kcell;
+    colk[nc + t] = klat;
+    colk[2 * nc + t] = kdiag > klat ? kdiag : klat;
 }
 
 }  // namespace cc

@@ -10,6 +10,12 @@
 //            evaluated in float (momentum fluxes also accumulated in float; the few scalar face
 //            fluxes of a cell are summed in double so that their cancellation between neighbours
 //            is exact).  Base state, group volumes and global sums stay double.
+//
+// Floating-point expressions are evaluated as written (no FMA contraction): a face flux is then
+// bitwise the same whichever of its two cells, and whichever code path, evaluates it, so the flux
+// divergence telescopes exactly and mass is conserved to rounding of the per-cell sums.
+#pragma clang fp contract(off)
+
 #include "cc_internal.hpp"
 
 namespace cc {
@@ -220,60 +226,264 @@ __device__ void momentum_tendency(const Dims &d, const Geo &G, const Phy &P, con
     }
 }
 
-// General path: one thread per cell / lattice index (i,j,k).  MODE 0: q_out = q_n + cdt L(q_s);
-// MODE 1: dq = L(q_s) (zero where no equation is solved).  Solid cells are zeroed; absorbed cells
-// and diagnosed lattice points are written by the diagnostic pass that follows.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_stage_general(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn,
-                                                       SOut<T> qo, double cdt, int final_stage,
-                                                       int64_t *st)
+// ------------------------------------------------------------------------------------------------
+// Tiled update kernel.  A block owns TX x TY columns x TZ levels.  It stages rho', (rho theta)' and
+// p' of the cells around the tile, and the velocities of the lattice points around it, in LDS once,
+// then every thread updates one cell (scalars) and one lattice point (momentum).  Above the
+// per-column bands (colk) cells and lattice points are regular and no geometry or class array is
+// read; inside the bands single-cell groups read their apertures, group volume and neighbour
+// masters, and masters of multi-cell groups take the general gather path.
+// ------------------------------------------------------------------------------------------------
+template <int TX, int TY, int TZ>
+struct Tile {
+    static constexpr int NT = TX * TY * TZ;
+    static constexpr int CX = TX + 3, CY = TY + 3, CZ = TZ + 3, NC = CX * CY * CZ;  // cells from (i0-2, j0-2, k0-2)
+    static constexpr int LX = TX + 2, LY = TY + 2, LZ = TZ + 2, NL = LX * LY * LZ;  // lattice from (i0-1, j0-1, k0-1)
+    __device__ static constexpr int cs(int a, int b, int c) { return (a * CY + b) * CZ + c; }
+    __device__ static constexpr int ls(int a, int b, int c) { return (a * LY + b) * LZ + c; }
+};
+
+// tile origin of this block with an XCD-aware order: blocks are dealt round-robin to the 8 XCDs,
+// so each XCD is given a contiguous range of tiles (k fastest, then j, then i) and shares halos in
+// its own L2
+__device__ __forceinline__ void tile_of_block(int nbx, int nby, int nbz, int &bi, int &bj, int &bk)
+{
+    int nb = nbx * nby * nbz;
+    int b = blockIdx.x;
+    int xcd = b & 7, idx = b >> 3, per = nb >> 3, rem = nb & 7;
+    int lb = xcd * per + (xcd < rem ? xcd : rem) + idx;
+    bk = lb % nbz;
+    int t2 = lb / nbz;
+    bj = t2 % nby;
+    bi = t2 / nby;
+}
+
+template <typename T, int TX, int TY, int TZ, int MODE>
+__global__ void __launch_bounds__(TX * TY * TZ)
+    k_stage_tiled(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn, SOut<T> qo, double cdt, int final_stage,
+                  int nbx, int nby, int nbz, int64_t *st)
 {
     using R = typename Compute<T>::R;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)d.nx * d.ny * d.nz) return;
-    int k = (int)(t % d.nz);
-    int64_t colI = t / d.nz;
-    int j = (int)(colI % d.ny), i = (int)(colI / d.ny);
-    int64_t c = cidx(d, i, j, k);
-    int8_t cl = G.cls[c];
+    using TL = Tile<TX, TY, TZ>;
+    __shared__ R s_rho[TL::NC], s_rth[TL::NC], s_pp[TL::NC];
+    __shared__ R s_u[TL::NL], s_v[TL::NL], s_w[TL::NL];
+    int bi, bj, bk;
+    tile_of_block(nbx, nby, nbz, bi, bj, bk);
+    const int i0 = bi * TX, j0 = bj * TY, k0 = bk * TZ;
+    const int tid = threadIdx.x;
+    const int64_t ncol = (int64_t)d.nx * d.ny;
+    const R Ux = (R)P.ux, Vy = (R)P.vy;
+
+    // phase 1: cell scalars and p' (p' only where a momentum stencil of the tile needs it)
+    for (int e = tid; e < TL::NC; e += TL::NT) {
+        int a = e / (TL::CY * TL::CZ), r = e - a * (TL::CY * TL::CZ), b = r / TL::CZ, c = r - b * TL::CZ;
+        int k = k0 - 2 + c;
+        R rp = (R)0, tp = (R)0, pp = (R)0;
+        if (k >= 0 && k < d.nz) {
+            int64_t ci = cidx(d, i0 - 2 + a, j0 - 2 + b, k);
+            rp = (R)qs.rho[ci];
+            tp = (R)qs.rth[ci];
+            if (a >= 1 && a <= TX && b >= 1 && b <= TY && c >= 1 && c <= TZ)
+                pp = eos_pprime<R>(tp, P.rthb[k], P.pb[k], P.gam);
+        }
+        s_rho[e] = rp;
+        s_rth[e] = tp;
+        s_pp[e] = pp;
+    }
+    __syncthreads();
+    // phase 2: lattice velocities (perturbations from the reference flow)
+    for (int e = tid; e < TL::NL; e += TL::NT) {
+        int a = e / (TL::LY * TL::LZ), r = e - a * (TL::LY * TL::LZ), b = r / TL::LZ, c = r - b * TL::LZ;
+        int K = k0 - 1 + c;
+        R u0 = (R)0, u1 = (R)0, u2 = (R)0;
+        if (K >= 0 && K <= d.nz) {
+            int I = i0 - 1 + a, J = j0 - 1 + b;
+            int Kc = K < d.nz ? K : d.nz - 1;  // the rigid lid copies the level below
+            int64_t p = cidx(d, I, J, Kc);
+            bool pred = Kc >= G.colk[ncol + hidx(d, I, J)] || G.vcls[p] == CC_PRED;
+            if (pred) {
+                int cz = Kc - k0 + 1;  // LDS level of cell level Kc-1
+                R s = ((s_rho[TL::cs(a, b, cz)] + s_rho[TL::cs(a + 1, b, cz)]) +
+                       (s_rho[TL::cs(a, b + 1, cz)] + s_rho[TL::cs(a + 1, b + 1, cz)])) +
+                      ((s_rho[TL::cs(a, b, cz + 1)] + s_rho[TL::cs(a + 1, b, cz + 1)]) +
+                       (s_rho[TL::cs(a, b + 1, cz + 1)] + s_rho[TL::cs(a + 1, b + 1, cz + 1)]));
+                R rpc = s * (R)0.125;
+                R rc = (R)(0.5 * (P.rhob[Kc - 1] + P.rhob[Kc])) + rpc;
+                u0 = ((R)qs.mu[p] - rpc * Ux) / rc;
+                u1 = ((R)qs.mv[p] - rpc * Vy) / rc;
+                u2 = (R)qs.mw[p] / rc;
+            } else {
+                u0 = (R)qs.mu[p];
+                u1 = (R)qs.mv[p];
+                u2 = (R)qs.mw[p];
+            }
+            if (K == d.nz) u2 = (R)0;
+        }
+        s_u[e] = u0;
+        s_v[e] = u1;
+        s_w[e] = u2;
+    }
+    __syncthreads();
+
+    // phase 3: one cell and one lattice point per thread
+    const int tx = tid / (TY * TZ), ty = (tid / TZ) % TY, tz = tid % TZ;
+    const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+    if (i >= d.nx || j >= d.ny || k >= d.nz) return;
+    const int64_t c = cidx(d, i, j, k);
+    const int64_t hc = hidx(d, i, j);
+    const int ca = tx + 2, cb = ty + 2, cc = tz + 2;  // LDS cell coordinates of (i,j,k)
+    const int la = tx + 1, lb = ty + 1, lc = tz + 1;  // LDS lattice coordinates of (i,j,k)
     bool bad = false;
+
+    // ---- scalars ----
+    bool band = k < G.colk[hc];
+    int8_t cl = band ? G.cls[c] : (int8_t)CC_OPEN;
     if (cl == CC_OPEN || cl == CC_ORPHAN) {
-        double L[2];
-        group_scalar_tendency<T>(d, G, P, qs, c, L);
+        double L0, L1;
+        if (band && G.gnext[c] != -1) {  // master of a multi-cell group: general gather
+            double L[2];
+            group_scalar_tendency<T>(d, G, P, qs, c, L);
+            L0 = L[0]; L1 = L[1];
+        } else {
+            double r0 = 0.0, r1 = 0.0, b0 = 0.0, b1 = 0.0;
+            const R rc0 = s_rho[TL::cs(ca, cb, cc)], rc1 = s_rth[TL::cs(ca, cb, cc)];
+            for (int f = 0; f < 6; ++f) {
+                int axis = f >> 1, plus = f & 1;
+                int da = 0, db = 0, dc = 0;
+                if (axis == 0) da = plus ? 1 : -1;
+                else if (axis == 1) db = plus ? 1 : -1;
+                else {
+                    dc = plus ? 1 : -1;
+                    if (k + dc < 0 || k + dc >= d.nz) continue;  // ground and rigid lid
+                }
+                // face "upper" cell (the one whose index carries the face) and aperture
+                double A = 1.0;
+                int kn = k + dc;
+                if (band) {
+                    int64_t fu = cidx(d, i + (axis == 0 && plus), j + (axis == 1 && plus), k + (axis == 2 && plus));
+                    A = axis == 0 ? G.Ax[fu] : (axis == 1 ? G.Ay[fu] : G.Az[fu]);
+                    if (A == 0.0) continue;
+                    int32_t mn = G.master[cidx(d, i + da, j + db, k + dc)];
+                    if (mn < 0) continue;
+                    kn = (int)(mn % d.nzs);
+                }
+                // face corners in canonical order (lattice coordinates of the face)
+                int fa = la + (axis == 0 && plus), fb = lb + (axis == 1 && plus), fc = lc + (axis == 2 && plus);
+                R un;
+                double S, Un;
+                if (axis == 0) {
+                    un = (R)0.25 * ((s_u[TL::ls(fa, fb, fc)] + s_u[TL::ls(fa, fb + 1, fc)]) +
+                                    (s_u[TL::ls(fa, fb, fc + 1)] + s_u[TL::ls(fa, fb + 1, fc + 1)]));
+                    S = d.dy * d.dz; Un = P.ux;
+                } else if (axis == 1) {
+                    un = (R)0.25 * ((s_v[TL::ls(fa, fb, fc)] + s_v[TL::ls(fa + 1, fb, fc)]) +
+                                    (s_v[TL::ls(fa, fb, fc + 1)] + s_v[TL::ls(fa + 1, fb, fc + 1)]));
+                    S = d.dz * d.dx; Un = P.vy;
+                } else {
+                    un = (R)0.25 * ((s_w[TL::ls(fa, fb, fc)] + s_w[TL::ls(fa + 1, fb, fc)]) +
+                                    (s_w[TL::ls(fa, fb + 1, fc)] + s_w[TL::ls(fa + 1, fb + 1, fc)]));
+                    S = d.dx * d.dy; Un = 0.0;
+                }
+                const R rn0 = s_rho[TL::cs(ca + da, cb + db, cc + dc)], rn1 = s_rth[TL::cs(ca + da, cb + db, cc + dc)];
+                int klo = plus ? k : kn, kup = plus ? kn : k;
+                double pb0 = 0.5 * (P.rhob[klo] + P.rhob[kup]);
+                double pb1 = 0.5 * (P.rthb[klo] + P.rthb[kup]);
+                R pp0 = plus ? (R)0.5 * (rc0 + rn0) : (R)0.5 * (rn0 + rc0);
+                R pp1 = plus ? (R)0.5 * (rc1 + rn1) : (R)0.5 * (rn1 + rc1);
+                R AS = (R)(A * S);
+                R unt = un + (R)Un;
+                R f0 = ((R)pb0 * un + pp0 * unt) * AS;
+                R f1 = ((R)pb1 * un + pp1 * unt) * AS;
+                if (plus) { r0 += (double)f0; r1 += (double)f1; }
+                else { r0 -= (double)f0; r1 -= (double)f1; }
+                if (band) {  // base-state / reference-flow flux: cancels exactly on regular cells
+                    double g0 = pb0 * Un * A * S, g1 = pb1 * Un * A * S;
+                    if (plus) { b0 += g0; b1 += g1; } else { b0 -= g0; b1 -= g1; }
+                }
+            }
+            double vol = (band ? G.Vgroup[c] : 1.0) * P.dV;
+            L0 = -(b0 + r0) / vol;
+            L1 = -(b1 + r1) / vol;
+        }
         if (MODE == 0) {
             double x0 = (double)qn.rho[c], x1 = (double)qn.rth[c];
             if (final_stage && qn.rho_lo) { x0 += (double)qn.rho_lo[c]; x1 += (double)qn.rth_lo[c]; }
-            x0 += cdt * L[0];
-            x1 += cdt * L[1];
+            x0 += cdt * L0;
+            x1 += cdt * L1;
             T a = (T)x0, b = (T)x1;
             bad = !isfinite(a) || !isfinite(b);
             qo.rho[c] = a;
             qo.rth[c] = b;
-            if (final_stage && qo.rho_lo) {  // compensated storage: keep the rounding remainder
+            if (final_stage && qo.rho_lo) {
                 qo.rho_lo[c] = (T)(x0 - (double)a);
                 qo.rth_lo[c] = (T)(x1 - (double)b);
             }
         } else {
-            qo.rho[c] = (T)L[0];
-            qo.rth[c] = (T)L[1];
+            qo.rho[c] = (T)L0;
+            qo.rth[c] = (T)L1;
         }
     } else if (cl == CC_SOLID || MODE == 1) {
         qo.rho[c] = (T)0;
         qo.rth[c] = (T)0;
         if (MODE == 0 && final_stage && qo.rho_lo) { qo.rho_lo[c] = (T)0; qo.rth_lo[c] = (T)0; }
     }
-    if (G.vcls[c] == CC_PRED) {
-        R L[3];
-        momentum_tendency<T>(d, G, P, qs, i, j, k, L);
+
+    // ---- momentum at the lattice point (i,j,k) ----
+    bool pred = k >= G.colk[ncol + hc] || G.vcls[c] == CC_PRED;
+    if (pred) {
+        R u[7][3];
+        const int off[7][3] = {{0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+        for (int s = 0; s < 7; ++s) {
+            int e = TL::ls(la + off[s][0], lb + off[s][1], lc + off[s][2]);
+            u[s][0] = s_u[e]; u[s][1] = s_v[e]; u[s][2] = s_w[e];
+        }
+        R rp[8], pp[8];  // bit0: i-1/i, bit1: j-1/j, bit2: k-1/k
+        for (int s = 0; s < 8; ++s) {
+            int e = TL::cs(ca - 1 + (s & 1), cb - 1 + ((s >> 1) & 1), cc - 1 + (s >> 2));
+            rp[s] = s_rho[e];
+            pp[s] = s_pp[e];
+        }
+        R q4 = (R)0.25;
+        R rxm = q4 * ((rp[0] + rp[2]) + (rp[4] + rp[6])), rxp = q4 * ((rp[1] + rp[3]) + (rp[5] + rp[7]));
+        R rym = q4 * ((rp[0] + rp[1]) + (rp[4] + rp[5])), ryp = q4 * ((rp[2] + rp[3]) + (rp[6] + rp[7]));
+        R rzm = q4 * ((rp[0] + rp[1]) + (rp[2] + rp[3])), rzp = q4 * ((rp[4] + rp[5]) + (rp[6] + rp[7]));
+        R pxm = q4 * ((pp[0] + pp[2]) + (pp[4] + pp[6])), pxp = q4 * ((pp[1] + pp[3]) + (pp[5] + pp[7]));
+        R pym = q4 * ((pp[0] + pp[1]) + (pp[4] + pp[5])), pyp = q4 * ((pp[2] + pp[3]) + (pp[6] + pp[7]));
+        R pzm = q4 * ((pp[0] + pp[1]) + (pp[2] + pp[3])), pzp = q4 * ((pp[4] + pp[5]) + (pp[6] + pp[7]));
+        R r8 = (R)0.125 * (((rp[0] + rp[1]) + (rp[2] + rp[3])) + ((rp[4] + rp[5]) + (rp[6] + rp[7])));
+        R rbc = (R)(0.5 * (P.rhob[k - 1] + P.rhob[k]));
+        R rbzm = (R)P.rhob[k - 1], rbzp = (R)P.rhob[k];
+        R h = (R)0.5;
+        R Lm[3];
+        for (int cm = 0; cm < 3; ++cm) {
+            R M0 = cm == 0 ? Ux : (cm == 1 ? Vy : (R)0);
+            R ub, mb;
+            ub = h * (u[0][0] + u[2][0]); mb = h * (u[0][cm] + u[2][cm]);
+            R fxp = rbc * (Ux * mb + ub * M0 + ub * mb) + rxp * (Ux + ub) * (M0 + mb);
+            ub = h * (u[1][0] + u[0][0]); mb = h * (u[1][cm] + u[0][cm]);
+            R fxm = rbc * (Ux * mb + ub * M0 + ub * mb) + rxm * (Ux + ub) * (M0 + mb);
+            ub = h * (u[0][1] + u[4][1]); mb = h * (u[0][cm] + u[4][cm]);
+            R fyp = rbc * (Vy * mb + ub * M0 + ub * mb) + ryp * (Vy + ub) * (M0 + mb);
+            ub = h * (u[3][1] + u[0][1]); mb = h * (u[3][cm] + u[0][cm]);
+            R fym = rbc * (Vy * mb + ub * M0 + ub * mb) + rym * (Vy + ub) * (M0 + mb);
+            ub = h * (u[0][2] + u[6][2]); mb = h * (u[0][cm] + u[6][cm]);
+            R fzp = (rbzp + rzp) * ub * (M0 + mb);
+            ub = h * (u[5][2] + u[0][2]); mb = h * (u[5][cm] + u[0][cm]);
+            R fzm = (rbzm + rzm) * ub * (M0 + mb);
+            R adv = (fxp - fxm) / (R)d.dx + (fyp - fym) / (R)d.dy + (fzp - fzm) / (R)d.dz;
+            R pgf = cm == 0 ? (pxp - pxm) / (R)d.dx : (cm == 1 ? (pyp - pym) / (R)d.dy : (pzp - pzm) / (R)d.dz);
+            R buoy = cm == 2 ? (R)P.g * r8 : (R)0;
+            Lm[cm] = -adv - pgf - buoy;
+        }
         if (MODE == 0) {
             R cd = (R)cdt;
-            T a = (T)((R)qn.mu[c] + cd * L[0]);
-            T b = (T)((R)qn.mv[c] + cd * L[1]);
-            T e = (T)((R)qn.mw[c] + cd * L[2]);
+            T a = (T)((R)qn.mu[c] + cd * Lm[0]);
+            T b = (T)((R)qn.mv[c] + cd * Lm[1]);
+            T e = (T)((R)qn.mw[c] + cd * Lm[2]);
             bad = bad || !isfinite(a) || !isfinite(b) || !isfinite(e);
             qo.mu[c] = a; qo.mv[c] = b; qo.mw[c] = e;
         } else {
-            qo.mu[c] = (T)L[0]; qo.mv[c] = (T)L[1]; qo.mw[c] = (T)L[2];
+            qo.mu[c] = (T)Lm[0]; qo.mv[c] = (T)Lm[1]; qo.mw[c] = (T)Lm[2];
         }
     } else if (MODE == 1) {
         qo.mu[c] = (T)0; qo.mv[c] = (T)0; qo.mw[c] = (T)0;
@@ -357,7 +567,7 @@ __device__ bool plane_family(const Dims &d, const Geo &G, const Phy &P, const SI
 // one thread per column corner (I,J): boundary velocity (free-slip projection of the nearest-plane
 // mean, eq. 33), then every diagnosed lattice point and absorbed/solid cell of the column
 template <typename T>
-__global__ void __launch_bounds__(256) k_diagnose(Dims d, Geo G, Phy P, SOut<T> qw, int64_t *st)
+__global__ void __launch_bounds__(64) k_diagnose(Dims d, Geo G, Phy P, SOut<T> qw, int64_t *st)
 {
     using R = typename Compute<T>::R;
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -379,7 +589,7 @@ __global__ void __launch_bounds__(256) k_diagnose(Dims d, Geo G, Phy P, SOut<T> 
     R dn = (ut[0] + (R)P.ux) * (R)n0 + (ut[1] + (R)P.vy) * (R)n1 + ut[2] * (R)n2;
     R ub[3] = {ut[0] - dn * (R)n0, ut[1] - dn * (R)n1, ut[2] - dn * (R)n2};
     double hh = G.H[t];
-    int ktop = G.colk[nc + t];
+    int ktop = G.colk[2 * nc + t];
     int64_t base = cidx(d, I, J, 0);
     for (int K = 0; K < ktop; ++K) {
         int64_t p = base + K;
@@ -593,16 +803,17 @@ template <typename T>
 static void launch_diagnose(const Dims &d, const Geo &G, const Phy &P, cc_state *q, int64_t *st, hipStream_t s)
 {
     int64_t nc = (int64_t)d.nx * d.ny;
-    hipLaunchKernelGGL(k_diagnose<T>, dim3(blocks_for(nc, 256)), dim3(256), 0, s, d, G, P, sout_of<T>(q), st);
+    hipLaunchKernelGGL(k_diagnose<T>, dim3(blocks_for(nc, 64)), dim3(64), 0, s, d, G, P, sout_of<T>(q), st);
 }
 
 template <typename T, int MODE>
 static void launch_stage(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
                          cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
 {
-    int64_t n = (int64_t)d.nx * d.ny * d.nz;
-    hipLaunchKernelGGL((k_stage_general<T, MODE>), dim3(blocks_for(n, 256)), dim3(256), 0, s, d, G, P,
-                       sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, st);
+    constexpr int TX = 4, TY = 4, TZ = 16;
+    int nbx = (d.nx + TX - 1) / TX, nby = (d.ny + TY - 1) / TY, nbz = (d.nz + TZ - 1) / TZ;
+    hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE>), dim3(nbx * nby * nbz), dim3(TX * TY * TZ), 0, s, d,
+                       G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, nbx, nby, nbz, st);
 }
 
 }  // namespace cc

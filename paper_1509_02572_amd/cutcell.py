@@ -219,7 +219,7 @@ class Domain:
             "cls": torch.zeros(self.n, dtype=i8, device=d), "dir": torch.zeros(self.n, dtype=i8, device=d),
             "vcls": torch.zeros(self.n, dtype=i8, device=d), "master": torch.zeros(self.n, dtype=i32, device=d),
             "gnext": torch.zeros(self.n, dtype=i32, device=d), "Vgroup": torch.zeros(self.n, dtype=f64, device=d),
-            "colk": torch.zeros(2 * nc, dtype=i32, device=d),
+            "colk": torch.zeros(3 * nc, dtype=i32, device=d),
         }
         self.geom = cc_geom(*[_ptr(self.g[k]) for k in ("H", "V", "Ax", "Ay", "Az", "col", "nrm", "cls",
                                                          "dir", "vcls", "master", "gnext", "Vgroup", "colk")])
@@ -301,7 +301,7 @@ class Domain:
         col = self.g["col"].cpu().numpy().reshape(3, cfg.nx, cfg.ny)
         out["hc"], out["gx"], out["gy"] = col[0].copy(), col[1].copy(), col[2].copy()
         out["nrm"] = self.g["nrm"].cpu().numpy().reshape(3, cfg.nx, cfg.ny).copy()
-        out["colk"] = self.g["colk"].cpu().numpy().reshape(2, cfg.nx, cfg.ny).copy()
+        out["colk"] = self.g["colk"].cpu().numpy().reshape(3, cfg.nx, cfg.ny).copy()
         m = out["master"].astype(np.int64)
         ok = m >= 0  # padded linear index -> unpadded linear index
         mm = m[ok]
