@@ -274,7 +274,8 @@ __global__ void __launch_bounds__(TX * TY * TZ)
     const int64_t ncol = (int64_t)d.nx * d.ny;
     const R Ux = (R)P.ux, Vy = (R)P.vy;
 
-    // phase 1: cell scalars and p' (p' only where a momentum stencil of the tile needs it)
+    // phase 1: cell scalars and p' (p' only for the cells (i0-1..i0+TX-1, ...) that the momentum
+    // stencils of the tile use)
     for (int e = tid; e < TL::NC; e += TL::NT) {
         int a = e / (TL::CY * TL::CZ), r = e - a * (TL::CY * TL::CZ), b = r / TL::CZ, c = r - b * TL::CZ;
         int k = k0 - 2 + c;
@@ -283,7 +284,7 @@ __global__ void __launch_bounds__(TX * TY * TZ)
             int64_t ci = cidx(d, i0 - 2 + a, j0 - 2 + b, k);
             rp = (R)qs.rho[ci];
             tp = (R)qs.rth[ci];
-            if (a >= 1 && a <= TX && b >= 1 && b <= TY && c >= 1 && c <= TZ)
+            if (a >= 1 && a <= TX + 1 && b >= 1 && b <= TY + 1 && c >= 1 && c <= TZ + 1)
                 pp = eos_pprime<R>(tp, P.rthb[k], P.pb[k], P.gam);
         }
         s_rho[e] = rp;
