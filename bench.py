@@ -42,8 +42,12 @@ def run_gpu(cfg, prec: str, steps: int, warmup: int):
     from paper_1509_02572_amd import cutcell as CC
     from paper_1509_02572_amd import workloads as W
 
+    from paper_1509_02572_amd import autotune
     dom = CC.Domain(cfg, prec, "cuda:0")
     q = dom.init_state(W.theta_noise(cfg))
+    tuned = autotune.tune(dom, q, path=None, dt=cfg.dt)  # untimed: picks the tile shape
+    log(f"bench: {prec} tile timings (ms per update launch): "
+        + ", ".join(f"{k}{autotune.TILE_IDS[k]}={v:.4f}" for k, v in tuned["ms"].items()))
     a, b, c = q, dom.new_state(), dom.new_state()
     dt = cfg.dt
     esz = 8 if prec == "f64" else 4
@@ -94,6 +98,7 @@ def run_gpu(cfg, prec: str, steps: int, warmup: int):
             roof["traffic"] = ent["hbm_bytes_per_launch"]
     value = ncell * 3 * steps / secs
     red = dom.reduce(a)
+    roof["tile"] = list(autotune.TILE_IDS[tuned["tile"]])
     return {"value": value, "ms_per_step": secs / steps * 1e3, "roofline": roof,
             "mass_total": float(red[2]), "mass_pert": float(red[0])}
 
@@ -122,12 +127,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the cut-cell stage is measured on a single MI355X); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     from paper_1509_02572_amd import workloads as W
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copy calibration: 3 copies of 1 GiB (1 GiB read + 1 GiB written each)")
+        del src, dst
     cfg = W.get("bell256")
     other = "f64" if args.prec == "f32" else "f32"
     log(f"bench: {cfg.name} {cfg.nx}x{cfg.ny}x{cfg.nz} prec={args.prec} steps={args.steps} warmup={args.warmup}")

@@ -68,7 +68,8 @@ typedef struct {
     int32_t nx, ny, nz, nzs; /* cells; padded k stride (nzs >= nz) */
     double dx, dy, dz;       /* spacings [m] */
     int32_t nsub;            /* sub-columns per cell edge for volumes/apertures, power of two */
-    int32_t reserved;
+    int32_t tile;            /* tile shape of the update kernel (0 = default; 1..8 see the tuning
+                                table of the stage kernels); results do not depend on it */
 } cc_grid;
 
 typedef struct {
@@ -108,8 +109,10 @@ const char *cutcell_version(void);
 const char *cutcell_last_error(void);
 
 /* Base state on cell centres z_k = (k+1/2) dz (Sec. 2.1 hydrostatic reference; constant N and
- * theta0 at z = 0, surface pressure p0, Sec. 3).  base: [4*nz] doubles = rhobar, (rho theta)bar,
- * pbar, thetabar; pbar follows from (rho theta)bar through the equation of state. */
+ * theta0 at z = 0, surface pressure p0, Sec. 3).  base: [6*nz] doubles = rhobar, (rho theta)bar,
+ * pbar, thetabar, 1/(rho theta)bar, and at lattice level K the mean of rhobar at levels K-1 and K;
+ * pbar follows from (rho theta)bar through the equation of state.  Every other call takes this
+ * array as `base`. */
 cc_status cutcell_base_state(const cc_grid *grid, const cc_phys *phys, double *base, cc_stream_t stream);
 
 /* Cut-cell geometry (Sec. 2.3): bilinear terrain per column (eq. bilin) from the corner heights H,

@@ -35,6 +35,15 @@ __global__ void k_base_state(int nz, double dz, cc_phys ph, double *base)
     base[nz + k] = rth;                                          // (rho theta)bar
     base[2 * nz + k] = ph.p0 * pow(ph.rd * rth / ph.p0, ph.cp / cv);  // pbar
     base[3 * nz + k] = th;                                       // thetabar
+    base[4 * nz + k] = 1.0 / rth;                                // 1 / (rho theta)bar
+}
+
+// mean base density of the two cell levels around lattice level K (K = 0: the lowest level)
+__global__ void k_base_lattice(int nz, double *base)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nz) return;
+    base[5 * nz + k] = k > 0 ? 0.5 * (base[k - 1] + base[k]) : base[0];
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -403,6 +412,8 @@ extern "C" cc_status cutcell_base_state(const cc_grid *grid, const cc_phys *phys
     CC_REQUIRE(phys && base, "cutcell_base_state: null argument");
     hipLaunchKernelGGL(k_base_state, dim3(blocks_for(grid->nz, 64)), dim3(64), 0, (hipStream_t)stream,
                        grid->nz, grid->dz, *phys, base);
+    hipLaunchKernelGGL(k_base_lattice, dim3(blocks_for(grid->nz, 64)), dim3(64), 0, (hipStream_t)stream,
+                       grid->nz, base);
     return launch_status("cutcell_base_state");
 }
 

@@ -37,9 +37,15 @@ struct Geo {
     const int32_t *master, *gnext, *colk;
 };
 
+constexpr int EOS_TERMS = 11;  // binomial series terms of (1+x)^gamma - 1 (double; float uses 6)
+constexpr double EOS_XMAX = 0.03;  // |x| above which the exact form is used
+
 struct Phy {
     const double *rhob, *rthb, *pb, *thb;  // base state at cell centres [nz]
-    double g, gam, ux, vy, dV;
+    const double *irthb;                   // 1 / (rho theta)bar [nz]
+    const double *rhobc;                   // mean base density of levels K-1, K at lattice level K [nz]
+    double g, gam, ux, vy, dV, idV, idx, idy, idz;
+    double binom[EOS_TERMS];               // (1+x)^gamma - 1 = sum_n binom[n-1] x^n
 };
 
 template <typename T>
@@ -66,6 +72,28 @@ __device__ __forceinline__ R eos_pprime(R rthp, double rthb, double pb, double g
     return (R)pb * expm1_r((R)gam * log1p_r(rthp / (R)rthb));
 }
 
+// the same p' for cell level k, evaluated with the binomial series of (1+x)^gamma when
+// |x| = |rth'/rthbar| <= EOS_XMAX (truncation below the storage precision: 6 terms in float, 11 in
+// double), otherwise with the exact form
+template <typename R>
+__device__ __forceinline__ R eos_pprime_k(R rthp, int k, const Phy &P)
+{
+    R x = rthp * (R)P.irthb[k];
+    R ax = x < (R)0 ? -x : x;
+    if (ax > (R)EOS_XMAX) return (R)P.pb[k] * expm1_r((R)P.gam * log1p_r(x));
+    constexpr int NTERM = sizeof(R) == 4 ? 6 : EOS_TERMS;
+    R acc = (R)P.binom[NTERM - 1];
+#pragma unroll
+    for (int n = NTERM - 2; n >= 0; --n) acc = (R)P.binom[n] + x * acc;
+    return (R)P.pb[k] * (x * acc);
+}
+
+// reciprocal used for velocities: hardware reciprocal in float (deterministic, 1 ulp), IEEE in double
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+__device__ __forceinline__ int wrap1(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
 // Velocity (perturbation from the reference flow) at lattice point (I,J,K).
 // Predicted points divide the momentum by the mean of the eight surrounding cell densities;
 // diagnosed points store the velocity; the rigid lid (K = nz) has w = 0 and copies (u, v) of the
@@ -83,10 +111,10 @@ __device__ __forceinline__ void lat_vel(const Dims &d, const Geo &G, const Phy &
         R s = (((R)q.rho[c00] + (R)q.rho[c10]) + ((R)q.rho[c01] + (R)q.rho[c11])) +
               (((R)q.rho[c00 + 1] + (R)q.rho[c10 + 1]) + ((R)q.rho[c01 + 1] + (R)q.rho[c11 + 1]));
         R rpc = s * (R)0.125;
-        R rc = (R)(0.5 * (P.rhob[K - 1] + P.rhob[K])) + rpc;
-        u[0] = ((R)q.mu[p] - rpc * (R)P.ux) / rc;
-        u[1] = ((R)q.mv[p] - rpc * (R)P.vy) / rc;
-        u[2] = (R)q.mw[p] / rc;
+        R ri = recip((R)P.rhobc[K] + rpc);
+        u[0] = ((R)q.mu[p] - rpc * (R)P.ux) * ri;
+        u[1] = ((R)q.mv[p] - rpc * (R)P.vy) * ri;
+        u[2] = (R)q.mw[p] * ri;
     } else {
         u[0] = (R)q.mu[p];
         u[1] = (R)q.mv[p];
@@ -168,65 +196,6 @@ __device__ void group_scalar_tendency(const Dims &d, const Geo &G, const Phy &P,
 }
 
 // ------------------------------------------------------------------------------------------------
-// Momentum tendency at a predicted point (eqs. momentum_u_d, momentum_v_d, momentum_w_d): advection
-// through the six faces of the rectangular velocity cell (face density = mean of the four cell
-// densities on the face, velocities averaged along the face normal), second-order pressure
-// gradient of p' and buoyancy -rho' g.  In the perturbation form the base-state/reference-flow
-// product rhobar U0 M0 cancels identically between opposite faces and is left out.
-// ------------------------------------------------------------------------------------------------
-template <typename T, typename R = typename Compute<T>::R>
-__device__ void momentum_tendency(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &q, int i,
-                                  int j, int k, R L[3])
-{
-    R u[7][3];
-    lat_vel<T>(d, G, P, q, i, j, k, u[0]);
-    lat_vel<T>(d, G, P, q, i - 1, j, k, u[1]);
-    lat_vel<T>(d, G, P, q, i + 1, j, k, u[2]);
-    lat_vel<T>(d, G, P, q, i, j - 1, k, u[3]);
-    lat_vel<T>(d, G, P, q, i, j + 1, k, u[4]);
-    lat_vel<T>(d, G, P, q, i, j, k - 1, u[5]);
-    lat_vel<T>(d, G, P, q, i, j, k + 1, u[6]);
-    R rp[8], pp[8];  // bit0: i-1/i, bit1: j-1/j, bit2: k-1/k
-    for (int s = 0; s < 8; ++s) {
-        int kk = k - 1 + (s >> 2);
-        int64_t cc = cidx(d, i - 1 + (s & 1), j - 1 + ((s >> 1) & 1), kk);
-        rp[s] = (R)q.rho[cc];
-        pp[s] = eos_pprime<R>((R)q.rth[cc], P.rthb[kk], P.pb[kk], P.gam);
-    }
-    R q4 = (R)0.25;
-    R rxm = q4 * ((rp[0] + rp[2]) + (rp[4] + rp[6])), rxp = q4 * ((rp[1] + rp[3]) + (rp[5] + rp[7]));
-    R rym = q4 * ((rp[0] + rp[1]) + (rp[4] + rp[5])), ryp = q4 * ((rp[2] + rp[3]) + (rp[6] + rp[7]));
-    R rzm = q4 * ((rp[0] + rp[1]) + (rp[2] + rp[3])), rzp = q4 * ((rp[4] + rp[5]) + (rp[6] + rp[7]));
-    R pxm = q4 * ((pp[0] + pp[2]) + (pp[4] + pp[6])), pxp = q4 * ((pp[1] + pp[3]) + (pp[5] + pp[7]));
-    R pym = q4 * ((pp[0] + pp[1]) + (pp[4] + pp[5])), pyp = q4 * ((pp[2] + pp[3]) + (pp[6] + pp[7]));
-    R pzm = q4 * ((pp[0] + pp[1]) + (pp[2] + pp[3])), pzp = q4 * ((pp[4] + pp[5]) + (pp[6] + pp[7]));
-    R r8 = (R)0.125 * (((rp[0] + rp[1]) + (rp[2] + rp[3])) + ((rp[4] + rp[5]) + (rp[6] + rp[7])));
-    R rbc = (R)(0.5 * (P.rhob[k - 1] + P.rhob[k]));
-    R rbzm = (R)P.rhob[k - 1], rbzp = (R)P.rhob[k];
-    R Ux = (R)P.ux, Vy = (R)P.vy, h = (R)0.5;
-    for (int c = 0; c < 3; ++c) {
-        R M0 = c == 0 ? Ux : (c == 1 ? Vy : (R)0);
-        R ub, mb;
-        ub = h * (u[0][0] + u[2][0]); mb = h * (u[0][c] + u[2][c]);
-        R fxp = rbc * (Ux * mb + ub * M0 + ub * mb) + rxp * (Ux + ub) * (M0 + mb);
-        ub = h * (u[1][0] + u[0][0]); mb = h * (u[1][c] + u[0][c]);
-        R fxm = rbc * (Ux * mb + ub * M0 + ub * mb) + rxm * (Ux + ub) * (M0 + mb);
-        ub = h * (u[0][1] + u[4][1]); mb = h * (u[0][c] + u[4][c]);
-        R fyp = rbc * (Vy * mb + ub * M0 + ub * mb) + ryp * (Vy + ub) * (M0 + mb);
-        ub = h * (u[3][1] + u[0][1]); mb = h * (u[3][c] + u[0][c]);
-        R fym = rbc * (Vy * mb + ub * M0 + ub * mb) + rym * (Vy + ub) * (M0 + mb);
-        ub = h * (u[0][2] + u[6][2]); mb = h * (u[0][c] + u[6][c]);
-        R fzp = (rbzp + rzp) * ub * (M0 + mb);
-        ub = h * (u[5][2] + u[0][2]); mb = h * (u[5][c] + u[0][c]);
-        R fzm = (rbzm + rzm) * ub * (M0 + mb);
-        R adv = (fxp - fxm) / (R)d.dx + (fyp - fym) / (R)d.dy + (fzp - fzm) / (R)d.dz;
-        R pgf = c == 0 ? (pxp - pxm) / (R)d.dx : (c == 1 ? (pyp - pym) / (R)d.dy : (pzp - pzm) / (R)d.dz);
-        R buoy = c == 2 ? (R)P.g * r8 : (R)0;
-        L[c] = -adv - pgf - buoy;
-    }
-}
-
-// ------------------------------------------------------------------------------------------------
 // Tiled update kernel.  A block owns TX x TY columns x TZ levels.  It stages rho', (rho theta)' and
 // p' of the cells around the tile, and the velocities of the lattice points around it, in LDS once,
 // then every thread updates one cell (scalars) and one lattice point (momentum).  Above the
@@ -265,89 +234,194 @@ __global__ void __launch_bounds__(TX * TY * TZ)
 {
     using R = typename Compute<T>::R;
     using TL = Tile<TX, TY, TZ>;
+    constexpr int NT = TL::NT;
+    constexpr int IT1 = (TL::NC + NT - 1) / NT, IT2 = (TL::NL + NT - 1) / NT;
     __shared__ R s_rho[TL::NC], s_rth[TL::NC], s_pp[TL::NC];
     __shared__ R s_u[TL::NL], s_v[TL::NL], s_w[TL::NL];
     int bi, bj, bk;
     tile_of_block(nbx, nby, nbz, bi, bj, bk);
     const int i0 = bi * TX, j0 = bj * TY, k0 = bk * TZ;
     const int tid = threadIdx.x;
-    const int64_t ncol = (int64_t)d.nx * d.ny;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, nzs = d.nzs;
+    const int ncol = nx * ny;
     const R Ux = (R)P.ux, Vy = (R)P.vy;
 
-    // phase 1: cell scalars and p' (p' only for the cells (i0-1..i0+TX-1, ...) that the momentum
-    // stencils of the tile use)
-    for (int e = tid; e < TL::NC; e += TL::NT) {
-        int a = e / (TL::CY * TL::CZ), r = e - a * (TL::CY * TL::CZ), b = r / TL::CZ, c = r - b * TL::CZ;
-        int k = k0 - 2 + c;
-        R rp = (R)0, tp = (R)0, pp = (R)0;
-        if (k >= 0 && k < d.nz) {
-            int64_t ci = cidx(d, i0 - 2 + a, j0 - 2 + b, k);
-            rp = (R)qs.rho[ci];
-            tp = (R)qs.rth[ci];
-            if (a >= 1 && a <= TX + 1 && b >= 1 && b <= TY + 1 && c >= 1 && c <= TZ + 1)
-                pp = eos_pprime<R>(tp, P.rthb[k], P.pb[k], P.gam);
+    // ---- issue every global load of the staging phases first ----
+    R c_rho[IT1], c_rth[IT1];
+#pragma unroll
+    for (int it = 0; it < IT1; ++it) {
+        int e = tid + it * NT;
+        c_rho[it] = (R)0;
+        c_rth[it] = (R)0;
+        if (e < TL::NC) {
+            int a = e / (TL::CY * TL::CZ), r = e - a * (TL::CY * TL::CZ), b = r / TL::CZ, c = r - b * TL::CZ;
+            int k = k0 - 2 + c;
+            if (k >= 0 && k < nz) {
+                int ci = (wrap1(i0 - 2 + a, nx) * ny + wrap1(j0 - 2 + b, ny)) * nzs + k;
+                c_rho[it] = (R)qs.rho[ci];
+                c_rth[it] = (R)qs.rth[ci];
+            }
         }
-        s_rho[e] = rp;
-        s_rth[e] = tp;
-        s_pp[e] = pp;
+    }
+    R l_m0[IT2], l_m1[IT2], l_m2[IT2];
+    int l_kb[IT2];
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+        int e = tid + it * NT;
+        l_m0[it] = l_m1[it] = l_m2[it] = (R)0;
+        l_kb[it] = 0;
+        if (e < TL::NL) {
+            int a = e / (TL::LY * TL::LZ), r = e - a * (TL::LY * TL::LZ), b = r / TL::LZ, c = r - b * TL::LZ;
+            int K = k0 - 1 + c;
+            if (K >= 0 && K <= nz) {
+                int Kc = K < nz ? K : nz - 1;
+                int hcol = wrap1(i0 - 1 + a, nx) * ny + wrap1(j0 - 1 + b, ny);
+                int p = hcol * nzs + Kc;
+                l_m0[it] = (R)qs.mu[p];
+                l_m1[it] = (R)qs.mv[p];
+                l_m2[it] = (R)qs.mw[p];
+                l_kb[it] = G.colk[ncol + hcol];
+            }
+        }
+    }
+    // ---- phase 1: cell scalars and p' (p' for the cells i0-1..i0+TX-1 x ... the momentum
+    // stencils of the tile use) ----
+#pragma unroll
+    for (int it = 0; it < IT1; ++it) {
+        int e = tid + it * NT;
+        if (e < TL::NC) {
+            int a = e / (TL::CY * TL::CZ), r = e - a * (TL::CY * TL::CZ), b = r / TL::CZ, c = r - b * TL::CZ;
+            int k = k0 - 2 + c;
+            R pp = (R)0;
+            if (k >= 0 && k < nz && a >= 1 && a <= TX + 1 && b >= 1 && b <= TY + 1 && c >= 1 && c <= TZ + 1)
+                pp = eos_pprime_k<R>(c_rth[it], k, P);
+            s_rho[e] = c_rho[it];
+            s_rth[e] = c_rth[it];
+            s_pp[e] = pp;
+        }
     }
     __syncthreads();
-    // phase 2: lattice velocities (perturbations from the reference flow)
-    for (int e = tid; e < TL::NL; e += TL::NT) {
-        int a = e / (TL::LY * TL::LZ), r = e - a * (TL::LY * TL::LZ), b = r / TL::LZ, c = r - b * TL::LZ;
-        int K = k0 - 1 + c;
-        R u0 = (R)0, u1 = (R)0, u2 = (R)0;
-        if (K >= 0 && K <= d.nz) {
-            int I = i0 - 1 + a, J = j0 - 1 + b;
-            int Kc = K < d.nz ? K : d.nz - 1;  // the rigid lid copies the level below
-            int64_t p = cidx(d, I, J, Kc);
-            bool pred = Kc >= G.colk[ncol + hidx(d, I, J)] || G.vcls[p] == CC_PRED;
-            if (pred) {
-                int cz = Kc - k0 + 1;  // LDS level of cell level Kc-1
-                R s = ((s_rho[TL::cs(a, b, cz)] + s_rho[TL::cs(a + 1, b, cz)]) +
-                       (s_rho[TL::cs(a, b + 1, cz)] + s_rho[TL::cs(a + 1, b + 1, cz)])) +
-                      ((s_rho[TL::cs(a, b, cz + 1)] + s_rho[TL::cs(a + 1, b, cz + 1)]) +
-                       (s_rho[TL::cs(a, b + 1, cz + 1)] + s_rho[TL::cs(a + 1, b + 1, cz + 1)]));
-                R rpc = s * (R)0.125;
-                R rc = (R)(0.5 * (P.rhob[Kc - 1] + P.rhob[Kc])) + rpc;
-                u0 = ((R)qs.mu[p] - rpc * Ux) / rc;
-                u1 = ((R)qs.mv[p] - rpc * Vy) / rc;
-                u2 = (R)qs.mw[p] / rc;
-            } else {
-                u0 = (R)qs.mu[p];
-                u1 = (R)qs.mv[p];
-                u2 = (R)qs.mw[p];
+    // ---- phase 2: lattice velocities (perturbations from the reference flow) ----
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+        int e = tid + it * NT;
+        if (e < TL::NL) {
+            int a = e / (TL::LY * TL::LZ), r = e - a * (TL::LY * TL::LZ), b = r / TL::LZ, c = r - b * TL::LZ;
+            int K = k0 - 1 + c;
+            R u0 = (R)0, u1 = (R)0, u2 = (R)0;
+            if (K >= 0 && K <= nz) {
+                int Kc = K < nz ? K : nz - 1;  // the rigid lid copies the level below
+                bool pred = Kc >= l_kb[it];
+                if (!pred) {
+                    int hcol = wrap1(i0 - 1 + a, nx) * ny + wrap1(j0 - 1 + b, ny);
+                    pred = G.vcls[hcol * nzs + Kc] == CC_PRED;
+                }
+                if (pred) {
+                    int cz = Kc - k0 + 1;  // LDS level of cell level Kc-1
+                    R sm = ((s_rho[TL::cs(a, b, cz)] + s_rho[TL::cs(a + 1, b, cz)]) +
+                            (s_rho[TL::cs(a, b + 1, cz)] + s_rho[TL::cs(a + 1, b + 1, cz)])) +
+                           ((s_rho[TL::cs(a, b, cz + 1)] + s_rho[TL::cs(a + 1, b, cz + 1)]) +
+                            (s_rho[TL::cs(a, b + 1, cz + 1)] + s_rho[TL::cs(a + 1, b + 1, cz + 1)]));
+                    R rpc = sm * (R)0.125;
+                    R ri = recip((R)P.rhobc[Kc] + rpc);
+                    u0 = (l_m0[it] - rpc * Ux) * ri;
+                    u1 = (l_m1[it] - rpc * Vy) * ri;
+                    u2 = l_m2[it] * ri;
+                } else {
+                    u0 = l_m0[it];
+                    u1 = l_m1[it];
+                    u2 = l_m2[it];
+                }
+                if (K == nz) u2 = (R)0;
             }
-            if (K == d.nz) u2 = (R)0;
+            s_u[e] = u0;
+            s_v[e] = u1;
+            s_w[e] = u2;
         }
-        s_u[e] = u0;
-        s_v[e] = u1;
-        s_w[e] = u2;
     }
     __syncthreads();
 
-    // phase 3: one cell and one lattice point per thread
+    // ---- phase 3: one cell and one lattice point per thread ----
     const int tx = tid / (TY * TZ), ty = (tid / TZ) % TY, tz = tid % TZ;
     const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
-    if (i >= d.nx || j >= d.ny || k >= d.nz) return;
-    const int64_t c = cidx(d, i, j, k);
-    const int64_t hc = hidx(d, i, j);
+    if (i >= nx || j >= ny || k >= nz) return;
+    const int hc = i * ny + j;
+    const int c = hc * nzs + k;
     const int ca = tx + 2, cb = ty + 2, cc = tz + 2;  // LDS cell coordinates of (i,j,k)
     const int la = tx + 1, lb = ty + 1, lc = tz + 1;  // LDS lattice coordinates of (i,j,k)
     bool bad = false;
 
     // ---- scalars ----
-    bool band = k < G.colk[hc];
-    int8_t cl = band ? G.cls[c] : (int8_t)CC_OPEN;
+    const bool band = k < G.colk[hc];
+    const int8_t cl = band ? G.cls[c] : (int8_t)CC_OPEN;
     if (cl == CC_OPEN || cl == CC_ORPHAN) {
         double L0, L1;
-        if (band && G.gnext[c] != -1) {  // master of a multi-cell group: general gather
+        const R rc0 = s_rho[TL::cs(ca, cb, cc)], rc1 = s_rth[TL::cs(ca, cb, cc)];
+        if (!band) {
+            // regular cell: V = 1, open faces, neighbours at their own level; the base-state and
+            // reference-flow fluxes of opposite faces cancel exactly
+            const R h = (R)0.5, q4 = (R)0.25;
+            const R Sx = (R)(d.dy * d.dz), Sy = (R)(d.dz * d.dx), Sz = (R)(d.dx * d.dy);
+            const R b0 = (R)P.rhob[k], b1 = (R)P.rthb[k];
+            double r0 = 0.0, r1 = 0.0;
+            // x faces
+            {
+                R unm = q4 * ((s_u[TL::ls(la, lb, lc)] + s_u[TL::ls(la, lb + 1, lc)]) +
+                              (s_u[TL::ls(la, lb, lc + 1)] + s_u[TL::ls(la, lb + 1, lc + 1)]));
+                R unp = q4 * ((s_u[TL::ls(la + 1, lb, lc)] + s_u[TL::ls(la + 1, lb + 1, lc)]) +
+                              (s_u[TL::ls(la + 1, lb, lc + 1)] + s_u[TL::ls(la + 1, lb + 1, lc + 1)]));
+                R nm0 = s_rho[TL::cs(ca - 1, cb, cc)], nm1 = s_rth[TL::cs(ca - 1, cb, cc)];
+                R np0 = s_rho[TL::cs(ca + 1, cb, cc)], np1 = s_rth[TL::cs(ca + 1, cb, cc)];
+                R tm = unm + Ux, tp = unp + Ux;
+                R fm0 = (b0 * unm + h * (nm0 + rc0) * tm) * Sx, fp0 = (b0 * unp + h * (rc0 + np0) * tp) * Sx;
+                R fm1 = (b1 * unm + h * (nm1 + rc1) * tm) * Sx, fp1 = (b1 * unp + h * (rc1 + np1) * tp) * Sx;
+                r0 += (double)fp0 - (double)fm0;
+                r1 += (double)fp1 - (double)fm1;
+            }
+            // y faces
+            {
+                R unm = q4 * ((s_v[TL::ls(la, lb, lc)] + s_v[TL::ls(la + 1, lb, lc)]) +
+                              (s_v[TL::ls(la, lb, lc + 1)] + s_v[TL::ls(la + 1, lb, lc + 1)]));
+                R unp = q4 * ((s_v[TL::ls(la, lb + 1, lc)] + s_v[TL::ls(la + 1, lb + 1, lc)]) +
+                              (s_v[TL::ls(la, lb + 1, lc + 1)] + s_v[TL::ls(la + 1, lb + 1, lc + 1)]));
+                R nm0 = s_rho[TL::cs(ca, cb - 1, cc)], nm1 = s_rth[TL::cs(ca, cb - 1, cc)];
+                R np0 = s_rho[TL::cs(ca, cb + 1, cc)], np1 = s_rth[TL::cs(ca, cb + 1, cc)];
+                R tm = unm + Vy, tp = unp + Vy;
+                R fm0 = (b0 * unm + h * (nm0 + rc0) * tm) * Sy, fp0 = (b0 * unp + h * (rc0 + np0) * tp) * Sy;
+                R fm1 = (b1 * unm + h * (nm1 + rc1) * tm) * Sy, fp1 = (b1 * unp + h * (rc1 + np1) * tp) * Sy;
+                r0 += (double)fp0 - (double)fm0;
+                r1 += (double)fp1 - (double)fm1;
+            }
+            // z faces (k >= 1 in the regular region; the rigid lid closes the top of k = nz-1)
+            {
+                R unm = q4 * ((s_w[TL::ls(la, lb, lc)] + s_w[TL::ls(la + 1, lb, lc)]) +
+                              (s_w[TL::ls(la, lb + 1, lc)] + s_w[TL::ls(la + 1, lb + 1, lc)]));
+                R nm0 = s_rho[TL::cs(ca, cb, cc - 1)], nm1 = s_rth[TL::cs(ca, cb, cc - 1)];
+                R bm0 = (R)(0.5 * (P.rhob[k - 1] + P.rhob[k])), bm1 = (R)(0.5 * (P.rthb[k - 1] + P.rthb[k]));
+                R fm0 = (bm0 * unm + h * (nm0 + rc0) * unm) * Sz;
+                R fm1 = (bm1 * unm + h * (nm1 + rc1) * unm) * Sz;
+                r0 -= (double)fm0;
+                r1 -= (double)fm1;
+                if (k + 1 < nz) {
+                    R unp = q4 * ((s_w[TL::ls(la, lb, lc + 1)] + s_w[TL::ls(la + 1, lb, lc + 1)]) +
+                                  (s_w[TL::ls(la, lb + 1, lc + 1)] + s_w[TL::ls(la + 1, lb + 1, lc + 1)]));
+                    R np0 = s_rho[TL::cs(ca, cb, cc + 1)], np1 = s_rth[TL::cs(ca, cb, cc + 1)];
+                    R bp0 = (R)(0.5 * (P.rhob[k] + P.rhob[k + 1])), bp1 = (R)(0.5 * (P.rthb[k] + P.rthb[k + 1]));
+                    R fp0 = (bp0 * unp + h * (rc0 + np0) * unp) * Sz;
+                    R fp1 = (bp1 * unp + h * (rc1 + np1) * unp) * Sz;
+                    r0 += (double)fp0;
+                    r1 += (double)fp1;
+                }
+            }
+            L0 = -r0 * P.idV;
+            L1 = -r1 * P.idV;
+        } else if (G.gnext[c] != -1) {  // master of a multi-cell group: general gather
             double L[2];
             group_scalar_tendency<T>(d, G, P, qs, c, L);
             L0 = L[0]; L1 = L[1];
         } else {
-            double r0 = 0.0, r1 = 0.0, b0 = 0.0, b1 = 0.0;
-            const R rc0 = s_rho[TL::cs(ca, cb, cc)], rc1 = s_rth[TL::cs(ca, cb, cc)];
+            // single-cell group in the band: apertures, group volume and neighbour masters
+            double r0 = 0.0, r1 = 0.0, g0 = 0.0, g1 = 0.0;
             for (int f = 0; f < 6; ++f) {
                 int axis = f >> 1, plus = f & 1;
                 int da = 0, db = 0, dc = 0;
@@ -355,20 +429,16 @@ __global__ void __launch_bounds__(TX * TY * TZ)
                 else if (axis == 1) db = plus ? 1 : -1;
                 else {
                     dc = plus ? 1 : -1;
-                    if (k + dc < 0 || k + dc >= d.nz) continue;  // ground and rigid lid
+                    if (k + dc < 0 || k + dc >= nz) continue;  // ground and rigid lid
                 }
-                // face "upper" cell (the one whose index carries the face) and aperture
-                double A = 1.0;
-                int kn = k + dc;
-                if (band) {
-                    int64_t fu = cidx(d, i + (axis == 0 && plus), j + (axis == 1 && plus), k + (axis == 2 && plus));
-                    A = axis == 0 ? G.Ax[fu] : (axis == 1 ? G.Ay[fu] : G.Az[fu]);
-                    if (A == 0.0) continue;
-                    int32_t mn = G.master[cidx(d, i + da, j + db, k + dc)];
-                    if (mn < 0) continue;
-                    kn = (int)(mn % d.nzs);
-                }
-                // face corners in canonical order (lattice coordinates of the face)
+                int ip = wrap1(i + (axis == 0 && plus), nx), jp = wrap1(j + (axis == 1 && plus), ny);
+                int fu = (ip * ny + jp) * nzs + k + (axis == 2 && plus);
+                double A = axis == 0 ? G.Ax[fu] : (axis == 1 ? G.Ay[fu] : G.Az[fu]);
+                if (A == 0.0) continue;
+                int in = wrap1(i + da, nx), jn = wrap1(j + db, ny);
+                int32_t mn = G.master[(in * ny + jn) * nzs + k + dc];
+                if (mn < 0) continue;
+                int kn = mn % nzs;
                 int fa = la + (axis == 0 && plus), fb = lb + (axis == 1 && plus), fc = lc + (axis == 2 && plus);
                 R un;
                 double S, Un;
@@ -395,16 +465,13 @@ __global__ void __launch_bounds__(TX * TY * TZ)
                 R unt = un + (R)Un;
                 R f0 = ((R)pb0 * un + pp0 * unt) * AS;
                 R f1 = ((R)pb1 * un + pp1 * unt) * AS;
-                if (plus) { r0 += (double)f0; r1 += (double)f1; }
-                else { r0 -= (double)f0; r1 -= (double)f1; }
-                if (band) {  // base-state / reference-flow flux: cancels exactly on regular cells
-                    double g0 = pb0 * Un * A * S, g1 = pb1 * Un * A * S;
-                    if (plus) { b0 += g0; b1 += g1; } else { b0 -= g0; b1 -= g1; }
-                }
+                double h0 = pb0 * Un * A * S, h1 = pb1 * Un * A * S;
+                if (plus) { r0 += (double)f0; r1 += (double)f1; g0 += h0; g1 += h1; }
+                else { r0 -= (double)f0; r1 -= (double)f1; g0 -= h0; g1 -= h1; }
             }
-            double vol = (band ? G.Vgroup[c] : 1.0) * P.dV;
-            L0 = -(b0 + r0) / vol;
-            L1 = -(b1 + r1) / vol;
+            double vol = G.Vgroup[c] * P.dV;
+            L0 = -(g0 + r0) / vol;
+            L1 = -(g1 + r1) / vol;
         }
         if (MODE == 0) {
             double x0 = (double)qn.rho[c], x1 = (double)qn.rth[c];
@@ -430,49 +497,56 @@ __global__ void __launch_bounds__(TX * TY * TZ)
     }
 
     // ---- momentum at the lattice point (i,j,k) ----
-    bool pred = k >= G.colk[ncol + hc] || G.vcls[c] == CC_PRED;
+    const bool pred = k >= G.colk[ncol + hc] || G.vcls[c] == CC_PRED;
     if (pred) {
         R u[7][3];
         const int off[7][3] = {{0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+#pragma unroll
         for (int s = 0; s < 7; ++s) {
             int e = TL::ls(la + off[s][0], lb + off[s][1], lc + off[s][2]);
             u[s][0] = s_u[e]; u[s][1] = s_v[e]; u[s][2] = s_w[e];
         }
         R rp[8], pp[8];  // bit0: i-1/i, bit1: j-1/j, bit2: k-1/k
+#pragma unroll
         for (int s = 0; s < 8; ++s) {
             int e = TL::cs(ca - 1 + (s & 1), cb - 1 + ((s >> 1) & 1), cc - 1 + (s >> 2));
             rp[s] = s_rho[e];
             pp[s] = s_pp[e];
         }
-        R q4 = (R)0.25;
+        const R q4 = (R)0.25, h = (R)0.5;
         R rxm = q4 * ((rp[0] + rp[2]) + (rp[4] + rp[6])), rxp = q4 * ((rp[1] + rp[3]) + (rp[5] + rp[7]));
         R rym = q4 * ((rp[0] + rp[1]) + (rp[4] + rp[5])), ryp = q4 * ((rp[2] + rp[3]) + (rp[6] + rp[7]));
         R rzm = q4 * ((rp[0] + rp[1]) + (rp[2] + rp[3])), rzp = q4 * ((rp[4] + rp[5]) + (rp[6] + rp[7]));
-        R pxm = q4 * ((pp[0] + pp[2]) + (pp[4] + pp[6])), pxp = q4 * ((pp[1] + pp[3]) + (pp[5] + pp[7]));
-        R pym = q4 * ((pp[0] + pp[1]) + (pp[4] + pp[5])), pyp = q4 * ((pp[2] + pp[3]) + (pp[6] + pp[7]));
-        R pzm = q4 * ((pp[0] + pp[1]) + (pp[2] + pp[3])), pzp = q4 * ((pp[4] + pp[5]) + (pp[6] + pp[7]));
+        R pgx = (q4 * ((pp[1] + pp[3]) + (pp[5] + pp[7])) - q4 * ((pp[0] + pp[2]) + (pp[4] + pp[6]))) * (R)P.idx;
+        R pgy = (q4 * ((pp[2] + pp[3]) + (pp[6] + pp[7])) - q4 * ((pp[0] + pp[1]) + (pp[4] + pp[5]))) * (R)P.idy;
+        R pgz = (q4 * ((pp[4] + pp[5]) + (pp[6] + pp[7])) - q4 * ((pp[0] + pp[1]) + (pp[2] + pp[3]))) * (R)P.idz;
         R r8 = (R)0.125 * (((rp[0] + rp[1]) + (rp[2] + rp[3])) + ((rp[4] + rp[5]) + (rp[6] + rp[7])));
-        R rbc = (R)(0.5 * (P.rhob[k - 1] + P.rhob[k]));
-        R rbzm = (R)P.rhob[k - 1], rbzp = (R)P.rhob[k];
-        R h = (R)0.5;
+        const R rbc = (R)P.rhobc[k];
+        const R rbzm = (R)P.rhob[k - 1], rbzp = (R)P.rhob[k];
+        const R ix = (R)P.idx, iy = (R)P.idy, iz = (R)P.idz;
+        // normal velocities on the six faces (shared by the three components)
+        const R uxp = h * (u[0][0] + u[2][0]), uxm = h * (u[1][0] + u[0][0]);
+        const R vyp = h * (u[0][1] + u[4][1]), vym = h * (u[3][1] + u[0][1]);
+        const R wzp = h * (u[0][2] + u[6][2]), wzm = h * (u[5][2] + u[0][2]);
         R Lm[3];
+#pragma unroll
         for (int cm = 0; cm < 3; ++cm) {
             R M0 = cm == 0 ? Ux : (cm == 1 ? Vy : (R)0);
-            R ub, mb;
-            ub = h * (u[0][0] + u[2][0]); mb = h * (u[0][cm] + u[2][cm]);
-            R fxp = rbc * (Ux * mb + ub * M0 + ub * mb) + rxp * (Ux + ub) * (M0 + mb);
-            ub = h * (u[1][0] + u[0][0]); mb = h * (u[1][cm] + u[0][cm]);
-            R fxm = rbc * (Ux * mb + ub * M0 + ub * mb) + rxm * (Ux + ub) * (M0 + mb);
-            ub = h * (u[0][1] + u[4][1]); mb = h * (u[0][cm] + u[4][cm]);
-            R fyp = rbc * (Vy * mb + ub * M0 + ub * mb) + ryp * (Vy + ub) * (M0 + mb);
-            ub = h * (u[3][1] + u[0][1]); mb = h * (u[3][cm] + u[0][cm]);
-            R fym = rbc * (Vy * mb + ub * M0 + ub * mb) + rym * (Vy + ub) * (M0 + mb);
-            ub = h * (u[0][2] + u[6][2]); mb = h * (u[0][cm] + u[6][cm]);
-            R fzp = (rbzp + rzp) * ub * (M0 + mb);
-            ub = h * (u[5][2] + u[0][2]); mb = h * (u[5][cm] + u[0][cm]);
-            R fzm = (rbzm + rzm) * ub * (M0 + mb);
-            R adv = (fxp - fxm) / (R)d.dx + (fyp - fym) / (R)d.dy + (fzp - fzm) / (R)d.dz;
-            R pgf = cm == 0 ? (pxp - pxm) / (R)d.dx : (cm == 1 ? (pyp - pym) / (R)d.dy : (pzp - pzm) / (R)d.dz);
+            R mb;
+            mb = h * (u[0][cm] + u[2][cm]);
+            R fxp = rbc * (Ux * mb + uxp * M0 + uxp * mb) + rxp * (Ux + uxp) * (M0 + mb);
+            mb = h * (u[1][cm] + u[0][cm]);
+            R fxm = rbc * (Ux * mb + uxm * M0 + uxm * mb) + rxm * (Ux + uxm) * (M0 + mb);
+            mb = h * (u[0][cm] + u[4][cm]);
+            R fyp = rbc * (Vy * mb + vyp * M0 + vyp * mb) + ryp * (Vy + vyp) * (M0 + mb);
+            mb = h * (u[3][cm] + u[0][cm]);
+            R fym = rbc * (Vy * mb + vym * M0 + vym * mb) + rym * (Vy + vym) * (M0 + mb);
+            mb = h * (u[0][cm] + u[6][cm]);
+            R fzp = (rbzp + rzp) * wzp * (M0 + mb);
+            mb = h * (u[5][cm] + u[0][cm]);
+            R fzm = (rbzm + rzm) * wzm * (M0 + mb);
+            R adv = (fxp - fxm) * ix + (fyp - fym) * iy + (fzp - fzm) * iz;
+            R pgf = cm == 0 ? pgx : (cm == 1 ? pgy : pgz);
             R buoy = cm == 2 ? (R)P.g * r8 : (R)0;
             Lm[cm] = -adv - pgf - buoy;
         }
@@ -770,11 +844,17 @@ static bool make_views(const char *what, const cc_grid *grid, const cc_phys *phy
     G = Geo{g->H, g->V, g->Ax, g->Ay, g->Az, g->nrm, g->Vgroup, g->cls, g->vcls, g->master, g->gnext, g->colk};
     double cv = phys->cp - phys->rd;
     P.rhob = base; P.rthb = base + d.nz; P.pb = base + 2 * d.nz; P.thb = base + 3 * d.nz;
+    P.irthb = base + 4 * d.nz; P.rhobc = base + 5 * d.nz;
     P.g = phys->g;
     P.gam = phys->cp / cv;
     P.ux = prec == CC_F32_PERT ? phys->u0 : 0.0;
     P.vy = prec == CC_F32_PERT ? phys->v0 : 0.0;
     P.dV = d.dx * d.dy * d.dz;
+    P.idV = 1.0 / P.dV;
+    P.idx = 1.0 / d.dx; P.idy = 1.0 / d.dy; P.idz = 1.0 / d.dz;
+    // binomial coefficients of (1+x)^gamma - 1
+    P.binom[0] = P.gam;
+    for (int n = 1; n < EOS_TERMS; ++n) P.binom[n] = P.binom[n - 1] * (P.gam - n) / (n + 1);
     return true;
 }
 
@@ -807,14 +887,51 @@ static void launch_diagnose(const Dims &d, const Geo &G, const Phy &P, cc_state 
     hipLaunchKernelGGL(k_diagnose<T>, dim3(blocks_for(nc, 64)), dim3(64), 0, s, d, G, P, sout_of<T>(q), st);
 }
 
-template <typename T, int MODE>
-static void launch_stage(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
+// tile shapes of the update kernel (id -> TX x TY x TZ); id 0 is the default
+struct TileShape { int tx, ty, tz; };
+constexpr TileShape TILES[] = {{4, 4, 16}, {4, 4, 16}, {8, 4, 16}, {4, 8, 16}, {8, 8, 8},
+                               {2, 4, 32}, {4, 4, 32}, {8, 8, 16}, {2, 2, 64}};
+constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
+
+template <typename T, int TX, int TY, int TZ, int MODE>
+static void launch_tiled(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
                          cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
 {
-    constexpr int TX = 4, TY = 4, TZ = 16;
     int nbx = (d.nx + TX - 1) / TX, nby = (d.ny + TY - 1) / TY, nbz = (d.nz + TZ - 1) / TZ;
     hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE>), dim3(nbx * nby * nbz), dim3(TX * TY * TZ), 0, s, d,
                        G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, nbx, nby, nbz, st);
+}
+
+// the tile of a grid: the requested shape if the grid holds at least one tile per direction in x
+// and y (the periodic index arithmetic wraps at most once), else 4x4x16, else 2x2x64
+static int pick_tile(int id, const Dims &d)
+{
+    if (id <= 0 || id >= NTILES) id = 0;
+    if (d.nx >= TILES[id].tx && d.ny >= TILES[id].ty) return id;
+    if (d.nx >= 4 && d.ny >= 4) return 1;
+    return 8;
+}
+
+template <typename T, int MODE>
+static void launch_stage(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
+                         cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s, int tile)
+{
+    int id = pick_tile(tile, d);
+    if (MODE == 1) id = (d.nx >= 4 && d.ny >= 4) ? 1 : 8;  // tendency evaluation: fixed shapes
+    switch (id) {
+#define CC_TILE_CASE(ID, X, Y, Z) \
+    case ID: launch_tiled<T, X, Y, Z, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
+    CC_TILE_CASE(0, 4, 4, 16)
+    CC_TILE_CASE(1, 4, 4, 16)
+    CC_TILE_CASE(2, 8, 4, 16)
+    CC_TILE_CASE(3, 4, 8, 16)
+    CC_TILE_CASE(4, 8, 8, 8)
+    CC_TILE_CASE(5, 2, 4, 32)
+    CC_TILE_CASE(6, 4, 4, 32)
+    CC_TILE_CASE(7, 8, 8, 16)
+    default: launch_tiled<T, 2, 2, 64, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
+#undef CC_TILE_CASE
+    }
 }
 
 }  // namespace cc
@@ -864,8 +981,8 @@ extern "C" cc_status cutcell_tendency(const cc_grid *grid, const cc_phys *phys, 
     if (!state_ok("cutcell_tendency", q) || !state_ok("cutcell_tendency", dq)) return CC_EINVAL;
     CC_REQUIRE(q->rho != dq->rho, "cutcell_tendency: output aliases input");
     hipStream_t s = (hipStream_t)stream;
-    if (prec == CC_F64) launch_stage<double, 1>(d, G, P, q, q, dq, 0.0, 0, nullptr, s);
-    else launch_stage<float, 1>(d, G, P, q, q, dq, 0.0, 0, nullptr, s);
+    if (prec == CC_F64) launch_stage<double, 1>(d, G, P, q, q, dq, 0.0, 0, nullptr, s, grid->tile);
+    else launch_stage<float, 1>(d, G, P, q, q, dq, 0.0, 0, nullptr, s, grid->tile);
     return launch_status("cutcell_tendency");
 }
 
@@ -882,10 +999,10 @@ extern "C" cc_status cutcell_rk_stage(const cc_grid *grid, const cc_phys *phys, 
                "cutcell_rk_stage: q_out must not alias q_n or q_s");
     hipStream_t s = (hipStream_t)stream;
     if (prec == CC_F64) {
-        launch_stage<double, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
+        launch_stage<double, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s, grid->tile);
         launch_diagnose<double>(d, G, P, qo, st, s);
     } else {
-        launch_stage<float, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
+        launch_stage<float, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s, grid->tile);
         launch_diagnose<float>(d, G, P, qo, st, s);
     }
     return launch_status("cutcell_rk_stage");
@@ -903,8 +1020,8 @@ extern "C" cc_status cutcell_rk_update(const cc_grid *grid, const cc_phys *phys,
     CC_REQUIRE(qo->rho != qs->rho && qo->rho != qn->rho && qo->mu != qs->mu && qo->mu != qn->mu,
                "cutcell_rk_update: q_out must not alias q_n or q_s");
     hipStream_t s = (hipStream_t)stream;
-    if (prec == CC_F64) launch_stage<double, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
-    else launch_stage<float, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
+    if (prec == CC_F64) launch_stage<double, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s, grid->tile);
+    else launch_stage<float, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s, grid->tile);
     return launch_status("cutcell_rk_update");
 }
 

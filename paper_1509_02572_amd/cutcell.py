@@ -29,7 +29,7 @@ STATUS_NAMES = ("unmergeable", "noplane", "nonfinite", "terrain", "groupsize")
 class cc_grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("nzs", C.c_int32),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
-                ("nsub", C.c_int32), ("reserved", C.c_int32)]
+                ("nsub", C.c_int32), ("tile", C.c_int32)]
 
 
 class cc_phys(C.Structure):
@@ -195,7 +195,7 @@ class Domain:
     ``prec`` is ``"f64"`` (paper variables in double) or ``"f32"`` (float perturbation form)."""
 
     def __init__(self, cfg, prec: str = "f64", device: str = "cuda:0", nzs: Optional[int] = None,
-                 H: Optional[np.ndarray] = None):
+                 H: Optional[np.ndarray] = None, tile: int = 0):
         from . import workloads
         if not torch.cuda.is_available():
             raise RuntimeError("libcutcell needs a HIP device")
@@ -206,7 +206,7 @@ class Domain:
         nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
         self.nzs = nzs or default_nzs(nz)
         self.n = nx * ny * self.nzs
-        self.grid = cc_grid(nx, ny, nz, self.nzs, cfg.dx, cfg.dy, cfg.dz, cfg.nsub, 0)
+        self.grid = cc_grid(nx, ny, nz, self.nzs, cfg.dx, cfg.dy, cfg.dz, cfg.nsub, tile)
         self.phys = cc_phys(cfg.g, cfg.rd, cfg.cp, cfg.p0, cfg.theta0, cfg.bvn, cfg.u0, cfg.v0)
         Hn = workloads.terrain(cfg) if H is None else H
         d, f64, i8, i32 = self.dev, torch.float64, torch.int8, torch.int32
@@ -223,7 +223,7 @@ class Domain:
         }
         self.geom = cc_geom(*[_ptr(self.g[k]) for k in ("H", "V", "Ax", "Ay", "Az", "col", "nrm", "cls",
                                                          "dir", "vcls", "master", "gnext", "Vgroup", "colk")])
-        self.base = torch.zeros(4 * nz, dtype=f64, device=d)
+        self.base = torch.zeros(6 * nz, dtype=f64, device=d)
         self.status = torch.zeros(CC_NSTATUS, dtype=torch.int64, device=d)
         self.ws = torch.zeros(lib().cutcell_reduce_workspace(C.byref(self.grid)) // 8 + 1, dtype=f64, device=d)
         self.red = torch.zeros(4, dtype=f64, device=d)
