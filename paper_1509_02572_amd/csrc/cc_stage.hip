@@ -46,6 +46,7 @@ struct Phy {
     const double *rhobc;                   // mean base density of levels K-1, K at lattice level K [nz]
     double g, gam, ux, vy, dV, idV, idx, idy, idz;
     double binom[EOS_TERMS];               // (1+x)^gamma - 1 = sum_n binom[n-1] x^n
+    float binomf[EOS_TERMS];
 };
 
 template <typename T>
@@ -94,6 +95,25 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 __device__ __forceinline__ int wrap1(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Fluxes of rho' and (rho theta)' (perturbation part) through one face.  Every code path calls
+// this with the same operands, so both cells of a face obtain bitwise the same value.
+//   s4   sum of the four corner normal velocities, ((a + b) + (c + d)) in canonical corner order
+//   AS4  aperture x area / 4, UAS = reference normal velocity x aperture x area
+//   b0,b1 base values on the face, lo*/up* perturbations of the lower / upper exchanging group
+// flux = bar (un A S) + (lo + up)/2 ((un + Un) A S) with un = s4 / 4.
+template <typename R>
+__device__ __forceinline__ void scalar_face_flux(R s4, R AS4, R UAS, R b0, R b1, R lo0, R up0, R lo1,
+                                                 R up1, R &f0, R &f1)
+{
+    R unS = s4 * AS4;
+    R htS = (R)0.5 * fmaR(s4, AS4, UAS);
+    f0 = fmaR(b0, unS, (lo0 + up0) * htS);
+    f1 = fmaR(b1, unS, (lo1 + up1) * htS);
+}
+
 // Velocity (perturbation from the reference flow) at lattice point (I,J,K).
 // Predicted points divide the momentum by the mean of the eight surrounding cell densities;
 // diagnosed points store the velocity; the rigid lid (K = nz) has w = 0 and copies (u, v) of the
@@ -112,8 +132,8 @@ __device__ __forceinline__ void lat_vel(const Dims &d, const Geo &G, const Phy &
               (((R)q.rho[c00 + 1] + (R)q.rho[c10 + 1]) + ((R)q.rho[c01 + 1] + (R)q.rho[c11 + 1]));
         R rpc = s * (R)0.125;
         R ri = recip((R)P.rhobc[K] + rpc);
-        u[0] = ((R)q.mu[p] - rpc * (R)P.ux) * ri;
-        u[1] = ((R)q.mv[p] - rpc * (R)P.vy) * ri;
+        u[0] = fmaR(-rpc, (R)P.ux, (R)q.mu[p]) * ri;
+        u[1] = fmaR(-rpc, (R)P.vy, (R)q.mv[p]) * ri;
         u[2] = (R)q.mw[p] * ri;
     } else {
         u[0] = (R)q.mu[p];
@@ -173,17 +193,14 @@ __device__ void group_scalar_tendency(const Dims &d, const Geo &G, const Phy &P,
                 lat_vel<T>(d, G, P, q, fi, fj + 1, fk, e); lat_vel<T>(d, G, P, q, fi + 1, fj + 1, fk, h);
                 S = d.dx * d.dy; Un = 0.0;
             }
-            R un = (R)0.25 * ((a[axis] + b[axis]) + (e[axis] + h[axis]));
+            R s4 = (a[axis] + b[axis]) + (e[axis] + h[axis]);
             int64_t mlo = plus ? c : (int64_t)mn, mup = plus ? (int64_t)mn : c;
             int klo = plus ? kc : (int)(mn % d.nzs), kup = plus ? (int)(mn % d.nzs) : kc;
             double pb0 = 0.5 * (P.rhob[klo] + P.rhob[kup]);
             double pb1 = 0.5 * (P.rthb[klo] + P.rthb[kup]);
-            R pp0 = (R)0.5 * ((R)q.rho[mlo] + (R)q.rho[mup]);
-            R pp1 = (R)0.5 * ((R)q.rth[mlo] + (R)q.rth[mup]);
-            R AS = (R)(A * S);
-            R unt = un + (R)Un;
-            R f0 = ((R)pb0 * un + pp0 * unt) * AS;
-            R f1 = ((R)pb1 * un + pp1 * unt) * AS;
+            R f0, f1;
+            scalar_face_flux<R>(s4, (R)(0.25 * A * S), (R)(Un * A * S), (R)pb0, (R)pb1, (R)q.rho[mlo],
+                                (R)q.rho[mup], (R)q.rth[mlo], (R)q.rth[mup], f0, f1);
             double g0 = pb0 * Un * A * S, g1 = pb1 * Un * A * S;
             if (plus) { rp0 += (double)f0; rp1 += (double)f1; rb0 += g0; rb1 += g1; }
             else { rp0 -= (double)f0; rp1 -= (double)f1; rb0 -= g0; rb1 -= g1; }
@@ -227,6 +244,21 @@ __device__ __forceinline__ void tile_of_block(int nbx, int nby, int nbz, int &bi
     bi = t2 / nby;
 }
 
+// p' of a cell from its (rho theta)' with base values staged in the compute precision: binomial
+// series of (1+x)^gamma when |x| <= EOS_XMAX, exact form otherwise
+template <typename R>
+__device__ __forceinline__ R eos_staged(R rthp, R irthb, R pb, const Phy &P)
+{
+    R x = rthp * irthb;
+    R ax = x < (R)0 ? -x : x;
+    if (ax > (R)EOS_XMAX) return pb * expm1_r((R)P.gam * log1p_r(x));
+    constexpr int NTERM = sizeof(R) == 4 ? 6 : EOS_TERMS;
+    R acc = sizeof(R) == 4 ? (R)P.binomf[NTERM - 1] : (R)P.binom[NTERM - 1];
+#pragma unroll
+    for (int n = NTERM - 2; n >= 0; --n) acc = fmaR(x, acc, sizeof(R) == 4 ? (R)P.binomf[n] : (R)P.binom[n]);
+    return pb * (x * acc);
+}
+
 template <typename T, int TX, int TY, int TZ, int MODE>
 __global__ void __launch_bounds__(TX * TY * TZ)
     k_stage_tiled(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn, SOut<T> qo, double cdt, int final_stage,
@@ -236,17 +268,21 @@ __global__ void __launch_bounds__(TX * TY * TZ)
     using TL = Tile<TX, TY, TZ>;
     constexpr int NT = TL::NT;
     constexpr int IT1 = (TL::NC + NT - 1) / NT, IT2 = (TL::NL + NT - 1) / NT;
+    constexpr int NB = TZ + 4;  // staged base levels k0-2 .. k0+TZ+1
     __shared__ R s_rho[TL::NC], s_rth[TL::NC], s_pp[TL::NC];
     __shared__ R s_u[TL::NL], s_v[TL::NL], s_w[TL::NL];
+    // base profiles in the compute precision: rhobar, (rho theta)bar, pbar, 1/(rho theta)bar, and
+    // the means of rhobar and (rho theta)bar over levels k-1, k (z faces / lattice level k)
+    __shared__ R s_b[6][NB];
     int bi, bj, bk;
     tile_of_block(nbx, nby, nbz, bi, bj, bk);
     const int i0 = bi * TX, j0 = bj * TY, k0 = bk * TZ;
     const int tid = threadIdx.x;
     const int nx = d.nx, ny = d.ny, nz = d.nz, nzs = d.nzs;
-    const int ncol = nx * ny;
+    const unsigned ncol = (unsigned)(nx * ny);
     const R Ux = (R)P.ux, Vy = (R)P.vy;
 
-    // ---- issue every global load of the staging phases first ----
+    // ---- issue the global loads of the staging phases first ----
     R c_rho[IT1], c_rth[IT1];
 #pragma unroll
     for (int it = 0; it < IT1; ++it) {
@@ -257,7 +293,8 @@ __global__ void __launch_bounds__(TX * TY * TZ)
             int a = e / (TL::CY * TL::CZ), r = e - a * (TL::CY * TL::CZ), b = r / TL::CZ, c = r - b * TL::CZ;
             int k = k0 - 2 + c;
             if (k >= 0 && k < nz) {
-                int ci = (wrap1(i0 - 2 + a, nx) * ny + wrap1(j0 - 2 + b, ny)) * nzs + k;
+                unsigned col = __umul24(wrap1(i0 - 2 + a, nx), ny) + wrap1(j0 - 2 + b, ny);
+                unsigned ci = __umul24(col, nzs) + k;
                 c_rho[it] = (R)qs.rho[ci];
                 c_rth[it] = (R)qs.rth[ci];
             }
@@ -275,17 +312,32 @@ __global__ void __launch_bounds__(TX * TY * TZ)
             int K = k0 - 1 + c;
             if (K >= 0 && K <= nz) {
                 int Kc = K < nz ? K : nz - 1;
-                int hcol = wrap1(i0 - 1 + a, nx) * ny + wrap1(j0 - 1 + b, ny);
-                int p = hcol * nzs + Kc;
+                unsigned col = __umul24(wrap1(i0 - 1 + a, nx), ny) + wrap1(j0 - 1 + b, ny);
+                unsigned p = __umul24(col, nzs) + Kc;
                 l_m0[it] = (R)qs.mu[p];
                 l_m1[it] = (R)qs.mv[p];
                 l_m2[it] = (R)qs.mw[p];
-                l_kb[it] = G.colk[ncol + hcol];
+                l_kb[it] = G.colk[ncol + col];
             }
         }
     }
-    // ---- phase 1: cell scalars and p' (p' for the cells i0-1..i0+TX-1 x ... the momentum
-    // stencils of the tile use) ----
+    for (int e = tid; e < 6 * NB; e += NT) {
+        int pr = e / NB, kk = k0 - 2 + (e - pr * NB);
+        kk = kk < 0 ? 0 : (kk >= nz ? nz - 1 : kk);
+        double v;
+        switch (pr) {
+        case 0: v = P.rhob[kk]; break;
+        case 1: v = P.rthb[kk]; break;
+        case 2: v = P.pb[kk]; break;
+        case 3: v = P.irthb[kk]; break;
+        case 4: v = P.rhobc[kk]; break;
+        default: v = kk > 0 ? 0.5 * (P.rthb[kk - 1] + P.rthb[kk]) : P.rthb[0]; break;
+        }
+        s_b[pr][e - pr * NB] = (R)v;
+    }
+    __syncthreads();
+    // ---- phase 1: cell scalars and p' (p' for the cells i0-1..i0+TX-1 x ... used by the momentum
+    // stencils of the tile) ----
 #pragma unroll
     for (int it = 0; it < IT1; ++it) {
         int e = tid + it * NT;
@@ -294,7 +346,7 @@ __global__ void __launch_bounds__(TX * TY * TZ)
             int k = k0 - 2 + c;
             R pp = (R)0;
             if (k >= 0 && k < nz && a >= 1 && a <= TX + 1 && b >= 1 && b <= TY + 1 && c >= 1 && c <= TZ + 1)
-                pp = eos_pprime_k<R>(c_rth[it], k, P);
+                pp = eos_staged<R>(c_rth[it], s_b[3][c], s_b[2][c], P);
             s_rho[e] = c_rho[it];
             s_rth[e] = c_rth[it];
             s_pp[e] = pp;
@@ -313,8 +365,8 @@ __global__ void __launch_bounds__(TX * TY * TZ)
                 int Kc = K < nz ? K : nz - 1;  // the rigid lid copies the level below
                 bool pred = Kc >= l_kb[it];
                 if (!pred) {
-                    int hcol = wrap1(i0 - 1 + a, nx) * ny + wrap1(j0 - 1 + b, ny);
-                    pred = G.vcls[hcol * nzs + Kc] == CC_PRED;
+                    unsigned col = __umul24(wrap1(i0 - 1 + a, nx), ny) + wrap1(j0 - 1 + b, ny);
+                    pred = G.vcls[__umul24(col, nzs) + Kc] == CC_PRED;
                 }
                 if (pred) {
                     int cz = Kc - k0 + 1;  // LDS level of cell level Kc-1
@@ -323,9 +375,9 @@ __global__ void __launch_bounds__(TX * TY * TZ)
                            ((s_rho[TL::cs(a, b, cz + 1)] + s_rho[TL::cs(a + 1, b, cz + 1)]) +
                             (s_rho[TL::cs(a, b + 1, cz + 1)] + s_rho[TL::cs(a + 1, b + 1, cz + 1)]));
                     R rpc = sm * (R)0.125;
-                    R ri = recip((R)P.rhobc[Kc] + rpc);
-                    u0 = (l_m0[it] - rpc * Ux) * ri;
-                    u1 = (l_m1[it] - rpc * Vy) * ri;
+                    R ri = recip(s_b[4][Kc - k0 + 2] + rpc);
+                    u0 = fmaR(-rpc, Ux, l_m0[it]) * ri;
+                    u1 = fmaR(-rpc, Vy, l_m1[it]) * ri;
                     u2 = l_m2[it] * ri;
                 } else {
                     u0 = l_m0[it];
@@ -345,10 +397,11 @@ __global__ void __launch_bounds__(TX * TY * TZ)
     const int tx = tid / (TY * TZ), ty = (tid / TZ) % TY, tz = tid % TZ;
     const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
     if (i >= nx || j >= ny || k >= nz) return;
-    const int hc = i * ny + j;
-    const int c = hc * nzs + k;
+    const unsigned hc = __umul24(i, ny) + j;
+    const unsigned c = __umul24(hc, nzs) + k;
     const int ca = tx + 2, cb = ty + 2, cc = tz + 2;  // LDS cell coordinates of (i,j,k)
     const int la = tx + 1, lb = ty + 1, lc = tz + 1;  // LDS lattice coordinates of (i,j,k)
+    const int kb = tz + 2;                            // staged base index of level k
     bool bad = false;
 
     // ---- scalars ----
@@ -360,55 +413,48 @@ __global__ void __launch_bounds__(TX * TY * TZ)
         if (!band) {
             // regular cell: V = 1, open faces, neighbours at their own level; the base-state and
             // reference-flow fluxes of opposite faces cancel exactly
-            const R h = (R)0.5, q4 = (R)0.25;
-            const R Sx = (R)(d.dy * d.dz), Sy = (R)(d.dz * d.dx), Sz = (R)(d.dx * d.dy);
-            const R b0 = (R)P.rhob[k], b1 = (R)P.rthb[k];
-            double r0 = 0.0, r1 = 0.0;
-            // x faces
-            {
-                R unm = q4 * ((s_u[TL::ls(la, lb, lc)] + s_u[TL::ls(la, lb + 1, lc)]) +
-                              (s_u[TL::ls(la, lb, lc + 1)] + s_u[TL::ls(la, lb + 1, lc + 1)]));
-                R unp = q4 * ((s_u[TL::ls(la + 1, lb, lc)] + s_u[TL::ls(la + 1, lb + 1, lc)]) +
-                              (s_u[TL::ls(la + 1, lb, lc + 1)] + s_u[TL::ls(la + 1, lb + 1, lc + 1)]));
-                R nm0 = s_rho[TL::cs(ca - 1, cb, cc)], nm1 = s_rth[TL::cs(ca - 1, cb, cc)];
-                R np0 = s_rho[TL::cs(ca + 1, cb, cc)], np1 = s_rth[TL::cs(ca + 1, cb, cc)];
-                R tm = unm + Ux, tp = unp + Ux;
-                R fm0 = (b0 * unm + h * (nm0 + rc0) * tm) * Sx, fp0 = (b0 * unp + h * (rc0 + np0) * tp) * Sx;
-                R fm1 = (b1 * unm + h * (nm1 + rc1) * tm) * Sx, fp1 = (b1 * unp + h * (rc1 + np1) * tp) * Sx;
+            const R ASx = (R)(0.25 * 1.0 * (d.dy * d.dz)), ASy = (R)(0.25 * 1.0 * (d.dz * d.dx));
+            const R ASz = (R)(0.25 * 1.0 * (d.dx * d.dy));
+            const R UASx = (R)(P.ux * 1.0 * (d.dy * d.dz)), UASy = (R)(P.vy * 1.0 * (d.dz * d.dx));
+            const R b0 = s_b[0][kb], b1 = s_b[1][kb];
+            R fm0, fm1, fp0, fp1;
+            double r0, r1;
+            {  // x faces
+                R sm = (s_u[TL::ls(la, lb, lc)] + s_u[TL::ls(la, lb + 1, lc)]) +
+                       (s_u[TL::ls(la, lb, lc + 1)] + s_u[TL::ls(la, lb + 1, lc + 1)]);
+                R sp = (s_u[TL::ls(la + 1, lb, lc)] + s_u[TL::ls(la + 1, lb + 1, lc)]) +
+                       (s_u[TL::ls(la + 1, lb, lc + 1)] + s_u[TL::ls(la + 1, lb + 1, lc + 1)]);
+                scalar_face_flux<R>(sm, ASx, UASx, b0, b1, s_rho[TL::cs(ca - 1, cb, cc)], rc0,
+                                    s_rth[TL::cs(ca - 1, cb, cc)], rc1, fm0, fm1);
+                scalar_face_flux<R>(sp, ASx, UASx, b0, b1, rc0, s_rho[TL::cs(ca + 1, cb, cc)], rc1,
+                                    s_rth[TL::cs(ca + 1, cb, cc)], fp0, fp1);
+                r0 = (double)fp0 - (double)fm0;
+                r1 = (double)fp1 - (double)fm1;
+            }
+            {  // y faces
+                R sm = (s_v[TL::ls(la, lb, lc)] + s_v[TL::ls(la + 1, lb, lc)]) +
+                       (s_v[TL::ls(la, lb, lc + 1)] + s_v[TL::ls(la + 1, lb, lc + 1)]);
+                R sp = (s_v[TL::ls(la, lb + 1, lc)] + s_v[TL::ls(la + 1, lb + 1, lc)]) +
+                       (s_v[TL::ls(la, lb + 1, lc + 1)] + s_v[TL::ls(la + 1, lb + 1, lc + 1)]);
+                scalar_face_flux<R>(sm, ASy, UASy, b0, b1, s_rho[TL::cs(ca, cb - 1, cc)], rc0,
+                                    s_rth[TL::cs(ca, cb - 1, cc)], rc1, fm0, fm1);
+                scalar_face_flux<R>(sp, ASy, UASy, b0, b1, rc0, s_rho[TL::cs(ca, cb + 1, cc)], rc1,
+                                    s_rth[TL::cs(ca, cb + 1, cc)], fp0, fp1);
                 r0 += (double)fp0 - (double)fm0;
                 r1 += (double)fp1 - (double)fm1;
             }
-            // y faces
-            {
-                R unm = q4 * ((s_v[TL::ls(la, lb, lc)] + s_v[TL::ls(la + 1, lb, lc)]) +
-                              (s_v[TL::ls(la, lb, lc + 1)] + s_v[TL::ls(la + 1, lb, lc + 1)]));
-                R unp = q4 * ((s_v[TL::ls(la, lb + 1, lc)] + s_v[TL::ls(la + 1, lb + 1, lc)]) +
-                              (s_v[TL::ls(la, lb + 1, lc + 1)] + s_v[TL::ls(la + 1, lb + 1, lc + 1)]));
-                R nm0 = s_rho[TL::cs(ca, cb - 1, cc)], nm1 = s_rth[TL::cs(ca, cb - 1, cc)];
-                R np0 = s_rho[TL::cs(ca, cb + 1, cc)], np1 = s_rth[TL::cs(ca, cb + 1, cc)];
-                R tm = unm + Vy, tp = unp + Vy;
-                R fm0 = (b0 * unm + h * (nm0 + rc0) * tm) * Sy, fp0 = (b0 * unp + h * (rc0 + np0) * tp) * Sy;
-                R fm1 = (b1 * unm + h * (nm1 + rc1) * tm) * Sy, fp1 = (b1 * unp + h * (rc1 + np1) * tp) * Sy;
-                r0 += (double)fp0 - (double)fm0;
-                r1 += (double)fp1 - (double)fm1;
-            }
-            // z faces (k >= 1 in the regular region; the rigid lid closes the top of k = nz-1)
-            {
-                R unm = q4 * ((s_w[TL::ls(la, lb, lc)] + s_w[TL::ls(la + 1, lb, lc)]) +
-                              (s_w[TL::ls(la, lb + 1, lc)] + s_w[TL::ls(la + 1, lb + 1, lc)]));
-                R nm0 = s_rho[TL::cs(ca, cb, cc - 1)], nm1 = s_rth[TL::cs(ca, cb, cc - 1)];
-                R bm0 = (R)(0.5 * (P.rhob[k - 1] + P.rhob[k])), bm1 = (R)(0.5 * (P.rthb[k - 1] + P.rthb[k]));
-                R fm0 = (bm0 * unm + h * (nm0 + rc0) * unm) * Sz;
-                R fm1 = (bm1 * unm + h * (nm1 + rc1) * unm) * Sz;
+            {  // z faces (k >= 1 in the regular region; the rigid lid closes the top of nz-1)
+                R sm = (s_w[TL::ls(la, lb, lc)] + s_w[TL::ls(la + 1, lb, lc)]) +
+                       (s_w[TL::ls(la, lb + 1, lc)] + s_w[TL::ls(la + 1, lb + 1, lc)]);
+                scalar_face_flux<R>(sm, ASz, (R)0, s_b[4][kb], s_b[5][kb], s_rho[TL::cs(ca, cb, cc - 1)], rc0,
+                                    s_rth[TL::cs(ca, cb, cc - 1)], rc1, fm0, fm1);
                 r0 -= (double)fm0;
                 r1 -= (double)fm1;
                 if (k + 1 < nz) {
-                    R unp = q4 * ((s_w[TL::ls(la, lb, lc + 1)] + s_w[TL::ls(la + 1, lb, lc + 1)]) +
-                                  (s_w[TL::ls(la, lb + 1, lc + 1)] + s_w[TL::ls(la + 1, lb + 1, lc + 1)]));
-                    R np0 = s_rho[TL::cs(ca, cb, cc + 1)], np1 = s_rth[TL::cs(ca, cb, cc + 1)];
-                    R bp0 = (R)(0.5 * (P.rhob[k] + P.rhob[k + 1])), bp1 = (R)(0.5 * (P.rthb[k] + P.rthb[k + 1]));
-                    R fp0 = (bp0 * unp + h * (rc0 + np0) * unp) * Sz;
-                    R fp1 = (bp1 * unp + h * (rc1 + np1) * unp) * Sz;
+                    R sp = (s_w[TL::ls(la, lb, lc + 1)] + s_w[TL::ls(la + 1, lb, lc + 1)]) +
+                           (s_w[TL::ls(la, lb + 1, lc + 1)] + s_w[TL::ls(la + 1, lb + 1, lc + 1)]);
+                    scalar_face_flux<R>(sp, ASz, (R)0, s_b[4][kb + 1], s_b[5][kb + 1], rc0,
+                                        s_rho[TL::cs(ca, cb, cc + 1)], rc1, s_rth[TL::cs(ca, cb, cc + 1)], fp0, fp1);
                     r0 += (double)fp0;
                     r1 += (double)fp1;
                 }
@@ -432,39 +478,38 @@ __global__ void __launch_bounds__(TX * TY * TZ)
                     if (k + dc < 0 || k + dc >= nz) continue;  // ground and rigid lid
                 }
                 int ip = wrap1(i + (axis == 0 && plus), nx), jp = wrap1(j + (axis == 1 && plus), ny);
-                int fu = (ip * ny + jp) * nzs + k + (axis == 2 && plus);
+                unsigned fu = __umul24(__umul24(ip, ny) + jp, nzs) + k + (axis == 2 && plus);
                 double A = axis == 0 ? G.Ax[fu] : (axis == 1 ? G.Ay[fu] : G.Az[fu]);
                 if (A == 0.0) continue;
                 int in = wrap1(i + da, nx), jn = wrap1(j + db, ny);
-                int32_t mn = G.master[(in * ny + jn) * nzs + k + dc];
+                int32_t mn = G.master[__umul24(__umul24(in, ny) + jn, nzs) + k + dc];
                 if (mn < 0) continue;
                 int kn = mn % nzs;
                 int fa = la + (axis == 0 && plus), fb = lb + (axis == 1 && plus), fc = lc + (axis == 2 && plus);
-                R un;
+                R s4;
                 double S, Un;
                 if (axis == 0) {
-                    un = (R)0.25 * ((s_u[TL::ls(fa, fb, fc)] + s_u[TL::ls(fa, fb + 1, fc)]) +
-                                    (s_u[TL::ls(fa, fb, fc + 1)] + s_u[TL::ls(fa, fb + 1, fc + 1)]));
+                    s4 = (s_u[TL::ls(fa, fb, fc)] + s_u[TL::ls(fa, fb + 1, fc)]) +
+                         (s_u[TL::ls(fa, fb, fc + 1)] + s_u[TL::ls(fa, fb + 1, fc + 1)]);
                     S = d.dy * d.dz; Un = P.ux;
                 } else if (axis == 1) {
-                    un = (R)0.25 * ((s_v[TL::ls(fa, fb, fc)] + s_v[TL::ls(fa + 1, fb, fc)]) +
-                                    (s_v[TL::ls(fa, fb, fc + 1)] + s_v[TL::ls(fa + 1, fb, fc + 1)]));
+                    s4 = (s_v[TL::ls(fa, fb, fc)] + s_v[TL::ls(fa + 1, fb, fc)]) +
+                         (s_v[TL::ls(fa, fb, fc + 1)] + s_v[TL::ls(fa + 1, fb, fc + 1)]);
                     S = d.dz * d.dx; Un = P.vy;
                 } else {
-                    un = (R)0.25 * ((s_w[TL::ls(fa, fb, fc)] + s_w[TL::ls(fa + 1, fb, fc)]) +
-                                    (s_w[TL::ls(fa, fb + 1, fc)] + s_w[TL::ls(fa + 1, fb + 1, fc)]));
+                    s4 = (s_w[TL::ls(fa, fb, fc)] + s_w[TL::ls(fa + 1, fb, fc)]) +
+                         (s_w[TL::ls(fa, fb + 1, fc)] + s_w[TL::ls(fa + 1, fb + 1, fc)]);
                     S = d.dx * d.dy; Un = 0.0;
                 }
                 const R rn0 = s_rho[TL::cs(ca + da, cb + db, cc + dc)], rn1 = s_rth[TL::cs(ca + da, cb + db, cc + dc)];
                 int klo = plus ? k : kn, kup = plus ? kn : k;
                 double pb0 = 0.5 * (P.rhob[klo] + P.rhob[kup]);
                 double pb1 = 0.5 * (P.rthb[klo] + P.rthb[kup]);
-                R pp0 = plus ? (R)0.5 * (rc0 + rn0) : (R)0.5 * (rn0 + rc0);
-                R pp1 = plus ? (R)0.5 * (rc1 + rn1) : (R)0.5 * (rn1 + rc1);
-                R AS = (R)(A * S);
-                R unt = un + (R)Un;
-                R f0 = ((R)pb0 * un + pp0 * unt) * AS;
-                R f1 = ((R)pb1 * un + pp1 * unt) * AS;
+                R f0, f1;
+                if (plus)
+                    scalar_face_flux<R>(s4, (R)(0.25 * A * S), (R)(Un * A * S), (R)pb0, (R)pb1, rc0, rn0, rc1, rn1, f0, f1);
+                else
+                    scalar_face_flux<R>(s4, (R)(0.25 * A * S), (R)(Un * A * S), (R)pb0, (R)pb1, rn0, rc0, rn1, rc1, f0, f1);
                 double h0 = pb0 * Un * A * S, h1 = pb1 * Un * A * S;
                 if (plus) { r0 += (double)f0; r1 += (double)f1; g0 += h0; g1 += h1; }
                 else { r0 -= (double)f0; r1 -= (double)f1; g0 -= h0; g1 -= h1; }
@@ -476,8 +521,8 @@ __global__ void __launch_bounds__(TX * TY * TZ)
         if (MODE == 0) {
             double x0 = (double)qn.rho[c], x1 = (double)qn.rth[c];
             if (final_stage && qn.rho_lo) { x0 += (double)qn.rho_lo[c]; x1 += (double)qn.rth_lo[c]; }
-            x0 += cdt * L0;
-            x1 += cdt * L1;
+            x0 = fmaR(cdt, L0, x0);
+            x1 = fmaR(cdt, L1, x1);
             T a = (T)x0, b = (T)x1;
             bad = !isfinite(a) || !isfinite(b);
             qo.rho[c] = a;
@@ -499,6 +544,7 @@ __global__ void __launch_bounds__(TX * TY * TZ)
     // ---- momentum at the lattice point (i,j,k) ----
     const bool pred = k >= G.colk[ncol + hc] || G.vcls[c] == CC_PRED;
     if (pred) {
+        const R h = (R)0.5, q4 = (R)0.25;
         R u[7][3];
         const int off[7][3] = {{0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
 #pragma unroll
@@ -513,48 +559,54 @@ __global__ void __launch_bounds__(TX * TY * TZ)
             rp[s] = s_rho[e];
             pp[s] = s_pp[e];
         }
-        const R q4 = (R)0.25, h = (R)0.5;
-        R rxm = q4 * ((rp[0] + rp[2]) + (rp[4] + rp[6])), rxp = q4 * ((rp[1] + rp[3]) + (rp[5] + rp[7]));
-        R rym = q4 * ((rp[0] + rp[1]) + (rp[4] + rp[5])), ryp = q4 * ((rp[2] + rp[3]) + (rp[6] + rp[7]));
-        R rzm = q4 * ((rp[0] + rp[1]) + (rp[2] + rp[3])), rzp = q4 * ((rp[4] + rp[5]) + (rp[6] + rp[7]));
-        R pgx = (q4 * ((pp[1] + pp[3]) + (pp[5] + pp[7])) - q4 * ((pp[0] + pp[2]) + (pp[4] + pp[6]))) * (R)P.idx;
-        R pgy = (q4 * ((pp[2] + pp[3]) + (pp[6] + pp[7])) - q4 * ((pp[0] + pp[1]) + (pp[4] + pp[5]))) * (R)P.idy;
-        R pgz = (q4 * ((pp[4] + pp[5]) + (pp[6] + pp[7])) - q4 * ((pp[0] + pp[1]) + (pp[2] + pp[3]))) * (R)P.idz;
-        R r8 = (R)0.125 * (((rp[0] + rp[1]) + (rp[2] + rp[3])) + ((rp[4] + rp[5]) + (rp[6] + rp[7])));
-        const R rbc = (R)P.rhobc[k];
-        const R rbzm = (R)P.rhob[k - 1], rbzp = (R)P.rhob[k];
+        // density perturbation on the six faces of the velocity cell, pressure gradient, buoyancy
+        const R rxm = q4 * ((rp[0] + rp[2]) + (rp[4] + rp[6])), rxp = q4 * ((rp[1] + rp[3]) + (rp[5] + rp[7]));
+        const R rym = q4 * ((rp[0] + rp[1]) + (rp[4] + rp[5])), ryp = q4 * ((rp[2] + rp[3]) + (rp[6] + rp[7]));
+        const R rzm = q4 * ((rp[0] + rp[1]) + (rp[2] + rp[3])), rzp = q4 * ((rp[4] + rp[5]) + (rp[6] + rp[7]));
         const R ix = (R)P.idx, iy = (R)P.idy, iz = (R)P.idz;
-        // normal velocities on the six faces (shared by the three components)
+        const R pgx = (((pp[1] + pp[3]) + (pp[5] + pp[7])) - ((pp[0] + pp[2]) + (pp[4] + pp[6]))) * (q4 * ix);
+        const R pgy = (((pp[2] + pp[3]) + (pp[6] + pp[7])) - ((pp[0] + pp[1]) + (pp[4] + pp[5]))) * (q4 * iy);
+        const R pgz = (((pp[4] + pp[5]) + (pp[6] + pp[7])) - ((pp[0] + pp[1]) + (pp[2] + pp[3]))) * (q4 * iz);
+        const R r8 = (R)0.125 * (((rp[0] + rp[1]) + (rp[2] + rp[3])) + ((rp[4] + rp[5]) + (rp[6] + rp[7])));
+        const R rbc = s_b[4][kb];                           // base density on x and y faces
+        const R rbzm = s_b[0][kb - 1], rbzp = s_b[0][kb];  // base density on the z faces
+        // Face flux of component m (perturbation form; the base product rbc U M0 cancels between
+        // opposite faces):  F = rbc U mb + (rbc ub + r'(U + ub)) (M0 + mb) on x/y faces with
+        // ub, mb the face means of the normal and m velocity perturbations; F = (rbz + r') wb (M0 + mb)
+        // on z faces.  The factor in front of (M0 + mb) is shared by the three components.
         const R uxp = h * (u[0][0] + u[2][0]), uxm = h * (u[1][0] + u[0][0]);
         const R vyp = h * (u[0][1] + u[4][1]), vym = h * (u[3][1] + u[0][1]);
         const R wzp = h * (u[0][2] + u[6][2]), wzm = h * (u[5][2] + u[0][2]);
+        const R Axf = rbc * Ux, Ayf = rbc * Vy;
+        const R Bxp = fmaR(rxp, Ux + uxp, rbc * uxp), Bxm = fmaR(rxm, Ux + uxm, rbc * uxm);
+        const R Byp = fmaR(ryp, Vy + vyp, rbc * vyp), Bym = fmaR(rym, Vy + vym, rbc * vym);
+        const R Czp = (rbzp + rzp) * wzp, Czm = (rbzm + rzm) * wzm;
         R Lm[3];
 #pragma unroll
         for (int cm = 0; cm < 3; ++cm) {
-            R M0 = cm == 0 ? Ux : (cm == 1 ? Vy : (R)0);
+            const R M0 = cm == 0 ? Ux : (cm == 1 ? Vy : (R)0);
             R mb;
             mb = h * (u[0][cm] + u[2][cm]);
-            R fxp = rbc * (Ux * mb + uxp * M0 + uxp * mb) + rxp * (Ux + uxp) * (M0 + mb);
+            R fxp = fmaR(Axf, mb, Bxp * (M0 + mb));
             mb = h * (u[1][cm] + u[0][cm]);
-            R fxm = rbc * (Ux * mb + uxm * M0 + uxm * mb) + rxm * (Ux + uxm) * (M0 + mb);
+            R fxm = fmaR(Axf, mb, Bxm * (M0 + mb));
             mb = h * (u[0][cm] + u[4][cm]);
-            R fyp = rbc * (Vy * mb + vyp * M0 + vyp * mb) + ryp * (Vy + vyp) * (M0 + mb);
+            R fyp = fmaR(Ayf, mb, Byp * (M0 + mb));
             mb = h * (u[3][cm] + u[0][cm]);
-            R fym = rbc * (Vy * mb + vym * M0 + vym * mb) + rym * (Vy + vym) * (M0 + mb);
+            R fym = fmaR(Ayf, mb, Bym * (M0 + mb));
             mb = h * (u[0][cm] + u[6][cm]);
-            R fzp = (rbzp + rzp) * wzp * (M0 + mb);
+            R fzp = Czp * (M0 + mb);
             mb = h * (u[5][cm] + u[0][cm]);
-            R fzm = (rbzm + rzm) * wzm * (M0 + mb);
-            R adv = (fxp - fxm) * ix + (fyp - fym) * iy + (fzp - fzm) * iz;
-            R pgf = cm == 0 ? pgx : (cm == 1 ? pgy : pgz);
-            R buoy = cm == 2 ? (R)P.g * r8 : (R)0;
-            Lm[cm] = -adv - pgf - buoy;
+            R fzm = Czm * (M0 + mb);
+            R adv = fmaR(fzp - fzm, iz, fmaR(fyp - fym, iy, (fxp - fxm) * ix));
+            R src = cm == 0 ? pgx : (cm == 1 ? pgy : fmaR((R)P.g, r8, pgz));
+            Lm[cm] = -(adv + src);
         }
         if (MODE == 0) {
-            R cd = (R)cdt;
-            T a = (T)((R)qn.mu[c] + cd * Lm[0]);
-            T b = (T)((R)qn.mv[c] + cd * Lm[1]);
-            T e = (T)((R)qn.mw[c] + cd * Lm[2]);
+            const R cd = (R)cdt;
+            T a = (T)fmaR(cd, Lm[0], (R)qn.mu[c]);
+            T b = (T)fmaR(cd, Lm[1], (R)qn.mv[c]);
+            T e = (T)fmaR(cd, Lm[2], (R)qn.mw[c]);
             bad = bad || !isfinite(a) || !isfinite(b) || !isfinite(e);
             qo.mu[c] = a; qo.mv[c] = b; qo.mw[c] = e;
         } else {
@@ -855,6 +907,7 @@ static bool make_views(const char *what, const cc_grid *grid, const cc_phys *phy
     // binomial coefficients of (1+x)^gamma - 1
     P.binom[0] = P.gam;
     for (int n = 1; n < EOS_TERMS; ++n) P.binom[n] = P.binom[n - 1] * (P.gam - n) / (n + 1);
+    for (int n = 0; n < EOS_TERMS; ++n) P.binomf[n] = (float)P.binom[n];
     return true;
 }
 
