@@ -259,6 +259,238 @@ __device__ __forceinline__ R eos_staged(R rthp, R irthb, R pb, const Phy &P)
     return pb * (x * acc);
 }
 
+// LDS view of the staged neighbourhood of one output point (i,j,k): cells at (i+di, j+dj, k+dk)
+// and lattice points at (i+di, j+dj, k+dk) for di in {-1,0,1}, addressed through the index of the
+// i-1 / i / i+1 plane entry plus dj * stride + dk; staged base profiles b[6][nb] at level kb.
+template <typename R>
+struct LView {
+    const R *rho, *rth, *pp, *u, *v, *w, *b;
+    int cb[3], lb[3];
+    int csj, lsj, nb, kb;
+    __device__ __forceinline__ int C(int di, int dj, int dk) const { return cb[di + 1] + dj * csj + dk; }
+    __device__ __forceinline__ int L(int di, int dj, int dk) const { return lb[di + 1] + dj * lsj + dk; }
+    __device__ __forceinline__ R B(int prof, int dk) const { return b[prof * nb + kb + dk]; }
+};
+
+// Update (MODE 0) or tendency (MODE 1) of cell (i,j,k) and lattice point (i,j,k) from the staged
+// neighbourhood.  Above the per-column bands cells and lattice points are regular and no geometry
+// or class array is read; inside the bands single-cell groups read their apertures, group volume
+// and neighbour masters, and masters of multi-cell groups take the general gather path.
+template <typename T, int MODE>
+__device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &qs,
+                                            const SIn<T> &qn, const SOut<T> &qo, double cdt, int final_stage,
+                                            int i, int j, int k, const LView<typename Compute<T>::R> &V,
+                                            int64_t *st)
+{
+    using R = typename Compute<T>::R;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, nzs = d.nzs;
+    const unsigned ncol = (unsigned)(nx * ny);
+    const R Ux = (R)P.ux, Vy = (R)P.vy;
+    const unsigned hc = __umul24(i, ny) + j;
+    const unsigned c = __umul24(hc, nzs) + k;
+    bool bad = false;
+
+    // ---- scalars ----
+    const bool band = k < G.colk[hc];
+    const int8_t cl = band ? G.cls[c] : (int8_t)CC_OPEN;
+    if (cl == CC_OPEN || cl == CC_ORPHAN) {
+        double L0, L1;
+        const R rc0 = V.rho[V.C(0, 0, 0)], rc1 = V.rth[V.C(0, 0, 0)];
+        if (!band) {
+            // regular cell: V = 1, open faces, neighbours at their own level; the base-state and
+            // reference-flow fluxes of opposite faces cancel exactly
+            const R ASx = (R)(0.25 * 1.0 * (d.dy * d.dz)), ASy = (R)(0.25 * 1.0 * (d.dz * d.dx));
+            const R ASz = (R)(0.25 * 1.0 * (d.dx * d.dy));
+            const R UASx = (R)(P.ux * 1.0 * (d.dy * d.dz)), UASy = (R)(P.vy * 1.0 * (d.dz * d.dx));
+            const R b0 = V.B(0, 0), b1 = V.B(1, 0);
+            R fm0, fm1, fp0, fp1;
+            double r0, r1;
+            {  // x faces
+                R sm = (V.u[V.L(0, 0, 0)] + V.u[V.L(0, 1, 0)]) + (V.u[V.L(0, 0, 1)] + V.u[V.L(0, 1, 1)]);
+                R sp = (V.u[V.L(1, 0, 0)] + V.u[V.L(1, 1, 0)]) + (V.u[V.L(1, 0, 1)] + V.u[V.L(1, 1, 1)]);
+                scalar_face_flux<R>(sm, ASx, UASx, b0, b1, V.rho[V.C(-1, 0, 0)], rc0, V.rth[V.C(-1, 0, 0)], rc1, fm0, fm1);
+                scalar_face_flux<R>(sp, ASx, UASx, b0, b1, rc0, V.rho[V.C(1, 0, 0)], rc1, V.rth[V.C(1, 0, 0)], fp0, fp1);
+                r0 = (double)fp0 - (double)fm0;
+                r1 = (double)fp1 - (double)fm1;
+            }
+            {  // y faces
+                R sm = (V.v[V.L(0, 0, 0)] + V.v[V.L(1, 0, 0)]) + (V.v[V.L(0, 0, 1)] + V.v[V.L(1, 0, 1)]);
+                R sp = (V.v[V.L(0, 1, 0)] + V.v[V.L(1, 1, 0)]) + (V.v[V.L(0, 1, 1)] + V.v[V.L(1, 1, 1)]);
+                scalar_face_flux<R>(sm, ASy, UASy, b0, b1, V.rho[V.C(0, -1, 0)], rc0, V.rth[V.C(0, -1, 0)], rc1, fm0, fm1);
+                scalar_face_flux<R>(sp, ASy, UASy, b0, b1, rc0, V.rho[V.C(0, 1, 0)], rc1, V.rth[V.C(0, 1, 0)], fp0, fp1);
+                r0 += (double)fp0 - (double)fm0;
+                r1 += (double)fp1 - (double)fm1;
+            }
+            {  // z faces (k >= 1 in the regular region; the rigid lid closes the top of nz-1)
+                R sm = (V.w[V.L(0, 0, 0)] + V.w[V.L(1, 0, 0)]) + (V.w[V.L(0, 1, 0)] + V.w[V.L(1, 1, 0)]);
+                scalar_face_flux<R>(sm, ASz, (R)0, V.B(4, 0), V.B(5, 0), V.rho[V.C(0, 0, -1)], rc0,
+                                    V.rth[V.C(0, 0, -1)], rc1, fm0, fm1);
+                r0 -= (double)fm0;
+                r1 -= (double)fm1;
+                if (k + 1 < nz) {
+                    R sp = (V.w[V.L(0, 0, 1)] + V.w[V.L(1, 0, 1)]) + (V.w[V.L(0, 1, 1)] + V.w[V.L(1, 1, 1)]);
+                    scalar_face_flux<R>(sp, ASz, (R)0, V.B(4, 1), V.B(5, 1), rc0, V.rho[V.C(0, 0, 1)], rc1,
+                                        V.rth[V.C(0, 0, 1)], fp0, fp1);
+                    r0 += (double)fp0;
+                    r1 += (double)fp1;
+                }
+            }
+            L0 = -r0 * P.idV;
+            L1 = -r1 * P.idV;
+        } else if (G.gnext[c] != -1) {  // master of a multi-cell group: general gather
+            double L[2];
+            group_scalar_tendency<T>(d, G, P, qs, c, L);
+            L0 = L[0]; L1 = L[1];
+        } else {
+            // single-cell group in the band: apertures, group volume and neighbour masters
+            double r0 = 0.0, r1 = 0.0, g0 = 0.0, g1 = 0.0;
+            for (int f = 0; f < 6; ++f) {
+                int axis = f >> 1, plus = f & 1;
+                int da = 0, db = 0, dc = 0;
+                if (axis == 0) da = plus ? 1 : -1;
+                else if (axis == 1) db = plus ? 1 : -1;
+                else {
+                    dc = plus ? 1 : -1;
+                    if (k + dc < 0 || k + dc >= nz) continue;  // ground and rigid lid
+                }
+                int ip = wrap1(i + (axis == 0 && plus), nx), jp = wrap1(j + (axis == 1 && plus), ny);
+                unsigned fu = __umul24(__umul24(ip, ny) + jp, nzs) + k + (axis == 2 && plus);
+                double A = axis == 0 ? G.Ax[fu] : (axis == 1 ? G.Ay[fu] : G.Az[fu]);
+                if (A == 0.0) continue;
+                int in = wrap1(i + da, nx), jn = wrap1(j + db, ny);
+                int32_t mn = G.master[__umul24(__umul24(in, ny) + jn, nzs) + k + dc];
+                if (mn < 0) continue;
+                int kn = mn % nzs;
+                int fa = axis == 0 && plus, fb = axis == 1 && plus, fc = axis == 2 && plus;
+                R s4;
+                double S, Un;
+                if (axis == 0) {
+                    s4 = (V.u[V.L(fa, fb, fc)] + V.u[V.L(fa, fb + 1, fc)]) + (V.u[V.L(fa, fb, fc + 1)] + V.u[V.L(fa, fb + 1, fc + 1)]);
+                    S = d.dy * d.dz; Un = P.ux;
+                } else if (axis == 1) {
+                    s4 = (V.v[V.L(fa, fb, fc)] + V.v[V.L(fa + 1, fb, fc)]) + (V.v[V.L(fa, fb, fc + 1)] + V.v[V.L(fa + 1, fb, fc + 1)]);
+                    S = d.dz * d.dx; Un = P.vy;
+                } else {
+                    s4 = (V.w[V.L(fa, fb, fc)] + V.w[V.L(fa + 1, fb, fc)]) + (V.w[V.L(fa, fb + 1, fc)] + V.w[V.L(fa + 1, fb + 1, fc)]);
+                    S = d.dx * d.dy; Un = 0.0;
+                }
+                const R rn0 = V.rho[V.C(da, db, dc)], rn1 = V.rth[V.C(da, db, dc)];
+                int klo = plus ? k : kn, kup = plus ? kn : k;
+                double pb0 = 0.5 * (P.rhob[klo] + P.rhob[kup]);
+                double pb1 = 0.5 * (P.rthb[klo] + P.rthb[kup]);
+                R f0, f1;
+                if (plus)
+                    scalar_face_flux<R>(s4, (R)(0.25 * A * S), (R)(Un * A * S), (R)pb0, (R)pb1, rc0, rn0, rc1, rn1, f0, f1);
+                else
+                    scalar_face_flux<R>(s4, (R)(0.25 * A * S), (R)(Un * A * S), (R)pb0, (R)pb1, rn0, rc0, rn1, rc1, f0, f1);
+                double h0 = pb0 * Un * A * S, h1 = pb1 * Un * A * S;
+                if (plus) { r0 += (double)f0; r1 += (double)f1; g0 += h0; g1 += h1; }
+                else { r0 -= (double)f0; r1 -= (double)f1; g0 -= h0; g1 -= h1; }
+            }
+            double vol = G.Vgroup[c] * P.dV;
+            L0 = -(g0 + r0) / vol;
+            L1 = -(g1 + r1) / vol;
+        }
+        if (MODE == 0) {
+            double x0 = (double)qn.rho[c], x1 = (double)qn.rth[c];
+            if (final_stage && qn.rho_lo) { x0 += (double)qn.rho_lo[c]; x1 += (double)qn.rth_lo[c]; }
+            x0 = fmaR(cdt, L0, x0);
+            x1 = fmaR(cdt, L1, x1);
+            T a = (T)x0, b = (T)x1;
+            bad = !isfinite(a) || !isfinite(b);
+            qo.rho[c] = a;
+            qo.rth[c] = b;
+            if (final_stage && qo.rho_lo) {
+                qo.rho_lo[c] = (T)(x0 - (double)a);
+                qo.rth_lo[c] = (T)(x1 - (double)b);
+            }
+        } else {
+            qo.rho[c] = (T)L0;
+            qo.rth[c] = (T)L1;
+        }
+    } else if (cl == CC_SOLID || MODE == 1) {
+        qo.rho[c] = (T)0;
+        qo.rth[c] = (T)0;
+        if (MODE == 0 && final_stage && qo.rho_lo) { qo.rho_lo[c] = (T)0; qo.rth_lo[c] = (T)0; }
+    }
+
+    // ---- momentum at the lattice point (i,j,k) ----
+    const bool pred = k >= G.colk[ncol + hc] || G.vcls[c] == CC_PRED;
+    if (pred) {
+        const R h = (R)0.5, q4 = (R)0.25;
+        R u[7][3];
+        const int off[7][3] = {{0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+#pragma unroll
+        for (int s = 0; s < 7; ++s) {
+            int e = V.L(off[s][0], off[s][1], off[s][2]);
+            u[s][0] = V.u[e]; u[s][1] = V.v[e]; u[s][2] = V.w[e];
+        }
+        R rp[8], pp[8];  // bit0: i-1/i, bit1: j-1/j, bit2: k-1/k
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            int e = V.C((s & 1) - 1, ((s >> 1) & 1) - 1, (s >> 2) - 1);
+            rp[s] = V.rho[e];
+            pp[s] = V.pp[e];
+        }
+        // density perturbation on the six faces of the velocity cell, pressure gradient, buoyancy
+        const R rxm = q4 * ((rp[0] + rp[2]) + (rp[4] + rp[6])), rxp = q4 * ((rp[1] + rp[3]) + (rp[5] + rp[7]));
+        const R rym = q4 * ((rp[0] + rp[1]) + (rp[4] + rp[5])), ryp = q4 * ((rp[2] + rp[3]) + (rp[6] + rp[7]));
+        const R rzm = q4 * ((rp[0] + rp[1]) + (rp[2] + rp[3])), rzp = q4 * ((rp[4] + rp[5]) + (rp[6] + rp[7]));
+        const R ix = (R)P.idx, iy = (R)P.idy, iz = (R)P.idz;
+        const R pgx = (((pp[1] + pp[3]) + (pp[5] + pp[7])) - ((pp[0] + pp[2]) + (pp[4] + pp[6]))) * (q4 * ix);
+        const R pgy = (((pp[2] + pp[3]) + (pp[6] + pp[7])) - ((pp[0] + pp[1]) + (pp[4] + pp[5]))) * (q4 * iy);
+        const R pgz = (((pp[4] + pp[5]) + (pp[6] + pp[7])) - ((pp[0] + pp[1]) + (pp[2] + pp[3]))) * (q4 * iz);
+        const R r8 = (R)0.125 * (((rp[0] + rp[1]) + (rp[2] + rp[3])) + ((rp[4] + rp[5]) + (rp[6] + rp[7])));
+        const R rbc = V.B(4, 0);                         // base density on x and y faces
+        const R rbzm = V.B(0, -1), rbzp = V.B(0, 0);     // base density on the z faces
+        // Face flux of component m (perturbation form; the base product rbc U M0 cancels between
+        // opposite faces):  F = rbc U mb + (rbc ub + r'(U + ub)) (M0 + mb) on x/y faces with
+        // ub, mb the face means of the normal and m velocity perturbations; F = (rbz + r') wb (M0 + mb)
+        // on z faces.  The factor in front of (M0 + mb) is shared by the three components.
+        const R uxp = h * (u[0][0] + u[2][0]), uxm = h * (u[1][0] + u[0][0]);
+        const R vyp = h * (u[0][1] + u[4][1]), vym = h * (u[3][1] + u[0][1]);
+        const R wzp = h * (u[0][2] + u[6][2]), wzm = h * (u[5][2] + u[0][2]);
+        const R Axf = rbc * Ux, Ayf = rbc * Vy;
+        const R Bxp = fmaR(rxp, Ux + uxp, rbc * uxp), Bxm = fmaR(rxm, Ux + uxm, rbc * uxm);
+        const R Byp = fmaR(ryp, Vy + vyp, rbc * vyp), Bym = fmaR(rym, Vy + vym, rbc * vym);
+        const R Czp = (rbzp + rzp) * wzp, Czm = (rbzm + rzm) * wzm;
+        R Lm[3];
+#pragma unroll
+        for (int cm = 0; cm < 3; ++cm) {
+            const R M0 = cm == 0 ? Ux : (cm == 1 ? Vy : (R)0);
+            R mb;
+            mb = h * (u[0][cm] + u[2][cm]);
+            R fxp = fmaR(Axf, mb, Bxp * (M0 + mb));
+            mb = h * (u[1][cm] + u[0][cm]);
+            R fxm = fmaR(Axf, mb, Bxm * (M0 + mb));
+            mb = h * (u[0][cm] + u[4][cm]);
+            R fyp = fmaR(Ayf, mb, Byp * (M0 + mb));
+            mb = h * (u[3][cm] + u[0][cm]);
+            R fym = fmaR(Ayf, mb, Bym * (M0 + mb));
+            mb = h * (u[0][cm] + u[6][cm]);
+            R fzp = Czp * (M0 + mb);
+            mb = h * (u[5][cm] + u[0][cm]);
+            R fzm = Czm * (M0 + mb);
+            R adv = fmaR(fzp - fzm, iz, fmaR(fyp - fym, iy, (fxp - fxm) * ix));
+            R src = cm == 0 ? pgx : (cm == 1 ? pgy : fmaR((R)P.g, r8, pgz));
+            Lm[cm] = -(adv + src);
+        }
+        if (MODE == 0) {
+            const R cd = (R)cdt;
+            T a = (T)fmaR(cd, Lm[0], (R)qn.mu[c]);
+            T b = (T)fmaR(cd, Lm[1], (R)qn.mv[c]);
+            T e = (T)fmaR(cd, Lm[2], (R)qn.mw[c]);
+            bad = bad || !isfinite(a) || !isfinite(b) || !isfinite(e);
+            qo.mu[c] = a; qo.mv[c] = b; qo.mw[c] = e;
+        } else {
+            qo.mu[c] = (T)Lm[0]; qo.mv[c] = (T)Lm[1]; qo.mw[c] = (T)Lm[2];
+        }
+    } else if (MODE == 1) {
+        qo.mu[c] = (T)0; qo.mv[c] = (T)0; qo.mw[c] = (T)0;
+    }
+    if (bad) count_status(st, ST_NONFINITE);
+}
+
 template <typename T, int TX, int TY, int TZ, int MODE>
 __global__ void __launch_bounds__(TX * TY * TZ)
     k_stage_tiled(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn, SOut<T> qo, double cdt, int final_stage,
@@ -397,225 +629,164 @@ __global__ void __launch_bounds__(TX * TY * TZ)
     const int tx = tid / (TY * TZ), ty = (tid / TZ) % TY, tz = tid % TZ;
     const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
     if (i >= nx || j >= ny || k >= nz) return;
-    const unsigned hc = __umul24(i, ny) + j;
-    const unsigned c = __umul24(hc, nzs) + k;
-    const int ca = tx + 2, cb = ty + 2, cc = tz + 2;  // LDS cell coordinates of (i,j,k)
-    const int la = tx + 1, lb = ty + 1, lc = tz + 1;  // LDS lattice coordinates of (i,j,k)
-    const int kb = tz + 2;                            // staged base index of level k
-    bool bad = false;
-
-    // ---- scalars ----
-    const bool band = k < G.colk[hc];
-    const int8_t cl = band ? G.cls[c] : (int8_t)CC_OPEN;
-    if (cl == CC_OPEN || cl == CC_ORPHAN) {
-        double L0, L1;
-        const R rc0 = s_rho[TL::cs(ca, cb, cc)], rc1 = s_rth[TL::cs(ca, cb, cc)];
-        if (!band) {
-            // regular cell: V = 1, open faces, neighbours at their own level; the base-state and
-            // reference-flow fluxes of opposite faces cancel exactly
-            const R ASx = (R)(0.25 * 1.0 * (d.dy * d.dz)), ASy = (R)(0.25 * 1.0 * (d.dz * d.dx));
-            const R ASz = (R)(0.25 * 1.0 * (d.dx * d.dy));
-            const R UASx = (R)(P.ux * 1.0 * (d.dy * d.dz)), UASy = (R)(P.vy * 1.0 * (d.dz * d.dx));
-            const R b0 = s_b[0][kb], b1 = s_b[1][kb];
-            R fm0, fm1, fp0, fp1;
-            double r0, r1;
-            {  // x faces
-                R sm = (s_u[TL::ls(la, lb, lc)] + s_u[TL::ls(la, lb + 1, lc)]) +
-                       (s_u[TL::ls(la, lb, lc + 1)] + s_u[TL::ls(la, lb + 1, lc + 1)]);
-                R sp = (s_u[TL::ls(la + 1, lb, lc)] + s_u[TL::ls(la + 1, lb + 1, lc)]) +
-                       (s_u[TL::ls(la + 1, lb, lc + 1)] + s_u[TL::ls(la + 1, lb + 1, lc + 1)]);
-                scalar_face_flux<R>(sm, ASx, UASx, b0, b1, s_rho[TL::cs(ca - 1, cb, cc)], rc0,
-                                    s_rth[TL::cs(ca - 1, cb, cc)], rc1, fm0, fm1);
-                scalar_face_flux<R>(sp, ASx, UASx, b0, b1, rc0, s_rho[TL::cs(ca + 1, cb, cc)], rc1,
-                                    s_rth[TL::cs(ca + 1, cb, cc)], fp0, fp1);
-                r0 = (double)fp0 - (double)fm0;
-                r1 = (double)fp1 - (double)fm1;
-            }
-            {  // y faces
-                R sm = (s_v[TL::ls(la, lb, lc)] + s_v[TL::ls(la + 1, lb, lc)]) +
-                       (s_v[TL::ls(la, lb, lc + 1)] + s_v[TL::ls(la + 1, lb, lc + 1)]);
-                R sp = (s_v[TL::ls(la, lb + 1, lc)] + s_v[TL::ls(la + 1, lb + 1, lc)]) +
-                       (s_v[TL::ls(la, lb + 1, lc + 1)] + s_v[TL::ls(la + 1, lb + 1, lc + 1)]);
-                scalar_face_flux<R>(sm, ASy, UASy, b0, b1, s_rho[TL::cs(ca, cb - 1, cc)], rc0,
-                                    s_rth[TL::cs(ca, cb - 1, cc)], rc1, fm0, fm1);
-                scalar_face_flux<R>(sp, ASy, UASy, b0, b1, rc0, s_rho[TL::cs(ca, cb + 1, cc)], rc1,
-                                    s_rth[TL::cs(ca, cb + 1, cc)], fp0, fp1);
-                r0 += (double)fp0 - (double)fm0;
-                r1 += (double)fp1 - (double)fm1;
-            }
-            {  // z faces (k >= 1 in the regular region; the rigid lid closes the top of nz-1)
-                R sm = (s_w[TL::ls(la, lb, lc)] + s_w[TL::ls(la + 1, lb, lc)]) +
-                       (s_w[TL::ls(la, lb + 1, lc)] + s_w[TL::ls(la + 1, lb + 1, lc)]);
-                scalar_face_flux<R>(sm, ASz, (R)0, s_b[4][kb], s_b[5][kb], s_rho[TL::cs(ca, cb, cc - 1)], rc0,
-                                    s_rth[TL::cs(ca, cb, cc - 1)], rc1, fm0, fm1);
-                r0 -= (double)fm0;
-                r1 -= (double)fm1;
-                if (k + 1 < nz) {
-                    R sp = (s_w[TL::ls(la, lb, lc + 1)] + s_w[TL::ls(la + 1, lb, lc + 1)]) +
-                           (s_w[TL::ls(la, lb + 1, lc + 1)] + s_w[TL::ls(la + 1, lb + 1, lc + 1)]);
-                    scalar_face_flux<R>(sp, ASz, (R)0, s_b[4][kb + 1], s_b[5][kb + 1], rc0,
-                                        s_rho[TL::cs(ca, cb, cc + 1)], rc1, s_rth[TL::cs(ca, cb, cc + 1)], fp0, fp1);
-                    r0 += (double)fp0;
-                    r1 += (double)fp1;
-                }
-            }
-            L0 = -r0 * P.idV;
-            L1 = -r1 * P.idV;
-        } else if (G.gnext[c] != -1) {  // master of a multi-cell group: general gather
-            double L[2];
-            group_scalar_tendency<T>(d, G, P, qs, c, L);
-            L0 = L[0]; L1 = L[1];
-        } else {
-            // single-cell group in the band: apertures, group volume and neighbour masters
-            double r0 = 0.0, r1 = 0.0, g0 = 0.0, g1 = 0.0;
-            for (int f = 0; f < 6; ++f) {
-                int axis = f >> 1, plus = f & 1;
-                int da = 0, db = 0, dc = 0;
-                if (axis == 0) da = plus ? 1 : -1;
-                else if (axis == 1) db = plus ? 1 : -1;
-                else {
-                    dc = plus ? 1 : -1;
-                    if (k + dc < 0 || k + dc >= nz) continue;  // ground and rigid lid
-                }
-                int ip = wrap1(i + (axis == 0 && plus), nx), jp = wrap1(j + (axis == 1 && plus), ny);
-                unsigned fu = __umul24(__umul24(ip, ny) + jp, nzs) + k + (axis == 2 && plus);
-                double A = axis == 0 ? G.Ax[fu] : (axis == 1 ? G.Ay[fu] : G.Az[fu]);
-                if (A == 0.0) continue;
-                int in = wrap1(i + da, nx), jn = wrap1(j + db, ny);
-                int32_t mn = G.master[__umul24(__umul24(in, ny) + jn, nzs) + k + dc];
-                if (mn < 0) continue;
-                int kn = mn % nzs;
-                int fa = la + (axis == 0 && plus), fb = lb + (axis == 1 && plus), fc = lc + (axis == 2 && plus);
-                R s4;
-                double S, Un;
-                if (axis == 0) {
-                    s4 = (s_u[TL::ls(fa, fb, fc)] + s_u[TL::ls(fa, fb + 1, fc)]) +
-                         (s_u[TL::ls(fa, fb, fc + 1)] + s_u[TL::ls(fa, fb + 1, fc + 1)]);
-                    S = d.dy * d.dz; Un = P.ux;
-                } else if (axis == 1) {
-                    s4 = (s_v[TL::ls(fa, fb, fc)] + s_v[TL::ls(fa + 1, fb, fc)]) +
-                         (s_v[TL::ls(fa, fb, fc + 1)] + s_v[TL::ls(fa + 1, fb, fc + 1)]);
-                    S = d.dz * d.dx; Un = P.vy;
-                } else {
-                    s4 = (s_w[TL::ls(fa, fb, fc)] + s_w[TL::ls(fa + 1, fb, fc)]) +
-                         (s_w[TL::ls(fa, fb + 1, fc)] + s_w[TL::ls(fa + 1, fb + 1, fc)]);
-                    S = d.dx * d.dy; Un = 0.0;
-                }
-                const R rn0 = s_rho[TL::cs(ca + da, cb + db, cc + dc)], rn1 = s_rth[TL::cs(ca + da, cb + db, cc + dc)];
-                int klo = plus ? k : kn, kup = plus ? kn : k;
-                double pb0 = 0.5 * (P.rhob[klo] + P.rhob[kup]);
-                double pb1 = 0.5 * (P.rthb[klo] + P.rthb[kup]);
-                R f0, f1;
-                if (plus)
-                    scalar_face_flux<R>(s4, (R)(0.25 * A * S), (R)(Un * A * S), (R)pb0, (R)pb1, rc0, rn0, rc1, rn1, f0, f1);
-                else
-                    scalar_face_flux<R>(s4, (R)(0.25 * A * S), (R)(Un * A * S), (R)pb0, (R)pb1, rn0, rc0, rn1, rc1, f0, f1);
-                double h0 = pb0 * Un * A * S, h1 = pb1 * Un * A * S;
-                if (plus) { r0 += (double)f0; r1 += (double)f1; g0 += h0; g1 += h1; }
-                else { r0 -= (double)f0; r1 -= (double)f1; g0 -= h0; g1 -= h1; }
-            }
-            double vol = G.Vgroup[c] * P.dV;
-            L0 = -(g0 + r0) / vol;
-            L1 = -(g1 + r1) / vol;
-        }
-        if (MODE == 0) {
-            double x0 = (double)qn.rho[c], x1 = (double)qn.rth[c];
-            if (final_stage && qn.rho_lo) { x0 += (double)qn.rho_lo[c]; x1 += (double)qn.rth_lo[c]; }
-            x0 = fmaR(cdt, L0, x0);
-            x1 = fmaR(cdt, L1, x1);
-            T a = (T)x0, b = (T)x1;
-            bad = !isfinite(a) || !isfinite(b);
-            qo.rho[c] = a;
-            qo.rth[c] = b;
-            if (final_stage && qo.rho_lo) {
-                qo.rho_lo[c] = (T)(x0 - (double)a);
-                qo.rth_lo[c] = (T)(x1 - (double)b);
-            }
-        } else {
-            qo.rho[c] = (T)L0;
-            qo.rth[c] = (T)L1;
-        }
-    } else if (cl == CC_SOLID || MODE == 1) {
-        qo.rho[c] = (T)0;
-        qo.rth[c] = (T)0;
-        if (MODE == 0 && final_stage && qo.rho_lo) { qo.rho_lo[c] = (T)0; qo.rth_lo[c] = (T)0; }
+    LView<R> V;
+    V.rho = s_rho; V.rth = s_rth; V.pp = s_pp; V.u = s_u; V.v = s_v; V.w = s_w; V.b = &s_b[0][0];
+    for (int m = 0; m < 3; ++m) {
+        V.cb[m] = TL::cs(tx + 1 + m, ty + 2, tz + 2);
+        V.lb[m] = TL::ls(tx + m, ty + 1, tz + 1);
     }
+    V.csj = TL::CZ; V.lsj = TL::LZ; V.nb = NB; V.kb = tz + 2;
+    stage_point<T, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, i, j, k, V, st);
+}
 
-    // ---- momentum at the lattice point (i,j,k) ----
-    const bool pred = k >= G.colk[ncol + hc] || G.vcls[c] == CC_PRED;
-    if (pred) {
-        const R h = (R)0.5, q4 = (R)0.25;
-        R u[7][3];
-        const int off[7][3] = {{0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+// ------------------------------------------------------------------------------------------------
+// Marching update kernel.  A block owns a TY x TZ slab of (j,k) columns and walks along i over a
+// chunk of LI planes.  Ring buffers hold four cell planes (rho', (rho theta)', p') and three
+// lattice-velocity planes in LDS, so every plane is loaded and every velocity computed once per
+// chunk; addresses advance by one plane per step.
+// ------------------------------------------------------------------------------------------------
+template <typename T, int TY, int TZ, int LI, int MODE>
+__global__ void __launch_bounds__(TY * TZ)
+    k_stage_march(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn, SOut<T> qo, double cdt, int final_stage,
+                  int nch, int nsj, int nsk, int64_t *st)
+{
+    using R = typename Compute<T>::R;
+    constexpr int NT = TY * TZ;
+    constexpr int CZ = TZ + 3, CP = (TY + 3) * CZ;  // cell plane: j0-2..j0+TY, k0-2..k0+TZ
+    constexpr int LZ = TZ + 2, LP = (TY + 2) * LZ;  // lattice plane: j0-1..j0+TY, k0-1..k0+TZ
+    constexpr int NCS = (CP + NT - 1) / NT, NLS = (LP + NT - 1) / NT;
+    constexpr int NB = TZ + 4;
+    __shared__ R s_rho[4 * CP], s_rth[4 * CP], s_pp[4 * CP];
+    __shared__ R s_u[3 * LP], s_v[3 * LP], s_w[3 * LP];
+    __shared__ R s_b[6][NB];
+    int bch, bsj, bsk;
+    tile_of_block(nch, nsj, nsk, bch, bsj, bsk);
+    const int nx = d.nx, ny = d.ny, nz = d.nz, nzs = d.nzs;
+    const unsigned ncol = (unsigned)(nx * ny);
+    const unsigned plane = (unsigned)(ny * nzs);
+    const int j0 = bsj * TY, k0 = bsk * TZ;
+    const int i_beg = bch * LI, i_end = i_beg + LI < nx ? i_beg + LI : nx;
+    const int tid = threadIdx.x;
+    const R Ux = (R)P.ux, Vy = (R)P.vy;
+
+    // this thread's slots of the cell and lattice planes
+    int c_off[NCS], c_e[NCS];
+    bool c_ok[NCS], c_pq[NCS];
 #pragma unroll
-        for (int s = 0; s < 7; ++s) {
-            int e = TL::ls(la + off[s][0], lb + off[s][1], lc + off[s][2]);
-            u[s][0] = s_u[e]; u[s][1] = s_v[e]; u[s][2] = s_w[e];
-        }
-        R rp[8], pp[8];  // bit0: i-1/i, bit1: j-1/j, bit2: k-1/k
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            int e = TL::cs(ca - 1 + (s & 1), cb - 1 + ((s >> 1) & 1), cc - 1 + (s >> 2));
-            rp[s] = s_rho[e];
-            pp[s] = s_pp[e];
-        }
-        // density perturbation on the six faces of the velocity cell, pressure gradient, buoyancy
-        const R rxm = q4 * ((rp[0] + rp[2]) + (rp[4] + rp[6])), rxp = q4 * ((rp[1] + rp[3]) + (rp[5] + rp[7]));
-        const R rym = q4 * ((rp[0] + rp[1]) + (rp[4] + rp[5])), ryp = q4 * ((rp[2] + rp[3]) + (rp[6] + rp[7]));
-        const R rzm = q4 * ((rp[0] + rp[1]) + (rp[2] + rp[3])), rzp = q4 * ((rp[4] + rp[5]) + (rp[6] + rp[7]));
-        const R ix = (R)P.idx, iy = (R)P.idy, iz = (R)P.idz;
-        const R pgx = (((pp[1] + pp[3]) + (pp[5] + pp[7])) - ((pp[0] + pp[2]) + (pp[4] + pp[6]))) * (q4 * ix);
-        const R pgy = (((pp[2] + pp[3]) + (pp[6] + pp[7])) - ((pp[0] + pp[1]) + (pp[4] + pp[5]))) * (q4 * iy);
-        const R pgz = (((pp[4] + pp[5]) + (pp[6] + pp[7])) - ((pp[0] + pp[1]) + (pp[2] + pp[3]))) * (q4 * iz);
-        const R r8 = (R)0.125 * (((rp[0] + rp[1]) + (rp[2] + rp[3])) + ((rp[4] + rp[5]) + (rp[6] + rp[7])));
-        const R rbc = s_b[4][kb];                           // base density on x and y faces
-        const R rbzm = s_b[0][kb - 1], rbzp = s_b[0][kb];  // base density on the z faces
-        // Face flux of component m (perturbation form; the base product rbc U M0 cancels between
-        // opposite faces):  F = rbc U mb + (rbc ub + r'(U + ub)) (M0 + mb) on x/y faces with
-        // ub, mb the face means of the normal and m velocity perturbations; F = (rbz + r') wb (M0 + mb)
-        // on z faces.  The factor in front of (M0 + mb) is shared by the three components.
-        const R uxp = h * (u[0][0] + u[2][0]), uxm = h * (u[1][0] + u[0][0]);
-        const R vyp = h * (u[0][1] + u[4][1]), vym = h * (u[3][1] + u[0][1]);
-        const R wzp = h * (u[0][2] + u[6][2]), wzm = h * (u[5][2] + u[0][2]);
-        const R Axf = rbc * Ux, Ayf = rbc * Vy;
-        const R Bxp = fmaR(rxp, Ux + uxp, rbc * uxp), Bxm = fmaR(rxm, Ux + uxm, rbc * uxm);
-        const R Byp = fmaR(ryp, Vy + vyp, rbc * vyp), Bym = fmaR(rym, Vy + vym, rbc * vym);
-        const R Czp = (rbzp + rzp) * wzp, Czm = (rbzm + rzm) * wzm;
-        R Lm[3];
-#pragma unroll
-        for (int cm = 0; cm < 3; ++cm) {
-            const R M0 = cm == 0 ? Ux : (cm == 1 ? Vy : (R)0);
-            R mb;
-            mb = h * (u[0][cm] + u[2][cm]);
-            R fxp = fmaR(Axf, mb, Bxp * (M0 + mb));
-            mb = h * (u[1][cm] + u[0][cm]);
-            R fxm = fmaR(Axf, mb, Bxm * (M0 + mb));
-            mb = h * (u[0][cm] + u[4][cm]);
-            R fyp = fmaR(Ayf, mb, Byp * (M0 + mb));
-            mb = h * (u[3][cm] + u[0][cm]);
-            R fym = fmaR(Ayf, mb, Bym * (M0 + mb));
-            mb = h * (u[0][cm] + u[6][cm]);
-            R fzp = Czp * (M0 + mb);
-            mb = h * (u[5][cm] + u[0][cm]);
-            R fzm = Czm * (M0 + mb);
-            R adv = fmaR(fzp - fzm, iz, fmaR(fyp - fym, iy, (fxp - fxm) * ix));
-            R src = cm == 0 ? pgx : (cm == 1 ? pgy : fmaR((R)P.g, r8, pgz));
-            Lm[cm] = -(adv + src);
-        }
-        if (MODE == 0) {
-            const R cd = (R)cdt;
-            T a = (T)fmaR(cd, Lm[0], (R)qn.mu[c]);
-            T b = (T)fmaR(cd, Lm[1], (R)qn.mv[c]);
-            T e = (T)fmaR(cd, Lm[2], (R)qn.mw[c]);
-            bad = bad || !isfinite(a) || !isfinite(b) || !isfinite(e);
-            qo.mu[c] = a; qo.mv[c] = b; qo.mw[c] = e;
-        } else {
-            qo.mu[c] = (T)Lm[0]; qo.mv[c] = (T)Lm[1]; qo.mw[c] = (T)Lm[2];
-        }
-    } else if (MODE == 1) {
-        qo.mu[c] = (T)0; qo.mv[c] = (T)0; qo.mw[c] = (T)0;
+    for (int s = 0; s < NCS; ++s) {
+        int e = tid + s * NT;
+        c_e[s] = e;
+        int b = e / CZ, c = e - b * CZ;
+        int k = k0 - 2 + c;
+        c_ok[s] = e < CP && k >= 0 && k < nz;
+        c_pq[s] = c_ok[s] && b >= 1 && b <= TY + 1 && c >= 1 && c <= TZ + 1;
+        c_off[s] = c_ok[s] ? (int)__umul24(wrap1(j0 - 2 + b, ny), nzs) + k : 0;
     }
-    if (bad) count_status(st, ST_NONFINITE);
+    int l_off[NLS], l_e[NLS], l_J[NLS], l_K[NLS];
+    bool l_ok[NLS];
+#pragma unroll
+    for (int s = 0; s < NLS; ++s) {
+        int e = tid + s * NT;
+        l_e[s] = e;
+        int b = e / LZ, c = e - b * LZ;
+        int K = k0 - 1 + c;
+        l_ok[s] = e < LP && K >= 0 && K <= nz;
+        l_K[s] = K;
+        l_J[s] = wrap1(j0 - 1 + b, ny);
+        l_off[s] = l_ok[s] ? (int)__umul24(l_J[s], nzs) + (K < nz ? K : nz - 1) : 0;
+    }
+    for (int e = tid; e < 6 * NB; e += NT) {
+        int pr = e / NB, kk = k0 - 2 + (e - pr * NB);
+        kk = kk < 0 ? 0 : (kk >= nz ? nz - 1 : kk);
+        double v;
+        switch (pr) {
+        case 0: v = P.rhob[kk]; break;
+        case 1: v = P.rthb[kk]; break;
+        case 2: v = P.pb[kk]; break;
+        case 3: v = P.irthb[kk]; break;
+        case 4: v = P.rhobc[kk]; break;
+        default: v = kk > 0 ? 0.5 * (P.rthb[kk - 1] + P.rthb[kk]) : P.rthb[0]; break;
+        }
+        s_b[pr][e - pr * NB] = (R)v;
+    }
+    __syncthreads();
+    const int ty = tid / TZ, tz = tid - (tid / TZ) * TZ;
+    const int j = j0 + ty, k = k0 + tz;
+    const bool own = j < ny && k < nz;
+
+    for (int ip = i_beg - 2; ip <= i_end; ++ip) {
+        const int iw = wrap1(ip, nx);
+        const unsigned pbase = __umul24(iw, plane);
+        const int cslot = (ip + 4) & 3;
+        // 1. cell plane ip
+#pragma unroll
+        for (int s = 0; s < NCS; ++s) {
+            if (c_e[s] < CP) {
+                R rp = (R)0, tp = (R)0, pq = (R)0;
+                if (c_ok[s]) {
+                    rp = (R)qs.rho[pbase + c_off[s]];
+                    tp = (R)qs.rth[pbase + c_off[s]];
+                    if (c_pq[s]) {
+                        int cz = c_e[s] - (c_e[s] / CZ) * CZ;
+                        pq = eos_staged<R>(tp, s_b[3][cz], s_b[2][cz], P);
+                    }
+                }
+                s_rho[cslot * CP + c_e[s]] = rp;
+                s_rth[cslot * CP + c_e[s]] = tp;
+                s_pp[cslot * CP + c_e[s]] = pq;
+            }
+        }
+        __syncthreads();
+        // 2. lattice-velocity plane ip (from cell planes ip-1 and ip)
+        if (ip >= i_beg - 1) {
+            const int lslot = (ip + 3) % 3;
+            const int c0 = ((ip + 3) & 3) * CP, c1 = cslot * CP;
+#pragma unroll
+            for (int s = 0; s < NLS; ++s) {
+                if (l_e[s] < LP) {
+                    R u0 = (R)0, u1 = (R)0, u2 = (R)0;
+                    if (l_ok[s]) {
+                        int K = l_K[s], Kc = K < nz ? K : nz - 1;
+                        unsigned p = pbase + l_off[s];
+                        R m0 = (R)qs.mu[p], m1 = (R)qs.mv[p], m2 = (R)qs.mw[p];
+                        bool pred = Kc >= G.colk[ncol + __umul24(iw, ny) + l_J[s]] || G.vcls[p] == CC_PRED;
+                        if (pred) {
+                            int b = l_e[s] / LZ;
+                            int cz = Kc - k0 + 1;  // plane position of cell level Kc-1
+                            int q0 = b * CZ + cz, q1 = (b + 1) * CZ + cz;
+                            R sm = ((s_rho[c0 + q0] + s_rho[c1 + q0]) + (s_rho[c0 + q1] + s_rho[c1 + q1])) +
+                                   ((s_rho[c0 + q0 + 1] + s_rho[c1 + q0 + 1]) + (s_rho[c0 + q1 + 1] + s_rho[c1 + q1 + 1]));
+                            R rpc = sm * (R)0.125;
+                            R ri = recip(s_b[4][Kc - k0 + 2] + rpc);
+                            u0 = fmaR(-rpc, Ux, m0) * ri;
+                            u1 = fmaR(-rpc, Vy, m1) * ri;
+                            u2 = m2 * ri;
+                        } else {
+                            u0 = m0; u1 = m1; u2 = m2;
+                        }
+                        if (K == nz) u2 = (R)0;
+                    }
+                    s_u[lslot * LP + l_e[s]] = u0;
+                    s_v[lslot * LP + l_e[s]] = u1;
+                    s_w[lslot * LP + l_e[s]] = u2;
+                }
+            }
+        }
+        __syncthreads();
+        // 3. outputs of plane i = ip - 1 (cell planes and velocity planes i-1, i, i+1)
+        const int i = ip - 1;
+        if (i >= i_beg && own) {
+            LView<R> V;
+            V.rho = s_rho; V.rth = s_rth; V.pp = s_pp; V.u = s_u; V.v = s_v; V.w = s_w; V.b = &s_b[0][0];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                V.cb[m] = ((i - 1 + m + 4) & 3) * CP + (ty + 2) * CZ + tz + 2;
+                V.lb[m] = ((i - 1 + m + 3) % 3) * LP + (ty + 1) * LZ + tz + 1;
+            }
+            V.csj = CZ; V.lsj = LZ; V.nb = NB; V.kb = tz + 2;
+            stage_point<T, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, i, j, k, V, st);
+        }
+    }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -940,11 +1111,22 @@ static void launch_diagnose(const Dims &d, const Geo &G, const Phy &P, cc_state 
     hipLaunchKernelGGL(k_diagnose<T>, dim3(blocks_for(nc, 64)), dim3(64), 0, s, d, G, P, sout_of<T>(q), st);
 }
 
-// tile shapes of the update kernel (id -> TX x TY x TZ); id 0 is the default
+// tile shapes of the update kernel (id -> TX x TY x TZ); id 0 is the default.  Ids 9.. are the
+// marching kernel with a TY x TZ slab and chunks of TX planes along i.
 struct TileShape { int tx, ty, tz; };
-constexpr TileShape TILES[] = {{4, 4, 16}, {4, 4, 16}, {8, 4, 16}, {4, 8, 16}, {8, 8, 8},
-                               {2, 4, 32}, {4, 4, 32}, {8, 8, 16}, {2, 2, 64}};
+constexpr TileShape TILES[] = {{8, 8, 8}, {4, 4, 16}, {8, 4, 16}, {4, 8, 16}, {8, 8, 8},
+                               {2, 4, 32}, {4, 4, 32}, {8, 8, 16}, {2, 2, 64},
+                               {32, 16, 16}, {32, 8, 32}, {64, 16, 16}, {32, 16, 32}, {16, 8, 32}};
 constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
+
+template <typename T, int LI, int TY, int TZ, int MODE>
+static void launch_march(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
+                         cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
+{
+    int nch = (d.nx + LI - 1) / LI, nsj = (d.ny + TY - 1) / TY, nsk = (d.nz + TZ - 1) / TZ;
+    hipLaunchKernelGGL((k_stage_march<T, TY, TZ, LI, MODE>), dim3(nch * nsj * nsk), dim3(TY * TZ), 0, s, d, G, P,
+                       sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, nch, nsj, nsk, st);
+}
 
 template <typename T, int TX, int TY, int TZ, int MODE>
 static void launch_tiled(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
@@ -960,7 +1142,8 @@ static void launch_tiled(const Dims &d, const Geo &G, const Phy &P, const cc_sta
 static int pick_tile(int id, const Dims &d)
 {
     if (id <= 0 || id >= NTILES) id = 0;
-    if (d.nx >= TILES[id].tx && d.ny >= TILES[id].ty) return id;
+    bool march = id >= 9;
+    if ((march || d.nx >= TILES[id].tx) && d.ny >= TILES[id].ty) return id;
     if (d.nx >= 4 && d.ny >= 4) return 1;
     return 8;
 }
@@ -971,10 +1154,11 @@ static void launch_stage(const Dims &d, const Geo &G, const Phy &P, const cc_sta
 {
     int id = pick_tile(tile, d);
     if (MODE == 1) id = (d.nx >= 4 && d.ny >= 4) ? 1 : 8;  // tendency evaluation: fixed shapes
+    if (MODE == 1 && id >= 9) id = 1;
     switch (id) {
 #define CC_TILE_CASE(ID, X, Y, Z) \
     case ID: launch_tiled<T, X, Y, Z, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
-    CC_TILE_CASE(0, 4, 4, 16)
+    CC_TILE_CASE(0, 8, 8, 8)
     CC_TILE_CASE(1, 4, 4, 16)
     CC_TILE_CASE(2, 8, 4, 16)
     CC_TILE_CASE(3, 4, 8, 16)
@@ -982,7 +1166,15 @@ static void launch_stage(const Dims &d, const Geo &G, const Phy &P, const cc_sta
     CC_TILE_CASE(5, 2, 4, 32)
     CC_TILE_CASE(6, 4, 4, 32)
     CC_TILE_CASE(7, 8, 8, 16)
+#define CC_MARCH_CASE(ID, L, Y, Z) \
+    case ID: launch_march<T, L, Y, Z, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
+    CC_MARCH_CASE(9, 32, 16, 16)
+    CC_MARCH_CASE(10, 32, 8, 32)
+    CC_MARCH_CASE(11, 64, 16, 16)
+    CC_MARCH_CASE(12, 32, 16, 32)
+    CC_MARCH_CASE(13, 16, 8, 32)
     default: launch_tiled<T, 2, 2, 64, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
+#undef CC_MARCH_CASE
 #undef CC_TILE_CASE
     }
 }

@@ -138,15 +138,16 @@ def test_f64_initial_state_and_tendency(name):
         assert not dgot[f][~m].any(), f
 
 
-@pytest.mark.parametrize("name,steps", [("bell32", 100), ("hemi_tiny", 100), ("bell_small", 100),
-                                        ("ragged", 100), ("steep_random", 100)])
-def test_f64_state_parity_after_steps(name, steps):
+@pytest.mark.parametrize("name,steps,tile", [("bell32", 100, 0), ("hemi_tiny", 100, 0), ("bell_small", 100, 0),
+                                             ("ragged", 100, 0), ("steep_random", 100, 0),
+                                             ("hemi_tiny", 100, 9), ("bell_small", 100, 13)])
+def test_f64_state_parity_after_steps(name, steps, tile):
     cfg = SMALL[name]()
-    print(f"case {name} steps {steps}", flush=True)
+    print(f"case {name} steps {steps} tile {tile}", flush=True)
     o = O.Oracle(cfg).merge()
     noise = W.theta_noise(cfg.replace(noise_sigma=0.01, seed=1))
     ref = o.run(o.init_state(noise), cfg.dt, steps)
-    dom = CC.Domain(cfg, "f64")
+    dom = CC.Domain(cfg, "f64", tile=tile)
     got = dom.run(dom.init_state(noise), cfg.dt, steps)
     torch.cuda.synchronize()
     _compare_state(o, dom.state_numpy(got), ref.a, 1e-12, name)
@@ -206,14 +207,14 @@ def _full_from_pert(o, got):
     return out
 
 
-@pytest.mark.parametrize("name", ["bell_small", "hemi_tiny", "ragged"])
-def test_f32_perturbation_error_after_100_steps(name):
+@pytest.mark.parametrize("name,tile", [("bell_small", 0), ("hemi_tiny", 0), ("ragged", 0), ("hemi_tiny", 10)])
+def test_f32_perturbation_error_after_100_steps(name, tile):
     cfg = SMALL[name]()
-    print(f"case {name}", flush=True)
+    print(f"case {name} tile {tile}", flush=True)
     o = O.Oracle(cfg).merge()
     noise = W.theta_noise(cfg.replace(noise_sigma=0.01, seed=1))
     ref = o.run(o.init_state(noise), cfg.dt, 100)
-    dom = CC.Domain(cfg, "f32")
+    dom = CC.Domain(cfg, "f32", tile=tile)
     q = dom.init_state(noise)
     r0 = dom.reduce(q)
     got = dom.run(q, cfg.dt, 100)
@@ -304,3 +305,30 @@ def test_error_paths():
     # host-side argument errors
     with pytest.raises(RuntimeError, match="alias"):
         dom.rk_stage(q, q, q, 0.1)
+
+
+# ------------------------------------------------------------------------------------------------
+# every tile shape the autotuner can pick computes bitwise the same stage
+# ------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,prec", [("bell256", "f32"), ("bell256", "f64"), ("ragged", "f32"),
+                                       ("hemi_tiny", "f64")])
+def test_tile_shapes_bitwise_identical(name, prec):
+    from paper_1509_02572_amd import autotune
+    cfg = W.get(name) if name in W.CONFIGS else SMALL[name]()
+    print(f"case {name} {prec}", flush=True)
+    dom = CC.Domain(cfg, prec)
+    q = dom.init_state(W.theta_noise(cfg.replace(noise_sigma=0.01, seed=2)))
+    a = dom.new_state()
+    dom.rk_stage(q, q, a, cfg.dt / 3.0)  # a state with non-trivial p' and velocities
+    ref = None
+    for tid in [0] + list(autotune.TILE_IDS):
+        dom.grid.tile = tid
+        out = dom.new_state()
+        dom.rk_stage(q, a, out, cfg.dt / 2.0, final_stage=True)
+        if ref is None:
+            ref = out
+            continue
+        for f in ref.t:
+            assert torch.equal(out.t[f], ref.t[f]), (tid, f)
+    assert not dom.check()[:5].any()
