@@ -15,11 +15,9 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning_cache.json")
-# id -> (TX, TY, TZ) of the 3-D tile kernel, or for ids >= 9 the marching kernel's
-# (planes per chunk along i, TY, TZ)
+# id -> (TX, TY, TZ) of the update kernel's tile
 TILE_IDS = {1: (4, 4, 16), 2: (8, 4, 16), 3: (4, 8, 16), 4: (8, 8, 8), 5: (2, 4, 32), 6: (4, 4, 32),
-            7: (8, 8, 16), 8: (2, 2, 64), 9: (32, 16, 16), 10: (32, 8, 32), 11: (64, 16, 16),
-            12: (32, 16, 32), 13: (16, 8, 32)}
+            7: (8, 8, 16), 8: (2, 2, 64)}
 
 
 def key(dom) -> str:

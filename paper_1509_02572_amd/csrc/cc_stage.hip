@@ -450,30 +450,44 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
         const R uxp = h * (u[0][0] + u[2][0]), uxm = h * (u[1][0] + u[0][0]);
         const R vyp = h * (u[0][1] + u[4][1]), vym = h * (u[3][1] + u[0][1]);
         const R wzp = h * (u[0][2] + u[6][2]), wzm = h * (u[5][2] + u[0][2]);
-        const R Axf = rbc * Ux, Ayf = rbc * Vy;
-        const R Bxp = fmaR(rxp, Ux + uxp, rbc * uxp), Bxm = fmaR(rxm, Ux + uxm, rbc * uxm);
-        const R Byp = fmaR(ryp, Vy + vyp, rbc * vyp), Bym = fmaR(rym, Vy + vym, rbc * vym);
         const R Czp = (rbzp + rzp) * wzp, Czm = (rbzm + rzm) * wzm;
         R Lm[3];
+        if constexpr (sizeof(T) == 4) {  // perturbation form
+            const R Axf = rbc * Ux, Ayf = rbc * Vy;
+            const R Bxp = fmaR(rxp, Ux + uxp, rbc * uxp), Bxm = fmaR(rxm, Ux + uxm, rbc * uxm);
+            const R Byp = fmaR(ryp, Vy + vyp, rbc * vyp), Bym = fmaR(rym, Vy + vym, rbc * vym);
 #pragma unroll
-        for (int cm = 0; cm < 3; ++cm) {
-            const R M0 = cm == 0 ? Ux : (cm == 1 ? Vy : (R)0);
-            R mb;
-            mb = h * (u[0][cm] + u[2][cm]);
-            R fxp = fmaR(Axf, mb, Bxp * (M0 + mb));
-            mb = h * (u[1][cm] + u[0][cm]);
-            R fxm = fmaR(Axf, mb, Bxm * (M0 + mb));
-            mb = h * (u[0][cm] + u[4][cm]);
-            R fyp = fmaR(Ayf, mb, Byp * (M0 + mb));
-            mb = h * (u[3][cm] + u[0][cm]);
-            R fym = fmaR(Ayf, mb, Bym * (M0 + mb));
-            mb = h * (u[0][cm] + u[6][cm]);
-            R fzp = Czp * (M0 + mb);
-            mb = h * (u[5][cm] + u[0][cm]);
-            R fzm = Czm * (M0 + mb);
-            R adv = fmaR(fzp - fzm, iz, fmaR(fyp - fym, iy, (fxp - fxm) * ix));
-            R src = cm == 0 ? pgx : (cm == 1 ? pgy : fmaR((R)P.g, r8, pgz));
-            Lm[cm] = -(adv + src);
+            for (int cm = 0; cm < 3; ++cm) {
+                const R M0 = cm == 0 ? Ux : (cm == 1 ? Vy : (R)0);
+                R mb;
+                mb = h * (u[0][cm] + u[2][cm]);
+                R fxp = fmaR(Axf, mb, Bxp * (M0 + mb));
+                mb = h * (u[1][cm] + u[0][cm]);
+                R fxm = fmaR(Axf, mb, Bxm * (M0 + mb));
+                mb = h * (u[0][cm] + u[4][cm]);
+                R fyp = fmaR(Ayf, mb, Byp * (M0 + mb));
+                mb = h * (u[3][cm] + u[0][cm]);
+                R fym = fmaR(Ayf, mb, Bym * (M0 + mb));
+                mb = h * (u[0][cm] + u[6][cm]);
+                R fzp = Czp * (M0 + mb);
+                mb = h * (u[5][cm] + u[0][cm]);
+                R fzm = Czm * (M0 + mb);
+                R adv = fmaR(fzp - fzm, iz, fmaR(fyp - fym, iy, (fxp - fxm) * ix));
+                R src = cm == 0 ? pgx : (cm == 1 ? pgy : fmaR((R)P.g, r8, pgz));
+                Lm[cm] = -(adv + src);
+            }
+        } else {  // paper variables: F = (rbar + r') ub mb on every face
+            const R Bxp = (rbc + rxp) * uxp, Bxm = (rbc + rxm) * uxm;
+            const R Byp = (rbc + ryp) * vyp, Bym = (rbc + rym) * vym;
+#pragma unroll
+            for (int cm = 0; cm < 3; ++cm) {
+                R fxp = Bxp * (h * (u[0][cm] + u[2][cm])), fxm = Bxm * (h * (u[1][cm] + u[0][cm]));
+                R fyp = Byp * (h * (u[0][cm] + u[4][cm])), fym = Bym * (h * (u[3][cm] + u[0][cm]));
+                R fzp = Czp * (h * (u[0][cm] + u[6][cm])), fzm = Czm * (h * (u[5][cm] + u[0][cm]));
+                R adv = fmaR(fzp - fzm, iz, fmaR(fyp - fym, iy, (fxp - fxm) * ix));
+                R src = cm == 0 ? pgx : (cm == 1 ? pgy : fmaR((R)P.g, r8, pgz));
+                Lm[cm] = -(adv + src);
+            }
         }
         if (MODE == 0) {
             const R cd = (R)cdt;
@@ -514,42 +528,84 @@ __global__ void __launch_bounds__(TX * TY * TZ)
     const unsigned ncol = (unsigned)(nx * ny);
     const R Ux = (R)P.ux, Vy = (R)P.vy;
 
+    // tiles whose halo lies inside the grid in x, y and k need no periodic wrap and no range check
+    const bool inner = i0 >= 2 && i0 + TX < nx && j0 >= 2 && j0 + TY < ny && k0 >= 2 && k0 + TZ < nz;
     // ---- issue the global loads of the staging phases first ----
     R c_rho[IT1], c_rth[IT1];
+    if (inner) {
+        const unsigned tbase = __umul24(__umul24(i0 - 2, ny) + (j0 - 2), nzs) + (k0 - 2);
 #pragma unroll
-    for (int it = 0; it < IT1; ++it) {
-        int e = tid + it * NT;
-        c_rho[it] = (R)0;
-        c_rth[it] = (R)0;
-        if (e < TL::NC) {
-            int a = e / (TL::CY * TL::CZ), r = e - a * (TL::CY * TL::CZ), b = r / TL::CZ, c = r - b * TL::CZ;
-            int k = k0 - 2 + c;
-            if (k >= 0 && k < nz) {
-                unsigned col = __umul24(wrap1(i0 - 2 + a, nx), ny) + wrap1(j0 - 2 + b, ny);
-                unsigned ci = __umul24(col, nzs) + k;
+        for (int it = 0; it < IT1; ++it) {
+            int e = tid + it * NT;
+            c_rho[it] = (R)0;
+            c_rth[it] = (R)0;
+            if (e < TL::NC) {
+                int a = e / (TL::CY * TL::CZ), r = e - a * (TL::CY * TL::CZ), b = r / TL::CZ, c = r - b * TL::CZ;
+                unsigned ci = tbase + __umul24(__umul24(a, ny) + b, nzs) + c;
                 c_rho[it] = (R)qs.rho[ci];
                 c_rth[it] = (R)qs.rth[ci];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < IT1; ++it) {
+            int e = tid + it * NT;
+            c_rho[it] = (R)0;
+            c_rth[it] = (R)0;
+            if (e < TL::NC) {
+                int a = e / (TL::CY * TL::CZ), r = e - a * (TL::CY * TL::CZ), b = r / TL::CZ, c = r - b * TL::CZ;
+                int k = k0 - 2 + c;
+                if (k >= 0 && k < nz) {
+                    unsigned col = __umul24(wrap1(i0 - 2 + a, nx), ny) + wrap1(j0 - 2 + b, ny);
+                    unsigned ci = __umul24(col, nzs) + k;
+                    c_rho[it] = (R)qs.rho[ci];
+                    c_rth[it] = (R)qs.rth[ci];
+                }
             }
         }
     }
     R l_m0[IT2], l_m1[IT2], l_m2[IT2];
     int l_kb[IT2];
+    unsigned l_p[IT2];
+    if (inner) {
+        const unsigned tcol = __umul24(i0 - 1, ny) + (j0 - 1);
 #pragma unroll
-    for (int it = 0; it < IT2; ++it) {
-        int e = tid + it * NT;
-        l_m0[it] = l_m1[it] = l_m2[it] = (R)0;
-        l_kb[it] = 0;
-        if (e < TL::NL) {
-            int a = e / (TL::LY * TL::LZ), r = e - a * (TL::LY * TL::LZ), b = r / TL::LZ, c = r - b * TL::LZ;
-            int K = k0 - 1 + c;
-            if (K >= 0 && K <= nz) {
-                int Kc = K < nz ? K : nz - 1;
-                unsigned col = __umul24(wrap1(i0 - 1 + a, nx), ny) + wrap1(j0 - 1 + b, ny);
-                unsigned p = __umul24(col, nzs) + Kc;
+        for (int it = 0; it < IT2; ++it) {
+            int e = tid + it * NT;
+            l_m0[it] = l_m1[it] = l_m2[it] = (R)0;
+            l_kb[it] = 0;
+            l_p[it] = 0;
+            if (e < TL::NL) {
+                int a = e / (TL::LY * TL::LZ), r = e - a * (TL::LY * TL::LZ), b = r / TL::LZ, c = r - b * TL::LZ;
+                unsigned col = tcol + __umul24(a, ny) + b;
+                unsigned p = __umul24(col, nzs) + (k0 - 1 + c);
+                l_p[it] = p;
                 l_m0[it] = (R)qs.mu[p];
                 l_m1[it] = (R)qs.mv[p];
                 l_m2[it] = (R)qs.mw[p];
                 l_kb[it] = G.colk[ncol + col];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < IT2; ++it) {
+            int e = tid + it * NT;
+            l_m0[it] = l_m1[it] = l_m2[it] = (R)0;
+            l_kb[it] = 0;
+            l_p[it] = 0;
+            if (e < TL::NL) {
+                int a = e / (TL::LY * TL::LZ), r = e - a * (TL::LY * TL::LZ), b = r / TL::LZ, c = r - b * TL::LZ;
+                int K = k0 - 1 + c;
+                if (K >= 0 && K <= nz) {
+                    int Kc = K < nz ? K : nz - 1;
+                    unsigned col = __umul24(wrap1(i0 - 1 + a, nx), ny) + wrap1(j0 - 1 + b, ny);
+                    unsigned p = __umul24(col, nzs) + Kc;
+                    l_p[it] = p;
+                    l_m0[it] = (R)qs.mu[p];
+                    l_m1[it] = (R)qs.mv[p];
+                    l_m2[it] = (R)qs.mw[p];
+                    l_kb[it] = G.colk[ncol + col];
+                }
             }
         }
     }
@@ -595,11 +651,7 @@ __global__ void __launch_bounds__(TX * TY * TZ)
             R u0 = (R)0, u1 = (R)0, u2 = (R)0;
             if (K >= 0 && K <= nz) {
                 int Kc = K < nz ? K : nz - 1;  // the rigid lid copies the level below
-                bool pred = Kc >= l_kb[it];
-                if (!pred) {
-                    unsigned col = __umul24(wrap1(i0 - 1 + a, nx), ny) + wrap1(j0 - 1 + b, ny);
-                    pred = G.vcls[__umul24(col, nzs) + Kc] == CC_PRED;
-                }
+                bool pred = Kc >= l_kb[it] || G.vcls[l_p[it]] == CC_PRED;
                 if (pred) {
                     int cz = Kc - k0 + 1;  // LDS level of cell level Kc-1
                     R sm = ((s_rho[TL::cs(a, b, cz)] + s_rho[TL::cs(a + 1, b, cz)]) +
@@ -637,156 +689,6 @@ __global__ void __launch_bounds__(TX * TY * TZ)
     }
     V.csj = TL::CZ; V.lsj = TL::LZ; V.nb = NB; V.kb = tz + 2;
     stage_point<T, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, i, j, k, V, st);
-}
-
-// ------------------------------------------------------------------------------------------------
-// Marching update kernel.  A block owns a TY x TZ slab of (j,k) columns and walks along i over a
-// chunk of LI planes.  Ring buffers hold four cell planes (rho', (rho theta)', p') and three
-// lattice-velocity planes in LDS, so every plane is loaded and every velocity computed once per
-// chunk; addresses advance by one plane per step.
-// ------------------------------------------------------------------------------------------------
-template <typename T, int TY, int TZ, int LI, int MODE>
-__global__ void __launch_bounds__(TY * TZ)
-    k_stage_march(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn, SOut<T> qo, double cdt, int final_stage,
-                  int nch, int nsj, int nsk, int64_t *st)
-{
-    using R = typename Compute<T>::R;
-    constexpr int NT = TY * TZ;
-    constexpr int CZ = TZ + 3, CP = (TY + 3) * CZ;  // cell plane: j0-2..j0+TY, k0-2..k0+TZ
-    constexpr int LZ = TZ + 2, LP = (TY + 2) * LZ;  // lattice plane: j0-1..j0+TY, k0-1..k0+TZ
-    constexpr int NCS = (CP + NT - 1) / NT, NLS = (LP + NT - 1) / NT;
-    constexpr int NB = TZ + 4;
-    __shared__ R s_rho[4 * CP], s_rth[4 * CP], s_pp[4 * CP];
-    __shared__ R s_u[3 * LP], s_v[3 * LP], s_w[3 * LP];
-    __shared__ R s_b[6][NB];
-    int bch, bsj, bsk;
-    tile_of_block(nch, nsj, nsk, bch, bsj, bsk);
-    const int nx = d.nx, ny = d.ny, nz = d.nz, nzs = d.nzs;
-    const unsigned ncol = (unsigned)(nx * ny);
-    const unsigned plane = (unsigned)(ny * nzs);
-    const int j0 = bsj * TY, k0 = bsk * TZ;
-    const int i_beg = bch * LI, i_end = i_beg + LI < nx ? i_beg + LI : nx;
-    const int tid = threadIdx.x;
-    const R Ux = (R)P.ux, Vy = (R)P.vy;
-
-    // this thread's slots of the cell and lattice planes
-    int c_off[NCS], c_e[NCS];
-    bool c_ok[NCS], c_pq[NCS];
-#pragma unroll
-    for (int s = 0; s < NCS; ++s) {
-        int e = tid + s * NT;
-        c_e[s] = e;
-        int b = e / CZ, c = e - b * CZ;
-        int k = k0 - 2 + c;
-        c_ok[s] = e < CP && k >= 0 && k < nz;
-        c_pq[s] = c_ok[s] && b >= 1 && b <= TY + 1 && c >= 1 && c <= TZ + 1;
-        c_off[s] = c_ok[s] ? (int)__umul24(wrap1(j0 - 2 + b, ny), nzs) + k : 0;
-    }
-    int l_off[NLS], l_e[NLS], l_J[NLS], l_K[NLS];
-    bool l_ok[NLS];
-#pragma unroll
-    for (int s = 0; s < NLS; ++s) {
-        int e = tid + s * NT;
-        l_e[s] = e;
-        int b = e / LZ, c = e - b * LZ;
-        int K = k0 - 1 + c;
-        l_ok[s] = e < LP && K >= 0 && K <= nz;
-        l_K[s] = K;
-        l_J[s] = wrap1(j0 - 1 + b, ny);
-        l_off[s] = l_ok[s] ? (int)__umul24(l_J[s], nzs) + (K < nz ? K : nz - 1) : 0;
-    }
-    for (int e = tid; e < 6 * NB; e += NT) {
-        int pr = e / NB, kk = k0 - 2 + (e - pr * NB);
-        kk = kk < 0 ? 0 : (kk >= nz ? nz - 1 : kk);
-        double v;
-        switch (pr) {
-        case 0: v = P.rhob[kk]; break;
-        case 1: v = P.rthb[kk]; break;
-        case 2: v = P.pb[kk]; break;
-        case 3: v = P.irthb[kk]; break;
-        case 4: v = P.rhobc[kk]; break;
-        default: v = kk > 0 ? 0.5 * (P.rthb[kk - 1] + P.rthb[kk]) : P.rthb[0]; break;
-        }
-        s_b[pr][e - pr * NB] = (R)v;
-    }
-    __syncthreads();
-    const int ty = tid / TZ, tz = tid - (tid / TZ) * TZ;
-    const int j = j0 + ty, k = k0 + tz;
-    const bool own = j < ny && k < nz;
-
-    for (int ip = i_beg - 2; ip <= i_end; ++ip) {
-        const int iw = wrap1(ip, nx);
-        const unsigned pbase = __umul24(iw, plane);
-        const int cslot = (ip + 4) & 3;
-        // 1. cell plane ip
-#pragma unroll
-        for (int s = 0; s < NCS; ++s) {
-            if (c_e[s] < CP) {
-                R rp = (R)0, tp = (R)0, pq = (R)0;
-                if (c_ok[s]) {
-                    rp = (R)qs.rho[pbase + c_off[s]];
-                    tp = (R)qs.rth[pbase + c_off[s]];
-                    if (c_pq[s]) {
-                        int cz = c_e[s] - (c_e[s] / CZ) * CZ;
-                        pq = eos_staged<R>(tp, s_b[3][cz], s_b[2][cz], P);
-                    }
-                }
-                s_rho[cslot * CP + c_e[s]] = rp;
-                s_rth[cslot * CP + c_e[s]] = tp;
-                s_pp[cslot * CP + c_e[s]] = pq;
-            }
-        }
-        __syncthreads();
-        // 2. lattice-velocity plane ip (from cell planes ip-1 and ip)
-        if (ip >= i_beg - 1) {
-            const int lslot = (ip + 3) % 3;
-            const int c0 = ((ip + 3) & 3) * CP, c1 = cslot * CP;
-#pragma unroll
-            for (int s = 0; s < NLS; ++s) {
-                if (l_e[s] < LP) {
-                    R u0 = (R)0, u1 = (R)0, u2 = (R)0;
-                    if (l_ok[s]) {
-                        int K = l_K[s], Kc = K < nz ? K : nz - 1;
-                        unsigned p = pbase + l_off[s];
-                        R m0 = (R)qs.mu[p], m1 = (R)qs.mv[p], m2 = (R)qs.mw[p];
-                        bool pred = Kc >= G.colk[ncol + __umul24(iw, ny) + l_J[s]] || G.vcls[p] == CC_PRED;
-                        if (pred) {
-                            int b = l_e[s] / LZ;
-                            int cz = Kc - k0 + 1;  // plane position of cell level Kc-1
-                            int q0 = b * CZ + cz, q1 = (b + 1) * CZ + cz;
-                            R sm = ((s_rho[c0 + q0] + s_rho[c1 + q0]) + (s_rho[c0 + q1] + s_rho[c1 + q1])) +
-                                   ((s_rho[c0 + q0 + 1] + s_rho[c1 + q0 + 1]) + (s_rho[c0 + q1 + 1] + s_rho[c1 + q1 + 1]));
-                            R rpc = sm * (R)0.125;
-                            R ri = recip(s_b[4][Kc - k0 + 2] + rpc);
-                            u0 = fmaR(-rpc, Ux, m0) * ri;
-                            u1 = fmaR(-rpc, Vy, m1) * ri;
-                            u2 = m2 * ri;
-                        } else {
-                            u0 = m0; u1 = m1; u2 = m2;
-                        }
-                        if (K == nz) u2 = (R)0;
-                    }
-                    s_u[lslot * LP + l_e[s]] = u0;
-                    s_v[lslot * LP + l_e[s]] = u1;
-                    s_w[lslot * LP + l_e[s]] = u2;
-                }
-            }
-        }
-        __syncthreads();
-        // 3. outputs of plane i = ip - 1 (cell planes and velocity planes i-1, i, i+1)
-        const int i = ip - 1;
-        if (i >= i_beg && own) {
-            LView<R> V;
-            V.rho = s_rho; V.rth = s_rth; V.pp = s_pp; V.u = s_u; V.v = s_v; V.w = s_w; V.b = &s_b[0][0];
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                V.cb[m] = ((i - 1 + m + 4) & 3) * CP + (ty + 2) * CZ + tz + 2;
-                V.lb[m] = ((i - 1 + m + 3) % 3) * LP + (ty + 1) * LZ + tz + 1;
-            }
-            V.csj = CZ; V.lsj = LZ; V.nb = NB; V.kb = tz + 2;
-            stage_point<T, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, i, j, k, V, st);
-        }
-    }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1111,22 +1013,11 @@ static void launch_diagnose(const Dims &d, const Geo &G, const Phy &P, cc_state 
     hipLaunchKernelGGL(k_diagnose<T>, dim3(blocks_for(nc, 64)), dim3(64), 0, s, d, G, P, sout_of<T>(q), st);
 }
 
-// tile shapes of the update kernel (id -> TX x TY x TZ); id 0 is the default.  Ids 9.. are the
-// marching kernel with a TY x TZ slab and chunks of TX planes along i.
+// tile shapes of the update kernel (id -> TX x TY x TZ); id 0 is the default
 struct TileShape { int tx, ty, tz; };
 constexpr TileShape TILES[] = {{8, 8, 8}, {4, 4, 16}, {8, 4, 16}, {4, 8, 16}, {8, 8, 8},
-                               {2, 4, 32}, {4, 4, 32}, {8, 8, 16}, {2, 2, 64},
-                               {32, 16, 16}, {32, 8, 32}, {64, 16, 16}, {32, 16, 32}, {16, 8, 32}};
+                               {2, 4, 32}, {4, 4, 32}, {8, 8, 16}, {2, 2, 64}};
 constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
-
-template <typename T, int LI, int TY, int TZ, int MODE>
-static void launch_march(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
-                         cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
-{
-    int nch = (d.nx + LI - 1) / LI, nsj = (d.ny + TY - 1) / TY, nsk = (d.nz + TZ - 1) / TZ;
-    hipLaunchKernelGGL((k_stage_march<T, TY, TZ, LI, MODE>), dim3(nch * nsj * nsk), dim3(TY * TZ), 0, s, d, G, P,
-                       sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, nch, nsj, nsk, st);
-}
 
 template <typename T, int TX, int TY, int TZ, int MODE>
 static void launch_tiled(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
@@ -1142,8 +1033,7 @@ static void launch_tiled(const Dims &d, const Geo &G, const Phy &P, const cc_sta
 static int pick_tile(int id, const Dims &d)
 {
     if (id <= 0 || id >= NTILES) id = 0;
-    bool march = id >= 9;
-    if ((march || d.nx >= TILES[id].tx) && d.ny >= TILES[id].ty) return id;
+    if (d.nx >= TILES[id].tx && d.ny >= TILES[id].ty) return id;
     if (d.nx >= 4 && d.ny >= 4) return 1;
     return 8;
 }
@@ -1154,7 +1044,6 @@ static void launch_stage(const Dims &d, const Geo &G, const Phy &P, const cc_sta
 {
     int id = pick_tile(tile, d);
     if (MODE == 1) id = (d.nx >= 4 && d.ny >= 4) ? 1 : 8;  // tendency evaluation: fixed shapes
-    if (MODE == 1 && id >= 9) id = 1;
     switch (id) {
 #define CC_TILE_CASE(ID, X, Y, Z) \
     case ID: launch_tiled<T, X, Y, Z, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
@@ -1166,15 +1055,7 @@ static void launch_stage(const Dims &d, const Geo &G, const Phy &P, const cc_sta
     CC_TILE_CASE(5, 2, 4, 32)
     CC_TILE_CASE(6, 4, 4, 32)
     CC_TILE_CASE(7, 8, 8, 16)
-#define CC_MARCH_CASE(ID, L, Y, Z) \
-    case ID: launch_march<T, L, Y, Z, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
-    CC_MARCH_CASE(9, 32, 16, 16)
-    CC_MARCH_CASE(10, 32, 8, 32)
-    CC_MARCH_CASE(11, 64, 16, 16)
-    CC_MARCH_CASE(12, 32, 16, 32)
-    CC_MARCH_CASE(13, 16, 8, 32)
     default: launch_tiled<T, 2, 2, 64, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
-#undef CC_MARCH_CASE
 #undef CC_TILE_CASE
     }
 }

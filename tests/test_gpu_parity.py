@@ -140,7 +140,7 @@ def test_f64_initial_state_and_tendency(name):
 
 @pytest.mark.parametrize("name,steps,tile", [("bell32", 100, 0), ("hemi_tiny", 100, 0), ("bell_small", 100, 0),
                                              ("ragged", 100, 0), ("steep_random", 100, 0),
-                                             ("hemi_tiny", 100, 9), ("bell_small", 100, 13)])
+                                             ("hemi_tiny", 100, 5), ("bell_small", 100, 7)])
 def test_f64_state_parity_after_steps(name, steps, tile):
     cfg = SMALL[name]()
     print(f"case {name} steps {steps} tile {tile}", flush=True)
@@ -207,7 +207,7 @@ def _full_from_pert(o, got):
     return out
 
 
-@pytest.mark.parametrize("name,tile", [("bell_small", 0), ("hemi_tiny", 0), ("ragged", 0), ("hemi_tiny", 10)])
+@pytest.mark.parametrize("name,tile", [("bell_small", 0), ("hemi_tiny", 0), ("ragged", 0), ("hemi_tiny", 2)])
 def test_f32_perturbation_error_after_100_steps(name, tile):
     cfg = SMALL[name]()
     print(f"case {name} tile {tile}", flush=True)
