@@ -47,7 +47,8 @@ def run_gpu(cfg, prec: str, steps: int, warmup: int):
     q = dom.init_state(W.theta_noise(cfg))
     tuned = autotune.tune(dom, q, path=None, dt=cfg.dt)  # untimed: picks the tile shape
     log(f"bench: {prec} tile timings (ms per update launch): "
-        + ", ".join(f"{k}{autotune.TILE_IDS[k]}={v:.4f}" for k, v in tuned["ms"].items()))
+        + ", ".join(f"{k}{autotune.TILE_IDS[k]}w{autotune.TILE_MINW.get(k, 0)}={v:.4f}"
+                    for k, v in tuned["ms"].items()))
     a, b, c = q, dom.new_state(), dom.new_state()
     dt = cfg.dt
     esz = 8 if prec == "f64" else 4
@@ -99,6 +100,7 @@ def run_gpu(cfg, prec: str, steps: int, warmup: int):
     value = ncell * 3 * steps / secs
     red = dom.reduce(a)
     roof["tile"] = list(autotune.TILE_IDS[tuned["tile"]])
+    roof["tile_min_waves_per_simd"] = autotune.TILE_MINW.get(tuned["tile"], 0)
     return {"value": value, "ms_per_step": secs / steps * 1e3, "roofline": roof,
             "mass_total": float(red[2]), "mass_pert": float(red[0])}
 

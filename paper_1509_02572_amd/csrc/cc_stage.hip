@@ -276,22 +276,44 @@ struct LView {
 // neighbourhood.  Above the per-column bands cells and lattice points are regular and no geometry
 // or class array is read; inside the bands single-cell groups read their apertures, group volume
 // and neighbour masters, and masters of multi-cell groups take the general gather path.
+// values of q_n at the output point and its column thresholds, loaded ahead of the staging phases
+template <typename T>
+struct PointIn {
+    T rho, rth, rho_lo, rth_lo, mu, mv, mw;
+    int kcell, klat;
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ void load_point(const Dims &d, const Geo &G, const SIn<T> &qn, int i, int j, int k,
+                                           int final_stage, PointIn<T> &pi)
+{
+    const unsigned hc = __umul24(i, d.ny) + j;
+    const unsigned c = __umul24(hc, d.nzs) + k;
+    pi.kcell = G.colk[hc];
+    pi.klat = G.colk[(unsigned)(d.nx * d.ny) + hc];
+    if (MODE == 0) {
+        pi.rho = qn.rho[c]; pi.rth = qn.rth[c];
+        pi.mu = qn.mu[c]; pi.mv = qn.mv[c]; pi.mw = qn.mw[c];
+        if (final_stage && qn.rho_lo) { pi.rho_lo = qn.rho_lo[c]; pi.rth_lo = qn.rth_lo[c]; }
+        else { pi.rho_lo = (T)0; pi.rth_lo = (T)0; }
+    }
+}
+
 template <typename T, int MODE>
 __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &qs,
-                                            const SIn<T> &qn, const SOut<T> &qo, double cdt, int final_stage,
+                                            const PointIn<T> &pin, const SOut<T> &qo, double cdt, int final_stage,
                                             int i, int j, int k, const LView<typename Compute<T>::R> &V,
                                             int64_t *st)
 {
     using R = typename Compute<T>::R;
     const int nx = d.nx, ny = d.ny, nz = d.nz, nzs = d.nzs;
-    const unsigned ncol = (unsigned)(nx * ny);
     const R Ux = (R)P.ux, Vy = (R)P.vy;
     const unsigned hc = __umul24(i, ny) + j;
     const unsigned c = __umul24(hc, nzs) + k;
     bool bad = false;
 
     // ---- scalars ----
-    const bool band = k < G.colk[hc];
+    const bool band = k < pin.kcell;
     const int8_t cl = band ? G.cls[c] : (int8_t)CC_OPEN;
     if (cl == CC_OPEN || cl == CC_ORPHAN) {
         double L0, L1;
@@ -392,8 +414,8 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
             L1 = -(g1 + r1) / vol;
         }
         if (MODE == 0) {
-            double x0 = (double)qn.rho[c], x1 = (double)qn.rth[c];
-            if (final_stage && qn.rho_lo) { x0 += (double)qn.rho_lo[c]; x1 += (double)qn.rth_lo[c]; }
+            double x0 = (double)pin.rho, x1 = (double)pin.rth;
+            if (final_stage && qo.rho_lo) { x0 += (double)pin.rho_lo; x1 += (double)pin.rth_lo; }
             x0 = fmaR(cdt, L0, x0);
             x1 = fmaR(cdt, L1, x1);
             T a = (T)x0, b = (T)x1;
@@ -415,7 +437,7 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
     }
 
     // ---- momentum at the lattice point (i,j,k) ----
-    const bool pred = k >= G.colk[ncol + hc] || G.vcls[c] == CC_PRED;
+    const bool pred = k >= pin.klat || G.vcls[c] == CC_PRED;
     if (pred) {
         const R h = (R)0.5, q4 = (R)0.25;
         R u[7][3];
@@ -491,9 +513,9 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
         }
         if (MODE == 0) {
             const R cd = (R)cdt;
-            T a = (T)fmaR(cd, Lm[0], (R)qn.mu[c]);
-            T b = (T)fmaR(cd, Lm[1], (R)qn.mv[c]);
-            T e = (T)fmaR(cd, Lm[2], (R)qn.mw[c]);
+            T a = (T)fmaR(cd, Lm[0], (R)pin.mu);
+            T b = (T)fmaR(cd, Lm[1], (R)pin.mv);
+            T e = (T)fmaR(cd, Lm[2], (R)pin.mw);
             bad = bad || !isfinite(a) || !isfinite(b) || !isfinite(e);
             qo.mu[c] = a; qo.mv[c] = b; qo.mw[c] = e;
         } else {
@@ -505,8 +527,8 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
     if (bad) count_status(st, ST_NONFINITE);
 }
 
-template <typename T, int TX, int TY, int TZ, int MODE>
-__global__ void __launch_bounds__(TX * TY * TZ)
+template <typename T, int TX, int TY, int TZ, int MODE, int MINW>
+__global__ void __launch_bounds__(TX * TY * TZ, MINW)
     k_stage_tiled(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn, SOut<T> qo, double cdt, int final_stage,
                   int nbx, int nby, int nbz, int64_t *st)
 {
@@ -528,6 +550,12 @@ __global__ void __launch_bounds__(TX * TY * TZ)
     const unsigned ncol = (unsigned)(nx * ny);
     const R Ux = (R)P.ux, Vy = (R)P.vy;
 
+    // the output point of this thread; its q_n values and column thresholds are loaded first
+    const int tx = tid / (TY * TZ), ty = (tid / TZ) % TY, tz = tid % TZ;
+    const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+    const bool own = i < nx && j < ny && k < nz;
+    PointIn<T> pin;
+    if (own) load_point<T, MODE>(d, G, qn, i, j, k, final_stage, pin);
     // tiles whose halo lies inside the grid in x, y and k need no periodic wrap and no range check
     const bool inner = i0 >= 2 && i0 + TX < nx && j0 >= 2 && j0 + TY < ny && k0 >= 2 && k0 + TZ < nz;
     // ---- issue the global loads of the staging phases first ----
@@ -678,9 +706,7 @@ __global__ void __launch_bounds__(TX * TY * TZ)
     __syncthreads();
 
     // ---- phase 3: one cell and one lattice point per thread ----
-    const int tx = tid / (TY * TZ), ty = (tid / TZ) % TY, tz = tid % TZ;
-    const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
-    if (i >= nx || j >= ny || k >= nz) return;
+    if (!own) return;
     LView<R> V;
     V.rho = s_rho; V.rth = s_rth; V.pp = s_pp; V.u = s_u; V.v = s_v; V.w = s_w; V.b = &s_b[0][0];
     for (int m = 0; m < 3; ++m) {
@@ -688,7 +714,7 @@ __global__ void __launch_bounds__(TX * TY * TZ)
         V.lb[m] = TL::ls(tx + m, ty + 1, tz + 1);
     }
     V.csj = TL::CZ; V.lsj = TL::LZ; V.nb = NB; V.kb = tz + 2;
-    stage_point<T, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, i, j, k, V, st);
+    stage_point<T, MODE>(d, G, P, qs, pin, qo, cdt, final_stage, i, j, k, V, st);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1013,19 +1039,21 @@ static void launch_diagnose(const Dims &d, const Geo &G, const Phy &P, cc_state 
     hipLaunchKernelGGL(k_diagnose<T>, dim3(blocks_for(nc, 64)), dim3(64), 0, s, d, G, P, sout_of<T>(q), st);
 }
 
-// tile shapes of the update kernel (id -> TX x TY x TZ); id 0 is the default
-struct TileShape { int tx, ty, tz; };
-constexpr TileShape TILES[] = {{8, 8, 8}, {4, 4, 16}, {8, 4, 16}, {4, 8, 16}, {8, 8, 8},
-                               {2, 4, 32}, {4, 4, 32}, {8, 8, 16}, {2, 2, 64}};
+// tile shapes of the update kernel (id -> TX x TY x TZ, minimum waves per SIMD the register
+// allocation must allow); id 0 is the default
+struct TileShape { int tx, ty, tz, minw; };
+constexpr TileShape TILES[] = {{8, 8, 8, 1}, {4, 4, 16, 1}, {8, 4, 16, 1}, {4, 8, 16, 1}, {8, 8, 8, 1},
+                               {2, 4, 32, 1}, {4, 4, 32, 1}, {8, 8, 16, 1}, {2, 2, 64, 1},
+                               {8, 8, 8, 6}, {8, 8, 8, 8}, {4, 4, 16, 8}, {4, 8, 16, 6}};
 constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
 
-template <typename T, int TX, int TY, int TZ, int MODE>
+template <typename T, int TX, int TY, int TZ, int MODE, int MINW = 1>
 static void launch_tiled(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
                          cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
 {
     int nbx = (d.nx + TX - 1) / TX, nby = (d.ny + TY - 1) / TY, nbz = (d.nz + TZ - 1) / TZ;
-    hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE>), dim3(nbx * nby * nbz), dim3(TX * TY * TZ), 0, s, d,
-                       G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, nbx, nby, nbz, st);
+    hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, MINW>), dim3(nbx * nby * nbz), dim3(TX * TY * TZ), 0, s,
+                       d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, nbx, nby, nbz, st);
 }
 
 // the tile of a grid: the requested shape if the grid holds at least one tile per direction in x
@@ -1055,6 +1083,13 @@ static void launch_stage(const Dims &d, const Geo &G, const Phy &P, const cc_sta
     CC_TILE_CASE(5, 2, 4, 32)
     CC_TILE_CASE(6, 4, 4, 32)
     CC_TILE_CASE(7, 8, 8, 16)
+#define CC_TILE_CASE_W(ID, X, Y, Z, W) \
+    case ID: launch_tiled<T, X, Y, Z, MODE, W>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
+    CC_TILE_CASE_W(9, 8, 8, 8, 6)
+    CC_TILE_CASE_W(10, 8, 8, 8, 8)
+    CC_TILE_CASE_W(11, 4, 4, 16, 8)
+    CC_TILE_CASE_W(12, 4, 8, 16, 6)
+#undef CC_TILE_CASE_W
     default: launch_tiled<T, 2, 2, 64, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
 #undef CC_TILE_CASE
     }
