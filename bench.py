@@ -12,7 +12,10 @@ measured with HIP events on the launch stream, against the 8 TB/s HBM peak.  Mea
 comes from a committed rocprofv3 counter summary when it was taken on the current kernel source.
 The CPU baseline times the FP64 oracle on this machine's host cores on one step of the workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f32|f64] [--no-cpu]
+The ensemble line (both precisions) advances 64 independent domains of uneven size through 50 steps
+with one captured graph of the batched kernels.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f32|f64] [--no-cpu] [--no-ensemble]
 """
 import argparse
 import hashlib
@@ -105,6 +108,51 @@ def run_gpu(cfg, prec: str, steps: int, warmup: int):
             "mass_total": float(red[2]), "mass_pert": float(red[0])}
 
 
+def run_ensemble(prec: str, warmup: int):
+    """The 64-member ensemble: every member advanced through all its steps by one graph launch of
+    the batched kernels (one update and one diagnostic launch per stage for the whole batch)."""
+    import torch
+    from paper_1509_02572_amd import cutcell as CC
+    from paper_1509_02572_amd import workloads as W
+    cfgs = W.ensemble(64, 0)
+    doms = [CC.Domain(c, prec, "cuda:0") for c in cfgs]
+    states = [d.init_state() for d in doms]
+    dt, nsteps = cfgs[0].dt, cfgs[0].nsteps
+    stream = torch.cuda.current_stream()
+    # tile shape of the batch: one eager step per candidate, timed with events
+    times = {}
+    for tile in (0, 1, 8, 9):
+        b = CC.Batch(doms, states, tile=tile)
+        b.step(dt, 1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.step(dt, 2)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times[tile] = e0.elapsed_time(e1)
+        b.close()
+    tile = min(times, key=times.get)
+    batch = CC.Batch(doms, states, tile=tile)
+    for _ in range(max(warmup, 1)):
+        batch.step(dt, nsteps, use_graph=True)  # the first call captures the graph
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    batch.step(dt, nsteps, use_graph=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    st = batch.check()
+    if st[:5].any():
+        raise RuntimeError(f"device status counters set: {st}")
+    cells = batch.cells
+    batch.close()
+    return {"value": cells * 3 * nsteps / secs, "unit": "cell-updates/s", "cells": cells,
+            "steps": nsteps, "ms_per_step": secs / nsteps * 1e3, "graph_ms": e0.elapsed_time(e1),
+            "tile": tile, "tile_ms_per_2_steps": {str(k): round(v, 4) for k, v in times.items()}}
+
+
 def run_cpu_baseline(cfg):
     """FP64 oracle on the host cores: one full step (three stages) of the same workload."""
     from oracle import oracle as O
@@ -129,6 +177,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -154,6 +203,11 @@ def main():
     side = run_gpu(cfg, other, args.steps, args.warmup)
     log(f"bench: {other} {side['value']:.4g} cell-updates/s, {side['ms_per_step']:.3f} ms/step")
     f64 = head if args.prec == "f64" else side
+    ens = {}
+    if not args.no_ensemble:
+        for p in (args.prec, other):
+            ens[p] = run_ensemble(p, args.warmup)
+            log(f"bench: ensemble {p} {ens[p]['value']:.4g} cell-updates/s, {ens[p]['ms_per_step']:.3f} ms/step")
     out = {
         "metric": "cell-updates/s per RK stage",
         "value": head["value"],
@@ -175,6 +229,10 @@ def main():
         other: {"value": side["value"], "ms_per_step": side["ms_per_step"], "roofline": side["roofline"]},
         "speedup_vs_fp64": head["value"] / f64["value"],
     }
+    if ens:
+        out["ensemble"] = {"workload": "64 periodic domains, nx,ny~U{48..96}, nz~U{48..64}, dx=dy=dz=100 m, "
+                                       "1-5 Gaussian hills each (seed 0), dt=0.09 s, 50 steps per graph launch",
+                           **ens}
     if not args.no_cpu:
         log("bench: timing the CPU oracle baseline")
         out["cpu_baseline"] = run_cpu_baseline(cfg)

@@ -183,6 +183,49 @@ cc_status cutcell_reduce(const cc_grid *grid, const cc_phys *phys, const cc_geom
                          const double *base, cc_prec prec, const cc_state *q, void *workspace,
                          double *out, cc_stream_t stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * Batched blocks (ensembles of independent domains; the building block of the refined hierarchy).
+ * Each block is a full uniform grid with its own geometry, base state and three state buffers;
+ * a batch steps every block with one update launch and one diagnostic launch per Runge-Kutta
+ * stage (load balance over blocks of uneven size: the launch enumerates the tiles of all blocks,
+ * Sec. 2.2 and Sec. 2.5 use equal cubes per thread instead).
+ * ------------------------------------------------------------------------------------------- */
+typedef struct {
+    cc_grid grid;
+    cc_phys phys;
+    cc_geom geom;         /* geometry and merge map of the block (cutcell_geometry/_merge_map) */
+    const double *base;   /* base state of the block (cutcell_base_state) */
+    cc_state q[3];        /* three state buffers; the current state starts in q[0] */
+    int32_t level;        /* refinement level (0 for ensemble members) */
+    int32_t reserved;
+} cc_block;
+
+typedef struct cc_batch_s *cc_batch;
+
+/* Device workspace (bytes) that holds the descriptors of nblocks blocks. */
+size_t amr_batch_workspace_bytes(int32_t nblocks, cc_prec prec);
+
+/* Describe nblocks level-0 blocks to the device (copies descriptors into `workspace`, which must
+ * stay allocated until amr_batch_destroy; synchronises `stream`).  `tile` selects the update
+ * kernel's tile shape as cc_grid.tile does (one shape for the batch).  The handle is host state
+ * owned by the caller. */
+cc_status amr_batch_create(const cc_block *blocks, int32_t nblocks, cc_prec prec, int32_t tile,
+                           void *workspace, cc_batch *out, cc_stream_t stream);
+
+/* nsteps three-stage steps (dt each) of every block of the batch, in place in the blocks' buffers:
+ * per stage one update launch over the tiles of all blocks and one diagnostic launch over their
+ * columns.  use_graph != 0: the sequence is captured once into a hipGraph (cached per nsteps, dt,
+ * starting buffer and status pointer) and replayed as a single graph launch on `stream`.  Device
+ * conditions are counted into dev_status as for the single-grid calls. */
+cc_status amr_block_step(cc_batch batch, double dt, int32_t nsteps, int32_t use_graph, int64_t *dev_status,
+                         cc_stream_t stream);
+
+/* Index (0..2) of the block buffer that holds the current state after the steps so far. */
+int32_t amr_batch_current(cc_batch batch);
+
+/* Release the handle (graph executables, capture stream). */
+cc_status amr_batch_destroy(cc_batch batch);
+
 /* Host helper: copies dev_status to the host (synchronising `stream`) and maps the first non-zero
  * counter to its status code. */
 cc_status cutcell_check_status(const int64_t *dev_status, int64_t *host_copy, cc_stream_t stream);

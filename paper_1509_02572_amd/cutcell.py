@@ -45,6 +45,11 @@ class cc_state(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("rho", "rth", "mu", "mv", "mw", "rho_lo", "rth_lo")]
 
 
+class cc_block(C.Structure):
+    _fields_ = [("grid", cc_grid), ("phys", cc_phys), ("geom", cc_geom), ("base", C.c_void_p),
+                ("q", cc_state * 3), ("level", C.c_int32), ("reserved", C.c_int32)]
+
+
 _lib = None
 
 
@@ -71,9 +76,17 @@ def lib():
         L.cutcell_reduce_workspace.restype = C.c_size_t
         L.cutcell_reduce.argtypes = [G, P, GM, vp, C.c_int, S, vp, vp, vp]
         L.cutcell_check_status.argtypes = [vp, vp, vp]
+        L.amr_batch_workspace_bytes.argtypes = [C.c_int32, C.c_int]
+        L.amr_batch_workspace_bytes.restype = C.c_size_t
+        L.amr_batch_create.argtypes = [C.POINTER(cc_block), C.c_int32, C.c_int, C.c_int32, vp,
+                                       C.POINTER(C.c_void_p), vp]
+        L.amr_block_step.argtypes = [vp, C.c_double, C.c_int32, C.c_int32, i64p, vp]
+        L.amr_batch_current.argtypes = [vp]
+        L.amr_batch_current.restype = C.c_int32
+        L.amr_batch_destroy.argtypes = [vp]
         for name in ("cutcell_base_state", "cutcell_geometry", "cutcell_merge_map", "cutcell_init_state",
                      "cutcell_diagnose", "cutcell_tendency", "cutcell_rk_stage", "cutcell_rk_update", "cutcell_reduce",
-                     "cutcell_check_status"):
+                     "cutcell_check_status", "amr_batch_create", "amr_block_step", "amr_batch_destroy"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -161,6 +174,32 @@ def cutcell_check_status(status: torch.Tensor, stream=None) -> (int, np.ndarray)
     host = np.zeros(CC_NSTATUS, np.int64)
     rc = lib().cutcell_check_status(_ptr(status), host.ctypes.data_as(C.c_void_p), _stream(stream))
     return rc, host
+
+
+def amr_batch_workspace_bytes(nblocks: int, prec: int) -> int:
+    return int(lib().amr_batch_workspace_bytes(nblocks, prec))
+
+
+def amr_batch_create(blocks, prec: int, tile: int, workspace: torch.Tensor, stream=None) -> C.c_void_p:
+    arr = (cc_block * len(blocks))(*blocks)
+    h = C.c_void_p()
+    _check(lib().amr_batch_create(arr, len(blocks), prec, tile, _ptr(workspace), C.byref(h), _stream(stream)),
+           "amr_batch_create")
+    return h
+
+
+def amr_block_step(batch: C.c_void_p, dt: float, nsteps: int, use_graph: bool, status: torch.Tensor,
+                   stream=None):
+    _check(lib().amr_block_step(batch, dt, nsteps, int(use_graph), _ptr(status), _stream(stream)),
+           "amr_block_step")
+
+
+def amr_batch_current(batch: C.c_void_p) -> int:
+    return int(lib().amr_batch_current(batch))
+
+
+def amr_batch_destroy(batch: C.c_void_p):
+    _check(lib().amr_batch_destroy(batch), "amr_batch_destroy")
 
 
 # ------------------------------------------------------------------------------------------------
@@ -318,3 +357,59 @@ class Domain:
             out["rho"] += self.unpad(q.t["rho_lo"]).astype(np.float64)
             out["rth"] += self.unpad(q.t["rth_lo"]).astype(np.float64)
         return out
+
+
+# ------------------------------------------------------------------------------------------------
+# Batch: independent domains stepped together (one update and one diagnostic launch per stage)
+# ------------------------------------------------------------------------------------------------
+class Batch:
+    """Level-0 blocks (each a ``Domain`` with three state buffers) stepped by ``amr_block_step``.
+
+    ``states[m]`` is the initial state of member m; it is copied into the member's first buffer."""
+
+    def __init__(self, domains, states, tile: int = 0):
+        if not domains or len(domains) != len(states):
+            raise ValueError("one initial state per domain expected")
+        prec = domains[0].prec
+        if any(d.prec != prec for d in domains):
+            raise ValueError("all members of a batch share one precision")
+        self.domains = list(domains)
+        self.prec = prec
+        self.bufs = []
+        blocks = []
+        for d, q in zip(domains, states):
+            b = [d.new_state(), d.new_state(), d.new_state()]
+            for f in q.t:
+                b[0].t[f].copy_(q.t[f])
+            self.bufs.append(b)
+            blocks.append(cc_block(d.grid, d.phys, d.geom, C.c_void_p(d.base.data_ptr()),
+                                   (cc_state * 3)(b[0].c, b[1].c, b[2].c), 0, 0))
+        dev = domains[0].dev
+        self.status = torch.zeros(CC_NSTATUS, dtype=torch.int64, device=dev)
+        nbytes = amr_batch_workspace_bytes(len(domains), prec)
+        self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        self.h = amr_batch_create(blocks, prec, tile, self.ws)
+        self.cells = sum(d.cfg.nx * d.cfg.ny * d.cfg.nz for d in domains)
+
+    def step(self, dt: float, nsteps: int = 1, use_graph: bool = False, stream=None):
+        amr_block_step(self.h, dt, nsteps, use_graph, self.status, stream)
+
+    def current(self):
+        """Current state of every member."""
+        c = amr_batch_current(self.h)
+        return [b[c] for b in self.bufs]
+
+    def check(self) -> np.ndarray:
+        rc, host = cutcell_check_status(self.status)
+        return host
+
+    def close(self):
+        if self.h:
+            amr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

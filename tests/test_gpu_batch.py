@@ -1,0 +1,139 @@
+"""Batched blocks (ensembles of independent domains) through amr_block_step.
+
+Bars: every member of a batch advances exactly (bitwise) as the same domain stepped alone with the
+single-grid calls; small members agree with the FP64 oracle to 1e-12 (FP64) after several steps;
+graph replays reproduce eager stepping bitwise on every replay.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1509_02572_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CC = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    global CC
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1509_02572_amd import cutcell
+    CC = cutcell
+    CC.lib()
+    O.build(force=False)
+
+
+def _small_ensemble(count=5, seed=11):
+    # small members (the oracle finishes them in seconds), uneven sizes including one that does not
+    # hold a whole 8x8 tile column in x
+    return W.ensemble(count, seed, nx_range=(7, 21), nz_range=(12, 20), dt=0.09)
+
+
+def _members(cfgs, prec):
+    doms = [CC.Domain(c, prec) for c in cfgs]
+    states = [d.init_state(W.theta_noise(c.replace(noise_sigma=0.01, seed=7 + m)))
+              for m, (d, c) in enumerate(zip(doms, cfgs))]
+    return doms, states
+
+
+def _equal(a, b):
+    return all(torch.equal(a.t[f], b.t[f]) for f in a.t)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_small_batch_matches_single_domains_bitwise(prec):
+    cfgs = _small_ensemble()
+    print("case small ensemble", prec, [(c.nx, c.ny, c.nz) for c in cfgs], flush=True)
+    doms, states = _members(cfgs, prec)
+    for tile in (0, 1, 8, 9):
+        batch = CC.Batch(doms, states, tile=tile)
+        batch.step(cfgs[0].dt, 3)
+        torch.cuda.synchronize()
+        for m, (d, q) in enumerate(zip(doms, states)):
+            ref = d.run(q, cfgs[0].dt, 3)
+            assert _equal(batch.current()[m], ref), (tile, m)
+        assert not batch.check()[:5].any()
+        batch.close()
+
+
+def test_small_batch_f64_against_oracle():
+    cfgs = _small_ensemble(count=4, seed=3)
+    doms, states = _members(cfgs, "f64")
+    batch = CC.Batch(doms, states)
+    steps = 10
+    batch.step(cfgs[0].dt, steps)
+    torch.cuda.synchronize()
+    for m, (c, d) in enumerate(zip(cfgs, doms)):
+        print(f"member {m} {c.nx}x{c.ny}x{c.nz}", flush=True)
+        o = O.Oracle(c).merge()
+        ref = o.run(o.init_state(W.theta_noise(c.replace(noise_sigma=0.01, seed=7 + m))), c.dt, steps)
+        got = d.state_numpy(batch.current()[m])
+        nonsolid, pred = o.cls != O.SOLID, o.vcls == O.PRED
+        for f, msk in (("rho", nonsolid), ("rth", nonsolid), ("mu", pred), ("mv", pred), ("mw", pred),
+                       ("mu", ~pred & nonsolid)):
+            if not msk.any():
+                continue
+            scale = np.abs(ref.a[f][msk]).max()
+            assert np.abs(got[f] - ref.a[f])[msk].max() <= 1e-12 * scale, (m, f)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_graph_replays_match_eager(prec):
+    cfgs = _small_ensemble(count=6, seed=5)
+    doms, states = _members(cfgs, prec)
+    eager = CC.Batch(doms, states)
+    graph = CC.Batch(doms, states)
+    dt = cfgs[0].dt
+    for rep in range(4):
+        nsteps = 2 if rep < 3 else 1  # the last call captures a second graph (odd step count)
+        eager.step(dt, nsteps)
+        graph.step(dt, nsteps, use_graph=True)
+        torch.cuda.synchronize()
+        for m in range(len(cfgs)):
+            assert _equal(eager.current()[m], graph.current()[m]), (rep, m)
+        # eager work between replays
+        _ = [d.reduce(q) for d, q in zip(doms, eager.current())]
+        torch.cuda.synchronize()
+    assert not graph.check()[:5].any()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_full_ensemble_members_bitwise_and_conservative(prec):
+    """The 64-member ensemble workload: two steps with one graph launch, every member bitwise equal
+    to its single-domain run; mass of every member conserved."""
+    cfgs = W.ensemble(64, 0)
+    print("case ensemble64", prec, sum(c.nx * c.ny * c.nz for c in cfgs), flush=True)
+    doms = [CC.Domain(c, prec) for c in cfgs]
+    states = [d.init_state() for d in doms]
+    assert all(not d.check()[:5].any() for d in doms)
+    batch = CC.Batch(doms, states)
+    batch.step(cfgs[0].dt, 2, use_graph=True)
+    torch.cuda.synchronize()
+    for m, (d, q) in enumerate(zip(doms, states)):
+        ref = d.run(q, cfgs[0].dt, 2)
+        got = batch.current()[m]
+        assert _equal(got, ref), m
+        r0, r1 = d.reduce(q), d.reduce(got)
+        assert abs(r1[0] - r0[0]) <= 1e-12 * r0[2], m
+    assert not batch.check()[:5].any()
+    batch.close()
+
+
+def test_batch_rejects_bad_arguments():
+    cfg = W.get("bell32")
+    d64 = CC.Domain(cfg, "f64")
+    d32 = CC.Domain(cfg, "f32")
+    with pytest.raises(ValueError):
+        CC.Batch([d64, d32], [d64.init_state(), d32.init_state()])
+    with pytest.raises(ValueError):
+        CC.Batch([d64], [])
+    # a block of a refinement level other than 0 is refused by the library
+    b = [d64.new_state() for _ in range(3)]
+    blk = CC.cc_block(d64.grid, d64.phys, d64.geom, CC.C.c_void_p(d64.base.data_ptr()),
+                      (CC.cc_state * 3)(b[0].c, b[1].c, b[2].c), 1, 0)
+    ws = torch.zeros(CC.amr_batch_workspace_bytes(1, CC.CC_F64), dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(RuntimeError, match="level"):
+        CC.amr_batch_create([blk], CC.CC_F64, 0, ws)
