@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_bell256.json")
-STAGE_SRC = os.path.join(ROOT, "paper_1509_02572_amd", "csrc", "cc_stage.hip")
+STAGE_SRC = os.path.join(ROOT, "paper_1509_02572_amd", "csrc", "cc_kernels.hpp")
 
 
 def log(*a):
@@ -40,7 +40,7 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(STAGE_SRC, "rb").read()).hexdigest()[:16]
 
 
-def run_gpu(cfg, prec: str, steps: int, warmup: int):
+def run_gpu(cfg, prec: str, steps: int, warmup: int, tile: int = 0):
     import torch
     from paper_1509_02572_amd import cutcell as CC
     from paper_1509_02572_amd import workloads as W
@@ -48,10 +48,14 @@ def run_gpu(cfg, prec: str, steps: int, warmup: int):
     from paper_1509_02572_amd import autotune
     dom = CC.Domain(cfg, prec, "cuda:0")
     q = dom.init_state(W.theta_noise(cfg))
-    tuned = autotune.tune(dom, q, path=None, dt=cfg.dt)  # untimed: picks the tile shape
-    log(f"bench: {prec} tile timings (ms per update launch): "
-        + ", ".join(f"{k}{autotune.TILE_IDS[k]}w{autotune.TILE_MINW.get(k, 0)}={v:.4f}"
-                    for k, v in tuned["ms"].items()))
+    if tile:
+        dom.grid.tile = tile  # fixed tile shape (profiling runs)
+        tuned = {"tile": tile}
+    else:
+        tuned = autotune.tune(dom, q, path=None, dt=cfg.dt)  # untimed: picks the tile shape
+        log(f"bench: {prec} tile timings (ms per update launch): "
+            + ", ".join(f"{k}{autotune.TILE_IDS[k]}w{autotune.TILE_MINW.get(k, 0)}={v:.4f}"
+                        for k, v in tuned["ms"].items()))
     a, b, c = q, dom.new_state(), dom.new_state()
     dt = cfg.dt
     esz = 8 if prec == "f64" else 4
@@ -93,7 +97,9 @@ def run_gpu(cfg, prec: str, steps: int, warmup: int):
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"k_stage_tiled<{'double' if prec == 'f64' else 'float'},0>",
+            "kernel": "k_stage_tiled<{},{},{},{},0,{}>".format(
+                "double" if prec == "f64" else "float", *autotune.TILE_IDS[tuned["tile"]],
+                max(1, autotune.TILE_MINW.get(tuned["tile"], 1))),
             "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(avg_bytes)}
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
@@ -178,6 +184,7 @@ def main():
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--tile", type=int, default=0, help="fixed update-kernel tile id (default: autotuned)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -198,9 +205,9 @@ def main():
     cfg = W.get("bell256")
     other = "f64" if args.prec == "f32" else "f32"
     log(f"bench: {cfg.name} {cfg.nx}x{cfg.ny}x{cfg.nz} prec={args.prec} steps={args.steps} warmup={args.warmup}")
-    head = run_gpu(cfg, args.prec, args.steps, args.warmup)
+    head = run_gpu(cfg, args.prec, args.steps, args.warmup, args.tile)
     log(f"bench: {args.prec} {head['value']:.4g} cell-updates/s, {head['ms_per_step']:.3f} ms/step")
-    side = run_gpu(cfg, other, args.steps, args.warmup)
+    side = run_gpu(cfg, other, args.steps, args.warmup, args.tile)
     log(f"bench: {other} {side['value']:.4g} cell-updates/s, {side['ms_per_step']:.3f} ms/step")
     f64 = head if args.prec == "f64" else side
     ens = {}

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcutcell.so")
-SOURCES = ["cc_api.hip", "cc_geometry.hip", "cc_stage.hip"]
+SOURCES = ["cc_api.hip", "cc_geometry.hip", "cc_stage.hip", "cc_batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,0 +1,984 @@
+// Device code of the cut-cell stage shared by the uniform-grid and the batched entry points:
+// state views, the equation of state, face fluxes, the tiled update kernel (single grid and
+// batched blocks) and the velocity diagnostics.  Host helpers at the end turn the C-ABI structs
+// into kernel views.
+//
+// Precision forms
+//   double : the paper's variables; reference velocity (ux, vy) = 0.
+//   float  : perturbation form.  Momentum is stored as m' = rho u - rhobar_c(K) (ux, vy, 0) and
+//            diagnosed velocities as u - (ux, vy, 0).  Fluxes are split into the part carried by
+//            the base state and the uniform reference flow, which is evaluated in double (it is a
+//            static quantity that cancels exactly on regular cells), and the perturbation part,
+//            evaluated in float (momentum fluxes also accumulated in float; the few scalar face
+//            fluxes of a cell are summed in double so that their cancellation between neighbours
+//            is exact).  Base state, group volumes and global sums stay double.
+//
+// Floating-point expressions are evaluated as written (no FMA contraction): a face flux is then
+// bitwise the same whichever of its two cells, and whichever code path, evaluates it, so the flux
+// divergence telescopes exactly and mass is conserved to rounding of the per-cell sums.
+#pragma once
+#pragma clang fp contract(off)
+
+#include "cc_internal.hpp"
+
+namespace cc {
+
+
+template <typename T>
+struct SIn {
+    const T *rho, *rth, *mu, *mv, *mw;
+    const T *rho_lo, *rth_lo;  // low-order parts (float form, nullable)
+};
+template <typename T>
+struct SOut {
+    T *rho, *rth, *mu, *mv, *mw;
+    T *rho_lo, *rth_lo;
+};
+
+struct Geo {
+    const double *H, *V, *Ax, *Ay, *Az, *nrm, *Vgroup;
+    const int8_t *cls, *vcls;
+    const int32_t *master, *gnext, *colk;
+};
+
+constexpr int EOS_TERMS = 11;  // binomial series terms of (1+x)^gamma - 1 (double; float uses 6)
+constexpr double EOS_XMAX = 0.03;  // |x| above which the exact form is used
+
+struct Phy {
+    const double *rhob, *rthb, *pb, *thb;  // base state at cell centres [nz]
+    const double *irthb;                   // 1 / (rho theta)bar [nz]
+    const double *rhobc;                   // mean base density of levels K-1, K at lattice level K [nz]
+    double g, gam, ux, vy, dV, idV, idx, idy, idz;
+    double binom[EOS_TERMS];               // (1+x)^gamma - 1 = sum_n binom[n-1] x^n
+    float binomf[EOS_TERMS];
+};
+
+template <typename T>
+struct Compute;
+template <>
+struct Compute<double> {
+    using R = double;
+};
+template <>
+struct Compute<float> {
+    using R = float;
+};
+
+__device__ __forceinline__ double expm1_r(double x) { return expm1(x); }
+__device__ __forceinline__ float expm1_r(float x) { return expm1f(x); }
+__device__ __forceinline__ double log1p_r(double x) { return log1p(x); }
+__device__ __forceinline__ float log1p_r(float x) { return log1pf(x); }
+
+// p' from (rho theta)' through the ideal-gas equation of state (Sec. 2.1):
+// p = p0 (R rho theta / p0)^(cp/cv)  =>  p' = pbar ((1 + rth'/rthbar)^gamma - 1)
+template <typename R>
+__device__ __forceinline__ R eos_pprime(R rthp, double rthb, double pb, double gam)
+{
+    return (R)pb * expm1_r((R)gam * log1p_r(rthp / (R)rthb));
+}
+
+// the same p' for cell level k, evaluated with the binomial series of (1+x)^gamma when
+// |x| = |rth'/rthbar| <= EOS_XMAX (truncation below the storage precision: 6 terms in float, 11 in
+// double), otherwise with the exact form
+template <typename R>
+__device__ __forceinline__ R eos_pprime_k(R rthp, int k, const Phy &P)
+{
+    R x = rthp * (R)P.irthb[k];
+    R ax = x < (R)0 ? -x : x;
+    if (ax > (R)EOS_XMAX) return (R)P.pb[k] * expm1_r((R)P.gam * log1p_r(x));
+    constexpr int NTERM = sizeof(R) == 4 ? 6 : EOS_TERMS;
+    R acc = (R)P.binom[NTERM - 1];
+#pragma unroll
+    for (int n = NTERM - 2; n >= 0; --n) acc = (R)P.binom[n] + x * acc;
+    return (R)P.pb[k] * (x * acc);
+}
+
+// reciprocal used for velocities: hardware reciprocal in float (deterministic, 1 ulp), IEEE in double
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+__device__ __forceinline__ int wrap1(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Fluxes of rho' and (rho theta)' (perturbation part) through one face.  Every code path calls
+// this with the same operands, so both cells of a face obtain bitwise the same value.
+//   s4   sum of the four corner normal velocities, ((a + b) + (c + d)) in canonical corner order
+//   AS4  aperture x area / 4, UAS = reference normal velocity x aperture x area
+//   b0,b1 base values on the face, lo*/up* perturbations of the lower / upper exchanging group
+// flux = bar (un A S) + (lo + up)/2 ((un + Un) A S) with un = s4 / 4.
+template <typename R>
+__device__ __forceinline__ void scalar_face_flux(R s4, R AS4, R UAS, R b0, R b1, R lo0, R up0, R lo1,
+                                                 R up1, R &f0, R &f1)
+{
+    R unS = s4 * AS4;
+    R htS = (R)0.5 * fmaR(s4, AS4, UAS);
+    f0 = fmaR(b0, unS, (lo0 + up0) * htS);
+    f1 = fmaR(b1, unS, (lo1 + up1) * htS);
+}
+
+// Velocity (perturbation from the reference flow) at lattice point (I,J,K).
+// Predicted points divide the momentum by the mean of the eight surrounding cell densities;
+// diagnosed points store the velocity; the rigid lid (K = nz) has w = 0 and copies (u, v) of the
+// level below.
+template <typename T, typename R = typename Compute<T>::R>
+__device__ __forceinline__ void lat_vel(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &q,
+                                        int I, int J, int K, R u[3])
+{
+    bool lid = K >= d.nz;
+    if (lid) K = d.nz - 1;
+    int64_t p = cidx(d, I, J, K);
+    if (G.vcls[p] == CC_PRED) {
+        int64_t c00 = cidx(d, I - 1, J - 1, K - 1), c10 = cidx(d, I, J - 1, K - 1);
+        int64_t c01 = cidx(d, I - 1, J, K - 1), c11 = cidx(d, I, J, K - 1);
+        R s = (((R)q.rho[c00] + (R)q.rho[c10]) + ((R)q.rho[c01] + (R)q.rho[c11])) +
+              (((R)q.rho[c00 + 1] + (R)q.rho[c10 + 1]) + ((R)q.rho[c01 + 1] + (R)q.rho[c11 + 1]));
+        R rpc = s * (R)0.125;
+        R ri = recip((R)P.rhobc[K] + rpc);
+        u[0] = fmaR(-rpc, (R)P.ux, (R)q.mu[p]) * ri;
+        u[1] = fmaR(-rpc, (R)P.vy, (R)q.mv[p]) * ri;
+        u[2] = (R)q.mw[p] * ri;
+    } else {
+        u[0] = (R)q.mu[p];
+        u[1] = (R)q.mv[p];
+        u[2] = (R)q.mw[p];
+    }
+    if (lid) u[2] = (R)0;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Scalar tendency of a merged group (Sec. 2.4): the surface integral over every external face of
+// every member (a face split among several neighbours contributes one sub-face per neighbour, with
+// its own aperture), face scalar = mean of the two exchanging groups, face normal velocity = mean
+// of the four corner velocities (eqs. ux1-ux3), zero flux through closed faces (terrain, ground,
+// rigid lid).  Returns d(rho')/dt and d(rho theta)'/dt of master c.
+// ------------------------------------------------------------------------------------------------
+template <typename T, typename R = typename Compute<T>::R>
+__device__ void group_scalar_tendency(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &q,
+                                      int64_t c, double L[2])
+{
+    double rb0 = 0.0, rb1 = 0.0;  // base-state / reference-flow part
+    // perturbation part: each face flux is evaluated in R; the per-group sum of those fluxes is
+    // formed in double, where a sum of a few floats is exact, so a face contributes exactly
+    // opposite amounts to its two groups and mass is conserved to FP64 rounding
+    double rp0 = 0.0, rp1 = 0.0;
+    int kc = (int)(c % d.nzs);
+    int64_t mem = c;
+    for (int guard = 0; mem >= 0 && guard <= CC_MAX_GROUP; ++guard) {
+        int i, j, k;
+        unidx(d, mem, i, j, k);
+        for (int f = 0; f < 6; ++f) {
+            int axis = f >> 1, plus = f & 1;
+            int fi = i, fj = j, fk = k, ni = i, nj = j, nk = k;
+            if (axis == 0) { if (plus) { fi = i + 1; ni = i + 1; } else ni = i - 1; }
+            else if (axis == 1) { if (plus) { fj = j + 1; nj = j + 1; } else nj = j - 1; }
+            else {
+                if (plus) { fk = k + 1; nk = k + 1; } else nk = k - 1;
+                if (nk < 0 || nk >= d.nz) continue;
+            }
+            int64_t fu = cidx(d, fi, fj, fk);
+            double A = axis == 0 ? G.Ax[fu] : (axis == 1 ? G.Ay[fu] : G.Az[fu]);
+            if (A == 0.0) continue;
+            int32_t mn = G.master[cidx(d, ni, nj, nk)];
+            if (mn == (int32_t)c || mn < 0) continue;  // internal face of the group
+            R a[3], b[3], e[3], h[3];
+            double S, Un;
+            if (axis == 0) {
+                lat_vel<T>(d, G, P, q, fi, fj, fk, a); lat_vel<T>(d, G, P, q, fi, fj + 1, fk, b);
+                lat_vel<T>(d, G, P, q, fi, fj, fk + 1, e); lat_vel<T>(d, G, P, q, fi, fj + 1, fk + 1, h);
+                S = d.dy * d.dz; Un = P.ux;
+            } else if (axis == 1) {
+                lat_vel<T>(d, G, P, q, fi, fj, fk, a); lat_vel<T>(d, G, P, q, fi + 1, fj, fk, b);
+                lat_vel<T>(d, G, P, q, fi, fj, fk + 1, e); lat_vel<T>(d, G, P, q, fi + 1, fj, fk + 1, h);
+                S = d.dz * d.dx; Un = P.vy;
+            } else {
+                lat_vel<T>(d, G, P, q, fi, fj, fk, a); lat_vel<T>(d, G, P, q, fi + 1, fj, fk, b);
+                lat_vel<T>(d, G, P, q, fi, fj + 1, fk, e); lat_vel<T>(d, G, P, q, fi + 1, fj + 1, fk, h);
+                S = d.dx * d.dy; Un = 0.0;
+            }
+            R s4 = (a[axis] + b[axis]) + (e[axis] + h[axis]);
+            int64_t mlo = plus ? c : (int64_t)mn, mup = plus ? (int64_t)mn : c;
+            int klo = plus ? kc : (int)(mn % d.nzs), kup = plus ? (int)(mn % d.nzs) : kc;
+            double pb0 = 0.5 * (P.rhob[klo] + P.rhob[kup]);
+            double pb1 = 0.5 * (P.rthb[klo] + P.rthb[kup]);
+            R f0, f1;
+            scalar_face_flux<R>(s4, (R)(0.25 * A * S), (R)(Un * A * S), (R)pb0, (R)pb1, (R)q.rho[mlo],
+                                (R)q.rho[mup], (R)q.rth[mlo], (R)q.rth[mup], f0, f1);
+            double g0 = pb0 * Un * A * S, g1 = pb1 * Un * A * S;
+            if (plus) { rp0 += (double)f0; rp1 += (double)f1; rb0 += g0; rb1 += g1; }
+            else { rp0 -= (double)f0; rp1 -= (double)f1; rb0 -= g0; rb1 -= g1; }
+        }
+        mem = G.gnext[mem];
+    }
+    double vol = G.Vgroup[c] * P.dV;
+    L[0] = -(rb0 + rp0) / vol;
+    L[1] = -(rb1 + rp1) / vol;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Tiled update kernel.  A block owns TX x TY columns x TZ levels.  It stages rho', (rho theta)' and
+// p' of the cells around the tile, and the velocities of the lattice points around it, in LDS once,
+// then every thread updates one cell (scalars) and one lattice point (momentum).  Above the
+// per-column bands (colk) cells and lattice points are regular and no geometry or class array is
+// read; inside the bands single-cell groups read their apertures, group volume and neighbour
+// masters, and masters of multi-cell groups take the general gather path.
+// ------------------------------------------------------------------------------------------------
+template <int TX, int TY, int TZ>
+struct Tile {
+    static constexpr int NT = TX * TY * TZ;
+    static constexpr int CX = TX + 3, CY = TY + 3, CZ = TZ + 3, NC = CX * CY * CZ;  // cells from (i0-2, j0-2, k0-2)
+    static constexpr int LX = TX + 2, LY = TY + 2, LZ = TZ + 2, NL = LX * LY * LZ;  // lattice from (i0-1, j0-1, k0-1)
+    __device__ static constexpr int cs(int a, int b, int c) { return (a * CY + b) * CZ + c; }
+    __device__ static constexpr int ls(int a, int b, int c) { return (a * LY + b) * LZ + c; }
+};
+
+// tile origin of this block with an XCD-aware order: blocks are dealt round-robin to the 8 XCDs,
+// so each XCD is given a contiguous range of tiles (k fastest, then j, then i) and shares halos in
+// its own L2
+__device__ __forceinline__ void tile_of_block(int nbx, int nby, int nbz, int &bi, int &bj, int &bk)
+{
+    int nb = nbx * nby * nbz;
+    int b = blockIdx.x;
+    int xcd = b & 7, idx = b >> 3, per = nb >> 3, rem = nb & 7;
+    int lb = xcd * per + (xcd < rem ? xcd : rem) + idx;
+    bk = lb % nbz;
+    int t2 = lb / nbz;
+    bj = t2 % nby;
+    bi = t2 / nby;
+}
+
+// p' of a cell from its (rho theta)' with base values staged in the compute precision: binomial
+// series of (1+x)^gamma when |x| <= EOS_XMAX, exact form otherwise
+template <typename R>
+__device__ __forceinline__ R eos_staged(R rthp, R irthb, R pb, const Phy &P)
+{
+    R x = rthp * irthb;
+    R ax = x < (R)0 ? -x : x;
+    if (ax > (R)EOS_XMAX) return pb * expm1_r((R)P.gam * log1p_r(x));
+    constexpr int NTERM = sizeof(R) == 4 ? 6 : EOS_TERMS;
+    R acc = sizeof(R) == 4 ? (R)P.binomf[NTERM - 1] : (R)P.binom[NTERM - 1];
+#pragma unroll
+    for (int n = NTERM - 2; n >= 0; --n) acc = fmaR(x, acc, sizeof(R) == 4 ? (R)P.binomf[n] : (R)P.binom[n]);
+    return pb * (x * acc);
+}
+
+// LDS view of the staged neighbourhood of one output point (i,j,k): cells at (i+di, j+dj, k+dk)
+// and lattice points at (i+di, j+dj, k+dk) for di in {-1,0,1}, addressed through the index of the
+// i-1 / i / i+1 plane entry plus dj * stride + dk; staged base profiles b[6][nb] at level kb.
+template <typename R>
+struct LView {
+    const R *rho, *rth, *pp, *u, *v, *w, *b;
+    int cb[3], lb[3];
+    int csj, lsj, nb, kb;
+    __device__ __forceinline__ int C(int di, int dj, int dk) const { return cb[di + 1] + dj * csj + dk; }
+    __device__ __forceinline__ int L(int di, int dj, int dk) const { return lb[di + 1] + dj * lsj + dk; }
+    __device__ __forceinline__ R B(int prof, int dk) const { return b[prof * nb + kb + dk]; }
+};
+
+// Update (MODE 0) or tendency (MODE 1) of cell (i,j,k) and lattice point (i,j,k) from the staged
+// neighbourhood.  Above the per-column bands cells and lattice points are regular and no geometry
+// or class array is read; inside the bands single-cell groups read their apertures, group volume
+// and neighbour masters, and masters of multi-cell groups take the general gather path.
+// values of q_n at the output point and its column thresholds, loaded ahead of the staging phases
+template <typename T>
+struct PointIn {
+    T rho, rth, rho_lo, rth_lo, mu, mv, mw;
+    int kcell, klat;
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ void load_point(const Dims &d, const Geo &G, const SIn<T> &qn, int i, int j, int k,
+                                           int final_stage, PointIn<T> &pi)
+{
+    const unsigned hc = __umul24(i, d.ny) + j;
+    const unsigned c = __umul24(hc, d.nzs) + k;
+    pi.kcell = G.colk[hc];
+    pi.klat = G.colk[(unsigned)(d.nx * d.ny) + hc];
+    if (MODE == 0) {
+        pi.rho = qn.rho[c]; pi.rth = qn.rth[c];
+        pi.mu = qn.mu[c]; pi.mv = qn.mv[c]; pi.mw = qn.mw[c];
+        if (final_stage && qn.rho_lo) { pi.rho_lo = qn.rho_lo[c]; pi.rth_lo = qn.rth_lo[c]; }
+        else { pi.rho_lo = (T)0; pi.rth_lo = (T)0; }
+    }
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &qs,
+                                            const PointIn<T> &pin, const SOut<T> &qo, double cdt, int final_stage,
+                                            int i, int j, int k, const LView<typename Compute<T>::R> &V,
+                                            int64_t *st)
+{
+    using R = typename Compute<T>::R;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, nzs = d.nzs;
+    const R Ux = (R)P.ux, Vy = (R)P.vy;
+    const unsigned hc = __umul24(i, ny) + j;
+    const unsigned c = __umul24(hc, nzs) + k;
+    bool bad = false;
+
+    // ---- scalars ----
+    const bool band = k < pin.kcell;
+    const int8_t cl = band ? G.cls[c] : (int8_t)CC_OPEN;
+    if (cl == CC_OPEN || cl == CC_ORPHAN) {
+        double L0, L1;
+        const R rc0 = V.rho[V.C(0, 0, 0)], rc1 = V.rth[V.C(0, 0, 0)];
+        if (!band) {
+            // regular cell: V = 1, open faces, neighbours at their own level; the base-state and
+            // reference-flow fluxes of opposite faces cancel exactly
+            const R ASx = (R)(0.25 * 1.0 * (d.dy * d.dz)), ASy = (R)(0.25 * 1.0 * (d.dz * d.dx));
+            const R ASz = (R)(0.25 * 1.0 * (d.dx * d.dy));
+            const R UASx = (R)(P.ux * 1.0 * (d.dy * d.dz)), UASy = (R)(P.vy * 1.0 * (d.dz * d.dx));
+            const R b0 = V.B(0, 0), b1 = V.B(1, 0);
+            R fm0, fm1, fp0, fp1;
+            double r0, r1;
+            {  // x faces
+                R sm = (V.u[V.L(0, 0, 0)] + V.u[V.L(0, 1, 0)]) + (V.u[V.L(0, 0, 1)] + V.u[V.L(0, 1, 1)]);
+                R sp = (V.u[V.L(1, 0, 0)] + V.u[V.L(1, 1, 0)]) + (V.u[V.L(1, 0, 1)] + V.u[V.L(1, 1, 1)]);
+                scalar_face_flux<R>(sm, ASx, UASx, b0, b1, V.rho[V.C(-1, 0, 0)], rc0, V.rth[V.C(-1, 0, 0)], rc1, fm0, fm1);
+                scalar_face_flux<R>(sp, ASx, UASx, b0, b1, rc0, V.rho[V.C(1, 0, 0)], rc1, V.rth[V.C(1, 0, 0)], fp0, fp1);
+                r0 = (double)fp0 - (double)fm0;
+                r1 = (double)fp1 - (double)fm1;
+            }
+            {  // y faces
+                R sm = (V.v[V.L(0, 0, 0)] + V.v[V.L(1, 0, 0)]) + (V.v[V.L(0, 0, 1)] + V.v[V.L(1, 0, 1)]);
+                R sp = (V.v[V.L(0, 1, 0)] + V.v[V.L(1, 1, 0)]) + (V.v[V.L(0, 1, 1)] + V.v[V.L(1, 1, 1)]);
+                scalar_face_flux<R>(sm, ASy, UASy, b0, b1, V.rho[V.C(0, -1, 0)], rc0, V.rth[V.C(0, -1, 0)], rc1, fm0, fm1);
+                scalar_face_flux<R>(sp, ASy, UASy, b0, b1, rc0, V.rho[V.C(0, 1, 0)], rc1, V.rth[V.C(0, 1, 0)], fp0, fp1);
+                r0 += (double)fp0 - (double)fm0;
+                r1 += (double)fp1 - (double)fm1;
+            }
+            {  // z faces (k >= 1 in the regular region; the rigid lid closes the top of nz-1)
+                R sm = (V.w[V.L(0, 0, 0)] + V.w[V.L(1, 0, 0)]) + (V.w[V.L(0, 1, 0)] + V.w[V.L(1, 1, 0)]);
+                scalar_face_flux<R>(sm, ASz, (R)0, V.B(4, 0), V.B(5, 0), V.rho[V.C(0, 0, -1)], rc0,
+                                    V.rth[V.C(0, 0, -1)], rc1, fm0, fm1);
+                r0 -= (double)fm0;
+                r1 -= (double)fm1;
+                if (k + 1 < nz) {
+                    R sp = (V.w[V.L(0, 0, 1)] + V.w[V.L(1, 0, 1)]) + (V.w[V.L(0, 1, 1)] + V.w[V.L(1, 1, 1)]);
+                    scalar_face_flux<R>(sp, ASz, (R)0, V.B(4, 1), V.B(5, 1), rc0, V.rho[V.C(0, 0, 1)], rc1,
+                                        V.rth[V.C(0, 0, 1)], fp0, fp1);
+                    r0 += (double)fp0;
+                    r1 += (double)fp1;
+                }
+            }
+            L0 = -r0 * P.idV;
+            L1 = -r1 * P.idV;
+        } else if (G.gnext[c] != -1) {  // master of a multi-cell group: general gather
+            double L[2];
+            group_scalar_tendency<T>(d, G, P, qs, c, L);
+            L0 = L[0]; L1 = L[1];
+        } else {
+            // single-cell group in the band: apertures, group volume and neighbour masters
+            double r0 = 0.0, r1 = 0.0, g0 = 0.0, g1 = 0.0;
+            for (int f = 0; f < 6; ++f) {
+                int axis = f >> 1, plus = f & 1;
+                int da = 0, db = 0, dc = 0;
+                if (axis == 0) da = plus ? 1 : -1;
+                else if (axis == 1) db = plus ? 1 : -1;
+                else {
+                    dc = plus ? 1 : -1;
+                    if (k + dc < 0 || k + dc >= nz) continue;  // ground and rigid lid
+                }
+                int ip = wrap1(i + (axis == 0 && plus), nx), jp = wrap1(j + (axis == 1 && plus), ny);
+                unsigned fu = __umul24(__umul24(ip, ny) + jp, nzs) + k + (axis == 2 && plus);
+                double A = axis == 0 ? G.Ax[fu] : (axis == 1 ? G.Ay[fu] : G.Az[fu]);
+                if (A == 0.0) continue;
+                int in = wrap1(i + da, nx), jn = wrap1(j + db, ny);
+                int32_t mn = G.master[__umul24(__umul24(in, ny) + jn, nzs) + k + dc];
+                if (mn < 0) continue;
+                int kn = mn % nzs;
+                int fa = axis == 0 && plus, fb = axis == 1 && plus, fc = axis == 2 && plus;
+                R s4;
+                double S, Un;
+                if (axis == 0) {
+                    s4 = (V.u[V.L(fa, fb, fc)] + V.u[V.L(fa, fb + 1, fc)]) + (V.u[V.L(fa, fb, fc + 1)] + V.u[V.L(fa, fb + 1, fc + 1)]);
+                    S = d.dy * d.dz; Un = P.ux;
+                } else if (axis == 1) {
+                    s4 = (V.v[V.L(fa, fb, fc)] + V.v[V.L(fa + 1, fb, fc)]) + (V.v[V.L(fa, fb, fc + 1)] + V.v[V.L(fa + 1, fb, fc + 1)]);
+                    S = d.dz * d.dx; Un = P.vy;
+                } else {
+                    s4 = (V.w[V.L(fa, fb, fc)] + V.w[V.L(fa + 1, fb, fc)]) + (V.w[V.L(fa, fb + 1, fc)] + V.w[V.L(fa + 1, fb + 1, fc)]);
+                    S = d.dx * d.dy; Un = 0.0;
+                }
+                const R rn0 = V.rho[V.C(da, db, dc)], rn1 = V.rth[V.C(da, db, dc)];
+                int klo = plus ? k : kn, kup = plus ? kn : k;
+                double pb0 = 0.5 * (P.rhob[klo] + P.rhob[kup]);
+                double pb1 = 0.5 * (P.rthb[klo] + P.rthb[kup]);
+                R f0, f1;
+                if (plus)
+                    scalar_face_flux<R>(s4, (R)(0.25 * A * S), (R)(Un * A * S), (R)pb0, (R)pb1, rc0, rn0, rc1, rn1, f0, f1);
+                else
+                    scalar_face_flux<R>(s4, (R)(0.25 * A * S), (R)(Un * A * S), (R)pb0, (R)pb1, rn0, rc0, rn1, rc1, f0, f1);
+                double h0 = pb0 * Un * A * S, h1 = pb1 * Un * A * S;
+                if (plus) { r0 += (double)f0; r1 += (double)f1; g0 += h0; g1 += h1; }
+                else { r0 -= (double)f0; r1 -= (double)f1; g0 -= h0; g1 -= h1; }
+            }
+            double vol = G.Vgroup[c] * P.dV;
+            L0 = -(g0 + r0) / vol;
+            L1 = -(g1 + r1) / vol;
+        }
+        if (MODE == 0) {
+            double x0 = (double)pin.rho, x1 = (double)pin.rth;
+            if (final_stage && qo.rho_lo) { x0 += (double)pin.rho_lo; x1 += (double)pin.rth_lo; }
+            x0 = fmaR(cdt, L0, x0);
+            x1 = fmaR(cdt, L1, x1);
+            T a = (T)x0, b = (T)x1;
+            bad = !isfinite(a) || !isfinite(b);
+            qo.rho[c] = a;
+            qo.rth[c] = b;
+            if (final_stage && qo.rho_lo) {
+                qo.rho_lo[c] = (T)(x0 - (double)a);
+                qo.rth_lo[c] = (T)(x1 - (double)b);
+            }
+        } else {
+            qo.rho[c] = (T)L0;
+            qo.rth[c] = (T)L1;
+        }
+    } else if (cl == CC_SOLID || MODE == 1) {
+        qo.rho[c] = (T)0;
+        qo.rth[c] = (T)0;
+        if (MODE == 0 && final_stage && qo.rho_lo) { qo.rho_lo[c] = (T)0; qo.rth_lo[c] = (T)0; }
+    }
+
+    // ---- momentum at the lattice point (i,j,k) ----
+    const bool pred = k >= pin.klat || G.vcls[c] == CC_PRED;
+    if (pred) {
+        const R h = (R)0.5, q4 = (R)0.25;
+        R u[7][3];
+        const int off[7][3] = {{0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+#pragma unroll
+        for (int s = 0; s < 7; ++s) {
+            int e = V.L(off[s][0], off[s][1], off[s][2]);
+            u[s][0] = V.u[e]; u[s][1] = V.v[e]; u[s][2] = V.w[e];
+        }
+        R rp[8], pp[8];  // bit0: i-1/i, bit1: j-1/j, bit2: k-1/k
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            int e = V.C((s & 1) - 1, ((s >> 1) & 1) - 1, (s >> 2) - 1);
+            rp[s] = V.rho[e];
+            pp[s] = V.pp[e];
+        }
+        // density perturbation on the six faces of the velocity cell, pressure gradient, buoyancy
+        const R rxm = q4 * ((rp[0] + rp[2]) + (rp[4] + rp[6])), rxp = q4 * ((rp[1] + rp[3]) + (rp[5] + rp[7]));
+        const R rym = q4 * ((rp[0] + rp[1]) + (rp[4] + rp[5])), ryp = q4 * ((rp[2] + rp[3]) + (rp[6] + rp[7]));
+        const R rzm = q4 * ((rp[0] + rp[1]) + (rp[2] + rp[3])), rzp = q4 * ((rp[4] + rp[5]) + (rp[6] + rp[7]));
+        const R ix = (R)P.idx, iy = (R)P.idy, iz = (R)P.idz;
+        const R pgx = (((pp[1] + pp[3]) + (pp[5] + pp[7])) - ((pp[0] + pp[2]) + (pp[4] + pp[6]))) * (q4 * ix);
+        const R pgy = (((pp[2] + pp[3]) + (pp[6] + pp[7])) - ((pp[0] + pp[1]) + (pp[4] + pp[5]))) * (q4 * iy);
+        const R pgz = (((pp[4] + pp[5]) + (pp[6] + pp[7])) - ((pp[0] + pp[1]) + (pp[2] + pp[3]))) * (q4 * iz);
+        const R r8 = (R)0.125 * (((rp[0] + rp[1]) + (rp[2] + rp[3])) + ((rp[4] + rp[5]) + (rp[6] + rp[7])));
+        const R rbc = V.B(4, 0);                         // base density on x and y faces
+        const R rbzm = V.B(0, -1), rbzp = V.B(0, 0);     // base density on the z faces
+        // Face flux of component m (perturbation form; the base product rbc U M0 cancels between
+        // opposite faces):  F = rbc U mb + (rbc ub + r'(U + ub)) (M0 + mb) on x/y faces with
+        // ub, mb the face means of the normal and m velocity perturbations; F = (rbz + r') wb (M0 + mb)
+        // on z faces.  The factor in front of (M0 + mb) is shared by the three components.
+        const R uxp = h * (u[0][0] + u[2][0]), uxm = h * (u[1][0] + u[0][0]);
+        const R vyp = h * (u[0][1] + u[4][1]), vym = h * (u[3][1] + u[0][1]);
+        const R wzp = h * (u[0][2] + u[6][2]), wzm = h * (u[5][2] + u[0][2]);
+        const R Czp = (rbzp + rzp) * wzp, Czm = (rbzm + rzm) * wzm;
+        R Lm[3];
+        if constexpr (sizeof(T) == 4) {  // perturbation form
+            const R Axf = rbc * Ux, Ayf = rbc * Vy;
+            const R Bxp = fmaR(rxp, Ux + uxp, rbc * uxp), Bxm = fmaR(rxm, Ux + uxm, rbc * uxm);
+            const R Byp = fmaR(ryp, Vy + vyp, rbc * vyp), Bym = fmaR(rym, Vy + vym, rbc * vym);
+#pragma unroll
+            for (int cm = 0; cm < 3; ++cm) {
+                const R M0 = cm == 0 ? Ux : (cm == 1 ? Vy : (R)0);
+                R mb;
+                mb = h * (u[0][cm] + u[2][cm]);
+                R fxp = fmaR(Axf, mb, Bxp * (M0 + mb));
+                mb = h * (u[1][cm] + u[0][cm]);
+                R fxm = fmaR(Axf, mb, Bxm * (M0 + mb));
+                mb = h * (u[0][cm] + u[4][cm]);
+                R fyp = fmaR(Ayf, mb, Byp * (M0 + mb));
+                mb = h * (u[3][cm] + u[0][cm]);
+                R fym = fmaR(Ayf, mb, Bym * (M0 + mb));
+                mb = h * (u[0][cm] + u[6][cm]);
+                R fzp = Czp * (M0 + mb);
+                mb = h * (u[5][cm] + u[0][cm]);
+                R fzm = Czm * (M0 + mb);
+                R adv = fmaR(fzp - fzm, iz, fmaR(fyp - fym, iy, (fxp - fxm) * ix));
+                R src = cm == 0 ? pgx : (cm == 1 ? pgy : fmaR((R)P.g, r8, pgz));
+                Lm[cm] = -(adv + src);
+            }
+        } else {  // paper variables: F = (rbar + r') ub mb on every face
+            const R Bxp = (rbc + rxp) * uxp, Bxm = (rbc + rxm) * uxm;
+            const R Byp = (rbc + ryp) * vyp, Bym = (rbc + rym) * vym;
+#pragma unroll
+            for (int cm = 0; cm < 3; ++cm) {
+                R fxp = Bxp * (h * (u[0][cm] + u[2][cm])), fxm = Bxm * (h * (u[1][cm] + u[0][cm]));
+                R fyp = Byp * (h * (u[0][cm] + u[4][cm])), fym = Bym * (h * (u[3][cm] + u[0][cm]));
+                R fzp = Czp * (h * (u[0][cm] + u[6][cm])), fzm = Czm * (h * (u[5][cm] + u[0][cm]));
+                R adv = fmaR(fzp - fzm, iz, fmaR(fyp - fym, iy, (fxp - fxm) * ix));
+                R src = cm == 0 ? pgx : (cm == 1 ? pgy : fmaR((R)P.g, r8, pgz));
+                Lm[cm] = -(adv + src);
+            }
+        }
+        if (MODE == 0) {
+            const R cd = (R)cdt;
+            T a = (T)fmaR(cd, Lm[0], (R)pin.mu);
+            T b = (T)fmaR(cd, Lm[1], (R)pin.mv);
+            T e = (T)fmaR(cd, Lm[2], (R)pin.mw);
+            bad = bad || !isfinite(a) || !isfinite(b) || !isfinite(e);
+            qo.mu[c] = a; qo.mv[c] = b; qo.mw[c] = e;
+        } else {
+            qo.mu[c] = (T)Lm[0]; qo.mv[c] = (T)Lm[1]; qo.mw[c] = (T)Lm[2];
+        }
+    } else if (MODE == 1) {
+        qo.mu[c] = (T)0; qo.mv[c] = (T)0; qo.mw[c] = (T)0;
+    }
+    if (bad) count_status(st, ST_NONFINITE);
+}
+
+template <typename T, int TX, int TY, int TZ, int MODE>
+__device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &qs,
+                                          const SIn<T> &qn, const SOut<T> &qo, double cdt, int final_stage,
+                                          const int i0, const int j0, const int k0, int64_t *st)
+{
+    using R = typename Compute<T>::R;
+    using TL = Tile<TX, TY, TZ>;
+    constexpr int NT = TL::NT;
+    constexpr int IT1 = (TL::NC + NT - 1) / NT, IT2 = (TL::NL + NT - 1) / NT;
+    constexpr int NB = TZ + 4;  // staged base levels k0-2 .. k0+TZ+1
+    __shared__ R s_rho[TL::NC], s_rth[TL::NC], s_pp[TL::NC];
+    __shared__ R s_u[TL::NL], s_v[TL::NL], s_w[TL::NL];
+    // base profiles in the compute precision: rhobar, (rho theta)bar, pbar, 1/(rho theta)bar, and
+    // the means of rhobar and (rho theta)bar over levels k-1, k (z faces / lattice level k)
+    __shared__ R s_b[6][NB];
+    const int tid = threadIdx.x;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, nzs = d.nzs;
+    const unsigned ncol = (unsigned)(nx * ny);
+    const R Ux = (R)P.ux, Vy = (R)P.vy;
+
+    // the output point of this thread; its q_n values and column thresholds are loaded first
+    const int tx = tid / (TY * TZ), ty = (tid / TZ) % TY, tz = tid % TZ;
+    const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+    const bool own = i < nx && j < ny && k < nz;
+    PointIn<T> pin;
+    if (own) load_point<T, MODE>(d, G, qn, i, j, k, final_stage, pin);
+    // tiles whose halo lies inside the grid in x, y and k need no periodic wrap and no range check
+    const bool inner = i0 >= 2 && i0 + TX < nx && j0 >= 2 && j0 + TY < ny && k0 >= 2 && k0 + TZ < nz;
+    // ---- issue the global loads of the staging phases first ----
+    R c_rho[IT1], c_rth[IT1];
+    if (inner) {
+        const unsigned tbase = __umul24(__umul24(i0 - 2, ny) + (j0 - 2), nzs) + (k0 - 2);
+#pragma unroll
+        for (int it = 0; it < IT1; ++it) {
+            int e = tid + it * NT;
+            c_rho[it] = (R)0;
+            c_rth[it] = (R)0;
+            if (e < TL::NC) {
+                int a = e / (TL::CY * TL::CZ), r = e - a * (TL::CY * TL::CZ), b = r / TL::CZ, c = r - b * TL::CZ;
+                unsigned ci = tbase + __umul24(__umul24(a, ny) + b, nzs) + c;
+                c_rho[it] = (R)qs.rho[ci];
+                c_rth[it] = (R)qs.rth[ci];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < IT1; ++it) {
+            int e = tid + it * NT;
+            c_rho[it] = (R)0;
+            c_rth[it] = (R)0;
+            if (e < TL::NC) {
+                int a = e / (TL::CY * TL::CZ), r = e - a * (TL::CY * TL::CZ), b = r / TL::CZ, c = r - b * TL::CZ;
+                int k = k0 - 2 + c;
+                if (k >= 0 && k < nz) {
+                    unsigned col = __umul24(wrap1(i0 - 2 + a, nx), ny) + wrap1(j0 - 2 + b, ny);
+                    unsigned ci = __umul24(col, nzs) + k;
+                    c_rho[it] = (R)qs.rho[ci];
+                    c_rth[it] = (R)qs.rth[ci];
+                }
+            }
+        }
+    }
+    R l_m0[IT2], l_m1[IT2], l_m2[IT2];
+    int l_kb[IT2];
+    unsigned l_p[IT2];
+    if (inner) {
+        const unsigned tcol = __umul24(i0 - 1, ny) + (j0 - 1);
+#pragma unroll
+        for (int it = 0; it < IT2; ++it) {
+            int e = tid + it * NT;
+            l_m0[it] = l_m1[it] = l_m2[it] = (R)0;
+            l_kb[it] = 0;
+            l_p[it] = 0;
+            if (e < TL::NL) {
+                int a = e / (TL::LY * TL::LZ), r = e - a * (TL::LY * TL::LZ), b = r / TL::LZ, c = r - b * TL::LZ;
+                unsigned col = tcol + __umul24(a, ny) + b;
+                unsigned p = __umul24(col, nzs) + (k0 - 1 + c);
+                l_p[it] = p;
+                l_m0[it] = (R)qs.mu[p];
+                l_m1[it] = (R)qs.mv[p];
+                l_m2[it] = (R)qs.mw[p];
+                l_kb[it] = G.colk[ncol + col];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < IT2; ++it) {
+            int e = tid + it * NT;
+            l_m0[it] = l_m1[it] = l_m2[it] = (R)0;
+            l_kb[it] = 0;
+            l_p[it] = 0;
+            if (e < TL::NL) {
+                int a = e / (TL::LY * TL::LZ), r = e - a * (TL::LY * TL::LZ), b = r / TL::LZ, c = r - b * TL::LZ;
+                int K = k0 - 1 + c;
+                if (K >= 0 && K <= nz) {
+                    int Kc = K < nz ? K : nz - 1;
+                    unsigned col = __umul24(wrap1(i0 - 1 + a, nx), ny) + wrap1(j0 - 1 + b, ny);
+                    unsigned p = __umul24(col, nzs) + Kc;
+                    l_p[it] = p;
+                    l_m0[it] = (R)qs.mu[p];
+                    l_m1[it] = (R)qs.mv[p];
+                    l_m2[it] = (R)qs.mw[p];
+                    l_kb[it] = G.colk[ncol + col];
+                }
+            }
+        }
+    }
+    for (int e = tid; e < 6 * NB; e += NT) {
+        int pr = e / NB, kk = k0 - 2 + (e - pr * NB);
+        kk = kk < 0 ? 0 : (kk >= nz ? nz - 1 : kk);
+        double v;
+        switch (pr) {
+        case 0: v = P.rhob[kk]; break;
+        case 1: v = P.rthb[kk]; break;
+        case 2: v = P.pb[kk]; break;
+        case 3: v = P.irthb[kk]; break;
+        case 4: v = P.rhobc[kk]; break;
+        default: v = kk > 0 ? 0.5 * (P.rthb[kk - 1] + P.rthb[kk]) : P.rthb[0]; break;
+        }
+        s_b[pr][e - pr * NB] = (R)v;
+    }
+    __syncthreads();
+    // ---- phase 1: cell scalars and p' (p' for the cells i0-1..i0+TX-1 x ... used by the momentum
+    // stencils of the tile) ----
+#pragma unroll
+    for (int it = 0; it < IT1; ++it) {
+        int e = tid + it * NT;
+        if (e < TL::NC) {
+            int a = e / (TL::CY * TL::CZ), r = e - a * (TL::CY * TL::CZ), b = r / TL::CZ, c = r - b * TL::CZ;
+            int k = k0 - 2 + c;
+            R pp = (R)0;
+            if (k >= 0 && k < nz && a >= 1 && a <= TX + 1 && b >= 1 && b <= TY + 1 && c >= 1 && c <= TZ + 1)
+                pp = eos_staged<R>(c_rth[it], s_b[3][c], s_b[2][c], P);
+            s_rho[e] = c_rho[it];
+            s_rth[e] = c_rth[it];
+            s_pp[e] = pp;
+        }
+    }
+    __syncthreads();
+    // ---- phase 2: lattice velocities (perturbations from the reference flow) ----
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+        int e = tid + it * NT;
+        if (e < TL::NL) {
+            int a = e / (TL::LY * TL::LZ), r = e - a * (TL::LY * TL::LZ), b = r / TL::LZ, c = r - b * TL::LZ;
+            int K = k0 - 1 + c;
+            R u0 = (R)0, u1 = (R)0, u2 = (R)0;
+            if (K >= 0 && K <= nz) {
+                int Kc = K < nz ? K : nz - 1;  // the rigid lid copies the level below
+                bool pred = Kc >= l_kb[it] || G.vcls[l_p[it]] == CC_PRED;
+                if (pred) {
+                    int cz = Kc - k0 + 1;  // LDS level of cell level Kc-1
+                    R sm = ((s_rho[TL::cs(a, b, cz)] + s_rho[TL::cs(a + 1, b, cz)]) +
+                            (s_rho[TL::cs(a, b + 1, cz)] + s_rho[TL::cs(a + 1, b + 1, cz)])) +
+                           ((s_rho[TL::cs(a, b, cz + 1)] + s_rho[TL::cs(a + 1, b, cz + 1)]) +
+                            (s_rho[TL::cs(a, b + 1, cz + 1)] + s_rho[TL::cs(a + 1, b + 1, cz + 1)]));
+                    R rpc = sm * (R)0.125;
+                    R ri = recip(s_b[4][Kc - k0 + 2] + rpc);
+                    u0 = fmaR(-rpc, Ux, l_m0[it]) * ri;
+                    u1 = fmaR(-rpc, Vy, l_m1[it]) * ri;
+                    u2 = l_m2[it] * ri;
+                } else {
+                    u0 = l_m0[it];
+                    u1 = l_m1[it];
+                    u2 = l_m2[it];
+                }
+                if (K == nz) u2 = (R)0;
+            }
+            s_u[e] = u0;
+            s_v[e] = u1;
+            s_w[e] = u2;
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 3: one cell and one lattice point per thread ----
+    if (!own) return;
+    LView<R> V;
+    V.rho = s_rho; V.rth = s_rth; V.pp = s_pp; V.u = s_u; V.v = s_v; V.w = s_w; V.b = &s_b[0][0];
+    for (int m = 0; m < 3; ++m) {
+        V.cb[m] = TL::cs(tx + 1 + m, ty + 2, tz + 2);
+        V.lb[m] = TL::ls(tx + m, ty + 1, tz + 1);
+    }
+    V.csj = TL::CZ; V.lsj = TL::LZ; V.nb = NB; V.kb = tz + 2;
+    stage_point<T, MODE>(d, G, P, qs, pin, qo, cdt, final_stage, i, j, k, V, st);
+}
+
+template <typename T, int TX, int TY, int TZ, int MODE, int MINW>
+__global__ void __launch_bounds__(TX * TY * TZ, MINW)
+    k_stage_tiled(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn, SOut<T> qo, double cdt, int final_stage,
+                  int nbx, int nby, int nbz, int64_t *st)
+{
+    int bi, bj, bk;
+    tile_of_block(nbx, nby, nbz, bi, bj, bk);
+    tile_body<T, TX, TY, TZ, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, bi * TX, bj * TY, bk * TZ, st);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Batched form: many independent blocks (ensemble members, refined blocks) in one launch.  Each
+// block is described on the device; the grid enumerates the tiles of all blocks (prefix table
+// tile0), each workgroup finds its block by binary search and runs the same tile body.
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+struct BlockDesc {
+    Dims d;
+    Geo G;
+    Phy P;
+    SOut<T> q[3];       // the block's three state buffers
+    int nbx, nby, nbz;  // tiles of the update kernel
+    int tile0;          // first tile of the block in the batched update grid
+    int col0;           // first column of the block in the batched diagnostic grid
+    int pad;
+};
+
+template <typename T>
+__device__ __forceinline__ SIn<T> as_in(const SOut<T> &q)
+{
+    return SIn<T>{q.rho, q.rth, q.mu, q.mv, q.mw, q.rho_lo, q.rth_lo};
+}
+
+template <typename T, int TX, int TY, int TZ, int MODE, int MINW>
+__global__ void __launch_bounds__(TX * TY * TZ, MINW)
+    k_stage_batch(const BlockDesc<T> *__restrict__ desc, int nblk, int ntiles, int rn, int rs, int ro,
+                  double cdt, int final_stage, int64_t *st)
+{
+    // XCD-aware order over the whole batch, then the block that owns this tile
+    int b = blockIdx.x;
+    int xcd = b & 7, idx = b >> 3, per = ntiles >> 3, rem = ntiles & 7;
+    int lb = xcd * per + (xcd < rem ? xcd : rem) + idx;
+    int lo = 0, hi = nblk - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (desc[mid].tile0 <= lb) lo = mid;
+        else hi = mid - 1;
+    }
+    const BlockDesc<T> &D = desc[lo];
+    int t = lb - D.tile0;
+    int bk = t % D.nbz, t2 = t / D.nbz, bj = t2 % D.nby, bi = t2 / D.nby;
+    tile_body<T, TX, TY, TZ, MODE>(D.d, D.G, D.P, as_in(D.q[rs]), as_in(D.q[rn]), D.q[ro], cdt, final_stage,
+                                   bi * TX, bj * TY, bk * TZ, st);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Velocity diagnostics (Sec. 2.4).  The plane search takes integer decisions (which plane, which
+// face, which corners carry weight) from floating-point positions, so it is evaluated without FMA
+// contraction in the written order.
+// ------------------------------------------------------------------------------------------------
+
+// Try the first three lattice planes of one family (0: x = const, 1: y = const, 2: z = const) beyond
+// the terrain point B along the normal line; on each plane the intersection falls in a face of four
+// lattice points (located with floor); the first plane whose corners with non-zero bilinear weight
+// are all predicted gives the interpolated velocity (the paper's u_N).
+template <typename T, typename R = typename Compute<T>::R>
+__device__ bool plane_family(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &q, int fam,
+                             int I, int J, R ut[3])
+{
+#pragma clang fp contract(off)
+    int64_t nc = (int64_t)d.nx * d.ny, hc = hidx(d, I, J);
+    double n0 = G.nrm[hc], n1 = G.nrm[nc + hc], n2 = G.nrm[2 * nc + hc];
+    double hh = G.H[hc];
+    if (!(hh >= 0.0 && hh < (double)d.nz * d.dz)) return false;  // terrain outside the column
+    double bx = (double)I * d.dx, by = (double)J * d.dy;
+    for (int m = 0; m < 3; ++m) {
+        int P4[4][3];
+        int ia, ib;
+        double a, b;
+        if (fam == 2) {
+            int K0 = (int)floor(hh / d.dz) + 1;
+            while (K0 > 0 && (double)(K0 - 1) * d.dz > hh) --K0;
+            while ((double)K0 * d.dz <= hh) ++K0;
+            int K = K0 + m;
+            if (K > d.nz - 1) return false;
+            double t = ((double)K * d.dz - hh) / n2;
+            double fx = (bx + t * n0) / d.dx, fy = (by + t * n1) / d.dy;
+            ia = (int)floor(fx); ib = (int)floor(fy);
+            a = fx - (double)ia; b = fy - (double)ib;
+            P4[0][0] = ia; P4[0][1] = ib; P4[0][2] = K;
+            P4[1][0] = ia + 1; P4[1][1] = ib; P4[1][2] = K;
+            P4[2][0] = ia; P4[2][1] = ib + 1; P4[2][2] = K;
+            P4[3][0] = ia + 1; P4[3][1] = ib + 1; P4[3][2] = K;
+        } else {
+            double nn = fam == 0 ? n0 : n1;
+            if (nn == 0.0) return false;
+            int step = (m + 1) * (nn > 0.0 ? 1 : -1);
+            double t = fam == 0 ? ((double)step * d.dx) / nn : ((double)step * d.dy) / nn;
+            double fa = fam == 0 ? (by + t * n1) / d.dy : (bx + t * n0) / d.dx;
+            double fz = (hh + t * n2) / d.dz;
+            ia = (int)floor(fa); ib = (int)floor(fz);
+            a = fa - (double)ia; b = fz - (double)ib;
+            if (ib < 0 || ib + 1 > d.nz - 1) continue;
+            for (int s = 0; s < 4; ++s) {
+                int pa = ia + (s & 1), pz = ib + (s >> 1);
+                if (fam == 0) { P4[s][0] = I + step; P4[s][1] = pa; }
+                else { P4[s][0] = pa; P4[s][1] = J + step; }
+                P4[s][2] = pz;
+            }
+        }
+        double w[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
+        bool ok = true;
+        for (int s = 0; s < 4 && ok; ++s)
+            if (w[s] != 0.0) ok = G.vcls[cidx(d, P4[s][0], P4[s][1], P4[s][2])] == CC_PRED;
+        if (!ok) continue;
+        R acc[3] = {(R)0, (R)0, (R)0};
+        for (int s = 0; s < 4; ++s) {
+            if (w[s] == 0.0) continue;
+            R v[3];
+            lat_vel<T>(d, G, P, q, P4[s][0], P4[s][1], P4[s][2], v);
+            for (int cc = 0; cc < 3; ++cc) acc[cc] += (R)w[s] * v[cc];
+        }
+        ut[0] = acc[0]; ut[1] = acc[1]; ut[2] = acc[2];
+        return true;
+    }
+    return false;
+}
+
+// one thread per column corner (I,J): boundary velocity (free-slip projection of the nearest-plane
+// mean, eq. 33), then every diagnosed lattice point and absorbed/solid cell of the column
+template <typename T>
+__device__ __forceinline__ void diagnose_column(const Dims &d, const Geo &G, const Phy &P, const SOut<T> &qw,
+                                                int64_t t, int64_t *st)
+{
+    using R = typename Compute<T>::R;
+    int64_t nc = (int64_t)d.nx * d.ny;
+    int I = (int)(t / d.ny), J = (int)(t % d.ny);
+    SIn<T> q{qw.rho, qw.rth, qw.mu, qw.mv, qw.mw, qw.rho_lo, qw.rth_lo};
+    double n0 = G.nrm[t], n1 = G.nrm[nc + t], n2 = G.nrm[2 * nc + t];
+    int dom = (fabs(n2) >= fabs(n0) && fabs(n2) >= fabs(n1)) ? 2 : (fabs(n0) >= fabs(n1) ? 0 : 1);
+    R ut[3];
+    bool ok = plane_family<T>(d, G, P, q, dom, I, J, ut);
+    const int order[3] = {2, 0, 1};
+    for (int f = 0; f < 3 && !ok; ++f)
+        if (order[f] != dom) ok = plane_family<T>(d, G, P, q, order[f], I, J, ut);
+    if (!ok) {  // no usable plane: u~ = 0 (as a perturbation: minus the reference flow)
+        ut[0] = -(R)P.ux; ut[1] = -(R)P.vy; ut[2] = (R)0;
+        count_status(st, ST_NOPLANE);
+    }
+    R dn = (ut[0] + (R)P.ux) * (R)n0 + (ut[1] + (R)P.vy) * (R)n1 + ut[2] * (R)n2;
+    R ub[3] = {ut[0] - dn * (R)n0, ut[1] - dn * (R)n1, ut[2] - dn * (R)n2};
+    double hh = G.H[t];
+    int ktop = G.colk[2 * nc + t];
+    int64_t base = cidx(d, I, J, 0);
+    for (int K = 0; K < ktop; ++K) {
+        int64_t p = base + K;
+        int8_t vc = G.vcls[p];
+        if (vc != CC_PRED) {
+            R u[3] = {ub[0], ub[1], ub[2]};
+            if (vc == CC_MFACE) {
+                int kp = -1;
+                for (int kk = K + 1; kk <= K + 8 && kk < d.nz; ++kk)
+                    if (G.vcls[base + kk] == CC_PRED) { kp = kk; break; }
+                if (kp >= 0) {
+                    double gm = ((double)K * d.dz - hh) / ((double)kp * d.dz - hh);
+                    R v[3];
+                    lat_vel<T>(d, G, P, q, I, J, kp, v);
+                    for (int cc = 0; cc < 3; ++cc) u[cc] = v[cc] * (R)gm + ub[cc] * (R)(1.0 - gm);
+                }
+            }
+            qw.mu[p] = (T)u[0]; qw.mv[p] = (T)u[1]; qw.mw[p] = (T)u[2];
+        }
+        int8_t cl = G.cls[p];
+        if (cl == CC_SOLID) {
+            qw.rho[p] = (T)0; qw.rth[p] = (T)0;
+            if (qw.rho_lo) { qw.rho_lo[p] = (T)0; qw.rth_lo[p] = (T)0; }
+        } else if (cl == CC_ABSORBED) {
+            int64_t m = G.master[p];
+            qw.rho[p] = qw.rho[m];
+            qw.rth[p] = qw.rth[m];
+            if (qw.rho_lo) { qw.rho_lo[p] = qw.rho_lo[m]; qw.rth_lo[p] = qw.rth_lo[m]; }
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_diagnose(Dims d, Geo G, Phy P, SOut<T> qw, int64_t *st)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)d.nx * d.ny) return;
+    diagnose_column<T>(d, G, P, qw, t, st);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_diagnose_batch(const BlockDesc<T> *__restrict__ desc, int nblk,
+                                                       int ncols, int ro, int64_t *st)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ncols) return;
+    int lo = 0, hi = nblk - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (desc[mid].col0 <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const BlockDesc<T> &D = desc[lo];
+    diagnose_column<T>(D.d, D.G, D.P, D.q[ro], t - D.col0, st);
+}
+
+
+// ------------------------------------------------------------------------------------------------
+// host helpers: C-ABI structs -> kernel views
+// ------------------------------------------------------------------------------------------------
+inline bool make_views(const char *what, const cc_grid *grid, const cc_phys *phys, const cc_geom *g,
+                       const double *base, cc_prec prec, Dims &d, Geo &G, Phy &P)
+{
+    if (!check_grid(grid)) return false;
+    if (!phys || !g || !base) { set_error("%s: null argument", what); return false; }
+    const void *p[] = {g->H, g->V, g->Ax, g->Ay, g->Az, g->nrm, g->Vgroup, g->cls, g->vcls,
+                       g->master, g->gnext, g->colk};
+    if (!check_ptrs(what, 12, p)) return false;
+    if (prec != CC_F64 && prec != CC_F32_PERT) { set_error("%s: unknown precision %d", what, (int)prec); return false; }
+    d = dims_of(grid);
+    G = Geo{g->H, g->V, g->Ax, g->Ay, g->Az, g->nrm, g->Vgroup, g->cls, g->vcls, g->master, g->gnext, g->colk};
+    double cv = phys->cp - phys->rd;
+    P.rhob = base; P.rthb = base + d.nz; P.pb = base + 2 * d.nz; P.thb = base + 3 * d.nz;
+    P.irthb = base + 4 * d.nz; P.rhobc = base + 5 * d.nz;
+    P.g = phys->g;
+    P.gam = phys->cp / cv;
+    P.ux = prec == CC_F32_PERT ? phys->u0 : 0.0;
+    P.vy = prec == CC_F32_PERT ? phys->v0 : 0.0;
+    P.dV = d.dx * d.dy * d.dz;
+    P.idV = 1.0 / P.dV;
+    P.idx = 1.0 / d.dx; P.idy = 1.0 / d.dy; P.idz = 1.0 / d.dz;
+    // binomial coefficients of (1+x)^gamma - 1
+    P.binom[0] = P.gam;
+    for (int n = 1; n < EOS_TERMS; ++n) P.binom[n] = P.binom[n - 1] * (P.gam - n) / (n + 1);
+    for (int n = 0; n < EOS_TERMS; ++n) P.binomf[n] = (float)P.binom[n];
+    return true;
+}
+
+inline bool state_ok(const char *what, const cc_state *q)
+{
+    if (!q) { set_error("%s: null state", what); return false; }
+    const void *p[] = {q->rho, q->rth, q->mu, q->mv, q->mw};
+    return check_ptrs(what, 5, p);
+}
+
+template <typename T>
+inline SIn<T> sin_of(const cc_state *q)
+{
+    bool lo = sizeof(T) == 4 && q->rho_lo && q->rth_lo;
+    return SIn<T>{(const T *)q->rho, (const T *)q->rth, (const T *)q->mu, (const T *)q->mv, (const T *)q->mw,
+                  lo ? (const T *)q->rho_lo : nullptr, lo ? (const T *)q->rth_lo : nullptr};
+}
+template <typename T>
+inline SOut<T> sout_of(cc_state *q)
+{
+    bool lo = sizeof(T) == 4 && q->rho_lo && q->rth_lo;
+    return SOut<T>{(T *)q->rho, (T *)q->rth, (T *)q->mu, (T *)q->mv, (T *)q->mw,
+                   lo ? (T *)q->rho_lo : nullptr, lo ? (T *)q->rth_lo : nullptr};
+}
+
+}  // namespace cc
