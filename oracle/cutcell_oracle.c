@@ -25,7 +25,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-typedef struct { int32_t nx, ny, nz, nsub; double dx, dy, dz; } or_grid;
+typedef struct { int32_t nx, ny, nz, nsub; double dx, dy, dz, z0; } or_grid;  /* z0: bottom height */
 typedef struct { double g, rd, cp, p0, theta0, bvn, u0, v0; } or_phys;
 
 /* cell classes, merge directions and lattice-point classes (numeric codes are an interface) */
@@ -62,13 +62,13 @@ static inline size_t hidx(const or_grid *g, int i, int j)
 /* theta(z) = theta0 exp(N^2 z/g); Exner pi from d pi/dz = -g/(cp theta); rho*theta from the     */
 /* equation of state; pbar through the same equation of state so that (rho theta)' = 0 <=> p'=0. */
 /* ------------------------------------------------------------------------------------------ */
-void or_base_state(const or_phys *ph, int nz, double dz, double *rhob, double *rthb, double *pb,
+void or_base_state(const or_phys *ph, int nz, double dz, double z0, double *rhob, double *rthb, double *pb,
                    double *thb)
 {
     double cv = ph->cp - ph->rd;
     double n2 = ph->bvn * ph->bvn;
     for (int k = 0; k < nz; ++k) {
-        double z = ((double)k + 0.5) * dz;
+        double z = z0 + ((double)k + 0.5) * dz;
         double th, pi;
         if (n2 > 0.0) {
             th = ph->theta0 * exp(n2 * z / ph->g);
@@ -430,7 +430,8 @@ static int plane_family(const or_ctx *x, int fam, int I, int J, double ut[3])
     double n0 = x->G->nrm[hc], n1 = x->G->nrm[nc + hc], n2 = x->G->nrm[2 * nc + hc];
     double h = x->G->H[hc];
     if (!(h >= 0.0 && h < (double)g->nz * g->dz)) return 0; /* terrain outside the column */
-    double bx = (double)I * g->dx, by = (double)J * g->dy;
+    /* horizontal positions are measured from the corner (I,J) in cell units, so the located face
+     * and weights do not depend on where the grid's origin lies */
     for (int m = 0; m < 3; ++m) {
         int P[4][3], ia, ib;
         double a, b;
@@ -441,9 +442,10 @@ static int plane_family(const or_ctx *x, int fam, int I, int J, double ut[3])
             int K = K0 + m;
             if (K > g->nz - 1) return 0;
             double t = ((double)K * g->dz - h) / n2;
-            double fx = (bx + t * n0) / g->dx, fy = (by + t * n1) / g->dy;
-            ia = (int)floor(fx); ib = (int)floor(fy);
-            a = fx - (double)ia; b = fy - (double)ib;
+            double fx = (t * n0) / g->dx, fy = (t * n1) / g->dy;
+            int sx = (int)floor(fx), sy = (int)floor(fy);
+            a = fx - (double)sx; b = fy - (double)sy;
+            ia = I + sx; ib = J + sy;
             int Q[4][3] = {{ia, ib, K}, {ia + 1, ib, K}, {ia, ib + 1, K}, {ia + 1, ib + 1, K}};
             memcpy(P, Q, sizeof(P));
         } else {
@@ -451,10 +453,12 @@ static int plane_family(const or_ctx *x, int fam, int I, int J, double ut[3])
             if (nn == 0.0) return 0;
             int step = (m + 1) * (nn > 0.0 ? 1 : -1);
             double t = fam == 0 ? ((double)step * g->dx) / nn : ((double)step * g->dy) / nn;
-            double fa = fam == 0 ? (by + t * n1) / g->dy : (bx + t * n0) / g->dx;
+            double fa = fam == 0 ? (t * n1) / g->dy : (t * n0) / g->dx;
             double fz = (h + t * n2) / g->dz;
-            ia = (int)floor(fa); ib = (int)floor(fz);
-            a = fa - (double)ia; b = fz - (double)ib;
+            int sa = (int)floor(fa);
+            ib = (int)floor(fz);
+            a = fa - (double)sa; b = fz - (double)ib;
+            ia = (fam == 0 ? J : I) + sa;
             if (ib < 0 || ib + 1 > g->nz - 1) continue;
             if (fam == 0) {
                 int X = I + step;
@@ -515,7 +519,10 @@ int64_t or_boundary_velocity(const or_grid *g, const or_phys *ph, const or_geom 
             size_t hc = hidx(g, I, J);
             double ut[3] = {0.0, 0.0, 0.0};
             int ok = nearest_plane_velocity(&x, I, J, ut);
-            if (!ok) ++noplane;
+            /* counted when the terrain point lies in the grid's height range (a raised block of a
+             * refined grid has its ground elsewhere) */
+            double h = G->H[hc];
+            if (!ok && h >= 0.0 && h < (double)g->nz * g->dz) ++noplane;
             if (flag) flag[hc] = (int8_t)!ok;
             double n0 = G->nrm[hc], n1 = G->nrm[nc + hc], n2 = G->nrm[2 * nc + hc];
             double d = ut[0] * n0 + ut[1] * n1 + ut[2] * n2;
@@ -826,9 +833,10 @@ void or_tendency_points(const or_grid *g, const or_phys *ph, const or_geom *G, c
 /* Explicit three-stage Runge-Kutta (Wicker & Skamarock 2002): q_out = q_n + cdt * L(q_s),       */
 /* applied to group masters and predicted points, followed by the diagnostic pass.              */
 /* ------------------------------------------------------------------------------------------ */
-void or_rk_stage(const or_grid *g, const or_phys *ph, const or_geom *G, const double *rhob,
-                 const double *rthb, const double *pb, const or_state *qn, const or_state *qs,
-                 or_state *qout, double cdt, int64_t *counts)
+/* the update alone (group masters and predicted points), without the diagnostic pass */
+void or_rk_update(const or_grid *g, const or_phys *ph, const or_geom *G, const double *rhob,
+                  const double *rthb, const double *pb, const or_state *qn, const or_state *qs,
+                  or_state *qout, double cdt)
 {
     size_t n = (size_t)g->nx * g->ny * g->nz;
     int64_t *head = (int64_t *)malloc(sizeof(int64_t) * n), *next = (int64_t *)malloc(sizeof(int64_t) * n);
@@ -850,7 +858,24 @@ void or_rk_stage(const or_grid *g, const or_phys *ph, const or_geom *G, const do
         }
     }
     free(head); free(next);
+}
+
+void or_rk_stage(const or_grid *g, const or_phys *ph, const or_geom *G, const double *rhob,
+                 const double *rthb, const double *pb, const or_state *qn, const or_state *qs,
+                 or_state *qout, double cdt, int64_t *counts)
+{
+    or_rk_update(g, ph, G, rhob, rthb, pb, qn, qs, qout, cdt);
     or_diagnose(g, ph, G, rhob, rthb, pb, qout, counts);
+}
+
+/* total fluxes of rho and rho*theta through the face at the lower side of cell (I,J,K) along
+ * `axis` (positive along +axis), as the tendency uses them */
+void or_face_flux(const or_grid *g, const or_phys *ph, const or_geom *G, const double *rhob,
+                  const double *rthb, const double *pb, const or_state *q, int axis, int I, int J, int K,
+                  double *F)
+{
+    or_ctx x = {g, ph, G, rhob, rthb, pb, q};
+    face_flux(&x, axis, I, J, K, F);
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -876,7 +901,7 @@ void or_reduce(const or_grid *g, const or_phys *ph, const or_geom *G, const doub
             double vg = G->Vgroup[c] * dV;
             double rho = rhob[k] + q->rho[c];
             double p = pb[k] + eos_pprime(q->rth[c], rthb[k], pb[k], gam);
-            double z = ((double)k + 0.5) * g->dz;
+            double z = g->z0 + ((double)k + 0.5) * g->dz;
             mp += vg * q->rho[c];
             tp += vg * q->rth[c];
             mt += vg * rho;

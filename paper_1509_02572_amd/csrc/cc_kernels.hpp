@@ -792,7 +792,8 @@ __device__ bool plane_family(const Dims &d, const Geo &G, const Phy &P, const SI
     double n0 = G.nrm[hc], n1 = G.nrm[nc + hc], n2 = G.nrm[2 * nc + hc];
     double hh = G.H[hc];
     if (!(hh >= 0.0 && hh < (double)d.nz * d.dz)) return false;  // terrain outside the column
-    double bx = (double)I * d.dx, by = (double)J * d.dy;
+    // horizontal positions are measured from the corner (I,J) in cell units, so the located face
+    // and weights do not depend on where the grid's origin lies
     for (int m = 0; m < 3; ++m) {
         int P4[4][3];
         int ia, ib;
@@ -804,9 +805,10 @@ __device__ bool plane_family(const Dims &d, const Geo &G, const Phy &P, const SI
             int K = K0 + m;
             if (K > d.nz - 1) return false;
             double t = ((double)K * d.dz - hh) / n2;
-            double fx = (bx + t * n0) / d.dx, fy = (by + t * n1) / d.dy;
-            ia = (int)floor(fx); ib = (int)floor(fy);
-            a = fx - (double)ia; b = fy - (double)ib;
+            double fx = (t * n0) / d.dx, fy = (t * n1) / d.dy;
+            int sx = (int)floor(fx), sy = (int)floor(fy);
+            a = fx - (double)sx; b = fy - (double)sy;
+            ia = I + sx; ib = J + sy;
             P4[0][0] = ia; P4[0][1] = ib; P4[0][2] = K;
             P4[1][0] = ia + 1; P4[1][1] = ib; P4[1][2] = K;
             P4[2][0] = ia; P4[2][1] = ib + 1; P4[2][2] = K;
@@ -816,10 +818,12 @@ __device__ bool plane_family(const Dims &d, const Geo &G, const Phy &P, const SI
             if (nn == 0.0) return false;
             int step = (m + 1) * (nn > 0.0 ? 1 : -1);
             double t = fam == 0 ? ((double)step * d.dx) / nn : ((double)step * d.dy) / nn;
-            double fa = fam == 0 ? (by + t * n1) / d.dy : (bx + t * n0) / d.dx;
+            double fa = fam == 0 ? (t * n1) / d.dy : (t * n0) / d.dx;
             double fz = (hh + t * n2) / d.dz;
-            ia = (int)floor(fa); ib = (int)floor(fz);
-            a = fa - (double)ia; b = fz - (double)ib;
+            int sa = (int)floor(fa);
+            ib = (int)floor(fz);
+            a = fa - (double)sa; b = fz - (double)ib;
+            ia = (fam == 0 ? J : I) + sa;
             if (ib < 0 || ib + 1 > d.nz - 1) continue;
             for (int s = 0; s < 4; ++s) {
                 int pa = ia + (s & 1), pz = ib + (s >> 1);
@@ -865,7 +869,10 @@ __device__ __forceinline__ void diagnose_column(const Dims &d, const Geo &G, con
         if (order[f] != dom) ok = plane_family<T>(d, G, P, q, order[f], I, J, ut);
     if (!ok) {  // no usable plane: u~ = 0 (as a perturbation: minus the reference flow)
         ut[0] = -(R)P.ux; ut[1] = -(R)P.vy; ut[2] = (R)0;
-        count_status(st, ST_NOPLANE);
+        // counted when the terrain point lies in the grid's height range (a raised block of a
+        // refined grid has its ground elsewhere)
+        double h0 = G.H[t];
+        if (h0 >= 0.0 && h0 < (double)d.nz * d.dz) count_status(st, ST_NOPLANE);
     }
     R dn = (ut[0] + (R)P.ux) * (R)n0 + (ut[1] + (R)P.vy) * (R)n1 + ut[2] * (R)n2;
     R ub[3] = {ut[0] - dn * (R)n0, ut[1] - dn * (R)n1, ut[2] - dn * (R)n2};
