@@ -28,7 +28,9 @@
  * return CC_EINVAL and launch nothing.  HIP launch failures return CC_EDEVICE.  Conditions found on
  * the device are counted into the caller's int64 status array `dev_status[CC_NSTATUS]` (never reset
  * by the library): [0] unmergeable cells, [1] corners without a nearest plane, [2] non-finite values,
- * [3] terrain corners outside [0, (nz-2) dz], [4] merged groups larger than CC_MAX_GROUP.  The
+ * [3] terrain corners outside [0, (nz-2) dz] (or above it for a raised block), [4] merged groups
+ * larger than CC_MAX_GROUP, [5] coarse-fine interface faces of a refined grid that are not open
+ * regular faces (the interface touches cut or merged cells).  The
  * caller synchronises and checks them (cutcell_check_status).  No exception crosses the ABI.
  * Calls are reentrant for distinct streams and buffers; calls sharing output buffers race.
  */
@@ -68,8 +70,12 @@ typedef struct {
     int32_t nx, ny, nz, nzs; /* cells; padded k stride (nzs >= nz) */
     double dx, dy, dz;       /* spacings [m] */
     int32_t nsub;            /* sub-columns per cell edge for volumes/apertures, power of two */
-    int32_t tile;            /* tile shape of the update kernel (0 = default; 1..8 see the tuning
+    int32_t tile;            /* tile shape of the update kernel (0 = default; 1..12 see the tuning
                                 table of the stage kernels); results do not depend on it */
+    double z0;               /* height of the grid's bottom face above the terrain datum [m]: 0 for
+                                a grid standing on the ground; > 0 for a block of a refined grid
+                                that starts higher (Sec. 2.2), whose H is then given relative to z0
+                                and may be negative (terrain below the block) */
 } cc_grid;
 
 typedef struct {
@@ -108,7 +114,7 @@ typedef struct {
 const char *cutcell_version(void);
 const char *cutcell_last_error(void);
 
-/* Base state on cell centres z_k = (k+1/2) dz (Sec. 2.1 hydrostatic reference; constant N and
+/* Base state on cell centres z_k = z0 + (k+1/2) dz (Sec. 2.1 hydrostatic reference; constant N and
  * theta0 at z = 0, surface pressure p0, Sec. 3).  base: [6*nz] doubles = rhobar, (rho theta)bar,
  * pbar, thetabar, 1/(rho theta)bar, and at lattice level K the mean of rhobar at levels K-1 and K;
  * pbar follows from (rho theta)bar through the equation of state.  Every other call takes this
@@ -119,7 +125,8 @@ cc_status cutcell_base_state(const cc_grid *grid, const cc_phys *phys, double *b
  * cell volume fractions V and face apertures Ax/Ay/Az from nsub x nsub narrow sub-columns, column
  * gradients (eqs. xgrad, ygrad) and the unit terrain normal at every corner from centred gradients
  * of the column-centre heights (Sec. 2.4).  A face touching a cell with V = 0 is closed.  Writes
- * V, Ax, Ay, Az, col, nrm of `geom`; counts terrain outside [0,(nz-2)dz] into dev_status[3]. */
+ * V, Ax, Ay, Az, col, nrm of `geom`; counts terrain outside [0,(nz-2)dz] into dev_status[3] (for a
+ * raised block, grid.z0 > 0, only non-finite heights count). */
 cc_status cutcell_geometry(const cc_grid *grid, cc_geom *geom, int64_t *dev_status, cc_stream_t stream);
 
 /* Cell merging (Sec. 2.3, Fig. 6): a cell with V > 0 merges when its centre is below the column's
@@ -184,44 +191,85 @@ cc_status cutcell_reduce(const cc_grid *grid, const cc_phys *phys, const cc_geom
                          double *out, cc_stream_t stream);
 
 /* ---------------------------------------------------------------------------------------------
- * Batched blocks (ensembles of independent domains; the building block of the refined hierarchy).
- * Each block is a full uniform grid with its own geometry, base state and three state buffers;
- * a batch steps every block with one update launch and one diagnostic launch per Runge-Kutta
- * stage (load balance over blocks of uneven size: the launch enumerates the tiles of all blocks,
- * Sec. 2.2 and Sec. 2.5 use equal cubes per thread instead).
+ * Batched blocks.  A block is a uniform grid with its own geometry, base state and three state
+ * buffers.  A batch steps all its blocks with one update launch and one diagnostic launch per
+ * Runge-Kutta stage (per level); the launch enumerates the tiles of all blocks, so blocks of uneven
+ * size balance by tile count (the paper gives every thread equal cubes instead, Sec. 2.2, 2.5).
+ *
+ *  - Ensembles (amr_batch_create): independent periodic domains, all of level 0.
+ *  - Refined grids (amr_hierarchy_create, Sec. 2.2): blocks of levels 0..L over one laterally
+ *    periodic domain of domain0[3] level-0 cells; level l has spacing and time step 2^-l of level
+ *    0's.  Each block's grid is a padded box: the block's own cells [ilo, ihi) and ghost cells
+ *    beyond them at the block's resolution (the same terrain, heights relative to the box bottom
+ *    grid.z0).  Own cells of one level do not overlap; own cells of all levels tile the domain
+ *    except buried regions; a coarse cell's eight children lie in one fine block.  Ghost cells are
+ *    integrated on like own cells and refilled: after every stage from same-level blocks (copy);
+ *    after every level-l step, level-l ghosts owned by level l+1 get the eight-point average and
+ *    level-(l+1) ghosts owned by level l get the coarse value (momentum keeps its total value
+ *    across levels, scalars their perturbation from each level's base state).  A level-l step
+ *    follows two level-(l+1) steps (fine first).  Flux matching: the fine fluxes through a
+ *    coarse-fine face, summed over the two fine final stages (x dt_fine), replace dt x the coarse
+ *    flux in the coarse final stage, which conserves mass exactly.  The ghost width must cover the
+ *    stages between refills and the diagnostic reach (6 cells: 2 fine steps x 3 stages); coarse-fine
+ *    interfaces must stay clear of cut and merged cells (counted into dev_status[5] otherwise).
  * ------------------------------------------------------------------------------------------- */
 typedef struct {
     cc_grid grid;
     cc_phys phys;
     cc_geom geom;         /* geometry and merge map of the block (cutcell_geometry/_merge_map) */
     const double *base;   /* base state of the block (cutcell_base_state) */
-    cc_state q[3];        /* three state buffers; the current state starts in q[0] */
+    cc_state q[3];        /* three state buffers; the current state starts in q[0] (the float form
+                             needs rho_lo and rth_lo in all three) */
     int32_t level;        /* refinement level (0 for ensemble members) */
-    int32_t reserved;
+    int32_t org[3];       /* level-l global index of grid cell (0,0,0) (may be negative; x and y
+                             wrap periodically); ignored by amr_batch_create */
+    int32_t ilo[3];       /* the block's own cells are grid cells [ilo, ihi) in each direction; */
+    int32_t ihi[3];       /* the others are ghost cells; ignored by amr_batch_create */
 } cc_block;
 
 typedef struct cc_batch_s *cc_batch;
 
-/* Device workspace (bytes) that holds the descriptors of nblocks blocks. */
+/* Device workspace (bytes) that holds the descriptors of nblocks independent blocks. */
 size_t amr_batch_workspace_bytes(int32_t nblocks, cc_prec prec);
 
-/* Describe nblocks level-0 blocks to the device (copies descriptors into `workspace`, which must
- * stay allocated until amr_batch_destroy; synchronises `stream`).  `tile` selects the update
- * kernel's tile shape as cc_grid.tile does (one shape for the batch).  The handle is host state
- * owned by the caller. */
+/* Describe nblocks level-0 blocks (independent periodic domains) to the device: copies the
+ * descriptors into `workspace`, which must stay allocated until amr_batch_destroy, and synchronises
+ * `stream`.  `tile` selects the update kernel's tile shape as cc_grid.tile does (ids 0, 1, 8, 9; one
+ * shape for the batch; smaller shapes are taken when a block cannot hold it).  The handle is host
+ * state owned by the caller.  Blocks with level != 0 return CC_EINVAL. */
 cc_status amr_batch_create(const cc_block *blocks, int32_t nblocks, cc_prec prec, int32_t tile,
                            void *workspace, cc_batch *out, cc_stream_t stream);
 
-/* nsteps three-stage steps (dt each) of every block of the batch, in place in the blocks' buffers:
- * per stage one update launch over the tiles of all blocks and one diagnostic launch over their
- * columns.  use_graph != 0: the sequence is captured once into a hipGraph (cached per nsteps, dt,
- * starting buffer and status pointer) and replayed as a single graph launch on `stream`.  Device
+/* Workspace (bytes) of a refined grid: descriptors, ghost-refill tables and flux registers.
+ * Validates the layout (CC_EINVAL with the reason in cutcell_last_error). */
+cc_status amr_hierarchy_workspace_bytes(const cc_block *blocks, int32_t nblocks, cc_prec prec,
+                                        const int32_t domain0[3], size_t *bytes);
+
+/* Describe a refined grid (see above) to the device: builds the refill and flux-matching tables on
+ * the host, uploads them with the descriptors into `workspace` (>= the size above; kept until
+ * amr_batch_destroy), clears the flux registers and synchronises `stream`. */
+cc_status amr_hierarchy_create(const cc_block *blocks, int32_t nblocks, cc_prec prec, int32_t tile,
+                               const int32_t domain0[3], void *workspace, size_t workspace_bytes,
+                               cc_batch *out, cc_stream_t stream);
+
+/* Refill every ghost cell of a refined grid from the current states (same level, coarse to fine,
+ * fine to coarse).  Call once after the initial states are set. */
+cc_status amr_hierarchy_sync(cc_batch batch, cc_stream_t stream);
+
+/* nsteps level-0 steps of dt (Sec. 2.2: level l takes 2^l steps of dt 2^-l, finest first), in place
+ * in the blocks' buffers; each step of a level is a three-stage Runge-Kutta step with one update and
+ * one diagnostic launch per stage over the level's blocks, plus refills and flux matching.  Ensembles
+ * have one level.  use_graph != 0: the sequence is captured once into a hipGraph (cached per nsteps,
+ * dt, starting buffers and status pointer) and replayed as a single graph launch on `stream`.  Device
  * conditions are counted into dev_status as for the single-grid calls. */
 cc_status amr_block_step(cc_batch batch, double dt, int32_t nsteps, int32_t use_graph, int64_t *dev_status,
                          cc_stream_t stream);
 
-/* Index (0..2) of the block buffer that holds the current state after the steps so far. */
-int32_t amr_batch_current(cc_batch batch);
+/* Index (0..2) of the buffer holding level `level`'s current state (-1 for a bad level). */
+int32_t amr_batch_current(cc_batch batch, int32_t level);
+
+/* Number of levels of the batch (1 for ensembles). */
+int32_t amr_batch_levels(cc_batch batch);
 
 /* Release the handle (graph executables, capture stream). */
 cc_status amr_batch_destroy(cc_batch batch);

@@ -34,7 +34,7 @@ def build(force: bool = True) -> str:
 
 class _Grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("nsub", C.c_int32),
-                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double)]
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("z0", C.c_double)]
 
 
 class _Phys(C.Structure):
@@ -67,7 +67,7 @@ def lib():
             build(force=True)
         L = C.CDLL(LIB)
         G, P, GM, S = C.POINTER(_Grid), C.POINTER(_Phys), C.POINTER(_Geom), C.POINTER(_State)
-        L.or_base_state.argtypes = [P, C.c_int, C.c_double, _DP, _DP, _DP, _DP]
+        L.or_base_state.argtypes = [P, C.c_int, C.c_double, C.c_double, _DP, _DP, _DP, _DP]
         L.or_geometry.argtypes = [G, GM]
         L.or_merge.argtypes = [G, GM, _I64]
         L.or_merge_direction.argtypes = [C.c_double, C.c_double]
@@ -79,6 +79,8 @@ def lib():
         L.or_tendency.argtypes = [G, P, GM, _DP, _DP, _DP, S, S]
         L.or_tendency_points.argtypes = [G, P, GM, _DP, _DP, _DP, S, _I64, C.c_int64, _DP]
         L.or_rk_stage.argtypes = [G, P, GM, _DP, _DP, _DP, S, S, S, C.c_double, _I64]
+        L.or_rk_update.argtypes = [G, P, GM, _DP, _DP, _DP, S, S, S, C.c_double]
+        L.or_face_flux.argtypes = [G, P, GM, _DP, _DP, _DP, S, C.c_int, C.c_int, C.c_int, C.c_int, _DP]
         L.or_reduce.argtypes = [G, P, GM, _DP, _DP, _DP, S, _DP]
         L.or_run.argtypes = [G, P, GM, _DP, _DP, _DP, S, S, S, C.c_double, C.c_int, _I64]
         L.or_set_threads.argtypes = [C.c_int]
@@ -132,10 +134,10 @@ class Oracle:
         self.H = np.ascontiguousarray(workloads.terrain(cfg) if H is None else H, dtype=np.float64)
         nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
         self.shape = (nx, ny, nz)
-        self.grid = _Grid(nx, ny, nz, cfg.nsub, cfg.dx, cfg.dy, cfg.dz)
+        self.grid = _Grid(nx, ny, nz, cfg.nsub, cfg.dx, cfg.dy, cfg.dz, cfg.z0)
         self.phys = _Phys(cfg.g, cfg.rd, cfg.cp, cfg.p0, cfg.theta0, cfg.bvn, cfg.u0, cfg.v0)
         self.rhob, self.rthb, self.pb, self.thb = (np.zeros(nz) for _ in range(4))
-        lib().or_base_state(C.byref(self.phys), nz, cfg.dz, _p(self.rhob), _p(self.rthb), _p(self.pb),
+        lib().or_base_state(C.byref(self.phys), nz, cfg.dz, cfg.z0, _p(self.rhob), _p(self.rthb), _p(self.pb),
                             _p(self.thb))
         sh3, sh2 = self.shape, (nx, ny)
         self.V, self.Ax, self.Ay, self.Az = (np.zeros(sh3) for _ in range(4))
@@ -223,6 +225,22 @@ class Oracle:
         a, b, c = qn.c(), qs.c(), out.c()
         lib().or_rk_stage(*self._args(), C.byref(a), C.byref(b), C.byref(c), cdt, _p(self.counts, _I64))
         return out
+
+    def rk_update(self, qn: State, qs: State, cdt: float) -> State:
+        """The stage update without the diagnostic pass (non-updated points are zero)."""
+        self._ready()
+        out = State(self.shape)
+        a, b, c = qn.c(), qs.c(), out.c()
+        lib().or_rk_update(*self._args(), C.byref(a), C.byref(b), C.byref(c), cdt)
+        return out
+
+    def face_flux(self, q: State, axis: int, I: int, J: int, K: int) -> np.ndarray:
+        """Total fluxes of rho and rho*theta through the face at the lower side of cell (I,J,K)."""
+        self._ready()
+        F = np.zeros(2)
+        cq = q.c()
+        lib().or_face_flux(*self._args(), C.byref(cq), axis, I, J, K, _p(F))
+        return F
 
     def step(self, q: State, dt: float) -> State:
         q1 = self.rk_stage(q, q, dt / 3.0)

@@ -30,7 +30,7 @@ cc_status launch_status(const char *what)
 
 Dims dims_of(const cc_grid *g)
 {
-    return Dims{g->nx, g->ny, g->nz, g->nzs, g->dx, g->dy, g->dz, g->nsub};
+    return Dims{g->nx, g->ny, g->nz, g->nzs, g->dx, g->dy, g->dz, g->nsub, g->z0};
 }
 
 bool check_grid(const cc_grid *g)
@@ -40,6 +40,7 @@ bool check_grid(const cc_grid *g)
         set_error("grid %dx%dx%d: need nx, ny >= 2 and nz >= 3", g->nx, g->ny, g->nz);
         return false;
     }
+    if (!(g->z0 >= 0.0 && g->z0 < 1e7)) { set_error("grid bottom z0=%g out of range", g->z0); return false; }
     if (g->nzs < g->nz) { set_error("padded stride nzs=%d below nz=%d", g->nzs, g->nz); return false; }
     if (!(g->dx > 0.0 && g->dy > 0.0 && g->dz > 0.0)) { set_error("spacings must be positive"); return false; }
     if (g->nsub < 1 || g->nsub > 1024 || (g->nsub & (g->nsub - 1))) {
@@ -82,6 +83,6 @@ extern "C" cc_status cutcell_check_status(const int64_t *dev_status, int64_t *ho
     if (host[cc::ST_UNMERGEABLE]) return CC_EUNMERGEABLE;
     if (host[cc::ST_NOPLANE]) return CC_ENOPLANE;
     if (host[cc::ST_NONFINITE]) return CC_ENONFINITE;
-    if (host[cc::ST_TERRAIN] || host[cc::ST_GROUPSIZE]) return CC_ETERRAIN;
+    if (host[cc::ST_TERRAIN] || host[cc::ST_GROUPSIZE] || host[cc::ST_INTERFACE]) return CC_ETERRAIN;
     return CC_OK;
 }

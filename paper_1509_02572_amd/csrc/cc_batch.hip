@@ -1,82 +1,563 @@
-// Batched blocks: many grids stepped by one update and one diagnostic launch per Runge-Kutta
-// stage, with the step sequence optionally captured into a hipGraph.
+// Batched blocks: many grids stepped by one update and one diagnostic launch per Runge-Kutta stage
+// and level, with the step sequence optionally captured into a hipGraph.
+//
+// Two kinds of batch share this code:
+//   * ensembles: independent periodic domains, one level;
+//   * refined grids (Sec. 2.2 of the paper): blocks of levels 0..L, level l with spacing and time step
+//     2^-l of level 0's.  Every block is a padded box: its own cells plus ghost cells beyond each
+//     side, at the block's resolution.  The box is stepped as one grid; ghost cells are integrated
+//     on like the block's own cells (the paper integrates on ghost cells instead of interpolating
+//     in time), so the outermost ghost layers go stale by one layer per stage while the block's
+//     own cells stay exact as long as the ghost width covers the stages between refills.
+//     Refills: after every stage a block's ghost cells owned by blocks of the same level are copied
+//     from them; at the end of a level-l step, ghost cells of level l owned by level l+1 receive the
+//     eight-point average of the fine cells, and ghost cells of level l+1 owned by level l receive
+//     the coarse cell's value (Sec. 2.2).  Levels advance fine first: two steps of level l+1, then
+//     one of level l.  Mass is conserved by flux matching: the fine fluxes through a coarse-fine
+//     interface, accumulated over the fine final stages, replace the coarse flux of the coarse
+//     final stage (the only stage that carries q^n to q^{n+1}).
 #pragma clang fp contract(off)
 
+#include <algorithm>
+#include <cmath>
+#include <numeric>
 #include <vector>
 
 #include "cc_kernels.hpp"
 
+namespace cc {
+
+// ghost-cell refill: destination block / box index, source block / box index (block numbers
+// within their levels)
+struct GhostEnt { int32_t dblk, didx, sblk, sidx; };
+// fine side of one coarse-fine face: fine block, axis and the four fine sub-faces, each given as
+// the box index of the cell on the +axis side of the sub-face
+struct FluxSlot { int32_t fblk, axis, idx[4]; };
+// coarse cell with coarse-fine faces: register slot of each face (-x,+x,-y,+y,-z,+z), -1 if none
+struct CorrEnt { int32_t cblk, cidx, slot[6]; };
+
+enum { FILL_COPY = 0, FILL_INJECT = 1, FILL_RESTRICT = 2 };
+
+// ------------------------------------------------------------------------------------------------
+// device: ghost refills
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void put_scalar(const SOut<T> &q, int64_t i, double v0, double v1)
+{
+    T a = (T)v0, b = (T)v1;
+    q.rho[i] = a;
+    q.rth[i] = b;
+    if (q.rho_lo) {
+        q.rho_lo[i] = (T)(v0 - (double)a);
+        q.rth_lo[i] = (T)(v1 - (double)b);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ double get_scalar(const SOut<T> &q, int64_t i, int w)
+{
+    const T *hi = w ? q.rth : q.rho, *lo = w ? q.rth_lo : q.rho_lo;
+    double v = (double)hi[i];
+    if (lo) v += (double)lo[i];
+    return v;
+}
+
+// One ghost cell and the lattice point that shares its index.  Copies within a level move the
+// stored values as they are.  Between levels the scalars (perturbations from each level's base
+// state) move as they are, and momentum at predicted points keeps its total value: the float form
+// stores rho u - rhobar_c(K) U, so the base term of the two levels' lattice levels is exchanged.
+template <typename T>
+__global__ void k_ghost_fill(const BlockDesc<T> *__restrict__ dd, int rd, const BlockDesc<T> *__restrict__ sd, int rs,
+                             const GhostEnt *__restrict__ e, int n, int mode)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const GhostEnt g = e[t];
+    const BlockDesc<T> &D = dd[g.dblk], &S = sd[g.sblk];
+    const SOut<T> qd = D.q[rd], qs = S.q[rs];
+    const int64_t di = g.didx, si = g.sidx;
+    if (mode == FILL_RESTRICT) {
+        const int64_t sx = (int64_t)S.d.ny * S.d.nzs, sy = S.d.nzs;
+        double v[2];
+        for (int w = 0; w < 2; ++w) {
+            double c0 = get_scalar(qs, si, w), c1 = get_scalar(qs, si + sx, w);
+            double c2 = get_scalar(qs, si + sy, w), c3 = get_scalar(qs, si + sx + sy, w);
+            double c4 = get_scalar(qs, si + 1, w), c5 = get_scalar(qs, si + sx + 1, w);
+            double c6 = get_scalar(qs, si + sy + 1, w), c7 = get_scalar(qs, si + sx + sy + 1, w);
+            v[w] = (((c0 + c1) + (c2 + c3)) + ((c4 + c5) + (c6 + c7))) * 0.125;
+        }
+        put_scalar(qd, di, v[0], v[1]);
+    } else {
+        qd.rho[di] = qs.rho[si];
+        qd.rth[di] = qs.rth[si];
+        if (qd.rho_lo) {
+            qd.rho_lo[di] = qs.rho_lo[si];
+            qd.rth_lo[di] = qs.rth_lo[si];
+        }
+    }
+    T mu = qs.mu[si], mv = qs.mv[si], mw = qs.mw[si];
+    if (mode != FILL_COPY && sizeof(T) == 4 && D.G.vcls[di] == CC_PRED && S.G.vcls[si] == CC_PRED) {
+        const int kd = (int)(di % D.d.nzs), ks = (int)(si % S.d.nzs);
+        const double dr = S.P.rhobc[ks] - D.P.rhobc[kd];
+        mu = (T)((double)mu + dr * S.P.ux);
+        mv = (T)((double)mv + dr * S.P.vy);
+    }
+    qd.mu[di] = mu;
+    qd.mv[di] = mv;
+    qd.mw[di] = mw;
+}
+
+// ------------------------------------------------------------------------------------------------
+// device: face fluxes of open regular faces (coarse-fine interfaces lie away from the terrain)
+// ------------------------------------------------------------------------------------------------
+// Total fluxes of rho' and (rho theta)' (kg/s and kg K/s) through the face at the lower side of box
+// cell (i,j,k) along `axis`, positive along +axis.  The perturbation part is evaluated exactly as
+// the update kernel evaluates it (same operands, same order: bitwise the same value); the part
+// carried by the base state and the reference flow (float form only) is added in double.
+template <typename T>
+__device__ void face_total_flux(const BlockDesc<T> &B, const SIn<T> &q, int axis, int i, int j, int k, double F[2],
+                                bool &regular)
+{
+    using R = typename Compute<T>::R;
+    const Dims &d = B.d;
+    const Geo &G = B.G;
+    const Phy &P = B.P;
+    int im = i - (axis == 0), jm = j - (axis == 1), km = k - (axis == 2);
+    int64_t up = cidx(d, i, j, k), lo = cidx(d, im, jm, km);
+    regular = G.cls[up] == CC_OPEN && G.cls[lo] == CC_OPEN && G.gnext[up] == -1 && G.gnext[lo] == -1 &&
+              G.V[up] == 1.0 && G.V[lo] == 1.0;
+    R s4, AS, UAS, b0, b1;
+    double S, Un;
+    if (axis == 0) {
+        R a[3], b[3], c[3], e[3];
+        lat_vel<T>(d, G, P, q, i, j, k, a); lat_vel<T>(d, G, P, q, i, j + 1, k, b);
+        lat_vel<T>(d, G, P, q, i, j, k + 1, c); lat_vel<T>(d, G, P, q, i, j + 1, k + 1, e);
+        s4 = (a[0] + b[0]) + (c[0] + e[0]);
+        S = d.dy * d.dz; Un = P.ux;
+        AS = (R)(0.25 * 1.0 * S); UAS = (R)(P.ux * 1.0 * S);
+        b0 = (R)P.rhob[k]; b1 = (R)P.rthb[k];
+    } else if (axis == 1) {
+        R a[3], b[3], c[3], e[3];
+        lat_vel<T>(d, G, P, q, i, j, k, a); lat_vel<T>(d, G, P, q, i + 1, j, k, b);
+        lat_vel<T>(d, G, P, q, i, j, k + 1, c); lat_vel<T>(d, G, P, q, i + 1, j, k + 1, e);
+        s4 = (a[1] + b[1]) + (c[1] + e[1]);
+        S = d.dz * d.dx; Un = P.vy;
+        AS = (R)(0.25 * 1.0 * S); UAS = (R)(P.vy * 1.0 * S);
+        b0 = (R)P.rhob[k]; b1 = (R)P.rthb[k];
+    } else {
+        R a[3], b[3], c[3], e[3];
+        lat_vel<T>(d, G, P, q, i, j, k, a); lat_vel<T>(d, G, P, q, i + 1, j, k, b);
+        lat_vel<T>(d, G, P, q, i, j + 1, k, c); lat_vel<T>(d, G, P, q, i + 1, j + 1, k, e);
+        s4 = (a[2] + b[2]) + (c[2] + e[2]);
+        S = d.dx * d.dy; Un = 0.0;
+        AS = (R)(0.25 * 1.0 * S); UAS = (R)0;
+        b0 = (R)P.rhobc[k]; b1 = (R)(k > 0 ? 0.5 * (P.rthb[k - 1] + P.rthb[k]) : P.rthb[0]);
+    }
+    R f0, f1;
+    scalar_face_flux<R>(s4, AS, UAS, b0, b1, (R)q.rho[lo], (R)q.rho[up], (R)q.rth[lo], (R)q.rth[up], f0, f1);
+    // base-state / reference-flow part (zero in the double form, where Un = 0)
+    double h0 = axis == 2 ? 0.0 : P.rhob[k] * Un * S, h1 = axis == 2 ? 0.0 : P.rthb[k] * Un * S;
+    F[0] = (double)f0 + h0;
+    F[1] = (double)f1 + h1;
+}
+
+// fine side: after a fine final stage, add dt_f x (sum of the four sub-face fluxes) to each slot
+template <typename T>
+__global__ void k_flux_accumulate(const BlockDesc<T> *__restrict__ fd, int rs, const FluxSlot *__restrict__ sl,
+                                  int n, double dtf, double *__restrict__ reg, int64_t *st)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const FluxSlot s = sl[t];
+    const BlockDesc<T> &B = fd[s.fblk];
+    const SIn<T> q = as_in(B.q[rs]);
+    double a0 = 0.0, a1 = 0.0;
+    bool ok = true;
+    for (int f = 0; f < 4; ++f) {
+        int i, j, k;
+        unidx(B.d, s.idx[f], i, j, k);
+        double F[2];
+        bool reg_ok;
+        face_total_flux<T>(B, q, s.axis, i, j, k, F, reg_ok);
+        ok = ok && reg_ok;
+        a0 += F[0];
+        a1 += F[1];
+    }
+    reg[2 * t] += dtf * a0;
+    reg[2 * t + 1] += dtf * a1;
+    if (!ok) count_status(st, ST_INTERFACE);
+}
+
+// coarse side: after the coarse final stage, replace dt x (coarse face flux) by the accumulated
+// fine fluxes in every coarse cell with coarse-fine faces, then clear the slots
+template <typename T>
+__global__ void k_flux_correct(const BlockDesc<T> *__restrict__ cd, int rs, int ro, const CorrEnt *__restrict__ ce,
+                               int n, double dt, double *__restrict__ reg, int64_t *st)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const CorrEnt e = ce[t];
+    const BlockDesc<T> &B = cd[e.cblk];
+    const SIn<T> q = as_in(B.q[rs]);
+    int i, j, k;
+    unidx(B.d, e.cidx, i, j, k);
+    double c0 = 0.0, c1 = 0.0;
+    bool ok = true;
+    for (int f = 0; f < 6; ++f) {
+        int r = e.slot[f];
+        if (r < 0) continue;
+        int axis = f >> 1, plus = f & 1;
+        double F[2];
+        bool reg_ok;
+        face_total_flux<T>(B, q, axis, i + (plus && axis == 0), j + (plus && axis == 1), k + (plus && axis == 2), F,
+                           reg_ok);
+        ok = ok && reg_ok;
+        double sg = plus ? 1.0 : -1.0;
+        c0 += sg * (dt * F[0] - reg[2 * r]);
+        c1 += sg * (dt * F[1] - reg[2 * r + 1]);
+        reg[2 * r] = 0.0;
+        reg[2 * r + 1] = 0.0;
+    }
+    const SOut<T> &qo = B.q[ro];
+    double vol = B.G.Vgroup[e.cidx] * B.P.dV;
+    double v0 = get_scalar(qo, e.cidx, 0) + c0 / vol;
+    double v1 = get_scalar(qo, e.cidx, 1) + c1 / vol;
+    put_scalar(qo, e.cidx, v0, v1);
+    if (!ok) count_status(st, ST_INTERFACE);
+}
+
+}  // namespace cc
+
 using namespace cc;
 
 // ------------------------------------------------------------------------------------------------
-// batched blocks: descriptors, stepping, graph capture
+// host: batch state
 // ------------------------------------------------------------------------------------------------
+struct Level {
+    int nblk = 0, ntiles = 0, ncols = 0, cur = 0;
+    size_t desc_off = 0;
+    size_t same_off = 0, inj_off = 0, res_off = 0, slot_off = 0, corr_off = 0, reg_off = 0;
+    int nsame = 0, ninj = 0, nres = 0, nslot = 0, ncorr = 0;
+};
+
 struct cc_batch_s {
     cc_prec prec;
-    int nblk = 0, ntiles = 0, ncols = 0, tile = 0;
-    void *desc = nullptr;            // device descriptors (caller workspace)
-    std::vector<char> host;          // host image of the descriptors
-    int cur = 0;                     // buffer index holding the current state
-    hipStream_t cap = nullptr;       // private stream used only for graph capture
-    struct Graph { int nsteps, cur; double dt; int64_t *st; hipGraphExec_t exec; };
+    int tile = 0;
+    char *ws = nullptr;  // caller workspace: descriptors, refill tables, flux registers
+    std::vector<Level> lev;
+    hipStream_t cap = nullptr;  // private stream used only for graph capture
+    struct Graph { int nsteps; double dt; int64_t *st; std::vector<int> cur0, cur1; hipGraphExec_t exec; };
     std::vector<Graph> graphs;
 };
 
-namespace cc {
+namespace {
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+template <typename T>
+const BlockDesc<T> *descs(const cc_batch_s *b, int l) { return (const BlockDesc<T> *)(b->ws + b->lev[l].desc_off); }
 
 template <typename T, int TX, int TY, int TZ, int MINW>
-static void launch_batch_stage(const cc_batch_s *b, int rn, int rs, int ro, double cdt, int fin, int64_t *st,
-                               hipStream_t s)
+void launch_batch_stage(const cc_batch_s *b, int l, int rn, int rs, int ro, double cdt, int fin, int64_t *st,
+                        hipStream_t s)
 {
-    hipLaunchKernelGGL((k_stage_batch<T, TX, TY, TZ, 0, MINW>), dim3(b->ntiles), dim3(TX * TY * TZ), 0, s,
-                       (const BlockDesc<T> *)b->desc, b->nblk, b->ntiles, rn, rs, ro, cdt, fin, st);
+    const Level &L = b->lev[l];
+    hipLaunchKernelGGL((k_stage_batch<T, TX, TY, TZ, 0, MINW>), dim3(L.ntiles), dim3(TX * TY * TZ), 0, s,
+                       descs<T>(b, l), L.nblk, L.ntiles, rn, rs, ro, cdt, fin, st);
 }
 
 template <typename T>
-static void batch_stage(const cc_batch_s *b, int rn, int rs, int ro, double cdt, int fin, int64_t *st, hipStream_t s)
+void fill(const cc_batch_s *b, int ld, int ls, size_t off, int n, int mode, hipStream_t s)
 {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_ghost_fill<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, descs<T>(b, ld), b->lev[ld].cur,
+                       descs<T>(b, ls), b->lev[ls].cur, (const GhostEnt *)(b->ws + off), n, mode);
+}
+
+// one Runge-Kutta stage of level l: update, flux matching in the final stage, diagnostics, then
+// same-level ghost refill of the stage output
+template <typename T>
+void level_stage(cc_batch_s *b, int l, int rn, int rs, int ro, double cdt, int fin, double dt, int64_t *st,
+                 hipStream_t s)
+{
+    const Level &L = b->lev[l];
     switch (b->tile) {
-    case 1: launch_batch_stage<T, 4, 4, 16, 1>(b, rn, rs, ro, cdt, fin, st, s); break;
-    case 8: launch_batch_stage<T, 2, 2, 64, 1>(b, rn, rs, ro, cdt, fin, st, s); break;
-    case 9: launch_batch_stage<T, 8, 8, 8, 6>(b, rn, rs, ro, cdt, fin, st, s); break;
-    default: launch_batch_stage<T, 8, 8, 8, 1>(b, rn, rs, ro, cdt, fin, st, s); break;
+    case 1: launch_batch_stage<T, 4, 4, 16, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
+    case 8: launch_batch_stage<T, 2, 2, 64, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
+    case 9: launch_batch_stage<T, 8, 8, 8, 6>(b, l, rn, rs, ro, cdt, fin, st, s); break;
+    default: launch_batch_stage<T, 8, 8, 8, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
     }
-    hipLaunchKernelGGL(k_diagnose_batch<T>, dim3(blocks_for(b->ncols, 64)), dim3(64), 0, s,
-                       (const BlockDesc<T> *)b->desc, b->nblk, b->ncols, ro, st);
+    if (fin) {
+        if (l > 0 && b->lev[l - 1].nslot > 0) {  // this level is the fine side of level l-1's interfaces
+            const Level &C = b->lev[l - 1];
+            hipLaunchKernelGGL(k_flux_accumulate<T>, dim3(blocks_for(C.nslot, 64)), dim3(64), 0, s, descs<T>(b, l), rs,
+                               (const FluxSlot *)(b->ws + C.slot_off), C.nslot, dt, (double *)(b->ws + C.reg_off), st);
+        }
+        if (L.ncorr > 0)
+            hipLaunchKernelGGL(k_flux_correct<T>, dim3(blocks_for(L.ncorr, 64)), dim3(64), 0, s, descs<T>(b, l), rs, ro,
+                               (const CorrEnt *)(b->ws + L.corr_off), L.ncorr, dt, (double *)(b->ws + L.reg_off), st);
+    }
+    hipLaunchKernelGGL(k_diagnose_batch<T>, dim3(blocks_for(L.ncols, 64)), dim3(64), 0, s, descs<T>(b, l), L.nblk,
+                       L.ncols, ro, st);
+    if (L.nsame > 0) {
+        hipLaunchKernelGGL(k_ghost_fill<T>, dim3(blocks_for(L.nsame, 256)), dim3(256), 0, s, descs<T>(b, l), ro,
+                           descs<T>(b, l), ro, (const GhostEnt *)(b->ws + L.same_off), L.nsame, (int)FILL_COPY);
+    }
 }
 
-// nsteps three-stage steps of every block, rotating the three buffers (the state of step n is in
-// buffer cur; the stages write the other two)
-static void batch_enqueue(cc_batch_s *b, double dt, int nsteps, int64_t *st, hipStream_t s)
+// one step of level l (dt), preceded by two steps of level l+1 and followed by the exchange with it
+template <typename T>
+void level_step(cc_batch_s *b, int l, double dt, int64_t *st, hipStream_t s)
 {
-    for (int n = 0; n < nsteps; ++n) {
-        int a = b->cur, o = 1 - b->cur, c = 2;
-        if (b->prec == CC_F64) {
-            batch_stage<double>(b, a, a, o, dt / 3.0, 0, st, s);
-            batch_stage<double>(b, a, o, c, dt / 2.0, 0, st, s);
-            batch_stage<double>(b, a, c, o, dt, 1, st, s);
-        } else {
-            batch_stage<float>(b, a, a, o, dt / 3.0, 0, st, s);
-            batch_stage<float>(b, a, o, c, dt / 2.0, 0, st, s);
-            batch_stage<float>(b, a, c, o, dt, 1, st, s);
-        }
-        b->cur = o;
+    int nl = (int)b->lev.size();
+    if (l + 1 < nl) {
+        level_step<T>(b, l + 1, 0.5 * dt, st, s);
+        level_step<T>(b, l + 1, 0.5 * dt, st, s);
+    }
+    Level &L = b->lev[l];
+    int a = L.cur, o = 1 - L.cur, c = 2;
+    level_stage<T>(b, l, a, a, o, dt / 3.0, 0, dt, st, s);
+    level_stage<T>(b, l, a, o, c, dt / 2.0, 0, dt, st, s);
+    level_stage<T>(b, l, a, c, o, dt, 1, dt, st, s);
+    L.cur = o;
+    if (l + 1 < nl) {
+        fill<T>(b, l, l + 1, L.res_off, L.nres, FILL_RESTRICT, s);             // level l <- level l+1
+        fill<T>(b, l + 1, l, b->lev[l + 1].inj_off, b->lev[l + 1].ninj, FILL_INJECT, s);  // level l+1 <- level l
     }
 }
 
 template <typename T>
-static bool build_descs(const cc_block *blocks, int nblk, cc_prec prec, int TX, int TY, int TZ, cc_batch_s *b)
+void batch_enqueue(cc_batch_s *b, double dt, int nsteps, int64_t *st, hipStream_t s)
 {
-    b->host.assign(sizeof(BlockDesc<T>) * nblk, 0);
-    BlockDesc<T> *h = (BlockDesc<T> *)b->host.data();
+    for (int n = 0; n < nsteps; ++n) level_step<T>(b, 0, dt, st, s);
+}
+
+void enqueue(cc_batch_s *b, double dt, int nsteps, int64_t *st, hipStream_t s)
+{
+    if (b->prec == CC_F64) batch_enqueue<double>(b, dt, nsteps, st, s);
+    else batch_enqueue<float>(b, dt, nsteps, st, s);
+}
+
+// all ghost cells from the current states: same level, coarse-to-fine and fine-to-coarse
+template <typename T>
+void sync_all(cc_batch_s *b, hipStream_t s)
+{
+    int nl = (int)b->lev.size();
+    for (int l = 0; l < nl; ++l) {
+        const Level &L = b->lev[l];
+        fill<T>(b, l, l, L.same_off, L.nsame, FILL_COPY, s);
+        if (l + 1 < nl) fill<T>(b, l, l + 1, L.res_off, L.nres, FILL_RESTRICT, s);
+        if (l > 0) fill<T>(b, l, l - 1, L.inj_off, L.ninj, FILL_INJECT, s);
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// host: descriptors and refill / flux-matching tables
+// ------------------------------------------------------------------------------------------------
+struct Tables {
+    std::vector<std::vector<int>> members;  // block ids per level
+    std::vector<int> local;                 // block id -> number within its level
+    std::vector<std::vector<GhostEnt>> same, inj, res;
+    std::vector<std::vector<FluxSlot>> slots;
+    std::vector<std::vector<CorrEnt>> corr;
+};
+
+inline int64_t pmod(int64_t a, int64_t n) { a %= n; return a < 0 ? a + n : a; }
+
+// owner map of one level: the block number owning each unit box of the level's cells
+struct OwnerMap {
+    int64_t N[3] = {0, 0, 0}, u[3] = {1, 1, 1}, nu[3] = {0, 0, 0};
+    std::vector<int32_t> own;
+    int at(int64_t x, int64_t y, int64_t z) const  // x, y periodic; z must be in range
+    {
+        if (z < 0 || z >= N[2]) return -1;
+        x = pmod(x, N[0]); y = pmod(y, N[1]);
+        return own[((x / u[0]) * nu[1] + y / u[1]) * nu[2] + z / u[2]];
+    }
+};
+
+bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, const char *what)
+{
+    int nl = 0;
+    for (int m = 0; m < n; ++m) {
+        if (B[m].level < 0 || B[m].level > 12) { set_error("%s: block %d has level %d", what, m, B[m].level); return false; }
+        nl = std::max(nl, B[m].level + 1);
+    }
+    t.members.assign(nl, {});
+    t.local.assign(n, 0);
+    for (int m = 0; m < n; ++m) {
+        t.local[m] = (int)t.members[B[m].level].size();
+        t.members[B[m].level].push_back(m);
+    }
+    for (int l = 0; l < nl; ++l)
+        if (t.members[l].empty()) { set_error("%s: no block on level %d", what, l); return false; }
+    const cc_block &R0 = B[t.members[0][0]];
+    std::vector<OwnerMap> om(nl);
+    for (int l = 0; l < nl; ++l) {
+        OwnerMap &M = om[l];
+        for (int a = 0; a < 3; ++a) {
+            M.N[a] = (int64_t)dom0[a] << l;
+            int64_t g = 0;
+            for (int m : t.members[l]) {
+                const cc_block &b = B[m];
+                g = std::gcd(g, (int64_t)(b.org[a] + b.ilo[a]));
+                g = std::gcd(g, (int64_t)(b.ihi[a] - b.ilo[a]));
+            }
+            g = std::gcd(g, M.N[a]);
+            M.u[a] = g > 0 ? g : 1;
+            M.nu[a] = M.N[a] / M.u[a];
+        }
+        M.own.assign((size_t)(M.nu[0] * M.nu[1] * M.nu[2]), -1);
+        double f = (double)(1 << l);
+        for (int m : t.members[l]) {
+            const cc_block &b = B[m];
+            const int box[3] = {b.grid.nx, b.grid.ny, b.grid.nz};
+            const double sp[3] = {b.grid.dx, b.grid.dy, b.grid.dz}, sp0[3] = {R0.grid.dx, R0.grid.dy, R0.grid.dz};
+            for (int a = 0; a < 3; ++a) {
+                int64_t g0 = b.org[a] + b.ilo[a], g1 = b.org[a] + b.ihi[a];
+                if (b.ilo[a] < 0 || b.ihi[a] > box[a] || b.ilo[a] >= b.ihi[a] || g0 < 0 || g1 > M.N[a]) {
+                    set_error("%s: block %d: own cells [%d,%d) of a %d-cell box at origin %d leave the level-%d "
+                              "domain of %lld cells", what, m, b.ilo[a], b.ihi[a], box[a], b.org[a], l, (long long)M.N[a]);
+                    return false;
+                }
+                if (std::fabs(sp[a] * f - sp0[a]) > 1e-9 * sp0[a]) {
+                    set_error("%s: block %d: spacing %g is not 2^-%d of level 0's %g", what, m, sp[a], l, sp0[a]);
+                    return false;
+                }
+            }
+            for (int64_t x = b.org[0] + b.ilo[0]; x < b.org[0] + b.ihi[0]; x += M.u[0])
+                for (int64_t y = b.org[1] + b.ilo[1]; y < b.org[1] + b.ihi[1]; y += M.u[1])
+                    for (int64_t z = b.org[2] + b.ilo[2]; z < b.org[2] + b.ihi[2]; z += M.u[2]) {
+                        int32_t &o = M.own[((x / M.u[0]) * M.nu[1] + y / M.u[1]) * M.nu[2] + z / M.u[2]];
+                        if (o >= 0) { set_error("%s: blocks %d and %d overlap on level %d", what, t.members[l][o], m, l); return false; }
+                        o = t.local[m];
+                    }
+        }
+    }
+    // box index of global level-l cell g inside block m (g lies in m's own cells)
+    auto box_index = [&](int m, int l, const int64_t g[3]) -> int32_t {
+        const cc_block &b = B[m];
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a) c[a] = b.ilo[a] + pmod(g[a] - (b.org[a] + b.ilo[a]), om[l].N[a]);
+        return (int32_t)((c[0] * b.grid.ny + c[1]) * b.grid.nzs + c[2]);
+    };
+    t.same.assign(nl, {}); t.inj.assign(nl, {}); t.res.assign(nl, {});
+    t.slots.assign(nl, {}); t.corr.assign(nl, {});
+    for (int l = 0; l < nl; ++l) {
+        for (int m : t.members[l]) {
+            const cc_block &b = B[m];
+            for (int i = 0; i < b.grid.nx; ++i)
+                for (int j = 0; j < b.grid.ny; ++j)
+                    for (int k = 0; k < b.grid.nz; ++k) {
+                        if (i >= b.ilo[0] && i < b.ihi[0] && j >= b.ilo[1] && j < b.ihi[1] && k >= b.ilo[2] && k < b.ihi[2])
+                            continue;
+                        int64_t g[3] = {pmod(b.org[0] + i, om[l].N[0]), pmod(b.org[1] + j, om[l].N[1]), (int64_t)b.org[2] + k};
+                        if (g[2] < 0 || g[2] >= om[l].N[2]) continue;
+                        int32_t didx = (int32_t)(((int64_t)i * b.grid.ny + j) * b.grid.nzs + k);
+                        int o = om[l].at(g[0], g[1], g[2]);
+                        if (o >= 0) {
+                            t.same[l].push_back({t.local[m], didx, o, box_index(t.members[l][o], l, g)});
+                            continue;
+                        }
+                        if (l > 0) {
+                            int64_t gc[3] = {g[0] >> 1, g[1] >> 1, g[2] >> 1};
+                            int oc = om[l - 1].at(gc[0], gc[1], gc[2]);
+                            if (oc >= 0) {
+                                t.inj[l].push_back({t.local[m], didx, oc, box_index(t.members[l - 1][oc], l - 1, gc)});
+                                continue;
+                            }
+                        }
+                        if (l + 1 < nl) {
+                            int64_t gf[3] = {2 * g[0], 2 * g[1], 2 * g[2]};
+                            int of = om[l + 1].at(gf[0], gf[1], gf[2]);
+                            if (of >= 0) {
+                                for (int c = 1; c < 8; ++c)
+                                    if (om[l + 1].at(gf[0] + (c >> 2), gf[1] + ((c >> 1) & 1), gf[2] + (c & 1)) != of) {
+                                        set_error("%s: the children of level-%d cell (%lld,%lld,%lld) are split between "
+                                                  "blocks", what, l, (long long)g[0], (long long)g[1], (long long)g[2]);
+                                        return false;
+                                    }
+                                t.res[l].push_back({t.local[m], didx, of, box_index(t.members[l + 1][of], l + 1, gf)});
+                            }
+                        }
+                    }
+        }
+        if (l + 1 >= nl) continue;
+        // coarse-fine faces of level l's own cells
+        for (int m : t.members[l]) {
+            const cc_block &b = B[m];
+            for (int i = b.ilo[0]; i < b.ihi[0]; ++i)
+                for (int j = b.ilo[1]; j < b.ihi[1]; ++j)
+                    for (int k = b.ilo[2]; k < b.ihi[2]; ++k) {
+                        CorrEnt ce{t.local[m], (int32_t)(((int64_t)i * b.grid.ny + j) * b.grid.nzs + k), {-1, -1, -1, -1, -1, -1}};
+                        bool any = false;
+                        const int64_t g[3] = {(int64_t)b.org[0] + i, (int64_t)b.org[1] + j, (int64_t)b.org[2] + k};
+                        for (int f = 0; f < 6; ++f) {
+                            int a = f >> 1, sg = (f & 1) ? 1 : -1;
+                            int64_t gn[3] = {g[0], g[1], g[2]};
+                            gn[a] += sg;
+                            if (a == 2 && (gn[2] < 0 || gn[2] >= om[l].N[2])) continue;
+                            if (om[l].at(gn[0], gn[1], gn[2]) >= 0) continue;
+                            int64_t gf[3] = {2 * gn[0], 2 * gn[1], 2 * gn[2]};
+                            int of = om[l + 1].at(gf[0], gf[1], gf[2]);
+                            if (of < 0) continue;
+                            int fb = t.members[l + 1][of];
+                            const cc_block &F = B[fb];
+                            FluxSlot fs{of, a, {0, 0, 0, 0}};
+                            int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;  // the two other axes, increasing
+                            for (int s = 0; s < 4; ++s) {
+                                int64_t c[3];
+                                c[a] = gf[a] + (sg > 0 ? 0 : 1);  // the fine child next to the face
+                                c[b1] = gf[b1] + (s & 1);
+                                c[b2] = gf[b2] + (s >> 1);
+                                if (om[l + 1].at(c[0], c[1], c[2]) != of) {
+                                    set_error("%s: coarse-fine face of level-%d cell (%lld,%lld,%lld) has sub-faces in "
+                                              "several fine blocks", what, l, (long long)g[0], (long long)g[1], (long long)g[2]);
+                                    return false;
+                                }
+                                int32_t ci = box_index(fb, l + 1, c);
+                                if (sg < 0) {  // the face is at the child's upper side: take the cell above it
+                                    int64_t stride = a == 0 ? (int64_t)F.grid.ny * F.grid.nzs : (a == 1 ? F.grid.nzs : 1);
+                                    ci = (int32_t)(ci + stride);
+                                    int cc3[3] = {(int)(ci / ((int64_t)F.grid.ny * F.grid.nzs)), (int)((ci / F.grid.nzs) % F.grid.ny),
+                                                  (int)(ci % F.grid.nzs)};
+                                    const int fbox[3] = {F.grid.nx, F.grid.ny, F.grid.nz};
+                                    if (cc3[a] >= fbox[a]) {
+                                        set_error("%s: fine block %d has no ghost cell beyond its side", what, fb);
+                                        return false;
+                                    }
+                                }
+                                fs.idx[s] = ci;
+                            }
+                            ce.slot[f] = (int32_t)t.slots[l].size();
+                            t.slots[l].push_back(fs);
+                            any = true;
+                        }
+                        if (any) t.corr[l].push_back(ce);
+                    }
+        }
+    }
+    return true;
+}
+
+template <typename T>
+bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, int TX, int TY, int TZ,
+                 std::vector<char> &host, Level &L, const char *what)
+{
+    host.assign(sizeof(BlockDesc<T>) * ids.size(), 0);
+    BlockDesc<T> *h = (BlockDesc<T> *)host.data();
     int tiles = 0, cols = 0;
-    for (int m = 0; m < nblk; ++m) {
-        const cc_block &B = blocks[m];
+    for (size_t m = 0; m < ids.size(); ++m) {
+        const cc_block &b = B[ids[m]];
         Dims d; Geo G; Phy P;
-        if (!make_views("amr_batch_create", &B.grid, &B.phys, &B.geom, B.base, prec, d, G, P)) return false;
+        if (!make_views(what, &b.grid, &b.phys, &b.geom, b.base, prec, d, G, P)) return false;
         for (int r = 0; r < 3; ++r) {
-            if (!state_ok("amr_batch_create", &B.q[r])) return false;
-            h[m].q[r] = sout_of<T>(const_cast<cc_state *>(&B.q[r]));
+            if (!state_ok(what, &b.q[r])) return false;
+            if (sizeof(T) == 4 && (!b.q[r].rho_lo || !b.q[r].rth_lo)) {
+                set_error("%s: the float form of a batch needs the low-order state arrays", what);
+                return false;
+            }
+            h[m].q[r] = sout_of<T>(const_cast<cc_state *>(&b.q[r]));
         }
         h[m].d = d; h[m].G = G; h[m].P = P;
         h[m].nbx = (d.nx + TX - 1) / TX; h[m].nby = (d.ny + TY - 1) / TY; h[m].nbz = (d.nz + TZ - 1) / TZ;
@@ -85,87 +566,199 @@ static bool build_descs(const cc_block *blocks, int nblk, cc_prec prec, int TX, 
         tiles += h[m].nbx * h[m].nby * h[m].nbz;
         cols += d.nx * d.ny;
     }
-    b->ntiles = tiles;
-    b->ncols = cols;
+    L.nblk = (int)ids.size();
+    L.ntiles = tiles;
+    L.ncols = cols;
     return true;
 }
 
-}  // namespace cc
+// tile shape of a batch: the requested one if every block holds a tile in x and y
+int batch_tile(const cc_block *B, int n, int tile, int &TX, int &TY, int &TZ)
+{
+    auto fits = [&](int tx, int ty) {
+        for (int m = 0; m < n; ++m)
+            if (B[m].grid.nx < tx || B[m].grid.ny < ty) return false;
+        return true;
+    };
+    int id = (tile == 1 || tile == 8 || tile == 9) ? tile : 0;
+    auto shape = [&](int i) {
+        TX = i == 1 ? 4 : (i == 8 ? 2 : 8); TY = TX; TZ = i == 1 ? 16 : (i == 8 ? 64 : 8);
+    };
+    shape(id);
+    if (!fits(TX, TY)) { id = fits(4, 4) ? 1 : 8; shape(id); }
+    return id;
+}
 
+// layout of the workspace and (when `b` is given) the host images to upload
+struct Plan {
+    size_t bytes = 0;
+    std::vector<std::vector<char>> desc;
+};
+
+bool plan_batch(const cc_block *B, int n, cc_prec prec, int tile, const Tables &t, cc_batch_s *b, Plan &plan,
+                const char *what)
+{
+    int TX, TY, TZ;
+    int id = batch_tile(B, n, tile, TX, TY, TZ);
+    int nl = (int)t.members.size();
+    std::vector<Level> lev(nl);
+    plan.desc.assign(nl, {});
+    size_t off = 0;
+    for (int l = 0; l < nl; ++l) {
+        bool ok = prec == CC_F64 ? build_descs<double>(B, t.members[l], prec, TX, TY, TZ, plan.desc[l], lev[l], what)
+                                 : build_descs<float>(B, t.members[l], prec, TX, TY, TZ, plan.desc[l], lev[l], what);
+        if (!ok) return false;
+        lev[l].desc_off = off;
+        off = align256(off + plan.desc[l].size());
+    }
+    for (int l = 0; l < nl; ++l) {
+        Level &L = lev[l];
+        L.nsame = (int)t.same[l].size(); L.same_off = off; off = align256(off + sizeof(GhostEnt) * L.nsame);
+        L.ninj = (int)t.inj[l].size(); L.inj_off = off; off = align256(off + sizeof(GhostEnt) * L.ninj);
+        L.nres = (int)t.res[l].size(); L.res_off = off; off = align256(off + sizeof(GhostEnt) * L.nres);
+        L.nslot = (int)t.slots[l].size(); L.slot_off = off; off = align256(off + sizeof(FluxSlot) * L.nslot);
+        L.ncorr = (int)t.corr[l].size(); L.corr_off = off; off = align256(off + sizeof(CorrEnt) * L.ncorr);
+        L.reg_off = off; off = align256(off + sizeof(double) * 2 * L.nslot);
+    }
+    plan.bytes = off;
+    if (b) {
+        b->prec = prec;
+        b->tile = id;
+        b->lev = lev;
+    }
+    return true;
+}
+
+bool upload(cc_batch_s *b, const Plan &plan, const Tables *t, hipStream_t s, const char *what)
+{
+    hipError_t e = hipSuccess;
+    int nl = (int)b->lev.size();
+    for (int l = 0; l < nl && e == hipSuccess; ++l) {
+        const Level &L = b->lev[l];
+        e = hipMemcpyAsync(b->ws + L.desc_off, plan.desc[l].data(), plan.desc[l].size(), hipMemcpyHostToDevice, s);
+        if (!t) continue;
+        auto put = [&](size_t off, const void *p, size_t nb) {
+            if (e == hipSuccess && nb) e = hipMemcpyAsync(b->ws + off, p, nb, hipMemcpyHostToDevice, s);
+        };
+        put(L.same_off, t->same[l].data(), sizeof(GhostEnt) * L.nsame);
+        put(L.inj_off, t->inj[l].data(), sizeof(GhostEnt) * L.ninj);
+        put(L.res_off, t->res[l].data(), sizeof(GhostEnt) * L.nres);
+        put(L.slot_off, t->slots[l].data(), sizeof(FluxSlot) * L.nslot);
+        put(L.corr_off, t->corr[l].data(), sizeof(CorrEnt) * L.ncorr);
+        if (e == hipSuccess && L.nslot) e = hipMemsetAsync(b->ws + L.reg_off, 0, sizeof(double) * 2 * L.nslot, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host images are freed on return
+    if (e != hipSuccess) { set_error("%s: %s", what, hipGetErrorString(e)); return false; }
+    return true;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------------
+// entry points
+// ------------------------------------------------------------------------------------------------
 extern "C" size_t amr_batch_workspace_bytes(int32_t nblocks, cc_prec prec)
 {
-    size_t one = prec == CC_F64 ? sizeof(cc::BlockDesc<double>) : sizeof(cc::BlockDesc<float>);
-    return (one * (size_t)(nblocks > 0 ? nblocks : 0) + 255) / 256 * 256;
+    size_t one = prec == CC_F64 ? sizeof(BlockDesc<double>) : sizeof(BlockDesc<float>);
+    return align256(one * (size_t)(nblocks > 0 ? nblocks : 0));
 }
 
 extern "C" cc_status amr_batch_create(const cc_block *blocks, int32_t nblocks, cc_prec prec, int32_t tile,
                                       void *workspace, cc_batch *out, cc_stream_t stream)
 {
-    using namespace cc;
     CC_REQUIRE(blocks && nblocks > 0 && workspace && out, "amr_batch_create: null or empty argument");
     CC_REQUIRE(prec == CC_F64 || prec == CC_F32_PERT, "amr_batch_create: unknown precision");
-    for (int m = 0; m < nblocks; ++m) {
-        CC_REQUIRE(blocks[m].level == 0, "amr_batch_create: block %d has level %d; a batch holds level-0 blocks only",
-                  m, blocks[m].level);
-    }
-    // one tile shape for the whole batch; every block must hold a tile in x and y
-    int id = tile;
-    auto fits = [&](int tx, int ty) {
-        for (int m = 0; m < nblocks; ++m)
-            if (blocks[m].grid.nx < tx || blocks[m].grid.ny < ty) return false;
-        return true;
-    };
-    if (id != 1 && id != 8 && id != 9) id = 0;
-    int TX = id == 1 ? 4 : (id == 8 ? 2 : 8), TY = TX, TZ = id == 1 ? 16 : (id == 8 ? 64 : 8);
-    if (!fits(TX, TY)) { id = fits(4, 4) ? 1 : 8; TX = id == 1 ? 4 : 2; TY = TX; TZ = id == 1 ? 16 : 64; }
+    for (int m = 0; m < nblocks; ++m)
+        CC_REQUIRE(blocks[m].level == 0, "amr_batch_create: block %d has level %d; a batch of independent domains "
+                                         "holds level-0 blocks only (refined grids: amr_hierarchy_create)", m, blocks[m].level);
+    Tables t;
+    t.members.assign(1, {});
+    for (int m = 0; m < nblocks; ++m) t.members[0].push_back(m);
+    t.same.assign(1, {}); t.inj.assign(1, {}); t.res.assign(1, {}); t.slots.assign(1, {}); t.corr.assign(1, {});
     cc_batch_s *b = new cc_batch_s();
-    b->prec = prec;
-    b->nblk = nblocks;
-    b->tile = id;
-    b->desc = workspace;
-    bool ok = prec == CC_F64 ? build_descs<double>(blocks, nblocks, prec, TX, TY, TZ, b)
-                             : build_descs<float>(blocks, nblocks, prec, TX, TY, TZ, b);
-    if (!ok) { delete b; return CC_EINVAL; }
-    hipError_t e = hipMemcpyAsync(workspace, b->host.data(), b->host.size(), hipMemcpyHostToDevice, (hipStream_t)stream);
-    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
-    if (e != hipSuccess) {
-        set_error("amr_batch_create: %s", hipGetErrorString(e));
-        delete b;
-        return CC_EDEVICE;
-    }
+    Plan plan;
+    if (!plan_batch(blocks, nblocks, prec, tile, t, b, plan, "amr_batch_create")) { delete b; return CC_EINVAL; }
+    b->ws = (char *)workspace;
+    if (!upload(b, plan, nullptr, (hipStream_t)stream, "amr_batch_create")) { delete b; return CC_EDEVICE; }
     *out = b;
     return CC_OK;
+}
+
+extern "C" cc_status amr_hierarchy_workspace_bytes(const cc_block *blocks, int32_t nblocks, cc_prec prec,
+                                                   const int32_t domain0[3], size_t *bytes)
+{
+    CC_REQUIRE(blocks && nblocks > 0 && domain0 && bytes, "amr_hierarchy_workspace_bytes: null or empty argument");
+    CC_REQUIRE(prec == CC_F64 || prec == CC_F32_PERT, "amr_hierarchy_workspace_bytes: unknown precision");
+    Tables t;
+    if (!build_tables(blocks, nblocks, domain0, t, "amr_hierarchy_workspace_bytes")) return CC_EINVAL;
+    Plan plan;
+    if (!plan_batch(blocks, nblocks, prec, 0, t, nullptr, plan, "amr_hierarchy_workspace_bytes")) return CC_EINVAL;
+    *bytes = plan.bytes;
+    return CC_OK;
+}
+
+extern "C" cc_status amr_hierarchy_create(const cc_block *blocks, int32_t nblocks, cc_prec prec, int32_t tile,
+                                          const int32_t domain0[3], void *workspace, size_t workspace_bytes,
+                                          cc_batch *out, cc_stream_t stream)
+{
+    CC_REQUIRE(blocks && nblocks > 0 && domain0 && workspace && out, "amr_hierarchy_create: null or empty argument");
+    CC_REQUIRE(prec == CC_F64 || prec == CC_F32_PERT, "amr_hierarchy_create: unknown precision");
+    CC_REQUIRE(domain0[0] > 0 && domain0[1] > 0 && domain0[2] > 0, "amr_hierarchy_create: empty level-0 domain");
+    Tables t;
+    if (!build_tables(blocks, nblocks, domain0, t, "amr_hierarchy_create")) return CC_EINVAL;
+    cc_batch_s *b = new cc_batch_s();
+    Plan plan;
+    if (!plan_batch(blocks, nblocks, prec, tile, t, b, plan, "amr_hierarchy_create")) { delete b; return CC_EINVAL; }
+    if (plan.bytes > workspace_bytes) {
+        set_error("amr_hierarchy_create: workspace of %zu bytes, %zu needed", workspace_bytes, plan.bytes);
+        delete b;
+        return CC_EINVAL;
+    }
+    b->ws = (char *)workspace;
+    if (!upload(b, plan, &t, (hipStream_t)stream, "amr_hierarchy_create")) { delete b; return CC_EDEVICE; }
+    *out = b;
+    return CC_OK;
+}
+
+extern "C" cc_status amr_hierarchy_sync(cc_batch b, cc_stream_t stream)
+{
+    CC_REQUIRE(b, "amr_hierarchy_sync: null batch");
+    if (b->prec == CC_F64) sync_all<double>(b, (hipStream_t)stream);
+    else sync_all<float>(b, (hipStream_t)stream);
+    return launch_status("amr_hierarchy_sync");
 }
 
 extern "C" cc_status amr_block_step(cc_batch b, double dt, int32_t nsteps, int32_t use_graph, int64_t *st,
                                     cc_stream_t stream)
 {
-    using namespace cc;
     CC_REQUIRE(b && nsteps >= 0, "amr_block_step: bad batch or step count");
     hipStream_t s = (hipStream_t)stream;
     if (!use_graph) {
-        batch_enqueue(b, dt, nsteps, st, s);
+        enqueue(b, dt, nsteps, st, s);
         return launch_status("amr_block_step");
     }
+    std::vector<int> cur0;
+    for (const Level &L : b->lev) cur0.push_back(L.cur);
     for (auto &g : b->graphs)
-        if (g.nsteps == nsteps && g.cur == b->cur && g.dt == dt && g.st == st) {
+        if (g.nsteps == nsteps && g.dt == dt && g.st == st && g.cur0 == cur0) {
             hipError_t e = hipGraphLaunch(g.exec, s);
             if (e != hipSuccess) { set_error("amr_block_step: %s", hipGetErrorString(e)); return CC_EDEVICE; }
-            if (nsteps % 2) b->cur = 1 - b->cur;
+            for (size_t l = 0; l < b->lev.size(); ++l) b->lev[l].cur = g.cur1[l];
             return CC_OK;
         }
     // capture the step sequence once on a private stream, then launch it on the caller's stream
     hipError_t e = hipSuccess;
     if (!b->cap) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
-    int cur0 = b->cur;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        batch_enqueue(b, dt, nsteps, st, b->cap);
+        enqueue(b, dt, nsteps, st, b->cap);
         e = hipStreamEndCapture(b->cap, &graph);
     }
-    b->cur = cur0;
+    std::vector<int> cur1;
+    for (const Level &L : b->lev) cur1.push_back(L.cur);
+    for (size_t l = 0; l < b->lev.size(); ++l) b->lev[l].cur = cur0[l];
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (graph) (void)hipGraphDestroy(graph);
     if (e == hipSuccess) e = hipGraphLaunch(exec, s);
@@ -173,12 +766,18 @@ extern "C" cc_status amr_block_step(cc_batch b, double dt, int32_t nsteps, int32
         set_error("amr_block_step (graph): %s", hipGetErrorString(e));
         return CC_EDEVICE;
     }
-    b->graphs.push_back({nsteps, cur0, dt, st, exec});
-    if (nsteps % 2) b->cur = 1 - b->cur;
+    b->graphs.push_back({nsteps, dt, st, cur0, cur1, exec});
+    for (size_t l = 0; l < b->lev.size(); ++l) b->lev[l].cur = cur1[l];
     return CC_OK;
 }
 
-extern "C" int32_t amr_batch_current(cc_batch b) { return b ? b->cur : -1; }
+extern "C" int32_t amr_batch_current(cc_batch b, int32_t level)
+{
+    if (!b || level < 0 || level >= (int32_t)b->lev.size()) return -1;
+    return b->lev[level].cur;
+}
+
+extern "C" int32_t amr_batch_levels(cc_batch b) { return b ? (int32_t)b->lev.size() : 0; }
 
 extern "C" cc_status amr_batch_destroy(cc_batch b)
 {

@@ -15,13 +15,13 @@ namespace cc {
 // theta = theta0 exp(N^2 z / g); Exner pi solves d pi/dz = -g/(cp theta); (rho theta) from the
 // equation of state; pbar through the same equation of state, so (rho theta)' = 0 <=> p' = 0.
 // ------------------------------------------------------------------------------------------------
-__global__ void k_base_state(int nz, double dz, cc_phys ph, double *base)
+__global__ void k_base_state(int nz, double dz, double z0, cc_phys ph, double *base)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nz) return;
     double cv = ph.cp - ph.rd;
     double n2 = ph.bvn * ph.bvn;
-    double z = ((double)k + 0.5) * dz;
+    double z = z0 + ((double)k + 0.5) * dz;
     double th, pi;
     if (n2 > 0.0) {
         th = ph.theta0 * exp(n2 * z / ph.g);
@@ -90,7 +90,10 @@ __global__ void k_terrain_check(Dims d, const double *__restrict__ H, int64_t *s
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)d.nx * d.ny) return;
     double h = H[t];
-    if (!(h >= 0.0 && h <= (double)(d.nz - 2) * d.dz)) count_status(st, ST_TERRAIN);
+    // a grid on the ground holds its terrain below the lid; a raised block of a refined grid may
+    // have the terrain below or above it
+    bool ok = d.z0 > 0.0 ? (h == h) : (h >= 0.0 && h <= (double)(d.nz - 2) * d.dz);
+    if (!ok) count_status(st, ST_TERRAIN);
 }
 
 // volume fraction and raw apertures of cell (i,j,k); one thread per cell, k fastest
@@ -411,7 +414,7 @@ extern "C" cc_status cutcell_base_state(const cc_grid *grid, const cc_phys *phys
     if (!check_grid(grid)) return CC_EINVAL;
     CC_REQUIRE(phys && base, "cutcell_base_state: null argument");
     hipLaunchKernelGGL(k_base_state, dim3(blocks_for(grid->nz, 64)), dim3(64), 0, (hipStream_t)stream,
-                       grid->nz, grid->dz, *phys, base);
+                       grid->nz, grid->dz, grid->z0, *phys, base);
     hipLaunchKernelGGL(k_base_lattice, dim3(blocks_for(grid->nz, 64)), dim3(64), 0, (hipStream_t)stream,
                        grid->nz, base);
     return launch_status("cutcell_base_state");

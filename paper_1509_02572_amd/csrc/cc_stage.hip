@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_partial(Dims d, Geo G, P
             if (q.rho_lo) { rp += (double)q.rho_lo[c]; tp += (double)q.rth_lo[c]; }
             double rho = P.rhob[k] + rp;
             double p = P.pb[k] + P.pb[k] * expm1(P.gam * log1p(tp / P.rthb[k]));
-            double z = ((double)k + 0.5) * d.dz;
+            double z = d.z0 + ((double)k + 0.5) * d.dz;
             acc[0] += vg * rp;
             acc[1] += vg * tp;
             acc[2] += vg * rho;

@@ -29,7 +29,7 @@ STATUS_NAMES = ("unmergeable", "noplane", "nonfinite", "terrain", "groupsize")
 class cc_grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("nzs", C.c_int32),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
-                ("nsub", C.c_int32), ("tile", C.c_int32)]
+                ("nsub", C.c_int32), ("tile", C.c_int32), ("z0", C.c_double)]
 
 
 class cc_phys(C.Structure):
@@ -47,7 +47,8 @@ class cc_state(C.Structure):
 
 class cc_block(C.Structure):
     _fields_ = [("grid", cc_grid), ("phys", cc_phys), ("geom", cc_geom), ("base", C.c_void_p),
-                ("q", cc_state * 3), ("level", C.c_int32), ("reserved", C.c_int32)]
+                ("q", cc_state * 3), ("level", C.c_int32), ("org", C.c_int32 * 3), ("ilo", C.c_int32 * 3),
+                ("ihi", C.c_int32 * 3)]
 
 
 _lib = None
@@ -81,12 +82,21 @@ def lib():
         L.amr_batch_create.argtypes = [C.POINTER(cc_block), C.c_int32, C.c_int, C.c_int32, vp,
                                        C.POINTER(C.c_void_p), vp]
         L.amr_block_step.argtypes = [vp, C.c_double, C.c_int32, C.c_int32, i64p, vp]
-        L.amr_batch_current.argtypes = [vp]
+        L.amr_batch_current.argtypes = [vp, C.c_int32]
         L.amr_batch_current.restype = C.c_int32
+        L.amr_batch_levels.argtypes = [vp]
+        L.amr_batch_levels.restype = C.c_int32
+        i3 = C.c_int32 * 3
+        L.amr_hierarchy_workspace_bytes.argtypes = [C.POINTER(cc_block), C.c_int32, C.c_int, i3,
+                                                    C.POINTER(C.c_size_t)]
+        L.amr_hierarchy_create.argtypes = [C.POINTER(cc_block), C.c_int32, C.c_int, C.c_int32, i3, vp, C.c_size_t,
+                                           C.POINTER(C.c_void_p), vp]
+        L.amr_hierarchy_sync.argtypes = [vp, vp]
         L.amr_batch_destroy.argtypes = [vp]
         for name in ("cutcell_base_state", "cutcell_geometry", "cutcell_merge_map", "cutcell_init_state",
                      "cutcell_diagnose", "cutcell_tendency", "cutcell_rk_stage", "cutcell_rk_update", "cutcell_reduce",
-                     "cutcell_check_status", "amr_batch_create", "amr_block_step", "amr_batch_destroy"):
+                     "cutcell_check_status", "amr_batch_create", "amr_block_step", "amr_batch_destroy",
+                     "amr_hierarchy_workspace_bytes", "amr_hierarchy_create", "amr_hierarchy_sync"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -194,8 +204,33 @@ def amr_block_step(batch: C.c_void_p, dt: float, nsteps: int, use_graph: bool, s
            "amr_block_step")
 
 
-def amr_batch_current(batch: C.c_void_p) -> int:
-    return int(lib().amr_batch_current(batch))
+def amr_batch_current(batch: C.c_void_p, level: int = 0) -> int:
+    return int(lib().amr_batch_current(batch, level))
+
+
+def amr_batch_levels(batch: C.c_void_p) -> int:
+    return int(lib().amr_batch_levels(batch))
+
+
+def amr_hierarchy_workspace_bytes(blocks, prec: int, domain0) -> int:
+    arr = (cc_block * len(blocks))(*blocks)
+    n = C.c_size_t()
+    _check(lib().amr_hierarchy_workspace_bytes(arr, len(blocks), prec, (C.c_int32 * 3)(*domain0), C.byref(n)),
+           "amr_hierarchy_workspace_bytes")
+    return int(n.value)
+
+
+def amr_hierarchy_create(blocks, prec: int, tile: int, domain0, workspace: torch.Tensor, stream=None) -> C.c_void_p:
+    arr = (cc_block * len(blocks))(*blocks)
+    h = C.c_void_p()
+    _check(lib().amr_hierarchy_create(arr, len(blocks), prec, tile, (C.c_int32 * 3)(*domain0), _ptr(workspace),
+                                      workspace.numel() * workspace.element_size(), C.byref(h), _stream(stream)),
+           "amr_hierarchy_create")
+    return h
+
+
+def amr_hierarchy_sync(batch: C.c_void_p, stream=None):
+    _check(lib().amr_hierarchy_sync(batch, _stream(stream)), "amr_hierarchy_sync")
 
 
 def amr_batch_destroy(batch: C.c_void_p):
@@ -245,7 +280,7 @@ class Domain:
         nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
         self.nzs = nzs or default_nzs(nz)
         self.n = nx * ny * self.nzs
-        self.grid = cc_grid(nx, ny, nz, self.nzs, cfg.dx, cfg.dy, cfg.dz, cfg.nsub, tile)
+        self.grid = cc_grid(nx, ny, nz, self.nzs, cfg.dx, cfg.dy, cfg.dz, cfg.nsub, tile, cfg.z0)
         self.phys = cc_phys(cfg.g, cfg.rd, cfg.cp, cfg.p0, cfg.theta0, cfg.bvn, cfg.u0, cfg.v0)
         Hn = workloads.terrain(cfg) if H is None else H
         d, f64, i8, i32 = self.dev, torch.float64, torch.int8, torch.int32
@@ -383,7 +418,8 @@ class Batch:
                 b[0].t[f].copy_(q.t[f])
             self.bufs.append(b)
             blocks.append(cc_block(d.grid, d.phys, d.geom, C.c_void_p(d.base.data_ptr()),
-                                   (cc_state * 3)(b[0].c, b[1].c, b[2].c), 0, 0))
+                                   (cc_state * 3)(b[0].c, b[1].c, b[2].c), 0, (C.c_int32 * 3)(0, 0, 0),
+                                   (C.c_int32 * 3)(0, 0, 0), (C.c_int32 * 3)(d.cfg.nx, d.cfg.ny, d.cfg.nz)))
         dev = domains[0].dev
         self.status = torch.zeros(CC_NSTATUS, dtype=torch.int64, device=dev)
         nbytes = amr_batch_workspace_bytes(len(domains), prec)
@@ -396,7 +432,7 @@ class Batch:
 
     def current(self):
         """Current state of every member."""
-        c = amr_batch_current(self.h)
+        c = amr_batch_current(self.h, 0)
         return [b[c] for b in self.bufs]
 
     def check(self) -> np.ndarray:
@@ -405,6 +441,74 @@ class Batch:
 
     def close(self):
         if self.h:
+            amr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------------------------------------
+# Hierarchy: a refined grid (blocks of several levels, each a padded box) stepped by amr_block_step
+# ------------------------------------------------------------------------------------------------
+class Hierarchy:
+    """Blocks of a ``workloads.AmrLayout`` on ``device``: one ``Domain`` per block (its padded box,
+    terrain heights relative to the box bottom), three state buffers each, initial state of uniform
+    inflow, all ghost cells synchronised."""
+
+    def __init__(self, layout, prec: str = "f64", device: str = "cuda:0", tile: int = 0):
+        self.layout = layout
+        self.doms = []
+        self.bufs = []
+        self.own = []  # (ilo, ihi) of each block's own cells in its box
+        blocks = []
+        for b in layout.blocks:
+            cfg = layout.block_config(b)
+            d = Domain(cfg, prec, device)
+            org, size, gb, gt = layout.box(b)
+            ilo = (layout.ghost, layout.ghost, gb)
+            ihi = (ilo[0] + b.size[0], ilo[1] + b.size[1], ilo[2] + b.size[2])
+            q = [d.init_state(), d.new_state(), d.new_state()]
+            self.doms.append(d)
+            self.bufs.append(q)
+            self.own.append((ilo, ihi))
+            blocks.append(cc_block(d.grid, d.phys, d.geom, C.c_void_p(d.base.data_ptr()),
+                                   (cc_state * 3)(q[0].c, q[1].c, q[2].c), b.level, (C.c_int32 * 3)(*org),
+                                   (C.c_int32 * 3)(*ilo), (C.c_int32 * 3)(*ihi)))
+        self.prec = self.doms[0].prec
+        dev = self.doms[0].dev
+        self.domain0 = (layout.base.nx, layout.base.ny, layout.base.nz)
+        nbytes = amr_hierarchy_workspace_bytes(blocks, self.prec, self.domain0)
+        self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        self.status = torch.zeros(CC_NSTATUS, dtype=torch.int64, device=dev)
+        self.h = amr_hierarchy_create(blocks, self.prec, tile, self.domain0, self.ws)
+        amr_hierarchy_sync(self.h)
+
+    def sync(self):
+        amr_hierarchy_sync(self.h)
+
+    def step(self, nsteps: int = 1, use_graph: bool = False, dt: Optional[float] = None, stream=None):
+        amr_block_step(self.h, self.layout.base.dt if dt is None else dt, nsteps, use_graph, self.status, stream)
+
+    def current(self):
+        cur = [amr_batch_current(self.h, l) for l in range(amr_batch_levels(self.h))]
+        return [q[cur[b.level]] for q, b in zip(self.bufs, self.layout.blocks)]
+
+    def own_cells(self, m: int, q: State) -> Dict[str, np.ndarray]:
+        """Host copy (double, low-order parts added) of block m's own cells."""
+        (i0, j0, k0), (i1, j1, k1) = self.own[m]
+        full = self.doms[m].state_numpy(q)
+        return {f: v[i0:i1, j0:j1, k0:k1] for f, v in full.items()}
+
+    def check(self) -> np.ndarray:
+        rc, host = cutcell_check_status(self.status)
+        return host
+
+    def close(self):
+        if getattr(self, "h", None):
             amr_batch_destroy(self.h)
             self.h = None
 

@@ -77,6 +77,7 @@ class Config:
     cp: float = CP
     p0: float = P0
     H: Optional[np.ndarray] = None  # explicit corner heights (overrides ``hill``)
+    z0: float = 0.0  # height of the grid's bottom face (blocks of a refined grid); H is then relative to it
 
     @property
     def ncells(self) -> int:
@@ -267,3 +268,197 @@ def ensemble(count: int = 64, seed: int = 0, nx_range=(48, 96), nz_range=(48, 64
         cfg.H = H
         out.append(cfg)
     return out
+
+
+# --------------------------------------------------------------------------------------------
+# Refined grid: cubes ("bricks") of equal cell count per level, refined near the terrain with 2:1
+# balance, fully buried bricks removed, then grouped into blocks of uneven size (Sec. 2.2).
+# --------------------------------------------------------------------------------------------
+
+def terrain_at(cfg: Config, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Height of ``cfg``'s analytic hill at positions (x, y), laterally periodic with the hill centre
+    on the lattice corner ``(nx/2 dx, ny/2 dy)`` of ``cfg`` (the same placement as ``terrain``)."""
+    Lx, Ly = cfg.nx * cfg.dx, cfg.ny * cfg.dy
+    rx = np.mod(np.asarray(x, dtype=np.float64) - (cfg.nx // 2) * cfg.dx + 0.5 * Lx, Lx) - 0.5 * Lx
+    ry = np.mod(np.asarray(y, dtype=np.float64) - (cfg.ny // 2) * cfg.dy + 0.5 * Ly, Ly) - 0.5 * Ly
+    return np.asarray(cfg.hill(rx, ry), dtype=np.float64)
+
+
+@dataclasses.dataclass
+class AmrBlock:
+    level: int
+    org: tuple  # interior origin in level-l global cells (x, y, z)
+    size: tuple  # interior size in cells
+
+
+@dataclasses.dataclass
+class AmrLayout:
+    base: Config  # level-0 grid, hill, physics and time step dt(0)
+    levels: int  # number of refinement levels (0 .. levels-1)
+    brick: int  # brick edge in cells (the same at every level)
+    ghost: int  # ghost cells beyond each block side (integrated on, Sec. 2.2)
+    dist: list  # refinement distances d_l [m]
+    blocks: List[AmrBlock]
+
+    def cells(self, level: Optional[int] = None) -> int:
+        return sum(int(np.prod(b.size)) for b in self.blocks if level is None or b.level == level)
+
+    def box(self, b: AmrBlock):
+        """Padded box of block b: (origin in level-l global cells, size, ghost below, ghost above)."""
+        nzl = self.base.nz << b.level
+        gb = self.ghost if b.org[2] > 0 else 0
+        gt = self.ghost if b.org[2] + b.size[2] < nzl else 0
+        org = (b.org[0] - self.ghost, b.org[1] - self.ghost, b.org[2] - gb)
+        size = (b.size[0] + 2 * self.ghost, b.size[1] + 2 * self.ghost, b.size[2] + gb + gt)
+        return org, size, gb, gt
+
+    def block_config(self, b: AmrBlock) -> Config:
+        """Uniform-grid configuration of block b's padded box: spacing of its level, corner heights of
+        the hill relative to the box bottom z0 (negative where the terrain lies below the box)."""
+        c = self.base
+        f = 1 << b.level
+        dx, dy, dz = c.dx / f, c.dy / f, c.dz / f
+        org, size, gb, gt = self.box(b)
+        I = np.mod(org[0] + np.arange(size[0]), c.nx * f).astype(np.float64)[:, None]
+        J = np.mod(org[1] + np.arange(size[1]), c.ny * f).astype(np.float64)[None, :]
+        z0 = org[2] * dz
+        H = terrain_at(c, I * dx, J * dy) - z0
+        return c.replace(name=f"{c.name}-L{b.level}-{b.org}", nx=size[0], ny=size[1], nz=size[2], dx=dx, dy=dy,
+                         dz=dz, H=np.ascontiguousarray(H), z0=z0, dt=c.dt / f)
+
+
+def _leaf_of(leaves, lev, p, nb):
+    """Level of the leaf brick covering brick position p of level lev (x, y periodic), or -1."""
+    x, y, z = p
+    for m in range(lev, -1, -1):
+        sh = lev - m
+        key = ((x % (nb[0] << lev)) >> sh, (y % (nb[1] << lev)) >> sh, z >> sh)
+        if key in leaves[m]:
+            return m
+    for m in range(lev + 1, len(leaves)):
+        sh = m - lev
+        key = ((x % (nb[0] << lev)) << sh, (y % (nb[1] << lev)) << sh, z << sh)
+        if key in leaves[m]:
+            return m
+    return -1
+
+
+def amr_layout(base: Config, levels: int = 3, brick: int = 8, ghost: int = 6, d_fine: float = 0.0,
+               band: float = 1600.0, seed: int = 0, shapes=((2, 2, 2), (4, 4, 2), (3, 3, 3))) -> AmrLayout:
+    """Bricks of ``brick``^3 cells per level over the level-0 grid of ``base``.
+
+    A brick of level l < levels-1 is refined when its bottom lies within d_l of the highest terrain
+    point of its footprint (d_{levels-2} = d_fine, each coarser level adds ``band``); 2:1 balance is
+    enforced across faces, edges and corners; bricks whose every cell is below the terrain are
+    removed.  Each level's bricks are then grouped in lexicographic order: at every unclaimed brick a
+    shape is drawn from ``shapes`` (PCG64(seed)) and the largest box of at most that shape made of
+    unclaimed bricks of the level is claimed as one block.
+    """
+    nb0 = (base.nx // brick, base.ny // brick, base.nz // brick)
+    assert all(n * brick == m for n, m in zip(nb0, (base.nx, base.ny, base.nz))), "grid must hold whole bricks"
+    L = levels - 1
+    dist = [d_fine + band * (L - 1 - l) for l in range(L)]
+    fL = 1 << L
+    # terrain at the finest corners: per-level footprint max / min from it
+    hx = np.arange(base.nx * fL + 1) * (base.dx / fL)
+    hy = np.arange(base.ny * fL + 1) * (base.dy / fL)
+    hf = terrain_at(base, hx[:, None], hy[None, :])
+
+    def foot(lev, bx, by):
+        s = brick << (L - lev)
+        return hf[bx * s:(bx + 1) * s + 1, by * s:(by + 1) * s + 1]
+
+    leaves = [set() for _ in range(levels)]
+    for bx in range(nb0[0]):
+        for by in range(nb0[1]):
+            for bz in range(nb0[2]):
+                leaves[0].add((bx, by, bz))
+    for lev in range(L):
+        dz = base.dz / (1 << lev)
+        for key in sorted(leaves[lev]):
+            bx, by, bz = key
+            if bz * brick * dz - foot(lev, bx, by).max() <= dist[lev]:
+                leaves[lev].remove(key)
+                for c in range(8):
+                    leaves[lev + 1].add((2 * bx + (c >> 2), 2 * by + ((c >> 1) & 1), 2 * bz + (c & 1)))
+    # 2:1 balance over the 26 neighbours
+    changed = True
+    while changed:
+        changed = False
+        for lev in range(L, 1, -1):
+            nbl = (nb0[0] << lev, nb0[1] << lev, nb0[2] << lev)
+            for (bx, by, bz) in sorted(leaves[lev]):
+                for ddx in (-1, 0, 1):
+                    for ddy in (-1, 0, 1):
+                        for ddz in (-1, 0, 1):
+                            z = bz + ddz
+                            if (ddx, ddy, ddz) == (0, 0, 0) or z < 0 or z >= nbl[2]:
+                                continue
+                            p = ((bx + ddx) % nbl[0], (by + ddy) % nbl[1], z)
+                            m = _leaf_of(leaves, lev, p, nb0)
+                            if 0 <= m < lev - 1:
+                                sh = lev - m
+                                key = (p[0] >> sh, p[1] >> sh, p[2] >> sh)
+                                leaves[m].remove(key)
+                                for c in range(8):
+                                    leaves[m + 1].add((2 * key[0] + (c >> 2), 2 * key[1] + ((c >> 1) & 1),
+                                                       2 * key[2] + (c & 1)))
+                                changed = True
+    # fully buried bricks: top at or below the lowest corner height of the footprint at their level
+    for lev in range(levels):
+        dz = base.dz / (1 << lev)
+        step = 1 << (L - lev)
+        for key in sorted(leaves[lev]):
+            bx, by, bz = key
+            if (bz + 1) * brick * dz <= foot(lev, bx, by)[::step, ::step].min():
+                leaves[lev].remove(key)
+    # group into blocks
+    rng = np.random.Generator(np.random.PCG64(seed))
+    blocks = []
+    for lev in range(levels):
+        nbl = (nb0[0] << lev, nb0[1] << lev, nb0[2] << lev)
+        free = set(leaves[lev])
+        for key in sorted(leaves[lev]):
+            if key not in free:
+                continue
+            sx, sy, sz = shapes[int(rng.integers(len(shapes)))]
+            best, bv = (1, 1, 1), 0
+            for ax in range(1, sx + 1):
+                for ay in range(1, sy + 1):
+                    for az in range(1, sz + 1):
+                        if key[0] + ax > nbl[0] or key[1] + ay > nbl[1] or key[2] + az > nbl[2]:
+                            continue
+                        if ax * ay * az <= bv:
+                            continue
+                        if all((key[0] + a, key[1] + b, key[2] + c) in free
+                               for a in range(ax) for b in range(ay) for c in range(az)):
+                            best, bv = (ax, ay, az), ax * ay * az
+            ax, ay, az = best
+            for a in range(ax):
+                for b in range(ay):
+                    for c in range(az):
+                        free.discard((key[0] + a, key[1] + b, key[2] + c))
+            blocks.append(AmrBlock(lev, (key[0] * brick, key[1] * brick, key[2] * brick),
+                                   (ax * brick, ay * brick, az * brick)))
+    return AmrLayout(base, levels, brick, ghost, dist, blocks)
+
+
+def amr_hemisphere(target_blocks: int = 2000, seed: int = 0) -> AmrLayout:
+    """The refined hemisphere workload: level-0 grid 128x128x64 at 200 m (25.6 x 25.6 x 12.8 km),
+    hemisphere of radius 1 km, levels 1 (100 m) and 2 (50 m), dt(0) = 0.2 s, 25 level-0 steps; the
+    level-2 distance is chosen by bisection so that the block count is closest to ``target_blocks``."""
+    base = Config("amr_hemi", 128, 128, 64, 200.0, 200.0, 200.0, Hill("hemisphere", 0.0, 1000.0),
+                  dt=0.2, nsteps=25)
+    lo, hi = 0.0, 6400.0
+    best = None
+    for _ in range(14):
+        mid = 0.5 * (lo + hi)
+        lay = amr_layout(base, d_fine=mid, seed=seed)
+        n = len(lay.blocks)
+        if best is None or abs(n - target_blocks) < abs(len(best.blocks) - target_blocks):
+            best = lay
+        if n < target_blocks:
+            lo = mid
+        else:
+            hi = mid
+    return best

@@ -52,3 +52,39 @@ def test_version_and_argument_errors_without_device(lib):
     assert b"null" in L.cutcell_last_error()
     g = CC.cc_grid(8, 8, 8, 4, 100.0, 100.0, 50.0, 16, 0)  # nzs < nz
     assert L.cutcell_merge_map(ctypes.byref(g), ctypes.byref(geom), None, None) == CC.CC_EINVAL
+
+
+def _fake_blocks(CC, layout, bad_overlap=False):
+    """cc_block structs of a layout with placeholder (never dereferenced) device pointers: the
+    layout checks and table construction run on the host."""
+    fake = CC.C.c_void_p(0x1000)
+    blocks = []
+    for b in layout.blocks:
+        cfg = layout.block_config(b)
+        nzs = CC.default_nzs(cfg.nz)
+        g = CC.cc_grid(cfg.nx, cfg.ny, cfg.nz, nzs, cfg.dx, cfg.dy, cfg.dz, cfg.nsub, 0, cfg.z0)
+        ph = CC.cc_phys(cfg.g, cfg.rd, cfg.cp, cfg.p0, cfg.theta0, cfg.bvn, cfg.u0, cfg.v0)
+        gm = CC.cc_geom(*([fake] * 14))
+        st = CC.cc_state(*([fake] * 7))
+        org, size, gb, gt = layout.box(b)
+        ilo = (layout.ghost, layout.ghost, gb)
+        ihi = tuple(a + s for a, s in zip(ilo, b.size))
+        blocks.append(CC.cc_block(g, ph, gm, fake, (CC.cc_state * 3)(st, st, st), b.level,
+                                  (CC.C.c_int32 * 3)(*org), (CC.C.c_int32 * 3)(*ilo), (CC.C.c_int32 * 3)(*ihi)))
+    if bad_overlap:
+        blocks.append(blocks[-1])
+    return blocks
+
+
+def test_hierarchy_layout_validation_on_host(lib):
+    from paper_1509_02572_amd import cutcell as CC
+    from paper_1509_02572_amd import workloads as W
+    base = W.Config("amr_test", 16, 16, 24, 200.0, 200.0, 200.0, W.Hill("hemisphere", 0.0, 600.0), dt=0.2)
+    lay = W.amr_layout(base, levels=3, brick=8, ghost=6, d_fine=300.0, band=400.0, seed=1)
+    dom0 = (base.nx, base.ny, base.nz)
+    n = CC.amr_hierarchy_workspace_bytes(_fake_blocks(CC, lay), CC.CC_F64, dom0)
+    assert n > 0 and n % 256 == 0
+    with pytest.raises(RuntimeError, match="overlap"):
+        CC.amr_hierarchy_workspace_bytes(_fake_blocks(CC, lay, bad_overlap=True), CC.CC_F64, dom0)
+    with pytest.raises(RuntimeError, match="leave the level"):
+        CC.amr_hierarchy_workspace_bytes(_fake_blocks(CC, lay), CC.CC_F64, (8, 16, 24))

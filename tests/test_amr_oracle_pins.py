@@ -1,0 +1,61 @@
+"""The refined-grid oracle (Sec. 2.2) against properties the method fixes.
+
+* A single level of blocks tiling the domain is the uniform grid cut into pieces: with ghost
+  refills after every stage it must reproduce the uniform-grid oracle bitwise.
+* Flux matching makes the refined step conserve mass and (rho theta)' to rounding; without it the
+  coarse and fine fluxes through the interfaces differ and mass drifts.
+"""
+import numpy as np
+import pytest
+
+from oracle import amr_oracle as A
+from oracle import oracle as O
+from paper_1509_02572_amd import workloads as W
+
+
+def small_layout():
+    base = W.Config("amr_test", 16, 16, 24, 200.0, 200.0, 200.0, W.Hill("hemisphere", 0.0, 600.0), dt=0.2)
+    return W.amr_layout(base, levels=3, brick=8, ghost=6, d_fine=300.0, band=400.0, seed=1)
+
+
+def test_layout_structure():
+    lay = small_layout()
+    levels = {b.level for b in lay.blocks}
+    assert levels == {0, 1, 2}
+    # own cells of all levels tile the domain volume (nothing is buried on this grid)
+    vol = sum(np.prod(b.size) * (8.0 ** -b.level) for b in lay.blocks)
+    assert vol == lay.base.nx * lay.base.ny * lay.base.nz
+    # cut cells only on the finest level: coarser blocks lie above the terrain
+    for b in lay.blocks:
+        if b.level < 2:
+            dz = lay.base.dz / (1 << b.level)
+            assert b.org[2] * dz > 600.0
+
+
+def test_single_level_equals_uniform_grid_bitwise():
+    base = W.Config("one", 32, 32, 16, 100.0, 100.0, 100.0, W.Hill("bell", 400.0, 600.0), dt=0.1, u0=8.0, v0=3.0)
+    lay = W.amr_layout(base, levels=1, brick=8, ghost=6, seed=2)
+    assert len(lay.blocks) > 1
+    a = A.AmrOracle(lay)
+    a.step(3)
+    u = O.Oracle(base).merge()
+    q = u.run(u.init_state(), base.dt, 3)
+    for m, b in enumerate(lay.blocks):
+        own = a.own_cells(m)
+        sl = tuple(slice(o, o + s) for o, s in zip(b.org, b.size))
+        for f in A.FIELDS:
+            assert np.array_equal(own[f], q.a[f][sl]), (m, f)
+
+
+@pytest.mark.parametrize("match", [True, False])
+def test_flux_matching_conserves_mass(match):
+    a = A.AmrOracle(small_layout(), match_fluxes=match)
+    assert len(a.faces) > 0
+    m0 = a.mass()
+    a.step(1)
+    m1 = a.mass()
+    drift = max(abs(m1[0] - m0[0]), abs(m1[1] - m0[1]) / 300.0) / m0[2]
+    if match:
+        assert drift <= 1e-12, drift
+    else:
+        assert drift > 1e-9, drift
