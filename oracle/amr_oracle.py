@@ -67,6 +67,7 @@ class AmrOracle:
         self.faces = self._coarse_fine_faces()
         self.maps = self._ghost_maps()
         self.reg = {key: np.zeros(2) for key in self.faces}
+        self.sync()  # every ghost cell starts from its owner's initial values
 
     # -- lookups ---------------------------------------------------------------------------------
     def _find(self, level, g):

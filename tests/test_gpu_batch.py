@@ -132,8 +132,10 @@ def test_batch_rejects_bad_arguments():
         CC.Batch([d64], [])
     # a block of a refinement level other than 0 is refused by the library
     b = [d64.new_state() for _ in range(3)]
+    i3 = CC.C.c_int32 * 3
     blk = CC.cc_block(d64.grid, d64.phys, d64.geom, CC.C.c_void_p(d64.base.data_ptr()),
-                      (CC.cc_state * 3)(b[0].c, b[1].c, b[2].c), 1, 0)
+                      (CC.cc_state * 3)(b[0].c, b[1].c, b[2].c), 1, i3(0, 0, 0), i3(0, 0, 0),
+                      i3(cfg.nx, cfg.ny, cfg.nz))
     ws = torch.zeros(CC.amr_batch_workspace_bytes(1, CC.CC_F64), dtype=torch.uint8, device="cuda:0")
     with pytest.raises(RuntimeError, match="level"):
         CC.amr_batch_create([blk], CC.CC_F64, 0, ws)
