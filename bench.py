@@ -12,10 +12,12 @@ measured with HIP events on the launch stream, against the 8 TB/s HBM peak.  Mea
 comes from a committed rocprofv3 counter summary when it was taken on the current kernel source.
 The CPU baseline times the FP64 oracle on this machine's host cores on one step of the workload.
 
+The refined line (both precisions) runs the three-level hemisphere grid of blocks (25 level-0 steps in
+one graph launch; cell-updates count the blocks' own cells x their level's steps x 3 stages).
 The ensemble line (both precisions) advances 64 independent domains of uneven size through 50 steps
 with one captured graph of the batched kernels.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f32|f64] [--no-cpu] [--no-ensemble]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f32|f64] [--no-cpu] [--no-ensemble] [--no-amr]
 """
 import argparse
 import hashlib
@@ -159,6 +161,44 @@ def run_ensemble(prec: str, warmup: int):
             "tile": tile, "tile_ms_per_2_steps": {str(k): round(v, 4) for k, v in times.items()}}
 
 
+def run_amr(prec: str, warmup: int, layout=None):
+    """The refined hemisphere (three levels of blocks, ghost cells integrated on, fine-first
+    subcycling with flux matching): all its level-0 steps in one graph launch.  Cell-updates count
+    own cells only (each level's cells x its steps x 3 stages); ghost work is overhead."""
+    import torch
+    from paper_1509_02572_amd import cutcell as CC
+    from paper_1509_02572_amd import workloads as W
+    lay = layout if layout is not None else W.amr_hemisphere(2000)
+    t0 = time.perf_counter()
+    h = CC.Hierarchy(lay, prec, "cuda:0", tile=9)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    nsteps = lay.base.nsteps
+    stream = torch.cuda.current_stream()
+    for _ in range(max(warmup, 1)):
+        h.step(1, use_graph=True)  # captures the single-step graphs (both starting buffers)
+        h.step(1, use_graph=True)
+    h.step(nsteps, use_graph=True)  # captures the timed sequence
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    h.step(nsteps, use_graph=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    st = h.check()
+    if st[:6].any():
+        raise RuntimeError(f"device status counters set: {st}")
+    updates = sum(lay.cells(l) * (1 << l) for l in range(lay.levels)) * 3 * nsteps
+    box = sum(int(d.cfg.nx * d.cfg.ny * d.cfg.nz) for d in h.doms)
+    h.close()
+    return {"value": updates / secs, "unit": "cell-updates/s", "blocks": len(lay.blocks),
+            "own_cells_per_level": [lay.cells(l) for l in range(lay.levels)], "box_cells": box,
+            "steps_level0": nsteps, "ms_per_level0_step": secs / nsteps * 1e3, "graph_ms": e0.elapsed_time(e1),
+            "setup_s": round(setup, 1)}
+
+
 def run_cpu_baseline(cfg):
     """FP64 oracle on the host cores: one full step (three stages) of the same workload."""
     from oracle import oracle as O
@@ -184,6 +224,7 @@ def main():
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="fixed update-kernel tile id (default: autotuned)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -210,6 +251,14 @@ def main():
     side = run_gpu(cfg, other, args.steps, args.warmup, args.tile)
     log(f"bench: {other} {side['value']:.4g} cell-updates/s, {side['ms_per_step']:.3f} ms/step")
     f64 = head if args.prec == "f64" else side
+    amr = {}
+    if not args.no_amr:
+        from paper_1509_02572_amd import workloads as W
+        lay = W.amr_hemisphere(2000)
+        for p in (args.prec, other):
+            amr[p] = run_amr(p, args.warmup, lay)
+            log(f"bench: refined hemisphere {p} {amr[p]['value']:.4g} cell-updates/s, "
+                f"{amr[p]['ms_per_level0_step']:.2f} ms per level-0 step")
     ens = {}
     if not args.no_ensemble:
         for p in (args.prec, other):
@@ -236,6 +285,11 @@ def main():
         other: {"value": side["value"], "ms_per_step": side["ms_per_step"], "roofline": side["roofline"]},
         "speedup_vs_fp64": head["value"] / f64["value"],
     }
+    if amr:
+        out["refined"] = {"workload": "hemisphere R=1 km on 128x128x64 level-0 cells at 200 m (25.6x25.6x12.8 km), "
+                                      "levels 1 (100 m) and 2 (50 m), 8^3-cell bricks, 6 ghost cells, dt(0)=0.2 s, "
+                                      "25 level-0 steps per graph launch",
+                          **amr}
     if ens:
         out["ensemble"] = {"workload": "64 periodic domains, nx,ny~U{48..96}, nz~U{48..64}, dx=dy=dz=100 m, "
                                        "1-5 Gaussian hills each (seed 0), dt=0.09 s, 50 steps per graph launch",

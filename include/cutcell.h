@@ -30,7 +30,9 @@
  * by the library): [0] unmergeable cells, [1] corners without a nearest plane, [2] non-finite values,
  * [3] terrain corners outside [0, (nz-2) dz] (or above it for a raised block), [4] merged groups
  * larger than CC_MAX_GROUP, [5] coarse-fine interface faces of a refined grid that are not open
- * regular faces (the interface touches cut or merged cells).  The
+ * regular faces (the interface touches cut or merged cells), [6] non-finite values written to
+ * ghost cells of refined-grid blocks (layers that go stale between refills and are overwritten;
+ * informational, not an error).  The
  * caller synchronises and checks them (cutcell_check_status).  No exception crosses the ABI.
  * Calls are reentrant for distinct streams and buffers; calls sharing output buffers race.
  */

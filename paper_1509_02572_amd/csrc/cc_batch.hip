@@ -542,7 +542,7 @@ bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, co
 
 template <typename T>
 bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, int TX, int TY, int TZ,
-                 std::vector<char> &host, Level &L, const char *what)
+                 bool own_range, std::vector<char> &host, Level &L, const char *what)
 {
     host.assign(sizeof(BlockDesc<T>) * ids.size(), 0);
     BlockDesc<T> *h = (BlockDesc<T> *)host.data();
@@ -563,6 +563,11 @@ bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, i
         h[m].nbx = (d.nx + TX - 1) / TX; h[m].nby = (d.ny + TY - 1) / TY; h[m].nbz = (d.nz + TZ - 1) / TZ;
         h[m].tile0 = tiles;
         h[m].col0 = cols;
+        for (int a = 0; a < 3; ++a) {  // own cells: as given for refined grids, the whole grid otherwise
+            const int box[3] = {d.nx, d.ny, d.nz};
+            h[m].ilo[a] = own_range ? b.ilo[a] : 0;
+            h[m].ihi[a] = own_range ? b.ihi[a] : box[a];
+        }
         tiles += h[m].nbx * h[m].nby * h[m].nbz;
         cols += d.nx * d.ny;
     }
@@ -595,8 +600,8 @@ struct Plan {
     std::vector<std::vector<char>> desc;
 };
 
-bool plan_batch(const cc_block *B, int n, cc_prec prec, int tile, const Tables &t, cc_batch_s *b, Plan &plan,
-                const char *what)
+bool plan_batch(const cc_block *B, int n, cc_prec prec, int tile, bool own_range, const Tables &t, cc_batch_s *b,
+                Plan &plan, const char *what)
 {
     int TX, TY, TZ;
     int id = batch_tile(B, n, tile, TX, TY, TZ);
@@ -605,8 +610,8 @@ bool plan_batch(const cc_block *B, int n, cc_prec prec, int tile, const Tables &
     plan.desc.assign(nl, {});
     size_t off = 0;
     for (int l = 0; l < nl; ++l) {
-        bool ok = prec == CC_F64 ? build_descs<double>(B, t.members[l], prec, TX, TY, TZ, plan.desc[l], lev[l], what)
-                                 : build_descs<float>(B, t.members[l], prec, TX, TY, TZ, plan.desc[l], lev[l], what);
+        bool ok = prec == CC_F64 ? build_descs<double>(B, t.members[l], prec, TX, TY, TZ, own_range, plan.desc[l], lev[l], what)
+                                 : build_descs<float>(B, t.members[l], prec, TX, TY, TZ, own_range, plan.desc[l], lev[l], what);
         if (!ok) return false;
         lev[l].desc_off = off;
         off = align256(off + plan.desc[l].size());
@@ -677,7 +682,7 @@ extern "C" cc_status amr_batch_create(const cc_block *blocks, int32_t nblocks, c
     t.same.assign(1, {}); t.inj.assign(1, {}); t.res.assign(1, {}); t.slots.assign(1, {}); t.corr.assign(1, {});
     cc_batch_s *b = new cc_batch_s();
     Plan plan;
-    if (!plan_batch(blocks, nblocks, prec, tile, t, b, plan, "amr_batch_create")) { delete b; return CC_EINVAL; }
+    if (!plan_batch(blocks, nblocks, prec, tile, false, t, b, plan, "amr_batch_create")) { delete b; return CC_EINVAL; }
     b->ws = (char *)workspace;
     if (!upload(b, plan, nullptr, (hipStream_t)stream, "amr_batch_create")) { delete b; return CC_EDEVICE; }
     *out = b;
@@ -692,7 +697,7 @@ extern "C" cc_status amr_hierarchy_workspace_bytes(const cc_block *blocks, int32
     Tables t;
     if (!build_tables(blocks, nblocks, domain0, t, "amr_hierarchy_workspace_bytes")) return CC_EINVAL;
     Plan plan;
-    if (!plan_batch(blocks, nblocks, prec, 0, t, nullptr, plan, "amr_hierarchy_workspace_bytes")) return CC_EINVAL;
+    if (!plan_batch(blocks, nblocks, prec, 0, true, t, nullptr, plan, "amr_hierarchy_workspace_bytes")) return CC_EINVAL;
     *bytes = plan.bytes;
     return CC_OK;
 }
@@ -708,7 +713,7 @@ extern "C" cc_status amr_hierarchy_create(const cc_block *blocks, int32_t nblock
     if (!build_tables(blocks, nblocks, domain0, t, "amr_hierarchy_create")) return CC_EINVAL;
     cc_batch_s *b = new cc_batch_s();
     Plan plan;
-    if (!plan_batch(blocks, nblocks, prec, tile, t, b, plan, "amr_hierarchy_create")) { delete b; return CC_EINVAL; }
+    if (!plan_batch(blocks, nblocks, prec, tile, true, t, b, plan, "amr_hierarchy_create")) { delete b; return CC_EINVAL; }
     if (plan.bytes > workspace_bytes) {
         set_error("amr_hierarchy_create: workspace of %zu bytes, %zu needed", workspace_bytes, plan.bytes);
         delete b;

@@ -43,7 +43,8 @@ __host__ __device__ __forceinline__ void unidx(const Dims &d, int64_t c, int &i,
 }
 
 // status counters (see cutcell.h)
-enum { ST_UNMERGEABLE = 0, ST_NOPLANE = 1, ST_NONFINITE = 2, ST_TERRAIN = 3, ST_GROUPSIZE = 4, ST_INTERFACE = 5 };
+enum { ST_UNMERGEABLE = 0, ST_NOPLANE = 1, ST_NONFINITE = 2, ST_TERRAIN = 3, ST_GROUPSIZE = 4, ST_INTERFACE = 5,
+       ST_STALE = 6 };
 
 __device__ __forceinline__ void count_status(int64_t *st, int which, int64_t n = 1)
 {

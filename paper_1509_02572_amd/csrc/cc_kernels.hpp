@@ -307,7 +307,7 @@ template <typename T, int MODE>
 __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &qs,
                                             const PointIn<T> &pin, const SOut<T> &qo, double cdt, int final_stage,
                                             int i, int j, int k, const LView<typename Compute<T>::R> &V,
-                                            int64_t *st)
+                                            int64_t *st, bool ghost)
 {
     using R = typename Compute<T>::R;
     const int nx = d.nx, ny = d.ny, nz = d.nz, nzs = d.nzs;
@@ -528,13 +528,17 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
     } else if (MODE == 1) {
         qo.mu[c] = (T)0; qo.mv[c] = (T)0; qo.mw[c] = (T)0;
     }
-    if (bad) count_status(st, ST_NONFINITE);
+    // ghost cells of a refined-grid block go stale between refills and are counted apart
+    if (bad) count_status(st, ghost ? ST_STALE : ST_NONFINITE);
 }
+
+// the cells a grid owns (a block of a refined grid: its own cells; any other grid: all of it)
+struct OwnRange { int lo[3], hi[3]; };
 
 template <typename T, int TX, int TY, int TZ, int MODE>
 __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &qs,
                                           const SIn<T> &qn, const SOut<T> &qo, double cdt, int final_stage,
-                                          const int i0, const int j0, const int k0, int64_t *st)
+                                          const int i0, const int j0, const int k0, int64_t *st, const OwnRange &ownr)
 {
     using R = typename Compute<T>::R;
     using TL = Tile<TX, TY, TZ>;
@@ -715,7 +719,9 @@ __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy
         V.lb[m] = TL::ls(tx + m, ty + 1, tz + 1);
     }
     V.csj = TL::CZ; V.lsj = TL::LZ; V.nb = NB; V.kb = tz + 2;
-    stage_point<T, MODE>(d, G, P, qs, pin, qo, cdt, final_stage, i, j, k, V, st);
+    const bool ghost = i < ownr.lo[0] || i >= ownr.hi[0] || j < ownr.lo[1] || j >= ownr.hi[1] || k < ownr.lo[2] ||
+                       k >= ownr.hi[2];
+    stage_point<T, MODE>(d, G, P, qs, pin, qo, cdt, final_stage, i, j, k, V, st, ghost);
 }
 
 template <typename T, int TX, int TY, int TZ, int MODE, int MINW>
@@ -725,7 +731,8 @@ __global__ void __launch_bounds__(TX * TY * TZ, MINW)
 {
     int bi, bj, bk;
     tile_of_block(nbx, nby, nbz, bi, bj, bk);
-    tile_body<T, TX, TY, TZ, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, bi * TX, bj * TY, bk * TZ, st);
+    const OwnRange all{{0, 0, 0}, {d.nx, d.ny, d.nz}};
+    tile_body<T, TX, TY, TZ, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, bi * TX, bj * TY, bk * TZ, st, all);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -742,7 +749,7 @@ struct BlockDesc {
     int nbx, nby, nbz;  // tiles of the update kernel
     int tile0;          // first tile of the block in the batched update grid
     int col0;           // first column of the block in the batched diagnostic grid
-    int pad;
+    int ilo[3], ihi[3];  // the block's own cells (the rest of the grid is ghost cells)
 };
 
 template <typename T>
@@ -770,7 +777,8 @@ __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     int t = lb - D.tile0;
     int bk = t % D.nbz, t2 = t / D.nbz, bj = t2 % D.nby, bi = t2 / D.nby;
     tile_body<T, TX, TY, TZ, MODE>(D.d, D.G, D.P, as_in(D.q[rs]), as_in(D.q[rn]), D.q[ro], cdt, final_stage,
-                                   bi * TX, bj * TY, bk * TZ, st);
+                                   bi * TX, bj * TY, bk * TZ, st,
+                                   OwnRange{{D.ilo[0], D.ilo[1], D.ilo[2]}, {D.ihi[0], D.ihi[1], D.ihi[2]}});
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -852,9 +860,11 @@ __device__ bool plane_family(const Dims &d, const Geo &G, const Phy &P, const SI
 
 // one thread per column corner (I,J): boundary velocity (free-slip projection of the nearest-plane
 // mean, eq. 33), then every diagnosed lattice point and absorbed/solid cell of the column
+// corners whose terrain point lies in [zlo, zhi) count a missing nearest plane (for a block of a
+// refined grid: its own columns and levels; elsewhere the block's ghost layers, which go stale)
 template <typename T>
 __device__ __forceinline__ void diagnose_column(const Dims &d, const Geo &G, const Phy &P, const SOut<T> &qw,
-                                                int64_t t, int64_t *st)
+                                                int64_t t, int64_t *st, double zlo, double zhi)
 {
     using R = typename Compute<T>::R;
     int64_t nc = (int64_t)d.nx * d.ny;
@@ -869,10 +879,8 @@ __device__ __forceinline__ void diagnose_column(const Dims &d, const Geo &G, con
         if (order[f] != dom) ok = plane_family<T>(d, G, P, q, order[f], I, J, ut);
     if (!ok) {  // no usable plane: u~ = 0 (as a perturbation: minus the reference flow)
         ut[0] = -(R)P.ux; ut[1] = -(R)P.vy; ut[2] = (R)0;
-        // counted when the terrain point lies in the grid's height range (a raised block of a
-        // refined grid has its ground elsewhere)
         double h0 = G.H[t];
-        if (h0 >= 0.0 && h0 < (double)d.nz * d.dz) count_status(st, ST_NOPLANE);
+        if (h0 >= zlo && h0 < zhi) count_status(st, ST_NOPLANE);
     }
     R dn = (ut[0] + (R)P.ux) * (R)n0 + (ut[1] + (R)P.vy) * (R)n1 + ut[2] * (R)n2;
     R ub[3] = {ut[0] - dn * (R)n0, ut[1] - dn * (R)n1, ut[2] - dn * (R)n2};
@@ -915,7 +923,7 @@ __global__ void __launch_bounds__(64) k_diagnose(Dims d, Geo G, Phy P, SOut<T> q
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)d.nx * d.ny) return;
-    diagnose_column<T>(d, G, P, qw, t, st);
+    diagnose_column<T>(d, G, P, qw, t, st, 0.0, (double)d.nz * d.dz);
 }
 
 template <typename T>
@@ -931,7 +939,11 @@ __global__ void __launch_bounds__(64) k_diagnose_batch(const BlockDesc<T> *__res
         else hi = mid - 1;
     }
     const BlockDesc<T> &D = desc[lo];
-    diagnose_column<T>(D.d, D.G, D.P, D.q[ro], t - D.col0, st);
+    const int64_t c = t - D.col0;
+    const int I = (int)(c / D.d.ny), J = (int)(c % D.d.ny);
+    const bool own = I >= D.ilo[0] && I < D.ihi[0] && J >= D.ilo[1] && J < D.ihi[1];
+    diagnose_column<T>(D.d, D.G, D.P, D.q[ro], c, st, own ? (double)D.ilo[2] * D.d.dz : 0.0,
+                       own ? (double)D.ihi[2] * D.d.dz : 0.0);
 }
 
 

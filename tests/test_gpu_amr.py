@@ -137,3 +137,18 @@ def test_graph_replays_match_eager():
                 assert torch.equal(a.t[f], b.t[f]), (rep, m, f)
         _ = _gpu_mass(eager)  # eager work between replays
     assert not graph.check()[:6].any()
+
+
+def test_full_refined_hemisphere_conserves_mass():
+    """The refined hemisphere workload (about 1800 blocks over three levels) in the float form: two
+    level-0 steps, mass conserved to 1e-12 of the total, no device condition."""
+    lay = W.amr_hemisphere(2000)
+    print("case refined hemisphere", len(lay.blocks), flush=True)
+    h = CC.Hierarchy(lay, "f32", tile=9)
+    m0 = _gpu_mass(h)
+    h.step(2, use_graph=True)
+    torch.cuda.synchronize()
+    m1 = _gpu_mass(h)
+    assert abs(m1[0] - m0[0]) <= 1e-12 * m0[2], (m0, m1)
+    assert not h.check()[:6].any(), h.check()
+    h.close()
