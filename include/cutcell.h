@@ -72,7 +72,7 @@ typedef struct {
     int32_t nx, ny, nz, nzs; /* cells; padded k stride (nzs >= nz) */
     double dx, dy, dz;       /* spacings [m] */
     int32_t nsub;            /* sub-columns per cell edge for volumes/apertures, power of two */
-    int32_t tile;            /* tile shape of the update kernel (0 = default; 1..12 see the tuning
+    int32_t tile;            /* tile shape of the update kernel (0 = default; 1..19 see the tuning
                                 table of the stage kernels); results do not depend on it */
     double z0;               /* height of the grid's bottom face above the terrain datum [m]: 0 for
                                 a grid standing on the ground; > 0 for a block of a refined grid

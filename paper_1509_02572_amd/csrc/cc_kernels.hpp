@@ -535,16 +535,18 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
 // the cells a grid owns (a block of a refined grid: its own cells; any other grid: all of it)
 struct OwnRange { int lo[3], hi[3]; };
 
-template <typename T, int TX, int TY, int TZ, int MODE>
+// TX x TY x TZ threads; each thread updates KP points spaced TZ apart in k, so the tile spans
+// TX x TY x (TZ KP) cells
+template <typename T, int TX, int TY, int TZ, int MODE, int KP = 1>
 __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &qs,
                                           const SIn<T> &qn, const SOut<T> &qo, double cdt, int final_stage,
                                           const int i0, const int j0, const int k0, int64_t *st, const OwnRange &ownr)
 {
     using R = typename Compute<T>::R;
-    using TL = Tile<TX, TY, TZ>;
-    constexpr int NT = TL::NT;
+    using TL = Tile<TX, TY, TZ * KP>;
+    constexpr int NT = TX * TY * TZ;
     constexpr int IT1 = (TL::NC + NT - 1) / NT, IT2 = (TL::NL + NT - 1) / NT;
-    constexpr int NB = TZ + 4;  // staged base levels k0-2 .. k0+TZ+1
+    constexpr int NB = TZ * KP + 4;  // staged base levels k0-2 .. k0+TZ KP+1
     __shared__ R s_rho[TL::NC], s_rth[TL::NC], s_pp[TL::NC];
     __shared__ R s_u[TL::NL], s_v[TL::NL], s_w[TL::NL];
     // base profiles in the compute precision: rhobar, (rho theta)bar, pbar, 1/(rho theta)bar, and
@@ -555,14 +557,16 @@ __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy
     const unsigned ncol = (unsigned)(nx * ny);
     const R Ux = (R)P.ux, Vy = (R)P.vy;
 
-    // the output point of this thread; its q_n values and column thresholds are loaded first
+    // the output points of this thread; their q_n values and column thresholds are loaded first
     const int tx = tid / (TY * TZ), ty = (tid / TZ) % TY, tz = tid % TZ;
-    const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
-    const bool own = i < nx && j < ny && k < nz;
-    PointIn<T> pin;
-    if (own) load_point<T, MODE>(d, G, qn, i, j, k, final_stage, pin);
+    const int i = i0 + tx, j = j0 + ty;
+    PointIn<T> pin[KP];
+#pragma unroll
+    for (int p = 0; p < KP; ++p)
+        if (i < nx && j < ny && k0 + tz + p * TZ < nz)
+            load_point<T, MODE>(d, G, qn, i, j, k0 + tz + p * TZ, final_stage, pin[p]);
     // tiles whose halo lies inside the grid in x, y and k need no periodic wrap and no range check
-    const bool inner = i0 >= 2 && i0 + TX < nx && j0 >= 2 && j0 + TY < ny && k0 >= 2 && k0 + TZ < nz;
+    const bool inner = i0 >= 2 && i0 + TX < nx && j0 >= 2 && j0 + TY < ny && k0 >= 2 && k0 + TZ * KP < nz;
     // ---- issue the global loads of the staging phases first ----
     R c_rho[IT1], c_rth[IT1];
     if (inner) {
@@ -666,7 +670,7 @@ __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy
             int a = e / (TL::CY * TL::CZ), r = e - a * (TL::CY * TL::CZ), b = r / TL::CZ, c = r - b * TL::CZ;
             int k = k0 - 2 + c;
             R pp = (R)0;
-            if (k >= 0 && k < nz && a >= 1 && a <= TX + 1 && b >= 1 && b <= TY + 1 && c >= 1 && c <= TZ + 1)
+            if (k >= 0 && k < nz && a >= 1 && a <= TX + 1 && b >= 1 && b <= TY + 1 && c >= 1 && c <= TZ * KP + 1)
                 pp = eos_staged<R>(c_rth[it], s_b[3][c], s_b[2][c], P);
             s_rho[e] = c_rho[it];
             s_rth[e] = c_rth[it];
@@ -710,21 +714,26 @@ __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy
     }
     __syncthreads();
 
-    // ---- phase 3: one cell and one lattice point per thread ----
-    if (!own) return;
-    LView<R> V;
-    V.rho = s_rho; V.rth = s_rth; V.pp = s_pp; V.u = s_u; V.v = s_v; V.w = s_w; V.b = &s_b[0][0];
-    for (int m = 0; m < 3; ++m) {
-        V.cb[m] = TL::cs(tx + 1 + m, ty + 2, tz + 2);
-        V.lb[m] = TL::ls(tx + m, ty + 1, tz + 1);
+    // ---- phase 3: KP cells and lattice points per thread ----
+#pragma unroll
+    for (int p = 0; p < KP; ++p) {
+        const int tzp = tz + p * TZ, k = k0 + tzp;
+        if (i < nx && j < ny && k < nz) {
+            LView<R> V;
+            V.rho = s_rho; V.rth = s_rth; V.pp = s_pp; V.u = s_u; V.v = s_v; V.w = s_w; V.b = &s_b[0][0];
+            for (int m = 0; m < 3; ++m) {
+                V.cb[m] = TL::cs(tx + 1 + m, ty + 2, tzp + 2);
+                V.lb[m] = TL::ls(tx + m, ty + 1, tzp + 1);
+            }
+            V.csj = TL::CZ; V.lsj = TL::LZ; V.nb = NB; V.kb = tzp + 2;
+            const bool ghost = i < ownr.lo[0] || i >= ownr.hi[0] || j < ownr.lo[1] || j >= ownr.hi[1] ||
+                               k < ownr.lo[2] || k >= ownr.hi[2];
+            stage_point<T, MODE>(d, G, P, qs, pin[p], qo, cdt, final_stage, i, j, k, V, st, ghost);
+        }
     }
-    V.csj = TL::CZ; V.lsj = TL::LZ; V.nb = NB; V.kb = tz + 2;
-    const bool ghost = i < ownr.lo[0] || i >= ownr.hi[0] || j < ownr.lo[1] || j >= ownr.hi[1] || k < ownr.lo[2] ||
-                       k >= ownr.hi[2];
-    stage_point<T, MODE>(d, G, P, qs, pin, qo, cdt, final_stage, i, j, k, V, st, ghost);
 }
 
-template <typename T, int TX, int TY, int TZ, int MODE, int MINW>
+template <typename T, int TX, int TY, int TZ, int MODE, int MINW, int KP = 1>
 __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     k_stage_tiled(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn, SOut<T> qo, double cdt, int final_stage,
                   int nbx, int nby, int nbz, int64_t *st)
@@ -732,7 +741,8 @@ __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     int bi, bj, bk;
     tile_of_block(nbx, nby, nbz, bi, bj, bk);
     const OwnRange all{{0, 0, 0}, {d.nx, d.ny, d.nz}};
-    tile_body<T, TX, TY, TZ, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, bi * TX, bj * TY, bk * TZ, st, all);
+    tile_body<T, TX, TY, TZ, MODE, KP>(d, G, P, qs, qn, qo, cdt, final_stage, bi * TX, bj * TY, bk * TZ * KP, st,
+                                       all);
 }
 
 // ------------------------------------------------------------------------------------------------

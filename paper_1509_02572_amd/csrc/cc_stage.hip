@@ -152,15 +152,17 @@ static void launch_diagnose(const Dims &d, const Geo &G, const Phy &P, cc_state 
 struct TileShape { int tx, ty, tz, minw; };
 constexpr TileShape TILES[] = {{8, 8, 8, 1}, {4, 4, 16, 1}, {8, 4, 16, 1}, {4, 8, 16, 1}, {8, 8, 8, 1},
                                {2, 4, 32, 1}, {4, 4, 32, 1}, {8, 8, 16, 1}, {2, 2, 64, 1},
-                               {8, 8, 8, 6}, {8, 8, 8, 8}, {4, 4, 16, 8}, {4, 8, 16, 6}};
+                               {8, 8, 8, 6}, {8, 8, 8, 8}, {4, 4, 16, 8}, {4, 8, 16, 6},
+                               {8, 8, 16, 4}, {8, 8, 16, 6}, {8, 8, 8, 6},  // 13-15: two points per thread in k
+                               {8, 8, 8, 8}, {4, 4, 16, 8}, {8, 8, 8, 4}, {8, 8, 16, 6}};  // 16-19: 2-4 points
 constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
 
-template <typename T, int TX, int TY, int TZ, int MODE, int MINW = 1>
+template <typename T, int TX, int TY, int TZ, int MODE, int MINW = 1, int KP = 1>
 static void launch_tiled(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
                          cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
 {
-    int nbx = (d.nx + TX - 1) / TX, nby = (d.ny + TY - 1) / TY, nbz = (d.nz + TZ - 1) / TZ;
-    hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, MINW>), dim3(nbx * nby * nbz), dim3(TX * TY * TZ), 0, s,
+    int nbx = (d.nx + TX - 1) / TX, nby = (d.ny + TY - 1) / TY, nbz = (d.nz + TZ * KP - 1) / (TZ * KP);
+    hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, MINW, KP>), dim3(nbx * nby * nbz), dim3(TX * TY * TZ), 0, s,
                        d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, nbx, nby, nbz, st);
 }
 
@@ -198,6 +200,13 @@ static void launch_stage(const Dims &d, const Geo &G, const Phy &P, const cc_sta
     CC_TILE_CASE_W(11, 4, 4, 16, 8)
     CC_TILE_CASE_W(12, 4, 8, 16, 6)
 #undef CC_TILE_CASE_W
+    case 13: launch_tiled<T, 8, 8, 8, MODE, 4, 2>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
+    case 14: launch_tiled<T, 8, 8, 8, MODE, 6, 2>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
+    case 15: launch_tiled<T, 8, 8, 4, MODE, 6, 2>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
+    case 16: launch_tiled<T, 8, 8, 2, MODE, 8, 4>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
+    case 17: launch_tiled<T, 4, 4, 8, MODE, 8, 2>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
+    case 18: launch_tiled<T, 8, 8, 4, MODE, 4, 2>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
+    case 19: launch_tiled<T, 8, 8, 4, MODE, 6, 4>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
     default: launch_tiled<T, 2, 2, 64, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s); break;
 #undef CC_TILE_CASE
     }
