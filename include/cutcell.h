@@ -72,7 +72,7 @@ typedef struct {
     int32_t nx, ny, nz, nzs; /* cells; padded k stride (nzs >= nz) */
     double dx, dy, dz;       /* spacings [m] */
     int32_t nsub;            /* sub-columns per cell edge for volumes/apertures, power of two */
-    int32_t tile;            /* tile shape of the update kernel (0 = default; 1..19 see the tuning
+    int32_t tile;            /* tile shape of the update kernel (0 = default; 1..20 see the tuning
                                 table of the stage kernels); results do not depend on it */
     double z0;               /* height of the grid's bottom face above the terrain datum [m]: 0 for
                                 a grid standing on the ground; > 0 for a block of a refined grid
@@ -100,6 +100,8 @@ typedef struct {
     int32_t *colk;            /* [3][nx*ny] per column: first k of the regular cell interior; 1 + top
                                  K of a lattice point that is not predicted; 1 + top level of any
                                  diagnosed point, absorbed or solid cell */
+    void *stage_ws;           /* optional workspace of cutcell_stage_workspace_bytes() bytes: enables
+                                 the two-pass update (cc_grid.tile = 20); NULL otherwise */
 } cc_geom;
 
 /* Five prognostic fields; element type double (CC_F64) or float (CC_F32_PERT).
@@ -114,6 +116,10 @@ typedef struct {
 } cc_state;
 
 const char *cutcell_version(void);
+
+/* Bytes of the optional stage workspace (cc_geom.stage_ws) of a grid: p' at every cell and the
+ * velocity at every lattice point, in the storage precision's compute type. */
+size_t cutcell_stage_workspace_bytes(const cc_grid *grid, cc_prec prec);
 const char *cutcell_last_error(void);
 
 /* Base state on cell centres z_k = z0 + (k+1/2) dz (Sec. 2.1 hydrostatic reference; constant N and

@@ -17,11 +17,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning_cache.json")
 # id -> (TX, TY, TZ) of the update kernel's tile; ids 9-12 repeat a shape with registers capped
 # for 6 or 8 waves per SIMD; ids 13-19 give every thread two or four points spaced evenly in k (13-15, 17, 18: two;
-# 16, 19: four)
+# 16, 19: four); id 20 is the two-pass update (p' and lattice velocities computed once into the
+# grid's stage workspace, then one point per thread)
 TILE_IDS = {1: (4, 4, 16), 2: (8, 4, 16), 3: (4, 8, 16), 4: (8, 8, 8), 5: (2, 4, 32), 6: (4, 4, 32),
             7: (8, 8, 16), 8: (2, 2, 64), 9: (8, 8, 8), 10: (8, 8, 8), 11: (4, 4, 16), 12: (4, 8, 16),
             13: (8, 8, 16), 14: (8, 8, 16), 15: (8, 8, 8), 16: (8, 8, 8), 17: (4, 4, 16), 18: (8, 8, 8),
-            19: (8, 8, 16)}
+            19: (8, 8, 16), 20: (1, 1, 1)}
 TILE_MINW = {9: 6, 10: 8, 11: 8, 12: 6, 13: 4, 14: 6, 15: 6, 16: 8, 17: 8, 18: 4, 19: 6}
 
 

@@ -39,6 +39,7 @@ struct Geo {
     const double *H, *V, *Ax, *Ay, *Az, *nrm, *Vgroup;
     const int8_t *cls, *vcls;
     const int32_t *master, *gnext, *colk;
+    void *ws;  // optional stage workspace (two-pass update), may be null
 };
 
 constexpr int EOS_TERMS = 11;  // binomial series terms of (1+x)^gamma - 1 (double; float uses 6)
@@ -276,6 +277,35 @@ struct LView {
     __device__ __forceinline__ R B(int prof, int dk) const { return b[prof * nb + kb + dk]; }
 };
 
+// The same neighbourhood read from global memory: q_s scalars, and p' and lattice velocities from
+// the prepare pass (p' at cells with the cells' stride, velocities at lattice levels 0..nz with a
+// stride of nzs + 16 so that the lid row is stored); base profiles converted on the fly exactly as
+// they are staged.
+template <typename R>
+struct GView {
+    const R *rho, *rth, *pp, *u, *v, *w;
+    const double *rhob, *rthb, *pb, *irthb, *rhobc;
+    int cb[3], cj[3], lb[3], lj[3];
+    int k, nz;
+    __device__ __forceinline__ int C(int di, int dj, int dk) const { return cb[di + 1] + cj[dj + 1] + dk; }
+    __device__ __forceinline__ int L(int di, int dj, int dk) const { return lb[di + 1] + lj[dj + 1] + dk; }
+    __device__ __forceinline__ R B(int prof, int dk) const
+    {
+        int kk = k + dk;
+        kk = kk < 0 ? 0 : (kk >= nz ? nz - 1 : kk);
+        double v;
+        switch (prof) {
+        case 0: v = rhob[kk]; break;
+        case 1: v = rthb[kk]; break;
+        case 2: v = pb[kk]; break;
+        case 3: v = irthb[kk]; break;
+        case 4: v = rhobc[kk]; break;
+        default: v = kk > 0 ? 0.5 * (rthb[kk - 1] + rthb[kk]) : rthb[0]; break;
+        }
+        return (R)v;
+    }
+};
+
 // Update (MODE 0) or tendency (MODE 1) of cell (i,j,k) and lattice point (i,j,k) from the staged
 // neighbourhood.  Above the per-column bands cells and lattice points are regular and no geometry
 // or class array is read; inside the bands single-cell groups read their apertures, group volume
@@ -303,10 +333,10 @@ __device__ __forceinline__ void load_point(const Dims &d, const Geo &G, const SI
     }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, typename VW>
 __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &qs,
                                             const PointIn<T> &pin, const SOut<T> &qo, double cdt, int final_stage,
-                                            int i, int j, int k, const LView<typename Compute<T>::R> &V,
+                                            int i, int j, int k, const VW &V,
                                             int64_t *st, bool ghost)
 {
     using R = typename Compute<T>::R;
@@ -728,7 +758,7 @@ __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy
             V.csj = TL::CZ; V.lsj = TL::LZ; V.nb = NB; V.kb = tzp + 2;
             const bool ghost = i < ownr.lo[0] || i >= ownr.hi[0] || j < ownr.lo[1] || j >= ownr.hi[1] ||
                                k < ownr.lo[2] || k >= ownr.hi[2];
-            stage_point<T, MODE>(d, G, P, qs, pin[p], qo, cdt, final_stage, i, j, k, V, st, ghost);
+            stage_point<T, MODE, LView<R>>(d, G, P, qs, pin[p], qo, cdt, final_stage, i, j, k, V, st, ghost);
         }
     }
 }
@@ -743,6 +773,88 @@ __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     const OwnRange all{{0, 0, 0}, {d.nx, d.ny, d.nz}};
     tile_body<T, TX, TY, TZ, MODE, KP>(d, G, P, qs, qn, qo, cdt, final_stage, bi * TX, bj * TY, bk * TZ * KP, st,
                                        all);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Two-pass form.  Pass 1 evaluates p' at every cell and the velocity at every lattice point (the
+// lid row included) once, into a workspace; pass 2 updates one point per thread, reading its
+// neighbourhood through the caches.  Both passes use the staging arithmetic of the tiled kernel,
+// so the results are bitwise the same.
+// ------------------------------------------------------------------------------------------------
+__host__ __device__ constexpr int lattice_stride(int nzs) { return nzs + 16; }
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_prepare(Dims d, Geo G, Phy P, SIn<T> qs, typename Compute<T>::R *ws)
+{
+    using R = typename Compute<T>::R;
+    const int nzl = lattice_stride(d.nzs);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ncol = (int64_t)d.nx * d.ny;
+    if (t >= ncol * nzl) return;
+    const int K = (int)(t % nzl);
+    const int64_t col = t / nzl;
+    if (K > d.nz) return;
+    const int I = (int)(col / d.ny), J = (int)(col % d.ny);
+    const int nz = d.nz, nzs = d.nzs;
+    R *pp = ws, *uu = ws + ncol * nzs, *vv = uu + ncol * nzl, *ww = vv + ncol * nzl;
+    if (K < nz) {
+        const int64_t c = col * nzs + K;
+        pp[c] = eos_staged<R>((R)qs.rth[c], (R)P.irthb[K], (R)P.pb[K], P);
+    }
+    const int Kc = K < nz ? K : nz - 1;  // the rigid lid copies the level below
+    const int64_t p = col * nzs + Kc;
+    const R m0 = (R)qs.mu[p], m1 = (R)qs.mv[p], m2 = (R)qs.mw[p];
+    R u0, u1, u2;
+    const bool pred = Kc >= G.colk[ncol + col] || G.vcls[p] == CC_PRED;
+    if (pred) {
+        const int64_t c00 = cidx(d, I - 1, J - 1, Kc - 1), c10 = cidx(d, I, J - 1, Kc - 1);
+        const int64_t c01 = cidx(d, I - 1, J, Kc - 1), c11 = cidx(d, I, J, Kc - 1);
+        R sm = (((R)qs.rho[c00] + (R)qs.rho[c10]) + ((R)qs.rho[c01] + (R)qs.rho[c11])) +
+               (((R)qs.rho[c00 + 1] + (R)qs.rho[c10 + 1]) + ((R)qs.rho[c01 + 1] + (R)qs.rho[c11 + 1]));
+        R rpc = sm * (R)0.125;
+        R ri = recip((R)P.rhobc[Kc] + rpc);
+        u0 = fmaR(-rpc, (R)P.ux, m0) * ri;
+        u1 = fmaR(-rpc, (R)P.vy, m1) * ri;
+        u2 = m2 * ri;
+    } else {
+        u0 = m0; u1 = m1; u2 = m2;
+    }
+    if (K == nz) u2 = (R)0;
+    const int64_t l = col * nzl + K;
+    uu[l] = u0; vv[l] = u1; ww[l] = u2;
+}
+
+// one point (cell and lattice point) per thread, k fastest across the wave
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_stage_points(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn, SOut<T> qo,
+                                                      const typename Compute<T>::R *ws, double cdt, int final_stage,
+                                                      int64_t *st)
+{
+    using R = typename Compute<T>::R;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ncol = (int64_t)d.nx * d.ny;
+    if (t >= ncol * d.nz) return;
+    const int k = (int)(t % d.nz);
+    const int64_t col = t / d.nz;
+    const int i = (int)(col / d.ny), j = (int)(col % d.ny);
+    const int nzs = d.nzs, nzl = lattice_stride(nzs), ny = d.ny;
+    PointIn<T> pin;
+    load_point<T, MODE>(d, G, qn, i, j, k, final_stage, pin);
+    GView<R> V;
+    V.rho = qs.rho; V.rth = qs.rth;
+    V.pp = ws;
+    V.u = ws + ncol * nzs; V.v = V.u + ncol * nzl; V.w = V.v + ncol * nzl;
+    V.rhob = P.rhob; V.rthb = P.rthb; V.pb = P.pb; V.irthb = P.irthb; V.rhobc = P.rhobc;
+    const int jm = wrap1(j - 1, ny), jp = wrap1(j + 1, ny);
+    for (int m = 0; m < 3; ++m) {
+        const int col_m = wrap1(i - 1 + m, d.nx) * ny + j;
+        V.cb[m] = col_m * nzs + k;
+        V.lb[m] = col_m * nzl + k;
+    }
+    V.cj[0] = (jm - j) * nzs; V.cj[1] = 0; V.cj[2] = (jp - j) * nzs;
+    V.lj[0] = (jm - j) * nzl; V.lj[1] = 0; V.lj[2] = (jp - j) * nzl;
+    V.k = k; V.nz = d.nz;
+    stage_point<T, MODE, GView<R>>(d, G, P, qs, pin, qo, cdt, final_stage, i, j, k, V, st, false);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -970,7 +1082,8 @@ inline bool make_views(const char *what, const cc_grid *grid, const cc_phys *phy
     if (!check_ptrs(what, 12, p)) return false;
     if (prec != CC_F64 && prec != CC_F32_PERT) { set_error("%s: unknown precision %d", what, (int)prec); return false; }
     d = dims_of(grid);
-    G = Geo{g->H, g->V, g->Ax, g->Ay, g->Az, g->nrm, g->Vgroup, g->cls, g->vcls, g->master, g->gnext, g->colk};
+    G = Geo{g->H, g->V, g->Ax, g->Ay, g->Az, g->nrm, g->Vgroup, g->cls, g->vcls, g->master, g->gnext, g->colk,
+            g->stage_ws};
     double cv = phys->cp - phys->rd;
     P.rhob = base; P.rthb = base + d.nz; P.pb = base + 2 * d.nz; P.thb = base + 3 * d.nz;
     P.irthb = base + 4 * d.nz; P.rhobc = base + 5 * d.nz;

@@ -154,7 +154,8 @@ constexpr TileShape TILES[] = {{8, 8, 8, 1}, {4, 4, 16, 1}, {8, 4, 16, 1}, {4, 8
                                {2, 4, 32, 1}, {4, 4, 32, 1}, {8, 8, 16, 1}, {2, 2, 64, 1},
                                {8, 8, 8, 6}, {8, 8, 8, 8}, {4, 4, 16, 8}, {4, 8, 16, 6},
                                {8, 8, 16, 4}, {8, 8, 16, 6}, {8, 8, 8, 6},  // 13-15: two points per thread in k
-                               {8, 8, 8, 8}, {4, 4, 16, 8}, {8, 8, 8, 4}, {8, 8, 16, 6}};  // 16-19: 2-4 points
+                               {8, 8, 8, 8}, {4, 4, 16, 8}, {8, 8, 8, 4}, {8, 8, 16, 6},  // 16-19: 2-4 points
+                               {1, 1, 1, 1}};  // 20: two-pass (prepare, then one point per thread)
 constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
 
 template <typename T, int TX, int TY, int TZ, int MODE, int MINW = 1, int KP = 1>
@@ -176,11 +177,37 @@ static int pick_tile(int id, const Dims &d)
     return 8;
 }
 
+// the workspace of the two-pass update fits in 32-bit indices
+static bool two_pass_ok(const Dims &d)
+{
+    return (int64_t)d.nx * d.ny * (d.nzs + 3 * (int64_t)lattice_stride(d.nzs)) < ((int64_t)1 << 31);
+}
+
+template <typename T, int MODE>
+static void launch_two_pass(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
+                            cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
+{
+    using R = typename Compute<T>::R;
+    R *ws = (R *)G.ws;
+    int64_t ncol = (int64_t)d.nx * d.ny;
+    hipLaunchKernelGGL(k_prepare<T>, dim3(blocks_for(ncol * lattice_stride(d.nzs), 256)), dim3(256), 0, s, d, G, P,
+                       sin_of<T>(qs), ws);
+    hipLaunchKernelGGL((k_stage_points<T, MODE>), dim3(blocks_for(ncol * d.nz, 256)), dim3(256), 0, s, d, G, P,
+                       sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), (const R *)ws, cdt, final_stage, st);
+}
+
 template <typename T, int MODE>
 static void launch_stage(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
                          cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s, int tile)
 {
     int id = pick_tile(tile, d);
+    if (id == 20) {
+        if (MODE == 0 && G.ws && two_pass_ok(d)) {
+            launch_two_pass<T, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
+            return;
+        }
+        id = pick_tile(0, d);  // no workspace: the default tile
+    }
     if (MODE == 1) id = (d.nx >= 4 && d.ny >= 4) ? 1 : 8;  // tendency evaluation: fixed shapes
     switch (id) {
 #define CC_TILE_CASE(ID, X, Y, Z) \
@@ -326,4 +353,12 @@ extern "C" cc_status cutcell_reduce(const cc_grid *grid, const cc_phys *phys, co
                            sin_of<float>(q), part);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, part, out);
     return launch_status("cutcell_reduce");
+}
+
+extern "C" size_t cutcell_stage_workspace_bytes(const cc_grid *grid, cc_prec prec)
+{
+    if (!grid || grid->nx <= 0 || grid->ny <= 0 || grid->nzs <= 0) return 0;
+    size_t esz = prec == CC_F64 ? sizeof(double) : sizeof(float);
+    size_t ncol = (size_t)grid->nx * grid->ny;
+    return esz * ncol * ((size_t)grid->nzs + 3 * (size_t)lattice_stride(grid->nzs));
 }

@@ -38,7 +38,7 @@ class cc_phys(C.Structure):
 
 class cc_geom(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("H", "V", "Ax", "Ay", "Az", "col", "nrm", "cls", "dir",
-                                           "vcls", "master", "gnext", "Vgroup", "colk")]
+                                           "vcls", "master", "gnext", "Vgroup", "colk", "stage_ws")]
 
 
 class cc_state(C.Structure):
@@ -73,6 +73,8 @@ def lib():
         L.cutcell_tendency.argtypes = [G, P, GM, vp, C.c_int, S, S, vp]
         L.cutcell_rk_stage.argtypes = [G, P, GM, vp, C.c_int, S, S, S, C.c_double, C.c_int32, i64p, vp]
         L.cutcell_rk_update.argtypes = [G, P, GM, vp, C.c_int, S, S, S, C.c_double, C.c_int32, i64p, vp]
+        L.cutcell_stage_workspace_bytes.argtypes = [G, C.c_int]
+        L.cutcell_stage_workspace_bytes.restype = C.c_size_t
         L.cutcell_reduce_workspace.argtypes = [G]
         L.cutcell_reduce_workspace.restype = C.c_size_t
         L.cutcell_reduce.argtypes = [G, P, GM, vp, C.c_int, S, vp, vp, vp]
@@ -269,7 +271,7 @@ class Domain:
     ``prec`` is ``"f64"`` (paper variables in double) or ``"f32"`` (float perturbation form)."""
 
     def __init__(self, cfg, prec: str = "f64", device: str = "cuda:0", nzs: Optional[int] = None,
-                 H: Optional[np.ndarray] = None, tile: int = 0):
+                 H: Optional[np.ndarray] = None, tile: int = 0, stage_ws: bool = True):
         from . import workloads
         if not torch.cuda.is_available():
             raise RuntimeError("libcutcell needs a HIP device")
@@ -295,8 +297,12 @@ class Domain:
             "gnext": torch.zeros(self.n, dtype=i32, device=d), "Vgroup": torch.zeros(self.n, dtype=f64, device=d),
             "colk": torch.zeros(3 * nc, dtype=i32, device=d),
         }
+        # workspace of the two-pass update (p' and lattice velocities), bytes rounded up to 8
+        wsb = lib().cutcell_stage_workspace_bytes(C.byref(self.grid), self.prec) if stage_ws else 0
+        self.g["stage_ws"] = torch.empty(max(wsb // 8, 1), dtype=torch.float64, device=d) if stage_ws else None
         self.geom = cc_geom(*[_ptr(self.g[k]) for k in ("H", "V", "Ax", "Ay", "Az", "col", "nrm", "cls",
-                                                         "dir", "vcls", "master", "gnext", "Vgroup", "colk")])
+                                                         "dir", "vcls", "master", "gnext", "Vgroup", "colk",
+                                                         "stage_ws")])
         self.base = torch.zeros(6 * nz, dtype=f64, device=d)
         self.status = torch.zeros(CC_NSTATUS, dtype=torch.int64, device=d)
         self.ws = torch.zeros(lib().cutcell_reduce_workspace(C.byref(self.grid)) // 8 + 1, dtype=f64, device=d)
@@ -467,7 +473,7 @@ class Hierarchy:
         blocks = []
         for b in layout.blocks:
             cfg = layout.block_config(b)
-            d = Domain(cfg, prec, device)
+            d = Domain(cfg, prec, device, stage_ws=False)
             org, size, gb, gt = layout.box(b)
             ilo = (layout.ghost, layout.ghost, gb)
             ihi = (ilo[0] + b.size[0], ilo[1] + b.size[1], ilo[2] + b.size[2])

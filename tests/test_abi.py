@@ -64,7 +64,7 @@ def _fake_blocks(CC, layout, bad_overlap=False):
         nzs = CC.default_nzs(cfg.nz)
         g = CC.cc_grid(cfg.nx, cfg.ny, cfg.nz, nzs, cfg.dx, cfg.dy, cfg.dz, cfg.nsub, 0, cfg.z0)
         ph = CC.cc_phys(cfg.g, cfg.rd, cfg.cp, cfg.p0, cfg.theta0, cfg.bvn, cfg.u0, cfg.v0)
-        gm = CC.cc_geom(*([fake] * 14))
+        gm = CC.cc_geom(*([fake] * 15))
         st = CC.cc_state(*([fake] * 7))
         org, size, gb, gt = layout.box(b)
         ilo = (layout.ghost, layout.ghost, gb)
