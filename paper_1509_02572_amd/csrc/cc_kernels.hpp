@@ -119,6 +119,23 @@ __device__ __forceinline__ void scalar_face_flux(R s4, R AS4, R UAS, R b0, R b1,
     f1 = fmaR(b1, unS, (lo1 + up1) * htS);
 }
 
+// Velocity of a predicted lattice point (1 <= K <= nz-1): momentum over the mean of the eight
+// surrounding cell densities, as in lat_vel
+template <typename T, typename R = typename Compute<T>::R>
+__device__ __forceinline__ void lat_vel_pred(const Dims &d, const Phy &P, const SIn<T> &q, int I, int J, int K, R u[3])
+{
+    int64_t p = cidx(d, I, J, K);
+    int64_t c00 = cidx(d, I - 1, J - 1, K - 1), c10 = cidx(d, I, J - 1, K - 1);
+    int64_t c01 = cidx(d, I - 1, J, K - 1), c11 = cidx(d, I, J, K - 1);
+    R s = (((R)q.rho[c00] + (R)q.rho[c10]) + ((R)q.rho[c01] + (R)q.rho[c11])) +
+          (((R)q.rho[c00 + 1] + (R)q.rho[c10 + 1]) + ((R)q.rho[c01 + 1] + (R)q.rho[c11 + 1]));
+    R rpc = s * (R)0.125;
+    R ri = recip((R)P.rhobc[K] + rpc);
+    u[0] = fmaR(-rpc, (R)P.ux, (R)q.mu[p]) * ri;
+    u[1] = fmaR(-rpc, (R)P.vy, (R)q.mv[p]) * ri;
+    u[2] = (R)q.mw[p] * ri;
+}
+
 // Velocity (perturbation from the reference flow) at lattice point (I,J,K).
 // Predicted points divide the momentum by the mean of the eight surrounding cell densities;
 // diagnosed points store the velocity; the rigid lid (K = nz) has w = 0 and copies (u, v) of the
@@ -963,16 +980,24 @@ __device__ bool plane_family(const Dims &d, const Geo &G, const Phy &P, const SI
             }
         }
         double w[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
+        // the four classes are read together (every corner index is in range), then the velocities
+        // of the weighted corners, which are predicted points, together
+        int8_t vc[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) vc[s] = G.vcls[cidx(d, P4[s][0], P4[s][1], P4[s][2])];
         bool ok = true;
-        for (int s = 0; s < 4 && ok; ++s)
-            if (w[s] != 0.0) ok = G.vcls[cidx(d, P4[s][0], P4[s][1], P4[s][2])] == CC_PRED;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (w[s] != 0.0 && vc[s] != CC_PRED) ok = false;
         if (!ok) continue;
+        R v[4][3];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (w[s] != 0.0) lat_vel_pred<T>(d, P, q, P4[s][0], P4[s][1], P4[s][2], v[s]);
         R acc[3] = {(R)0, (R)0, (R)0};
         for (int s = 0; s < 4; ++s) {
             if (w[s] == 0.0) continue;
-            R v[3];
-            lat_vel<T>(d, G, P, q, P4[s][0], P4[s][1], P4[s][2], v);
-            for (int cc = 0; cc < 3; ++cc) acc[cc] += (R)w[s] * v[cc];
+            for (int cc = 0; cc < 3; ++cc) acc[cc] += (R)w[s] * v[s][cc];
         }
         ut[0] = acc[0]; ut[1] = acc[1]; ut[2] = acc[2];
         return true;
@@ -1015,13 +1040,17 @@ __device__ __forceinline__ void diagnose_column(const Dims &d, const Geo &G, con
         if (vc != CC_PRED) {
             R u[3] = {ub[0], ub[1], ub[2]};
             if (vc == CC_MFACE) {
+                // the lowest predicted point within 8 levels above (classes read together)
+                int8_t cv[8];
+#pragma unroll
+                for (int s = 0; s < 8; ++s) cv[s] = K + 1 + s < d.nz ? G.vcls[base + K + 1 + s] : (int8_t)-1;
                 int kp = -1;
-                for (int kk = K + 1; kk <= K + 8 && kk < d.nz; ++kk)
-                    if (G.vcls[base + kk] == CC_PRED) { kp = kk; break; }
+                for (int s = 0; s < 8; ++s)
+                    if (cv[s] == CC_PRED) { kp = K + 1 + s; break; }
                 if (kp >= 0) {
                     double gm = ((double)K * d.dz - hh) / ((double)kp * d.dz - hh);
                     R v[3];
-                    lat_vel<T>(d, G, P, q, I, J, kp, v);
+                    lat_vel_pred<T>(d, P, q, I, J, kp, v);
                     for (int cc = 0; cc < 3; ++cc) u[cc] = v[cc] * (R)gm + ub[cc] * (R)(1.0 - gm);
                 }
             }
