@@ -19,6 +19,7 @@
 #pragma clang fp contract(off)
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <numeric>
 #include <vector>
@@ -297,12 +298,17 @@ void level_stage(cc_batch_s *b, int l, int rn, int rs, int ro, double cdt, int f
             hipLaunchKernelGGL(k_flux_correct<T>, dim3(blocks_for(L.ncorr, 64)), dim3(64), 0, s, descs<T>(b, l), rs, ro,
                                (const CorrEnt *)(b->ws + L.corr_off), L.ncorr, dt, (double *)(b->ws + L.reg_off), st);
     }
+    // ghost cells of the same level were not updated: they take their owners' values before the
+    // diagnostics (whose nearest-plane walk reads neighbouring columns) and again after them
+    auto refill = [&]() {
+        if (L.nsame > 0)
+            hipLaunchKernelGGL(k_ghost_fill<T>, dim3(blocks_for(L.nsame, 256)), dim3(256), 0, s, descs<T>(b, l), ro,
+                               descs<T>(b, l), ro, (const GhostEnt *)(b->ws + L.same_off), L.nsame, (int)FILL_COPY);
+    };
+    refill();
     hipLaunchKernelGGL(k_diagnose_batch<T>, dim3(blocks_for(L.ncols, 64)), dim3(64), 0, s, descs<T>(b, l), L.nblk,
                        L.ncols, ro, st);
-    if (L.nsame > 0) {
-        hipLaunchKernelGGL(k_ghost_fill<T>, dim3(blocks_for(L.nsame, 256)), dim3(256), 0, s, descs<T>(b, l), ro,
-                           descs<T>(b, l), ro, (const GhostEnt *)(b->ws + L.same_off), L.nsame, (int)FILL_COPY);
-    }
+    refill();
 }
 
 // one step of level l (dt), preceded by two steps of level l+1 and followed by the exchange with it
@@ -360,6 +366,7 @@ struct Tables {
     std::vector<std::vector<GhostEnt>> same, inj, res;
     std::vector<std::vector<FluxSlot>> slots;
     std::vector<std::vector<CorrEnt>> corr;
+    std::vector<std::array<int, 6>> range;  // per block: cells to update [lo, hi) (empty: the whole grid)
 };
 
 inline int64_t pmod(int64_t a, int64_t n) { a %= n; return a < 0 ? a + n : a; }
@@ -443,6 +450,16 @@ bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, co
     };
     t.same.assign(nl, {}); t.inj.assign(nl, {}); t.res.assign(nl, {});
     t.slots.assign(nl, {}); t.corr.assign(nl, {});
+    // cells a block must update: its own cells and the ghost cells of other levels (integrated on
+    // between refills); ghosts of the same level are refilled after every stage
+    t.range.assign(n, {0, 0, 0, 0, 0, 0});
+    for (int m = 0; m < n; ++m)
+        t.range[m] = {B[m].ilo[0], B[m].ilo[1], B[m].ilo[2], B[m].ihi[0], B[m].ihi[1], B[m].ihi[2]};
+    auto grow = [&](int m, int i, int j, int k) {
+        std::array<int, 6> &r = t.range[m];
+        r[0] = std::min(r[0], i); r[1] = std::min(r[1], j); r[2] = std::min(r[2], k);
+        r[3] = std::max(r[3], i + 1); r[4] = std::max(r[4], j + 1); r[5] = std::max(r[5], k + 1);
+    };
     for (int l = 0; l < nl; ++l) {
         for (int m : t.members[l]) {
             const cc_block &b = B[m];
@@ -464,6 +481,7 @@ bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, co
                             int oc = om[l - 1].at(gc[0], gc[1], gc[2]);
                             if (oc >= 0) {
                                 t.inj[l].push_back({t.local[m], didx, oc, box_index(t.members[l - 1][oc], l - 1, gc)});
+                                grow(m, i, j, k);
                                 continue;
                             }
                         }
@@ -478,6 +496,7 @@ bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, co
                                         return false;
                                     }
                                 t.res[l].push_back({t.local[m], didx, of, box_index(t.members[l + 1][of], l + 1, gf)});
+                                grow(m, i, j, k);
                             }
                         }
                     }
@@ -542,7 +561,7 @@ bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, co
 
 template <typename T>
 bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, int TX, int TY, int TZ,
-                 bool own_range, std::vector<char> &host, Level &L, const char *what)
+                 bool own_range, const Tables &t, std::vector<char> &host, Level &L, const char *what)
 {
     host.assign(sizeof(BlockDesc<T>) * ids.size(), 0);
     BlockDesc<T> *h = (BlockDesc<T> *)host.data();
@@ -560,16 +579,20 @@ bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, i
             h[m].q[r] = sout_of<T>(const_cast<cc_state *>(&b.q[r]));
         }
         h[m].d = d; h[m].G = G; h[m].P = P;
-        h[m].nbx = (d.nx + TX - 1) / TX; h[m].nby = (d.ny + TY - 1) / TY; h[m].nbz = (d.nz + TZ - 1) / TZ;
+        const int box[3] = {d.nx, d.ny, d.nz};
+        for (int a = 0; a < 3; ++a) {  // own cells and update range: from the tables for refined grids,
+            h[m].ilo[a] = own_range ? b.ilo[a] : 0;             // the whole grid otherwise
+            h[m].ihi[a] = own_range ? b.ihi[a] : box[a];
+            h[m].rlo[a] = own_range ? t.range[ids[m]][a] : 0;
+            h[m].rhi[a] = own_range ? t.range[ids[m]][3 + a] : box[a];
+        }
+        h[m].nbx = (h[m].rhi[0] - h[m].rlo[0] + TX - 1) / TX;
+        h[m].nby = (h[m].rhi[1] - h[m].rlo[1] + TY - 1) / TY;
+        h[m].nbz = (h[m].rhi[2] - h[m].rlo[2] + TZ - 1) / TZ;
         h[m].tile0 = tiles;
         h[m].col0 = cols;
-        for (int a = 0; a < 3; ++a) {  // own cells: as given for refined grids, the whole grid otherwise
-            const int box[3] = {d.nx, d.ny, d.nz};
-            h[m].ilo[a] = own_range ? b.ilo[a] : 0;
-            h[m].ihi[a] = own_range ? b.ihi[a] : box[a];
-        }
         tiles += h[m].nbx * h[m].nby * h[m].nbz;
-        cols += d.nx * d.ny;
+        cols += (h[m].rhi[0] - h[m].rlo[0]) * (h[m].rhi[1] - h[m].rlo[1]);
     }
     L.nblk = (int)ids.size();
     L.ntiles = tiles;
@@ -610,8 +633,9 @@ bool plan_batch(const cc_block *B, int n, cc_prec prec, int tile, bool own_range
     plan.desc.assign(nl, {});
     size_t off = 0;
     for (int l = 0; l < nl; ++l) {
-        bool ok = prec == CC_F64 ? build_descs<double>(B, t.members[l], prec, TX, TY, TZ, own_range, plan.desc[l], lev[l], what)
-                                 : build_descs<float>(B, t.members[l], prec, TX, TY, TZ, own_range, plan.desc[l], lev[l], what);
+        bool ok = prec == CC_F64
+                      ? build_descs<double>(B, t.members[l], prec, TX, TY, TZ, own_range, t, plan.desc[l], lev[l], what)
+                      : build_descs<float>(B, t.members[l], prec, TX, TY, TZ, own_range, t, plan.desc[l], lev[l], what);
         if (!ok) return false;
         lev[l].desc_off = off;
         off = align256(off + plan.desc[l].size());

@@ -889,6 +889,8 @@ struct BlockDesc {
     int tile0;          // first tile of the block in the batched update grid
     int col0;           // first column of the block in the batched diagnostic grid
     int ilo[3], ihi[3];  // the block's own cells (the rest of the grid is ghost cells)
+    int rlo[3], rhi[3];  // cells the batch updates: own cells and the ghost cells no same-level block
+                         // refills (the tiles start at rlo; the diagnostics cover columns [rlo, rhi))
 };
 
 template <typename T>
@@ -916,7 +918,7 @@ __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     int t = lb - D.tile0;
     int bk = t % D.nbz, t2 = t / D.nbz, bj = t2 % D.nby, bi = t2 / D.nby;
     tile_body<T, TX, TY, TZ, MODE>(D.d, D.G, D.P, as_in(D.q[rs]), as_in(D.q[rn]), D.q[ro], cdt, final_stage,
-                                   bi * TX, bj * TY, bk * TZ, st,
+                                   D.rlo[0] + bi * TX, D.rlo[1] + bj * TY, D.rlo[2] + bk * TZ, st,
                                    OwnRange{{D.ilo[0], D.ilo[1], D.ilo[2]}, {D.ihi[0], D.ihi[1], D.ihi[2]}});
 }
 
@@ -1090,8 +1092,10 @@ __global__ void __launch_bounds__(64) k_diagnose_batch(const BlockDesc<T> *__res
         else hi = mid - 1;
     }
     const BlockDesc<T> &D = desc[lo];
-    const int64_t c = t - D.col0;
-    const int I = (int)(c / D.d.ny), J = (int)(c % D.d.ny);
+    const int wy = D.rhi[1] - D.rlo[1];
+    const int64_t r = t - D.col0;
+    const int I = D.rlo[0] + (int)(r / wy), J = D.rlo[1] + (int)(r % wy);
+    const int64_t c = (int64_t)I * D.d.ny + J;
     const bool own = I >= D.ilo[0] && I < D.ihi[0] && J >= D.ilo[1] && J < D.ihi[1];
     diagnose_column<T>(D.d, D.G, D.P, D.q[ro], c, st, own ? (double)D.ilo[2] * D.d.dz : 0.0,
                        own ? (double)D.ihi[2] * D.d.dz : 0.0);
