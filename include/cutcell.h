@@ -102,6 +102,10 @@ typedef struct {
                                  diagnosed point, absorbed or solid cell */
     void *stage_ws;           /* optional workspace of cutcell_stage_workspace_bytes() bytes: enables
                                  the two-pass update (cc_grid.tile = 20); NULL otherwise */
+    int32_t kband;            /* host value set by cutcell_merge_map: every cell and lattice point at
+                                 k >= kband is regular (above all columns' bands); the update runs a
+                                 kernel without the band paths there.  0 or out of [1, nz]: unknown
+                                 (the full kernel everywhere) */
 } cc_geom;
 
 /* Five prognostic fields; element type double (CC_F64) or float (CC_F32_PERT).
@@ -145,6 +149,7 @@ cc_status cutcell_geometry(const cc_grid *grid, cc_geom *geom, int64_t *dev_stat
  * col from cutcell_geometry.  Unmergeable cells become their own master (CC_ORPHAN) and are counted
  * into dev_status[0]. */
 cc_status cutcell_merge_map(const cc_grid *grid, cc_geom *geom, int64_t *dev_status, cc_stream_t stream);
+/* (cutcell_merge_map synchronises `stream` once at the end to read the band height into geom->kband.) */
 
 /* Initial state: theta' (nullable, cell layout, double) applied at constant pressure to group
  * masters, (rho theta)' = 0, uniform inflow (u0, v0, 0) as momentum at predicted points, then one

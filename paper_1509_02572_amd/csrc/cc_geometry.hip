@@ -6,6 +6,8 @@
 // any IEEE-754 double implementation that follows the same order.
 #pragma clang fp contract(off)
 
+#include <vector>
+
 #include "cc_internal.hpp"
 
 namespace cc {
@@ -456,5 +458,18 @@ extern "C" cc_status cutcell_merge_map(const cc_grid *grid, cc_geom *g, int64_t 
     hipLaunchKernelGGL(k_lattice_class, gb, tb, 0, s, d, g->H, g->cls, g->vcls);
     hipLaunchKernelGGL(k_column_bands, dim3(blocks_for(nc, 256)), tb, 0, s, d, g->V, g->Ax, g->Ay, g->Az,
                        g->cls, g->gnext, g->vcls, g->colk);
-    return launch_status("cutcell_merge_map");
+    cc_status rc = launch_status("cutcell_merge_map");
+    if (rc != CC_OK) return rc;
+    // band height: the highest cell band or lattice band top over all columns
+    std::vector<int32_t> bands((size_t)(2 * nc));
+    hipError_t e = hipMemcpyAsync(bands.data(), g->colk, sizeof(int32_t) * 2 * nc, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        set_error("cutcell_merge_map: %s", hipGetErrorString(e));
+        return CC_EDEVICE;
+    }
+    int32_t top = 1;
+    for (int32_t v : bands) top = v > top ? v : top;
+    g->kband = top < d.nz ? top : d.nz;
+    return CC_OK;
 }

@@ -39,7 +39,8 @@ struct Geo {
     const double *H, *V, *Ax, *Ay, *Az, *nrm, *Vgroup;
     const int8_t *cls, *vcls;
     const int32_t *master, *gnext, *colk;
-    void *ws;  // optional stage workspace (two-pass update), may be null
+    void *ws;   // optional stage workspace (two-pass update), may be null
+    int kband;  // cells and lattice points at k >= kband are regular (0: unknown)
 };
 
 constexpr int EOS_TERMS = 11;  // binomial series terms of (1+x)^gamma - 1 (double; float uses 6)
@@ -350,7 +351,9 @@ __device__ __forceinline__ void load_point(const Dims &d, const Geo &G, const SI
     }
 }
 
-template <typename T, int MODE, typename VW>
+// REG: the point lies at or above the band height (regular cell, predicted lattice point), so the
+// band and gather paths are not compiled in
+template <typename T, int MODE, typename VW, bool REG = false>
 __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &qs,
                                             const PointIn<T> &pin, const SOut<T> &qo, double cdt, int final_stage,
                                             int i, int j, int k, const VW &V,
@@ -364,7 +367,7 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
     bool bad = false;
 
     // ---- scalars ----
-    const bool band = k < pin.kcell;
+    const bool band = !REG && k < pin.kcell;
     const int8_t cl = band ? G.cls[c] : (int8_t)CC_OPEN;
     if (cl == CC_OPEN || cl == CC_ORPHAN) {
         double L0, L1;
@@ -488,7 +491,7 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
     }
 
     // ---- momentum at the lattice point (i,j,k) ----
-    const bool pred = k >= pin.klat || G.vcls[c] == CC_PRED;
+    const bool pred = REG || k >= pin.klat || G.vcls[c] == CC_PRED;
     if (pred) {
         const R h = (R)0.5, q4 = (R)0.25;
         R u[7][3];
@@ -584,7 +587,8 @@ struct OwnRange { int lo[3], hi[3]; };
 
 // TX x TY x TZ threads; each thread updates KP points spaced TZ apart in k, so the tile spans
 // TX x TY x (TZ KP) cells
-template <typename T, int TX, int TY, int TZ, int MODE, int KP = 1>
+// REG: every point of the tile lies at or above the band height
+template <typename T, int TX, int TY, int TZ, int MODE, int KP = 1, bool REG = false>
 __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &qs,
                                           const SIn<T> &qn, const SOut<T> &qo, double cdt, int final_stage,
                                           const int i0, const int j0, const int k0, int64_t *st, const OwnRange &ownr)
@@ -775,21 +779,22 @@ __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy
             V.csj = TL::CZ; V.lsj = TL::LZ; V.nb = NB; V.kb = tzp + 2;
             const bool ghost = i < ownr.lo[0] || i >= ownr.hi[0] || j < ownr.lo[1] || j >= ownr.hi[1] ||
                                k < ownr.lo[2] || k >= ownr.hi[2];
-            stage_point<T, MODE, LView<R>>(d, G, P, qs, pin[p], qo, cdt, final_stage, i, j, k, V, st, ghost);
+            stage_point<T, MODE, LView<R>, REG>(d, G, P, qs, pin[p], qo, cdt, final_stage, i, j, k, V, st, ghost);
         }
     }
 }
 
-template <typename T, int TX, int TY, int TZ, int MODE, int MINW, int KP = 1>
+// the launch covers the k-tiles [bk0, bk0 + nbz); REG: all of them lie at or above the band height
+template <typename T, int TX, int TY, int TZ, int MODE, int MINW, int KP = 1, bool REG = false>
 __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     k_stage_tiled(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn, SOut<T> qo, double cdt, int final_stage,
-                  int nbx, int nby, int nbz, int64_t *st)
+                  int nbx, int nby, int nbz, int bk0, int64_t *st)
 {
     int bi, bj, bk;
     tile_of_block(nbx, nby, nbz, bi, bj, bk);
     const OwnRange all{{0, 0, 0}, {d.nx, d.ny, d.nz}};
-    tile_body<T, TX, TY, TZ, MODE, KP>(d, G, P, qs, qn, qo, cdt, final_stage, bi * TX, bj * TY, bk * TZ * KP, st,
-                                       all);
+    tile_body<T, TX, TY, TZ, MODE, KP, REG>(d, G, P, qs, qn, qo, cdt, final_stage, bi * TX, bj * TY,
+                                            (bk0 + bk) * TZ * KP, st, all);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1116,7 +1121,7 @@ inline bool make_views(const char *what, const cc_grid *grid, const cc_phys *phy
     if (prec != CC_F64 && prec != CC_F32_PERT) { set_error("%s: unknown precision %d", what, (int)prec); return false; }
     d = dims_of(grid);
     G = Geo{g->H, g->V, g->Ax, g->Ay, g->Az, g->nrm, g->Vgroup, g->cls, g->vcls, g->master, g->gnext, g->colk,
-            g->stage_ws};
+            g->stage_ws, g->kband};
     double cv = phys->cp - phys->rd;
     P.rhob = base; P.rthb = base + d.nz; P.pb = base + 2 * d.nz; P.thb = base + 3 * d.nz;
     P.irthb = base + 4 * d.nz; P.rhobc = base + 5 * d.nz;

@@ -162,9 +162,19 @@ template <typename T, int TX, int TY, int TZ, int MODE, int MINW = 1, int KP = 1
 static void launch_tiled(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
                          cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
 {
-    int nbx = (d.nx + TX - 1) / TX, nby = (d.ny + TY - 1) / TY, nbz = (d.nz + TZ * KP - 1) / (TZ * KP);
-    hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, MINW, KP>), dim3(nbx * nby * nbz), dim3(TX * TY * TZ), 0, s,
-                       d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, nbx, nby, nbz, st);
+    constexpr int KT = TZ * KP;
+    int nbx = (d.nx + TX - 1) / TX, nby = (d.ny + TY - 1) / TY, nbz = (d.nz + KT - 1) / KT;
+    // k-tiles at or above the band height take the kernel without the band paths
+    int kb = (MODE == 0 && G.kband >= 1 && G.kband <= d.nz) ? (G.kband + KT - 1) / KT : nbz;
+    if (kb > nbz) kb = nbz;
+    if (kb > 0)
+        hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, MINW, KP, false>), dim3(nbx * nby * kb),
+                           dim3(TX * TY * TZ), 0, s, d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt,
+                           final_stage, nbx, nby, kb, 0, st);
+    if (nbz > kb)
+        hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, MINW, KP, true>), dim3(nbx * nby * (nbz - kb)),
+                           dim3(TX * TY * TZ), 0, s, d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt,
+                           final_stage, nbx, nby, nbz - kb, kb, st);
 }
 
 // the tile of a grid: the requested shape if the grid holds at least one tile per direction in x

@@ -38,7 +38,8 @@ class cc_phys(C.Structure):
 
 class cc_geom(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("H", "V", "Ax", "Ay", "Az", "col", "nrm", "cls", "dir",
-                                           "vcls", "master", "gnext", "Vgroup", "colk", "stage_ws")]
+                                           "vcls", "master", "gnext", "Vgroup", "colk", "stage_ws")] + \
+               [("kband", C.c_int32)]
 
 
 class cc_state(C.Structure):
