@@ -235,7 +235,7 @@ using namespace cc;
 // host: batch state
 // ------------------------------------------------------------------------------------------------
 struct Level {
-    int nblk = 0, ntiles = 0, ncols = 0, cur = 0;
+    int nblk = 0, ntiles = 0, ntilesr = 0, ncols = 0, cur = 0;  // band tiles, above-band tiles, columns
     size_t desc_off = 0;
     size_t same_off = 0, inj_off = 0, res_off = 0, slot_off = 0, corr_off = 0, reg_off = 0;
     int nsame = 0, ninj = 0, nres = 0, nslot = 0, ncorr = 0;
@@ -263,8 +263,12 @@ void launch_batch_stage(const cc_batch_s *b, int l, int rn, int rs, int ro, doub
                         hipStream_t s)
 {
     const Level &L = b->lev[l];
-    hipLaunchKernelGGL((k_stage_batch<T, TX, TY, TZ, 0, MINW>), dim3(L.ntiles), dim3(TX * TY * TZ), 0, s,
-                       descs<T>(b, l), L.nblk, L.ntiles, rn, rs, ro, cdt, fin, st);
+    if (L.ntiles > 0)
+        hipLaunchKernelGGL((k_stage_batch<T, TX, TY, TZ, 0, MINW, false>), dim3(L.ntiles), dim3(TX * TY * TZ), 0, s,
+                           descs<T>(b, l), L.nblk, L.ntiles, rn, rs, ro, cdt, fin, st);
+    if (L.ntilesr > 0)
+        hipLaunchKernelGGL((k_stage_batch<T, TX, TY, TZ, 0, MINW, true>), dim3(L.ntilesr), dim3(TX * TY * TZ), 0, s,
+                           descs<T>(b, l), L.nblk, L.ntilesr, rn, rs, ro, cdt, fin, st);
 }
 
 template <typename T>
@@ -286,6 +290,8 @@ void level_stage(cc_batch_s *b, int l, int rn, int rs, int ro, double cdt, int f
     case 1: launch_batch_stage<T, 4, 4, 16, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
     case 8: launch_batch_stage<T, 2, 2, 64, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
     case 9: launch_batch_stage<T, 8, 8, 8, 6>(b, l, rn, rs, ro, cdt, fin, st, s); break;
+    case 7: launch_batch_stage<T, 8, 8, 16, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
+    case 12: launch_batch_stage<T, 4, 8, 16, 6>(b, l, rn, rs, ro, cdt, fin, st, s); break;
     default: launch_batch_stage<T, 8, 8, 8, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
     }
     if (fin) {
@@ -565,7 +571,7 @@ bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, i
 {
     host.assign(sizeof(BlockDesc<T>) * ids.size(), 0);
     BlockDesc<T> *h = (BlockDesc<T> *)host.data();
-    int tiles = 0, cols = 0;
+    int tiles = 0, tilesr = 0, cols = 0;
     for (size_t m = 0; m < ids.size(); ++m) {
         const cc_block &b = B[ids[m]];
         Dims d; Geo G; Phy P;
@@ -589,13 +595,24 @@ bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, i
         h[m].nbx = (h[m].rhi[0] - h[m].rlo[0] + TX - 1) / TX;
         h[m].nby = (h[m].rhi[1] - h[m].rlo[1] + TY - 1) / TY;
         h[m].nbz = (h[m].rhi[2] - h[m].rlo[2] + TZ - 1) / TZ;
+        // k-tiles starting below the band height take the full kernel
+        int kbt = h[m].nbz;
+        if (G.kband >= 1 && G.kband <= d.nz) {
+            int above = G.kband - h[m].rlo[2];
+            kbt = above <= 0 ? 0 : (above + TZ - 1) / TZ;
+            if (kbt > h[m].nbz) kbt = h[m].nbz;
+        }
+        h[m].kbt = kbt;
         h[m].tile0 = tiles;
+        h[m].tile0r = tilesr;
         h[m].col0 = cols;
-        tiles += h[m].nbx * h[m].nby * h[m].nbz;
+        tiles += h[m].nbx * h[m].nby * kbt;
+        tilesr += h[m].nbx * h[m].nby * (h[m].nbz - kbt);
         cols += (h[m].rhi[0] - h[m].rlo[0]) * (h[m].rhi[1] - h[m].rlo[1]);
     }
     L.nblk = (int)ids.size();
     L.ntiles = tiles;
+    L.ntilesr = tilesr;
     L.ncols = cols;
     return true;
 }
@@ -608,9 +625,11 @@ int batch_tile(const cc_block *B, int n, int tile, int &TX, int &TY, int &TZ)
             if (B[m].grid.nx < tx || B[m].grid.ny < ty) return false;
         return true;
     };
-    int id = (tile == 1 || tile == 8 || tile == 9) ? tile : 0;
+    int id = (tile == 1 || tile == 7 || tile == 8 || tile == 9 || tile == 12) ? tile : 0;
     auto shape = [&](int i) {
-        TX = i == 1 ? 4 : (i == 8 ? 2 : 8); TY = TX; TZ = i == 1 ? 16 : (i == 8 ? 64 : 8);
+        TX = (i == 1 || i == 12) ? 4 : (i == 8 ? 2 : 8);
+        TY = i == 1 ? 4 : (i == 8 ? 2 : 8);
+        TZ = (i == 1 || i == 7 || i == 12) ? 16 : (i == 8 ? 64 : 8);
     };
     shape(id);
     if (!fits(TX, TY)) { id = fits(4, 4) ? 1 : 8; shape(id); }

@@ -891,7 +891,10 @@ struct BlockDesc {
     Phy P;
     SOut<T> q[3];       // the block's three state buffers
     int nbx, nby, nbz;  // tiles of the update kernel
-    int tile0;          // first tile of the block in the batched update grid
+    int kbt;            // the first kbt k-tiles reach below the band height (full kernel), the rest
+                        // lie above it (kernel without the band paths)
+    int tile0;          // first band tile of the block in the batched band-tile grid
+    int tile0r;         // first tile of the block in the batched above-band grid
     int col0;           // first column of the block in the batched diagnostic grid
     int ilo[3], ihi[3];  // the block's own cells (the rest of the grid is ghost cells)
     int rlo[3], rhi[3];  // cells the batch updates: own cells and the ghost cells no same-level block
@@ -904,7 +907,9 @@ __device__ __forceinline__ SIn<T> as_in(const SOut<T> &q)
     return SIn<T>{q.rho, q.rth, q.mu, q.mv, q.mw, q.rho_lo, q.rth_lo};
 }
 
-template <typename T, int TX, int TY, int TZ, int MODE, int MINW>
+// REG = false: the band tiles of every block (full kernel); REG = true: the tiles above the band
+// height (band paths compiled out)
+template <typename T, int TX, int TY, int TZ, int MODE, int MINW, bool REG = false>
 __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     k_stage_batch(const BlockDesc<T> *__restrict__ desc, int nblk, int ntiles, int rn, int rs, int ro,
                   double cdt, int final_stage, int64_t *st)
@@ -916,15 +921,17 @@ __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     int lo = 0, hi = nblk - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (desc[mid].tile0 <= lb) lo = mid;
+        if ((REG ? desc[mid].tile0r : desc[mid].tile0) <= lb) lo = mid;
         else hi = mid - 1;
     }
     const BlockDesc<T> &D = desc[lo];
-    int t = lb - D.tile0;
-    int bk = t % D.nbz, t2 = t / D.nbz, bj = t2 % D.nby, bi = t2 / D.nby;
-    tile_body<T, TX, TY, TZ, MODE>(D.d, D.G, D.P, as_in(D.q[rs]), as_in(D.q[rn]), D.q[ro], cdt, final_stage,
-                                   D.rlo[0] + bi * TX, D.rlo[1] + bj * TY, D.rlo[2] + bk * TZ, st,
-                                   OwnRange{{D.ilo[0], D.ilo[1], D.ilo[2]}, {D.ihi[0], D.ihi[1], D.ihi[2]}});
+    const int nk = REG ? D.nbz - D.kbt : D.kbt;
+    int t = lb - (REG ? D.tile0r : D.tile0);
+    int bk = t % nk, t2 = t / nk, bj = t2 % D.nby, bi = t2 / D.nby;
+    if (REG) bk += D.kbt;
+    tile_body<T, TX, TY, TZ, MODE, 1, REG>(D.d, D.G, D.P, as_in(D.q[rs]), as_in(D.q[rn]), D.q[ro], cdt, final_stage,
+                                           D.rlo[0] + bi * TX, D.rlo[1] + bj * TY, D.rlo[2] + bk * TZ, st,
+                                           OwnRange{{D.ilo[0], D.ilo[1], D.ilo[2]}, {D.ihi[0], D.ihi[1], D.ihi[2]}});
 }
 
 // ------------------------------------------------------------------------------------------------
