@@ -6,9 +6,11 @@ fused tendency+update kernel and the velocity-diagnostic kernel.  The metric is 
 cell-updates per second per stage (nx*ny*nz cells x 3 stages per step), for the FP32 perturbation
 form (headline) and the plain FP64 path (reported beside it).
 
-The roofline object describes the dominant kernel (the fused update): algorithmic bytes per launch
-(5 fields read and written per cell, plus q_n read in stages 2 and 3) over the launch duration
-measured with HIP events on the launch stream, against the 8 TB/s HBM peak.  Measured HBM traffic
+The roofline object describes the dominant kernel, the fused update of one stage, which runs as two
+back-to-back launches of the same kernel template (the k-tiles reaching below the band height, then
+the ones above it with the band paths compiled out).  Its algorithmic bytes per stage (5 fields read
+and written per cell, plus q_n read in stages 2 and 3) are divided by the stage's update duration,
+measured with HIP events around the two launches on the launch stream, against the 8 TB/s HBM peak.  Measured HBM traffic
 comes from a committed rocprofv3 counter summary when it was taken on the current kernel source.
 The CPU baseline times the FP64 oracle on this machine's host cores on one step of the workload.
 
@@ -99,9 +101,7 @@ def run_gpu(cfg, prec: str, steps: int, warmup: int, tile: int = 0):
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_stage_tiled<{},{},{},{},0,{}>".format(
-                "double" if prec == "f64" else "float", *autotune.TILE_IDS[tuned["tile"]],
-                max(1, autotune.TILE_MINW.get(tuned["tile"], 1))),
+            "kernel": " + ".join(autotune.kernel_names(tuned["tile"], prec)),
             "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(avg_bytes)}
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))

@@ -24,6 +24,21 @@ TILE_IDS = {1: (4, 4, 16), 2: (8, 4, 16), 3: (4, 8, 16), 4: (8, 8, 8), 5: (2, 4,
             13: (8, 8, 16), 14: (8, 8, 16), 15: (8, 8, 8), 16: (8, 8, 8), 17: (4, 4, 16), 18: (8, 8, 8),
             19: (8, 8, 16), 20: (1, 1, 1)}
 TILE_MINW = {9: 6, 10: 8, 11: 8, 12: 6, 13: 4, 14: 6, 15: 6, 16: 8, 17: 8, 18: 4, 19: 6}
+# id -> template arguments of k_stage_tiled: threads per tile (TX, TY, TZ), minimum waves, points per
+# thread along k
+TILE_TEMPLATE = {0: (8, 8, 8, 1, 1), 1: (4, 4, 16, 1, 1), 2: (8, 4, 16, 1, 1), 3: (4, 8, 16, 1, 1),
+                 4: (8, 8, 8, 1, 1), 5: (2, 4, 32, 1, 1), 6: (4, 4, 32, 1, 1), 7: (8, 8, 16, 1, 1),
+                 8: (2, 2, 64, 1, 1), 9: (8, 8, 8, 6, 1), 10: (8, 8, 8, 8, 1), 11: (4, 4, 16, 8, 1),
+                 12: (4, 8, 16, 6, 1), 13: (8, 8, 8, 4, 2), 14: (8, 8, 8, 6, 2), 15: (8, 8, 4, 6, 2),
+                 16: (8, 8, 2, 8, 4), 17: (4, 4, 8, 8, 2), 18: (8, 8, 4, 4, 2), 19: (8, 8, 4, 6, 4)}
+
+
+def kernel_names(tile: int, prec: str):
+    """rocprofv3 names (without arguments) of the two launches of one update stage: the tiles that
+    reach below the band height, then the tiles above it."""
+    t = "double" if prec == "f64" else "float"
+    tx, ty, tz, w, kp = TILE_TEMPLATE[tile]
+    return tuple(f"cc::k_stage_tiled<{t}, {tx}, {ty}, {tz}, 0, {w}, {kp}, {r}>" for r in ("false", "true"))
 
 
 def key(dom) -> str:
