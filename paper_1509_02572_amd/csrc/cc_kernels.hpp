@@ -418,23 +418,35 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
             group_scalar_tendency<T>(d, G, P, qs, c, L);
             L0 = L[0]; L1 = L[1];
         } else {
-            // single-cell group in the band: apertures, group volume and neighbour masters
+            // single-cell group in the band: apertures, group volume and neighbour masters.  The
+            // apertures and neighbour masters of the six faces are read together first.
+            double Af[6];
+            int32_t mnf[6];
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                int axis = f >> 1, plus = f & 1;
+                int da = axis == 0 ? (plus ? 1 : -1) : 0, db = axis == 1 ? (plus ? 1 : -1) : 0;
+                int dc = axis == 2 ? (plus ? 1 : -1) : 0;
+                Af[f] = 0.0;
+                mnf[f] = -1;
+                if (axis == 2 && (k + dc < 0 || k + dc >= nz)) continue;  // ground and rigid lid
+                int ip = wrap1(i + (axis == 0 && plus), nx), jp = wrap1(j + (axis == 1 && plus), ny);
+                unsigned fu = __umul24(__umul24(ip, ny) + jp, nzs) + k + (axis == 2 && plus);
+                Af[f] = axis == 0 ? G.Ax[fu] : (axis == 1 ? G.Ay[fu] : G.Az[fu]);
+                int in = wrap1(i + da, nx), jn = wrap1(j + db, ny);
+                mnf[f] = G.master[__umul24(__umul24(in, ny) + jn, nzs) + k + dc];
+            }
+            const double vgroup = G.Vgroup[c];
             double r0 = 0.0, r1 = 0.0, g0 = 0.0, g1 = 0.0;
             for (int f = 0; f < 6; ++f) {
                 int axis = f >> 1, plus = f & 1;
                 int da = 0, db = 0, dc = 0;
                 if (axis == 0) da = plus ? 1 : -1;
                 else if (axis == 1) db = plus ? 1 : -1;
-                else {
-                    dc = plus ? 1 : -1;
-                    if (k + dc < 0 || k + dc >= nz) continue;  // ground and rigid lid
-                }
-                int ip = wrap1(i + (axis == 0 && plus), nx), jp = wrap1(j + (axis == 1 && plus), ny);
-                unsigned fu = __umul24(__umul24(ip, ny) + jp, nzs) + k + (axis == 2 && plus);
-                double A = axis == 0 ? G.Ax[fu] : (axis == 1 ? G.Ay[fu] : G.Az[fu]);
-                if (A == 0.0) continue;
-                int in = wrap1(i + da, nx), jn = wrap1(j + db, ny);
-                int32_t mn = G.master[__umul24(__umul24(in, ny) + jn, nzs) + k + dc];
+                else dc = plus ? 1 : -1;
+                const double A = Af[f];
+                if (A == 0.0) continue;  // closed face (terrain, solid neighbour, ground, lid)
+                const int32_t mn = mnf[f];
                 if (mn < 0) continue;
                 int kn = mn % nzs;
                 int fa = axis == 0 && plus, fb = axis == 1 && plus, fc = axis == 2 && plus;
@@ -463,7 +475,7 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
                 if (plus) { r0 += (double)f0; r1 += (double)f1; g0 += h0; g1 += h1; }
                 else { r0 -= (double)f0; r1 -= (double)f1; g0 -= h0; g1 -= h1; }
             }
-            double vol = G.Vgroup[c] * P.dV;
+            double vol = vgroup * P.dV;
             L0 = -(g0 + r0) / vol;
             L1 = -(g1 + r1) / vol;
         }
