@@ -7,8 +7,9 @@ cell-updates per second per stage (nx*ny*nz cells x 3 stages per step), for the 
 form (headline) and the plain FP64 path (reported beside it).
 
 The roofline object describes the dominant kernel, the fused update of one stage, which runs as two
-back-to-back launches of the same kernel template (the k-tiles reaching below the band height, then
-the ones above it with the band paths compiled out).  Its algorithmic bytes per stage (5 fields read
+back-to-back launches of the same kernel template: every point at or above its column's band top
+(over the whole grid, the band paths compiled out), then the points below it (cut, merged and
+next-to-terrain cells; lattice points not predicted) in one-wave tiles.  Its algorithmic bytes per stage (5 fields read
 and written per cell, plus q_n read in stages 2 and 3) are divided by the stage's update duration,
 measured with HIP events around the two launches on the launch stream, against the 8 TB/s HBM peak.  Measured HBM traffic
 comes from a committed rocprofv3 counter summary when it was taken on the current kernel source.

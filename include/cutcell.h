@@ -102,9 +102,13 @@ typedef struct {
                                  diagnosed point, absorbed or solid cell */
     void *stage_ws;           /* optional workspace of cutcell_stage_workspace_bytes() bytes: enables
                                  the two-pass update (cc_grid.tile = 20); NULL otherwise */
-    int32_t kband;            /* host value set by cutcell_merge_map: every cell and lattice point at
-                                 k >= kband is regular (above all columns' bands); the update runs a
-                                 kernel without the band paths there.  0 or out of [1, nz]: unknown
+    int32_t kband;            /* host value set by cutcell_merge_map: the highest column band top.
+                                 A column's band top is one above its highest point that is not
+                                 regular (a cell that is cut, merged, or next to a closed face or a
+                                 cell that is not open; a lattice point above the ground row that is
+                                 not predicted).  The update runs the points at or above their
+                                 column's band top with a kernel without the band paths and the rest
+                                 with the full kernel over k < kband.  0 or out of [1, nz]: unknown
                                  (the full kernel everywhere) */
 } cc_geom;
 

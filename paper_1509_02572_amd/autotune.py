@@ -33,12 +33,16 @@ TILE_TEMPLATE = {0: (8, 8, 8, 1, 1), 1: (4, 4, 16, 1, 1), 2: (8, 4, 16, 1, 1), 3
                  16: (8, 8, 2, 8, 4), 17: (4, 4, 8, 8, 2), 18: (8, 8, 4, 4, 2), 19: (8, 8, 4, 6, 4)}
 
 
-def kernel_names(tile: int, prec: str):
-    """rocprofv3 names (without arguments) of the two launches of one update stage: the tiles that
-    reach below the band height, then the tiles above it."""
+def kernel_names(tile: int, prec: str, small: bool = False):
+    """rocprofv3 names (without arguments) of the two launches of one update stage on a grid with a
+    known band height: the points at or above their column's band top over the whole grid (the
+    kernel without the band paths), then the points below it in one-wave tiles (8x8x1; 4x4x4 on a
+    grid with ``small`` = fewer than 8 columns in x or y)."""
     t = "double" if prec == "f64" else "float"
     tx, ty, tz, w, kp = TILE_TEMPLATE[tile]
-    return tuple(f"cc::k_stage_tiled<{t}, {tx}, {ty}, {tz}, 0, {w}, {kp}, {r}>" for r in ("false", "true"))
+    band = "4, 4, 4" if small else "8, 8, 1"
+    return (f"cc::k_stage_tiled<{t}, {tx}, {ty}, {tz}, 0, {w}, {kp}, true, 1>",
+            f"cc::k_stage_tiled<{t}, {band}, 0, 1, 1, false, 2>")
 
 
 def key(dom) -> str:

@@ -393,12 +393,14 @@ __global__ void k_column_bands(Dims d, const double *__restrict__ V, const doubl
         int8_t cl = cls[c];
         if (vcls[c] != CC_PRED) klat = k + 1;
         if (cl == CC_ABSORBED || cl == CC_SOLID) kdiag = k + 1;
-        bool sp = k == 0 || cl != CC_OPEN || gnext[c] != -1 || V[c] != 1.0;
+        // a regular cell: full, open, unmerged, every face fully open and every neighbour open; the
+        // ground (below k = 0) and the lid (above nz-1) are closed faces the regular update skips
+        bool sp = cl != CC_OPEN || gnext[c] != -1 || V[c] != 1.0;
         sp = sp || Ax[c] != 1.0 || Ax[cidx(d, i + 1, j, k)] != 1.0 || Ay[c] != 1.0 ||
-             Ay[cidx(d, i, j + 1, k)] != 1.0 || Az[c] != 1.0 || (k + 1 < d.nz && Az[c + 1] != 1.0);
+             Ay[cidx(d, i, j + 1, k)] != 1.0 || (k > 0 && Az[c] != 1.0) || (k + 1 < d.nz && Az[c + 1] != 1.0);
         sp = sp || cls[cidx(d, i - 1, j, k)] != CC_OPEN || cls[cidx(d, i + 1, j, k)] != CC_OPEN ||
              cls[cidx(d, i, j - 1, k)] != CC_OPEN || cls[cidx(d, i, j + 1, k)] != CC_OPEN ||
-             cls[c - 1] != CC_OPEN || (k + 1 < d.nz && cls[c + 1] != CC_OPEN);
+             (k > 0 && cls[c - 1] != CC_OPEN) || (k + 1 < d.nz && cls[c + 1] != CC_OPEN);
         if (sp) kcell = k + 1;
     }
     colk[t] = kcell;
@@ -469,7 +471,10 @@ extern "C" cc_status cutcell_merge_map(const cc_grid *grid, cc_geom *g, int64_t 
         return CC_EDEVICE;
     }
     int32_t top = 1;
-    for (int32_t v : bands) top = v > top ? v : top;
+    for (int64_t c = 0; c < nc; ++c) {
+        int32_t b = band_top(bands[(size_t)c], bands[(size_t)(nc + c)]);
+        top = b > top ? b : top;
+    }
     g->kband = top < d.nz ? top : d.nz;
     return CC_OK;
 }

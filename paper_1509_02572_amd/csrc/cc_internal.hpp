@@ -46,6 +46,16 @@ __host__ __device__ __forceinline__ void unidx(const Dims &d, int64_t c, int &i,
 enum { ST_UNMERGEABLE = 0, ST_NOPLANE = 1, ST_NONFINITE = 2, ST_TERRAIN = 3, ST_GROUPSIZE = 4, ST_INTERFACE = 5,
        ST_STALE = 6 };
 
+// band top of a column from its cell band (one above its highest cell that is not regular) and its
+// lattice band (one above its highest lattice point that is not predicted): the ground row K = 0 is
+// never predicted, so a lattice band of 1 adds nothing.  Every point at or above the band top takes
+// the regular update.
+__host__ __device__ __forceinline__ int band_top(int kcell, int klat)
+{
+    const int kl = klat > 1 ? klat : 0;
+    return kcell > kl ? kcell : kl;
+}
+
 __device__ __forceinline__ void count_status(int64_t *st, int which, int64_t n = 1)
 {
     if (st) atomicAdd(reinterpret_cast<unsigned long long *>(st + which), (unsigned long long)n);

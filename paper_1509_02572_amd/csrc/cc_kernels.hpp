@@ -40,7 +40,7 @@ struct Geo {
     const int8_t *cls, *vcls;
     const int32_t *master, *gnext, *colk;
     void *ws;   // optional stage workspace (two-pass update), may be null
-    int kband;  // cells and lattice points at k >= kband are regular (0: unknown)
+    int kband;  // highest column band top: every point at k >= kband is regular (0: unknown)
 };
 
 constexpr int EOS_TERMS = 11;  // binomial series terms of (1+x)^gamma - 1 (double; float uses 6)
@@ -397,12 +397,14 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
                 r0 += (double)fp0 - (double)fm0;
                 r1 += (double)fp1 - (double)fm1;
             }
-            {  // z faces (k >= 1 in the regular region; the rigid lid closes the top of nz-1)
-                R sm = (V.w[V.L(0, 0, 0)] + V.w[V.L(1, 0, 0)]) + (V.w[V.L(0, 1, 0)] + V.w[V.L(1, 1, 0)]);
-                scalar_face_flux<R>(sm, ASz, (R)0, V.B(4, 0), V.B(5, 0), V.rho[V.C(0, 0, -1)], rc0,
-                                    V.rth[V.C(0, 0, -1)], rc1, fm0, fm1);
-                r0 -= (double)fm0;
-                r1 -= (double)fm1;
+            {  // z faces (the ground closes the bottom of k = 0, the rigid lid the top of nz-1)
+                if (k > 0) {
+                    R sm = (V.w[V.L(0, 0, 0)] + V.w[V.L(1, 0, 0)]) + (V.w[V.L(0, 1, 0)] + V.w[V.L(1, 1, 0)]);
+                    scalar_face_flux<R>(sm, ASz, (R)0, V.B(4, 0), V.B(5, 0), V.rho[V.C(0, 0, -1)], rc0,
+                                        V.rth[V.C(0, 0, -1)], rc1, fm0, fm1);
+                    r0 -= (double)fm0;
+                    r1 -= (double)fm1;
+                }
                 if (k + 1 < nz) {
                     R sp = (V.w[V.L(0, 0, 1)] + V.w[V.L(1, 0, 1)]) + (V.w[V.L(0, 1, 1)] + V.w[V.L(1, 1, 1)]);
                     scalar_face_flux<R>(sp, ASz, (R)0, V.B(4, 1), V.B(5, 1), rc0, V.rho[V.C(0, 0, 1)], rc1,
@@ -503,7 +505,8 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
     }
 
     // ---- momentum at the lattice point (i,j,k) ----
-    const bool pred = REG || k >= pin.klat || G.vcls[c] == CC_PRED;
+    // (REG: every lattice point of the tile above the ground row is predicted)
+    const bool pred = REG ? k >= 1 : (k >= pin.klat || G.vcls[c] == CC_PRED);
     if (pred) {
         const R h = (R)0.5, q4 = (R)0.25;
         R u[7][3];
@@ -599,8 +602,10 @@ struct OwnRange { int lo[3], hi[3]; };
 
 // TX x TY x TZ threads; each thread updates KP points spaced TZ apart in k, so the tile spans
 // TX x TY x (TZ KP) cells
-// REG: every point of the tile lies at or above the band height
-template <typename T, int TX, int TY, int TZ, int MODE, int KP = 1, bool REG = false>
+// REG: every point the tile updates takes the regular update
+// SEL: 0 updates every point of the tile, 1 only the points at or above their column's band top, 2
+// only the points below it
+template <typename T, int TX, int TY, int TZ, int MODE, int KP = 1, bool REG = false, int SEL = 0>
 __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &qs,
                                           const SIn<T> &qn, const SOut<T> &qo, double cdt, int final_stage,
                                           const int i0, const int j0, const int k0, int64_t *st, const OwnRange &ownr)
@@ -781,7 +786,9 @@ __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy
 #pragma unroll
     for (int p = 0; p < KP; ++p) {
         const int tzp = tz + p * TZ, k = k0 + tzp;
-        if (i < nx && j < ny && k < nz) {
+        bool mine = i < nx && j < ny && k < nz;
+        if (SEL != 0 && mine) mine = (k >= band_top(pin[p].kcell, pin[p].klat)) == (SEL == 1);
+        if (mine) {
             LView<R> V;
             V.rho = s_rho; V.rth = s_rth; V.pp = s_pp; V.u = s_u; V.v = s_v; V.w = s_w; V.b = &s_b[0][0];
             for (int m = 0; m < 3; ++m) {
@@ -796,17 +803,31 @@ __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy
     }
 }
 
-// the launch covers the k-tiles [bk0, bk0 + nbz); REG: all of them lie at or above the band height
-template <typename T, int TX, int TY, int TZ, int MODE, int MINW, int KP = 1, bool REG = false>
+// the launch covers the k-tiles [bk0, bk0 + nbz); REG: every point the launch updates takes the
+// regular update; SEL as in tile_body (SEL 2: a tile with no point below its column's band top ends
+// at once)
+template <typename T, int TX, int TY, int TZ, int MODE, int MINW, int KP = 1, bool REG = false, int SEL = 0>
 __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     k_stage_tiled(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn, SOut<T> qo, double cdt, int final_stage,
                   int nbx, int nby, int nbz, int bk0, int64_t *st)
 {
+    static_assert(SEL != 2 || KP == 1, "band tiles hold one point per thread");
     int bi, bj, bk;
     tile_of_block(nbx, nby, nbz, bi, bj, bk);
+    const int k0 = (bk0 + bk) * TZ * KP;
+    if (SEL == 2) {
+        const int t = threadIdx.x;
+        const int i = bi * TX + t / (TY * TZ), j = bj * TY + (t / TZ) % TY, k = k0 + t % TZ;
+        bool any = false;
+        if (i < d.nx && j < d.ny && k < d.nz) {
+            const unsigned hc = __umul24(i, d.ny) + j;
+            any = k < band_top(G.colk[hc], G.colk[(unsigned)(d.nx * d.ny) + hc]);
+        }
+        if (!__syncthreads_or(any)) return;
+    }
     const OwnRange all{{0, 0, 0}, {d.nx, d.ny, d.nz}};
-    tile_body<T, TX, TY, TZ, MODE, KP, REG>(d, G, P, qs, qn, qo, cdt, final_stage, bi * TX, bj * TY,
-                                            (bk0 + bk) * TZ * KP, st, all);
+    tile_body<T, TX, TY, TZ, MODE, KP, REG, SEL>(d, G, P, qs, qn, qo, cdt, final_stage, bi * TX, bj * TY, k0, st,
+                                                 all);
 }
 
 // ------------------------------------------------------------------------------------------------

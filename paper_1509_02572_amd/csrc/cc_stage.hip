@@ -158,23 +158,39 @@ constexpr TileShape TILES[] = {{8, 8, 8, 1}, {4, 4, 16, 1}, {8, 4, 16, 1}, {4, 8
                                {1, 1, 1, 1}};  // 20: two-pass (prepare, then one point per thread)
 constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
 
+template <typename T, int TX, int TY, int TZ, int MODE>
+static void launch_band(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
+                        cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
+{
+    int nbx = (d.nx + TX - 1) / TX, nby = (d.ny + TY - 1) / TY, nbz = (G.kband + TZ - 1) / TZ;
+    hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, 1, 1, false, 2>), dim3(nbx * nby * nbz), dim3(TX * TY * TZ),
+                       0, s, d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, nbx, nby, nbz,
+                       0, st);
+}
+
 template <typename T, int TX, int TY, int TZ, int MODE, int MINW = 1, int KP = 1>
 static void launch_tiled(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
                          cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
 {
     constexpr int KT = TZ * KP;
     int nbx = (d.nx + TX - 1) / TX, nby = (d.ny + TY - 1) / TY, nbz = (d.nz + KT - 1) / KT;
-    // k-tiles at or above the band height take the kernel without the band paths
-    int kb = (MODE == 0 && G.kband >= 1 && G.kband <= d.nz) ? (G.kband + KT - 1) / KT : nbz;
-    if (kb > nbz) kb = nbz;
-    if (kb > 0)
-        hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, MINW, KP, false>), dim3(nbx * nby * kb),
-                           dim3(TX * TY * TZ), 0, s, d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt,
-                           final_stage, nbx, nby, kb, 0, st);
-    if (nbz > kb)
-        hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, MINW, KP, true>), dim3(nbx * nby * (nbz - kb)),
-                           dim3(TX * TY * TZ), 0, s, d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt,
-                           final_stage, nbx, nby, nbz - kb, kb, st);
+    if (!(MODE == 0 && G.kband >= 1 && G.kband <= d.nz)) {  // band height unknown: the full kernel
+        hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, MINW, KP>), dim3(nbx * nby * nbz), dim3(TX * TY * TZ),
+                           0, s, d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, nbx, nby,
+                           nbz, 0, st);
+        return;
+    }
+    // the points at or above their column's band top: the kernel without the band paths
+    hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, MINW, KP, true, 1>), dim3(nbx * nby * nbz),
+                       dim3(TX * TY * TZ), 0, s, d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt,
+                       final_stage, nbx, nby, nbz, 0, st);
+    // the points below it: one-wave tiles of the full kernel over k < kband
+    if (d.nx >= 8 && d.ny >= 8)
+        launch_band<T, 8, 8, 1, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
+    else if (d.nx >= 4 && d.ny >= 4)
+        launch_band<T, 4, 4, 4, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
+    else
+        launch_band<T, 2, 2, 16, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
 }
 
 // the tile of a grid: the requested shape if the grid holds at least one tile per direction in x
