@@ -2,9 +2,47 @@
 // diagnostics, tendency, Runge-Kutta stage and the conservation sums, for both storage precisions.
 #pragma clang fp contract(off)
 
+#include <mutex>
+
 #include "cc_kernels.hpp"
 
 namespace cc {
+
+// ------------------------------------------------------------------------------------------------
+// Side stream of a device: the band points of an update run on it beside the regular points (the
+// two launches write disjoint points and read only the inputs).  Created on first use outside
+// stream capture; fork and join go through events, so a capture of the caller's stream takes the
+// side stream's work in.  One fork/launch/join at a time per device (the events are shared).
+// ------------------------------------------------------------------------------------------------
+struct Side {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    bool failed = false;
+};
+constexpr int MAX_DEVICES = 64;
+static Side g_side[MAX_DEVICES];
+static std::mutex g_side_mu;
+
+// the side stream of the current device, or null (creation failed, or the caller's stream is being
+// captured before the side stream exists): then the band launch goes on the caller's stream
+static Side *side_of(hipStream_t s)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    Side &x = g_side[dev];
+    if (x.s) return &x;
+    if (x.failed) return nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    if (hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&x.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&x.join, hipEventDisableTiming) != hipSuccess) {
+        x.failed = true;
+        x.s = nullptr;
+        return nullptr;
+    }
+    return &x;
+}
 
 // ------------------------------------------------------------------------------------------------
 // Initial state: theta' at constant pressure on group masters, (rho theta)' = 0, inflow (u0, v0, 0)
@@ -180,17 +218,26 @@ static void launch_tiled(const Dims &d, const Geo &G, const Phy &P, const cc_sta
                            nbz, 0, st);
         return;
     }
-    // the points at or above their column's band top: the kernel without the band paths
+    // the points below their column's band top: one-wave tiles of the full kernel over k < kband, on
+    // the side stream (forked from s)
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    Side *x = side_of(s);
+    hipStream_t sb = s;
+    if (x && hipEventRecord(x->fork, s) == hipSuccess && hipStreamWaitEvent(x->s, x->fork, 0) == hipSuccess)
+        sb = x->s;
+    if (d.nx >= 8 && d.ny >= 8)
+        launch_band<T, 8, 8, 1, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, sb);
+    else if (d.nx >= 4 && d.ny >= 4)
+        launch_band<T, 4, 4, 4, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, sb);
+    else
+        launch_band<T, 2, 2, 16, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, sb);
+    // the points at or above it: the kernel without the band paths over the whole grid
     hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, MINW, KP, true, 1>), dim3(nbx * nby * nbz),
                        dim3(TX * TY * TZ), 0, s, d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt,
                        final_stage, nbx, nby, nbz, 0, st);
-    // the points below it: one-wave tiles of the full kernel over k < kband
-    if (d.nx >= 8 && d.ny >= 8)
-        launch_band<T, 8, 8, 1, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
-    else if (d.nx >= 4 && d.ny >= 4)
-        launch_band<T, 4, 4, 4, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
-    else
-        launch_band<T, 2, 2, 16, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
+    // join: later work on s waits for the band launch (should the join fail, the host waits)
+    if (sb != s && (hipEventRecord(x->join, sb) != hipSuccess || hipStreamWaitEvent(s, x->join, 0) != hipSuccess))
+        (void)hipStreamSynchronize(sb);
 }
 
 // the tile of a grid: the requested shape if the grid holds at least one tile per direction in x
