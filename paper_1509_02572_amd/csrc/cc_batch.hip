@@ -312,7 +312,7 @@ void level_stage(cc_batch_s *b, int l, int rn, int rs, int ro, double cdt, int f
                                descs<T>(b, l), ro, (const GhostEnt *)(b->ws + L.same_off), L.nsame, (int)FILL_COPY);
     };
     refill();
-    hipLaunchKernelGGL(k_diagnose_batch<T>, dim3(blocks_for(L.ncols, 64)), dim3(64), 0, s, descs<T>(b, l), L.nblk,
+    hipLaunchKernelGGL(k_diagnose_batch<T>, dim3(blocks_for(L.ncols, DIAG_COLS)), dim3(DIAG_THREADS), 0, s, descs<T>(b, l), L.nblk,
                        L.ncols, ro, st);
     refill();
 }

@@ -1052,15 +1052,14 @@ __device__ bool plane_family(const Dims &d, const Geo &G, const Phy &P, const SI
     return false;
 }
 
-// one thread per column corner (I,J): boundary velocity (free-slip projection of the nearest-plane
-// mean, eq. 33), then every diagnosed lattice point and absorbed/solid cell of the column
-// corners whose terrain point lies in [zlo, zhi) count a missing nearest plane (for a block of a
-// refined grid: its own columns and levels; elsewhere the block's ghost layers, which go stale)
-template <typename T>
-__device__ __forceinline__ void diagnose_column(const Dims &d, const Geo &G, const Phy &P, const SOut<T> &qw,
-                                                int64_t t, int64_t *st, double zlo, double zhi)
+// boundary velocity of the column corner t = (I,J): free-slip projection of the nearest-plane mean
+// (eq. 33).  Corners whose terrain point lies in [zlo, zhi) count a missing nearest plane (for a
+// block of a refined grid: its own columns and levels; elsewhere the block's ghost layers, which go
+// stale).
+template <typename T, typename R = typename Compute<T>::R>
+__device__ __forceinline__ void boundary_velocity(const Dims &d, const Geo &G, const Phy &P, const SOut<T> &qw,
+                                                  int64_t t, int64_t *st, double zlo, double zhi, R ub[3])
 {
-    using R = typename Compute<T>::R;
     int64_t nc = (int64_t)d.nx * d.ny;
     int I = (int)(t / d.ny), J = (int)(t % d.ny);
     SIn<T> q{qw.rho, qw.rth, qw.mu, qw.mv, qw.mw, qw.rho_lo, qw.rth_lo};
@@ -1077,75 +1076,145 @@ __device__ __forceinline__ void diagnose_column(const Dims &d, const Geo &G, con
         if (h0 >= zlo && h0 < zhi) count_status(st, ST_NOPLANE);
     }
     R dn = (ut[0] + (R)P.ux) * (R)n0 + (ut[1] + (R)P.vy) * (R)n1 + ut[2] * (R)n2;
-    R ub[3] = {ut[0] - dn * (R)n0, ut[1] - dn * (R)n1, ut[2] - dn * (R)n2};
-    double hh = G.H[t];
-    int ktop = G.colk[2 * nc + t];
-    int64_t base = cidx(d, I, J, 0);
-    for (int K = 0; K < ktop; ++K) {
-        int64_t p = base + K;
-        int8_t vc = G.vcls[p];
-        if (vc != CC_PRED) {
-            R u[3] = {ub[0], ub[1], ub[2]};
-            if (vc == CC_MFACE) {
-                // the lowest predicted point within 8 levels above (classes read together)
-                int8_t cv[8];
+    ub[0] = ut[0] - dn * (R)n0;
+    ub[1] = ut[1] - dn * (R)n1;
+    ub[2] = ut[2] - dn * (R)n2;
+}
+
+// level K of column corner t (K below the column's diagnostic top): a diagnosed lattice point takes
+// u_B (ground points) or the interpolation between u_B and the lowest predicted point above
+// (merged-face points); an absorbed cell takes its master's scalars, a solid cell zero.  Every level
+// reads only predicted points and masters, which no level writes, so levels are independent.
+template <typename T, typename R = typename Compute<T>::R>
+__device__ __forceinline__ void diagnose_level(const Dims &d, const Geo &G, const Phy &P, const SOut<T> &qw,
+                                               int64_t t, int K, const R ub[3])
+{
+    int I = (int)(t / d.ny), J = (int)(t % d.ny);
+    SIn<T> q{qw.rho, qw.rth, qw.mu, qw.mv, qw.mw, qw.rho_lo, qw.rth_lo};
+    const int64_t base = cidx(d, I, J, 0), p = base + K;
+    const int8_t vc = G.vcls[p], cl = G.cls[p];
+    if (vc != CC_PRED) {
+        R u[3] = {ub[0], ub[1], ub[2]};
+        if (vc == CC_MFACE) {
+            // the lowest predicted point within 8 levels above (classes read together)
+            int8_t cv[8];
 #pragma unroll
-                for (int s = 0; s < 8; ++s) cv[s] = K + 1 + s < d.nz ? G.vcls[base + K + 1 + s] : (int8_t)-1;
-                int kp = -1;
-                for (int s = 0; s < 8; ++s)
-                    if (cv[s] == CC_PRED) { kp = K + 1 + s; break; }
-                if (kp >= 0) {
-                    double gm = ((double)K * d.dz - hh) / ((double)kp * d.dz - hh);
-                    R v[3];
-                    lat_vel_pred<T>(d, P, q, I, J, kp, v);
-                    for (int cc = 0; cc < 3; ++cc) u[cc] = v[cc] * (R)gm + ub[cc] * (R)(1.0 - gm);
-                }
+            for (int s = 0; s < 8; ++s) cv[s] = K + 1 + s < d.nz ? G.vcls[base + K + 1 + s] : (int8_t)-1;
+            int kp = -1;
+            for (int s = 0; s < 8; ++s)
+                if (cv[s] == CC_PRED) { kp = K + 1 + s; break; }
+            if (kp >= 0) {
+                double hh = G.H[t];
+                double gm = ((double)K * d.dz - hh) / ((double)kp * d.dz - hh);
+                R v[3];
+                lat_vel_pred<T>(d, P, q, I, J, kp, v);
+                for (int cc = 0; cc < 3; ++cc) u[cc] = v[cc] * (R)gm + ub[cc] * (R)(1.0 - gm);
             }
-            qw.mu[p] = (T)u[0]; qw.mv[p] = (T)u[1]; qw.mw[p] = (T)u[2];
         }
-        int8_t cl = G.cls[p];
-        if (cl == CC_SOLID) {
-            qw.rho[p] = (T)0; qw.rth[p] = (T)0;
-            if (qw.rho_lo) { qw.rho_lo[p] = (T)0; qw.rth_lo[p] = (T)0; }
-        } else if (cl == CC_ABSORBED) {
-            int64_t m = G.master[p];
-            qw.rho[p] = qw.rho[m];
-            qw.rth[p] = qw.rth[m];
-            if (qw.rho_lo) { qw.rho_lo[p] = qw.rho_lo[m]; qw.rth_lo[p] = qw.rth_lo[m]; }
+        qw.mu[p] = (T)u[0]; qw.mv[p] = (T)u[1]; qw.mw[p] = (T)u[2];
+    }
+    if (cl == CC_SOLID) {
+        qw.rho[p] = (T)0; qw.rth[p] = (T)0;
+        if (qw.rho_lo) { qw.rho_lo[p] = (T)0; qw.rth_lo[p] = (T)0; }
+    } else if (cl == CC_ABSORBED) {
+        int64_t m = G.master[p];
+        T r0 = qw.rho[m], r1 = qw.rth[m];
+        if (qw.rho_lo) {
+            T l0 = qw.rho_lo[m], l1 = qw.rth_lo[m];
+            qw.rho_lo[p] = l0; qw.rth_lo[p] = l1;
         }
+        qw.rho[p] = r0; qw.rth[p] = r1;
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(64) k_diagnose(Dims d, Geo G, Phy P, SOut<T> qw, int64_t *st)
-{
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)d.nx * d.ny) return;
-    diagnose_column<T>(d, G, P, qw, t, st, 0.0, (double)d.nz * d.dz);
-}
+// Diagnostics in blocks of DIAG_COLS column corners and DIAG_THREADS threads: the first DIAG_COLS
+// threads find the corners' boundary velocities, then all threads take the (corner, level) pairs
+// below the corners' diagnostic tops, level by level, so a deep column is spread over many threads.
+constexpr int DIAG_COLS = 64, DIAG_THREADS = 256;
 
 template <typename T>
-__global__ void __launch_bounds__(64) k_diagnose_batch(const BlockDesc<T> *__restrict__ desc, int nblk,
-                                                       int ncols, int ro, int64_t *st)
+__global__ void __launch_bounds__(DIAG_THREADS) k_diagnose(Dims d, Geo G, Phy P, SOut<T> qw, int64_t *st)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ncols) return;
-    int lo = 0, hi = nblk - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (desc[mid].col0 <= t) lo = mid;
-        else hi = mid - 1;
+    using R = typename Compute<T>::R;
+    __shared__ R s_ub[3][DIAG_COLS];
+    __shared__ int s_top[DIAG_COLS];
+    __shared__ int s_kmax;
+    const int tid = threadIdx.x;
+    const int64_t nc = (int64_t)d.nx * d.ny;
+    if (tid == 0) s_kmax = 0;
+    __syncthreads();
+    if (tid < DIAG_COLS) {
+        const int64_t t = (int64_t)blockIdx.x * DIAG_COLS + tid;
+        int top = 0;
+        if (t < nc) {
+            R ub[3];
+            boundary_velocity<T>(d, G, P, qw, t, st, 0.0, (double)d.nz * d.dz, ub);
+            s_ub[0][tid] = ub[0]; s_ub[1][tid] = ub[1]; s_ub[2][tid] = ub[2];
+            top = G.colk[2 * nc + t];
+        }
+        s_top[tid] = top;
+        atomicMax(&s_kmax, top);
     }
-    const BlockDesc<T> &D = desc[lo];
-    const int wy = D.rhi[1] - D.rlo[1];
-    const int64_t r = t - D.col0;
-    const int I = D.rlo[0] + (int)(r / wy), J = D.rlo[1] + (int)(r % wy);
-    const int64_t c = (int64_t)I * D.d.ny + J;
-    const bool own = I >= D.ilo[0] && I < D.ihi[0] && J >= D.ilo[1] && J < D.ihi[1];
-    diagnose_column<T>(D.d, D.G, D.P, D.q[ro], c, st, own ? (double)D.ilo[2] * D.d.dz : 0.0,
-                       own ? (double)D.ihi[2] * D.d.dz : 0.0);
+    __syncthreads();
+    const int n = s_kmax * DIAG_COLS;
+    for (int it = tid; it < n; it += DIAG_THREADS) {
+        const int slot = it % DIAG_COLS, K = it / DIAG_COLS;
+        if (K >= s_top[slot]) continue;
+        const R ub[3] = {s_ub[0][slot], s_ub[1][slot], s_ub[2][slot]};
+        diagnose_level<T>(d, G, P, qw, (int64_t)blockIdx.x * DIAG_COLS + slot, K, ub);
+    }
 }
 
+// the same over the columns of every block of a batch (column indices in the order of the blocks'
+// col0 offsets; each block maps its columns over [rlo, rhi) in x and y)
+template <typename T>
+__global__ void __launch_bounds__(DIAG_THREADS) k_diagnose_batch(const BlockDesc<T> *__restrict__ desc, int nblk,
+                                                                 int ncols, int ro, int64_t *st)
+{
+    using R = typename Compute<T>::R;
+    __shared__ R s_ub[3][DIAG_COLS];
+    __shared__ int s_top[DIAG_COLS], s_blk[DIAG_COLS], s_col[DIAG_COLS];
+    __shared__ int s_kmax;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_kmax = 0;
+    __syncthreads();
+    if (tid < DIAG_COLS) {
+        const int t = blockIdx.x * DIAG_COLS + tid;
+        int top = 0, lo = 0, c = 0;
+        if (t < ncols) {
+            int hi = nblk - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (desc[mid].col0 <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            const BlockDesc<T> &D = desc[lo];
+            const int wy = D.rhi[1] - D.rlo[1];
+            const int r = t - D.col0;
+            const int I = D.rlo[0] + r / wy, J = D.rlo[1] + r % wy;
+            c = I * D.d.ny + J;
+            const bool own = I >= D.ilo[0] && I < D.ihi[0] && J >= D.ilo[1] && J < D.ihi[1];
+            R ub[3];
+            boundary_velocity<T>(D.d, D.G, D.P, D.q[ro], c, st, own ? (double)D.ilo[2] * D.d.dz : 0.0,
+                                 own ? (double)D.ihi[2] * D.d.dz : 0.0, ub);
+            s_ub[0][tid] = ub[0]; s_ub[1][tid] = ub[1]; s_ub[2][tid] = ub[2];
+            top = D.G.colk[2 * (D.d.nx * D.d.ny) + c];
+        }
+        s_top[tid] = top;
+        s_blk[tid] = lo;
+        s_col[tid] = c;
+        atomicMax(&s_kmax, top);
+    }
+    __syncthreads();
+    const int n = s_kmax * DIAG_COLS;
+    for (int it = tid; it < n; it += DIAG_THREADS) {
+        const int slot = it % DIAG_COLS, K = it / DIAG_COLS;
+        if (K >= s_top[slot]) continue;
+        const BlockDesc<T> &D = desc[s_blk[slot]];
+        const R ub[3] = {s_ub[0][slot], s_ub[1][slot], s_ub[2][slot]};
+        diagnose_level<T>(D.d, D.G, D.P, D.q[ro], (int64_t)s_col[slot], K, ub);
+    }
+}
 
 // ------------------------------------------------------------------------------------------------
 // host helpers: C-ABI structs -> kernel views

@@ -182,7 +182,7 @@ template <typename T>
 static void launch_diagnose(const Dims &d, const Geo &G, const Phy &P, cc_state *q, int64_t *st, hipStream_t s)
 {
     int64_t nc = (int64_t)d.nx * d.ny;
-    hipLaunchKernelGGL(k_diagnose<T>, dim3(blocks_for(nc, 64)), dim3(64), 0, s, d, G, P, sout_of<T>(q), st);
+    hipLaunchKernelGGL(k_diagnose<T>, dim3(blocks_for(nc, DIAG_COLS)), dim3(DIAG_THREADS), 0, s, d, G, P, sout_of<T>(q), st);
 }
 
 // tile shapes of the update kernel (id -> TX x TY x TZ, minimum waves per SIMD the register
