@@ -1081,20 +1081,29 @@ __device__ __forceinline__ void boundary_velocity(const Dims &d, const Geo &G, c
     ub[2] = ut[2] - dn * (R)n2;
 }
 
-// level K of column corner t (K below the column's diagnostic top): a diagnosed lattice point takes
-// u_B (ground points) or the interpolation between u_B and the lowest predicted point above
-// (merged-face points); an absorbed cell takes its master's scalars, a solid cell zero.  Every level
-// reads only predicted points and masters, which no level writes, so levels are independent.
+// Level K of column corner t (K below the column's diagnostic top), in two parts.  The first reads
+// the classes, writes the scalars of an absorbed cell (its master's) or a solid cell (zero), and for a
+// diagnosed lattice point forms what does not need u_B: a ground point takes u_B itself; a merged-face
+// point the interpolation v gm + u_B (1 - gm) between u_B and the lowest predicted point above (v),
+// whose first product and weight are formed here.  The second writes the lattice velocity.  Every
+// level reads only predicted points and masters, which no level writes, so levels are independent.
+template <typename R>
+struct DiagLevel {
+    R a[3], b;  // interpolation: u = a + u_B b
+    int mode;   // 0: nothing to write, 1: u = u_B, 2: interpolation
+};
+
 template <typename T, typename R = typename Compute<T>::R>
-__device__ __forceinline__ void diagnose_level(const Dims &d, const Geo &G, const Phy &P, const SOut<T> &qw,
-                                               int64_t t, int K, const R ub[3])
+__device__ __forceinline__ void diagnose_level_pre(const Dims &d, const Geo &G, const Phy &P, const SOut<T> &qw,
+                                                   int64_t t, int K, DiagLevel<R> &o)
 {
     int I = (int)(t / d.ny), J = (int)(t % d.ny);
     SIn<T> q{qw.rho, qw.rth, qw.mu, qw.mv, qw.mw, qw.rho_lo, qw.rth_lo};
     const int64_t base = cidx(d, I, J, 0), p = base + K;
     const int8_t vc = G.vcls[p], cl = G.cls[p];
+    o.mode = 0;
     if (vc != CC_PRED) {
-        R u[3] = {ub[0], ub[1], ub[2]};
+        o.mode = 1;
         if (vc == CC_MFACE) {
             // the lowest predicted point within 8 levels above (classes read together)
             int8_t cv[8];
@@ -1108,10 +1117,11 @@ __device__ __forceinline__ void diagnose_level(const Dims &d, const Geo &G, cons
                 double gm = ((double)K * d.dz - hh) / ((double)kp * d.dz - hh);
                 R v[3];
                 lat_vel_pred<T>(d, P, q, I, J, kp, v);
-                for (int cc = 0; cc < 3; ++cc) u[cc] = v[cc] * (R)gm + ub[cc] * (R)(1.0 - gm);
+                for (int cc = 0; cc < 3; ++cc) o.a[cc] = v[cc] * (R)gm;
+                o.b = (R)(1.0 - gm);
+                o.mode = 2;
             }
         }
-        qw.mu[p] = (T)u[0]; qw.mv[p] = (T)u[1]; qw.mw[p] = (T)u[2];
     }
     if (cl == CC_SOLID) {
         qw.rho[p] = (T)0; qw.rth[p] = (T)0;
@@ -1127,93 +1137,149 @@ __device__ __forceinline__ void diagnose_level(const Dims &d, const Geo &G, cons
     }
 }
 
-// Diagnostics in blocks of DIAG_COLS column corners and DIAG_THREADS threads: the first DIAG_COLS
-// threads find the corners' boundary velocities, then all threads take the (corner, level) pairs
-// below the corners' diagnostic tops, level by level, so a deep column is spread over many threads.
-constexpr int DIAG_COLS = 64, DIAG_THREADS = 256;
+template <typename T, typename R = typename Compute<T>::R>
+__device__ __forceinline__ void diagnose_level_post(const Dims &d, const SOut<T> &qw, int64_t t, int K,
+                                                    const DiagLevel<R> &o, const R ub[3])
+{
+    if (o.mode == 0) return;
+    const int64_t p = t * d.nzs + K;
+    R u[3];
+    for (int cc = 0; cc < 3; ++cc) u[cc] = o.mode == 2 ? o.a[cc] + ub[cc] * o.b : ub[cc];
+    qw.mu[p] = (T)u[0]; qw.mv[p] = (T)u[1]; qw.mw[p] = (T)u[2];
+}
+
+// Diagnostics in blocks of DIAG_COLS column corners and DIAG_THREADS threads.  The first DIAG_COLS
+// threads find the corners' boundary velocities while the others take levels 0 .. DIAG_EARLY-1 of the
+// corners (one each) up to the point where u_B is needed; after a barrier those levels are finished
+// and all threads take the levels above, level by level, so a deep column is spread over many threads.
+constexpr int DIAG_COLS = 64, DIAG_THREADS = 256, DIAG_EARLY = DIAG_THREADS / DIAG_COLS - 1;
+
+// the column of a slot: its grid (b: block of a batch), corner index and the terrain range that
+// counts a missing plane
+struct DiagCol {
+    bool valid;
+    int b;
+    int64_t t;
+    double zlo, zhi;
+};
+
+template <typename T, typename VIEWS>
+__device__ __forceinline__ void diagnose_block(const VIEWS &views, int64_t *st)
+{
+    using R = typename Compute<T>::R;
+    __shared__ R s_ub[3][DIAG_COLS];
+    __shared__ int s_top[DIAG_COLS], s_b[DIAG_COLS];
+    __shared__ int64_t s_t[DIAG_COLS];
+    __shared__ int s_kmax;
+    const int tid = threadIdx.x, slot = tid % DIAG_COLS, grp = tid / DIAG_COLS;
+    if (tid == 0) s_kmax = 0;
+    __syncthreads();
+    const DiagCol col = views.column(slot);
+    const Dims &d = views.dims(col.b);
+    const Geo &G = views.geo(col.b);
+    const Phy &P = views.phy(col.b);
+    const SOut<T> &qw = views.state(col.b);
+    DiagLevel<R> early;
+    early.mode = 0;
+    const int top = col.valid ? G.colk[2 * (int64_t)d.nx * d.ny + col.t] : 0;
+    if (grp == 0) {
+        if (col.valid) {
+            R ub[3];
+            boundary_velocity<T>(d, G, P, qw, col.t, st, col.zlo, col.zhi, ub);
+            s_ub[0][slot] = ub[0]; s_ub[1][slot] = ub[1]; s_ub[2][slot] = ub[2];
+        }
+        s_top[slot] = top;
+        s_b[slot] = col.b;
+        s_t[slot] = col.t;
+        atomicMax(&s_kmax, top);
+    } else if (grp - 1 < top) {
+        diagnose_level_pre<T>(d, G, P, qw, col.t, grp - 1, early);
+    }
+    __syncthreads();
+    if (early.mode != 0) {
+        const R ub[3] = {s_ub[0][slot], s_ub[1][slot], s_ub[2][slot]};
+        diagnose_level_post<T>(d, qw, col.t, grp - 1, early, ub);
+    }
+    const int n = (s_kmax - DIAG_EARLY) * DIAG_COLS;
+    for (int it = tid; it < n; it += DIAG_THREADS) {
+        const int sl = it % DIAG_COLS, K = DIAG_EARLY + it / DIAG_COLS;
+        if (K >= s_top[sl]) continue;
+        const int b = s_b[sl];
+        const int64_t t = s_t[sl];
+        const Dims &d2 = views.dims(b);
+        const SOut<T> &q2 = views.state(b);
+        DiagLevel<R> o;
+        diagnose_level_pre<T>(d2, views.geo(b), views.phy(b), q2, t, K, o);
+        const R ub[3] = {s_ub[0][sl], s_ub[1][sl], s_ub[2][sl]};
+        diagnose_level_post<T>(d2, q2, t, K, o, ub);
+    }
+}
+
+// views of a single grid: slot s of block b is corner b DIAG_COLS + s
+template <typename T>
+struct GridDiagViews {
+    const Dims &d;
+    const Geo &G;
+    const Phy &P;
+    const SOut<T> &q;
+    __device__ DiagCol column(int slot) const
+    {
+        const int64_t t = (int64_t)blockIdx.x * DIAG_COLS + slot;
+        return DiagCol{t < (int64_t)d.nx * d.ny, 0, t, 0.0, (double)d.nz * d.dz};
+    }
+    __device__ const Dims &dims(int) const { return d; }
+    __device__ const Geo &geo(int) const { return G; }
+    __device__ const Phy &phy(int) const { return P; }
+    __device__ const SOut<T> &state(int) const { return q; }
+};
 
 template <typename T>
 __global__ void __launch_bounds__(DIAG_THREADS) k_diagnose(Dims d, Geo G, Phy P, SOut<T> qw, int64_t *st)
 {
-    using R = typename Compute<T>::R;
-    __shared__ R s_ub[3][DIAG_COLS];
-    __shared__ int s_top[DIAG_COLS];
-    __shared__ int s_kmax;
-    const int tid = threadIdx.x;
-    const int64_t nc = (int64_t)d.nx * d.ny;
-    if (tid == 0) s_kmax = 0;
-    __syncthreads();
-    if (tid < DIAG_COLS) {
-        const int64_t t = (int64_t)blockIdx.x * DIAG_COLS + tid;
-        int top = 0;
-        if (t < nc) {
-            R ub[3];
-            boundary_velocity<T>(d, G, P, qw, t, st, 0.0, (double)d.nz * d.dz, ub);
-            s_ub[0][tid] = ub[0]; s_ub[1][tid] = ub[1]; s_ub[2][tid] = ub[2];
-            top = G.colk[2 * nc + t];
-        }
-        s_top[tid] = top;
-        atomicMax(&s_kmax, top);
-    }
-    __syncthreads();
-    const int n = s_kmax * DIAG_COLS;
-    for (int it = tid; it < n; it += DIAG_THREADS) {
-        const int slot = it % DIAG_COLS, K = it / DIAG_COLS;
-        if (K >= s_top[slot]) continue;
-        const R ub[3] = {s_ub[0][slot], s_ub[1][slot], s_ub[2][slot]};
-        diagnose_level<T>(d, G, P, qw, (int64_t)blockIdx.x * DIAG_COLS + slot, K, ub);
-    }
+    diagnose_block<T>(GridDiagViews<T>{d, G, P, qw}, st);
 }
 
-// the same over the columns of every block of a batch (column indices in the order of the blocks'
-// col0 offsets; each block maps its columns over [rlo, rhi) in x and y)
+// views of a batch: column indices follow the blocks' col0 offsets; each block maps its columns over
+// [rlo, rhi) in x and y; corners of a block's own columns count a missing plane for terrain in its
+// own levels, the others (ghost layers, which go stale) never
+template <typename T>
+struct BatchDiagViews {
+    const BlockDesc<T> *desc;
+    int nblk, ncols, ro;
+    __device__ int block_of(int t) const
+    {
+        int lo = 0, hi = nblk - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (desc[mid].col0 <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    }
+    __device__ DiagCol column(int slot) const
+    {
+        const int t = blockIdx.x * DIAG_COLS + slot;
+        if (t >= ncols) return DiagCol{false, 0, 0, 0.0, 0.0};
+        const int b = block_of(t);
+        const BlockDesc<T> &D = desc[b];
+        const int wy = D.rhi[1] - D.rlo[1];
+        const int r = t - D.col0;
+        const int I = D.rlo[0] + r / wy, J = D.rlo[1] + r % wy;
+        const bool own = I >= D.ilo[0] && I < D.ihi[0] && J >= D.ilo[1] && J < D.ihi[1];
+        return DiagCol{true, b, (int64_t)I * D.d.ny + J, own ? (double)D.ilo[2] * D.d.dz : 0.0,
+                       own ? (double)D.ihi[2] * D.d.dz : 0.0};
+    }
+    __device__ const Dims &dims(int b) const { return desc[b].d; }
+    __device__ const Geo &geo(int b) const { return desc[b].G; }
+    __device__ const Phy &phy(int b) const { return desc[b].P; }
+    __device__ const SOut<T> &state(int b) const { return desc[b].q[ro]; }
+};
+
 template <typename T>
 __global__ void __launch_bounds__(DIAG_THREADS) k_diagnose_batch(const BlockDesc<T> *__restrict__ desc, int nblk,
                                                                  int ncols, int ro, int64_t *st)
 {
-    using R = typename Compute<T>::R;
-    __shared__ R s_ub[3][DIAG_COLS];
-    __shared__ int s_top[DIAG_COLS], s_blk[DIAG_COLS], s_col[DIAG_COLS];
-    __shared__ int s_kmax;
-    const int tid = threadIdx.x;
-    if (tid == 0) s_kmax = 0;
-    __syncthreads();
-    if (tid < DIAG_COLS) {
-        const int t = blockIdx.x * DIAG_COLS + tid;
-        int top = 0, lo = 0, c = 0;
-        if (t < ncols) {
-            int hi = nblk - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (desc[mid].col0 <= t) lo = mid;
-                else hi = mid - 1;
-            }
-            const BlockDesc<T> &D = desc[lo];
-            const int wy = D.rhi[1] - D.rlo[1];
-            const int r = t - D.col0;
-            const int I = D.rlo[0] + r / wy, J = D.rlo[1] + r % wy;
-            c = I * D.d.ny + J;
-            const bool own = I >= D.ilo[0] && I < D.ihi[0] && J >= D.ilo[1] && J < D.ihi[1];
-            R ub[3];
-            boundary_velocity<T>(D.d, D.G, D.P, D.q[ro], c, st, own ? (double)D.ilo[2] * D.d.dz : 0.0,
-                                 own ? (double)D.ihi[2] * D.d.dz : 0.0, ub);
-            s_ub[0][tid] = ub[0]; s_ub[1][tid] = ub[1]; s_ub[2][tid] = ub[2];
-            top = D.G.colk[2 * (D.d.nx * D.d.ny) + c];
-        }
-        s_top[tid] = top;
-        s_blk[tid] = lo;
-        s_col[tid] = c;
-        atomicMax(&s_kmax, top);
-    }
-    __syncthreads();
-    const int n = s_kmax * DIAG_COLS;
-    for (int it = tid; it < n; it += DIAG_THREADS) {
-        const int slot = it % DIAG_COLS, K = it / DIAG_COLS;
-        if (K >= s_top[slot]) continue;
-        const BlockDesc<T> &D = desc[s_blk[slot]];
-        const R ub[3] = {s_ub[0][slot], s_ub[1][slot], s_ub[2][slot]};
-        diagnose_level<T>(D.d, D.G, D.P, D.q[ro], (int64_t)s_col[slot], K, ub);
-    }
+    diagnose_block<T>(BatchDiagViews<T>{desc, nblk, ncols, ro}, st);
 }
 
 // ------------------------------------------------------------------------------------------------
