@@ -976,7 +976,10 @@ __global__ void __launch_bounds__(TX * TY * TZ, MINW)
 // Try the first three lattice planes of one family (0: x = const, 1: y = const, 2: z = const) beyond
 // the terrain point B along the normal line; on each plane the intersection falls in a face of four
 // lattice points (located with floor); the first plane whose corners with non-zero bilinear weight
-// are all predicted gives the interpolated velocity (the paper's u_N).
+// are all predicted gives the interpolated velocity (the paper's u_N).  The faces and weights of the
+// three planes are formed first and the classes of their corners read together; then the velocities
+// of the chosen face's corners are read together (a corner that is not predicted is read at a level
+// of at least 1, which keeps the read in range, and takes no part).
 template <typename T, typename R = typename Compute<T>::R>
 __device__ bool plane_family(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &q, int fam,
                              int I, int J, R ut[3])
@@ -986,30 +989,37 @@ __device__ bool plane_family(const Dims &d, const Geo &G, const Phy &P, const SI
     double n0 = G.nrm[hc], n1 = G.nrm[nc + hc], n2 = G.nrm[2 * nc + hc];
     double hh = G.H[hc];
     if (!(hh >= 0.0 && hh < (double)d.nz * d.dz)) return false;  // terrain outside the column
+    if (fam != 2 && (fam == 0 ? n0 : n1) == 0.0) return false;
     // horizontal positions are measured from the corner (I,J) in cell units, so the located face
     // and weights do not depend on where the grid's origin lies
+    int P4[3][4][3];
+    double w[3][4];
+    bool valid[3];
+    int K0 = 0;
+    if (fam == 2) {
+        K0 = (int)floor(hh / d.dz) + 1;
+        while (K0 > 0 && (double)(K0 - 1) * d.dz > hh) --K0;
+        while ((double)K0 * d.dz <= hh) ++K0;
+    }
+#pragma unroll
     for (int m = 0; m < 3; ++m) {
-        int P4[4][3];
         int ia, ib;
         double a, b;
+        valid[m] = true;
         if (fam == 2) {
-            int K0 = (int)floor(hh / d.dz) + 1;
-            while (K0 > 0 && (double)(K0 - 1) * d.dz > hh) --K0;
-            while ((double)K0 * d.dz <= hh) ++K0;
             int K = K0 + m;
-            if (K > d.nz - 1) return false;
+            valid[m] = K <= d.nz - 1;  // (a plane above the lid ends the search)
             double t = ((double)K * d.dz - hh) / n2;
             double fx = (t * n0) / d.dx, fy = (t * n1) / d.dy;
             int sx = (int)floor(fx), sy = (int)floor(fy);
             a = fx - (double)sx; b = fy - (double)sy;
             ia = I + sx; ib = J + sy;
-            P4[0][0] = ia; P4[0][1] = ib; P4[0][2] = K;
-            P4[1][0] = ia + 1; P4[1][1] = ib; P4[1][2] = K;
-            P4[2][0] = ia; P4[2][1] = ib + 1; P4[2][2] = K;
-            P4[3][0] = ia + 1; P4[3][1] = ib + 1; P4[3][2] = K;
+            P4[m][0][0] = ia; P4[m][0][1] = ib; P4[m][0][2] = K;
+            P4[m][1][0] = ia + 1; P4[m][1][1] = ib; P4[m][1][2] = K;
+            P4[m][2][0] = ia; P4[m][2][1] = ib + 1; P4[m][2][2] = K;
+            P4[m][3][0] = ia + 1; P4[m][3][1] = ib + 1; P4[m][3][2] = K;
         } else {
             double nn = fam == 0 ? n0 : n1;
-            if (nn == 0.0) return false;
             int step = (m + 1) * (nn > 0.0 ? 1 : -1);
             double t = fam == 0 ? ((double)step * d.dx) / nn : ((double)step * d.dy) / nn;
             double fa = fam == 0 ? (t * n1) / d.dy : (t * n0) / d.dx;
@@ -1018,38 +1028,52 @@ __device__ bool plane_family(const Dims &d, const Geo &G, const Phy &P, const SI
             ib = (int)floor(fz);
             a = fa - (double)sa; b = fz - (double)ib;
             ia = (fam == 0 ? J : I) + sa;
-            if (ib < 0 || ib + 1 > d.nz - 1) continue;
+            valid[m] = !(ib < 0 || ib + 1 > d.nz - 1);
             for (int s = 0; s < 4; ++s) {
                 int pa = ia + (s & 1), pz = ib + (s >> 1);
-                if (fam == 0) { P4[s][0] = I + step; P4[s][1] = pa; }
-                else { P4[s][0] = pa; P4[s][1] = J + step; }
-                P4[s][2] = pz;
+                if (fam == 0) { P4[m][s][0] = I + step; P4[m][s][1] = pa; }
+                else { P4[m][s][0] = pa; P4[m][s][1] = J + step; }
+                P4[m][s][2] = pz;
             }
         }
-        double w[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
-        // the four classes are read together (every corner index is in range), then the velocities
-        // of the weighted corners, which are predicted points, together
-        int8_t vc[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) vc[s] = G.vcls[cidx(d, P4[s][0], P4[s][1], P4[s][2])];
-        bool ok = true;
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-            if (w[s] != 0.0 && vc[s] != CC_PRED) ok = false;
-        if (!ok) continue;
-        R v[4][3];
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-            if (w[s] != 0.0) lat_vel_pred<T>(d, P, q, P4[s][0], P4[s][1], P4[s][2], v[s]);
-        R acc[3] = {(R)0, (R)0, (R)0};
-        for (int s = 0; s < 4; ++s) {
-            if (w[s] == 0.0) continue;
-            for (int cc = 0; cc < 3; ++cc) acc[cc] += (R)w[s] * v[s][cc];
-        }
-        ut[0] = acc[0]; ut[1] = acc[1]; ut[2] = acc[2];
-        return true;
+        w[m][0] = (1.0 - a) * (1.0 - b); w[m][1] = a * (1.0 - b); w[m][2] = (1.0 - a) * b; w[m][3] = a * b;
     }
-    return false;
+    // classes of the valid planes' corners (every corner index of a valid plane is in range)
+    int8_t vc[3][4];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            vc[m][s] = valid[m] ? G.vcls[cidx(d, P4[m][s][0], P4[m][s][1], P4[m][s][2])] : (int8_t)CC_GROUND;
+    int pick = -1;
+    for (int m = 0; m < 3 && pick < 0; ++m) {
+        if (!valid[m]) {
+            if (fam == 2) return false;  // planes further up lie above the lid too
+            continue;
+        }
+        bool ok = true;
+        for (int s = 0; s < 4; ++s)
+            if (w[m][s] != 0.0 && vc[m][s] != CC_PRED) ok = false;
+        if (ok) pick = m;
+    }
+    if (pick < 0) return false;
+    int C4[4][3];
+    double wp[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        for (int e = 0; e < 3; ++e) C4[s][e] = pick == 0 ? P4[0][s][e] : (pick == 1 ? P4[1][s][e] : P4[2][s][e]);
+        wp[s] = pick == 0 ? w[0][s] : (pick == 1 ? w[1][s] : w[2][s]);
+    }
+    R v[4][3];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) lat_vel_pred<T>(d, P, q, C4[s][0], C4[s][1], C4[s][2] > 1 ? C4[s][2] : 1, v[s]);
+    R acc[3] = {(R)0, (R)0, (R)0};
+    for (int s = 0; s < 4; ++s) {
+        if (wp[s] == 0.0) continue;
+        for (int cc = 0; cc < 3; ++cc) acc[cc] += (R)wp[s] * v[s][cc];
+    }
+    ut[0] = acc[0]; ut[1] = acc[1]; ut[2] = acc[2];
+    return true;
 }
 
 // boundary velocity of the column corner t = (I,J): free-slip projection of the nearest-plane mean
