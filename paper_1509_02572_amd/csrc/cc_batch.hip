@@ -235,7 +235,7 @@ using namespace cc;
 // host: batch state
 // ------------------------------------------------------------------------------------------------
 struct Level {
-    int nblk = 0, ntiles = 0, ntilesr = 0, ncols = 0, cur = 0;  // band tiles, above-band tiles, columns
+    int nblk = 0, ntiles = 0, ntilesr = 0, ncols = 0, cur = 0;  // band-point tiles, regular-point tiles, columns
     size_t desc_off = 0;
     size_t same_off = 0, inj_off = 0, res_off = 0, slot_off = 0, corr_off = 0, reg_off = 0;
     int nsame = 0, ninj = 0, nres = 0, nslot = 0, ncorr = 0;
@@ -244,6 +244,7 @@ struct Level {
 struct cc_batch_s {
     cc_prec prec;
     int tile = 0;
+    int btile = 0;  // band-point tiles: 0 8x8x1, 1 4x4x4, 2 2x2x16
     char *ws = nullptr;  // caller workspace: descriptors, refill tables, flux registers
     std::vector<Level> lev;
     hipStream_t cap = nullptr;  // private stream used only for graph capture
@@ -263,12 +264,20 @@ void launch_batch_stage(const cc_batch_s *b, int l, int rn, int rs, int ro, doub
                         hipStream_t s)
 {
     const Level &L = b->lev[l];
-    if (L.ntiles > 0)
-        hipLaunchKernelGGL((k_stage_batch<T, TX, TY, TZ, 0, MINW, false>), dim3(L.ntiles), dim3(TX * TY * TZ), 0, s,
-                           descs<T>(b, l), L.nblk, L.ntiles, rn, rs, ro, cdt, fin, st);
-    if (L.ntilesr > 0)
-        hipLaunchKernelGGL((k_stage_batch<T, TX, TY, TZ, 0, MINW, true>), dim3(L.ntilesr), dim3(TX * TY * TZ), 0, s,
+    if (L.ntilesr > 0)  // the points at or above their column's band top
+        hipLaunchKernelGGL((k_stage_batch<T, TX, TY, TZ, 0, MINW, 1>), dim3(L.ntilesr), dim3(TX * TY * TZ), 0, s,
                            descs<T>(b, l), L.nblk, L.ntilesr, rn, rs, ro, cdt, fin, st);
+    if (L.ntiles > 0) {  // the points below it
+        if (b->btile == 0)
+            hipLaunchKernelGGL((k_stage_batch<T, 8, 8, 1, 0, 1, 2>), dim3(L.ntiles), dim3(64), 0, s, descs<T>(b, l),
+                               L.nblk, L.ntiles, rn, rs, ro, cdt, fin, st);
+        else if (b->btile == 1)
+            hipLaunchKernelGGL((k_stage_batch<T, 4, 4, 4, 0, 1, 2>), dim3(L.ntiles), dim3(64), 0, s, descs<T>(b, l),
+                               L.nblk, L.ntiles, rn, rs, ro, cdt, fin, st);
+        else
+            hipLaunchKernelGGL((k_stage_batch<T, 2, 2, 16, 0, 1, 2>), dim3(L.ntiles), dim3(64), 0, s, descs<T>(b, l),
+                               L.nblk, L.ntiles, rn, rs, ro, cdt, fin, st);
+    }
 }
 
 template <typename T>
@@ -566,8 +575,8 @@ bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, co
 }
 
 template <typename T>
-bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, int TX, int TY, int TZ,
-                 bool own_range, const Tables &t, std::vector<char> &host, Level &L, const char *what)
+bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, int TX, int TY, int TZ, int BX,
+                 int BY, int BZ, bool own_range, const Tables &t, std::vector<char> &host, Level &L, const char *what)
 {
     host.assign(sizeof(BlockDesc<T>) * ids.size(), 0);
     BlockDesc<T> *h = (BlockDesc<T> *)host.data();
@@ -595,19 +604,18 @@ bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, i
         h[m].nbx = (h[m].rhi[0] - h[m].rlo[0] + TX - 1) / TX;
         h[m].nby = (h[m].rhi[1] - h[m].rlo[1] + TY - 1) / TY;
         h[m].nbz = (h[m].rhi[2] - h[m].rlo[2] + TZ - 1) / TZ;
-        // k-tiles starting below the band height take the full kernel
-        int kbt = h[m].nbz;
-        if (G.kband >= 1 && G.kband <= d.nz) {
-            int above = G.kband - h[m].rlo[2];
-            kbt = above <= 0 ? 0 : (above + TZ - 1) / TZ;
-            if (kbt > h[m].nbz) kbt = h[m].nbz;
-        }
-        h[m].kbt = kbt;
+        // band-point tiles: the range's levels below the highest column band top (every level when it
+        // is unknown)
+        const int kband = (G.kband >= 1 && G.kband <= d.nz) ? G.kband : d.nz;
+        const int nlev = std::min(kband, h[m].rhi[2]) - h[m].rlo[2];
+        h[m].nbxb = (h[m].rhi[0] - h[m].rlo[0] + BX - 1) / BX;
+        h[m].nbyb = (h[m].rhi[1] - h[m].rlo[1] + BY - 1) / BY;
+        h[m].nbzb = nlev > 0 ? (nlev + BZ - 1) / BZ : 0;
         h[m].tile0 = tiles;
         h[m].tile0r = tilesr;
         h[m].col0 = cols;
-        tiles += h[m].nbx * h[m].nby * kbt;
-        tilesr += h[m].nbx * h[m].nby * (h[m].nbz - kbt);
+        tiles += h[m].nbxb * h[m].nbyb * h[m].nbzb;
+        tilesr += h[m].nbx * h[m].nby * h[m].nbz;
         cols += (h[m].rhi[0] - h[m].rlo[0]) * (h[m].rhi[1] - h[m].rlo[1]);
     }
     L.nblk = (int)ids.size();
@@ -636,6 +644,21 @@ int batch_tile(const cc_block *B, int n, int tile, int &TX, int &TY, int &TZ)
     return id;
 }
 
+// one-wave tile shape of the band-point launch: 8x8x1 if every block holds it in x and y, else 4x4x4,
+// else 2x2x16
+int band_tile(const cc_block *B, int n, int &BX, int &BY, int &BZ)
+{
+    int id = 0;
+    for (int m = 0; m < n; ++m) {
+        if (B[m].grid.nx < 4 || B[m].grid.ny < 4) id = 2;
+        else if ((B[m].grid.nx < 8 || B[m].grid.ny < 8) && id < 1) id = 1;
+    }
+    BX = id == 0 ? 8 : (id == 1 ? 4 : 2);
+    BY = BX;
+    BZ = id == 0 ? 1 : (id == 1 ? 4 : 16);
+    return id;
+}
+
 // layout of the workspace and (when `b` is given) the host images to upload
 struct Plan {
     size_t bytes = 0;
@@ -645,16 +668,19 @@ struct Plan {
 bool plan_batch(const cc_block *B, int n, cc_prec prec, int tile, bool own_range, const Tables &t, cc_batch_s *b,
                 Plan &plan, const char *what)
 {
-    int TX, TY, TZ;
+    int TX, TY, TZ, BX, BY, BZ;
     int id = batch_tile(B, n, tile, TX, TY, TZ);
+    int bid = band_tile(B, n, BX, BY, BZ);
     int nl = (int)t.members.size();
     std::vector<Level> lev(nl);
     plan.desc.assign(nl, {});
     size_t off = 0;
     for (int l = 0; l < nl; ++l) {
         bool ok = prec == CC_F64
-                      ? build_descs<double>(B, t.members[l], prec, TX, TY, TZ, own_range, t, plan.desc[l], lev[l], what)
-                      : build_descs<float>(B, t.members[l], prec, TX, TY, TZ, own_range, t, plan.desc[l], lev[l], what);
+                      ? build_descs<double>(B, t.members[l], prec, TX, TY, TZ, BX, BY, BZ, own_range, t, plan.desc[l],
+                                            lev[l], what)
+                      : build_descs<float>(B, t.members[l], prec, TX, TY, TZ, BX, BY, BZ, own_range, t, plan.desc[l],
+                                           lev[l], what);
         if (!ok) return false;
         lev[l].desc_off = off;
         off = align256(off + plan.desc[l].size());
@@ -672,6 +698,7 @@ bool plan_batch(const cc_block *B, int n, cc_prec prec, int tile, bool own_range
     if (b) {
         b->prec = prec;
         b->tile = id;
+        b->btile = bid;
         b->lev = lev;
     }
     return true;

@@ -803,6 +803,20 @@ __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy
     }
 }
 
+// whether a tile holds a point below its column's band top (block-uniform; every thread calls it)
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ bool band_tile_busy(const Dims &d, const Geo &G, int i0, int j0, int k0)
+{
+    const int t = threadIdx.x;
+    const int i = i0 + t / (TY * TZ), j = j0 + (t / TZ) % TY, k = k0 + t % TZ;
+    bool any = false;
+    if (i < d.nx && j < d.ny && k < d.nz) {
+        const unsigned hc = __umul24(i, d.ny) + j;
+        any = k < band_top(G.colk[hc], G.colk[(unsigned)(d.nx * d.ny) + hc]);
+    }
+    return __syncthreads_or(any);
+}
+
 // the launch covers the k-tiles [bk0, bk0 + nbz); REG: every point the launch updates takes the
 // regular update; SEL as in tile_body (SEL 2: a tile with no point below its column's band top ends
 // at once)
@@ -815,16 +829,7 @@ __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     int bi, bj, bk;
     tile_of_block(nbx, nby, nbz, bi, bj, bk);
     const int k0 = (bk0 + bk) * TZ * KP;
-    if (SEL == 2) {
-        const int t = threadIdx.x;
-        const int i = bi * TX + t / (TY * TZ), j = bj * TY + (t / TZ) % TY, k = k0 + t % TZ;
-        bool any = false;
-        if (i < d.nx && j < d.ny && k < d.nz) {
-            const unsigned hc = __umul24(i, d.ny) + j;
-            any = k < band_top(G.colk[hc], G.colk[(unsigned)(d.nx * d.ny) + hc]);
-        }
-        if (!__syncthreads_or(any)) return;
-    }
+    if (SEL == 2 && !band_tile_busy<TX, TY, TZ>(d, G, bi * TX, bj * TY, k0)) return;
     const OwnRange all{{0, 0, 0}, {d.nx, d.ny, d.nz}};
     tile_body<T, TX, TY, TZ, MODE, KP, REG, SEL>(d, G, P, qs, qn, qo, cdt, final_stage, bi * TX, bj * TY, k0, st,
                                                  all);
@@ -923,11 +928,10 @@ struct BlockDesc {
     Geo G;
     Phy P;
     SOut<T> q[3];       // the block's three state buffers
-    int nbx, nby, nbz;  // tiles of the update kernel
-    int kbt;            // the first kbt k-tiles reach below the band height (full kernel), the rest
-                        // lie above it (kernel without the band paths)
-    int tile0;          // first band tile of the block in the batched band-tile grid
-    int tile0r;         // first tile of the block in the batched above-band grid
+    int nbx, nby, nbz;     // tiles of the regular-point launch (the batch's tile shape) over the range
+    int nbxb, nbyb, nbzb;  // tiles of the band-point launch (one-wave tiles) over the range below kband
+    int tile0;             // first tile of the block in the batched band-point grid
+    int tile0r;            // first tile of the block in the batched regular-point grid
     int col0;           // first column of the block in the batched diagnostic grid
     int ilo[3], ihi[3];  // the block's own cells (the rest of the grid is ghost cells)
     int rlo[3], rhi[3];  // cells the batch updates: own cells and the ghost cells no same-level block
@@ -940,13 +944,14 @@ __device__ __forceinline__ SIn<T> as_in(const SOut<T> &q)
     return SIn<T>{q.rho, q.rth, q.mu, q.mv, q.mw, q.rho_lo, q.rth_lo};
 }
 
-// REG = false: the band tiles of every block (full kernel); REG = true: the tiles above the band
-// height (band paths compiled out)
-template <typename T, int TX, int TY, int TZ, int MODE, int MINW, bool REG = false>
+// SEL = 1 (REG): the points at or above their column's band top, in the batch's tiles over every
+// block's range; SEL = 2: the points below it, in one-wave tiles over the range below kband
+template <typename T, int TX, int TY, int TZ, int MODE, int MINW, int SEL>
 __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     k_stage_batch(const BlockDesc<T> *__restrict__ desc, int nblk, int ntiles, int rn, int rs, int ro,
                   double cdt, int final_stage, int64_t *st)
 {
+    static_assert(SEL == 1 || SEL == 2, "regular or band points");
     // XCD-aware order over the whole batch, then the block that owns this tile
     int b = blockIdx.x;
     int xcd = b & 7, idx = b >> 3, per = ntiles >> 3, rem = ntiles & 7;
@@ -954,17 +959,19 @@ __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     int lo = 0, hi = nblk - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if ((REG ? desc[mid].tile0r : desc[mid].tile0) <= lb) lo = mid;
+        if ((SEL == 1 ? desc[mid].tile0r : desc[mid].tile0) <= lb) lo = mid;
         else hi = mid - 1;
     }
     const BlockDesc<T> &D = desc[lo];
-    const int nk = REG ? D.nbz - D.kbt : D.kbt;
-    int t = lb - (REG ? D.tile0r : D.tile0);
-    int bk = t % nk, t2 = t / nk, bj = t2 % D.nby, bi = t2 / D.nby;
-    if (REG) bk += D.kbt;
-    tile_body<T, TX, TY, TZ, MODE, 1, REG>(D.d, D.G, D.P, as_in(D.q[rs]), as_in(D.q[rn]), D.q[ro], cdt, final_stage,
-                                           D.rlo[0] + bi * TX, D.rlo[1] + bj * TY, D.rlo[2] + bk * TZ, st,
-                                           OwnRange{{D.ilo[0], D.ilo[1], D.ilo[2]}, {D.ihi[0], D.ihi[1], D.ihi[2]}});
+    const int nk = SEL == 1 ? D.nbz : D.nbzb, ny = SEL == 1 ? D.nby : D.nbyb;
+    int t = lb - (SEL == 1 ? D.tile0r : D.tile0);
+    int bk = t % nk, t2 = t / nk, bj = t2 % ny, bi = t2 / ny;
+    const int i0 = D.rlo[0] + bi * TX, j0 = D.rlo[1] + bj * TY, k0 = D.rlo[2] + bk * TZ;
+    if (SEL == 2 && !band_tile_busy<TX, TY, TZ>(D.d, D.G, i0, j0, k0)) return;
+    tile_body<T, TX, TY, TZ, MODE, 1, SEL == 1, SEL>(D.d, D.G, D.P, as_in(D.q[rs]), as_in(D.q[rn]), D.q[ro], cdt,
+                                                     final_stage, i0, j0, k0, st,
+                                                     OwnRange{{D.ilo[0], D.ilo[1], D.ilo[2]},
+                                                              {D.ihi[0], D.ihi[1], D.ihi[2]}});
 }
 
 // ------------------------------------------------------------------------------------------------
