@@ -173,62 +173,105 @@ __device__ __forceinline__ void lat_vel(const Dims &d, const Geo &G, const Phy &
 // of the four corner velocities (eqs. ux1-ux3), zero flux through closed faces (terrain, ground,
 // rigid lid).  Returns d(rho')/dt and d(rho theta)'/dt of master c.
 // ------------------------------------------------------------------------------------------------
-template <typename T, typename R = typename Compute<T>::R>
-__device__ void group_scalar_tendency(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &q,
-                                      int64_t c, double L[2])
+// Offset b - a on a periodic axis of n points, in (-n/2, n/2].
+__device__ __forceinline__ int periodic_offset(int b, int a, int n)
+{
+    int r = b - a;
+    if (2 * r > n) r -= n;
+    else if (2 * r <= -n) r += n;
+    return r;
+}
+
+// The master (i,j,k) = c reads the staged neighbourhood V where a member's corner or neighbour lies in
+// it (the staged values are the ones lat_vel and the state hold) and global memory elsewhere.  The
+// apertures and neighbour masters of a member's six faces are read together.
+template <typename T, typename VW, typename R = typename Compute<T>::R>
+__device__ void group_scalar_tendency(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &q, int64_t c,
+                                      const VW &V, int i, int j, int k, double L[2])
 {
     double rb0 = 0.0, rb1 = 0.0;  // base-state / reference-flow part
     // perturbation part: each face flux is evaluated in R; the per-group sum of those fluxes is
     // formed in double, where a sum of a few floats is exact, so a face contributes exactly
     // opposite amounts to its two groups and mass is conserved to FP64 rounding
     double rp0 = 0.0, rp1 = 0.0;
-    int kc = (int)(c % d.nzs);
+    const int kc = k;
+    const R rc0 = V.rho[V.C(0, 0, 0)], rc1 = V.rth[V.C(0, 0, 0)];
+    // normal velocity component ax of lattice point (I,J,K)
+    auto vel = [&](int I, int J, int K, int ax) -> R {
+        const int di = periodic_offset(I, i, d.nx), dj = periodic_offset(J, j, d.ny), dk = K - k;
+        if (V.has_lat(di, dj, dk)) {
+            const int e = V.Lg(di, dj, dk);
+            return ax == 0 ? V.u[e] : (ax == 1 ? V.v[e] : V.w[e]);
+        }
+        R u[3];
+        lat_vel<T>(d, G, P, q, I, J, K, u);
+        return u[ax];
+    };
     int64_t mem = c;
     for (int guard = 0; mem >= 0 && guard <= CC_MAX_GROUP; ++guard) {
-        int i, j, k;
-        unidx(d, mem, i, j, k);
+        int mi, mj, mk;
+        unidx(d, mem, mi, mj, mk);
+        double Af[6];
+        int32_t mnf[6];
+#pragma unroll
         for (int f = 0; f < 6; ++f) {
-            int axis = f >> 1, plus = f & 1;
-            int fi = i, fj = j, fk = k, ni = i, nj = j, nk = k;
-            if (axis == 0) { if (plus) { fi = i + 1; ni = i + 1; } else ni = i - 1; }
-            else if (axis == 1) { if (plus) { fj = j + 1; nj = j + 1; } else nj = j - 1; }
-            else {
-                if (plus) { fk = k + 1; nk = k + 1; } else nk = k - 1;
-                if (nk < 0 || nk >= d.nz) continue;
-            }
-            int64_t fu = cidx(d, fi, fj, fk);
-            double A = axis == 0 ? G.Ax[fu] : (axis == 1 ? G.Ay[fu] : G.Az[fu]);
+            const int axis = f >> 1, plus = f & 1;
+            const int dc = axis == 2 ? (plus ? 1 : -1) : 0;
+            Af[f] = 0.0;
+            mnf[f] = -1;
+            if (axis == 2 && (mk + dc < 0 || mk + dc >= d.nz)) continue;  // ground and rigid lid
+            const int fi = mi + (axis == 0 && plus), fj = mj + (axis == 1 && plus), fk = mk + (axis == 2 && plus);
+            const int64_t fu = cidx(d, fi, fj, fk);
+            Af[f] = axis == 0 ? G.Ax[fu] : (axis == 1 ? G.Ay[fu] : G.Az[fu]);
+            const int ni = mi + (axis == 0 ? (plus ? 1 : -1) : 0), nj = mj + (axis == 1 ? (plus ? 1 : -1) : 0);
+            mnf[f] = G.master[cidx(d, ni, nj, mk + dc)];
+        }
+        const int64_t next = G.gnext[mem];
+        for (int f = 0; f < 6; ++f) {
+            const int axis = f >> 1, plus = f & 1;
+            const double A = Af[f];
             if (A == 0.0) continue;
-            int32_t mn = G.master[cidx(d, ni, nj, nk)];
+            const int32_t mn = mnf[f];
             if (mn == (int32_t)c || mn < 0) continue;  // internal face of the group
-            R a[3], b[3], e[3], h[3];
+            const int fi = mi + (axis == 0 && plus), fj = mj + (axis == 1 && plus), fk = mk + (axis == 2 && plus);
+            R s4;
             double S, Un;
             if (axis == 0) {
-                lat_vel<T>(d, G, P, q, fi, fj, fk, a); lat_vel<T>(d, G, P, q, fi, fj + 1, fk, b);
-                lat_vel<T>(d, G, P, q, fi, fj, fk + 1, e); lat_vel<T>(d, G, P, q, fi, fj + 1, fk + 1, h);
+                s4 = (vel(fi, fj, fk, 0) + vel(fi, fj + 1, fk, 0)) + (vel(fi, fj, fk + 1, 0) + vel(fi, fj + 1, fk + 1, 0));
                 S = d.dy * d.dz; Un = P.ux;
             } else if (axis == 1) {
-                lat_vel<T>(d, G, P, q, fi, fj, fk, a); lat_vel<T>(d, G, P, q, fi + 1, fj, fk, b);
-                lat_vel<T>(d, G, P, q, fi, fj, fk + 1, e); lat_vel<T>(d, G, P, q, fi + 1, fj, fk + 1, h);
+                s4 = (vel(fi, fj, fk, 1) + vel(fi + 1, fj, fk, 1)) + (vel(fi, fj, fk + 1, 1) + vel(fi + 1, fj, fk + 1, 1));
                 S = d.dz * d.dx; Un = P.vy;
             } else {
-                lat_vel<T>(d, G, P, q, fi, fj, fk, a); lat_vel<T>(d, G, P, q, fi + 1, fj, fk, b);
-                lat_vel<T>(d, G, P, q, fi, fj + 1, fk, e); lat_vel<T>(d, G, P, q, fi + 1, fj + 1, fk, h);
+                s4 = (vel(fi, fj, fk, 2) + vel(fi + 1, fj, fk, 2)) + (vel(fi, fj + 1, fk, 2) + vel(fi + 1, fj + 1, fk, 2));
                 S = d.dx * d.dy; Un = 0.0;
             }
-            R s4 = (a[axis] + b[axis]) + (e[axis] + h[axis]);
-            int64_t mlo = plus ? c : (int64_t)mn, mup = plus ? (int64_t)mn : c;
-            int klo = plus ? kc : (int)(mn % d.nzs), kup = plus ? (int)(mn % d.nzs) : kc;
+            // scalars of the neighbouring master
+            int ni, nj, nk;
+            unidx(d, mn, ni, nj, nk);
+            const int ei = periodic_offset(ni, i, d.nx), ej = periodic_offset(nj, j, d.ny), ek = nk - k;
+            R rn0, rn1;
+            if (V.has_cell(ei, ej, ek)) {
+                const int e = V.Cg(ei, ej, ek);
+                rn0 = V.rho[e];
+                rn1 = V.rth[e];
+            } else {
+                rn0 = (R)q.rho[mn];
+                rn1 = (R)q.rth[mn];
+            }
+            const int klo = plus ? kc : nk, kup = plus ? nk : kc;
             double pb0 = 0.5 * (P.rhob[klo] + P.rhob[kup]);
             double pb1 = 0.5 * (P.rthb[klo] + P.rthb[kup]);
             R f0, f1;
-            scalar_face_flux<R>(s4, (R)(0.25 * A * S), (R)(Un * A * S), (R)pb0, (R)pb1, (R)q.rho[mlo],
-                                (R)q.rho[mup], (R)q.rth[mlo], (R)q.rth[mup], f0, f1);
+            if (plus)
+                scalar_face_flux<R>(s4, (R)(0.25 * A * S), (R)(Un * A * S), (R)pb0, (R)pb1, rc0, rn0, rc1, rn1, f0, f1);
+            else
+                scalar_face_flux<R>(s4, (R)(0.25 * A * S), (R)(Un * A * S), (R)pb0, (R)pb1, rn0, rc0, rn1, rc1, f0, f1);
             double g0 = pb0 * Un * A * S, g1 = pb1 * Un * A * S;
             if (plus) { rp0 += (double)f0; rp1 += (double)f1; rb0 += g0; rb1 += g1; }
             else { rp0 -= (double)f0; rp1 -= (double)f1; rb0 -= g0; rb1 -= g1; }
         }
-        mem = G.gnext[mem];
+        mem = next;
     }
     double vol = G.Vgroup[c] * P.dV;
     L[0] = -(rb0 + rp0) / vol;
@@ -290,9 +333,24 @@ struct LView {
     const R *rho, *rth, *pp, *u, *v, *w, *b;
     int cb[3], lb[3];
     int csj, lsj, nb, kb;
+    // the point's position in the tile (lattice box from (i0-1, j0-1, k0-1), cell box from
+    // (i0-2, j0-2, k0-2)) and the boxes' extents and x strides, for reads at any offset
+    int px, py, pz, lx, ly, lz, cx, cy, cz, lsi, csi;
     __device__ __forceinline__ int C(int di, int dj, int dk) const { return cb[di + 1] + dj * csj + dk; }
     __device__ __forceinline__ int L(int di, int dj, int dk) const { return lb[di + 1] + dj * lsj + dk; }
     __device__ __forceinline__ R B(int prof, int dk) const { return b[prof * nb + kb + dk]; }
+    __device__ __forceinline__ bool has_lat(int di, int dj, int dk) const
+    {
+        const int a = px + 1 + di, b_ = py + 1 + dj, c = pz + 1 + dk;
+        return a >= 0 && a < lx && b_ >= 0 && b_ < ly && c >= 0 && c < lz;
+    }
+    __device__ __forceinline__ int Lg(int di, int dj, int dk) const { return lb[1] + di * lsi + dj * lsj + dk; }
+    __device__ __forceinline__ bool has_cell(int di, int dj, int dk) const
+    {
+        const int a = px + 2 + di, b_ = py + 2 + dj, c = pz + 2 + dk;
+        return a >= 0 && a < cx && b_ >= 0 && b_ < cy && c >= 0 && c < cz;
+    }
+    __device__ __forceinline__ int Cg(int di, int dj, int dk) const { return cb[1] + di * csi + dj * csj + dk; }
 };
 
 // The same neighbourhood read from global memory: q_s scalars, and p' and lattice velocities from
@@ -307,6 +365,11 @@ struct GView {
     int k, nz;
     __device__ __forceinline__ int C(int di, int dj, int dk) const { return cb[di + 1] + cj[dj + 1] + dk; }
     __device__ __forceinline__ int L(int di, int dj, int dk) const { return lb[di + 1] + lj[dj + 1] + dk; }
+    // reads beyond the immediate neighbours go to the state and lat_vel
+    __device__ __forceinline__ bool has_lat(int, int, int) const { return false; }
+    __device__ __forceinline__ int Lg(int, int, int) const { return 0; }
+    __device__ __forceinline__ bool has_cell(int, int, int) const { return false; }
+    __device__ __forceinline__ int Cg(int, int, int) const { return 0; }
     __device__ __forceinline__ R B(int prof, int dk) const
     {
         int kk = k + dk;
@@ -417,7 +480,7 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
             L1 = -r1 * P.idV;
         } else if (G.gnext[c] != -1) {  // master of a multi-cell group: general gather
             double L[2];
-            group_scalar_tendency<T>(d, G, P, qs, c, L);
+            group_scalar_tendency<T>(d, G, P, qs, c, V, i, j, k, L);
             L0 = L[0]; L1 = L[1];
         } else {
             // single-cell group in the band: apertures, group volume and neighbour masters.  The
@@ -796,6 +859,9 @@ __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy
                 V.lb[m] = TL::ls(tx + m, ty + 1, tzp + 1);
             }
             V.csj = TL::CZ; V.lsj = TL::LZ; V.nb = NB; V.kb = tzp + 2;
+            V.px = tx; V.py = ty; V.pz = tzp;
+            V.lx = TL::LX; V.ly = TL::LY; V.lz = TL::LZ; V.cx = TL::CX; V.cy = TL::CY; V.cz = TL::CZ;
+            V.lsi = TL::LY * TL::LZ; V.csi = TL::CY * TL::CZ;
             const bool ghost = i < ownr.lo[0] || i >= ownr.hi[0] || j < ownr.lo[1] || j >= ownr.hi[1] ||
                                k < ownr.lo[2] || k >= ownr.hi[2];
             stage_point<T, MODE, LView<R>, REG>(d, G, P, qs, pin[p], qo, cdt, final_stage, i, j, k, V, st, ghost);
