@@ -104,9 +104,9 @@ def run_gpu(cfg, prec: str, steps: int, warmup: int, tile: int = 0):
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": " + ".join(autotune.kernel_names(tuned["tile"], prec)),
             "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(avg_bytes)}
-    if os.path.exists(TRAFFIC_FILE):
+    if os.path.exists(TRAFFIC_FILE):  # counters taken on this kernel source and tile shape
         tr = json.load(open(TRAFFIC_FILE))
-        ent = tr.get(prec)
+        ent = tr.get(prec, {}).get(str(tuned["tile"]))
         if ent and tr.get("kernel_source_sha256_16") == kernel_hash():
             roof["traffic"] = ent["hbm_bytes_per_launch"]
     value = ncell * 3 * steps / secs
