@@ -248,6 +248,10 @@ struct cc_batch_s {
     char *ws = nullptr;  // caller workspace: descriptors, refill tables, flux registers
     std::vector<Level> lev;
     hipStream_t cap = nullptr;  // private stream used only for graph capture
+    // side stream of the band-point launches, forked from and joined to the stepping stream with
+    // events (created with the batch, outside any capture; null: band launches stay on the stream)
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     struct Graph { int nsteps; double dt; int64_t *st; std::vector<int> cur0, cur1; hipGraphExec_t exec; };
     std::vector<Graph> graphs;
 };
@@ -264,20 +268,29 @@ void launch_batch_stage(const cc_batch_s *b, int l, int rn, int rs, int ro, doub
                         hipStream_t s)
 {
     const Level &L = b->lev[l];
+    // the points below their column's band top, on the side stream beside the regular points (the
+    // two launches write disjoint points and read only inputs)
+    hipStream_t sb = s;
+    if (L.ntiles > 0 && b->side && hipEventRecord(b->fork, s) == hipSuccess &&
+        hipStreamWaitEvent(b->side, b->fork, 0) == hipSuccess)
+        sb = b->side;
+    if (L.ntiles > 0) {
+        if (b->btile == 0)
+            hipLaunchKernelGGL((k_stage_batch<T, 8, 8, 1, 0, 1, 2>), dim3(L.ntiles), dim3(64), 0, sb, descs<T>(b, l),
+                               L.nblk, L.ntiles, rn, rs, ro, cdt, fin, st);
+        else if (b->btile == 1)
+            hipLaunchKernelGGL((k_stage_batch<T, 4, 4, 4, 0, 1, 2>), dim3(L.ntiles), dim3(64), 0, sb, descs<T>(b, l),
+                               L.nblk, L.ntiles, rn, rs, ro, cdt, fin, st);
+        else
+            hipLaunchKernelGGL((k_stage_batch<T, 2, 2, 16, 0, 1, 2>), dim3(L.ntiles), dim3(64), 0, sb, descs<T>(b, l),
+                               L.nblk, L.ntiles, rn, rs, ro, cdt, fin, st);
+    }
     if (L.ntilesr > 0)  // the points at or above their column's band top
         hipLaunchKernelGGL((k_stage_batch<T, TX, TY, TZ, 0, MINW, 1>), dim3(L.ntilesr), dim3(TX * TY * TZ), 0, s,
                            descs<T>(b, l), L.nblk, L.ntilesr, rn, rs, ro, cdt, fin, st);
-    if (L.ntiles > 0) {  // the points below it
-        if (b->btile == 0)
-            hipLaunchKernelGGL((k_stage_batch<T, 8, 8, 1, 0, 1, 2>), dim3(L.ntiles), dim3(64), 0, s, descs<T>(b, l),
-                               L.nblk, L.ntiles, rn, rs, ro, cdt, fin, st);
-        else if (b->btile == 1)
-            hipLaunchKernelGGL((k_stage_batch<T, 4, 4, 4, 0, 1, 2>), dim3(L.ntiles), dim3(64), 0, s, descs<T>(b, l),
-                               L.nblk, L.ntiles, rn, rs, ro, cdt, fin, st);
-        else
-            hipLaunchKernelGGL((k_stage_batch<T, 2, 2, 16, 0, 1, 2>), dim3(L.ntiles), dim3(64), 0, s, descs<T>(b, l),
-                               L.nblk, L.ntiles, rn, rs, ro, cdt, fin, st);
-    }
+    // join: later work on s waits for the band launch (should the join fail, the host waits)
+    if (sb != s && (hipEventRecord(b->join, sb) != hipSuccess || hipStreamWaitEvent(s, b->join, 0) != hipSuccess))
+        (void)hipStreamSynchronize(sb);
 }
 
 template <typename T>
@@ -704,6 +717,18 @@ bool plan_batch(const cc_block *B, int n, cc_prec prec, int tile, bool own_range
     return true;
 }
 
+// side stream and fork/join events of a batch; without them the band launches stay on the stepping
+// stream
+void make_side(cc_batch_s *b)
+{
+    if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess) { b->side = nullptr; return; }
+    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(b->side);
+        b->side = nullptr;
+    }
+}
+
 bool upload(cc_batch_s *b, const Plan &plan, const Tables *t, hipStream_t s, const char *what)
 {
     hipError_t e = hipSuccess;
@@ -754,7 +779,8 @@ extern "C" cc_status amr_batch_create(const cc_block *blocks, int32_t nblocks, c
     Plan plan;
     if (!plan_batch(blocks, nblocks, prec, tile, false, t, b, plan, "amr_batch_create")) { delete b; return CC_EINVAL; }
     b->ws = (char *)workspace;
-    if (!upload(b, plan, nullptr, (hipStream_t)stream, "amr_batch_create")) { delete b; return CC_EDEVICE; }
+    make_side(b);
+    if (!upload(b, plan, nullptr, (hipStream_t)stream, "amr_batch_create")) { amr_batch_destroy(b); return CC_EDEVICE; }
     *out = b;
     return CC_OK;
 }
@@ -790,7 +816,8 @@ extern "C" cc_status amr_hierarchy_create(const cc_block *blocks, int32_t nblock
         return CC_EINVAL;
     }
     b->ws = (char *)workspace;
-    if (!upload(b, plan, &t, (hipStream_t)stream, "amr_hierarchy_create")) { delete b; return CC_EDEVICE; }
+    make_side(b);
+    if (!upload(b, plan, &t, (hipStream_t)stream, "amr_hierarchy_create")) { amr_batch_destroy(b); return CC_EDEVICE; }
     *out = b;
     return CC_OK;
 }
@@ -859,6 +886,9 @@ extern "C" cc_status amr_batch_destroy(cc_batch b)
     if (!b) return CC_OK;
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
     delete b;
     return CC_OK;
 }
