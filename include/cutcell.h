@@ -100,8 +100,10 @@ typedef struct {
     int32_t *colk;            /* [3][nx*ny] per column: first k of the regular cell interior; 1 + top
                                  K of a lattice point that is not predicted; 1 + top level of any
                                  diagnosed point, absorbed or solid cell */
-    void *stage_ws;           /* optional workspace of cutcell_stage_workspace_bytes() bytes: enables
-                                 the two-pass update (cc_grid.tile = 20); NULL otherwise */
+    void *stage_ws;           /* optional workspace of cutcell_stage_workspace_bytes() bytes: holds the
+                                 list of band tiles cutcell_merge_map writes (the band-point launch
+                                 then covers only tiles with band points) and enables the two-pass
+                                 update (cc_grid.tile = 20); NULL otherwise */
     int32_t kband;            /* host value set by cutcell_merge_map: the highest column band top.
                                  A column's band top is one above its highest point that is not
                                  regular (a cell that is cut, merged, or next to a closed face or a
@@ -110,6 +112,9 @@ typedef struct {
                                  column's band top with a kernel without the band paths and the rest
                                  with the full kernel over k < kband.  0 or out of [1, nz]: unknown
                                  (the full kernel everywhere) */
+    int32_t nband_tiles;      /* host value set by cutcell_merge_map: number of band tiles in the list
+                                 at the start of stage_ws; -1 without stage_ws (the band-point launch
+                                 then covers every tile below kband) */
 } cc_geom;
 
 /* Five prognostic fields; element type double (CC_F64) or float (CC_F32_PERT).
@@ -125,8 +130,9 @@ typedef struct {
 
 const char *cutcell_version(void);
 
-/* Bytes of the optional stage workspace (cc_geom.stage_ws) of a grid: p' at every cell and the
- * velocity at every lattice point, in the storage precision's compute type. */
+/* Bytes of the optional stage workspace (cc_geom.stage_ws) of a grid: the band-tile list (one int32
+ * per one-wave tile of the grid, rounded up to 256 bytes), then p' at every cell and the velocity at
+ * every lattice point, in the storage precision's compute type. */
 size_t cutcell_stage_workspace_bytes(const cc_grid *grid, cc_prec prec);
 const char *cutcell_last_error(void);
 

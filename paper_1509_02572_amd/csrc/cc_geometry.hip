@@ -6,6 +6,7 @@
 // any IEEE-754 double implementation that follows the same order.
 #pragma clang fp contract(off)
 
+#include <algorithm>
 #include <vector>
 
 #include "cc_internal.hpp"
@@ -476,5 +477,32 @@ extern "C" cc_status cutcell_merge_map(const cc_grid *grid, cc_geom *g, int64_t 
         top = b > top ? b : top;
     }
     g->kband = top < d.nz ? top : d.nz;
+    // the band-point launch's one-wave tiles that hold band points, each listed as
+    // (bk nbx + bi) nby + bj in (bi, bj, bk) order, at the start of the stage workspace
+    g->nband_tiles = -1;
+    if (g->stage_ws) {
+        const BandTile bt = band_tile_of(d.nx, d.ny, d.nz);
+        std::vector<int32_t> list;
+        for (int bi = 0; bi < bt.nbx; ++bi)
+            for (int bj = 0; bj < bt.nby; ++bj) {
+                int deep = 0;
+                for (int i = bi * bt.bx; i < std::min(d.nx, (bi + 1) * bt.bx); ++i)
+                    for (int j = bj * bt.by; j < std::min(d.ny, (bj + 1) * bt.by); ++j) {
+                        const int64_t c = (int64_t)i * d.ny + j;
+                        deep = std::max(deep, band_top(bands[(size_t)c], bands[(size_t)(nc + c)]));
+                    }
+                for (int bk = 0; bk * bt.bz < std::min(deep, d.nz); ++bk)
+                    list.push_back((bk * bt.nbx + bi) * bt.nby + bj);
+            }
+        if (!list.empty()) {
+            e = hipMemcpyAsync(g->stage_ws, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host list is freed on return
+            if (e != hipSuccess) {
+                set_error("cutcell_merge_map: %s", hipGetErrorString(e));
+                return CC_EDEVICE;
+            }
+        }
+        g->nband_tiles = (int32_t)list.size();
+    }
     return CC_OK;
 }

@@ -56,6 +56,29 @@ __host__ __device__ __forceinline__ int band_top(int kcell, int klat)
     return kcell > kl ? kcell : kl;
 }
 
+// One-wave tiles of the band-point update: 8x8x1, or 4x4x4 / 2x2x16 on grids narrower than 8 / 4
+// columns (the periodic index arithmetic wraps at most once)
+struct BandTile { int bx, by, bz, nbx, nby, nbz; };
+inline BandTile band_tile_of(int nx, int ny, int nz)
+{
+    BandTile t;
+    if (nx >= 8 && ny >= 8) { t.bx = 8; t.by = 8; t.bz = 1; }
+    else if (nx >= 4 && ny >= 4) { t.bx = 4; t.by = 4; t.bz = 4; }
+    else { t.bx = 2; t.by = 2; t.bz = 16; }
+    t.nbx = (nx + t.bx - 1) / t.bx;
+    t.nby = (ny + t.by - 1) / t.by;
+    t.nbz = (nz + t.bz - 1) / t.bz;
+    return t;
+}
+// The stage workspace starts with the list of band tiles that hold band points (one int32 each),
+// room for every tile of the grid, rounded up to 256 bytes; the two-pass arrays follow it.
+inline size_t band_list_bytes(int nx, int ny, int nz)
+{
+    const BandTile t = band_tile_of(nx, ny, nz);
+    const size_t b = sizeof(int32_t) * (size_t)t.nbx * t.nby * t.nbz;
+    return (b + 255) / 256 * 256;
+}
+
 __device__ __forceinline__ void count_status(int64_t *st, int which, int64_t n = 1)
 {
     if (st) atomicAdd(reinterpret_cast<unsigned long long *>(st + which), (unsigned long long)n);

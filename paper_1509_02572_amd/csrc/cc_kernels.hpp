@@ -39,8 +39,9 @@ struct Geo {
     const double *H, *V, *Ax, *Ay, *Az, *nrm, *Vgroup;
     const int8_t *cls, *vcls;
     const int32_t *master, *gnext, *colk;
-    void *ws;   // optional stage workspace (two-pass update), may be null
+    void *ws;   // optional stage workspace (band-tile list, two-pass update), may be null
     int kband;  // highest column band top: every point at k >= kband is regular (0: unknown)
+    int nband;  // tiles in the band-tile list at the start of ws (-1: no list)
 };
 
 constexpr int EOS_TERMS = 11;  // binomial series terms of (1+x)^gamma - 1 (double; float uses 6)
@@ -893,9 +894,19 @@ __global__ void __launch_bounds__(TX * TY * TZ, MINW)
 {
     static_assert(SEL != 2 || KP == 1, "band tiles hold one point per thread");
     int bi, bj, bk;
-    tile_of_block(nbx, nby, nbz, bi, bj, bk);
+    if (SEL == 2 && G.nband >= 0) {  // the listed band tiles (each holds band points), XCD-aware order
+        const int b = blockIdx.x, n = G.nband;
+        const int xcd = b & 7, idx = b >> 3, per = n >> 3, rem = n & 7;
+        const int t = ((const int32_t *)G.ws)[xcd * per + (xcd < rem ? xcd : rem) + idx];
+        const int r = t % (nbx * nby);
+        bk = t / (nbx * nby);
+        bi = r / nby;
+        bj = r % nby;
+    } else {
+        tile_of_block(nbx, nby, nbz, bi, bj, bk);
+    }
     const int k0 = (bk0 + bk) * TZ * KP;
-    if (SEL == 2 && !band_tile_busy<TX, TY, TZ>(d, G, bi * TX, bj * TY, k0)) return;
+    if (SEL == 2 && G.nband < 0 && !band_tile_busy<TX, TY, TZ>(d, G, bi * TX, bj * TY, k0)) return;
     const OwnRange all{{0, 0, 0}, {d.nx, d.ny, d.nz}};
     tile_body<T, TX, TY, TZ, MODE, KP, REG, SEL>(d, G, P, qs, qn, qo, cdt, final_stage, bi * TX, bj * TY, k0, st,
                                                  all);
@@ -1393,7 +1404,7 @@ inline bool make_views(const char *what, const cc_grid *grid, const cc_phys *phy
     if (prec != CC_F64 && prec != CC_F32_PERT) { set_error("%s: unknown precision %d", what, (int)prec); return false; }
     d = dims_of(grid);
     G = Geo{g->H, g->V, g->Ax, g->Ay, g->Az, g->nrm, g->Vgroup, g->cls, g->vcls, g->master, g->gnext, g->colk,
-            g->stage_ws, g->kband};
+            g->stage_ws, g->kband, g->stage_ws ? g->nband_tiles : -1};
     double cv = phys->cp - phys->rd;
     P.rhob = base; P.rthb = base + d.nz; P.pb = base + 2 * d.nz; P.thb = base + 3 * d.nz;
     P.irthb = base + 4 * d.nz; P.rhobc = base + 5 * d.nz;

@@ -201,9 +201,10 @@ static void launch_band(const Dims &d, const Geo &G, const Phy &P, const cc_stat
                         cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
 {
     int nbx = (d.nx + TX - 1) / TX, nby = (d.ny + TY - 1) / TY, nbz = (G.kband + TZ - 1) / TZ;
-    hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, 1, 1, false, 2>), dim3(nbx * nby * nbz), dim3(TX * TY * TZ),
-                       0, s, d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, nbx, nby, nbz,
-                       0, st);
+    const int n = G.nband >= 0 ? G.nband : nbx * nby * nbz;  // the listed tiles, else all below kband
+    if (n > 0)
+        hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, 1, 1, false, 2>), dim3(n), dim3(TX * TY * TZ), 0, s, d,
+                           G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, nbx, nby, nbz, 0, st);
 }
 
 template <typename T, int TX, int TY, int TZ, int MODE, int MINW = 1, int KP = 1>
@@ -261,7 +262,7 @@ static void launch_two_pass(const Dims &d, const Geo &G, const Phy &P, const cc_
                             cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
 {
     using R = typename Compute<T>::R;
-    R *ws = (R *)G.ws;
+    R *ws = (R *)((char *)G.ws + band_list_bytes(d.nx, d.ny, d.nz));
     int64_t ncol = (int64_t)d.nx * d.ny;
     hipLaunchKernelGGL(k_prepare<T>, dim3(blocks_for(ncol * lattice_stride(d.nzs), 256)), dim3(256), 0, s, d, G, P,
                        sin_of<T>(qs), ws);
@@ -433,5 +434,6 @@ extern "C" size_t cutcell_stage_workspace_bytes(const cc_grid *grid, cc_prec pre
     if (!grid || grid->nx <= 0 || grid->ny <= 0 || grid->nzs <= 0) return 0;
     size_t esz = prec == CC_F64 ? sizeof(double) : sizeof(float);
     size_t ncol = (size_t)grid->nx * grid->ny;
-    return esz * ncol * ((size_t)grid->nzs + 3 * (size_t)lattice_stride(grid->nzs));
+    return band_list_bytes(grid->nx, grid->ny, grid->nz) +
+           esz * ncol * ((size_t)grid->nzs + 3 * (size_t)lattice_stride(grid->nzs));
 }

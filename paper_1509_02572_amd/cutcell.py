@@ -39,7 +39,7 @@ class cc_phys(C.Structure):
 class cc_geom(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("H", "V", "Ax", "Ay", "Az", "col", "nrm", "cls", "dir",
                                            "vcls", "master", "gnext", "Vgroup", "colk", "stage_ws")] + \
-               [("kband", C.c_int32)]
+               [("kband", C.c_int32), ("nband_tiles", C.c_int32)]
 
 
 class cc_state(C.Structure):

@@ -332,3 +332,25 @@ def test_tile_shapes_bitwise_identical(name, prec):
         for f in ref.t:
             assert torch.equal(out.t[f], ref.t[f]), (tid, f)
     assert not dom.check()[:5].any()
+
+
+# ------------------------------------------------------------------------------------------------
+# the band-point launch over the listed band tiles (grid with a stage workspace) and over every
+# tile below the band height (no workspace) compute bitwise the same stage
+# ------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,prec", [("bell_small", "f32"), ("ragged", "f64"), ("steep_random", "f64")])
+def test_band_tile_list_matches_full_band_grid(name, prec):
+    cfg = SMALL[name]()
+    print(f"case {name} {prec}", flush=True)
+    listed = CC.Domain(cfg, prec)
+    plain = CC.Domain(cfg, prec, stage_ws=False)
+    assert listed.geom.nband_tiles >= 0 and plain.geom.nband_tiles == -1
+    assert listed.geom.kband == plain.geom.kband
+    noise = W.theta_noise(cfg.replace(noise_sigma=0.01, seed=4))
+    a = listed.run(listed.init_state(noise), cfg.dt, 3)
+    b = plain.run(plain.init_state(noise), cfg.dt, 3)
+    torch.cuda.synchronize()
+    for f in a.t:
+        assert torch.equal(a.t[f], b.t[f]), f
+    assert not listed.check()[:5].any() and not plain.check()[:5].any()
