@@ -297,18 +297,31 @@ struct Tile {
 };
 
 // tile origin of this block with an XCD-aware order: blocks are dealt round-robin to the 8 XCDs,
-// so each XCD is given a contiguous range of tiles (k fastest, then j, then i) and shares halos in
-// its own L2
+// so each XCD is given a contiguous range of tiles and shares halos in its own L2.  The range runs
+// through strips of SJ tile columns in j, and inside a strip k fastest, then j, then i: a tile's
+// neighbours in i and j follow it within a few strip rows, while their halos are still in L2.
 __device__ __forceinline__ void tile_of_block(int nbx, int nby, int nbz, int &bi, int &bj, int &bk)
 {
-    int nb = nbx * nby * nbz;
-    int b = blockIdx.x;
-    int xcd = b & 7, idx = b >> 3, per = nb >> 3, rem = nb & 7;
-    int lb = xcd * per + (xcd < rem ? xcd : rem) + idx;
-    bk = lb % nbz;
-    int t2 = lb / nbz;
-    bj = t2 % nby;
-    bi = t2 / nby;
+    constexpr int SJ = 4;
+    const int nb = nbx * nby * nbz;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, idx = b >> 3, per = nb >> 3, rem = nb & 7;
+    const int lb = xcd * per + (xcd < rem ? xcd : rem) + idx;
+    const int nfull = nby / SJ, full = nfull * SJ * nbx * nbz;
+    int s, w, r;
+    if (lb < full) {
+        s = lb / (SJ * nbx * nbz);
+        r = lb - s * (SJ * nbx * nbz);
+        w = SJ;
+    } else {  // the last, narrower strip
+        s = nfull;
+        r = lb - full;
+        w = nby - nfull * SJ;
+    }
+    bk = r % nbz;
+    r /= nbz;
+    bj = s * SJ + r % w;
+    bi = r / w;
 }
 
 // p' of a cell from its (rho theta)' with base values staged in the compute precision: binomial
