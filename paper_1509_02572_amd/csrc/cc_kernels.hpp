@@ -296,17 +296,14 @@ struct Tile {
     __device__ static constexpr int ls(int a, int b, int c) { return (a * LY + b) * LZ + c; }
 };
 
-// tile origin of this block with an XCD-aware order: blocks are dealt round-robin to the 8 XCDs,
-// so each XCD is given a contiguous range of tiles and shares halos in its own L2.  The range runs
-// through strips of SJ tile columns in j, and inside a strip k fastest, then j, then i: a tile's
-// neighbours in i and j follow it within a few strip rows, while their halos are still in L2.
-__device__ __forceinline__ void tile_of_block(int nbx, int nby, int nbz, int &bi, int &bj, int &bk)
+// Tile lb of an nbx x nby x nbz grid of tiles: the tiles run through strips of SJ tile columns in j,
+// and inside a strip k fastest, then j, then i, so a tile's neighbours in i and j follow it within a
+// few strip rows, while their halos are still in L2.
+// tile_of_block: the tile of this block with an XCD-aware order: blocks are dealt round-robin to the
+// 8 XCDs, so each XCD is given a contiguous range of tiles and shares halos in its own L2.
+__device__ __forceinline__ void strip_tile(int lb, int nbx, int nby, int nbz, int &bi, int &bj, int &bk)
 {
     constexpr int SJ = 4;
-    const int nb = nbx * nby * nbz;
-    const int b = blockIdx.x;
-    const int xcd = b & 7, idx = b >> 3, per = nb >> 3, rem = nb & 7;
-    const int lb = xcd * per + (xcd < rem ? xcd : rem) + idx;
     const int nfull = nby / SJ, full = nfull * SJ * nbx * nbz;
     int s, w, r;
     if (lb < full) {
@@ -322,6 +319,14 @@ __device__ __forceinline__ void tile_of_block(int nbx, int nby, int nbz, int &bi
     r /= nbz;
     bj = s * SJ + r % w;
     bi = r / w;
+}
+
+__device__ __forceinline__ void tile_of_block(int nbx, int nby, int nbz, int &bi, int &bj, int &bk)
+{
+    const int nb = nbx * nby * nbz;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, idx = b >> 3, per = nb >> 3, rem = nb & 7;
+    strip_tile(xcd * per + (xcd < rem ? xcd : rem) + idx, nbx, nby, nbz, bi, bj, bk);
 }
 
 // p' of a cell from its (rho theta)' with base values staged in the compute precision: binomial
@@ -1054,8 +1059,8 @@ __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     }
     const BlockDesc<T> &D = desc[lo];
     const int nk = SEL == 1 ? D.nbz : D.nbzb, ny = SEL == 1 ? D.nby : D.nbyb;
-    int t = lb - (SEL == 1 ? D.tile0r : D.tile0);
-    int bk = t % nk, t2 = t / nk, bj = t2 % ny, bi = t2 / ny;
+    int bi, bj, bk;
+    strip_tile(lb - (SEL == 1 ? D.tile0r : D.tile0), SEL == 1 ? D.nbx : D.nbxb, ny, nk, bi, bj, bk);
     const int i0 = D.rlo[0] + bi * TX, j0 = D.rlo[1] + bj * TY, k0 = D.rlo[2] + bk * TZ;
     if (SEL == 2 && !band_tile_busy<TX, TY, TZ>(D.d, D.G, i0, j0, k0)) return;
     tile_body<T, TX, TY, TZ, MODE, 1, SEL == 1, SEL>(D.d, D.G, D.P, as_in(D.q[rs]), as_in(D.q[rn]), D.q[ro], cdt,
