@@ -354,3 +354,36 @@ def test_band_tile_list_matches_full_band_grid(name, prec):
     for f in a.t:
         assert torch.equal(a.t[f], b.t[f]), f
     assert not listed.check()[:5].any() and not plain.check()[:5].any()
+
+
+# ------------------------------------------------------------------------------------------------
+# one step of a single grid captured into a HIP graph (the band-point launch forked to the side
+# stream inside the capture) replays bitwise like eager stepping, with eager work between replays
+# ------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_single_grid_graph_replays_match_eager(prec):
+    cfg = SMALL["bell_small"]()
+    print(f"case graph bell_small {prec}", flush=True)
+    dom = CC.Domain(cfg, prec)
+    x = dom.init_state(W.theta_noise(cfg.replace(noise_sigma=0.01, seed=6)))
+    y, z = dom.new_state(), dom.new_state()
+    dom.step(x, y, z, cfg.dt)  # eager first call (creates the side stream); x is only read
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        dom.step(x, y, z, cfg.dt)
+    torch.cuda.synchronize()
+    ea, eb, ec = dom.new_state(), dom.new_state(), dom.new_state()
+    for rep in range(3):
+        for f in x.t:
+            ea.t[f].copy_(x.t[f])
+        ref = dom.step(ea, eb, ec, cfg.dt)[0]
+        g.replay()
+        torch.cuda.synchronize()
+        for f in x.t:
+            assert torch.equal(y.t[f], ref.t[f]), (rep, f)
+        for f in x.t:  # the next replay starts from this one's output
+            x.t[f].copy_(y.t[f])
+        torch.cuda.synchronize()
+    assert not dom.check()[:5].any()
