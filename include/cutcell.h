@@ -257,7 +257,7 @@ size_t amr_batch_workspace_bytes(int32_t nblocks, cc_prec prec);
 
 /* Describe nblocks level-0 blocks (independent periodic domains) to the device: copies the
  * descriptors into `workspace`, which must stay allocated until amr_batch_destroy, and synchronises
- * `stream`.  `tile` selects the update kernel's tile shape as cc_grid.tile does (ids 0, 1, 7, 8, 9, 12; one
+ * `stream`.  `tile` selects the update kernel's tile shape as cc_grid.tile does (ids 0, 1, 6, 7, 8, 9, 11, 12; one
  * shape for the batch; smaller shapes are taken when a block cannot hold it).  The handle is host
  * state owned by the caller.  Blocks with level != 0 return CC_EINVAL. */
 cc_status amr_batch_create(const cc_block *blocks, int32_t nblocks, cc_prec prec, int32_t tile,

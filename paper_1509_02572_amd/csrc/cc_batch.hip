@@ -310,6 +310,8 @@ void level_stage(cc_batch_s *b, int l, int rn, int rs, int ro, double cdt, int f
     const Level &L = b->lev[l];
     switch (b->tile) {
     case 1: launch_batch_stage<T, 4, 4, 16, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
+    case 6: launch_batch_stage<T, 4, 4, 32, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
+    case 11: launch_batch_stage<T, 4, 4, 16, 8>(b, l, rn, rs, ro, cdt, fin, st, s); break;
     case 8: launch_batch_stage<T, 2, 2, 64, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
     case 9: launch_batch_stage<T, 8, 8, 8, 6>(b, l, rn, rs, ro, cdt, fin, st, s); break;
     case 7: launch_batch_stage<T, 8, 8, 16, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
@@ -646,11 +648,11 @@ int batch_tile(const cc_block *B, int n, int tile, int &TX, int &TY, int &TZ)
             if (B[m].grid.nx < tx || B[m].grid.ny < ty) return false;
         return true;
     };
-    int id = (tile == 1 || tile == 7 || tile == 8 || tile == 9 || tile == 12) ? tile : 0;
+    int id = (tile == 1 || tile == 6 || tile == 7 || tile == 8 || tile == 9 || tile == 11 || tile == 12) ? tile : 0;
     auto shape = [&](int i) {
-        TX = (i == 1 || i == 12) ? 4 : (i == 8 ? 2 : 8);
-        TY = i == 1 ? 4 : (i == 8 ? 2 : 8);
-        TZ = (i == 1 || i == 7 || i == 12) ? 16 : (i == 8 ? 64 : 8);
+        TX = (i == 1 || i == 6 || i == 11 || i == 12) ? 4 : (i == 8 ? 2 : 8);
+        TY = (i == 1 || i == 6 || i == 11) ? 4 : (i == 8 ? 2 : 8);
+        TZ = i == 6 ? 32 : ((i == 1 || i == 7 || i == 11 || i == 12) ? 16 : (i == 8 ? 64 : 8));
     };
     shape(id);
     if (!fits(TX, TY)) { id = fits(4, 4) ? 1 : 8; shape(id); }
