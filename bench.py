@@ -171,7 +171,7 @@ def run_amr(prec: str, warmup: int, layout=None):
     from paper_1509_02572_amd import workloads as W
     lay = layout if layout is not None else W.amr_hemisphere(2000)
     t0 = time.perf_counter()
-    h = CC.Hierarchy(lay, prec, "cuda:0", tile=9)
+    h = CC.Hierarchy(lay, prec, "cuda:0", tile=11)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     nsteps = lay.base.nsteps
