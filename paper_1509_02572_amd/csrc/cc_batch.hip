@@ -626,10 +626,13 @@ bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, i
         h[m].nbxb = (h[m].rhi[0] - h[m].rlo[0] + BX - 1) / BX;
         h[m].nbyb = (h[m].rhi[1] - h[m].rlo[1] + BY - 1) / BY;
         h[m].nbzb = nlev > 0 ? (nlev + BZ - 1) / BZ : 0;
+        // a whole-grid block whose stage workspace lists its band tiles in this shape takes the list
+        const BandTile own = band_tile_of(d.nx, d.ny, d.nz);
+        h[m].blist = !own_range && G.ws && G.nband >= 0 && own.bx == BX && own.by == BY && own.bz == BZ;
         h[m].tile0 = tiles;
         h[m].tile0r = tilesr;
         h[m].col0 = cols;
-        tiles += h[m].nbxb * h[m].nbyb * h[m].nbzb;
+        tiles += h[m].blist ? G.nband : h[m].nbxb * h[m].nbyb * h[m].nbzb;
         tilesr += h[m].nbx * h[m].nby * h[m].nbz;
         cols += (h[m].rhi[0] - h[m].rlo[0]) * (h[m].rhi[1] - h[m].rlo[1]);
     }

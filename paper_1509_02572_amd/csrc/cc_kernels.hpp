@@ -1025,6 +1025,8 @@ struct BlockDesc {
     SOut<T> q[3];       // the block's three state buffers
     int nbx, nby, nbz;     // tiles of the regular-point launch (the batch's tile shape) over the range
     int nbxb, nbyb, nbzb;  // tiles of the band-point launch (one-wave tiles) over the range below kband
+    int blist;             // 1: the band-point launch takes the block's listed band tiles (G.nband of
+                           // them, at the start of G.ws) instead of all nbxb nbyb nbzb
     int tile0;             // first tile of the block in the batched band-point grid
     int tile0r;            // first tile of the block in the batched regular-point grid
     int col0;           // first column of the block in the batched diagnostic grid
@@ -1060,9 +1062,17 @@ __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     const BlockDesc<T> &D = desc[lo];
     const int nk = SEL == 1 ? D.nbz : D.nbzb, ny = SEL == 1 ? D.nby : D.nbyb;
     int bi, bj, bk;
-    strip_tile(lb - (SEL == 1 ? D.tile0r : D.tile0), SEL == 1 ? D.nbx : D.nbxb, ny, nk, bi, bj, bk);
+    if (SEL == 2 && D.blist) {  // the block's listed band tiles (each holds band points)
+        const int t = ((const int32_t *)D.G.ws)[lb - D.tile0];
+        const int r = t % (D.nbxb * D.nbyb);
+        bk = t / (D.nbxb * D.nbyb);
+        bi = r / D.nbyb;
+        bj = r % D.nbyb;
+    } else {
+        strip_tile(lb - (SEL == 1 ? D.tile0r : D.tile0), SEL == 1 ? D.nbx : D.nbxb, ny, nk, bi, bj, bk);
+    }
     const int i0 = D.rlo[0] + bi * TX, j0 = D.rlo[1] + bj * TY, k0 = D.rlo[2] + bk * TZ;
-    if (SEL == 2 && !band_tile_busy<TX, TY, TZ>(D.d, D.G, i0, j0, k0)) return;
+    if (SEL == 2 && !D.blist && !band_tile_busy<TX, TY, TZ>(D.d, D.G, i0, j0, k0)) return;
     tile_body<T, TX, TY, TZ, MODE, 1, SEL == 1, SEL>(D.d, D.G, D.P, as_in(D.q[rs]), as_in(D.q[rn]), D.q[ro], cdt,
                                                      final_stage, i0, j0, k0, st,
                                                      OwnRange{{D.ilo[0], D.ilo[1], D.ilo[2]},
