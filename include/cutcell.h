@@ -114,7 +114,10 @@ typedef struct {
                                  (the full kernel everywhere) */
     int32_t nband_tiles;      /* host value set by cutcell_merge_map: number of band tiles in the list
                                  at the start of stage_ws; -1 without stage_ws (the band-point launch
-                                 then covers every tile below kband) */
+                                 then covers every tile below kband).  The list lives in the
+                                 workspace given to cutcell_merge_map: another workspace needs
+                                 another call (or nband_tiles = -1); entries that are not tiles of
+                                 the grid are skipped */
 } cc_geom;
 
 /* Five prognostic fields; element type double (CC_F64) or float (CC_F32_PERT).

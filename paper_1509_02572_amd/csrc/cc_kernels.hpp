@@ -916,6 +916,7 @@ __global__ void __launch_bounds__(TX * TY * TZ, MINW)
         const int b = blockIdx.x, n = G.nband;
         const int xcd = b & 7, idx = b >> 3, per = n >> 3, rem = n & 7;
         const int t = ((const int32_t *)G.ws)[xcd * per + (xcd < rem ? xcd : rem) + idx];
+        if (t < 0 || t >= nbx * nby * nbz) return;  // not a tile of this grid (a stale list)
         const int r = t % (nbx * nby);
         bk = t / (nbx * nby);
         bi = r / nby;
@@ -1064,6 +1065,7 @@ __global__ void __launch_bounds__(TX * TY * TZ, MINW)
     int bi, bj, bk;
     if (SEL == 2 && D.blist) {  // the block's listed band tiles (each holds band points)
         const int t = ((const int32_t *)D.G.ws)[lb - D.tile0];
+        if (t < 0 || t >= D.nbxb * D.nbyb * D.nbzb) return;  // not a tile of this block (a stale list)
         const int r = t % (D.nbxb * D.nbyb);
         bk = t / (D.nbxb * D.nbyb);
         bi = r / D.nbyb;
