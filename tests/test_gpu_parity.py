@@ -44,7 +44,13 @@ def _steep_random():
     raise RuntimeError
 
 
+def _flat():
+    # no terrain above the ground: every cell is regular, the band is empty
+    return W.Config("flat", 24, 20, 16, 100.0, 100.0, 50.0, W.Hill("flat"), u0=6.0, v0=1.5, dt=0.05)
+
+
 SMALL = {
+    "flat": _flat,
     "bell32": lambda: W.get("bell32"),
     "hemi_tiny": lambda: W.get("hemi_tiny"),
     "bell_small": lambda: W.get("bell_small"),
@@ -387,3 +393,29 @@ def test_single_grid_graph_replays_match_eager(prec):
             x.t[f].copy_(y.t[f])
         torch.cuda.synchronize()
     assert not dom.check()[:5].any()
+
+
+def test_flat_terrain_f64_parity():
+    """Flat ground: only the regular update runs (no band).  Without terrain the flow stays close to
+    the reference state, so the perturbations are driven by a 1 K theta' noise, large enough that
+    they stand well above the FP64 rounding of the base-state fluxes the oracle sums and the kernel
+    cancels exactly."""
+    cfg = _flat()
+    o = O.Oracle(cfg).merge()
+    noise = W.theta_noise(cfg.replace(noise_sigma=1.0, seed=1))
+    ref = o.run(o.init_state(noise), cfg.dt, 20)
+    dom = CC.Domain(cfg, "f64")
+    got = dom.run(dom.init_state(noise), cfg.dt, 20)
+    torch.cuda.synchronize()
+    _compare_state(o, dom.state_numpy(got), ref.a, 1e-12, "flat")
+    assert not dom.check()[:5].any()
+
+
+def test_flat_terrain_has_no_band():
+    """Over flat ground every point is regular (the ground row of lattice points is never
+    predicted and the ground closes the bottom faces): the band height is 1 and no band tile is
+    listed, so the update is the regular-point launch alone."""
+    dom = CC.Domain(_flat(), "f64")
+    assert dom.geom.kband == 1 and dom.geom.nband_tiles == 0
+    colk = dom.g["colk"].cpu().numpy().reshape(3, -1)
+    assert colk[0].max() == 0 and colk[1].max() == 1
