@@ -196,7 +196,7 @@ __device__ void group_scalar_tendency(const Dims &d, const Geo &G, const Phy &P,
     // opposite amounts to its two groups and mass is conserved to FP64 rounding
     double rp0 = 0.0, rp1 = 0.0;
     const int kc = k;
-    const R rc0 = V.rho[V.C(0, 0, 0)], rc1 = V.rth[V.C(0, 0, 0)];
+    const R rc0 = V.rho[V.C(0, 0, 0)], rc1 = V.rth[V.Ct(0, 0, 0)];
     // normal velocity component ax of lattice point (I,J,K)
     auto vel = [&](int I, int J, int K, int ax) -> R {
         const int di = periodic_offset(I, i, d.nx), dj = periodic_offset(J, j, d.ny), dk = K - k;
@@ -252,14 +252,8 @@ __device__ void group_scalar_tendency(const Dims &d, const Geo &G, const Phy &P,
             unidx(d, mn, ni, nj, nk);
             const int ei = periodic_offset(ni, i, d.nx), ej = periodic_offset(nj, j, d.ny), ek = nk - k;
             R rn0, rn1;
-            if (V.has_cell(ei, ej, ek)) {
-                const int e = V.Cg(ei, ej, ek);
-                rn0 = V.rho[e];
-                rn1 = V.rth[e];
-            } else {
-                rn0 = (R)q.rho[mn];
-                rn1 = (R)q.rth[mn];
-            }
+            rn0 = V.has_cell(ei, ej, ek) ? V.rho[V.Cg(ei, ej, ek)] : (R)q.rho[mn];
+            rn1 = V.has_rth(ei, ej, ek) ? V.rth[V.Ct(ei, ej, ek)] : (R)q.rth[mn];
             const int klo = plus ? kc : nk, kup = plus ? nk : kc;
             double pb0 = 0.5 * (P.rhob[klo] + P.rhob[kup]);
             double pb1 = 0.5 * (P.rthb[klo] + P.rthb[kup]);
@@ -292,8 +286,13 @@ struct Tile {
     static constexpr int NT = TX * TY * TZ;
     static constexpr int CX = TX + 3, CY = TY + 3, CZ = TZ + 3, NC = CX * CY * CZ;  // cells from (i0-2, j0-2, k0-2)
     static constexpr int LX = TX + 2, LY = TY + 2, LZ = TZ + 2, NL = LX * LY * LZ;  // lattice from (i0-1, j0-1, k0-1)
+    // (rho theta)' is read one cell around the tile, p' at the cells i0-1.. i0+TX-1 (and so in y, z)
+    static constexpr int RX = TX + 2, RY = TY + 2, RZ = TZ + 2, NR = RX * RY * RZ;  // from (i0-1, j0-1, k0-1)
+    static constexpr int PX = TX + 1, PY = TY + 1, PZ = TZ + 1, NP = PX * PY * PZ;  // from (i0-1, j0-1, k0-1)
     __device__ static constexpr int cs(int a, int b, int c) { return (a * CY + b) * CZ + c; }
     __device__ static constexpr int ls(int a, int b, int c) { return (a * LY + b) * LZ + c; }
+    __device__ static constexpr int rs(int a, int b, int c) { return (a * RY + b) * RZ + c; }
+    __device__ static constexpr int ps(int a, int b, int c) { return (a * PY + b) * PZ + c; }
 };
 
 // Tile lb of an nbx x nby x nbz grid of tiles: the tiles run through strips of SJ tile columns in j,
@@ -355,7 +354,16 @@ struct LView {
     // the point's position in the tile (lattice box from (i0-1, j0-1, k0-1), cell box from
     // (i0-2, j0-2, k0-2)) and the boxes' extents and x strides, for reads at any offset
     int px, py, pz, lx, ly, lz, cx, cy, cz, lsi, csi;
+    // (rho theta)' box (cells one around the tile) and p' box: index of the point's own cell, strides
+    int rb, rsi, rsj, rx, ry, rz, pb, psi, psj;
     __device__ __forceinline__ int C(int di, int dj, int dk) const { return cb[di + 1] + dj * csj + dk; }
+    __device__ __forceinline__ int Ct(int di, int dj, int dk) const { return rb + di * rsi + dj * rsj + dk; }
+    __device__ __forceinline__ int Pp(int di, int dj, int dk) const { return pb + di * psi + dj * psj + dk; }
+    __device__ __forceinline__ bool has_rth(int di, int dj, int dk) const
+    {
+        const int a = px + 1 + di, b_ = py + 1 + dj, c = pz + 1 + dk;
+        return a >= 0 && a < rx && b_ >= 0 && b_ < ry && c >= 0 && c < rz;
+    }
     __device__ __forceinline__ int L(int di, int dj, int dk) const { return lb[di + 1] + dj * lsj + dk; }
     __device__ __forceinline__ R B(int prof, int dk) const { return b[prof * nb + kb + dk]; }
     __device__ __forceinline__ bool has_lat(int di, int dj, int dk) const
@@ -384,6 +392,9 @@ struct GView {
     int k, nz;
     __device__ __forceinline__ int C(int di, int dj, int dk) const { return cb[di + 1] + cj[dj + 1] + dk; }
     __device__ __forceinline__ int L(int di, int dj, int dk) const { return lb[di + 1] + lj[dj + 1] + dk; }
+    __device__ __forceinline__ int Ct(int di, int dj, int dk) const { return C(di, dj, dk); }
+    __device__ __forceinline__ int Pp(int di, int dj, int dk) const { return C(di, dj, dk); }
+    __device__ __forceinline__ bool has_rth(int, int, int) const { return false; }
     // reads beyond the immediate neighbours go to the state and lat_vel
     __device__ __forceinline__ bool has_lat(int, int, int) const { return false; }
     __device__ __forceinline__ int Lg(int, int, int) const { return 0; }
@@ -453,7 +464,7 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
     const int8_t cl = band ? G.cls[c] : (int8_t)CC_OPEN;
     if (cl == CC_OPEN || cl == CC_ORPHAN) {
         double L0, L1;
-        const R rc0 = V.rho[V.C(0, 0, 0)], rc1 = V.rth[V.C(0, 0, 0)];
+        const R rc0 = V.rho[V.C(0, 0, 0)], rc1 = V.rth[V.Ct(0, 0, 0)];
         if (!band) {
             // regular cell: V = 1, open faces, neighbours at their own level; the base-state and
             // reference-flow fluxes of opposite faces cancel exactly
@@ -466,16 +477,16 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
             {  // x faces
                 R sm = (V.u[V.L(0, 0, 0)] + V.u[V.L(0, 1, 0)]) + (V.u[V.L(0, 0, 1)] + V.u[V.L(0, 1, 1)]);
                 R sp = (V.u[V.L(1, 0, 0)] + V.u[V.L(1, 1, 0)]) + (V.u[V.L(1, 0, 1)] + V.u[V.L(1, 1, 1)]);
-                scalar_face_flux<R>(sm, ASx, UASx, b0, b1, V.rho[V.C(-1, 0, 0)], rc0, V.rth[V.C(-1, 0, 0)], rc1, fm0, fm1);
-                scalar_face_flux<R>(sp, ASx, UASx, b0, b1, rc0, V.rho[V.C(1, 0, 0)], rc1, V.rth[V.C(1, 0, 0)], fp0, fp1);
+                scalar_face_flux<R>(sm, ASx, UASx, b0, b1, V.rho[V.C(-1, 0, 0)], rc0, V.rth[V.Ct(-1, 0, 0)], rc1, fm0, fm1);
+                scalar_face_flux<R>(sp, ASx, UASx, b0, b1, rc0, V.rho[V.C(1, 0, 0)], rc1, V.rth[V.Ct(1, 0, 0)], fp0, fp1);
                 r0 = (double)fp0 - (double)fm0;
                 r1 = (double)fp1 - (double)fm1;
             }
             {  // y faces
                 R sm = (V.v[V.L(0, 0, 0)] + V.v[V.L(1, 0, 0)]) + (V.v[V.L(0, 0, 1)] + V.v[V.L(1, 0, 1)]);
                 R sp = (V.v[V.L(0, 1, 0)] + V.v[V.L(1, 1, 0)]) + (V.v[V.L(0, 1, 1)] + V.v[V.L(1, 1, 1)]);
-                scalar_face_flux<R>(sm, ASy, UASy, b0, b1, V.rho[V.C(0, -1, 0)], rc0, V.rth[V.C(0, -1, 0)], rc1, fm0, fm1);
-                scalar_face_flux<R>(sp, ASy, UASy, b0, b1, rc0, V.rho[V.C(0, 1, 0)], rc1, V.rth[V.C(0, 1, 0)], fp0, fp1);
+                scalar_face_flux<R>(sm, ASy, UASy, b0, b1, V.rho[V.C(0, -1, 0)], rc0, V.rth[V.Ct(0, -1, 0)], rc1, fm0, fm1);
+                scalar_face_flux<R>(sp, ASy, UASy, b0, b1, rc0, V.rho[V.C(0, 1, 0)], rc1, V.rth[V.Ct(0, 1, 0)], fp0, fp1);
                 r0 += (double)fp0 - (double)fm0;
                 r1 += (double)fp1 - (double)fm1;
             }
@@ -483,14 +494,14 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
                 if (k > 0) {
                     R sm = (V.w[V.L(0, 0, 0)] + V.w[V.L(1, 0, 0)]) + (V.w[V.L(0, 1, 0)] + V.w[V.L(1, 1, 0)]);
                     scalar_face_flux<R>(sm, ASz, (R)0, V.B(4, 0), V.B(5, 0), V.rho[V.C(0, 0, -1)], rc0,
-                                        V.rth[V.C(0, 0, -1)], rc1, fm0, fm1);
+                                        V.rth[V.Ct(0, 0, -1)], rc1, fm0, fm1);
                     r0 -= (double)fm0;
                     r1 -= (double)fm1;
                 }
                 if (k + 1 < nz) {
                     R sp = (V.w[V.L(0, 0, 1)] + V.w[V.L(1, 0, 1)]) + (V.w[V.L(0, 1, 1)] + V.w[V.L(1, 1, 1)]);
                     scalar_face_flux<R>(sp, ASz, (R)0, V.B(4, 1), V.B(5, 1), rc0, V.rho[V.C(0, 0, 1)], rc1,
-                                        V.rth[V.C(0, 0, 1)], fp0, fp1);
+                                        V.rth[V.Ct(0, 0, 1)], fp0, fp1);
                     r0 += (double)fp0;
                     r1 += (double)fp1;
                 }
@@ -546,7 +557,7 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
                     s4 = (V.w[V.L(fa, fb, fc)] + V.w[V.L(fa + 1, fb, fc)]) + (V.w[V.L(fa, fb + 1, fc)] + V.w[V.L(fa + 1, fb + 1, fc)]);
                     S = d.dx * d.dy; Un = 0.0;
                 }
-                const R rn0 = V.rho[V.C(da, db, dc)], rn1 = V.rth[V.C(da, db, dc)];
+                const R rn0 = V.rho[V.C(da, db, dc)], rn1 = V.rth[V.Ct(da, db, dc)];
                 int klo = plus ? k : kn, kup = plus ? kn : k;
                 double pb0 = 0.5 * (P.rhob[klo] + P.rhob[kup]);
                 double pb1 = 0.5 * (P.rthb[klo] + P.rthb[kup]);
@@ -601,9 +612,8 @@ __device__ __forceinline__ void stage_point(const Dims &d, const Geo &G, const P
         R rp[8], pp[8];  // bit0: i-1/i, bit1: j-1/j, bit2: k-1/k
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            int e = V.C((s & 1) - 1, ((s >> 1) & 1) - 1, (s >> 2) - 1);
-            rp[s] = V.rho[e];
-            pp[s] = V.pp[e];
+            rp[s] = V.rho[V.C((s & 1) - 1, ((s >> 1) & 1) - 1, (s >> 2) - 1)];
+            pp[s] = V.pp[V.Pp((s & 1) - 1, ((s >> 1) & 1) - 1, (s >> 2) - 1)];
         }
         // density perturbation on the six faces of the velocity cell, pressure gradient, buoyancy
         const R rxm = q4 * ((rp[0] + rp[2]) + (rp[4] + rp[6])), rxp = q4 * ((rp[1] + rp[3]) + (rp[5] + rp[7]));
@@ -697,7 +707,7 @@ __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy
     constexpr int NT = TX * TY * TZ;
     constexpr int IT1 = (TL::NC + NT - 1) / NT, IT2 = (TL::NL + NT - 1) / NT;
     constexpr int NB = TZ * KP + 4;  // staged base levels k0-2 .. k0+TZ KP+1
-    __shared__ R s_rho[TL::NC], s_rth[TL::NC], s_pp[TL::NC];
+    __shared__ R s_rho[TL::NC], s_rth[TL::NR], s_pp[TL::NP];
     __shared__ R s_u[TL::NL], s_v[TL::NL], s_w[TL::NL];
     // base profiles in the compute precision: rhobar, (rho theta)bar, pbar, 1/(rho theta)bar, and
     // the means of rhobar and (rho theta)bar over levels k-1, k (z faces / lattice level k)
@@ -819,12 +829,14 @@ __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy
         if (e < TL::NC) {
             int a = e / (TL::CY * TL::CZ), r = e - a * (TL::CY * TL::CZ), b = r / TL::CZ, c = r - b * TL::CZ;
             int k = k0 - 2 + c;
-            R pp = (R)0;
-            if (k >= 0 && k < nz && a >= 1 && a <= TX + 1 && b >= 1 && b <= TY + 1 && c >= 1 && c <= TZ * KP + 1)
-                pp = eos_staged<R>(c_rth[it], s_b[3][c], s_b[2][c], P);
             s_rho[e] = c_rho[it];
-            s_rth[e] = c_rth[it];
-            s_pp[e] = pp;
+            if (a >= 1 && a <= TX + 2 && b >= 1 && b <= TY + 2 && c >= 1 && c <= TZ * KP + 2)
+                s_rth[TL::rs(a - 1, b - 1, c - 1)] = c_rth[it];
+            if (a >= 1 && a <= TX + 1 && b >= 1 && b <= TY + 1 && c >= 1 && c <= TZ * KP + 1) {
+                R pp = (R)0;
+                if (k >= 0 && k < nz) pp = eos_staged<R>(c_rth[it], s_b[3][c], s_b[2][c], P);
+                s_pp[TL::ps(a - 1, b - 1, c - 1)] = pp;
+            }
         }
     }
     __syncthreads();
@@ -881,6 +893,9 @@ __device__ __forceinline__ void tile_body(const Dims &d, const Geo &G, const Phy
             V.px = tx; V.py = ty; V.pz = tzp;
             V.lx = TL::LX; V.ly = TL::LY; V.lz = TL::LZ; V.cx = TL::CX; V.cy = TL::CY; V.cz = TL::CZ;
             V.lsi = TL::LY * TL::LZ; V.csi = TL::CY * TL::CZ;
+            V.rb = TL::rs(tx + 1, ty + 1, tzp + 1); V.rsi = TL::RY * TL::RZ; V.rsj = TL::RZ;
+            V.rx = TL::RX; V.ry = TL::RY; V.rz = TL::RZ;
+            V.pb = TL::ps(tx + 1, ty + 1, tzp + 1); V.psi = TL::PY * TL::PZ; V.psj = TL::PZ;
             const bool ghost = i < ownr.lo[0] || i >= ownr.hi[0] || j < ownr.lo[1] || j >= ownr.hi[1] ||
                                k < ownr.lo[2] || k >= ownr.hi[2];
             stage_point<T, MODE, LView<R>, REG>(d, G, P, qs, pin[p], qo, cdt, final_stage, i, j, k, V, st, ghost);
