@@ -88,3 +88,23 @@ def test_hierarchy_layout_validation_on_host(lib):
         CC.amr_hierarchy_workspace_bytes(_fake_blocks(CC, lay, bad_overlap=True), CC.CC_F64, dom0)
     with pytest.raises(RuntimeError, match="leave the level"):
         CC.amr_hierarchy_workspace_bytes(_fake_blocks(CC, lay), CC.CC_F64, (8, 16, 24))
+
+
+def test_stage_workspace_layout(lib):
+    """cutcell_stage_workspace_bytes: the band-tile list (one int32 per one-wave tile of the grid,
+    8x8x1 tiles, or 4x4x4 / 2x2x16 on grids narrower than 8 / 4 columns, rounded up to 256 bytes)
+    followed by p' per cell and three velocity components per lattice point (nzs + 16 levels)."""
+    from paper_1509_02572_amd import cutcell as CC
+
+    def expected(nx, ny, nz, nzs, esz):
+        bx, by, bz = (8, 8, 1) if nx >= 8 and ny >= 8 else ((4, 4, 4) if nx >= 4 and ny >= 4 else (2, 2, 16))
+        tiles = -(-nx // bx) * -(-ny // by) * -(-nz // bz)
+        head = -(-4 * tiles // 256) * 256
+        return head + esz * nx * ny * (nzs + 3 * (nzs + 16))
+
+    L = CC.lib()
+    for nx, ny, nz in ((256, 256, 128), (37, 29, 23), (6, 6, 6), (3, 5, 40)):
+        nzs = CC.default_nzs(nz)
+        g = CC.cc_grid(nx, ny, nz, nzs, 100.0, 100.0, 50.0, 16, 0)
+        for prec, esz in ((CC.CC_F64, 8), (CC.CC_F32_PERT, 4)):
+            assert L.cutcell_stage_workspace_bytes(ctypes.byref(g), prec) == expected(nx, ny, nz, nzs, esz)
