@@ -1,26 +1,32 @@
 """Benchmark of the cut-cell Runge-Kutta stage on one MI355X.
 
-Workload: the 256 x 256 x 128 bell-hill domain (dx = dy = 100 m, dz = 50 m, h0 = 400 m, a = 2 km,
-theta' noise from seed 0, dt = 0.05 s).  A "step" is one three-stage Runge-Kutta step: per stage the
-fused tendency+update kernel and the velocity-diagnostic kernel.  The metric is interior
-cell-updates per second per stage (nx*ny*nz cells x 3 stages per step), for the FP32 perturbation
-form (headline) and the plain FP64 path (reported beside it).
+Headline workload: the 512 x 512 x 160 hemisphere domain (dx = dy = dz = 50 m, R = 1 km, N = 0.01 1/s,
+U = 10 m/s, no noise, dt = 0.05 s), the largest single-grid configuration.  A "step" is one
+three-stage Runge-Kutta step: per stage the fused tendency+update and the velocity-diagnostic
+kernel.  The metric is interior cell-updates per second per stage (nx*ny*nz cells x 3 stages per
+step), for the FP32 perturbation form (headline) and the plain FP64 path (reported beside it).  The
+256 x 256 x 128 bell-hill domain (theta' noise, seed 0) is reported as a second line.
 
-The roofline object describes the dominant kernel, the fused update of one stage, which runs as two
-back-to-back launches of the same kernel template: every point at or above its column's band top
-(over the whole grid, the band paths compiled out), then the points below it (cut, merged and
-next-to-terrain cells; lattice points not predicted) in one-wave tiles.  Its algorithmic bytes per stage (5 fields read
-and written per cell, plus q_n read in stages 2 and 3) are divided by the stage's update duration,
-measured with HIP events around the two launches on the launch stream, against the 8 TB/s HBM peak.  Measured HBM traffic
-comes from a committed rocprofv3 counter summary when it was taken on the current kernel source.
-The CPU baseline times the FP64 oracle on this machine's host cores on four steps of the workload.
+The roofline object describes the dominant kernel, the fused update of one stage (the regular-point
+launch over the whole grid plus the band-point launch below the band height).  Its algorithmic bytes
+are those the method must move per cell-stage: stage 1 reads q_s (= q_n) and writes q_out, 5 fields
+each (40 B in the FP32 form, 80 B in FP64); stages 2-3 also read q_n (60 B / 120 B).  The FP32 form's
+final stage also moves the low-order parts of rho' and (rho theta)' (+16 B/cell), reported as overhead
+and not counted.  They are divided by the stage's update duration, measured with HIP events around
+the launches on the launch stream, against the 8 TB/s HBM peak.  Measured HBM traffic comes from a
+committed rocprofv3 counter summary when it was taken on the current kernel source.
 
 The refined line (both precisions) runs the three-level hemisphere grid of blocks (25 level-0 steps in
 one graph launch; cell-updates count the blocks' own cells x their level's steps x 3 stages).
 The ensemble line (both precisions) advances 64 independent domains of uneven size through 50 steps
-with one captured graph of the batched kernels.
+with one captured graph of the batched kernels.  Both carry a roofline object over their graph time
+with the same per-cell algorithmic bytes (own cells only).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f32|f64] [--no-cpu] [--no-ensemble] [--no-amr]
+The CPU baseline times the FP64 oracle on this machine's host cores on one step of the headline
+workload; --cpu-sweep also times one stage at 1, 2, 4, ... host threads.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f32|f64] [--workload hemi512|bell256]
+                       [--no-cpu] [--no-ensemble] [--no-amr] [--no-second] [--cpu-sweep]
 """
 import argparse
 import hashlib
@@ -33,8 +39,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_bell256.json")
 STAGE_SRC = os.path.join(ROOT, "paper_1509_02572_amd", "csrc", "cc_kernels.hpp")
+WORKLOADS = {
+    "hemi512": "hemi512: 512x512x160 cells at dx=dy=dz=50 m, hemisphere R=1 km, N=0.01 1/s, U=10 m/s, "
+               "no noise, dt=0.05 s",
+    "bell256": "bell256: 256x256x128 cells, dx=dy=100 m, dz=50 m, bell hill h0=400 m a=2 km, N=0.01 1/s, "
+               "U=10 m/s, theta' noise N(0,0.01 K) seed 0, dt=0.05 s",
+}
 
 
 def log(*a):
@@ -45,25 +56,48 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(STAGE_SRC, "rb").read()).hexdigest()[:16]
 
 
+def traffic_file(name: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_update_{name}.json")
+
+
+def algorithmic_bytes(prec: str, stage: int) -> int:
+    """Bytes per cell the method must move in RK stage `stage` (0, 1, 2): read q_s (stage 1: q_s is
+    q_n) and write q_out, stages 2-3 also read q_n; 5 fields of 4 B (FP32 form) or 8 B (FP64)."""
+    esz = 8 if prec == "f64" else 4
+    return 5 * esz * (2 if stage == 0 else 3)
+
+
+def lo_overhead_bytes(prec: str, stage: int) -> int:
+    """Extra bytes per cell of the FP32 form's final stage: the low-order parts of rho' and (rho
+    theta)' read from q_n and written to q_out (not part of the algorithmic count)."""
+    return 16 if (prec == "f32" and stage == 2) else 0
+
+
+def roofline(bytes_per_launch: float, ms: float, **extra) -> dict:
+    achieved = bytes_per_launch / (ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    out.update(extra)
+    return out
+
+
 def run_gpu(cfg, prec: str, steps: int, warmup: int, tile: int = 0):
     import torch
+    from paper_1509_02572_amd import autotune
     from paper_1509_02572_amd import cutcell as CC
     from paper_1509_02572_amd import workloads as W
 
-    from paper_1509_02572_amd import autotune
     dom = CC.Domain(cfg, prec, "cuda:0")
     q = dom.init_state(W.theta_noise(cfg))
     if tile:
         dom.grid.tile = tile  # fixed tile shape (profiling runs)
-        tuned = {"tile": tile}
+        tuned = {"tile": tile, "source": "fixed"}
     else:
-        tuned = autotune.tune(dom, q, path=None, dt=cfg.dt)  # untimed: picks the tile shape
-        log(f"bench: {prec} tile timings (ms per update launch): "
-            + ", ".join(f"{k}{autotune.TILE_IDS[k]}w{autotune.TILE_MINW.get(k, 0)}={v:.4f}"
-                        for k, v in tuned["ms"].items()))
+        tuned = autotune.tune(dom, q, dt=cfg.dt)  # untimed: picks the tile shape (or reads the cache)
+        log(f"bench: {cfg.name} {prec} tile {tuned['tile']} ({tuned['source']}); ms per update launch: "
+            + ", ".join(f"{k}={v:.4f}" for k, v in tuned["ms"].items()))
     a, b, c = q, dom.new_state(), dom.new_state()
     dt = cfg.dt
-    esz = 8 if prec == "f64" else 4
     ncell = cfg.nx * cfg.ny * cfg.nz
     stream = torch.cuda.current_stream()
 
@@ -92,27 +126,29 @@ def run_gpu(cfg, prec: str, steps: int, warmup: int, tile: int = 0):
     if st[:5].any():
         raise RuntimeError(f"device status counters set: {st}")
     secs = t1 - t0
-    upd_ms = [e0.elapsed_time(e1) for e0, e1, _ in ev]
-    # algorithmic bytes: stage 1 reads q_s (= q_n) and writes q_out; stages 2-3 also read q_n; the
-    # float form's final stage also reads and writes the low-order parts of rho' and (rho theta)'
-    lo = 16 if prec == "f32" else 0
-    bytes_per = [ncell * (5 * esz * (2 if s == 0 else 3) + (lo if s == 2 else 0)) for _, _, s in ev]
-    avg_ms = sum(upd_ms) / len(upd_ms)
-    avg_bytes = sum(bytes_per) / len(bytes_per)
-    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": " + ".join(autotune.kernel_names(tuned["tile"], prec)),
-            "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(avg_bytes)}
-    if os.path.exists(TRAFFIC_FILE):  # counters taken on this kernel source and tile shape
-        tr = json.load(open(TRAFFIC_FILE))
+    upd = [(e0.elapsed_time(e1), s) for e0, e1, s in ev]
+    avg_ms = sum(m for m, _ in upd) / len(upd)
+    avg_bytes = sum(ncell * algorithmic_bytes(prec, s) for _, s in upd) / len(upd)
+    over = sum(ncell * lo_overhead_bytes(prec, s) for _, s in upd) / len(upd)
+    per_stage = {}
+    for s in range(3):
+        ms = [m for m, t in upd if t == s]
+        per_stage[f"stage{s + 1}"] = {"ms": round(sum(ms) / len(ms), 4),
+                                      "cell_updates_per_s": ncell / (sum(ms) / len(ms) * 1e-3),
+                                      "bytes_per_cell": algorithmic_bytes(prec, s)}
+    roof = roofline(avg_bytes, avg_ms, kernel=" + ".join(autotune.kernel_names(tuned["tile"], prec)),
+                    avg_launch_ms=round(avg_ms, 4), algorithmic_bytes_per_launch=int(avg_bytes),
+                    bytes_per_cell_stage=round(avg_bytes / ncell, 2), overhead_bytes_per_launch=int(over),
+                    per_stage=per_stage, tile=tuned["tile"], tile_shape=list(autotune.TILE_IDS[tuned["tile"]]))
+    tf = traffic_file(cfg.name)
+    if os.path.exists(tf):  # counters taken on this kernel source and tile shape
+        tr = json.load(open(tf))
         ent = tr.get(prec, {}).get(str(tuned["tile"]))
         if ent and tr.get("kernel_source_sha256_16") == kernel_hash():
             roof["traffic"] = ent["hbm_bytes_per_launch"]
+            roof["traffic_source"] = os.path.relpath(tf, ROOT)
     value = ncell * 3 * steps / secs
     red = dom.reduce(a)
-    roof["tile"] = list(autotune.TILE_IDS[tuned["tile"]])
-    roof["tile_min_waves_per_simd"] = autotune.TILE_MINW.get(tuned["tile"], 0)
     return {"value": value, "ms_per_step": secs / steps * 1e3, "roofline": roof,
             "mass_total": float(red[2]), "mass_pert": float(red[0])}
 
@@ -121,6 +157,7 @@ def run_ensemble(prec: str, warmup: int):
     """The 64-member ensemble: every member advanced through all its steps by one graph launch of
     the batched kernels (one update and one diagnostic launch per stage for the whole batch)."""
     import torch
+    from paper_1509_02572_amd import autotune
     from paper_1509_02572_amd import cutcell as CC
     from paper_1509_02572_amd import workloads as W
     cfgs = W.ensemble(64, 0)
@@ -128,20 +165,8 @@ def run_ensemble(prec: str, warmup: int):
     states = [d.init_state() for d in doms]
     dt, nsteps = cfgs[0].dt, cfgs[0].nsteps
     stream = torch.cuda.current_stream()
-    # tile shape of the batch: one eager step per candidate, timed with events
-    times = {}
-    for tile in (0, 1, 6, 7, 9, 11, 12):
-        b = CC.Batch(doms, states, tile=tile)
-        b.step(dt, 1)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        b.step(dt, 2)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        times[tile] = e0.elapsed_time(e1)
-        b.close()
-    tile = min(times, key=times.get)
-    batch = CC.Batch(doms, states, tile=tile)
+    tuned = autotune.tune_batch(doms, states, dt, prec)
+    batch = CC.Batch(doms, states, tile=tuned["tile"])
     for _ in range(max(warmup, 1)):
         batch.step(dt, nsteps, use_graph=True)  # the first call captures the graph
     torch.cuda.synchronize()
@@ -157,9 +182,15 @@ def run_ensemble(prec: str, warmup: int):
         raise RuntimeError(f"device status counters set: {st}")
     cells = batch.cells
     batch.close()
+    gms = e0.elapsed_time(e1)
+    # whole graph (updates, band launches, diagnostics) against the algorithmic bytes of its stages
+    byts = cells * sum(algorithmic_bytes(prec, s) for s in range(3)) * nsteps
     return {"value": cells * 3 * nsteps / secs, "unit": "cell-updates/s", "cells": cells,
-            "steps": nsteps, "ms_per_step": secs / nsteps * 1e3, "graph_ms": e0.elapsed_time(e1),
-            "tile": tile, "tile_ms_per_2_steps": {str(k): round(v, 4) for k, v in times.items()}}
+            "steps": nsteps, "ms_per_step": secs / nsteps * 1e3, "graph_ms": gms,
+            "tile": tuned["tile"], "tile_source": tuned["source"],
+            "tile_ms": {str(k): round(v, 4) for k, v in tuned["ms"].items()},
+            "roofline": roofline(byts, gms, scope="whole graph (all stages, diagnostics included)",
+                                 algorithmic_bytes=int(byts))}
 
 
 def run_amr(prec: str, warmup: int, layout=None):
@@ -167,11 +198,13 @@ def run_amr(prec: str, warmup: int, layout=None):
     subcycling with flux matching): all its level-0 steps in one graph launch.  Cell-updates count
     own cells only (each level's cells x its steps x 3 stages); ghost work is overhead."""
     import torch
+    from paper_1509_02572_amd import autotune
     from paper_1509_02572_amd import cutcell as CC
     from paper_1509_02572_amd import workloads as W
     lay = layout if layout is not None else W.amr_hemisphere(2000)
+    tuned = autotune.tune_refined(lay, prec)
     t0 = time.perf_counter()
-    h = CC.Hierarchy(lay, prec, "cuda:0", tile=11)
+    h = CC.Hierarchy(lay, prec, "cuda:0", tile=tuned["tile"])
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     nsteps = lay.base.nsteps
@@ -191,32 +224,68 @@ def run_amr(prec: str, warmup: int, layout=None):
     st = h.check()
     if st[:6].any():
         raise RuntimeError(f"device status counters set: {st}")
-    updates = sum(lay.cells(l) * (1 << l) for l in range(lay.levels)) * 3 * nsteps
+    own = sum(lay.cells(l) * (1 << l) for l in range(lay.levels))  # own-cell updates per level-0 stage
+    updates = own * 3 * nsteps
     box = sum(int(d.cfg.nx * d.cfg.ny * d.cfg.nz) for d in h.doms)
     h.close()
+    gms = e0.elapsed_time(e1)
+    byts = own * sum(algorithmic_bytes(prec, s) for s in range(3)) * nsteps
     return {"value": updates / secs, "unit": "cell-updates/s", "blocks": len(lay.blocks),
             "own_cells_per_level": [lay.cells(l) for l in range(lay.levels)], "box_cells": box,
-            "steps_level0": nsteps, "ms_per_level0_step": secs / nsteps * 1e3, "graph_ms": e0.elapsed_time(e1),
-            "setup_s": round(setup, 1)}
+            "steps_level0": nsteps, "ms_per_level0_step": secs / nsteps * 1e3, "graph_ms": gms,
+            "setup_s": round(setup, 1), "tile": tuned["tile"], "tile_source": tuned["source"],
+            "roofline": roofline(byts, gms, scope="whole graph (own cells; ghost updates, refills, flux "
+                                                  "matching and diagnostics included in the time)",
+                                 algorithmic_bytes=int(byts))}
 
 
-def run_cpu_baseline(cfg):
-    """FP64 oracle on the host cores: four full steps (three stages each) of the same workload,
-    about 10 s of CPU work."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_cpu_baseline(cfg, sweep: bool = False):
+    """FP64 oracle on the host cores: one full step (three stages with their diagnostics) of the
+    headline workload.  With `sweep`, one stage is also timed at 1, 2, 4, ... threads."""
     from oracle import oracle as O
     from paper_1509_02572_amd import workloads as W
     O.build(force=False)
     o = O.Oracle(cfg).merge()
     q = o.init_state(W.theta_noise(cfg))
     threads = O.set_threads(0)
-    nsteps = 4
+    nsteps = 1
     t0 = time.perf_counter()
     o.run(q, cfg.dt, nsteps)
     secs = time.perf_counter() - t0
     n = cfg.nx * cfg.ny * cfg.nz
-    return {"value": n * 3 * nsteps / secs, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{nsteps} RK steps (3 stages each) of the {cfg.nx}x{cfg.ny}x{cfg.nz} workload, FP64, "
-                      f"{secs:.1f} s"}
+    out = {"value": n * 3 * nsteps / secs, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{nsteps} RK step (3 stages with diagnostics) of the {cfg.nx}x{cfg.ny}x{cfg.nz} workload, "
+                     f"FP64, {secs:.1f} s", "cpu_model": cpu_model()}
+    if sweep:
+        rows = []
+        t = 1
+        counts = []
+        while t < threads:
+            counts.append(t)
+            t *= 2
+        counts.append(threads)
+        buf = o.rk_stage(q, q, cfg.dt / 3.0)  # output state, its pages touched outside the timing
+        for t in counts:
+            O.set_threads(t)
+            t0 = time.perf_counter()
+            o.rk_stage(q, q, cfg.dt / 3.0, out=buf)
+            rows.append((t, time.perf_counter() - t0))
+            log(f"bench: cpu oracle {t} threads: one stage {rows[-1][1]:.2f} s")
+        O.set_threads(threads)
+        t1 = rows[0][1]
+        out["sweep"] = [{"threads": t, "stage_s": round(s, 3), "cell_updates_per_s": n / s,
+                         "parallel_efficiency": round(t1 / (t * s), 3)} for t, s in rows]
+    return out
 
 
 def main():
@@ -225,9 +294,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--workload", default="hemi512", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sweep", action="store_true", help="also time one oracle stage at 1, 2, 4, ... threads")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
+    ap.add_argument("--no-second", action="store_true", help="skip the second single-grid workload")
+    ap.add_argument("--no-other-prec", action="store_true", help="time the chosen precision only")
     ap.add_argument("--tile", type=int, default=0, help="fixed update-kernel tile id (default: autotuned)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -246,17 +319,28 @@ def main():
         torch.cuda.synchronize()
         log("bench: copy calibration: 3 copies of 1 GiB (1 GiB read + 1 GiB written each)")
         del src, dst
-    cfg = W.get("bell256")
+    cfg = W.get(args.workload)
     other = "f64" if args.prec == "f32" else "f32"
     log(f"bench: {cfg.name} {cfg.nx}x{cfg.ny}x{cfg.nz} prec={args.prec} steps={args.steps} warmup={args.warmup}")
     head = run_gpu(cfg, args.prec, args.steps, args.warmup, args.tile)
-    log(f"bench: {args.prec} {head['value']:.4g} cell-updates/s, {head['ms_per_step']:.3f} ms/step")
-    side = run_gpu(cfg, other, args.steps, args.warmup, args.tile)
-    log(f"bench: {other} {side['value']:.4g} cell-updates/s, {side['ms_per_step']:.3f} ms/step")
-    f64 = head if args.prec == "f64" else side
+    log(f"bench: {cfg.name} {args.prec} {head['value']:.4g} cell-updates/s, {head['ms_per_step']:.3f} ms/step, "
+        f"frac {head['roofline']['frac']}")
+    side = None
+    if not args.no_other_prec:
+        side = run_gpu(cfg, other, args.steps, args.warmup, args.tile)
+        log(f"bench: {cfg.name} {other} {side['value']:.4g} cell-updates/s, {side['ms_per_step']:.3f} ms/step, "
+            f"frac {side['roofline']['frac']}")
+    second = {}
+    if not args.no_second:
+        name2 = "bell256" if args.workload == "hemi512" else "hemi512"
+        cfg2 = W.get(name2)
+        for p in (args.prec, other):
+            r = run_gpu(cfg2, p, args.steps, args.warmup, args.tile)
+            second[p] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "roofline": r["roofline"]}
+            log(f"bench: {name2} {p} {r['value']:.4g} cell-updates/s, frac {r['roofline']['frac']}")
+        second = {"workload": WORKLOADS[name2], **second}
     amr = {}
     if not args.no_amr:
-        from paper_1509_02572_amd import workloads as W
         lay = W.amr_hemisphere(2000)
         for p in (args.prec, other):
             amr[p] = run_amr(p, args.warmup, lay)
@@ -280,14 +364,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.prec == "f32" else "f64",
         "data": "synthetic",
-        "config": {"workload": "bell256: 256x256x128 cells, dx=dy=100 m, dz=50 m, bell hill h0=400 m "
-                               "a=2 km, N=0.01 1/s, U=10 m/s, theta' noise N(0,0.01 K) seed 0, dt=0.05 s",
+        "config": {"workload": WORKLOADS[args.workload],
                    "precision": "FP32 perturbation (FP64 base state and sums)" if args.prec == "f32" else "FP64",
                    "cells": cfg.nx * cfg.ny * cfg.nz, "stages_per_step": 3},
         "roofline": head["roofline"],
-        other: {"value": side["value"], "ms_per_step": side["ms_per_step"], "roofline": side["roofline"]},
-        "speedup_vs_fp64": head["value"] / f64["value"],
     }
+    if side is not None:
+        f64 = head if args.prec == "f64" else side
+        out[other] = {"value": side["value"], "ms_per_step": side["ms_per_step"], "roofline": side["roofline"]}
+        out["speedup_vs_fp64"] = head["value"] / f64["value"]
+    if second:
+        out["second_workload"] = second
     if amr:
         out["refined"] = {"workload": "hemisphere R=1 km on 128x128x64 level-0 cells at 200 m (25.6x25.6x12.8 km), "
                                       "levels 1 (100 m) and 2 (50 m), 8^3-cell bricks, 6 ghost cells, dt(0)=0.2 s, "
@@ -299,7 +386,7 @@ def main():
                            **ens}
     if not args.no_cpu:
         log("bench: timing the CPU oracle baseline")
-        out["cpu_baseline"] = run_cpu_baseline(cfg)
+        out["cpu_baseline"] = run_cpu_baseline(cfg, args.cpu_sweep)
     print(json.dumps(out), flush=True)
 
 

@@ -255,16 +255,15 @@ static int needs_merge(const or_grid *g, const or_geom *G, size_t c, int k)
     return v > 0.0 && (hc > zc || v < 0.5);
 }
 
-/* merge direction from the column gradients, tested in the order of Fig. 6 */
+/* merge direction from the column gradients (Sec. 2.3, Fig. 5): upward where neither gradient
+ * exceeds 1 in magnitude; otherwise along the steeper axis (x when both are equally steep), to the
+ * neighbour on the lower side of the slope */
 int or_merge_direction(double gx, double gy)
 {
     double ax = fabs(gx), ay = fabs(gy);
     if (ax <= 1.0 && ay <= 1.0) return OR_ZP;
-    if (gx > 1.0 && ax >= ay) return OR_XM;
-    if (gx < -1.0 && ax >= ay) return OR_XP;
-    if (gy > 1.0 && ax < ay) return OR_YM;
-    if (gy < -1.0 && ax < ay) return OR_YP;
-    return OR_NONE; /* unreachable: the five cases cover the plane */
+    if (ax >= ay) return gx > 0.0 ? OR_XM : OR_XP;
+    return gy > 0.0 ? OR_YM : OR_YP;
 }
 
 /* the cell a cut cell merges into; returns 0 if it lies outside the domain */
@@ -833,14 +832,12 @@ void or_tendency_points(const or_grid *g, const or_phys *ph, const or_geom *G, c
 /* Explicit three-stage Runge-Kutta (Wicker & Skamarock 2002): q_out = q_n + cdt * L(q_s),       */
 /* applied to group masters and predicted points, followed by the diagnostic pass.              */
 /* ------------------------------------------------------------------------------------------ */
-/* the update alone (group masters and predicted points), without the diagnostic pass */
-void or_rk_update(const or_grid *g, const or_phys *ph, const or_geom *G, const double *rhob,
-                  const double *rthb, const double *pb, const or_state *qn, const or_state *qs,
-                  or_state *qout, double cdt)
+/* the update alone (group masters and predicted points) with the group member lists given */
+static void rk_update_groups(const or_grid *g, const or_phys *ph, const or_geom *G, const double *rhob,
+                             const double *rthb, const double *pb, const or_state *qn, const or_state *qs,
+                             or_state *qout, double cdt, const int64_t *head, const int64_t *next)
 {
     size_t n = (size_t)g->nx * g->ny * g->nz;
-    int64_t *head = (int64_t *)malloc(sizeof(int64_t) * n), *next = (int64_t *)malloc(sizeof(int64_t) * n);
-    build_groups(g, G, head, next);
     or_ctx x = {g, ph, G, rhob, rthb, pb, qs};
 #pragma omp parallel for schedule(static)
     for (long long cc = 0; cc < (long long)n; ++cc) {
@@ -857,6 +854,17 @@ void or_rk_update(const or_grid *g, const or_phys *ph, const or_geom *G, const d
             qout->mw[cc] = qn->mw[cc] + cdt * d[4];
         }
     }
+}
+
+/* the update alone (group masters and predicted points), without the diagnostic pass */
+void or_rk_update(const or_grid *g, const or_phys *ph, const or_geom *G, const double *rhob,
+                  const double *rthb, const double *pb, const or_state *qn, const or_state *qs,
+                  or_state *qout, double cdt)
+{
+    size_t n = (size_t)g->nx * g->ny * g->nz;
+    int64_t *head = (int64_t *)malloc(sizeof(int64_t) * n), *next = (int64_t *)malloc(sizeof(int64_t) * n);
+    build_groups(g, G, head, next);
+    rk_update_groups(g, ph, G, rhob, rthb, pb, qn, qs, qout, cdt, head, next);
     free(head); free(next);
 }
 
@@ -916,22 +924,29 @@ void or_reduce(const or_grid *g, const or_phys *ph, const or_geom *G, const doub
     out[0] = mp; out[1] = tp; out[2] = mt; out[3] = e;
 }
 
-/* nsteps full WS-RK3 steps; q is advanced in place using two scratch states */
+/* nsteps full WS-RK3 steps; q is advanced in place using two scratch states (the group member
+ * lists depend only on the geometry and are built once) */
 void or_run(const or_grid *g, const or_phys *ph, const or_geom *G, const double *rhob,
             const double *rthb, const double *pb, or_state *q, or_state *s1, or_state *s2,
             double dt, int nsteps, int64_t *counts)
 {
+    size_t n = (size_t)g->nx * g->ny * g->nz;
+    int64_t *head = (int64_t *)malloc(sizeof(int64_t) * n), *next = (int64_t *)malloc(sizeof(int64_t) * n);
+    build_groups(g, G, head, next);
     for (int st = 0; st < nsteps; ++st) {
-        or_rk_stage(g, ph, G, rhob, rthb, pb, q, q, s1, dt / 3.0, counts);
-        or_rk_stage(g, ph, G, rhob, rthb, pb, q, s1, s2, dt / 2.0, counts);
-        or_rk_stage(g, ph, G, rhob, rthb, pb, q, s2, s1, dt, counts);
-        size_t n = (size_t)g->nx * g->ny * g->nz;
+        rk_update_groups(g, ph, G, rhob, rthb, pb, q, q, s1, dt / 3.0, head, next);
+        or_diagnose(g, ph, G, rhob, rthb, pb, s1, counts);
+        rk_update_groups(g, ph, G, rhob, rthb, pb, q, s1, s2, dt / 2.0, head, next);
+        or_diagnose(g, ph, G, rhob, rthb, pb, s2, counts);
+        rk_update_groups(g, ph, G, rhob, rthb, pb, q, s2, s1, dt, head, next);
+        or_diagnose(g, ph, G, rhob, rthb, pb, s1, counts);
         memcpy(q->rho, s1->rho, n * sizeof(double));
         memcpy(q->rth, s1->rth, n * sizeof(double));
         memcpy(q->mu, s1->mu, n * sizeof(double));
         memcpy(q->mv, s1->mv, n * sizeof(double));
         memcpy(q->mw, s1->mw, n * sizeof(double));
     }
+    free(head); free(next);
 }
 
 /* thread count for the OpenMP loops (results are independent of it: every output element is

@@ -219,9 +219,9 @@ class Oracle:
         lib().or_tendency_points(*self._args(), C.byref(cq), _p(pts, _I64), len(pts), _p(out))
         return out
 
-    def rk_stage(self, qn: State, qs: State, cdt: float) -> State:
+    def rk_stage(self, qn: State, qs: State, cdt: float, out: Optional[State] = None) -> State:
         self._ready()
-        out = State(self.shape)
+        out = State(self.shape) if out is None else out
         a, b, c = qn.c(), qs.c(), out.c()
         lib().or_rk_stage(*self._args(), C.byref(a), C.byref(b), C.byref(c), cdt, _p(self.counts, _I64))
         return out

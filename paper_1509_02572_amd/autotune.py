@@ -1,20 +1,23 @@
-"""Autotuner of the update kernel's tile shape.
+"""Autotuner of the update kernel's tile shapes: single grids, ensemble batches and refined grids.
 
-For a domain and precision, every tile shape the library offers (``cc_grid.tile`` ids) is timed on
-the domain's own state with HIP events around the update kernel, and the fastest is kept.  Results
-are cached in a JSON file keyed by precision and grid size, so later runs reuse them.  Results of
-the stage do not depend on the tile shape (the kernel's arithmetic is the same for every shape).
+For a single grid every tile shape the library offers (``cc_grid.tile`` ids) is timed on the
+domain's own state with HIP events around the update launches, and the fastest is kept.  Batches
+(ensembles of independent domains) and refined grids time the batch tile shapes on their own blocks.
+Results are cached in a JSON file keyed by what was tuned (kind, precision, sizes) and by a hash of
+the kernel sources, so a cached choice is reused only for the kernels it was measured on.  The
+stage's results do not depend on the tile shape (the arithmetic is the same for every shape).
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
-from typing import Dict, Optional
-
-import torch
+from typing import Dict, Iterable, Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning_cache.json")
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("cc_kernels.hpp", "cc_stage.hip", "cc_batch.hip")]
+
 # id -> (TX, TY, TZ) of the update kernel's tile; ids 9-12 repeat a shape with registers capped
 # for 6 or 8 waves per SIMD; ids 13-19 give every thread two or four points spaced evenly in k (13-15, 17, 18: two;
 # 16, 19: four); id 20 is the two-pass update (p' and lattice velocities computed once into the
@@ -31,42 +34,89 @@ TILE_TEMPLATE = {0: (8, 8, 8, 1, 1), 1: (4, 4, 16, 1, 1), 2: (8, 4, 16, 1, 1), 3
                  8: (2, 2, 64, 1, 1), 9: (8, 8, 8, 6, 1), 10: (8, 8, 8, 8, 1), 11: (4, 4, 16, 8, 1),
                  12: (4, 8, 16, 6, 1), 13: (8, 8, 8, 4, 2), 14: (8, 8, 8, 6, 2), 15: (8, 8, 4, 6, 2),
                  16: (8, 8, 2, 8, 4), 17: (4, 4, 8, 8, 2), 18: (8, 8, 4, 4, 2), 19: (8, 8, 4, 6, 4)}
+# tile ids a batch (ensemble or refined grid) accepts
+BATCH_TILES = (0, 1, 6, 7, 8, 9, 11, 12)
+BATCH_CANDIDATES = (0, 1, 6, 7, 9, 11, 12)
+REFINED_CANDIDATES = (1, 6, 9, 11)
 
 
 def kernel_names(tile: int, prec: str, small: bool = False):
-    """rocprofv3 names (without arguments) of the two launches of one update stage on a grid with a
-    known band height: the points at or above their column's band top over the whole grid (the
-    kernel without the band paths), then the points below it in one-wave tiles (8x8x1; 4x4x4 on a
-    grid with ``small`` = fewer than 8 columns in x or y)."""
+    """rocprofv3 names (without arguments) of the launches of one update stage on a grid with a
+    known band height.  Tiled shapes: the points at or above their column's band top over the whole
+    grid (the kernel without the band paths), then the points below it in one-wave tiles (8x8x1;
+    4x4x4 on a grid with ``small`` = fewer than 8 columns in x or y).  The two-pass form (id 20):
+    the prepare pass and the point pass."""
     t = "double" if prec == "f64" else "float"
+    if tile == 20:
+        return (f"cc::k_prepare<{t}>", f"cc::k_stage_points<{t}, 0>")
     tx, ty, tz, w, kp = TILE_TEMPLATE[tile]
     band = "4, 4, 4" if small else "8, 8, 1"
     return (f"cc::k_stage_tiled<{t}, {tx}, {ty}, {tz}, 0, {w}, {kp}, true, 1>",
             f"cc::k_stage_tiled<{t}, {band}, 0, 1, 1, false, 2>")
 
 
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _prec(p) -> str:
+    if isinstance(p, str):
+        return p
+    return "f64" if p == 0 else "f32"
+
+
 def key(dom) -> str:
-    prec = "f64" if dom.prec == 0 else "f32"
-    return f"{prec}:{dom.cfg.nx}x{dom.cfg.ny}x{dom.cfg.nz}"
+    return f"grid:{_prec(dom.prec)}:{dom.cfg.nx}x{dom.cfg.ny}x{dom.cfg.nz}"
 
 
 def load_cache(path: str = CACHE) -> Dict[str, dict]:
-    if os.path.exists(path):
+    if path and os.path.exists(path):
         with open(path) as f:
             return json.load(f)
     return {}
 
 
+def _lookup(k: str, path: Optional[str]) -> Optional[dict]:
+    ent = load_cache(path).get(k) if path else None
+    if ent and ent.get("source_hash") == source_hash():
+        return ent
+    return None
+
+
+def _store(k: str, best: int, times: Dict[int, float], path: Optional[str]):
+    if not path:
+        return
+    cache = load_cache(path)
+    cache[k] = {"tile": int(best), "ms": {str(t): round(v, 5) for t, v in times.items()},
+                "source_hash": source_hash()}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
 def cached_tile(dom, path: str = CACHE) -> Optional[int]:
-    ent = load_cache(path).get(key(dom))
+    ent = _lookup(key(dom), path)
     return int(ent["tile"]) if ent else None
 
 
-def tune(dom, q, reps: int = 5, path: Optional[str] = CACHE, dt: float = 0.05) -> dict:
-    """Time the update kernel (stage-2 form: q_n and q_s distinct) for every tile id on ``dom``.
+def tune(dom, q, reps: int = 5, path: Optional[str] = CACHE, dt: float = 0.05, force: bool = False,
+         candidates: Optional[Iterable[int]] = None) -> dict:
+    """Tile id of the single-grid update on ``dom`` (stage-2 form: q_n and q_s distinct).
 
-    ``q`` is a valid state of ``dom``.  Returns {"tile": best id, "ms": {id: ms per launch}} and,
-    when ``path`` is given, stores it in the cache.  The domain's tile is left at the best id."""
+    A cached choice for the same grid size, precision and kernel sources is reused unless ``force``;
+    otherwise every candidate is timed (median of ``reps`` launches after one warm-up) and the
+    result cached.  ``q`` is a valid state of ``dom``.  The domain's tile is set to the choice.
+    Returns {"tile", "ms": {id: ms}, "source": "cache" | "timed"}."""
+    import torch
+    ent = None if force else _lookup(key(dom), path)
+    if ent:
+        dom.grid.tile = int(ent["tile"])
+        return {"tile": int(ent["tile"]), "ms": {int(k): v for k, v in ent["ms"].items()}, "source": "cache"}
     a, b = dom.new_state(), dom.new_state()
     for f in q.t:
         a.t[f].copy_(q.t[f])
@@ -74,7 +124,7 @@ def tune(dom, q, reps: int = 5, path: Optional[str] = CACHE, dt: float = 0.05) -
     stream = torch.cuda.current_stream()
     out = dom.new_state()
     times = {}
-    for tid in TILE_IDS:
+    for tid in (candidates or TILE_IDS):
         dom.grid.tile = tid
         dom.rk_update(a, b, out, dt / 2.0)  # warm-up
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
@@ -86,12 +136,62 @@ def tune(dom, q, reps: int = 5, path: Optional[str] = CACHE, dt: float = 0.05) -
         times[tid] = sorted(e0.elapsed_time(e1) for e0, e1 in ev)[reps // 2]
     best = min(times, key=times.get)
     dom.grid.tile = best
-    res = {"tile": best, "shape": TILE_IDS[best], "ms": times}
-    if path:
-        cache = load_cache(path)
-        cache[key(dom)] = {"tile": best, "shape": list(TILE_IDS[best]),
-                           "ms": {str(k): round(v, 5) for k, v in times.items()}}
-        with open(path, "w") as f:
-            json.dump(cache, f, indent=1, sort_keys=True)
-    return res
+    _store(key(dom), best, times, path)
+    return {"tile": best, "ms": times, "source": "timed"}
 
+
+def tune_batch(doms, states, dt: float, prec: str, path: Optional[str] = CACHE, force: bool = False,
+               candidates: Iterable[int] = BATCH_CANDIDATES) -> dict:
+    """Tile id of a batch of independent domains: each candidate steps the batch eagerly (one step,
+    then two timed steps with HIP events); the states are advanced by the timing runs."""
+    import torch
+    from . import cutcell as CC
+    sizes = hashlib.sha256(json.dumps([[d.cfg.nx, d.cfg.ny, d.cfg.nz] for d in doms]).encode()).hexdigest()[:12]
+    k = f"batch:{_prec(prec)}:{len(doms)}:{sizes}"
+    ent = None if force else _lookup(k, path)
+    if ent:
+        return {"tile": int(ent["tile"]), "ms": {int(t): v for t, v in ent["ms"].items()}, "source": "cache"}
+    stream = torch.cuda.current_stream()
+    times = {}
+    for tile in candidates:
+        b = CC.Batch(doms, states, tile=tile)
+        b.step(dt, 1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.step(dt, 2)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times[tile] = e0.elapsed_time(e1)
+        b.close()
+    best = min(times, key=times.get)
+    _store(k, best, times, path)
+    return {"tile": best, "ms": times, "source": "timed"}
+
+
+def tune_refined(layout, prec: str, path: Optional[str] = CACHE, force: bool = False,
+                 candidates: Iterable[int] = REFINED_CANDIDATES) -> dict:
+    """Tile id of a refined grid: each candidate builds the hierarchy and times one eager level-0
+    step (after one untimed step) with HIP events."""
+    import torch
+    from . import cutcell as CC
+    desc = json.dumps([[int(b.level), [int(v) for v in b.org], [int(v) for v in b.size]] for b in layout.blocks])
+    k = f"refined:{_prec(prec)}:{len(layout.blocks)}:{hashlib.sha256(desc.encode()).hexdigest()[:12]}"
+    ent = None if force else _lookup(k, path)
+    if ent:
+        return {"tile": int(ent["tile"]), "ms": {int(t): v for t, v in ent["ms"].items()}, "source": "cache"}
+    stream = torch.cuda.current_stream()
+    times = {}
+    for tile in candidates:
+        h = CC.Hierarchy(layout, prec, "cuda:0", tile=tile)
+        h.step(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        h.step(1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times[tile] = e0.elapsed_time(e1)
+        h.close()
+        del h
+    best = min(times, key=times.get)
+    _store(k, best, times, path)
+    return {"tile": best, "ms": times, "source": "timed"}

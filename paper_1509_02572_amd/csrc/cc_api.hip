@@ -47,6 +47,12 @@ bool check_grid(const cc_grid *g)
         set_error("nsub=%d must be a power of two in [1, 1024]", g->nsub);
         return false;
     }
+    // the kernels form column and cell indices with 24-bit multiplies (__umul24): the column count
+    // nx*ny and the padded stride must stay below 2^24
+    if ((int64_t)g->nx * g->ny >= ((int64_t)1 << 24) || g->nzs >= (1 << 24)) {
+        set_error("grid %dx%d columns (stride %d) exceeds the 2^24 column and stride limit", g->nx, g->ny, g->nzs);
+        return false;
+    }
     if ((int64_t)g->nx * g->ny * g->nzs >= ((int64_t)1 << 31)) {
         set_error("grid of %lld slots exceeds 32-bit cell indices", (long long)g->nx * g->ny * g->nzs);
         return false;

@@ -205,7 +205,7 @@ __global__ void k_normals(Dims d, const double *__restrict__ col, double *__rest
 }
 
 // ------------------------------------------------------------------------------------------------
-// Cell merging (Sec. 2.3, Fig. 6)
+// Cell merging (Sec. 2.3, Figs. 5 and 6)
 // ------------------------------------------------------------------------------------------------
 __device__ __forceinline__ bool needs_merge(double v, double hc, int k, double dz)
 {
@@ -213,15 +213,15 @@ __device__ __forceinline__ bool needs_merge(double v, double hc, int k, double d
     return v > 0.0 && (hc > zc || v < 0.5);
 }
 
+// Sec. 2.3, Fig. 5: where both column gradients are at most 1 in magnitude the cell merges upward;
+// otherwise it merges along the axis of the steeper gradient (x when the two are equal), towards
+// the lower terrain (a positive gradient means lower ground on the minus side)
 __device__ __forceinline__ int merge_direction(double gx, double gy)
 {
-    double ax = fabs(gx), ay = fabs(gy);
+    const double ax = fabs(gx), ay = fabs(gy);
     if (ax <= 1.0 && ay <= 1.0) return CC_DIR_ZP;
-    if (gx > 1.0 && ax >= ay) return CC_DIR_XM;
-    if (gx < -1.0 && ax >= ay) return CC_DIR_XP;
-    if (gy > 1.0 && ax < ay) return CC_DIR_YM;
-    if (gy < -1.0 && ax < ay) return CC_DIR_YP;
-    return CC_DIR_NONE;
+    if (ax >= ay) return gx > 0.0 ? CC_DIR_XM : CC_DIR_XP;
+    return gy > 0.0 ? CC_DIR_YM : CC_DIR_YP;
 }
 
 // target cell of direction dir; false if it lies above the domain

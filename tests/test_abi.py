@@ -52,6 +52,10 @@ def test_version_and_argument_errors_without_device(lib):
     assert b"null" in L.cutcell_last_error()
     g = CC.cc_grid(8, 8, 8, 4, 100.0, 100.0, 50.0, 16, 0)  # nzs < nz
     assert L.cutcell_merge_map(ctypes.byref(g), ctypes.byref(geom), None, None) == CC.CC_EINVAL
+    # 4200 x 4200 columns exceed the 24-bit column index of the kernels (below 2^31 slots)
+    g = CC.cc_grid(4200, 4200, 16, 16, 100.0, 100.0, 50.0, 16, 0)
+    assert L.cutcell_geometry(ctypes.byref(g), ctypes.byref(geom), None, None) == CC.CC_EINVAL
+    assert b"2^24" in L.cutcell_last_error()
 
 
 def _fake_blocks(CC, layout, bad_overlap=False):
