@@ -107,16 +107,45 @@ __global__ void k_init_momentum_full(Dims d, Geo G, Phy P, double u0, double v0,
 }
 
 // ------------------------------------------------------------------------------------------------
-// Conservation sums: fixed grid, fixed per-thread order, fixed tree -> bitwise reproducible.
+// Conservation sums: fixed grid, fixed per-thread order, fixed tree -> bitwise reproducible.  Each
+// thread sums its grid-stride cells in order; a wavefront combines its 64 lanes with a butterfly of
+// cross-lane shuffles; the block's waves are then added in wave order, and the final pass adds the
+// block partials the same way.  No float atomics.
 // ------------------------------------------------------------------------------------------------
-constexpr int RED_BLOCKS = 1024, RED_THREADS = 256;
+constexpr int RED_BLOCKS = 1024, RED_THREADS = 256, RED_WAVES = RED_THREADS / 64;
+
+// sum of v over the 64 lanes of the wavefront (every lane receives the same bits: the butterfly
+// adds the same pairs in the same order on every lane)
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// the four sums of a block, in wave order, into out[0..3] (thread 0 writes)
+__device__ __forceinline__ void block_sum4(double acc[4], double *out)
+{
+    __shared__ double sh[4][RED_WAVES];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const double w = wave_sum(acc[a]);
+        if (lane == 0) sh[a][wave] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int w = 0; w < RED_WAVES; ++w) t += sh[threadIdx.x][w];
+        out[threadIdx.x] = t;
+    }
+}
 
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS) k_reduce_partial(Dims d, Geo G, Phy P, SIn<T> q,
                                                                 double *part)
 {
     using R = typename Compute<T>::R;
-    __shared__ double sh[4][RED_THREADS];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int64_t n = (int64_t)d.nx * d.ny * d.nz;
     for (int64_t t = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; t < n;
@@ -149,30 +178,15 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_partial(Dims d, Geo G, P
             acc[3] += P.dV * 0.5 * rc * (uu * uu + vv * vv + ww * ww);
         }
     }
-    for (int a = 0; a < 4; ++a) sh[a][threadIdx.x] = acc[a];
-    __syncthreads();
-    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int a = 0; a < 4; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 4) part[(int64_t)blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+    block_sum4(acc, part + (int64_t)blockIdx.x * 4);
 }
 
 __global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double *part, double *out)
 {
-    __shared__ double sh[4][RED_THREADS];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < RED_BLOCKS; b += RED_THREADS)
         for (int a = 0; a < 4; ++a) acc[a] += part[b * 4 + a];
-    for (int a = 0; a < 4; ++a) sh[a][threadIdx.x] = acc[a];
-    __syncthreads();
-    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int a = 0; a < 4; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
+    block_sum4(acc, out);
 }
 
 // ------------------------------------------------------------------------------------------------
