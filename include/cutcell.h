@@ -216,6 +216,18 @@ cc_status cutcell_reduce(const cc_grid *grid, const cc_phys *phys, const cc_geom
                          const double *base, cc_prec prec, const cc_state *q, void *workspace,
                          double *out, cc_stream_t stream);
 
+/* cutcell_reduce without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The block
+ * partial sums live in a static device array of the library (4 x 1024 doubles = 32 KiB, one copy
+ * per device, held until the process ends; its address is looked up once per device on the first
+ * call with that device current).  The call itself allocates and frees nothing.  Every call on a
+ * device shares that device's array: calls that overlap on one device (on different streams, or
+ * from different threads) race and must be ordered by the caller.  Same arguments, results and
+ * errors as cutcell_reduce; CC_EDEVICE when the array's address cannot be obtained. */
+cc_status cutcell_reduce_noalloc(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                                 const double *base, cc_prec prec, const cc_state *q, double *out,
+                                 cc_stream_t stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Batched blocks.  A block is a uniform grid with its own geometry, base state and three state
  * buffers.  A batch steps all its blocks with one update launch and one diagnostic launch per

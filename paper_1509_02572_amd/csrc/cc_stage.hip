@@ -189,6 +189,38 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double *part
     block_sum4(acc, out);
 }
 
+// Scratch of the allocation-free reduction: the block partials, one copy per device (file-scope
+// device array; host code uses the address hipGetSymbolAddress returns for the current device,
+// never the array's name).
+static __device__ __align__(256) double scratch[4 * RED_BLOCKS];
+constexpr size_t SCRATCH_BYTES = sizeof(double) * 4 * RED_BLOCKS;
+constexpr int MAX_SCRATCH_DEVICES = 64;
+static void *g_scratch[MAX_SCRATCH_DEVICES];
+static std::mutex g_scratch_mu;
+
+// device address of `scratch` on the current device, looked up once per device; null on failure
+// (the error text is set)
+static double *scratch_of_current_device()
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= MAX_SCRATCH_DEVICES) {
+        set_error("cutcell_reduce_noalloc: no usable current device (%s)", hipGetErrorString(e));
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error("cutcell_reduce_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch[dev] = ptr;
+    }
+    return (double *)g_scratch[dev];
+}
+
 // ------------------------------------------------------------------------------------------------
 // host side
 // ------------------------------------------------------------------------------------------------
@@ -441,6 +473,31 @@ extern "C" cc_status cutcell_reduce(const cc_grid *grid, const cc_phys *phys, co
                            sin_of<float>(q), part);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, part, out);
     return launch_status("cutcell_reduce");
+}
+
+extern "C" cc_status cutcell_reduce_noalloc(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                                            const double *base, cc_prec prec, const cc_state *q, double *out,
+                                            cc_stream_t stream)
+{
+    Dims d; Geo G; Phy P;
+    if (!make_views("cutcell_reduce_noalloc", grid, phys, geom, base, prec, d, G, P)) return CC_EINVAL;
+    if (!state_ok("cutcell_reduce_noalloc", q)) return CC_EINVAL;
+    CC_REQUIRE(out, "cutcell_reduce_noalloc: null output");
+    CC_REQUIRE(cutcell_reduce_workspace(grid) <= SCRATCH_BYTES,
+               "cutcell_reduce_noalloc: %zu bytes of partial sums exceed the %zu-byte static scratch",
+               cutcell_reduce_workspace(grid), SCRATCH_BYTES);
+    double *part = scratch_of_current_device();
+    if (!part) return CC_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    // every partial is written before the final pass reads it: nothing to clear
+    if (prec == CC_F64)
+        hipLaunchKernelGGL(k_reduce_partial<double>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, d, G, P,
+                           sin_of<double>(q), part);
+    else
+        hipLaunchKernelGGL(k_reduce_partial<float>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, d, G, P,
+                           sin_of<float>(q), part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, part, out);
+    return launch_status("cutcell_reduce_noalloc");
 }
 
 extern "C" size_t cutcell_stage_workspace_bytes(const cc_grid *grid, cc_prec prec)

@@ -79,6 +79,7 @@ def lib():
         L.cutcell_reduce_workspace.argtypes = [G]
         L.cutcell_reduce_workspace.restype = C.c_size_t
         L.cutcell_reduce.argtypes = [G, P, GM, vp, C.c_int, S, vp, vp, vp]
+        L.cutcell_reduce_noalloc.argtypes = [G, P, GM, vp, C.c_int, S, vp, vp]
         L.cutcell_check_status.argtypes = [vp, vp, vp]
         L.amr_batch_workspace_bytes.argtypes = [C.c_int32, C.c_int]
         L.amr_batch_workspace_bytes.restype = C.c_size_t
@@ -98,6 +99,7 @@ def lib():
         L.amr_batch_destroy.argtypes = [vp]
         for name in ("cutcell_base_state", "cutcell_geometry", "cutcell_merge_map", "cutcell_init_state",
                      "cutcell_diagnose", "cutcell_tendency", "cutcell_rk_stage", "cutcell_rk_update", "cutcell_reduce",
+                     "cutcell_reduce_noalloc",
                      "cutcell_check_status", "amr_batch_create", "amr_block_step", "amr_batch_destroy",
                      "amr_hierarchy_workspace_bytes", "amr_hierarchy_create", "amr_hierarchy_sync"):
             getattr(L, name).restype = C.c_int
@@ -181,6 +183,11 @@ def cutcell_rk_update(grid, phys, geom, base, prec, qn: cc_state, qs: cc_state, 
 def cutcell_reduce(grid, phys, geom, base, prec, q: cc_state, workspace, out, stream=None):
     _check(lib().cutcell_reduce(C.byref(grid), C.byref(phys), C.byref(geom), _ptr(base), prec,
                                 C.byref(q), _ptr(workspace), _ptr(out), _stream(stream)), "cutcell_reduce")
+
+
+def cutcell_reduce_noalloc(grid, phys, geom, base, prec, q: cc_state, out, stream=None):
+    _check(lib().cutcell_reduce_noalloc(C.byref(grid), C.byref(phys), C.byref(geom), _ptr(base), prec,
+                                        C.byref(q), _ptr(out), _stream(stream)), "cutcell_reduce_noalloc")
 
 
 def cutcell_check_status(status: torch.Tensor, stream=None) -> (int, np.ndarray):
