@@ -15,10 +15,11 @@
  * x and y are periodic.  Terrain heights H[I*ny+J] are given at the column corners.
  *
  * Pins (tests): the 18.1 and 71 degree slopes of Sec. 3.1, the merge directions of Sec. 3.1.1/3.1.2,
- * the volume closed form, face-area closure, brute force on 4^3 grids, rest stays at rest, the flat
- * terrain finite-difference reduction of Sec. 2.4, mass conservation, a face-list scatter form of
- * the flux divergence, symmetry and translation.  Items downstream of the tendency that the paper
- * leaves open (velocity diagnostics in 3-D) are "parity unpinned" beyond those properties.
+ * the volume closed form and the analytic hill volumes, face-area closure of every cut cell, brute
+ * force on 4^3 grids, the exact normal of a planar patch, the diagnostics of a uniform flow (eq. 33
+ * and the merged-face interpolation in closed form) and their mirror symmetry, rest stays at rest,
+ * the flat terrain finite-difference reduction of Sec. 2.4, mass conservation, a face-list scatter
+ * form of the flux divergence, symmetry and translation.
  */
 #include <math.h>
 #include <stdint.h>
