@@ -161,7 +161,7 @@ def run_ensemble(prec: str, warmup: int):
     from paper_1509_02572_amd import cutcell as CC
     from paper_1509_02572_amd import workloads as W
     cfgs = W.ensemble(64, 0)
-    doms = [CC.Domain(c, prec, "cuda:0") for c in cfgs]
+    doms = [CC.Domain(c, prec, "cuda:0", side_stream=False) for c in cfgs]
     states = [d.init_state() for d in doms]
     dt, nsteps = cfgs[0].dt, cfgs[0].nsteps
     stream = torch.cuda.current_stream()

@@ -6,9 +6,12 @@
  * Conventions shared by every entry point
  * ----------------------------------------
  * Memory.  Every array pointer is DEVICE memory allocated and owned by the caller; the library never
- * allocates or frees on these paths and keeps no global state apart from a thread-local last-error
- * string.  Calls are ordered on the caller's HIP stream (`stream`, a hipStream_t; NULL = the default
- * stream) and return as soon as their kernels are enqueued.
+ * allocates or frees device memory on these paths and keeps no global state apart from a
+ * thread-local last-error string (and the static scratch array of cutcell_reduce_noalloc).  Host
+ * objects it creates (stage contexts, batch handles) are created and destroyed by explicit calls.
+ * Calls are ordered on the caller's HIP stream (`stream`, a hipStream_t; NULL = the default stream)
+ * and return as soon as their kernels are enqueued; the only calls that wait for the stream are the
+ * ones documented to (cutcell_band_setup, cutcell_check_status, the batch set-up calls).
  *
  * Layout.  Cell (i,j,k), 0<=i<nx, 0<=j<ny, 0<=k<nz, spans [i dx,(i+1)dx] x [j dy,(j+1)dy] x
  * [k dz,(k+1)dz].  Every 3-D array is structure-of-arrays, k fastest, index ((i*ny + j)*nzs + k) with
@@ -60,6 +63,12 @@ typedef enum {
 
 typedef enum { CC_F64 = 0, CC_F32_PERT = 1 } cc_prec;
 
+/* Stage context: a side stream and two events on one device, created by the caller
+ * (cutcell_stage_ctx_create).  Given in cc_geom.side, the band-point launch of an update runs on the
+ * side stream, forked from and joined to the caller's stream, beside the regular-point launch.  A
+ * context serves one call at a time: grids stepped concurrently on different streams need one each. */
+typedef struct cc_stage_ctx_s *cc_stage_ctx;
+
 #define CC_NSTATUS 8
 #define CC_MAX_GROUP 32
 
@@ -72,8 +81,9 @@ typedef struct {
     int32_t nx, ny, nz, nzs; /* cells; padded k stride (nzs >= nz) */
     double dx, dy, dz;       /* spacings [m] */
     int32_t nsub;            /* sub-columns per cell edge for volumes/apertures, power of two */
-    int32_t tile;            /* tile shape of the update kernel (0 = default; 1..20 see the tuning
-                                table of the stage kernels); results do not depend on it */
+    int32_t tile;            /* tile shape of the update kernel (0 = default; 1..20 three-dimensional
+                                tiles, 21..26 streaming forms, see the tuning table of the stage
+                                kernels); results do not depend on it */
     double z0;               /* height of the grid's bottom face above the terrain datum [m]: 0 for
                                 a grid standing on the ground; > 0 for a block of a refined grid
                                 that starts higher (Sec. 2.2), whose H is then given relative to z0
@@ -104,7 +114,7 @@ typedef struct {
                                  list of band tiles cutcell_merge_map writes (the band-point launch
                                  then covers only tiles with band points) and enables the two-pass
                                  update (cc_grid.tile = 20); NULL otherwise */
-    int32_t kband;            /* host value set by cutcell_merge_map: the highest column band top.
+    int32_t kband;            /* host value set by cutcell_band_setup: the highest column band top.
                                  A column's band top is one above its highest point that is not
                                  regular (a cell that is cut, merged, or next to a closed face or a
                                  cell that is not open; a lattice point above the ground row that is
@@ -112,12 +122,14 @@ typedef struct {
                                  column's band top with a kernel without the band paths and the rest
                                  with the full kernel over k < kband.  0 or out of [1, nz]: unknown
                                  (the full kernel everywhere) */
-    int32_t nband_tiles;      /* host value set by cutcell_merge_map: number of band tiles in the list
+    int32_t nband_tiles;      /* host value set by cutcell_band_setup: number of band tiles in the list
                                  at the start of stage_ws; -1 without stage_ws (the band-point launch
                                  then covers every tile below kband).  The list lives in the
-                                 workspace given to cutcell_merge_map: another workspace needs
+                                 workspace given to cutcell_band_setup: another workspace needs
                                  another call (or nband_tiles = -1); entries that are not tiles of
                                  the grid are skipped */
+    cc_stage_ctx side;        /* optional stage context (NULL: the band points of an update run on the
+                                 caller's stream before the regular points) */
 } cc_geom;
 
 /* Five prognostic fields; element type double (CC_F64) or float (CC_F32_PERT).
@@ -154,15 +166,26 @@ cc_status cutcell_base_state(const cc_grid *grid, const cc_phys *phys, double *b
  * raised block, grid.z0 > 0, only non-finite heights count). */
 cc_status cutcell_geometry(const cc_grid *grid, cc_geom *geom, int64_t *dev_status, cc_stream_t stream);
 
-/* Cell merging (Sec. 2.3, Fig. 6): a cell with V > 0 merges when its centre is below the column's
- * centre height or V < 1/2; direction from the column gradients (vertical if |gx|,|gy| <= 1, else
- * towards lower terrain, x preferred on ties).  Chains of targets that must merge themselves are
+/* Cell merging (Sec. 2.3, Figs. 5 and 6): a cell with V > 0 merges when its centre is below the
+ * column's centre height or V < 1/2; direction from the column gradients (vertical if |gx|,|gy| <= 1,
+ * else towards lower terrain, x preferred on ties).  Chains of targets that must merge themselves are
  * followed up to 8 hops to the master.  Also classifies lattice points (predicted when all eight
  * surrounding cells are available, Sec. 2.4) and fills gnext, Vgroup and colk.  Needs V, Az.. and
  * col from cutcell_geometry.  Unmergeable cells become their own master (CC_ORPHAN) and are counted
- * into dev_status[0]. */
+ * into dev_status[0].  Enqueues only; sets geom->kband = 0 and geom->nband_tiles = -1 (band height
+ * unknown: updates run the full kernel everywhere until cutcell_band_setup is called). */
 cc_status cutcell_merge_map(const cc_grid *grid, cc_geom *geom, int64_t *dev_status, cc_stream_t stream);
-/* (cutcell_merge_map synchronises `stream` once at the end to read the band height into geom->kband.) */
+
+/* Band set-up (host query): synchronises `stream`, reads the column bands cutcell_merge_map wrote
+ * (colk) and sets geom->kband, the highest column band top; with geom->stage_ws it also writes the
+ * list of one-wave band tiles that hold band points at the start of stage_ws (copied before the call
+ * returns) and sets geom->nband_tiles.  Updates then split into the regular-point launch and the
+ * band-point launch.  Call after cutcell_merge_map, once per geometry. */
+cc_status cutcell_band_setup(const cc_grid *grid, cc_geom *geom, cc_stream_t stream);
+
+/* Stage context (see cc_stage_ctx): a non-blocking side stream and two events on the current device. */
+cc_status cutcell_stage_ctx_create(cc_stage_ctx *out);
+cc_status cutcell_stage_ctx_destroy(cc_stage_ctx ctx);
 
 /* Initial state: theta' (nullable, cell layout, double) applied at constant pressure to group
  * masters, (rho theta)' = 0, uniform inflow (u0, v0, 0) as momentum at predicted points, then one

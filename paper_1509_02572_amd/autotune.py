@@ -16,7 +16,8 @@ from typing import Dict, Iterable, Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning_cache.json")
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("cc_kernels.hpp", "cc_stage.hip", "cc_batch.hip")]
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("cc_kernels.hpp", "cc_stage.hip", "cc_stream.hip",
+                                                          "cc_batch.hip")]
 
 # id -> (TX, TY, TZ) of the update kernel's tile; ids 9-12 repeat a shape with registers capped
 # for 6 or 8 waves per SIMD; ids 13-19 give every thread two or four points spaced evenly in k (13-15, 17, 18: two;
@@ -25,7 +26,12 @@ KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("cc_kernels.hpp", "cc_
 TILE_IDS = {1: (4, 4, 16), 2: (8, 4, 16), 3: (4, 8, 16), 4: (8, 8, 8), 5: (2, 4, 32), 6: (4, 4, 32),
             7: (8, 8, 16), 8: (2, 2, 64), 9: (8, 8, 8), 10: (8, 8, 8), 11: (4, 4, 16), 12: (4, 8, 16),
             13: (8, 8, 16), 14: (8, 8, 16), 15: (8, 8, 8), 16: (8, 8, 8), 17: (4, 4, 16), 18: (8, 8, 8),
-            19: (8, 8, 16), 20: (1, 1, 1)}
+            19: (8, 8, 16), 20: (1, 1, 1),
+            21: (8, 32), 22: (8, 32), 23: (8, 16), 24: (8, 32), 25: (8, 32), 26: (8, 16)}
+# ids 21-26: streaming forms of the regular points, (TY, TZ) threads over a j-k cross-section
+# marching along x through chunks of STREAM_CHUNK planes with STREAM_NBAR barriers per plane
+STREAM_CHUNK = {21: 32, 22: 32, 23: 32, 24: 64, 25: 64, 26: 32}
+STREAM_NBAR = {21: 2, 22: 1, 23: 1, 24: 2, 25: 1, 26: 2}
 TILE_MINW = {9: 6, 10: 8, 11: 8, 12: 6, 13: 4, 14: 6, 15: 6, 16: 8, 17: 8, 18: 4, 19: 6}
 # id -> template arguments of k_stage_tiled: threads per tile (TX, TY, TZ), minimum waves, points per
 # thread along k
@@ -49,8 +55,13 @@ def kernel_names(tile: int, prec: str, small: bool = False):
     t = "double" if prec == "f64" else "float"
     if tile == 20:
         return (f"cc::k_prepare<{t}>", f"cc::k_stage_points<{t}, 0>")
-    tx, ty, tz, w, kp = TILE_TEMPLATE[tile]
     band = "4, 4, 4" if small else "8, 8, 1"
+    if tile in STREAM_CHUNK:
+        ty, tz = TILE_IDS[tile]
+        w = 3 if prec == "f32" else 1
+        return (f"cc::k_stage_stream<{t}, {ty}, {tz}, {STREAM_CHUNK[tile]}, {w}, {STREAM_NBAR[tile]}>",
+                f"cc::k_stage_tiled<{t}, {band}, 0, 1, 1, false, 2>")
+    tx, ty, tz, w, kp = TILE_TEMPLATE[tile]
     return (f"cc::k_stage_tiled<{t}, {tx}, {ty}, {tz}, 0, {w}, {kp}, true, 1>",
             f"cc::k_stage_tiled<{t}, {band}, 0, 1, 1, false, 2>")
 

@@ -461,14 +461,24 @@ extern "C" cc_status cutcell_merge_map(const cc_grid *grid, cc_geom *g, int64_t 
     hipLaunchKernelGGL(k_lattice_class, gb, tb, 0, s, d, g->H, g->cls, g->vcls);
     hipLaunchKernelGGL(k_column_bands, dim3(blocks_for(nc, 256)), tb, 0, s, d, g->V, g->Ax, g->Ay, g->Az,
                        g->cls, g->gnext, g->vcls, g->colk);
-    cc_status rc = launch_status("cutcell_merge_map");
-    if (rc != CC_OK) return rc;
+    g->kband = 0;  // unknown until cutcell_band_setup
+    g->nband_tiles = -1;
+    return launch_status("cutcell_merge_map");
+}
+
+extern "C" cc_status cutcell_band_setup(const cc_grid *grid, cc_geom *g, cc_stream_t stream)
+{
+    if (!check_grid(grid)) return CC_EINVAL;
+    CC_REQUIRE(g && g->colk, "cutcell_band_setup: null geometry or column bands");
+    Dims d = dims_of(grid);
+    hipStream_t s = (hipStream_t)stream;
+    int64_t nc = (int64_t)d.nx * d.ny;
     // band height: the highest cell band or lattice band top over all columns
     std::vector<int32_t> bands((size_t)(2 * nc));
     hipError_t e = hipMemcpyAsync(bands.data(), g->colk, sizeof(int32_t) * 2 * nc, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        set_error("cutcell_merge_map: %s", hipGetErrorString(e));
+        set_error("cutcell_band_setup: %s", hipGetErrorString(e));
         return CC_EDEVICE;
     }
     int32_t top = 1;
@@ -498,7 +508,7 @@ extern "C" cc_status cutcell_merge_map(const cc_grid *grid, cc_geom *g, int64_t 
             e = hipMemcpyAsync(g->stage_ws, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host list is freed on return
             if (e != hipSuccess) {
-                set_error("cutcell_merge_map: %s", hipGetErrorString(e));
+                set_error("cutcell_band_setup: %s", hipGetErrorString(e));
                 return CC_EDEVICE;
             }
         }

@@ -42,6 +42,7 @@ struct Geo {
     void *ws;   // optional stage workspace (band-tile list, two-pass update), may be null
     int kband;  // highest column band top: every point at k >= kband is regular (0: unknown)
     int nband;  // tiles in the band-tile list at the start of ws (-1: no list)
+    cc_stage_ctx side;  // host only: stage context of the band-point launch (may be null)
 };
 
 constexpr int EOS_TERMS = 11;  // binomial series terms of (1+x)^gamma - 1 (double; float uses 6)
@@ -1449,7 +1450,7 @@ inline bool make_views(const char *what, const cc_grid *grid, const cc_phys *phy
     if (prec != CC_F64 && prec != CC_F32_PERT) { set_error("%s: unknown precision %d", what, (int)prec); return false; }
     d = dims_of(grid);
     G = Geo{g->H, g->V, g->Ax, g->Ay, g->Az, g->nrm, g->Vgroup, g->cls, g->vcls, g->master, g->gnext, g->colk,
-            g->stage_ws, g->kband, g->stage_ws ? g->nband_tiles : -1};
+            g->stage_ws, g->kband, g->stage_ws ? g->nband_tiles : -1, g->side};
     double cv = phys->cp - phys->rd;
     P.rhob = base; P.rthb = base + d.nz; P.pb = base + 2 * d.nz; P.thb = base + 3 * d.nz;
     P.irthb = base + 4 * d.nz; P.rhobc = base + 5 * d.nz;

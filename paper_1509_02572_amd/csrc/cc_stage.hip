@@ -5,44 +5,23 @@
 #include <mutex>
 
 #include "cc_kernels.hpp"
+#include "cc_stream.hpp"
 
 namespace cc {
 
 // ------------------------------------------------------------------------------------------------
-// Side stream of a device: the band points of an update run on it beside the regular points (the
-// two launches write disjoint points and read only the inputs).  Created on first use outside
-// stream capture; fork and join go through events, so a capture of the caller's stream takes the
-// side stream's work in.  One fork/launch/join at a time per device (the events are shared).
+// Stage context: the caller's side stream for the band-point launch of an update (the two launches
+// of an update write disjoint points and read only the inputs, so they may run side by side).  Fork
+// and join go through events, so a capture of the caller's stream takes the side stream's work in.
 // ------------------------------------------------------------------------------------------------
-struct Side {
-    hipStream_t s = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
-    bool failed = false;
-};
-constexpr int MAX_DEVICES = 64;
-static Side g_side[MAX_DEVICES];
-static std::mutex g_side_mu;
+}  // namespace cc
 
-// the side stream of the current device, or null (creation failed, or the caller's stream is being
-// captured before the side stream exists): then the band launch goes on the caller's stream
-static Side *side_of(hipStream_t s)
-{
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
-    Side &x = g_side[dev];
-    if (x.s) return &x;
-    if (x.failed) return nullptr;
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
-    if (hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&x.fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&x.join, hipEventDisableTiming) != hipSuccess) {
-        x.failed = true;
-        x.s = nullptr;
-        return nullptr;
-    }
-    return &x;
-}
+struct cc_stage_ctx_s {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+namespace cc {
 
 // ------------------------------------------------------------------------------------------------
 // Initial state: theta' at constant pressure on group masters, (rho theta)' = 0, inflow (u0, v0, 0)
@@ -253,6 +232,30 @@ static void launch_band(const Dims &d, const Geo &G, const Phy &P, const cc_stat
                            G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, nbx, nby, nbz, 0, st);
 }
 
+// One update split by point: the band points (below their column's band top) in one-wave tiles of
+// the full kernel over k < kband, then the regular points by `regular` on s.  With a stage context
+// the band launch goes to its side stream, forked from s and joined back into it; otherwise it runs
+// on s first.
+template <typename T, int MODE, typename F>
+static void launch_split(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
+                         cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s, F regular)
+{
+    cc_stage_ctx x = G.side;
+    hipStream_t sb = s;
+    if (x && hipEventRecord(x->fork, s) == hipSuccess && hipStreamWaitEvent(x->side, x->fork, 0) == hipSuccess)
+        sb = x->side;
+    if (d.nx >= 8 && d.ny >= 8)
+        launch_band<T, 8, 8, 1, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, sb);
+    else if (d.nx >= 4 && d.ny >= 4)
+        launch_band<T, 4, 4, 4, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, sb);
+    else
+        launch_band<T, 2, 2, 16, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, sb);
+    regular();
+    // join: later work on s waits for the band launch (should the join fail, the host waits)
+    if (sb != s && (hipEventRecord(x->join, sb) != hipSuccess || hipStreamWaitEvent(s, x->join, 0) != hipSuccess))
+        (void)hipStreamSynchronize(sb);
+}
+
 template <typename T, int TX, int TY, int TZ, int MODE, int MINW = 1, int KP = 1>
 static void launch_tiled(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
                          cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
@@ -265,32 +268,19 @@ static void launch_tiled(const Dims &d, const Geo &G, const Phy &P, const cc_sta
                            nbz, 0, st);
         return;
     }
-    // the points below their column's band top: one-wave tiles of the full kernel over k < kband, on
-    // the side stream (forked from s)
-    std::lock_guard<std::mutex> lock(g_side_mu);
-    Side *x = side_of(s);
-    hipStream_t sb = s;
-    if (x && hipEventRecord(x->fork, s) == hipSuccess && hipStreamWaitEvent(x->s, x->fork, 0) == hipSuccess)
-        sb = x->s;
-    if (d.nx >= 8 && d.ny >= 8)
-        launch_band<T, 8, 8, 1, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, sb);
-    else if (d.nx >= 4 && d.ny >= 4)
-        launch_band<T, 4, 4, 4, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, sb);
-    else
-        launch_band<T, 2, 2, 16, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, sb);
-    // the points at or above it: the kernel without the band paths over the whole grid
-    hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, MINW, KP, true, 1>), dim3(nbx * nby * nbz),
-                       dim3(TX * TY * TZ), 0, s, d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt,
-                       final_stage, nbx, nby, nbz, 0, st);
-    // join: later work on s waits for the band launch (should the join fail, the host waits)
-    if (sb != s && (hipEventRecord(x->join, sb) != hipSuccess || hipStreamWaitEvent(s, x->join, 0) != hipSuccess))
-        (void)hipStreamSynchronize(sb);
+    // the points at or above the band top: the kernel without the band paths over the whole grid
+    launch_split<T, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s, [&] {
+        hipLaunchKernelGGL((k_stage_tiled<T, TX, TY, TZ, MODE, MINW, KP, true, 1>), dim3(nbx * nby * nbz),
+                           dim3(TX * TY * TZ), 0, s, d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt,
+                           final_stage, nbx, nby, nbz, 0, st);
+    });
 }
 
 // the tile of a grid: the requested shape if the grid holds at least one tile per direction in x
 // and y (the periodic index arithmetic wraps at most once), else 4x4x16, else 2x2x64
 static int pick_tile(int id, const Dims &d)
 {
+    if (id >= STREAM_ID_MIN && id <= STREAM_ID_MAX) return id;
     if (id <= 0 || id >= NTILES) id = 0;
     if (d.nx >= TILES[id].tx && d.ny >= TILES[id].ty) return id;
     if (d.nx >= 4 && d.ny >= 4) return 1;
@@ -321,6 +311,22 @@ static void launch_stage(const Dims &d, const Geo &G, const Phy &P, const cc_sta
                          cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s, int tile)
 {
     int id = pick_tile(tile, d);
+    if (id >= STREAM_ID_MIN && id <= STREAM_ID_MAX) {
+        // streaming form of the regular points (needs the band height; else the default tile)
+        if (MODE == 0 && G.kband >= 1 && G.kband <= d.nz) {
+            bool ok = true;
+            launch_split<T, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s, [&] {
+                ok = launch_stream<T>(id, d, G, P, qs, qn, qo, cdt, final_stage, st, s);
+                if (!ok)  // a form whose planes do not fit in LDS in this precision: the default tile
+                    hipLaunchKernelGGL((k_stage_tiled<T, 8, 8, 8, MODE, 1, 1, true, 1>),
+                                       dim3(((d.nx + 7) / 8) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8)), dim3(512), 0, s,
+                                       d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage,
+                                       (d.nx + 7) / 8, (d.ny + 7) / 8, (d.nz + 7) / 8, 0, st);
+            });
+            return;
+        }
+        id = pick_tile(0, d);
+    }
     if (id == 20) {
         if (MODE == 0 && G.ws && two_pass_ok(d)) {
             launch_two_pass<T, MODE>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
@@ -362,6 +368,32 @@ static void launch_stage(const Dims &d, const Geo &G, const Phy &P, const cc_sta
 }  // namespace cc
 
 using namespace cc;
+
+extern "C" cc_status cutcell_stage_ctx_create(cc_stage_ctx *out)
+{
+    CC_REQUIRE(out, "cutcell_stage_ctx_create: null output");
+    cc_stage_ctx x = new cc_stage_ctx_s();
+    hipError_t e = hipStreamCreateWithFlags(&x->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&x->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&x->join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        set_error("cutcell_stage_ctx_create: %s", hipGetErrorString(e));
+        cutcell_stage_ctx_destroy(x);
+        return CC_EDEVICE;
+    }
+    *out = x;
+    return CC_OK;
+}
+
+extern "C" cc_status cutcell_stage_ctx_destroy(cc_stage_ctx x)
+{
+    if (!x) return CC_OK;
+    if (x->join) (void)hipEventDestroy(x->join);
+    if (x->fork) (void)hipEventDestroy(x->fork);
+    if (x->side) (void)hipStreamDestroy(x->side);
+    delete x;
+    return CC_OK;
+}
 
 extern "C" cc_status cutcell_init_state(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
                                         const double *base, cc_prec prec, const double *noise,

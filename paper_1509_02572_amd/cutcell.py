@@ -39,7 +39,7 @@ class cc_phys(C.Structure):
 class cc_geom(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("H", "V", "Ax", "Ay", "Az", "col", "nrm", "cls", "dir",
                                            "vcls", "master", "gnext", "Vgroup", "colk", "stage_ws")] + \
-               [("kband", C.c_int32), ("nband_tiles", C.c_int32)]
+               [("kband", C.c_int32), ("nband_tiles", C.c_int32), ("side", C.c_void_p)]
 
 
 class cc_state(C.Structure):
@@ -69,6 +69,9 @@ def lib():
         L.cutcell_base_state.argtypes = [G, P, vp, vp]
         L.cutcell_geometry.argtypes = [G, GM, i64p, vp]
         L.cutcell_merge_map.argtypes = [G, GM, i64p, vp]
+        L.cutcell_band_setup.argtypes = [G, GM, vp]
+        L.cutcell_stage_ctx_create.argtypes = [C.POINTER(C.c_void_p)]
+        L.cutcell_stage_ctx_destroy.argtypes = [vp]
         L.cutcell_init_state.argtypes = [G, P, GM, vp, C.c_int, vp, S, i64p, vp]
         L.cutcell_diagnose.argtypes = [G, P, GM, vp, C.c_int, S, i64p, vp]
         L.cutcell_tendency.argtypes = [G, P, GM, vp, C.c_int, S, S, vp]
@@ -99,7 +102,8 @@ def lib():
         L.amr_batch_destroy.argtypes = [vp]
         for name in ("cutcell_base_state", "cutcell_geometry", "cutcell_merge_map", "cutcell_init_state",
                      "cutcell_diagnose", "cutcell_tendency", "cutcell_rk_stage", "cutcell_rk_update", "cutcell_reduce",
-                     "cutcell_reduce_noalloc",
+                     "cutcell_reduce_noalloc", "cutcell_band_setup", "cutcell_stage_ctx_create",
+                     "cutcell_stage_ctx_destroy",
                      "cutcell_check_status", "amr_batch_create", "amr_block_step", "amr_batch_destroy",
                      "amr_hierarchy_workspace_bytes", "amr_hierarchy_create", "amr_hierarchy_sync"):
             getattr(L, name).restype = C.c_int
@@ -148,6 +152,20 @@ def cutcell_geometry(grid: cc_grid, geom: cc_geom, status: torch.Tensor, stream=
 def cutcell_merge_map(grid: cc_grid, geom: cc_geom, status: torch.Tensor, stream=None):
     _check(lib().cutcell_merge_map(C.byref(grid), C.byref(geom), _ptr(status), _stream(stream)),
            "cutcell_merge_map")
+
+
+def cutcell_band_setup(grid: cc_grid, geom: cc_geom, stream=None):
+    _check(lib().cutcell_band_setup(C.byref(grid), C.byref(geom), _stream(stream)), "cutcell_band_setup")
+
+
+def cutcell_stage_ctx_create() -> C.c_void_p:
+    out = C.c_void_p()
+    _check(lib().cutcell_stage_ctx_create(C.byref(out)), "cutcell_stage_ctx_create")
+    return out
+
+
+def cutcell_stage_ctx_destroy(ctx):
+    _check(lib().cutcell_stage_ctx_destroy(ctx), "cutcell_stage_ctx_destroy")
 
 
 def cutcell_init_state(grid, phys, geom, base, prec, noise, q: cc_state, status, stream=None):
@@ -276,10 +294,12 @@ class State:
 class Domain:
     """Grid, geometry, merge map and base state of one configuration on ``device``.
 
-    ``prec`` is ``"f64"`` (paper variables in double) or ``"f32"`` (float perturbation form)."""
+    ``prec`` is ``"f64"`` (paper variables in double) or ``"f32"`` (float perturbation form).
+    ``side_stream``: give the geometry a stage context, so that the band points of an update run on
+    its side stream beside the regular points (members of a batch do not need one)."""
 
     def __init__(self, cfg, prec: str = "f64", device: str = "cuda:0", nzs: Optional[int] = None,
-                 H: Optional[np.ndarray] = None, tile: int = 0, stage_ws: bool = True):
+                 H: Optional[np.ndarray] = None, tile: int = 0, stage_ws: bool = True, side_stream: bool = True):
         from . import workloads
         if not torch.cuda.is_available():
             raise RuntimeError("libcutcell needs a HIP device")
@@ -318,6 +338,18 @@ class Domain:
         cutcell_base_state(self.grid, self.phys, self.base)
         cutcell_geometry(self.grid, self.geom, self.status)
         cutcell_merge_map(self.grid, self.geom, self.status)
+        cutcell_band_setup(self.grid, self.geom)
+        self.ctx = None
+        if side_stream:
+            self.ctx = cutcell_stage_ctx_create()
+            self.geom.side = self.ctx
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and _lib is not None:
+            self.geom.side = None
+            cutcell_stage_ctx_destroy(ctx)
+            self.ctx = None
 
     # -- states -------------------------------------------------------------------------------
     def new_state(self) -> State:
@@ -481,7 +513,7 @@ class Hierarchy:
         blocks = []
         for b in layout.blocks:
             cfg = layout.block_config(b)
-            d = Domain(cfg, prec, device, stage_ws=False)
+            d = Domain(cfg, prec, device, stage_ws=False, side_stream=False)
             org, size, gb, gt = layout.box(b)
             ilo = (layout.ghost, layout.ghost, gb)
             ihi = (ilo[0] + b.size[0], ilo[1] + b.size[1], ilo[2] + b.size[2])

@@ -33,7 +33,7 @@ def _small_ensemble(count=5, seed=11):
 
 
 def _members(cfgs, prec):
-    doms = [CC.Domain(c, prec) for c in cfgs]
+    doms = [CC.Domain(c, prec, side_stream=False) for c in cfgs]
     states = [d.init_state(W.theta_noise(c.replace(noise_sigma=0.01, seed=7 + m)))
               for m, (d, c) in enumerate(zip(doms, cfgs))]
     return doms, states
@@ -106,7 +106,7 @@ def test_full_ensemble_members_bitwise_and_conservative(prec):
     to its single-domain run; mass of every member conserved."""
     cfgs = W.ensemble(64, 0)
     print("case ensemble64", prec, sum(c.nx * c.ny * c.nz for c in cfgs), flush=True)
-    doms = [CC.Domain(c, prec) for c in cfgs]
+    doms = [CC.Domain(c, prec, side_stream=False) for c in cfgs]
     states = [d.init_state() for d in doms]
     assert all(not d.check()[:5].any() for d in doms)
     batch = CC.Batch(doms, states)

@@ -428,3 +428,32 @@ def test_flat_terrain_has_no_band():
     assert dom.geom.kband == 1 and dom.geom.nband_tiles == 0
     colk = dom.g["colk"].cpu().numpy().reshape(3, -1)
     assert colk[0].max() == 0 and colk[1].max() == 1
+
+
+# ------------------------------------------------------------------------------------------------
+# two grids stepped at once on two streams (each with its own stage context) match serial stepping
+# ------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_two_grids_on_two_streams_match_serial(prec):
+    cfgs = [SMALL["bell_small"](), SMALL["ragged"]()]
+    print(f"case two streams {prec}", flush=True)
+    doms = [CC.Domain(c, prec, tile=21) for c in cfgs]
+    noise = [W.theta_noise(c.replace(noise_sigma=0.01, seed=8)) for c in cfgs]
+    ref = [d.run(d.init_state(n), c.dt, 4) for d, c, n in zip(doms, cfgs, noise)]
+    torch.cuda.synchronize()
+    starts = [d.init_state(n) for d, n in zip(doms, noise)]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    bufs = [(q, d.new_state(), d.new_state()) for d, q in zip(doms, starts)]
+    torch.cuda.synchronize()
+    for _ in range(4):  # interleave the two grids' stages on their own streams
+        for m in range(2):
+            with torch.cuda.stream(streams[m]):
+                a, b, c = bufs[m]
+                bufs[m] = doms[m].step(a, b, c, cfgs[m].dt)
+    torch.cuda.synchronize()
+    for m in range(2):
+        for f in ref[m].t:
+            assert torch.equal(bufs[m][0].t[f], ref[m].t[f]), (m, f)
+        assert not doms[m].check()[:5].any()
