@@ -224,6 +224,7 @@ def run_amr(prec: str, warmup: int, layout=None):
     st = h.check()
     if st[:6].any():
         raise RuntimeError(f"device status counters set: {st}")
+    tables = [CC.amr_batch_info(h.h, l) for l in range(lay.levels)]
     own = sum(lay.cells(l) * (1 << l) for l in range(lay.levels))  # own-cell updates per level-0 stage
     updates = own * 3 * nsteps
     box = sum(int(d.cfg.nx * d.cfg.ny * d.cfg.nz) for d in h.doms)
@@ -233,7 +234,7 @@ def run_amr(prec: str, warmup: int, layout=None):
     return {"value": updates / secs, "unit": "cell-updates/s", "blocks": len(lay.blocks),
             "own_cells_per_level": [lay.cells(l) for l in range(lay.levels)], "box_cells": box,
             "steps_level0": nsteps, "ms_per_level0_step": secs / nsteps * 1e3, "graph_ms": gms,
-            "setup_s": round(setup, 1), "tile": tuned["tile"], "tile_source": tuned["source"],
+            "setup_s": round(setup, 1), "tile": tuned["tile"], "tile_source": tuned["source"], "levels": tables,
             "roofline": roofline(byts, gms, scope="whole graph (own cells; ghost updates, refills, flux "
                                                   "matching and diagnostics included in the time)",
                                  algorithmic_bytes=int(byts))}
@@ -302,6 +303,8 @@ def main():
     ap.add_argument("--no-second", action="store_true", help="skip the second single-grid workload")
     ap.add_argument("--no-other-prec", action="store_true", help="time the chosen precision only")
     ap.add_argument("--tile", type=int, default=0, help="fixed update-kernel tile id (default: autotuned)")
+    ap.add_argument("--only", choices=["refined", "ensemble"], default=None,
+                    help="run only the refined-grid or the ensemble part (profiling runs; prints its JSON)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -321,6 +324,14 @@ def main():
         del src, dst
     cfg = W.get(args.workload)
     other = "f64" if args.prec == "f32" else "f32"
+    if args.only:
+        precs = (args.prec,) if args.no_other_prec else (args.prec, other)
+        part = {}
+        for p in precs:
+            part[p] = run_amr(p, args.warmup) if args.only == "refined" else run_ensemble(p, args.warmup)
+            log(f"bench: {args.only} {p} {part[p]['value']:.4g} cell-updates/s")
+        print(json.dumps({args.only: part}), flush=True)
+        return
     log(f"bench: {cfg.name} {cfg.nx}x{cfg.ny}x{cfg.nz} prec={args.prec} steps={args.steps} warmup={args.warmup}")
     head = run_gpu(cfg, args.prec, args.steps, args.warmup, args.tile)
     log(f"bench: {cfg.name} {args.prec} {head['value']:.4g} cell-updates/s, {head['ms_per_step']:.3f} ms/step, "

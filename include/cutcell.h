@@ -332,6 +332,12 @@ int32_t amr_batch_current(cc_batch batch, int32_t level);
 /* Number of levels of the batch (1 for ensembles). */
 int32_t amr_batch_levels(cc_batch batch);
 
+/* Launch sizes of one level: out[8] = {blocks, regular-point tiles, band-point tiles, diagnostic
+ * columns, same-level refill entries refilled before the diagnostics, those refilled after them (the
+ * ghost cells within reach of the next stage's update), coarse-to-fine entries, fine-to-coarse
+ * entries}. */
+cc_status amr_batch_info(cc_batch batch, int32_t level, int64_t out[8]);
+
 /* Release the handle (graph executables, capture stream). */
 cc_status amr_batch_destroy(cc_batch batch);
 

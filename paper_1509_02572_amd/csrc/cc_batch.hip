@@ -31,6 +31,12 @@ namespace cc {
 // ghost-cell refill: destination block / box index, source block / box index (block numbers
 // within their levels)
 struct GhostEnt { int32_t dblk, didx, sblk, sidx; };
+// on the device the refill lists are packed by (destination, source) block pair: chunks of at most
+// 64 entries of one pair (one wavefront each, so the pair's descriptors are read once per wave), and
+// the entries' destination and source box indices
+struct GhostPair { int32_t didx, sidx; };
+struct GhostChunk { int32_t dblk, sblk, first, count; };
+constexpr int FILL_CHUNK = 64;
 // fine side of one coarse-fine face: fine block, axis and the four fine sub-faces, each given as
 // the box index of the cell on the +axis side of the sub-face
 struct FluxSlot { int32_t fblk, axis, idx[4]; };
@@ -68,13 +74,20 @@ __device__ __forceinline__ double get_scalar(const SOut<T> &q, int64_t i, int w)
 // state) move as they are, and momentum at predicted points keeps its total value: the float form
 // stores rho u - rhobar_c(K) U, so the base term of the two levels' lattice levels is exchanged.
 template <typename T>
-__global__ void k_ghost_fill(const BlockDesc<T> *__restrict__ dd, int rd, const BlockDesc<T> *__restrict__ sd, int rs,
-                             const GhostEnt *__restrict__ e, int n, int mode)
+__global__ void __launch_bounds__(256) k_ghost_fill(const BlockDesc<T> *__restrict__ dd, int rd,
+                                                    const BlockDesc<T> *__restrict__ sd, int rs,
+                                                    const GhostChunk *__restrict__ ch,
+                                                    const GhostPair *__restrict__ pr, int nch, int mode)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const GhostEnt g = e[t];
-    const BlockDesc<T> &D = dd[g.dblk], &S = sd[g.sblk];
+    const int c = blockIdx.x * (256 / FILL_CHUNK) + (int)(threadIdx.x / FILL_CHUNK);
+    if (c >= nch) return;
+    const int lane = threadIdx.x % FILL_CHUNK;
+    // the chunk's block pair is the same on every lane of the wave
+    const int dblk = __builtin_amdgcn_readfirstlane(ch[c].dblk), sblk = __builtin_amdgcn_readfirstlane(ch[c].sblk);
+    const int first = __builtin_amdgcn_readfirstlane(ch[c].first), count = __builtin_amdgcn_readfirstlane(ch[c].count);
+    if (lane >= count) return;
+    const GhostPair g = pr[first + lane];
+    const BlockDesc<T> &D = dd[dblk], &S = sd[sblk];
     const SOut<T> qd = D.q[rd], qs = S.q[rs];
     const int64_t di = g.didx, si = g.sidx;
     if (mode == FILL_RESTRICT) {
@@ -239,6 +252,10 @@ struct Level {
     size_t desc_off = 0;
     size_t same_off = 0, inj_off = 0, res_off = 0, slot_off = 0, corr_off = 0, reg_off = 0;
     int nsame = 0, ninj = 0, nres = 0, nslot = 0, ncorr = 0;
+    int nsame_near = 0;  // the first same-level entries: ghost cells within NEAR_GHOST of the update range
+    // packed refill lists: chunk tables (the entries follow each table in the workspace)
+    size_t same_ch = 0, inj_ch = 0, res_ch = 0;
+    int csame = 0, csame_near = 0, cinj = 0, cres = 0;  // chunks
 };
 
 struct cc_batch_s {
@@ -293,12 +310,15 @@ void launch_batch_stage(const cc_batch_s *b, int l, int rn, int rs, int ro, doub
         (void)hipStreamSynchronize(sb);
 }
 
+// refill of level ld's ghost cells from level ls: nch chunks of the table at chunk offset ch, whose
+// entries start at entry offset off
 template <typename T>
-void fill(const cc_batch_s *b, int ld, int ls, size_t off, int n, int mode, hipStream_t s)
+void fill(const cc_batch_s *b, int ld, int ls, size_t ch, size_t off, int nch, int mode, hipStream_t s)
 {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_ghost_fill<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, descs<T>(b, ld), b->lev[ld].cur,
-                       descs<T>(b, ls), b->lev[ls].cur, (const GhostEnt *)(b->ws + off), n, mode);
+    if (nch <= 0) return;
+    hipLaunchKernelGGL(k_ghost_fill<T>, dim3(blocks_for(nch, 256 / FILL_CHUNK)), dim3(256), 0, s, descs<T>(b, ld),
+                       b->lev[ld].cur, descs<T>(b, ls), b->lev[ls].cur, (const GhostChunk *)(b->ws + ch),
+                       (const GhostPair *)(b->ws + off), nch, mode);
 }
 
 // one Runge-Kutta stage of level l: update, flux matching in the final stage, diagnostics, then
@@ -329,16 +349,18 @@ void level_stage(cc_batch_s *b, int l, int rn, int rs, int ro, double cdt, int f
                                (const CorrEnt *)(b->ws + L.corr_off), L.ncorr, dt, (double *)(b->ws + L.reg_off), st);
     }
     // ghost cells of the same level were not updated: they take their owners' values before the
-    // diagnostics (whose nearest-plane walk reads neighbouring columns) and again after them
-    auto refill = [&]() {
-        if (L.nsame > 0)
-            hipLaunchKernelGGL(k_ghost_fill<T>, dim3(blocks_for(L.nsame, 256)), dim3(256), 0, s, descs<T>(b, l), ro,
-                               descs<T>(b, l), ro, (const GhostEnt *)(b->ws + L.same_off), L.nsame, (int)FILL_COPY);
+    // diagnostics (whose nearest-plane walk reads neighbouring columns: every listed ghost cell) and
+    // again after them (the ghost cells the next stage's update reads: the near ones)
+    auto refill = [&](int nch) {
+        if (nch > 0)
+            hipLaunchKernelGGL(k_ghost_fill<T>, dim3(blocks_for(nch, 256 / FILL_CHUNK)), dim3(256), 0, s,
+                               descs<T>(b, l), ro, descs<T>(b, l), ro, (const GhostChunk *)(b->ws + L.same_ch),
+                               (const GhostPair *)(b->ws + L.same_off), nch, (int)FILL_COPY);
     };
-    refill();
+    refill(L.csame);
     hipLaunchKernelGGL(k_diagnose_batch<T>, dim3(blocks_for(L.ncols, DIAG_COLS)), dim3(DIAG_THREADS), 0, s, descs<T>(b, l), L.nblk,
                        L.ncols, ro, st);
-    refill();
+    refill(L.csame_near);
 }
 
 // one step of level l (dt), preceded by two steps of level l+1 and followed by the exchange with it
@@ -357,8 +379,9 @@ void level_step(cc_batch_s *b, int l, double dt, int64_t *st, hipStream_t s)
     level_stage<T>(b, l, a, c, o, dt, 1, dt, st, s);
     L.cur = o;
     if (l + 1 < nl) {
-        fill<T>(b, l, l + 1, L.res_off, L.nres, FILL_RESTRICT, s);             // level l <- level l+1
-        fill<T>(b, l + 1, l, b->lev[l + 1].inj_off, b->lev[l + 1].ninj, FILL_INJECT, s);  // level l+1 <- level l
+        fill<T>(b, l, l + 1, L.res_ch, L.res_off, L.cres, FILL_RESTRICT, s);  // level l <- level l+1
+        const Level &F = b->lev[l + 1];
+        fill<T>(b, l + 1, l, F.inj_ch, F.inj_off, F.cinj, FILL_INJECT, s);    // level l+1 <- level l
     }
 }
 
@@ -381,9 +404,9 @@ void sync_all(cc_batch_s *b, hipStream_t s)
     int nl = (int)b->lev.size();
     for (int l = 0; l < nl; ++l) {
         const Level &L = b->lev[l];
-        fill<T>(b, l, l, L.same_off, L.nsame, FILL_COPY, s);
-        if (l + 1 < nl) fill<T>(b, l, l + 1, L.res_off, L.nres, FILL_RESTRICT, s);
-        if (l > 0) fill<T>(b, l, l - 1, L.inj_off, L.ninj, FILL_INJECT, s);
+        fill<T>(b, l, l, L.same_ch, L.same_off, L.csame, FILL_COPY, s);
+        if (l + 1 < nl) fill<T>(b, l, l + 1, L.res_ch, L.res_off, L.cres, FILL_RESTRICT, s);
+        if (l > 0) fill<T>(b, l, l - 1, L.inj_ch, L.inj_off, L.cinj, FILL_INJECT, s);
     }
 }
 
@@ -397,6 +420,7 @@ struct Tables {
     std::vector<std::vector<FluxSlot>> slots;
     std::vector<std::vector<CorrEnt>> corr;
     std::vector<std::array<int, 6>> range;  // per block: cells to update [lo, hi) (empty: the whole grid)
+    std::vector<int> near;                  // per level: same-level entries within NEAR_GHOST (listed first)
 };
 
 inline int64_t pmod(int64_t a, int64_t n) { a %= n; return a < 0 ? a + n : a; }
@@ -413,7 +437,39 @@ struct OwnerMap {
     }
 };
 
-bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, const char *what)
+// Same-level ghost cells a stage reads, by distance (cells, along the furthest axis) from the cells
+// whose values matter (the block's own cells and its ghost cells owned by other levels): the update
+// reads up to two cells beyond them, three for the members and face corners of a merged group at
+// their edge (NEAR_GHOST); the nearest-plane walk of the diagnostics reads predicted velocities up to
+// four lattice points sideways, with the densities of the cells around them (DIAG_GHOST), and only
+// at heights near the terrain (below the block's highest diagnosed level plus DIAG_RISE).  Other
+// ghost cells of the same level are never read by those cells and are not refilled (the update
+// computes them with the rest of its box; their values are never used).
+constexpr int NEAR_GHOST = 3, DIAG_GHOST = 5, DIAG_RISE = 8;
+
+// cells of a box within Chebyshev distance r of a marked cell (separable: a window of 2r+1 per axis)
+static std::vector<uint8_t> dilate(const std::vector<uint8_t> &m, int nx, int ny, int nz, int r)
+{
+    std::vector<uint8_t> a = m, b(m.size());
+    const int n[3] = {nx, ny, nz};
+    const int64_t st[3] = {(int64_t)ny * nz, nz, 1};
+    for (int ax = 0; ax < 3; ++ax) {
+        std::fill(b.begin(), b.end(), 0);
+        for (int64_t c = 0; c < (int64_t)a.size(); ++c) {
+            if (!a[c]) continue;
+            const int pos = (int)((c / st[ax]) % n[ax]);
+            const int lo = std::max(0, pos - r), hi = std::min(n[ax] - 1, pos + r);
+            for (int q = lo; q <= hi; ++q) b[c + (int64_t)(q - pos) * st[ax]] = 1;
+        }
+        std::swap(a, b);
+    }
+    return a;
+}
+
+// ktop: per block, the level below which its diagnostics read (empty: every level, the upper bound
+// of the table sizes)
+bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, const char *what,
+                  const std::vector<int> &ktop = {})
 {
     int nl = 0;
     for (int m = 0; m < n; ++m) {
@@ -480,6 +536,7 @@ bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, co
     };
     t.same.assign(nl, {}); t.inj.assign(nl, {}); t.res.assign(nl, {});
     t.slots.assign(nl, {}); t.corr.assign(nl, {});
+    t.near.assign(nl, 0);
     // cells a block must update: its own cells and the ghost cells of other levels (integrated on
     // between refills); ghosts of the same level are refilled after every stage
     t.range.assign(n, {0, 0, 0, 0, 0, 0});
@@ -491,8 +548,18 @@ bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, co
         r[3] = std::max(r[3], i + 1); r[4] = std::max(r[4], j + 1); r[5] = std::max(r[5], k + 1);
     };
     for (int l = 0; l < nl; ++l) {
+        std::vector<GhostEnt> far;  // same-level entries read by the diagnostics only
         for (int m : t.members[l]) {
             const cc_block &b = B[m];
+            std::vector<std::array<int, 3>> at;  // box position of each same-level entry of this block
+            const size_t first = t.same[l].size();
+            // the cells whose values matter: own cells and ghost cells owned by another level
+            const int bx = b.grid.nx, by = b.grid.ny, bz = b.grid.nz;
+            std::vector<uint8_t> real((size_t)bx * by * bz, 0);
+            auto mark = [&](int i, int j, int k) { real[((size_t)i * by + j) * bz + k] = 1; };
+            for (int i = b.ilo[0]; i < b.ihi[0]; ++i)
+                for (int j = b.ilo[1]; j < b.ihi[1]; ++j)
+                    for (int k = b.ilo[2]; k < b.ihi[2]; ++k) mark(i, j, k);
             for (int i = 0; i < b.grid.nx; ++i)
                 for (int j = 0; j < b.grid.ny; ++j)
                     for (int k = 0; k < b.grid.nz; ++k) {
@@ -504,6 +571,7 @@ bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, co
                         int o = om[l].at(g[0], g[1], g[2]);
                         if (o >= 0) {
                             t.same[l].push_back({t.local[m], didx, o, box_index(t.members[l][o], l, g)});
+                            at.push_back({i, j, k});
                             continue;
                         }
                         if (l > 0) {
@@ -512,6 +580,7 @@ bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, co
                             if (oc >= 0) {
                                 t.inj[l].push_back({t.local[m], didx, oc, box_index(t.members[l - 1][oc], l - 1, gc)});
                                 grow(m, i, j, k);
+                                mark(i, j, k);
                                 continue;
                             }
                         }
@@ -527,10 +596,25 @@ bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, co
                                     }
                                 t.res[l].push_back({t.local[m], didx, of, box_index(t.members[l + 1][of], l + 1, gf)});
                                 grow(m, i, j, k);
+                                mark(i, j, k);
                             }
                         }
                     }
+            // keep the same-level entries a stage reads: the near ones in place, the diagnostic-only
+            // ones aside
+            const std::vector<uint8_t> near = dilate(real, bx, by, bz, NEAR_GHOST);
+            const std::vector<uint8_t> diag = dilate(real, bx, by, bz, DIAG_GHOST);
+            size_t w = first;
+            for (size_t e = first; e < t.same[l].size(); ++e) {
+                const std::array<int, 3> &p = at[e - first];
+                const size_t c = ((size_t)p[0] * by + p[1]) * bz + p[2];
+                if (near[c]) t.same[l][w++] = t.same[l][e];
+                else if (diag[c] && (ktop.empty() || p[2] < ktop[m])) far.push_back(t.same[l][e]);
+            }
+            t.same[l].resize(w);
         }
+        t.near[l] = (int)t.same[l].size();
+        t.same[l].insert(t.same[l].end(), far.begin(), far.end());
         if (l + 1 >= nl) continue;
         // coarse-fine faces of level l's own cells
         for (int m : t.members[l]) {
@@ -677,10 +761,42 @@ int band_tile(const cc_block *B, int n, int &BX, int &BY, int &BZ)
     return id;
 }
 
+// a refill list packed for the device: entries [0, nfirst) and [nfirst, n) are each ordered by
+// (destination, source) block pair (stably, so box order is kept within a pair) and cut into chunks
+// of at most FILL_CHUNK entries of one pair; the first part's chunks come first
+struct Packed {
+    std::vector<GhostPair> pairs;
+    std::vector<GhostChunk> chunks;
+    int nchunks_first = 0;
+};
+
+static Packed pack(const std::vector<GhostEnt> &v, size_t nfirst)
+{
+    Packed p;
+    auto part = [&](size_t lo, size_t hi) {
+        std::vector<GhostEnt> e(v.begin() + lo, v.begin() + hi);
+        std::stable_sort(e.begin(), e.end(), [](const GhostEnt &a, const GhostEnt &b) {
+            return a.dblk != b.dblk ? a.dblk < b.dblk : a.sblk < b.sblk;
+        });
+        for (size_t a = 0; a < e.size();) {
+            size_t z = a;
+            while (z < e.size() && z - a < (size_t)FILL_CHUNK && e[z].dblk == e[a].dblk && e[z].sblk == e[a].sblk) ++z;
+            p.chunks.push_back({e[a].dblk, e[a].sblk, (int32_t)p.pairs.size(), (int32_t)(z - a)});
+            for (size_t q = a; q < z; ++q) p.pairs.push_back({e[q].didx, e[q].sidx});
+            a = z;
+        }
+    };
+    part(0, nfirst);
+    p.nchunks_first = (int)p.chunks.size();
+    part(nfirst, v.size());
+    return p;
+}
+
 // layout of the workspace and (when `b` is given) the host images to upload
 struct Plan {
     size_t bytes = 0;
     std::vector<std::vector<char>> desc;
+    std::vector<Packed> same, inj, res;  // per level
 };
 
 bool plan_batch(const cc_block *B, int n, cc_prec prec, int tile, bool own_range, const Tables &t, cc_batch_s *b,
@@ -692,6 +808,7 @@ bool plan_batch(const cc_block *B, int n, cc_prec prec, int tile, bool own_range
     int nl = (int)t.members.size();
     std::vector<Level> lev(nl);
     plan.desc.assign(nl, {});
+    plan.same.assign(nl, {}); plan.inj.assign(nl, {}); plan.res.assign(nl, {});
     size_t off = 0;
     for (int l = 0; l < nl; ++l) {
         bool ok = prec == CC_F64
@@ -705,9 +822,22 @@ bool plan_batch(const cc_block *B, int n, cc_prec prec, int tile, bool own_range
     }
     for (int l = 0; l < nl; ++l) {
         Level &L = lev[l];
-        L.nsame = (int)t.same[l].size(); L.same_off = off; off = align256(off + sizeof(GhostEnt) * L.nsame);
-        L.ninj = (int)t.inj[l].size(); L.inj_off = off; off = align256(off + sizeof(GhostEnt) * L.ninj);
-        L.nres = (int)t.res[l].size(); L.res_off = off; off = align256(off + sizeof(GhostEnt) * L.nres);
+        L.nsame = (int)t.same[l].size();
+        L.nsame_near = t.near.empty() ? L.nsame : t.near[l];
+        L.ninj = (int)t.inj[l].size();
+        L.nres = (int)t.res[l].size();
+        plan.same[l] = pack(t.same[l], (size_t)L.nsame_near);
+        plan.inj[l] = pack(t.inj[l], t.inj[l].size());
+        plan.res[l] = pack(t.res[l], t.res[l].size());
+        auto put = [&](const Packed &p, size_t &ch, size_t &pe, int &nch) {
+            nch = (int)p.chunks.size();
+            ch = off; off = align256(off + sizeof(GhostChunk) * p.chunks.size());
+            pe = off; off = align256(off + sizeof(GhostPair) * p.pairs.size());
+        };
+        put(plan.same[l], L.same_ch, L.same_off, L.csame);
+        L.csame_near = plan.same[l].nchunks_first;
+        put(plan.inj[l], L.inj_ch, L.inj_off, L.cinj);
+        put(plan.res[l], L.res_ch, L.res_off, L.cres);
         L.nslot = (int)t.slots[l].size(); L.slot_off = off; off = align256(off + sizeof(FluxSlot) * L.nslot);
         L.ncorr = (int)t.corr[l].size(); L.corr_off = off; off = align256(off + sizeof(CorrEnt) * L.ncorr);
         L.reg_off = off; off = align256(off + sizeof(double) * 2 * L.nslot);
@@ -745,9 +875,12 @@ bool upload(cc_batch_s *b, const Plan &plan, const Tables *t, hipStream_t s, con
         auto put = [&](size_t off, const void *p, size_t nb) {
             if (e == hipSuccess && nb) e = hipMemcpyAsync(b->ws + off, p, nb, hipMemcpyHostToDevice, s);
         };
-        put(L.same_off, t->same[l].data(), sizeof(GhostEnt) * L.nsame);
-        put(L.inj_off, t->inj[l].data(), sizeof(GhostEnt) * L.ninj);
-        put(L.res_off, t->res[l].data(), sizeof(GhostEnt) * L.nres);
+        put(L.same_ch, plan.same[l].chunks.data(), sizeof(GhostChunk) * plan.same[l].chunks.size());
+        put(L.same_off, plan.same[l].pairs.data(), sizeof(GhostPair) * plan.same[l].pairs.size());
+        put(L.inj_ch, plan.inj[l].chunks.data(), sizeof(GhostChunk) * plan.inj[l].chunks.size());
+        put(L.inj_off, plan.inj[l].pairs.data(), sizeof(GhostPair) * plan.inj[l].pairs.size());
+        put(L.res_ch, plan.res[l].chunks.data(), sizeof(GhostChunk) * plan.res[l].chunks.size());
+        put(L.res_off, plan.res[l].pairs.data(), sizeof(GhostPair) * plan.res[l].pairs.size());
         put(L.slot_off, t->slots[l].data(), sizeof(FluxSlot) * L.nslot);
         put(L.corr_off, t->corr[l].data(), sizeof(CorrEnt) * L.ncorr);
         if (e == hipSuccess && L.nslot) e = hipMemsetAsync(b->ws + L.reg_off, 0, sizeof(double) * 2 * L.nslot, s);
@@ -780,6 +913,7 @@ extern "C" cc_status amr_batch_create(const cc_block *blocks, int32_t nblocks, c
     t.members.assign(1, {});
     for (int m = 0; m < nblocks; ++m) t.members[0].push_back(m);
     t.same.assign(1, {}); t.inj.assign(1, {}); t.res.assign(1, {}); t.slots.assign(1, {}); t.corr.assign(1, {});
+    t.near.assign(1, 0);
     cc_batch_s *b = new cc_batch_s();
     Plan plan;
     if (!plan_batch(blocks, nblocks, prec, tile, false, t, b, plan, "amr_batch_create")) { delete b; return CC_EINVAL; }
@@ -810,8 +944,26 @@ extern "C" cc_status amr_hierarchy_create(const cc_block *blocks, int32_t nblock
     CC_REQUIRE(blocks && nblocks > 0 && domain0 && workspace && out, "amr_hierarchy_create: null or empty argument");
     CC_REQUIRE(prec == CC_F64 || prec == CC_F32_PERT, "amr_hierarchy_create: unknown precision");
     CC_REQUIRE(domain0[0] > 0 && domain0[1] > 0 && domain0[2] > 0, "amr_hierarchy_create: empty level-0 domain");
+    // the level below which each block's diagnostics read: its highest diagnosed level (column
+    // bands written by cutcell_merge_map) plus DIAG_RISE
+    std::vector<int> ktop(nblocks, 0);
+    for (int m = 0; m < nblocks; ++m) {
+        const cc_grid &g = blocks[m].grid;
+        CC_REQUIRE(blocks[m].geom.colk, "amr_hierarchy_create: block %d has no column bands", m);
+        std::vector<int32_t> ck((size_t)g.nx * g.ny);
+        hipError_t e = hipMemcpyAsync(ck.data(), blocks[m].geom.colk + 2 * (size_t)g.nx * g.ny,
+                                      sizeof(int32_t) * ck.size(), hipMemcpyDeviceToHost, (hipStream_t)stream);
+        if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) {
+            set_error("amr_hierarchy_create: %s", hipGetErrorString(e));
+            return CC_EDEVICE;
+        }
+        int top = 0;
+        for (int32_t v : ck) top = std::max(top, (int)v);
+        ktop[m] = top + DIAG_RISE;
+    }
     Tables t;
-    if (!build_tables(blocks, nblocks, domain0, t, "amr_hierarchy_create")) return CC_EINVAL;
+    if (!build_tables(blocks, nblocks, domain0, t, "amr_hierarchy_create", ktop)) return CC_EINVAL;
     cc_batch_s *b = new cc_batch_s();
     Plan plan;
     if (!plan_batch(blocks, nblocks, prec, tile, true, t, b, plan, "amr_hierarchy_create")) { delete b; return CC_EINVAL; }
@@ -885,6 +1037,15 @@ extern "C" int32_t amr_batch_current(cc_batch b, int32_t level)
 }
 
 extern "C" int32_t amr_batch_levels(cc_batch b) { return b ? (int32_t)b->lev.size() : 0; }
+
+extern "C" cc_status amr_batch_info(cc_batch b, int32_t level, int64_t out[8])
+{
+    CC_REQUIRE(b && out && level >= 0 && level < (int32_t)b->lev.size(), "amr_batch_info: bad batch or level");
+    const Level &L = b->lev[level];
+    const int64_t v[8] = {L.nblk, L.ntilesr, L.ntiles, L.ncols, L.nsame, L.nsame_near, L.ninj, L.nres};
+    for (int a = 0; a < 8; ++a) out[a] = v[a];
+    return CC_OK;
+}
 
 extern "C" cc_status amr_batch_destroy(cc_batch b)
 {

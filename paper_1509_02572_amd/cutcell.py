@@ -92,6 +92,8 @@ def lib():
         L.amr_batch_current.argtypes = [vp, C.c_int32]
         L.amr_batch_current.restype = C.c_int32
         L.amr_batch_levels.argtypes = [vp]
+        L.amr_batch_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64)]
+        L.amr_batch_info.restype = C.c_int
         L.amr_batch_levels.restype = C.c_int32
         i3 = C.c_int32 * 3
         L.amr_hierarchy_workspace_bytes.argtypes = [C.POINTER(cc_block), C.c_int32, C.c_int, i3,
@@ -234,6 +236,14 @@ def amr_block_step(batch: C.c_void_p, dt: float, nsteps: int, use_graph: bool, s
 
 def amr_batch_current(batch: C.c_void_p, level: int = 0) -> int:
     return int(lib().amr_batch_current(batch, level))
+
+
+def amr_batch_info(batch: C.c_void_p, level: int) -> Dict[str, int]:
+    out = (C.c_int64 * 8)()
+    _check(lib().amr_batch_info(batch, level, out), "amr_batch_info")
+    keys = ("blocks", "regular_tiles", "band_tiles", "diag_columns", "same_refill", "same_refill_near",
+            "inject", "restrict")
+    return {k: int(v) for k, v in zip(keys, out)}
 
 
 def amr_batch_levels(batch: C.c_void_p) -> int:
