@@ -27,7 +27,9 @@
 #include <string.h>
 
 typedef struct { int32_t nx, ny, nz, nsub; double dx, dy, dz, z0; } or_grid;  /* z0: bottom height */
-typedef struct { double g, rd, cp, p0, theta0, bvn, u0, v0; } or_phys;
+/* kdh, kdv: rates [1/s] of the fourth-order artificial diffusion in the horizontal and the vertical
+ * (0: none) */
+typedef struct { double g, rd, cp, p0, theta0, bvn, u0, v0, kdh, kdv; } or_phys;
 
 /* cell classes, merge directions and lattice-point classes (numeric codes are an interface) */
 enum { OR_SOLID = 0, OR_OPEN = 1, OR_ABSORBED = 2, OR_ORPHAN = 3 };
@@ -767,6 +769,129 @@ static void build_groups(const or_grid *g, const or_geom *G, int64_t *head, int6
     free(tail);
 }
 
+/* ------------------------------------------------------------------------------------------ */
+/* Fourth-order artificial diffusion (Sec. 2.1: source terms D of every prognostic equation; a  */
+/* 5-point stencil per direction, Sec. 2.2; a second-order term where the fourth-order stencil  */
+/* lacks fluid neighbours, with the terrain as boundary, Sec. 2.4).  Written in flux form: the   */
+/* flux through a face is the third difference of the four values straddling it, or -4 x their  */
+/* first difference when one of the outer two is missing, and zero through a closed face, so    */
+/* D = -k x (flux out - flux in) reduces to -k (phi_{i-2} - 4 phi_{i-1} + 6 phi_i - 4 phi_{i+1} + */
+/* phi_{i+2}) in the interior and conserves the scalars.  Scalars: the group values of rho' and  */
+/* (rho theta)', apertures and group volume as for the advective fluxes; momentum: the           */
+/* perturbation rho u - rhobar_c (u0, v0, 0) at predicted points, the others act as boundary.    */
+/* ------------------------------------------------------------------------------------------ */
+
+/* group value of scalar w (0: rho', 1: (rho theta)') of non-solid cell c */
+static double group_pert(const or_ctx *x, size_t c, int w)
+{
+    int32_t m = x->G->master[c];
+    return w == 0 ? x->q->rho[m] : x->q->rth[m];
+}
+
+/* diffusive flux of both scalars through the face between L = (i,j,k) - e_a and U = (i,j,k) along
+ * axis a, positive along +a (without the rate): F[w] */
+static void diffusion_face(const or_ctx *x, int a, int i, int j, int k, double F[2])
+{
+    const or_grid *g = x->g;
+    int dl[3] = {0, 0, 0};
+    dl[a] = 1;
+    size_t U = cidx(g, i, j, k), L = cidx(g, i - dl[0], j - dl[1], k - dl[2]);
+    double A = a == 0 ? x->G->Ax[U] : (a == 1 ? x->G->Ay[U] : x->G->Az[U]);
+    F[0] = F[1] = 0.0;
+    if (a == 2 && (k - 1 < 0 || k >= g->nz)) return; /* ground and lid */
+    if (A == 0.0 || x->G->master[L] == x->G->master[U]) return; /* closed or internal face */
+    int k2l = k - 2 * dl[2], k2u = k + dl[2];
+    int outer = k2l >= 0 && k2u < g->nz;
+    size_t L2 = 0, U2 = 0;
+    if (outer) {
+        L2 = cidx(g, i - 2 * dl[0], j - 2 * dl[1], k2l);
+        U2 = cidx(g, i + dl[0], j + dl[1], k2u);
+        outer = x->G->V[L2] > 0.0 && x->G->V[U2] > 0.0;
+    }
+    for (int w = 0; w < 2; ++w) {
+        double pl = group_pert(x, L, w), pu = group_pert(x, U, w);
+        if (outer)
+            F[w] = ((group_pert(x, U2, w) - 3.0 * pu) + 3.0 * pl) - group_pert(x, L2, w);
+        else
+            F[w] = -4.0 * (pu - pl);
+    }
+}
+
+/* D of the two scalars at master m (members in increasing linear index, faces -x,+x,-y,+y,-z,+z) */
+static void diffusion_group(const or_ctx *x, size_t m, const size_t *mem, int nmem, double D[2])
+{
+    const or_grid *g = x->g;
+    double acc[2] = {0.0, 0.0};
+    for (int t = 0; t < nmem; ++t) {
+        size_t c = mem[t];
+        int k = (int)(c % g->nz), j = (int)((c / g->nz) % g->ny), i = (int)(c / ((size_t)g->nz * g->ny));
+        for (int f = 0; f < 6; ++f) {
+            int a = f / 2, plus = f & 1;
+            int fi = i + (a == 0 && plus), fj = j + (a == 1 && plus), fk = k + (a == 2 && plus);
+            if (a == 2 && (fk <= 0 || fk >= g->nz)) continue;
+            size_t fu = cidx(g, fi, fj, fk);
+            double A = a == 0 ? x->G->Ax[fu] : (a == 1 ? x->G->Ay[fu] : x->G->Az[fu]);
+            double kr = a == 2 ? x->ph->kdv : x->ph->kdh;
+            double F[2];
+            diffusion_face(x, a, fi, fj, fk, F);
+            for (int w = 0; w < 2; ++w) {
+                double term = (kr * A) * F[w];
+                acc[w] = plus ? acc[w] + term : acc[w] - term;
+            }
+        }
+    }
+    double vg = x->G->Vgroup[m];
+    D[0] = -acc[0] / vg;
+    D[1] = -acc[1] / vg;
+}
+
+/* momentum perturbation component c at lattice point p (level K) */
+static double mom_pert(const or_ctx *x, size_t p, int K, int c)
+{
+    double rbc = 0.5 * (x->rhob[K - 1] + x->rhob[K]);
+    if (c == 0) return x->q->mu[p] - rbc * x->ph->u0;
+    if (c == 1) return x->q->mv[p] - rbc * x->ph->v0;
+    return x->q->mw[p];
+}
+
+/* diffusive flux of the momentum perturbation through the face between lattice points P = (I,J,K)
+ * and Q = P + e_a, positive along +a: F[3] */
+static void diffusion_lattice_face(const or_ctx *x, int a, int I, int J, int K, double F[3])
+{
+    int d[3] = {0, 0, 0};
+    d[a] = 1;
+    F[0] = F[1] = F[2] = 0.0;
+    if (!is_pred(x, I, J, K) || !is_pred(x, I + d[0], J + d[1], K + d[2])) return;
+    const or_grid *g = x->g;
+    size_t P = cidx(g, I, J, K), Q = cidx(g, I + d[0], J + d[1], K + d[2]);
+    int outer = is_pred(x, I - d[0], J - d[1], K - d[2]) && is_pred(x, I + 2 * d[0], J + 2 * d[1], K + 2 * d[2]);
+    size_t P2 = outer ? cidx(g, I - d[0], J - d[1], K - d[2]) : 0;
+    size_t Q2 = outer ? cidx(g, I + 2 * d[0], J + 2 * d[1], K + 2 * d[2]) : 0;
+    for (int c = 0; c < 3; ++c) {
+        double mp = mom_pert(x, P, K, c), mq = mom_pert(x, Q, K + d[2], c);
+        if (outer)
+            F[c] = ((mom_pert(x, Q2, K + 2 * d[2], c) - 3.0 * mq) + 3.0 * mp) - mom_pert(x, P2, K - d[2], c);
+        else
+            F[c] = -4.0 * (mq - mp);
+    }
+}
+
+/* D of the momentum perturbation at predicted point (I,J,K): axes x, y, z */
+static void diffusion_point(const or_ctx *x, int I, int J, int K, double D[3])
+{
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 3; ++a) {
+        int d[3] = {0, 0, 0};
+        d[a] = 1;
+        double kr = a == 2 ? x->ph->kdv : x->ph->kdh;
+        double Fp[3], Fm[3];
+        diffusion_lattice_face(x, a, I, J, K, Fp);
+        diffusion_lattice_face(x, a, I - d[0], J - d[1], K - d[2], Fm);
+        for (int c = 0; c < 3; ++c) acc[c] += kr * (Fp[c] - Fm[c]);
+    }
+    for (int c = 0; c < 3; ++c) D[c] = -acc[c];
+}
+
 static void tendency_cell(const or_ctx *x, size_t c, const int64_t *head, const int64_t *next,
                           double dq[5], int *has_scalar, int *has_mom)
 {
@@ -784,12 +909,23 @@ static void tendency_cell(const or_ctx *x, size_t c, const int64_t *head, const 
         double vol = G->Vgroup[c] * (g->dx * g->dy * g->dz);
         dq[0] = -R[0] / vol;
         dq[1] = -R[1] / vol;
+        if (x->ph->kdh != 0.0 || x->ph->kdv != 0.0) {
+            double D[2];
+            diffusion_group(x, c, mem, nm, D);
+            dq[0] += D[0];
+            dq[1] += D[1];
+        }
         *has_scalar = 1;
     }
     if (G->vcls[c] == OR_PRED) {
         double m3[3];
         momentum_tendency(x, i, j, k, m3);
         dq[2] = m3[0]; dq[3] = m3[1]; dq[4] = m3[2];
+        if (x->ph->kdh != 0.0 || x->ph->kdv != 0.0) {
+            double D[3];
+            diffusion_point(x, i, j, k, D);
+            dq[2] += D[0]; dq[3] += D[1]; dq[4] += D[2];
+        }
         *has_mom = 1;
     }
 }

@@ -78,6 +78,8 @@ class Config:
     p0: float = P0
     H: Optional[np.ndarray] = None  # explicit corner heights (overrides ``hill``)
     z0: float = 0.0  # height of the grid's bottom face (blocks of a refined grid); H is then relative to it
+    kdh: float = 0.0  # rate of the fourth-order artificial diffusion in x and y [1/s] (0: none)
+    kdv: float = 0.0  # the same in z
 
     @property
     def ncells(self) -> int:
