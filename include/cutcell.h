@@ -94,6 +94,10 @@ typedef struct {
     double g, rd, cp, p0; /* gravity, gas constant, specific heat at constant pressure, p_ref */
     double theta0, bvn;   /* sea-level potential temperature [K], Brunt-Vaisala frequency [1/s] */
     double u0, v0;        /* uniform inflow (reference velocity of the perturbation form) */
+    double kdh, kdv;      /* rates [1/s] of the fourth-order artificial diffusion in x, y and in z
+                             (Sec. 2.1 D terms; 0: none; single grids only).  The 2-dx mode of a field
+                             decays at 16 kdh per horizontal direction (16 kdv vertically); the
+                             explicit stage needs dt (32 kdh + 16 kdv) below about 2.5 */
 } cc_phys;
 
 /* Geometry and merge map (device arrays, caller-allocated). */
@@ -205,8 +209,13 @@ cc_status cutcell_diagnose(const cc_grid *grid, const cc_phys *phys, const cc_ge
 
 /* Tendency L(q) (Sec. 2.4): scalar fluxes with apertures over the whole merged group divided by the
  * group volume (eqs. gauss_m, gauss_d, fvm_d and the merged-cell face split), momentum, pressure
- * gradient and buoyancy at predicted points (eqs. momentum_u_d, _v_d, _w_d).  dqdt: same element
- * type as q; scalars at group masters, momentum at predicted points, zero elsewhere. */
+ * gradient and buoyancy at predicted points (eqs. momentum_u_d, _v_d, _w_d), plus the fourth-order
+ * artificial diffusion when phys->kdh or kdv is non-zero: in flux form, the flux through a face being
+ * the third difference of the four values straddling it, or -4 x their first difference where an
+ * outer one is missing (solid cell, point not predicted, ground, lid: the second-order term of
+ * Sec. 2.4), zero through closed faces; scalars with apertures and group volumes (conservative),
+ * momentum as the perturbation rho u - rhobar_c (u0, v0, 0).  dqdt: same element type as q; scalars
+ * at group masters, momentum at predicted points, zero elsewhere. */
 cc_status cutcell_tendency(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
                            const double *base, cc_prec prec, const cc_state *q, cc_state *dqdt,
                            cc_stream_t stream);

@@ -6,6 +6,7 @@
 
 #include "cc_kernels.hpp"
 #include "cc_stream.hpp"
+#include "cc_diffuse.hpp"
 
 namespace cc {
 
@@ -438,8 +439,13 @@ extern "C" cc_status cutcell_tendency(const cc_grid *grid, const cc_phys *phys, 
     if (!state_ok("cutcell_tendency", q) || !state_ok("cutcell_tendency", dq)) return CC_EINVAL;
     CC_REQUIRE(q->rho != dq->rho, "cutcell_tendency: output aliases input");
     hipStream_t s = (hipStream_t)stream;
-    if (prec == CC_F64) launch_stage<double, 1>(d, G, P, q, q, dq, 0.0, 0, nullptr, s, grid->tile);
-    else launch_stage<float, 1>(d, G, P, q, q, dq, 0.0, 0, nullptr, s, grid->tile);
+    if (prec == CC_F64) {
+        launch_stage<double, 1>(d, G, P, q, q, dq, 0.0, 0, nullptr, s, grid->tile);
+        launch_diffuse<double>(d, G, P, q, dq, 1.0, 0, s);
+    } else {
+        launch_stage<float, 1>(d, G, P, q, q, dq, 0.0, 0, nullptr, s, grid->tile);
+        launch_diffuse<float>(d, G, P, q, dq, 1.0, 0, s);
+    }
     return launch_status("cutcell_tendency");
 }
 
@@ -457,9 +463,11 @@ extern "C" cc_status cutcell_rk_stage(const cc_grid *grid, const cc_phys *phys, 
     hipStream_t s = (hipStream_t)stream;
     if (prec == CC_F64) {
         launch_stage<double, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s, grid->tile);
+        launch_diffuse<double>(d, G, P, qs, qo, cdt, final_stage, s);
         launch_diagnose<double>(d, G, P, qo, st, s);
     } else {
         launch_stage<float, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s, grid->tile);
+        launch_diffuse<float>(d, G, P, qs, qo, cdt, final_stage, s);
         launch_diagnose<float>(d, G, P, qo, st, s);
     }
     return launch_status("cutcell_rk_stage");
@@ -477,8 +485,13 @@ extern "C" cc_status cutcell_rk_update(const cc_grid *grid, const cc_phys *phys,
     CC_REQUIRE(qo->rho != qs->rho && qo->rho != qn->rho && qo->mu != qs->mu && qo->mu != qn->mu,
                "cutcell_rk_update: q_out must not alias q_n or q_s");
     hipStream_t s = (hipStream_t)stream;
-    if (prec == CC_F64) launch_stage<double, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s, grid->tile);
-    else launch_stage<float, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s, grid->tile);
+    if (prec == CC_F64) {
+        launch_stage<double, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s, grid->tile);
+        launch_diffuse<double>(d, G, P, qs, qo, cdt, final_stage, s);
+    } else {
+        launch_stage<float, 0>(d, G, P, qs, qn, qo, cdt, final_stage, st, s, grid->tile);
+        launch_diffuse<float>(d, G, P, qs, qo, cdt, final_stage, s);
+    }
     return launch_status("cutcell_rk_update");
 }
 
