@@ -29,7 +29,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f32|f64] [--w
                        [--no-cpu] [--no-ensemble] [--no-amr] [--no-second] [--cpu-sweep]
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -39,7 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-STAGE_SRC = os.path.join(ROOT, "paper_1509_02572_amd", "csrc", "cc_kernels.hpp")
+
 WORKLOADS = {
     "hemi512": "hemi512: 512x512x160 cells at dx=dy=dz=50 m, hemisphere R=1 km, N=0.01 1/s, U=10 m/s, "
                "no noise, dt=0.05 s",
@@ -53,7 +52,9 @@ def log(*a):
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(STAGE_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the stage kernels' sources (the traffic counters are valid only for the same code)."""
+    from paper_1509_02572_amd import autotune
+    return autotune.source_hash()
 
 
 def traffic_file(name: str) -> str:
