@@ -28,8 +28,9 @@
 
 typedef struct { int32_t nx, ny, nz, nsub; double dx, dy, dz, z0; } or_grid;  /* z0: bottom height */
 /* kdh, kdv: rates [1/s] of the fourth-order artificial diffusion in the horizontal and the vertical
- * (0: none) */
-typedef struct { double g, rd, cp, p0, theta0, bvn, u0, v0, kdh, kdv; } or_phys;
+ * (0: none); zsp, rsp: bottom height [m] of the sponge layer and its damping rate [1/s] at the lid
+ * (rsp = 0: none) */
+typedef struct { double g, rd, cp, p0, theta0, bvn, u0, v0, kdh, kdv, zsp, rsp; } or_phys;
 
 /* cell classes, merge directions and lattice-point classes (numeric codes are an interface) */
 enum { OR_SOLID = 0, OR_OPEN = 1, OR_ABSORBED = 2, OR_ORPHAN = 3 };
@@ -892,6 +893,22 @@ static void diffusion_point(const or_ctx *x, int I, int J, int K, double D[3])
     for (int c = 0; c < 3; ++c) D[c] = -acc[c];
 }
 
+/* ------------------------------------------------------------------------------------------ */
+/* Sponge layer below the rigid lid (Sec. 3: absorbing layer above 10 km after Klemp & Lilly).   */
+/* The paper names the layer but not its form.  Reading: Rayleigh damping towards the initial    */
+/* state, -tau(z) (q - q_ref), with tau rising from 0 at z = zsp to rsp at the lid as             */
+/* sin^2(pi/2 (z - zsp)/(ztop - zsp)).  It acts on (rho theta)' at group masters (cell centre     */
+/* height) and on the momentum perturbation rho u - rhobar_c (u0, v0, 0) at predicted points      */
+/* (lattice height); rho' is left alone, so the total mass stays conserved.                       */
+/* ------------------------------------------------------------------------------------------ */
+static double sponge_rate(const or_grid *g, const or_phys *ph, double z)
+{
+    double ztop = g->z0 + g->nz * g->dz;
+    if (ph->rsp == 0.0 || z <= ph->zsp || ph->zsp >= ztop) return 0.0;
+    double s = sin(0.5 * 3.14159265358979323846 * (z - ph->zsp) / (ztop - ph->zsp));
+    return ph->rsp * (s * s);
+}
+
 static void tendency_cell(const or_ctx *x, size_t c, const int64_t *head, const int64_t *next,
                           double dq[5], int *has_scalar, int *has_mom)
 {
@@ -915,6 +932,8 @@ static void tendency_cell(const or_ctx *x, size_t c, const int64_t *head, const 
             dq[0] += D[0];
             dq[1] += D[1];
         }
+        double tau = sponge_rate(g, x->ph, g->z0 + (k + 0.5) * g->dz);
+        if (tau != 0.0) dq[1] += -tau * x->q->rth[c];
         *has_scalar = 1;
     }
     if (G->vcls[c] == OR_PRED) {
@@ -925,6 +944,12 @@ static void tendency_cell(const or_ctx *x, size_t c, const int64_t *head, const 
             double D[3];
             diffusion_point(x, i, j, k, D);
             dq[2] += D[0]; dq[3] += D[1]; dq[4] += D[2];
+        }
+        double tau = sponge_rate(g, x->ph, g->z0 + k * g->dz);
+        if (tau != 0.0) {
+            dq[2] += -tau * mom_pert(x, c, k, 0);
+            dq[3] += -tau * mom_pert(x, c, k, 1);
+            dq[4] += -tau * mom_pert(x, c, k, 2);
         }
         *has_mom = 1;
     }

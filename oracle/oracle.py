@@ -38,7 +38,8 @@ class _Grid(C.Structure):
 
 
 class _Phys(C.Structure):
-    _fields_ = [(n, C.c_double) for n in ("g", "rd", "cp", "p0", "theta0", "bvn", "u0", "v0", "kdh", "kdv")]
+    _fields_ = [(n, C.c_double)
+                for n in ("g", "rd", "cp", "p0", "theta0", "bvn", "u0", "v0", "kdh", "kdv", "zsp", "rsp")]
 
 
 _DP = C.POINTER(C.c_double)
@@ -135,7 +136,8 @@ class Oracle:
         nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
         self.shape = (nx, ny, nz)
         self.grid = _Grid(nx, ny, nz, cfg.nsub, cfg.dx, cfg.dy, cfg.dz, cfg.z0)
-        self.phys = _Phys(cfg.g, cfg.rd, cfg.cp, cfg.p0, cfg.theta0, cfg.bvn, cfg.u0, cfg.v0, cfg.kdh, cfg.kdv)
+        self.phys = _Phys(cfg.g, cfg.rd, cfg.cp, cfg.p0, cfg.theta0, cfg.bvn, cfg.u0, cfg.v0, cfg.kdh, cfg.kdv,
+                           cfg.zsp, cfg.rsp)
         self.rhob, self.rthb, self.pb, self.thb = (np.zeros(nz) for _ in range(4))
         lib().or_base_state(C.byref(self.phys), nz, cfg.dz, cfg.z0, _p(self.rhob), _p(self.rthb), _p(self.pb),
                             _p(self.thb))

@@ -80,6 +80,8 @@ class Config:
     z0: float = 0.0  # height of the grid's bottom face (blocks of a refined grid); H is then relative to it
     kdh: float = 0.0  # rate of the fourth-order artificial diffusion in x and y [1/s] (0: none)
     kdv: float = 0.0  # the same in z
+    zsp: float = 0.0  # bottom height of the sponge layer below the lid [m]
+    rsp: float = 0.0  # damping rate of the sponge at the lid [1/s] (0: none)
 
     @property
     def ncells(self) -> int:

@@ -1,0 +1,129 @@
+"""Pins of the oracle's sponge layer below the lid (no GPU).
+
+The paper places an absorbing layer (after Klemp & Lilly) above 10 km to keep gravity waves from
+reflecting at the rigid lid (Sec. 3) but gives no formula.  The oracle reads it as Rayleigh damping
+towards the initial state, -tau(z) (q - q_ref), with tau rising from 0 at the layer's bottom to the
+given rate at the lid as sin^2 of the fractional height (see cutcell_oracle.c).  The pins:
+
+* a horizontally uniform shear of v over flat ground is a steady solution of the undamped equations
+  (every flux difference vanishes), so with the sponge each lattice level decays by exactly the
+  three-stage Runge-Kutta amplification factor 1 - x + x^2/2 - x^3/6, x = tau dt, per step; solving
+  for tau gives the profile, which must be 0 at and below the layer's bottom, a quarter, a half and
+  three quarters of the lid rate at a third, half and two thirds of the layer (sin^2 of pi/6, pi/4,
+  pi/3), and rise monotonically;
+* (rho theta)' at group masters and the momentum perturbation at predicted points feel -tau q, with
+  one tau per height shared by every field and column, zero below the layer; rho' feels nothing;
+* mass stays conserved over steps with the sponge over terrain, and the sponge changes the run.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1509_02572_amd import workloads as W
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build():
+    O.build(force=False)
+
+
+NZ, DZ = 24, 100.0
+ZSP = 1200.0  # lattice levels K = 12 .. 23 lie in the layer; K = 16, 18, 20 at 1/3, 1/2, 2/3 of it
+RSP = 0.02
+
+
+def _flat(**kw):
+    return W.Config("flatsponge", 8, 6, NZ, 100.0, 100.0, DZ, W.Hill("flat"), u0=10.0, v0=0.0, dt=0.5,
+                    zsp=ZSP, rsp=RSP, **kw)
+
+
+def _rk3_rate(r, dt):
+    """tau with (1 - x + x^2/2 - x^3/6) = r, x = tau dt (the real root near 0)."""
+    x = 0.0
+    for _ in range(60):  # Newton: the polynomial falls monotonically for x >= 0
+        f = 1.0 - x + x * x / 2.0 - x ** 3 / 6.0 - r
+        fp = -1.0 + x - x * x / 2.0
+        x -= f / fp
+    return x / dt
+
+
+def test_uniform_shear_decays_by_rk3_factor():
+    cfg = _flat()
+    o = O.Oracle(cfg).merge()
+    q0 = o.init_state()
+    pred = o.vcls == O.PRED
+    K = np.broadcast_to(np.arange(NZ)[None, None, :], o.shape)
+    q0.a["mv"][pred] = (1e-2 * (1.0 + K / NZ))[pred]
+    n = 8
+    q = o.run(q0, cfg.dt, n)
+    # every other field unchanged: the shear is steady without the sponge
+    for f in ("rho", "rth", "mw"):
+        assert np.abs(q.a[f][pred] - q0.a[f][pred]).max() <= 1e-14 * max(1.0, np.abs(q0.a[f]).max()), f
+    assert np.abs(q.a["mu"][pred] - q0.a["mu"][pred]).max() <= 1e-14 * np.abs(q0.a["mu"]).max()
+    ratio = (q.a["mv"][pred] / q0.a["mv"][pred]).reshape(cfg.nx, cfg.ny, NZ - 1)
+    # one ratio per level, the same in every column
+    assert np.ptp(ratio, axis=(0, 1)).max() <= 1e-15
+    tau = np.array([_rk3_rate(ratio[0, 0, K - 1] ** (1.0 / n), cfg.dt) for K in range(1, NZ)])
+    zK = np.arange(1, NZ) * DZ
+    below = zK <= ZSP
+    assert (ratio[0, 0, below[:]] == 1.0).all()  # bitwise untouched
+    assert np.all(np.abs(tau[below]) <= 1e-13)
+    at = {16: 0.25, 18: 0.5, 20: 0.75}
+    for Kl, frac in at.items():
+        assert abs(tau[Kl - 1] - frac * RSP) <= 1e-9 * RSP, (Kl, tau[Kl - 1])
+    assert np.all(np.diff(tau[~below]) > 0)
+    assert tau[-1] < RSP
+
+
+def test_sponge_term_is_minus_tau_times_perturbation():
+    cfg = W.get("hemi_tiny").replace(zsp=700.0, rsp=RSP)
+    o = O.Oracle(cfg).merge()
+    rs = W.random_state(cfg, 3)
+    q = O.State(None, rs)
+    a = o.tendency(q)
+    b = O.Oracle(cfg.replace(rsp=0.0)).merge().tendency(q)
+    nz = cfg.nz
+    masters = (o.cls == O.OPEN) | (o.cls == O.ORPHAN)
+    pred = o.vcls == O.PRED
+    K = np.broadcast_to(np.arange(nz)[None, None, :], o.shape)
+    assert np.array_equal(a["rho"], b["rho"])
+    rbc = np.zeros(nz)
+    rbc[1:] = 0.5 * (o.rhob[:-1] + o.rhob[1:])
+    pert = {"rth": q.a["rth"], "mu": q.a["mu"] - rbc[K] * cfg.u0, "mv": q.a["mv"] - rbc[K] * cfg.v0,
+            "mw": q.a["mw"]}
+    taus = {}
+    for f, m, zc in (("rth", masters, (K + 0.5) * cfg.dz), ("mu", pred, K * cfg.dz), ("mv", pred, K * cfg.dz),
+                     ("mw", pred, K * cfg.dz)):
+        d = (a[f] - b[f])[m]
+        p = pert[f][m]
+        z = zc[m]
+        lo = z <= cfg.zsp
+        assert np.abs(d[lo]).max() <= 1e-13 * np.abs(b[f][m]).max(), f
+        t = -d[~lo] / p[~lo]
+        for zz in np.unique(z[~lo]):
+            sel = z[~lo] == zz
+            taus.setdefault(float(zz), []).append(t[sel])
+    # one tau per height for every field and column, rising with height
+    hs = sorted(taus)
+    vals = []
+    for zz in hs:
+        t = np.concatenate(taus[zz])
+        assert np.ptp(t) <= 1e-9 * RSP, zz
+        vals.append(t.mean())
+    assert np.all(np.diff(vals) > 0) and vals[-1] < RSP
+    # half the lid rate at half the layer: the lattice level at z = 1050 m lies midway in [700, 1400]
+    ztop = cfg.nz * cfg.dz
+    zmid = 0.5 * (cfg.zsp + ztop)
+    assert zmid in taus and abs(vals[hs.index(zmid)] - 0.5 * RSP) <= 1e-9 * RSP
+
+
+def test_mass_conserved_with_sponge():
+    cfg = W.get("hemi_tiny").replace(zsp=600.0, rsp=0.05)
+    o = O.Oracle(cfg).merge()
+    q0 = o.init_state(W.theta_noise(cfg.replace(noise_sigma=0.5, seed=4)))
+    r0 = o.reduce(q0)
+    q1 = o.run(q0, cfg.dt, 20)
+    r1 = o.reduce(q1)
+    assert abs(r1[0] - r0[0]) <= 1e-12 * r0[2]
+    q2 = O.Oracle(cfg.replace(rsp=0.0)).merge().run(q0, cfg.dt, 20)
+    assert np.abs(q1["rth"] - q2["rth"]).max() > 0
