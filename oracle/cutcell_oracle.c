@@ -1055,6 +1055,19 @@ void or_face_flux(const or_grid *g, const or_phys *ph, const or_geom *G, const d
 /* groups + kinetic energy of predicted points (not conserved by the scheme).  Summed in linear */
 /* index order.                                                                                 */
 /* ------------------------------------------------------------------------------------------ */
+/* compensated (Neumaier) running sum: the sums below run over every cell of a grid (tens of
+ * millions of terms of one sign), where a plain running sum loses accuracy in proportion to the
+ * number of terms; with the correction term the result is within a few rounding errors of the
+ * exact sum whatever the count */
+typedef struct { double s, c; } or_ksum;
+static inline void ksum_add(or_ksum *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+
 void or_reduce(const or_grid *g, const or_phys *ph, const or_geom *G, const double *rhob,
                const double *rthb, const double *pb, const or_state *q, double out[4])
 {
@@ -1062,7 +1075,7 @@ void or_reduce(const or_grid *g, const or_phys *ph, const or_geom *G, const doub
     size_t n = (size_t)g->nx * g->ny * g->nz;
     double dV = g->dx * g->dy * g->dz;
     double gam = ph->cp / (ph->cp - ph->rd);
-    double mp = 0.0, tp = 0.0, mt = 0.0, e = 0.0;
+    or_ksum mp = {0.0, 0.0}, tp = {0.0, 0.0}, mt = {0.0, 0.0}, e = {0.0, 0.0};
     for (size_t c = 0; c < n; ++c) {
         int k = (int)(c % g->nz);
         int j = (int)((c / g->nz) % g->ny);
@@ -1072,18 +1085,18 @@ void or_reduce(const or_grid *g, const or_phys *ph, const or_geom *G, const doub
             double rho = rhob[k] + q->rho[c];
             double p = pb[k] + eos_pprime(q->rth[c], rthb[k], pb[k], gam);
             double z = g->z0 + ((double)k + 0.5) * g->dz;
-            mp += vg * q->rho[c];
-            tp += vg * q->rth[c];
-            mt += vg * rho;
-            e += vg * (p / (gam - 1.0) + rho * ph->g * z);
+            ksum_add(&mp, vg * q->rho[c]);
+            ksum_add(&tp, vg * q->rth[c]);
+            ksum_add(&mt, vg * rho);
+            ksum_add(&e, vg * (p / (gam - 1.0) + rho * ph->g * z));
         }
         if (G->vcls[c] == OR_PRED) {
             double rc = rho_corner(&x, i, j, k);
             double u = q->mu[c] / rc, v = q->mv[c] / rc, w = q->mw[c] / rc;
-            e += dV * 0.5 * rc * (u * u + v * v + w * w);
+            ksum_add(&e, dV * 0.5 * rc * (u * u + v * v + w * w));
         }
     }
-    out[0] = mp; out[1] = tp; out[2] = mt; out[3] = e;
+    out[0] = mp.s + mp.c; out[1] = tp.s + tp.c; out[2] = mt.s + mt.c; out[3] = e.s + e.c;
 }
 
 /* nsteps full WS-RK3 steps; q is advanced in place using two scratch states (the group member
