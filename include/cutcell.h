@@ -98,6 +98,13 @@ typedef struct {
                              (Sec. 2.1 D terms; 0: none; single grids only).  The 2-dx mode of a field
                              decays at 16 kdh per horizontal direction (16 kdv vertically); the
                              explicit stage needs dt (32 kdh + 16 kdv) below about 2.5 */
+    double zsp, rsp;      /* sponge layer below the lid (Sec. 3, absorbing layer after Klemp & Lilly):
+                             bottom height zsp [m, same datum as z0] and damping rate rsp [1/s] at the
+                             lid (0: none; single grids only).  Rayleigh damping -tau(z) (q - q_ref)
+                             with tau = rsp sin^2(pi/2 (z - zsp)/(ztop - zsp)) above zsp, ztop =
+                             z0 + nz dz, on (rho theta)' at group masters (cell-centre height) and on
+                             rho u - rhobar_c (u0, v0, 0) at predicted points (lattice height); rho'
+                             is not damped, so mass stays conserved.  Needs dt rsp below about 2.5 */
 } cc_phys;
 
 /* Geometry and merge map (device arrays, caller-allocated). */
@@ -214,8 +221,9 @@ cc_status cutcell_diagnose(const cc_grid *grid, const cc_phys *phys, const cc_ge
  * the third difference of the four values straddling it, or -4 x their first difference where an
  * outer one is missing (solid cell, point not predicted, ground, lid: the second-order term of
  * Sec. 2.4), zero through closed faces; scalars with apertures and group volumes (conservative),
- * momentum as the perturbation rho u - rhobar_c (u0, v0, 0).  dqdt: same element type as q; scalars
- * at group masters, momentum at predicted points, zero elsewhere. */
+ * momentum as the perturbation rho u - rhobar_c (u0, v0, 0); and the sponge's Rayleigh damping when
+ * phys->rsp is non-zero (see cc_phys).  dqdt: same element type as q; scalars at group masters,
+ * momentum at predicted points, zero elsewhere. */
 cc_status cutcell_tendency(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
                            const double *base, cc_prec prec, const cc_state *q, cc_state *dqdt,
                            cc_stream_t stream);

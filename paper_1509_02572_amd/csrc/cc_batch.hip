@@ -684,8 +684,9 @@ bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, i
         const cc_block &b = B[ids[m]];
         Dims d; Geo G; Phy P;
         if (!make_views(what, &b.grid, &b.phys, &b.geom, b.base, prec, d, G, P)) return false;
-        if (P.kdh != 0.0 || P.kdv != 0.0) {
-            set_error("%s: block %d: the artificial diffusion runs on single grids only", what, ids[m]);
+        if (P.kdh != 0.0 || P.kdv != 0.0 || P.rsp != 0.0) {
+            set_error("%s: block %d: the artificial diffusion and the sponge run on single grids only", what,
+                      ids[m]);
             return false;
         }
         for (int r = 0; r < 3; ++r) {

@@ -1,18 +1,26 @@
-// Fourth-order artificial diffusion of the prognostic fields (the D terms of every equation of
-// Sec. 2.1; 5-point stencils per direction, Sec. 2.2; a second-order term where the stencil lacks
-// fluid neighbours, with the terrain as boundary, Sec. 2.4).
+// Explicit source terms applied after the update: the fourth-order artificial diffusion of the
+// prognostic fields (the D terms of every equation of Sec. 2.1; 5-point stencils per direction,
+// Sec. 2.2; a second-order term where the stencil lacks fluid neighbours, with the terrain as
+// boundary, Sec. 2.4) and the sponge layer below the lid (Sec. 3).
 //
-// Flux form.  Through a face between two cells (or lattice points) L and U along an axis, the flux
-// is the third difference of the four values straddling it, phi(U+1) - 3 phi(U) + 3 phi(L) - phi(L-1),
-// or -4 (phi(U) - phi(L)) when one of the two outer values is missing (a solid cell, a point that is
-// not predicted, beyond the ground or the lid), and zero through a closed face; a point's term is
-// -rate x (outgoing - incoming flux).  In the interior this is -rate x the 5-point fourth difference.
-// Scalars use group values (the master's), the faces' apertures and the group volume, as the
-// advective fluxes do, and so stay conserved; momentum uses the perturbation from the reference
-// flow, rho u - rhobar_c (u0, v0, 0), at predicted points.  Evaluated in double in the order the
-// CPU reference uses: members of a group from the master along gnext, faces -x,+x,-y,+y,-z,+z, axes
-// x, y, z for momentum.  Launched after the update (or tendency) kernel, which it follows on the
-// stream: q_out += scale x D(q_s).
+// Diffusion, flux form.  Through a face between two cells (or lattice points) L and U along an axis,
+// the flux is the third difference of the four values straddling it,
+// phi(U+1) - 3 phi(U) + 3 phi(L) - phi(L-1), or -4 (phi(U) - phi(L)) when one of the two outer values
+// is missing (a solid cell, a point that is not predicted, beyond the ground or the lid), and zero
+// through a closed face; a point's term is -rate x (outgoing - incoming flux).  In the interior this
+// is -rate x the 5-point fourth difference.  Scalars use group values (the master's), the faces'
+// apertures and the group volume, as the advective fluxes do, and so stay conserved; momentum uses
+// the perturbation from the reference flow, rho u - rhobar_c (u0, v0, 0), at predicted points.
+// Evaluated in double in the order the CPU reference uses: members of a group from the master along
+// gnext, faces -x,+x,-y,+y,-z,+z, axes x, y, z for momentum.
+//
+// Sponge: Rayleigh damping -tau(z) q of (rho theta)' at group masters (cell-centre height) and of the
+// momentum perturbation at predicted points (lattice height), tau = rsp sin^2(pi/2 (z - zsp)/(ztop -
+// zsp)) above zsp; rho' is not damped.
+//
+// Launched after the update (or tendency) kernel, which it follows on the stream:
+// q_out += scale x (D(q_s) + S(q_s)).  With the diffusion off, only the levels that reach into the
+// sponge are launched.
 #pragma clang fp contract(off)
 
 #include "cc_diffuse.hpp"
@@ -85,21 +93,32 @@ __device__ void lattice_diff_flux(const Dims &d, const Geo &G, const Phy &P, con
     }
 }
 
+// sponge rate at height z: 0 below the layer
+__device__ __forceinline__ double sponge_tau(const Phy &P, double z)
+{
+    if (P.rsp == 0.0 || z <= P.zsp || P.zsp >= P.ztop) return 0.0;
+    const double s = sin(0.5 * 3.14159265358979323846 * (z - P.zsp) / (P.ztop - P.zsp));
+    return P.rsp * (s * s);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_diffuse(Dims d, Geo G, Phy P, SIn<T> q, SOut<T> qo, double scale,
-                                                 int final_stage)
+                                                 int final_stage, int kmin)
 {
+    const int nk = d.nz - kmin;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)d.nx * d.ny * d.nz) return;
-    const int k = (int)(t % d.nz);
-    const int64_t col = t / d.nz;
+    if (t >= (int64_t)d.nx * d.ny * nk) return;
+    const int k = kmin + (int)(t % nk);
+    const int64_t col = t / nk;
     const int j = (int)(col % d.ny), i = (int)(col / d.ny);
     const int64_t c = col * d.nzs + k;
+    const bool diff = P.kdh != 0.0 || P.kdv != 0.0;
     // ---- scalars at a group master ----
     const int8_t cl = G.cls[c];
-    if (cl == CC_OPEN || cl == CC_ORPHAN) {
+    const double tau_c = sponge_tau(P, d.z0 + (k + 0.5) * d.dz);
+    if ((cl == CC_OPEN || cl == CC_ORPHAN) && (diff || tau_c != 0.0)) {
         double acc[2] = {0.0, 0.0};
-        int64_t mem = c;
+        int64_t mem = diff ? c : -1;
         for (int guard = 0; mem >= 0 && guard <= CC_MAX_GROUP; ++guard) {
             int mi, mj, mk;
             unidx(d, mem, mi, mj, mk);
@@ -120,7 +139,9 @@ __global__ void __launch_bounds__(256) k_diffuse(Dims d, Geo G, Phy P, SIn<T> q,
             mem = G.gnext[mem];
         }
         const double vg = G.Vgroup[c];
-        const double D0 = -acc[0] / vg, D1 = -acc[1] / vg;
+        const double D0 = diff ? -acc[0] / vg : 0.0;
+        double D1 = diff ? -acc[1] / vg : 0.0;
+        if (tau_c != 0.0) D1 += -tau_c * (double)q.rth[c];
         double x0 = (double)qo.rho[c], x1 = (double)qo.rth[c];
         const bool lo = final_stage && qo.rho_lo;
         if (lo) {
@@ -138,18 +159,22 @@ __global__ void __launch_bounds__(256) k_diffuse(Dims d, Geo G, Phy P, SIn<T> q,
         }
     }
     // ---- momentum at a predicted point ----
-    if (G.vcls[c] == CC_PRED) {
+    const double tau_p = sponge_tau(P, d.z0 + k * d.dz);
+    if (G.vcls[c] == CC_PRED && (diff || tau_p != 0.0)) {
         double acc[3] = {0.0, 0.0, 0.0};
-        for (int a = 0; a < 3; ++a) {
+        for (int a = 0; diff && a < 3; ++a) {
             const double kr = a == 2 ? P.kdv : P.kdh;
             double Fp[3], Fm[3];
             lattice_diff_flux<T>(d, G, P, q, a, i, j, k, Fp);
             lattice_diff_flux<T>(d, G, P, q, a, i - (a == 0), j - (a == 1), k - (a == 2), Fm);
             for (int cc = 0; cc < 3; ++cc) acc[cc] += kr * (Fp[cc] - Fm[cc]);
         }
-        qo.mu[c] = (T)((double)qo.mu[c] + scale * -acc[0]);
-        qo.mv[c] = (T)((double)qo.mv[c] + scale * -acc[1]);
-        qo.mw[c] = (T)((double)qo.mw[c] + scale * -acc[2]);
+        double S[3] = {-acc[0], -acc[1], -acc[2]};
+        if (tau_p != 0.0)
+            for (int cc = 0; cc < 3; ++cc) S[cc] += -tau_p * mom_pert(P, q, c, k, cc);
+        qo.mu[c] = (T)((double)qo.mu[c] + scale * S[0]);
+        qo.mv[c] = (T)((double)qo.mv[c] + scale * S[1]);
+        qo.mw[c] = (T)((double)qo.mw[c] + scale * S[2]);
     }
 }
 
@@ -157,10 +182,18 @@ template <typename T>
 void launch_diffuse(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, cc_state *qo, double scale,
                     int final_stage, hipStream_t s)
 {
-    if (P.kdh == 0.0 && P.kdv == 0.0) return;
-    const int64_t n = (int64_t)d.nx * d.ny * d.nz;
+    const bool diff = P.kdh != 0.0 || P.kdv != 0.0;
+    const bool sponge = P.rsp != 0.0 && P.zsp < P.ztop;
+    if (!diff && !sponge) return;
+    int kmin = 0;
+    if (!diff) {  // levels below the layer feel nothing: start one level under the first one reaching in
+        const double kz = std::floor((P.zsp - d.z0) / d.dz) - 1.0;
+        kmin = kz <= 0.0 ? 0 : (kz >= d.nz ? d.nz : (int)kz);
+        if (kmin >= d.nz) return;
+    }
+    const int64_t n = (int64_t)d.nx * d.ny * (d.nz - kmin);
     hipLaunchKernelGGL(k_diffuse<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, G, P, sin_of<T>(qs),
-                       sout_of<T>(qo), scale, final_stage);
+                       sout_of<T>(qo), scale, final_stage, kmin);
 }
 
 template void launch_diffuse<float>(const Dims &, const Geo &, const Phy &, const cc_state *, cc_state *, double,

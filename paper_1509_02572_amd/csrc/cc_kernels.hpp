@@ -54,6 +54,7 @@ struct Phy {
     const double *rhobc;                   // mean base density of levels K-1, K at lattice level K [nz]
     double g, gam, ux, vy, dV, idV, idx, idy, idz;
     double u0, v0, kdh, kdv;               // inflow and diffusion rates (always the caller's values)
+    double zsp, rsp, ztop;                 // sponge: bottom height, rate at the lid, lid height
     double binom[EOS_TERMS];               // (1+x)^gamma - 1 = sum_n binom[n-1] x^n
     float binomf[EOS_TERMS];
 };
@@ -1461,6 +1462,11 @@ inline bool make_views(const char *what, const cc_grid *grid, const cc_phys *phy
     P.vy = prec == CC_F32_PERT ? phys->v0 : 0.0;
     P.u0 = phys->u0; P.v0 = phys->v0; P.kdh = phys->kdh; P.kdv = phys->kdv;
     if (!(P.kdh >= 0.0 && P.kdv >= 0.0)) { set_error("%s: negative diffusion rate", what); return false; }
+    P.zsp = phys->zsp; P.rsp = phys->rsp; P.ztop = d.z0 + d.nz * d.dz;
+    if (!(P.rsp >= 0.0) || !std::isfinite(P.rsp) || (P.rsp != 0.0 && !std::isfinite(P.zsp))) {
+        set_error("%s: invalid sponge (rate %g, bottom %g)", what, P.rsp, P.zsp);
+        return false;
+    }
     P.dV = d.dx * d.dy * d.dz;
     P.idV = 1.0 / P.dV;
     P.idx = 1.0 / d.dx; P.idy = 1.0 / d.dy; P.idz = 1.0 / d.dz;

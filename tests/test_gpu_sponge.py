@@ -1,0 +1,110 @@
+"""GPU sponge layer below the lid (Rayleigh damping towards the initial state, sin^2 rise to the lid
+rate) against the FP64 CPU oracle: tendency and 100-step states in FP64 at 1e-12, alone and together
+with the artificial diffusion; the FP32 form at 1e-5 (L2) with mass conserved to 1e-12; the launch
+that covers only the levels reaching into the layer; batches refuse a non-zero rate."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1509_02572_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CC = None
+RSP = 0.05  # 1/s; dt RSP stays far inside the stable range
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    global CC
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1509_02572_amd import cutcell
+    CC = cutcell
+    CC.lib()
+    O.build(force=False)
+
+
+# bottom heights: on a cell face (700 m), between faces (1234 m, so the sponge-only launch starts
+# mid-grid), below the ground (the whole column damped)
+CASES = {
+    "hemi_tiny_700": lambda: W.get("hemi_tiny").replace(zsp=700.0, rsp=RSP),
+    "bell_small_1234": lambda: W.get("bell_small").replace(zsp=1234.0, rsp=RSP),
+    "flat_all": lambda: W.Config("flat", 24, 20, 16, 100.0, 100.0, 50.0, W.Hill("flat"), u0=6.0, v0=1.5,
+                                 dt=0.05, zsp=-100.0, rsp=RSP),
+    "hemi_tiny_diffusion": lambda: W.get("hemi_tiny").replace(zsp=700.0, rsp=RSP, kdh=0.08, kdv=0.05),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_f64_tendency_with_sponge(name):
+    cfg = CASES[name]()
+    print(f"case sponge tendency {name}", flush=True)
+    o = O.Oracle(cfg).merge()
+    dom = CC.Domain(cfg, "f64")
+    rs = W.random_state(cfg, 29)
+    qo = O.State(None, rs)
+    o.diagnose(qo)
+    qg = dom.new_state()
+    for f in O.FIELDS:
+        qg.t[f].copy_(dom.pad(rs[f]))
+    dom.diagnose(qg)
+    dref = o.tendency(qo)
+    dgot = dom.state_numpy(dom.tendency(qg))
+    # the sponge is active in the case: the tendency differs from one without it
+    dnos = O.Oracle(cfg.replace(rsp=0.0)).merge().tendency(qo)
+    assert np.abs(dref["rth"] - dnos["rth"]).max() > 0
+    pred, mast = o.vcls == O.PRED, (o.cls == O.OPEN) | (o.cls == O.ORPHAN)
+    for f, m in (("rho", mast), ("rth", mast), ("mu", pred), ("mv", pred), ("mw", pred)):
+        scale = np.abs(dref[f][m]).max()
+        err = np.abs(dgot[f] - dref[f])[m].max() / scale
+        assert err <= 1e-12, (f, err)
+
+
+@pytest.mark.parametrize("name", ["hemi_tiny_700", "bell_small_1234", "hemi_tiny_diffusion"])
+def test_f64_state_with_sponge_after_100_steps(name):
+    cfg = CASES[name]()
+    print(f"case sponge f64 100 steps {name}", flush=True)
+    o = O.Oracle(cfg).merge()
+    noise = W.theta_noise(cfg.replace(noise_sigma=0.5, seed=5))
+    ref = o.run(o.init_state(noise), cfg.dt, 100)
+    dom = CC.Domain(cfg, "f64")
+    got = dom.state_numpy(dom.run(dom.init_state(noise), cfg.dt, 100))
+    nonsolid, pred = o.cls != O.SOLID, o.vcls == O.PRED
+    for f, m in (("rho", nonsolid), ("rth", nonsolid), ("mu", pred), ("mv", pred), ("mw", pred),
+                 ("mu", ~pred), ("mw", ~pred)):
+        scale = max(np.abs(ref[f][m]).max(), 1e-300)
+        err = np.abs(got[f] - ref[f])[m].max() / scale
+        assert err <= 1e-12, (f, err)
+    assert not dom.check()[:5].any()
+
+
+def test_f32_with_sponge_after_100_steps():
+    cfg = CASES["hemi_tiny_700"]()
+    print("case sponge f32 100 steps hemi_tiny_700", flush=True)
+    o = O.Oracle(cfg).merge()
+    noise = W.theta_noise(cfg.replace(noise_sigma=0.5, seed=5))
+    ref = o.run(o.init_state(noise), cfg.dt, 100)
+    dom = CC.Domain(cfg, "f32")
+    q = dom.init_state(noise)
+    r0 = dom.reduce(q)
+    out = dom.run(q, cfg.dt, 100)
+    r1 = dom.reduce(out)
+    raw = dom.state_numpy(out)
+    pred, nonsolid = o.vcls == O.PRED, o.cls != O.SOLID
+    rbc = np.zeros(cfg.nz)
+    rbc[1:] = 0.5 * (o.rhob[:-1] + o.rhob[1:])
+    full = dict(raw)
+    for f, u in (("mu", cfg.u0), ("mv", cfg.v0)):
+        full[f] = np.where(pred, raw[f] + rbc[None, None, :] * u, raw[f] + u)
+    for f, m in (("rho", nonsolid), ("rth", nonsolid), ("mu", pred), ("mv", pred), ("mw", pred)):
+        e = np.linalg.norm((full[f] - ref[f])[m]) / np.linalg.norm(ref[f][m])
+        assert e <= 1e-5, (f, e)
+    assert abs(r1[0] - r0[0]) <= 1e-12 * r0[2]
+
+
+def test_batch_refuses_sponge():
+    cfg = CASES["hemi_tiny_700"]()
+    dom = CC.Domain(cfg, "f64", side_stream=False)
+    with pytest.raises(RuntimeError, match="single grids"):
+        CC.Batch([dom], [dom.init_state()])
