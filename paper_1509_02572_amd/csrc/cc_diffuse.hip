@@ -12,7 +12,10 @@
 // apertures and the group volume, as the advective fluxes do, and so stay conserved; momentum uses
 // the perturbation from the reference flow, rho u - rhobar_c (u0, v0, 0), at predicted points.
 // Evaluated in double in the order the CPU reference uses: members of a group from the master along
-// gnext, faces -x,+x,-y,+y,-z,+z, axes x, y, z for momentum.
+// gnext, faces -x,+x,-y,+y,-z,+z, axes x, y, z for momentum.  Where every cell and lattice point
+// within two of the centre is regular (from two levels above the band height to three below the lid)
+// the flux form collapses to the 5-point fourth difference, which a launch of its own evaluates
+// directly; the flux form covers the levels below and above.
 //
 // Sponge: Rayleigh damping -tau(z) q of (rho theta)' at group masters (cell-centre height) and of the
 // momentum perturbation at predicted points (lattice height), tau = rsp sin^2(pi/2 (z - zsp)/(ztop -
@@ -101,46 +104,90 @@ __device__ __forceinline__ double sponge_tau(const Phy &P, double z)
     return P.rsp * (s * s);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_diffuse(Dims d, Geo G, Phy P, SIn<T> q, SOut<T> qo, double scale,
-                                                 int final_stage, int kmin)
+// interior form of the fourth difference along the three axes: -(kdh (d4x + d4y) + kdv d4z) of the
+// values v(o) at offsets o from the centre (the flux form collapses to it where every cell and point
+// within two of the centre is regular)
+template <typename V>
+__device__ __forceinline__ double interior_d4(const Phy &P, V v, int64_t c, const int64_t xm[2], const int64_t xp[2],
+                                              const int64_t ym[2], const int64_t yp[2])
 {
-    const int nk = d.nz - kmin;
+    const double v0 = v(c, 0);
+    const double dx4 = (((v(xp[1], 0) - 4.0 * v(xp[0], 0)) + 6.0 * v0) - 4.0 * v(xm[0], 0)) + v(xm[1], 0);
+    const double dy4 = (((v(yp[1], 0) - 4.0 * v(yp[0], 0)) + 6.0 * v0) - 4.0 * v(ym[0], 0)) + v(ym[1], 0);
+    const double dz4 = (((v(c + 2, 2) - 4.0 * v(c + 1, 1)) + 6.0 * v0) - 4.0 * v(c - 1, -1)) + v(c - 2, -2);
+    return -(P.kdh * (dx4 + dy4) + P.kdv * dz4);
+}
+
+// FAST: levels [k0, k1) where every cell and lattice point within two of the centre is regular
+// (k >= band height + 2, k <= nz - 3), interior stencils; otherwise the flux form over levels
+// [k0, k1) and [kt, nz).
+template <typename T, bool FAST>
+__global__ void __launch_bounds__(256) k_diffuse(Dims d, Geo G, Phy P, SIn<T> q, SOut<T> qo, double scale,
+                                                 int final_stage, int k0, int k1, int kt)
+{
+    const int nlo = k1 - k0, nk = nlo + (FAST ? 0 : d.nz - kt);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)d.nx * d.ny * nk) return;
-    const int k = kmin + (int)(t % nk);
+    const int l = (int)(t % nk);
+    const int k = l < nlo ? k0 + l : kt + (l - nlo);
     const int64_t col = t / nk;
     const int j = (int)(col % d.ny), i = (int)(col / d.ny);
     const int64_t c = col * d.nzs + k;
     const bool diff = P.kdh != 0.0 || P.kdv != 0.0;
+    // the flux-form launch takes the interior form too where the column band tops show every cell and
+    // point within two of the centre regular (most columns away from the terrain)
+    bool inner = FAST;
+    if (!FAST && diff && k >= 2 && k <= d.nz - 3) {
+        const int64_t nc = (int64_t)d.nx * d.ny;
+        auto top = [&](int ii, int jj) {
+            const int64_t cc = (int64_t)wrap(ii, d.nx) * d.ny + wrap(jj, d.ny);
+            return max(G.colk[cc], G.colk[nc + cc]);
+        };
+        inner = k - 2 >= top(i, j) && k >= top(i - 1, j) && k >= top(i - 2, j) && k >= top(i + 1, j) &&
+                k >= top(i + 2, j) && k >= top(i, j - 1) && k >= top(i, j - 2) && k >= top(i, j + 1) &&
+                k >= top(i, j + 2);
+    }
+    int64_t xm[2], xp[2], ym[2], yp[2];
+    if (inner) {
+        xm[0] = cidx(d, i - 1, j, k); xm[1] = cidx(d, i - 2, j, k);
+        xp[0] = cidx(d, i + 1, j, k); xp[1] = cidx(d, i + 2, j, k);
+        ym[0] = cidx(d, i, j - 1, k); ym[1] = cidx(d, i, j - 2, k);
+        yp[0] = cidx(d, i, j + 1, k); yp[1] = cidx(d, i, j + 2, k);
+    }
     // ---- scalars at a group master ----
     const int8_t cl = G.cls[c];
     const double tau_c = sponge_tau(P, d.z0 + (k + 0.5) * d.dz);
     if ((cl == CC_OPEN || cl == CC_ORPHAN) && (diff || tau_c != 0.0)) {
-        double acc[2] = {0.0, 0.0};
-        int64_t mem = diff ? c : -1;
-        for (int guard = 0; mem >= 0 && guard <= CC_MAX_GROUP; ++guard) {
-            int mi, mj, mk;
-            unidx(d, mem, mi, mj, mk);
-            for (int f = 0; f < 6; ++f) {
-                const int a = f >> 1, plus = f & 1;
-                const int fi = mi + (a == 0 && plus), fj = mj + (a == 1 && plus), fk = mk + (a == 2 && plus);
-                if (a == 2 && (fk <= 0 || fk >= d.nz)) continue;
-                const int64_t fu = cidx(d, fi, fj, fk);
-                const double A = a == 0 ? G.Ax[fu] : (a == 1 ? G.Ay[fu] : G.Az[fu]);
-                const double kr = a == 2 ? P.kdv : P.kdh;
-                double F[2];
-                scalar_diff_flux<T>(d, G, q, a, fi, fj, fk, F);
-                for (int w = 0; w < 2; ++w) {
-                    const double term = (kr * A) * F[w];
-                    acc[w] = plus ? acc[w] + term : acc[w] - term;
+        double D0 = 0.0, D1 = 0.0;
+        if (inner) {
+            D0 = interior_d4(P, [&](int64_t p, int) { return (double)q.rho[p]; }, c, xm, xp, ym, yp);
+            D1 = interior_d4(P, [&](int64_t p, int) { return (double)q.rth[p]; }, c, xm, xp, ym, yp);
+        } else if (diff) {
+            double acc[2] = {0.0, 0.0};
+            int64_t mem = c;
+            for (int guard = 0; mem >= 0 && guard <= CC_MAX_GROUP; ++guard) {
+                int mi, mj, mk;
+                unidx(d, mem, mi, mj, mk);
+                for (int f = 0; f < 6; ++f) {
+                    const int a = f >> 1, plus = f & 1;
+                    const int fi = mi + (a == 0 && plus), fj = mj + (a == 1 && plus), fk = mk + (a == 2 && plus);
+                    if (a == 2 && (fk <= 0 || fk >= d.nz)) continue;
+                    const int64_t fu = cidx(d, fi, fj, fk);
+                    const double A = a == 0 ? G.Ax[fu] : (a == 1 ? G.Ay[fu] : G.Az[fu]);
+                    const double kr = a == 2 ? P.kdv : P.kdh;
+                    double F[2];
+                    scalar_diff_flux<T>(d, G, q, a, fi, fj, fk, F);
+                    for (int w = 0; w < 2; ++w) {
+                        const double term = (kr * A) * F[w];
+                        acc[w] = plus ? acc[w] + term : acc[w] - term;
+                    }
                 }
+                mem = G.gnext[mem];
             }
-            mem = G.gnext[mem];
+            const double vg = G.Vgroup[c];
+            D0 = -acc[0] / vg;
+            D1 = -acc[1] / vg;
         }
-        const double vg = G.Vgroup[c];
-        const double D0 = diff ? -acc[0] / vg : 0.0;
-        double D1 = diff ? -acc[1] / vg : 0.0;
         if (tau_c != 0.0) D1 += -tau_c * (double)q.rth[c];
         double x0 = (double)qo.rho[c], x1 = (double)qo.rth[c];
         const bool lo = final_stage && qo.rho_lo;
@@ -161,15 +208,22 @@ __global__ void __launch_bounds__(256) k_diffuse(Dims d, Geo G, Phy P, SIn<T> q,
     // ---- momentum at a predicted point ----
     const double tau_p = sponge_tau(P, d.z0 + k * d.dz);
     if (G.vcls[c] == CC_PRED && (diff || tau_p != 0.0)) {
-        double acc[3] = {0.0, 0.0, 0.0};
-        for (int a = 0; diff && a < 3; ++a) {
-            const double kr = a == 2 ? P.kdv : P.kdh;
-            double Fp[3], Fm[3];
-            lattice_diff_flux<T>(d, G, P, q, a, i, j, k, Fp);
-            lattice_diff_flux<T>(d, G, P, q, a, i - (a == 0), j - (a == 1), k - (a == 2), Fm);
-            for (int cc = 0; cc < 3; ++cc) acc[cc] += kr * (Fp[cc] - Fm[cc]);
+        double S[3] = {0.0, 0.0, 0.0};
+        if (inner) {
+            for (int cc = 0; cc < 3; ++cc)
+                S[cc] = interior_d4(P, [&](int64_t p, int dk) { return mom_pert(P, q, p, k + dk, cc); }, c, xm, xp,
+                                    ym, yp);
+        } else if (diff) {
+            double acc[3] = {0.0, 0.0, 0.0};
+            for (int a = 0; a < 3; ++a) {
+                const double kr = a == 2 ? P.kdv : P.kdh;
+                double Fp[3], Fm[3];
+                lattice_diff_flux<T>(d, G, P, q, a, i, j, k, Fp);
+                lattice_diff_flux<T>(d, G, P, q, a, i - (a == 0), j - (a == 1), k - (a == 2), Fm);
+                for (int cc = 0; cc < 3; ++cc) acc[cc] += kr * (Fp[cc] - Fm[cc]);
+            }
+            for (int cc = 0; cc < 3; ++cc) S[cc] = -acc[cc];
         }
-        double S[3] = {-acc[0], -acc[1], -acc[2]};
         if (tau_p != 0.0)
             for (int cc = 0; cc < 3; ++cc) S[cc] += -tau_p * mom_pert(P, q, c, k, cc);
         qo.mu[c] = (T)((double)qo.mu[c] + scale * S[0]);
@@ -185,15 +239,27 @@ void launch_diffuse(const Dims &d, const Geo &G, const Phy &P, const cc_state *q
     const bool diff = P.kdh != 0.0 || P.kdv != 0.0;
     const bool sponge = P.rsp != 0.0 && P.zsp < P.ztop;
     if (!diff && !sponge) return;
-    int kmin = 0;
+    const int64_t nc = (int64_t)d.nx * d.ny;
     if (!diff) {  // levels below the layer feel nothing: start one level under the first one reaching in
         const double kz = std::floor((P.zsp - d.z0) / d.dz) - 1.0;
-        kmin = kz <= 0.0 ? 0 : (kz >= d.nz ? d.nz : (int)kz);
+        const int kmin = kz <= 0.0 ? 0 : (kz >= d.nz ? d.nz : (int)kz);
         if (kmin >= d.nz) return;
+        hipLaunchKernelGGL((k_diffuse<T, false>), dim3(blocks_for(nc * (d.nz - kmin), 256)), dim3(256), 0, s, d, G,
+                           P, sin_of<T>(qs), sout_of<T>(qo), scale, final_stage, kmin, d.nz, d.nz);
+        return;
     }
-    const int64_t n = (int64_t)d.nx * d.ny * (d.nz - kmin);
-    hipLaunchKernelGGL(k_diffuse<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, G, P, sin_of<T>(qs),
-                       sout_of<T>(qo), scale, final_stage, kmin);
+    // interior levels [kf, nz - 2) when the band height is known, the flux form below and above
+    int kf = d.nz, ke = d.nz;
+    if (G.kband >= 1 && G.kband <= d.nz && G.kband + 2 < d.nz - 2) {
+        kf = G.kband + 2;
+        ke = d.nz - 2;
+    }
+    if (kf < ke)
+        hipLaunchKernelGGL((k_diffuse<T, true>), dim3(blocks_for(nc * (ke - kf), 256)), dim3(256), 0, s, d, G, P,
+                           sin_of<T>(qs), sout_of<T>(qo), scale, final_stage, kf, ke, ke);
+    const int nslow = kf + (d.nz - ke);
+    hipLaunchKernelGGL((k_diffuse<T, false>), dim3(blocks_for(nc * nslow, 256)), dim3(256), 0, s, d, G, P,
+                       sin_of<T>(qs), sout_of<T>(qo), scale, final_stage, 0, kf, ke);
 }
 
 template void launch_diffuse<float>(const Dims &, const Geo &, const Phy &, const cc_state *, cc_state *, double,
