@@ -1124,6 +1124,105 @@ void or_run(const or_grid *g, const or_phys *ph, const or_geom *G, const double 
     free(head); free(next);
 }
 
+/* ------------------------------------------------------------------------------------------ */
+/* The paper's own time stepping (Sec. 2.2): leap-frog with the Robert-Asselin filter, with the   */
+/* perturbation pressure p' as the prognostic thermodynamic variable (Sec. 2.1, eq. heat).  A     */
+/* state "in p' form" holds p' where the (rho theta)' form holds (rho theta)'.                   */
+/*                                                                                               */
+/* Readings: the coefficient of eq. heat is taken as (cp/cv) R (p/p0)^(R/cp), the factor that     */
+/* makes it the chain rule of p = p0 (R rho theta / p0)^(cp/cv) (the printed 1/p0 does not fit    */
+/* the units); rho theta in the flux follows from p through that equation of state; D_theta is    */
+/* the diffusion and sponge term of (rho theta)'.  The first step is a forward step; the filter   */
+/* weight nu is a parameter (the paper gives none).                                             */
+/* ------------------------------------------------------------------------------------------ */
+/* (rho theta)' from p' through the equation of state: rho theta = rthbar (1 + p'/pbar)^(cv/cp) */
+static double eos_rthprime(double pp, double rthbar, double pbar, double gam)
+{
+    return rthbar * expm1(log1p(pp / pbar) / gam);
+}
+
+/* convert the thermodynamic slot of q in place at every non-solid cell: to_p != 0: (rho theta)' ->
+ * p'; else p' -> (rho theta)' */
+void or_pform(const or_grid *g, const or_phys *ph, const or_geom *G, const double *rthb, const double *pb,
+              or_state *q, int to_p)
+{
+    size_t n = (size_t)g->nx * g->ny * g->nz;
+    double gam = ph->cp / (ph->cp - ph->rd);
+    for (size_t c = 0; c < n; ++c) {
+        if (G->cls[c] == OR_SOLID) continue;
+        int k = (int)(c % g->nz);
+        q->rth[c] = to_p ? eos_pprime(q->rth[c], rthb[k], pb[k], gam) : eos_rthprime(q->rth[c], rthb[k], pb[k], gam);
+    }
+}
+
+/* one leap-frog step in p' form.  first != 0: forward step qp = q0 + dt L(q0) (qm unused, q0 not
+ * filtered).  Else qp = qm + 2 dt L(q0), with qm the filtered state of the previous time level,
+ * then q0 is filtered in place: q0 += nu (qm - 2 q0 + qp).  L of p' at a group master is
+ * (cp/cv) R (p/p0)^(R/cp) times the (rho theta)' tendency of the merged-cell scheme, p and rho
+ * theta of the master's level at time n.  Updates and the filter act at group masters (scalars)
+ * and predicted points (momentum); qp then takes the diagnostic pass. */
+void or_lf_step(const or_grid *g, const or_phys *ph, const or_geom *G, const double *rhob,
+                const double *rthb, const double *pb, const or_state *qm, or_state *q0, or_state *qp,
+                double dt, double nu, int first, int64_t *counts)
+{
+    size_t n = (size_t)g->nx * g->ny * g->nz;
+    double gam = ph->cp / (ph->cp - ph->rd);
+    double kappa = ph->rd / ph->cp;
+    /* the tendency of the (rho theta)' form at time n */
+    or_state t = {(double *)malloc(n * sizeof(double)), (double *)malloc(n * sizeof(double)), q0->mu, q0->mv,
+                  q0->mw};
+    memcpy(t.rho, q0->rho, n * sizeof(double));
+    memcpy(t.rth, q0->rth, n * sizeof(double));
+    or_pform(g, ph, G, rthb, pb, &t, 0);
+    int64_t *head = (int64_t *)malloc(sizeof(int64_t) * n), *next = (int64_t *)malloc(sizeof(int64_t) * n);
+    build_groups(g, G, head, next);
+    or_ctx x = {g, ph, G, rhob, rthb, pb, &t};
+    const or_state *base = first ? q0 : qm;
+    double h = first ? dt : 2.0 * dt;
+#pragma omp parallel for schedule(static)
+    for (long long cc = 0; cc < (long long)n; ++cc) {
+        size_t c = (size_t)cc;
+        double d[5];
+        int hs, hm;
+        tendency_cell(&x, c, head, next, d, &hs, &hm);
+        if (hs) {
+            int k = (int)(c % g->nz);
+            double p = pb[k] + q0->rth[c];
+            double coef = gam * ph->rd * pow(p / ph->p0, kappa);
+            qp->rho[c] = base->rho[c] + h * d[0];
+            qp->rth[c] = base->rth[c] + h * (coef * d[1]);
+        }
+        if (hm) {
+            qp->mu[c] = base->mu[c] + h * d[2];
+            qp->mv[c] = base->mv[c] + h * d[3];
+            qp->mw[c] = base->mw[c] + h * d[4];
+        }
+    }
+    /* the filter, once every tendency (which reads q0's momentum) has been taken */
+    if (!first) {
+#pragma omp parallel for schedule(static)
+        for (long long cc = 0; cc < (long long)n; ++cc) {
+            size_t c = (size_t)cc;
+            int hs = G->cls[c] == OR_OPEN || G->cls[c] == OR_ORPHAN, hm = G->vcls[c] == OR_PRED;
+            if (hs) {
+                q0->rho[c] += nu * ((qm->rho[c] - 2.0 * q0->rho[c]) + qp->rho[c]);
+                q0->rth[c] += nu * ((qm->rth[c] - 2.0 * q0->rth[c]) + qp->rth[c]);
+            }
+            if (hm) {
+                q0->mu[c] += nu * ((qm->mu[c] - 2.0 * q0->mu[c]) + qp->mu[c]);
+                q0->mv[c] += nu * ((qm->mv[c] - 2.0 * q0->mv[c]) + qp->mv[c]);
+                q0->mw[c] += nu * ((qm->mw[c] - 2.0 * q0->mw[c]) + qp->mw[c]);
+            }
+        }
+    }
+    /* solid cells of qp hold zero, as after a Runge-Kutta update */
+    for (size_t c = 0; c < n; ++c)
+        if (G->cls[c] == OR_SOLID) { qp->rho[c] = 0.0; qp->rth[c] = 0.0; }
+    free(head); free(next);
+    free(t.rho); free(t.rth);
+    or_diagnose(g, ph, G, rhob, rthb, pb, qp, counts);
+}
+
 /* thread count for the OpenMP loops (results are independent of it: every output element is
  * written by one thread and every sum runs in a fixed order) */
 #ifdef _OPENMP

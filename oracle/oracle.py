@@ -84,6 +84,8 @@ def lib():
         L.or_face_flux.argtypes = [G, P, GM, _DP, _DP, _DP, S, C.c_int, C.c_int, C.c_int, C.c_int, _DP]
         L.or_reduce.argtypes = [G, P, GM, _DP, _DP, _DP, S, _DP]
         L.or_run.argtypes = [G, P, GM, _DP, _DP, _DP, S, S, S, C.c_double, C.c_int, _I64]
+        L.or_pform.argtypes = [G, P, GM, _DP, _DP, S, C.c_int]
+        L.or_lf_step.argtypes = [G, P, GM, _DP, _DP, _DP, S, S, S, C.c_double, C.c_double, C.c_int, _I64]
         L.or_set_threads.argtypes = [C.c_int]
         L.or_set_threads.restype = C.c_int
         _lib = L
@@ -256,6 +258,38 @@ class Oracle:
         a, b, c = q.c(), s1.c(), s2.c()
         lib().or_run(*self._args(), C.byref(a), C.byref(b), C.byref(c), dt, nsteps, _p(self.counts, _I64))
         return q
+
+    # -- leap-frog with the Robert-Asselin filter, p' form ---------------------------------------
+    def pform(self, q: State, to_p: bool = True) -> State:
+        """Copy of q with the thermodynamic slot converted: (rho theta)' -> p' (to_p) or back."""
+        self._ready()
+        out = q.copy()
+        co = out.c()
+        lib().or_pform(C.byref(self.grid), C.byref(self.phys), C.byref(self._geom), _p(self.rthb), _p(self.pb),
+                       C.byref(co), 1 if to_p else 0)
+        return out
+
+    def lf_step(self, qm: Optional[State], q0: State, dt: float, nu: float, first: bool = False) -> State:
+        """One leap-frog step in p' form: returns q^{n+1}; q0 (time n) is filtered in place unless
+        `first` (a forward step from q0; qm is then not read)."""
+        self._ready()
+        qp = State(self.shape)
+        a = (qm if qm is not None else q0).c()
+        b, c = q0.c(), qp.c()
+        lib().or_lf_step(*self._args(), C.byref(a), C.byref(b), C.byref(c), dt, nu, 1 if first else 0,
+                         _p(self.counts, _I64))
+        return qp
+
+    def run_lf(self, q: State, dt: float, nsteps: int, nu: float):
+        """nsteps leap-frog steps from q (p' form; the first a forward step): returns (q^N, filtered
+        q^{N-1})."""
+        q0 = q.copy()
+        qp = self.lf_step(None, q0, dt, nu, first=True)
+        qm, q0 = q0, qp
+        for _ in range(nsteps - 1):
+            qp = self.lf_step(qm, q0, dt, nu)
+            qm, q0 = q0, qp
+        return q0, qm
 
     def reduce(self, q: State) -> np.ndarray:
         self._ready()
