@@ -247,6 +247,37 @@ cc_status cutcell_rk_update(const cc_grid *grid, const cc_phys *phys, const cc_g
                             cc_state *q_out, double stage_dt, int32_t final_stage, int64_t *dev_status,
                             cc_stream_t stream);
 
+/* The paper's own time stepping (Sec. 2.2): leap-frog with the Robert-Asselin filter, with the
+ * perturbation pressure p' as the prognostic thermodynamic variable (Sec. 2.1, eq. heat).  A state
+ * in "p' form" holds p' [Pa] in its rth slot (and rth_lo for CC_F32_PERT); every other field is as in
+ * the (rho theta)' form.
+ *
+ * cutcell_pform converts q in place at every non-solid cell through the equation of state
+ * p = p0 (R rho theta / p0)^(cp/cv): to_p != 0: (rho theta)' -> p', else p' -> (rho theta)'.
+ *
+ * cutcell_lf_step advances one step.  first != 0: a forward step q_p = q_0 + dt L(q_0) (q_m is not
+ * read and may be NULL; q_0 is left as it is).  Else q_p = q_m + 2 dt L(q_0), with q_m the filtered
+ * state of the previous time level, and then q_0 is filtered in place: q_0 += nu (q_m - 2 q_0 + q_p)
+ * (Robert-Asselin, weight nu in [0, 1/2]).  L is the merged-cell tendency of cutcell_tendency
+ * (diffusion and sponge included) at (rho theta)' from p' of q_0, except that p' takes the (rho
+ * theta)' tendency times (cp/cv) p / (rho theta) = (cp/cv) R (p/p0)^(R/cp) (the chain rule of the
+ * equation of state; eq. heat).  Updates and the filter act at group masters (rho', p') and
+ * predicted points (momentum); solid cells of q_p are zeroed and q_p takes the velocity-diagnostic
+ * pass (absorbed cells mirror the master's p').  The filtered q_0 keeps its diagnosed points and
+ * absorbed cells as they were (the scheme never reads them).  With the low-order arrays
+ * (CC_F32_PERT) rho' and p' are carried with them through update and filter, so mass stays
+ * conserved.  The update runs the kernels of cutcell_rk_update (grid.tile applies) as one stage of
+ * step 2 dt.  work: caller-allocated device memory of cutcell_lf_workspace_bytes(grid, prec) bytes
+ * ((rho theta)' of q_0 and zeroed scratch), not read across calls.  q_m, q_0, q_p distinct.
+ * Non-finite results are counted into dev_status[2].  The caller rotates (q_m, q_0, q_p) <-
+ * (q_0, q_p, q_m) between steps. */
+size_t cutcell_lf_workspace_bytes(const cc_grid *grid, cc_prec prec);
+cc_status cutcell_pform(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom, const double *base,
+                        cc_prec prec, cc_state *q, int32_t to_p, cc_stream_t stream);
+cc_status cutcell_lf_step(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom, const double *base,
+                          cc_prec prec, const cc_state *q_m, cc_state *q_0, cc_state *q_p, void *work,
+                          double dt, double nu, int32_t first, int64_t *dev_status, cc_stream_t stream);
+
 /* Conservation sums (FP64, deterministic order): out[4] = { M' = sum Vgroup dV rho',
  * Theta' = sum Vgroup dV (rho theta)', M_total (with the base density at each master's level),
  * E = internal + potential energy of the groups + kinetic energy at predicted points }.  Mass is

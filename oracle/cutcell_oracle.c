@@ -1142,7 +1142,8 @@ static double eos_rthprime(double pp, double rthbar, double pbar, double gam)
 }
 
 /* convert the thermodynamic slot of q in place at every non-solid cell: to_p != 0: (rho theta)' ->
- * p'; else p' -> (rho theta)' */
+ * p'; else p' -> (rho theta)'.  A merged group's value belongs to its master, so the base state of
+ * the master's level applies to every member (absorbed cells keep mirroring the master). */
 void or_pform(const or_grid *g, const or_phys *ph, const or_geom *G, const double *rthb, const double *pb,
               or_state *q, int to_p)
 {
@@ -1150,7 +1151,7 @@ void or_pform(const or_grid *g, const or_phys *ph, const or_geom *G, const doubl
     double gam = ph->cp / (ph->cp - ph->rd);
     for (size_t c = 0; c < n; ++c) {
         if (G->cls[c] == OR_SOLID) continue;
-        int k = (int)(c % g->nz);
+        int k = (int)((size_t)G->master[c] % g->nz);
         q->rth[c] = to_p ? eos_pprime(q->rth[c], rthb[k], pb[k], gam) : eos_rthprime(q->rth[c], rthb[k], pb[k], gam);
     }
 }

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcutcell.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["cc_api.hip", "cc_geometry.hip", "cc_stage.hip", "cc_stream.hip", "cc_diffuse.hip", "cc_batch.hip"]
+SOURCES = ["cc_api.hip", "cc_geometry.hip", "cc_stage.hip", "cc_stream.hip", "cc_diffuse.hip", "cc_leapfrog.hip", "cc_batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

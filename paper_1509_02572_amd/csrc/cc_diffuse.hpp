@@ -5,10 +5,11 @@
 
 namespace cc {
 
-// Add scale x D(q_s) to q_out at group masters (rho', (rho theta)') and predicted lattice points
-// (momentum) on stream s: scale = the stage's c dt after an update, 1 after a tendency evaluation.
-// final_stage: q_out's low-order parts (float form) are carried.  Nothing is launched when both
-// rates of P are zero.
+// Add scale x (D(q_s) + S(q_s)) (diffusion and sponge) to q_out at group masters (rho', (rho theta)')
+// and predicted lattice points (momentum) on stream s: scale = the stage's c dt after an update, 1
+// after a tendency evaluation.
+// final_stage: q_out's low-order parts (float form) are carried.  Nothing is launched when the
+// diffusion rates and the sponge rate of P are all zero.
 template <typename T>
 void launch_diffuse(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, cc_state *qo, double scale,
                     int final_stage, hipStream_t s);

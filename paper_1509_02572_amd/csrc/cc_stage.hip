@@ -7,6 +7,7 @@
 #include "cc_kernels.hpp"
 #include "cc_stream.hpp"
 #include "cc_diffuse.hpp"
+#include "cc_leapfrog.hpp"
 
 namespace cc {
 
@@ -493,6 +494,80 @@ extern "C" cc_status cutcell_rk_update(const cc_grid *grid, const cc_phys *phys,
         launch_diffuse<float>(d, G, P, qs, qo, cdt, final_stage, s);
     }
     return launch_status("cutcell_rk_update");
+}
+
+// ---- leap-frog with the Robert-Asselin filter, p' form (Sec. 2.2, eq. heat) ----
+static size_t lf_array_bytes(const cc_grid *grid, cc_prec prec)
+{
+    const size_t n = (size_t)grid->nx * grid->ny * grid->nzs;
+    return (n * (prec == CC_F64 ? 8 : 4) + 255) / 256 * 256;
+}
+
+extern "C" size_t cutcell_lf_workspace_bytes(const cc_grid *grid, cc_prec prec)
+{
+    if (!check_grid(grid)) return 0;
+    return 3 * lf_array_bytes(grid, prec);
+}
+
+extern "C" cc_status cutcell_pform(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                                   const double *base, cc_prec prec, cc_state *q, int32_t to_p,
+                                   cc_stream_t stream)
+{
+    Dims d; Geo G; Phy P;
+    if (!make_views("cutcell_pform", grid, phys, geom, base, prec, d, G, P)) return CC_EINVAL;
+    if (!state_ok("cutcell_pform", q)) return CC_EINVAL;
+    if (prec == CC_F64) launch_pform<double>(d, G, P, q, to_p, (hipStream_t)stream);
+    else launch_pform<float>(d, G, P, q, to_p, (hipStream_t)stream);
+    return launch_status("cutcell_pform");
+}
+
+template <typename T>
+static void lf_step(const cc_grid *grid, const Dims &d, const Geo &G, const Phy &P, const cc_state *qm,
+                    cc_state *q0, cc_state *qp, char *work, size_t abytes, double dt, double nu, int first,
+                    int64_t *st, hipStream_t s)
+{
+    T *w[3];
+    for (int a = 0; a < 3; ++a) w[a] = (T *)(work + a * abytes);
+    const bool lo = sizeof(T) == 4 && q0->rho_lo && q0->rth_lo && qp->rho_lo && qp->rth_lo;
+    // q_s: q(n) with (rho theta)' from its p'; q_n: the base level with a zero thermodynamic slot
+    launch_rthp<T>(d, G, P, q0, w[0], w[1], lo ? w[2] : nullptr, s);
+    cc_state tin = *q0;
+    tin.rth = w[0];
+    tin.rho_lo = tin.rth_lo = nullptr;
+    const cc_state *qb = first ? q0 : qm;
+    cc_state base = *qb;
+    base.rth = w[1];
+    base.rth_lo = lo ? w[2] : nullptr;
+    if (!lo) base.rho_lo = nullptr;
+    cc_state out = *qp;
+    if (!lo) out.rho_lo = out.rth_lo = nullptr;
+    const double h = first ? dt : 2.0 * dt;
+    launch_stage<T, 0>(d, G, P, &tin, &base, &out, h, lo ? 1 : 0, st, s, grid->tile);
+    launch_diffuse<T>(d, G, P, &tin, &out, h, lo ? 1 : 0, s);
+    launch_lf_finish<T>(d, G, P, qb, q0, &out, nu, first, st, s);
+    launch_diagnose<T>(d, G, P, &out, st, s);
+}
+
+extern "C" cc_status cutcell_lf_step(const cc_grid *grid, const cc_phys *phys, const cc_geom *geom,
+                                     const double *base, cc_prec prec, const cc_state *q_m, cc_state *q_0,
+                                     cc_state *q_p, void *work, double dt, double nu, int32_t first,
+                                     int64_t *st, cc_stream_t stream)
+{
+    Dims d; Geo G; Phy P;
+    const char *what = "cutcell_lf_step";
+    if (!make_views(what, grid, phys, geom, base, prec, d, G, P)) return CC_EINVAL;
+    if (!state_ok(what, q_0) || !state_ok(what, q_p) || (!first && !state_ok(what, q_m))) return CC_EINVAL;
+    CC_REQUIRE(work, "cutcell_lf_step: null workspace");
+    CC_REQUIRE(q_p->rho != q_0->rho && q_p->mu != q_0->mu && (first || (q_p->rho != q_m->rho && q_p->mu != q_m->mu &&
+                                                                         q_m->rho != q_0->rho)),
+               "cutcell_lf_step: q_m, q_0 and q_p must be distinct states");
+    CC_REQUIRE(dt > 0.0 && std::isfinite(dt), "cutcell_lf_step: dt must be positive");
+    CC_REQUIRE(nu >= 0.0 && nu <= 0.5, "cutcell_lf_step: filter weight outside [0, 1/2]");
+    const size_t ab = lf_array_bytes(grid, prec);
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == CC_F64) lf_step<double>(grid, d, G, P, q_m, q_0, q_p, (char *)work, ab, dt, nu, first != 0, st, s);
+    else lf_step<float>(grid, d, G, P, q_m, q_0, q_p, (char *)work, ab, dt, nu, first != 0, st, s);
+    return launch_status(what);
 }
 
 extern "C" size_t cutcell_reduce_workspace(const cc_grid *)

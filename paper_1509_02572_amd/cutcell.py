@@ -78,6 +78,11 @@ def lib():
         L.cutcell_tendency.argtypes = [G, P, GM, vp, C.c_int, S, S, vp]
         L.cutcell_rk_stage.argtypes = [G, P, GM, vp, C.c_int, S, S, S, C.c_double, C.c_int32, i64p, vp]
         L.cutcell_rk_update.argtypes = [G, P, GM, vp, C.c_int, S, S, S, C.c_double, C.c_int32, i64p, vp]
+        L.cutcell_lf_workspace_bytes.argtypes = [G, C.c_int]
+        L.cutcell_lf_workspace_bytes.restype = C.c_size_t
+        L.cutcell_pform.argtypes = [G, P, GM, vp, C.c_int, S, C.c_int32, vp]
+        L.cutcell_lf_step.argtypes = [G, P, GM, vp, C.c_int, S, S, S, vp, C.c_double, C.c_double, C.c_int32, i64p,
+                                      vp]
         L.cutcell_stage_workspace_bytes.argtypes = [G, C.c_int]
         L.cutcell_stage_workspace_bytes.restype = C.c_size_t
         L.cutcell_reduce_workspace.argtypes = [G]
@@ -105,7 +110,8 @@ def lib():
         L.amr_batch_destroy.argtypes = [vp]
         for name in ("cutcell_base_state", "cutcell_geometry", "cutcell_merge_map", "cutcell_init_state",
                      "cutcell_diagnose", "cutcell_tendency", "cutcell_rk_stage", "cutcell_rk_update", "cutcell_reduce",
-                     "cutcell_reduce_noalloc", "cutcell_band_setup", "cutcell_stage_ctx_create",
+                     "cutcell_reduce_noalloc", "cutcell_band_setup", "cutcell_stage_ctx_create", "cutcell_pform",
+                     "cutcell_lf_step",
                      "cutcell_stage_ctx_destroy",
                      "cutcell_check_status", "amr_batch_create", "amr_block_step", "amr_batch_destroy",
                      "amr_hierarchy_workspace_bytes", "amr_hierarchy_create", "amr_hierarchy_sync"):
@@ -185,6 +191,18 @@ def cutcell_diagnose(grid, phys, geom, base, prec, q: cc_state, status, stream=N
 def cutcell_tendency(grid, phys, geom, base, prec, q: cc_state, dq: cc_state, stream=None):
     _check(lib().cutcell_tendency(C.byref(grid), C.byref(phys), C.byref(geom), _ptr(base), prec,
                                   C.byref(q), C.byref(dq), _stream(stream)), "cutcell_tendency")
+
+
+def cutcell_pform(grid, phys, geom, base, prec, q: cc_state, to_p: bool, stream=None):
+    _check(lib().cutcell_pform(C.byref(grid), C.byref(phys), C.byref(geom), _ptr(base), prec, C.byref(q),
+                               1 if to_p else 0, _stream(stream)), "cutcell_pform")
+
+
+def cutcell_lf_step(grid, phys, geom, base, prec, qm: Optional[cc_state], q0: cc_state, qp: cc_state, work, dt: float,
+                    nu: float, first: bool, status, stream=None):
+    _check(lib().cutcell_lf_step(C.byref(grid), C.byref(phys), C.byref(geom), _ptr(base), prec,
+                                 C.byref(qm) if qm is not None else None, C.byref(q0), C.byref(qp), _ptr(work), dt,
+                                 nu, 1 if first else 0, _ptr(status), _stream(stream)), "cutcell_lf_step")
 
 
 def cutcell_rk_stage(grid, phys, geom, base, prec, qn: cc_state, qs: cc_state, qo: cc_state,
@@ -414,6 +432,33 @@ class Domain:
         for _ in range(nsteps):
             a, b, c = self.step(a, b, c, dt)
         return a
+
+    # -- leap-frog with the Robert-Asselin filter, p' form -------------------------------------
+    def pform(self, q: State, to_p: bool = True) -> State:
+        """Convert q's thermodynamic slot in place: (rho theta)' -> p' (to_p) or back; returns q."""
+        cutcell_pform(self.grid, self.phys, self.geom, self.base, self.prec, q.c, to_p)
+        return q
+
+    def lf_step(self, qm: Optional[State], q0: State, qp: State, dt: float, nu: float, first: bool = False):
+        """One leap-frog step in p' form into qp; q0 is filtered in place unless `first`."""
+        if getattr(self, "_lfws", None) is None:
+            nb = lib().cutcell_lf_workspace_bytes(C.byref(self.grid), self.prec)
+            self._lfws = torch.empty(nb // 8 + 1, dtype=torch.float64, device=self.dev)
+        cutcell_lf_step(self.grid, self.phys, self.geom, self.base, self.prec, qm.c if qm is not None else None,
+                        q0.c, qp.c, self._lfws, dt, nu, first, self.status)
+
+    def run_lf(self, q: State, dt: float, nsteps: int, nu: float):
+        """nsteps leap-frog steps from q (p' form, left untouched; the first a forward step):
+        returns (q^N, filtered q^{N-1})."""
+        qm, q0, qp = self.new_state(), self.new_state(), self.new_state()
+        for f in q.t:
+            q0.t[f].copy_(q.t[f])
+        self.lf_step(None, q0, qp, dt, nu, first=True)
+        qm, q0, qp = q0, qp, qm
+        for _ in range(nsteps - 1):
+            self.lf_step(qm, q0, qp, dt, nu)
+            qm, q0, qp = q0, qp, qm
+        return q0, qm
 
     def reduce(self, q: State) -> np.ndarray:
         cutcell_reduce(self.grid, self.phys, self.geom, self.base, self.prec, q.c, self.ws, self.red)

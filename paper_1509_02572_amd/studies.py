@@ -22,8 +22,11 @@ the sponge (Rayleigh damping rising as sin^2 from 10 km to a rate of 0.01 1/s at
 evaluation region (every lattice point above the hilltop height, up to the lid, over the whole
 horizontal domain).
 
-Usage:  python -m paper_1509_02572_amd.studies convergence [--t-end 3600] [--out FILE]
-        python -m paper_1509_02572_amd.studies lee-wave [--delta 100] [--t-end 3600] [--out FILE]
+Both run with the three-stage Runge-Kutta scheme of the (rho theta)' form, or with ``--scheme lf``
+with the paper's leap-frog and Robert-Asselin filter in p' form (filter weight ``--nu``).
+
+Usage:  python -m paper_1509_02572_amd.studies convergence [--t-end 3600] [--scheme rk3|lf] [--out FILE]
+        python -m paper_1509_02572_amd.studies lee-wave [--delta 100] [--t-end 3600] [--scheme rk3|lf] [--out FILE]
 """
 from __future__ import annotations
 
@@ -42,6 +45,7 @@ LX, LY, LZ = 64000.0, 32000.0, 16000.0  # domain of Sec. 3 [m]
 HILL_TOP = 400.0
 KD = 1e-3  # artificial-diffusion rate [1/s]
 ZSP, RSP = 10000.0, 0.01  # sponge bottom [m] and rate at the lid [1/s]
+NU = 0.1  # Robert-Asselin filter weight of the leap-frog scheme
 
 
 def log(*a):
@@ -66,8 +70,10 @@ def bell_config(delta: float, t_end: float = 3600.0, **kw) -> W.Config:
     return domain_config(f"bell{int(delta)}", W.Hill("bell", 400.0, 2000.0), delta, t_end, **kw)
 
 
-def integrate(cfg: W.Config, prec: str = "f64", every: float = 30.0):
-    """Run cfg.nsteps steps from the initial state; progress on stderr every `every` seconds."""
+def integrate(cfg: W.Config, prec: str = "f64", every: float = 30.0, scheme: str = "rk3", nu: float = NU):
+    """Run cfg.nsteps steps from the initial state; progress on stderr every `every` seconds.
+    scheme "rk3": three-stage Runge-Kutta, (rho theta)' form; "lf": the paper's leap-frog with the
+    Robert-Asselin filter (weight nu) in p' form (the returned state is q^N)."""
     import torch
     from . import autotune
     from . import cutcell as CC
@@ -76,11 +82,17 @@ def integrate(cfg: W.Config, prec: str = "f64", every: float = 30.0):
     tile = autotune.tune(dom, q, dt=cfg.dt, path=None)["tile"]  # untimed: the fastest update form
     r0 = dom.reduce(q)
     a, b, c = q, dom.new_state(), dom.new_state()
+    if scheme == "lf":
+        dom.pform(a, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     last = t0
     for n in range(cfg.nsteps):
-        a, b, c = dom.step(a, b, c, cfg.dt)
+        if scheme == "rk3":
+            a, b, c = dom.step(a, b, c, cfg.dt)
+        else:  # (qbar(n-1), q(n), scratch) in (c, a, b)
+            dom.lf_step(c, a, b, cfg.dt, nu, first=(n == 0))
+            c, a, b = a, b, c
         if (n + 1) % 200 == 0:
             torch.cuda.synchronize()
             now = time.perf_counter()
@@ -94,7 +106,8 @@ def integrate(cfg: W.Config, prec: str = "f64", every: float = 30.0):
     if st[:5].any():
         raise RuntimeError(f"{cfg.name}: device status counters set: {st}")
     info = {"nx": cfg.nx, "ny": cfg.ny, "nz": cfg.nz, "delta": cfg.dx, "dt": cfg.dt, "steps": cfg.nsteps,
-            "tile": tile, "wall_s": round(secs, 2), "cell_updates_per_s": cfg.ncells * 3 * cfg.nsteps / secs,
+            "scheme": scheme, "tile": tile, "wall_s": round(secs, 2),
+            "cell_updates_per_s": cfg.ncells * (3 if scheme == "rk3" else 1) * cfg.nsteps / secs,
             "mass_drift_rel": float(abs(r1[0] - r0[0]) / r0[2])}
     log(f"  {cfg.name}: {cfg.nsteps} steps in {secs:.1f} s, mass drift {info['mass_drift_rel']:.1e}")
     return dom, a, info
@@ -170,20 +183,21 @@ def error_norms(vc: np.ndarray, vref_c: np.ndarray, dc: float) -> Dict[str, obje
 
 
 def convergence(deltas=(400.0, 250.0, 200.0), ref: float = 100.0, t_end: float = 3600.0, prec: str = "f64",
-                out: Optional[str] = None) -> dict:
+                out: Optional[str] = None, scheme: str = "rk3", nu: float = NU) -> dict:
     import torch
-    log(f"convergence: cosine hill, deltas {deltas}, reference {ref} m, t_end {t_end} s, {prec}")
+    log(f"convergence: cosine hill, deltas {deltas}, reference {ref} m, t_end {t_end} s, {prec}, {scheme}")
     cfg = cosine_config(ref, t_end)
-    dom, q, info_ref = integrate(cfg, prec)
+    dom, q, info_ref = integrate(cfg, prec, scheme=scheme, nu=nu)
     vref = lattice_velocity(dom, q)
     del dom, q
     torch.cuda.empty_cache()
     res = {"case": "cosine hill h_m=400 m a=2 km at (32,16) km, 64x32x16 km, U=10 m/s, N=0.01 1/s",
-           "t_end_s": t_end, "prec": prec, "kd_per_s": KD, "sponge": {"bottom_m": ZSP, "rate_per_s": RSP},
+           "t_end_s": t_end, "prec": prec, "scheme": scheme, "nu": nu if scheme == "lf" else None, "kd_per_s": KD,
+           "sponge": {"bottom_m": ZSP, "rate_per_s": RSP},
            "reference": info_ref, "runs": {}}
     for dc in deltas:
         c = cosine_config(dc, t_end)
-        d, qc, info = integrate(c, prec)
+        d, qc, info = integrate(c, prec, scheme=scheme, nu=nu)
         vc = lattice_velocity(d, qc)
         for f in ("u", "w"):
             info[f] = error_norms(vc[f], sample_reference(vref[f], ref, dc, vc[f].shape), dc)
@@ -222,10 +236,11 @@ def lee_wavelength(w_line: np.ndarray, dx: float, x0: float, x_from: float, x_to
             "maxima_m": [round(float(p), 1) for p in peaks], "spacings_m": [round(float(v), 1) for v in sp]}
 
 
-def lee_wave(delta: float = 100.0, t_end: float = 3600.0, prec: str = "f64", out: Optional[str] = None) -> dict:
-    log(f"lee wave: bell hill, delta {delta} m, t_end {t_end} s, {prec}")
+def lee_wave(delta: float = 100.0, t_end: float = 3600.0, prec: str = "f64", out: Optional[str] = None,
+             scheme: str = "rk3", nu: float = NU) -> dict:
+    log(f"lee wave: bell hill, delta {delta} m, t_end {t_end} s, {prec}, {scheme}")
     cfg = bell_config(delta, t_end)
-    dom, q, info = integrate(cfg, prec)
+    dom, q, info = integrate(cfg, prec, scheme=scheme, nu=nu)
     v = lattice_velocity(dom, q)
     K = int(round(800.0 / delta))
     jc, ic = cfg.ny // 2, cfg.nx // 2
@@ -254,16 +269,21 @@ def main(argv=None):
     c.add_argument("--deltas", default="400,250,200")
     c.add_argument("--ref", type=float, default=100.0)
     c.add_argument("--out", default=None)
+    c.add_argument("--scheme", default="rk3", choices=["rk3", "lf"])
+    c.add_argument("--nu", type=float, default=NU)
     lw = sub.add_parser("lee-wave")
     lw.add_argument("--delta", type=float, default=100.0)
     lw.add_argument("--t-end", type=float, default=3600.0)
     lw.add_argument("--prec", default="f64", choices=["f32", "f64"])
     lw.add_argument("--out", default=None)
+    lw.add_argument("--scheme", default="rk3", choices=["rk3", "lf"])
+    lw.add_argument("--nu", type=float, default=NU)
     a = ap.parse_args(argv)
     if a.cmd == "convergence":
-        r = convergence(tuple(float(x) for x in a.deltas.split(",")), a.ref, a.t_end, a.prec, a.out)
+        r = convergence(tuple(float(x) for x in a.deltas.split(",")), a.ref, a.t_end, a.prec, a.out, a.scheme,
+                        a.nu)
     else:
-        r = lee_wave(a.delta, a.t_end, a.prec, a.out)
+        r = lee_wave(a.delta, a.t_end, a.prec, a.out, a.scheme, a.nu)
     print(json.dumps({k: v for k, v in r.items() if k != "w_profile_800m"}))
 
 
