@@ -163,6 +163,9 @@ def run_ensemble(prec: str, warmup: int):
     from paper_1509_02572_amd import workloads as W
     cfgs = W.ensemble(64, 0)
     doms = [CC.Domain(c, prec, "cuda:0", side_stream=False) for c in cfgs]
+    bad = [m for m, d in enumerate(doms) if d.check()[0]]
+    if bad:  # the generator does not redraw on an unmergeable cell: treat one as an error
+        raise RuntimeError(f"ensemble members with unmergeable cells: {bad}")
     states = [d.init_state() for d in doms]
     dt, nsteps = cfgs[0].dt, cfgs[0].nsteps
     stream = torch.cuda.current_stream()
@@ -187,6 +190,7 @@ def run_ensemble(prec: str, warmup: int):
     # whole graph (updates, band launches, diagnostics) against the algorithmic bytes of its stages
     byts = cells * sum(algorithmic_bytes(prec, s) for s in range(3)) * nsteps
     return {"value": cells * 3 * nsteps / secs, "unit": "cell-updates/s", "cells": cells,
+            "redraws": sum(c.redraws for c in cfgs),
             "steps": nsteps, "ms_per_step": secs / nsteps * 1e3, "graph_ms": gms,
             "tile": tuned["tile"], "tile_source": tuned["source"],
             "tile_ms": {str(k): round(v, 4) for k, v in tuned["ms"].items()},

@@ -46,6 +46,7 @@ HILL_TOP = 400.0
 KD = 1e-3  # artificial-diffusion rate [1/s]
 ZSP, RSP = 10000.0, 0.01  # sponge bottom [m] and rate at the lid [1/s]
 NU = 0.1  # Robert-Asselin filter weight of the leap-frog scheme
+MIN_SPACING = 2000.0  # lee-wave maxima closer than this [m] count as one
 
 
 def log(*a):
@@ -220,8 +221,9 @@ def convergence(deltas=(400.0, 250.0, 200.0), ref: float = 100.0, t_end: float =
 
 def lee_wavelength(w_line: np.ndarray, dx: float, x0: float, x_from: float, x_to: float) -> Dict[str, object]:
     """Spacing of the successive maxima of w along x in [x_from, x_to] downstream of the hill centre x0
-    (a maximum: larger than the two neighbours on each side, located by a parabola through three
-    points); the wavelength is the mean spacing."""
+    (a maximum: positive, larger than the two neighbours on each side, located by a parabola through
+    three points; of maxima closer than MIN_SPACING the larger is kept, so small ripples on a crest do
+    not count); the wavelength is the mean spacing."""
     x = np.arange(len(w_line)) * dx
     peaks = []
     for n in range(2, len(w_line) - 2):
@@ -230,7 +232,13 @@ def lee_wavelength(w_line: np.ndarray, dx: float, x0: float, x_from: float, x_to
         a, b, c = w_line[n - 1], w_line[n], w_line[n + 1]
         if b > a and b >= c and b > w_line[n - 2] and b >= w_line[n + 2] and b > 0.0:
             den = a - 2.0 * b + c
-            peaks.append(x[n] + (0.5 * dx * (a - c) / den if den != 0.0 else 0.0) - x0)
+            xp = x[n] + (0.5 * dx * (a - c) / den if den != 0.0 else 0.0) - x0
+            if peaks and xp - peaks[-1][0] < MIN_SPACING:
+                if b > peaks[-1][1]:
+                    peaks[-1] = (xp, b)
+                continue
+            peaks.append((xp, b))
+    peaks = [p for p, _ in peaks]
     sp = np.diff(peaks)
     return {"wavelength_m": float(sp.mean()) if len(sp) else float("nan"),
             "maxima_m": [round(float(p), 1) for p in peaks], "spacings_m": [round(float(v), 1) for v in sp]}

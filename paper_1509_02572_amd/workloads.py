@@ -80,6 +80,7 @@ class Config:
     z0: float = 0.0  # height of the grid's bottom face (blocks of a refined grid); H is then relative to it
     kdh: float = 0.0  # rate of the fourth-order artificial diffusion in x and y [1/s] (0: none)
     kdv: float = 0.0  # the same in z
+    redraws: int = 0  # ensemble members: hill sets redrawn before this one was accepted
     zsp: float = 0.0  # bottom height of the sponge layer below the lid [m]
     rsp: float = 0.0  # damping rate of the sponge at the lid [1/s] (0: none)
 
@@ -229,11 +230,15 @@ def paper_grid(hill: str) -> Config:
 TAN60 = math.tan(math.radians(60.0))
 
 
-def _edge_slope(H: np.ndarray, dx: float, dy: float) -> float:
-    """Largest corner-to-corner height difference per unit length (terrain-only check)."""
-    sx = np.abs(np.roll(H, -1, 0) - H).max() / dx
-    sy = np.abs(np.roll(H, -1, 1) - H).max() / dy
-    return float(max(sx, sy))
+def _column_slope(H: np.ndarray, dx: float, dy: float) -> float:
+    """Largest resolved slope of the terrain: max over columns of max(|gx|, |gy|), a column's
+    gradient being the mean of the height differences along its two edges in that direction (the
+    slope a grid of this spacing resolves, not the steeper corner-to-corner one)."""
+    Hx = np.roll(H, -1, 0)
+    gx = ((Hx + np.roll(Hx, -1, 1)) - (H + np.roll(H, -1, 1))) / (2.0 * dx)
+    Hy = np.roll(H, -1, 1)
+    gy = ((Hy + np.roll(Hy, -1, 0)) - (H + np.roll(H, -1, 0))) / (2.0 * dy)
+    return float(max(np.abs(gx).max(), np.abs(gy).max()))
 
 
 def ensemble(count: int = 64, seed: int = 0, nx_range=(48, 96), nz_range=(48, 64),
@@ -243,8 +248,11 @@ def ensemble(count: int = 64, seed: int = 0, nx_range=(48, 96), nz_range=(48, 64
     Per domain: ``nx, ny ~ U{48..96}``, ``nz ~ U{48..64}``, spacing ``delta`` in all directions,
     ``n ~ U{1..5}`` hills with heights ``U[100, 800]`` m, widths ``U[300, 3000]`` m and uniform
     centres, inflow ``U ~ U[5, 20]`` m/s along x and ``N ~ U[0.008, 0.02]`` 1/s.  A domain's hill set
-    is redrawn (sub-seed + 1) while its steepest corner-to-corner slope exceeds 60 degrees or its
-    highest point exceeds half the domain height.
+    is redrawn (sub-seed + 1) while its largest resolved column slope exceeds 60 degrees or its
+    highest point exceeds half the domain height; the number of redraws is kept in
+    ``Config.redraws``.  An unmergeable cell is not redrawn here (finding one takes the merge
+    rule, which this module does not hold): the merge map counts such cells and the callers treat a
+    non-zero count as an error.
     """
     out = []
     master = np.random.Generator(np.random.PCG64(seed))
@@ -266,10 +274,11 @@ def ensemble(count: int = 64, seed: int = 0, nx_range=(48, 96), nz_range=(48, 64
             cfg = Config(f"ens{d}", nx, ny, nz, delta, delta, delta, Hill("gauss", extra=hills),
                          bvn=bvn, u0=u0, dt=dt, nsteps=nsteps, seed=sub + redraws)
             H = terrain(cfg)
-            if _edge_slope(H, delta, delta) <= TAN60 and H.max() <= 0.5 * nz * delta:
+            if _column_slope(H, delta, delta) <= TAN60 and H.max() <= 0.5 * nz * delta:
                 break
             redraws += 1
         cfg.H = H
+        cfg.redraws = redraws
         out.append(cfg)
     return out
 

@@ -54,3 +54,15 @@ def test_lee_wavelength_of_a_damped_wave():
     r = S.lee_wavelength(w, dx, x0, 2000.0, 30000.0)
     assert abs(r["wavelength_m"] - lam) < 0.01 * lam
     assert len(r["maxima_m"]) >= 3
+
+
+def test_lee_wavelength_ignores_ripples_on_a_crest():
+    dx = 100.0
+    x = np.arange(640) * dx
+    x0 = 32000.0
+    lam = 6300.0
+    w = np.where(x > x0, np.sin(2 * np.pi * (x - x0) / lam), 0.0)
+    w = w + np.where((x > x0 + 24000.0) & (x < x0 + 26000.0), 0.05 * np.sin(2 * np.pi * x / 500.0), 0.0)
+    r = S.lee_wavelength(w, dx, x0, 2000.0, 30000.0)
+    assert all(s > 2000.0 for s in r["spacings_m"])
+    assert abs(r["wavelength_m"] - lam) < 0.05 * lam
