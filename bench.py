@@ -154,6 +154,81 @@ def run_gpu(cfg, prec: str, steps: int, warmup: int, tile: int = 0):
             "mass_total": float(red[2]), "mass_pert": float(red[0])}
 
 
+def paper_model_config(cfg):
+    """The workload with the source terms of the paper's model switched on: fourth-order artificial
+    diffusion at 1e-3 1/s in every direction and a sponge over the top third of the domain at
+    0.01 1/s at the lid."""
+    return cfg.replace(kdh=1e-3, kdv=1e-3, zsp=cfg.z0 + cfg.nz * cfg.dz * 2.0 / 3.0, rsp=0.01)
+
+
+def run_paper_model(cfg, prec: str, steps: int, warmup: int, tile: int):
+    """Two runs of the workload with diffusion and sponge on (paper_model_config): the Runge-Kutta
+    stage as in the headline (stage time beside the headline's gives the cost of the source-term
+    launch), and the paper's own scheme, leap-frog with the Robert-Asselin filter (weight 0.1) in p'
+    form: one update per step, timed with HIP events around each step."""
+    import torch
+    from paper_1509_02572_amd import cutcell as CC
+    from paper_1509_02572_amd import workloads as W
+    pc = paper_model_config(cfg)
+    dom = CC.Domain(pc, prec, "cuda:0")
+    q = dom.init_state(W.theta_noise(pc))
+    dom.grid.tile = tile  # the headline's update form
+    stream = torch.cuda.current_stream()
+    ncell = pc.nx * pc.ny * pc.nz
+    esz = 8 if prec == "f64" else 4
+    # Runge-Kutta stages with the source terms
+    a, b, c = q, dom.new_state(), dom.new_state()
+    for _ in range(warmup):
+        a, b, c = dom.step(a, b, c, pc.dt)
+    ev = []
+    for _ in range(steps):
+        for s, (qs, qo, cdt) in enumerate(((a, b, pc.dt / 3.0), (b, c, pc.dt / 2.0), (c, b, pc.dt))):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dom.rk_update(a, qs, qo, cdt, final_stage=(s == 2))
+            e1.record(stream)
+            ev.append((e0, e1))
+            dom.diagnose(qo)
+        a, b, c = b, a, c
+    torch.cuda.synchronize()
+    rk_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / len(ev)
+    # leap-frog in p' form
+    q = dom.init_state(W.theta_noise(pc))
+    dom.pform(q, True)
+    qm, q0, qp = dom.new_state(), q, dom.new_state()
+    dom.lf_step(None, q0, qp, pc.dt, 0.1, first=True)
+    qm, q0, qp = q0, qp, qm
+    for _ in range(warmup):
+        dom.lf_step(qm, q0, qp, pc.dt, 0.1)
+        qm, q0, qp = q0, qp, qm
+    torch.cuda.synchronize()
+    ev = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dom.lf_step(qm, q0, qp, pc.dt, 0.1)
+        e1.record(stream)
+        ev.append((e0, e1))
+        qm, q0, qp = q0, qp, qm
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    st = dom.check()
+    if st[:5].any():
+        raise RuntimeError(f"device status counters set: {st}")
+    lf_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / len(ev)
+    # a leap-frog step must read q(n) and qbar(n-1) and write q(n+1) and qbar(n): 20 fields per cell
+    lf_bytes = ncell * 20 * esz
+    return {"diffusion_per_s": pc.kdh, "sponge": {"bottom_m": pc.zsp, "rate_per_s": pc.rsp},
+            "rk3_stage_ms": round(rk_ms, 4), "rk3_cell_updates_per_s": ncell / (rk_ms * 1e-3),
+            "leapfrog": {"value": ncell * steps / secs, "unit": "cell-updates/s (one update per step)",
+                         "ms_per_step": round(lf_ms, 4), "filter_weight": 0.1,
+                         "roofline": roofline(lf_bytes, lf_ms, scope="whole step (p' conversion, update, source "
+                                              "terms, finish and filter, diagnostics)",
+                                              algorithmic_bytes=int(lf_bytes),
+                                              bytes_per_cell=20 * esz)}}
+
+
 def run_ensemble(prec: str, warmup: int):
     """The 64-member ensemble: every member advanced through all its steps by one graph launch of
     the batched kernels (one update and one diagnostic launch per stage for the whole batch)."""
@@ -306,6 +381,8 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--no-second", action="store_true", help="skip the second single-grid workload")
+    ap.add_argument("--no-paper-model", action="store_true",
+                    help="skip the runs with diffusion and sponge (Runge-Kutta and leap-frog)")
     ap.add_argument("--no-other-prec", action="store_true", help="time the chosen precision only")
     ap.add_argument("--tile", type=int, default=0, help="fixed update-kernel tile id (default: autotuned)")
     ap.add_argument("--only", choices=["refined", "ensemble"], default=None,
@@ -346,6 +423,24 @@ def main():
         side = run_gpu(cfg, other, args.steps, args.warmup, args.tile)
         log(f"bench: {cfg.name} {other} {side['value']:.4g} cell-updates/s, {side['ms_per_step']:.3f} ms/step, "
             f"frac {side['roofline']['frac']}")
+    paper = {}
+    if not args.no_paper_model:
+        for p, r in ((args.prec, head), (other, side)):
+            if r is None:
+                continue
+            paper[p] = run_paper_model(cfg, p, min(args.steps, 10), min(args.warmup, 2), r["roofline"]["tile"])
+            base_ms = r["roofline"]["avg_launch_ms"]
+            if base_ms:
+                extra = paper[p]["rk3_stage_ms"] - base_ms
+                paper[p]["source_terms_ms_per_stage"] = round(extra, 4)
+                # the source-term launch reads q_s and reads and writes q_out: 15 fields per cell
+                byts = cfg.nx * cfg.ny * cfg.nz * 15 * (8 if p == "f64" else 4)
+                if extra > 0:
+                    paper[p]["source_terms_roofline"] = roofline(byts, extra, algorithmic_bytes=int(byts),
+                                                                 scope="stage time with minus without")
+            log(f"bench: paper model {p}: RK3 stage {paper[p]['rk3_stage_ms']:.3f} ms with diffusion and sponge; "
+                f"leap-frog {paper[p]['leapfrog']['value']:.4g} cell-updates/s, "
+                f"{paper[p]['leapfrog']['ms_per_step']:.3f} ms/step")
     second = {}
     if not args.no_second:
         name2 = "bell256" if args.workload == "hemi512" else "hemi512"
@@ -389,6 +484,8 @@ def main():
         f64 = head if args.prec == "f64" else side
         out[other] = {"value": side["value"], "ms_per_step": side["ms_per_step"], "roofline": side["roofline"]}
         out["speedup_vs_fp64"] = head["value"] / f64["value"]
+    if paper:
+        out["paper_model"] = {"workload": WORKLOADS[args.workload] + ", with artificial diffusion and sponge", **paper}
     if second:
         out["second_workload"] = second
     if amr:

@@ -7,8 +7,10 @@ The GPU runs the same 100 steps in the launch configuration the benchmark times 
 tuning cache when it holds one for the grid, else the default).
 
 Bars: FP64 within 1e-12 of the field's L-infinity norm at every sampled point, conservation sums
-within 1e-12 of the total mass; FP32 perturbation form within 1e-5 relative per field (L2 over the
-sampled points where the field is defined), mass conserved to 1e-12 of the total mass.
+within 1e-12 of the total mass; FP32 perturbation form within 1e-5 of the field's L-infinity norm at
+every sampled point (the same relative measure as FP64; the momentum perturbation rho u - rhobar_c U0
+also against its own norm), mass conserved to 1e-12 of the total mass.  The L2 error over the
+sampled points is printed beside it.
 """
 import os
 
@@ -103,23 +105,27 @@ def test_fullsize_f32_100_steps_against_oracle(name):
     for f, u in (("mu", cfg.u0), ("mv", cfg.v0)):
         full[f] = np.where(pred, got[f] + rbc[k] * u, got[f] + u)
     errs, linf = {}, {}
+    norm = {"rho": g["linf_rho"], "rth": g["linf_rth"]}
+    for f in ("mu", "mv", "mw"):
+        norm[f], norm[f + "_diag"] = g[f"linf_{f}_pred"], g[f"linf_{f}_diag"]
     for f, m in (("rho", nonsolid), ("rth", nonsolid), ("mu", pred), ("mv", pred), ("mw", pred), ("mu", ~pred),
                  ("mw", ~pred)):
         key = f if (m is nonsolid or m is pred) else f + "_diag"
         ref = g[f][m]
-        if np.linalg.norm(ref) == 0:
+        if norm[key] == 0:
             continue
         errs[key] = np.linalg.norm(full[f][m] - ref) / np.linalg.norm(ref)
-        linf[key] = np.abs(full[f][m] - ref).max() / np.abs(ref).max()
+        linf[key] = np.abs(full[f][m] - ref).max() / norm[key]
     # the perturbation of the horizontal momenta from rhobar_c U0, relative to its own norm
     for f, u in (("mu", cfg.u0), ("mv", cfg.v0)):
         pert_ref = (g[f] - rbc[k] * u)[pred]
-        if np.linalg.norm(pert_ref) > 0:
+        if np.abs(pert_ref).max() > 0:
             errs[f + "_pert"] = np.linalg.norm(got[f][pred] - pert_ref) / np.linalg.norm(pert_ref)
-    print(f"  {name} f32 L2 rel err per field: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+            linf[f + "_pert"] = np.abs(got[f][pred] - pert_ref).max() / np.abs(pert_ref).max()
     print(f"  {name} f32 Linf rel err per field: " + ", ".join(f"{k}={v:.2e}" for k, v in linf.items()),
           flush=True)
-    bad = {k: v for k, v in errs.items() if not v <= 1e-5}
+    print(f"  {name} f32 L2 rel err per field: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    bad = {k: v for k, v in linf.items() if not v <= 1e-5}
     assert not bad, bad
     # mass conserved to 1e-12 of the total, and equal to the oracle's to the same bar
     mtot = g["reduce1"][2]
