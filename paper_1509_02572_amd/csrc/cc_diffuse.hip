@@ -12,10 +12,12 @@
 // apertures and the group volume, as the advective fluxes do, and so stay conserved; momentum uses
 // the perturbation from the reference flow, rho u - rhobar_c (u0, v0, 0), at predicted points.
 // Evaluated in double in the order the CPU reference uses: members of a group from the master along
-// gnext, faces -x,+x,-y,+y,-z,+z, axes x, y, z for momentum.  Where every cell and lattice point
-// within two of the centre is regular (from two levels above the band height to three below the lid)
-// the flux form collapses to the 5-point fourth difference, which a launch of its own evaluates
-// directly; the flux form covers the levels below and above.
+// gnext, faces -x,+x,-y,+y,-z,+z, axes x, y, z for momentum.  Where the cells and lattice points
+// within two of the centre are regular (by the column band tops) the flux form collapses to the
+// 5-point fourth differences in x and y and to the plain flux form along the column (shortened at
+// the ground and the lid), which a launch of its own evaluates directly in the compute precision
+// (float for the float form); a second launch takes the remaining points near the terrain in the
+// general flux form.
 //
 // Sponge: Rayleigh damping -tau(z) q of (rho theta)' at group masters (cell-centre height) and of the
 // momentum perturbation at predicted points (lattice height), tau = rsp sin^2(pi/2 (z - zsp)/(ztop -
@@ -104,65 +106,142 @@ __device__ __forceinline__ double sponge_tau(const Phy &P, double z)
     return P.rsp * (s * s);
 }
 
-// interior form of the fourth difference along the three axes: -(kdh (d4x + d4y) + kdv d4z) of the
-// values v(o) at offsets o from the centre (the flux form collapses to it where every cell and point
-// within two of the centre is regular)
-template <typename V>
-__device__ __forceinline__ double interior_d4(const Phy &P, V v, int64_t c, const int64_t xm[2], const int64_t xp[2],
-                                              const int64_t ym[2], const int64_t yp[2])
+// which parts of point (i, j, k) take the direct stencil, from the column band tops (colk: first k
+// of the regular cells, first K of the predicted lattice points): the cell (ic) when the cells two
+// apart in x and y at its level and those of its own column within two levels are regular; the
+// lattice point (ip) when it is predicted and so are the points two apart in x and y at its level
+// and those of its own column within two levels that exist.  Every level at or above kall (two above
+// the band height) qualifies.
+__device__ __forceinline__ void direct_parts(const Dims &d, const Geo &G, int i, int j, int k, int kall, bool &ic,
+                                             bool &ip)
 {
-    const double v0 = v(c, 0);
-    const double dx4 = (((v(xp[1], 0) - 4.0 * v(xp[0], 0)) + 6.0 * v0) - 4.0 * v(xm[0], 0)) + v(xm[1], 0);
-    const double dy4 = (((v(yp[1], 0) - 4.0 * v(yp[0], 0)) + 6.0 * v0) - 4.0 * v(ym[0], 0)) + v(ym[1], 0);
-    const double dz4 = (((v(c + 2, 2) - 4.0 * v(c + 1, 1)) + 6.0 * v0) - 4.0 * v(c - 1, -1)) + v(c - 2, -2);
-    return -(P.kdh * (dx4 + dy4) + P.kdv * dz4);
+    if (k >= kall) { ic = ip = true; return; }
+    const int64_t nc = (int64_t)d.nx * d.ny;
+    int hc = 0, hl = 0;
+    const int oi[8] = {-2, -1, 1, 2, 0, 0, 0, 0}, oj[8] = {0, 0, 0, 0, -2, -1, 1, 2};
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+        const int64_t cc = (int64_t)wrap(i + oi[n], d.nx) * d.ny + wrap(j + oj[n], d.ny);
+        hc = max(hc, G.colk[cc]);
+        hl = max(hl, G.colk[nc + cc]);
+    }
+    const int64_t c0 = (int64_t)i * d.ny + j;
+    const int kc = G.colk[c0], kl = G.colk[nc + c0];
+    ic = hc <= k && kc <= max(k - 2, 0);
+    ip = hl <= k && kl <= k && kl <= max(k - 2, 1);
 }
 
-// FAST: levels [k0, k1) where every cell and lattice point within two of the centre is regular
-// (k >= band height + 2, k <= nz - 3), interior stencils; otherwise the flux form over levels
-// [k0, k1) and [kt, nz).
-template <typename T, bool FAST>
-__global__ void __launch_bounds__(256) k_diffuse(Dims d, Geo G, Phy P, SIn<T> q, SOut<T> qo, double scale,
-                                                 int final_stage, int k0, int k1, int kt)
+// add scale x (D + S) at one cell / lattice point
+template <typename T>
+__device__ __forceinline__ void apply_scalars(const SOut<T> &qo, int64_t c, double scale, int final_stage,
+                                              double D0, double D1)
 {
-    const int nlo = k1 - k0, nk = nlo + (FAST ? 0 : d.nz - kt);
+    double x0 = (double)qo.rho[c], x1 = (double)qo.rth[c];
+    const bool lo = final_stage && qo.rho_lo;
+    if (lo) {
+        x0 += (double)qo.rho_lo[c];
+        x1 += (double)qo.rth_lo[c];
+    }
+    x0 = x0 + scale * D0;
+    x1 = x1 + scale * D1;
+    const T a = (T)x0, b = (T)x1;
+    qo.rho[c] = a;
+    qo.rth[c] = b;
+    if (lo) {
+        qo.rho_lo[c] = (T)(x0 - (double)a);
+        qo.rth_lo[c] = (T)(x1 - (double)b);
+    }
+}
+
+// INNER: the direct-stencil launch over levels [k0, k1): the parts of each point direct_parts
+// selects, 5-point fourth differences in x and y and the flux form along the column in z (where the
+// ground and the lid shorten it), in the compute precision.  Otherwise the flux form over levels
+// [k0, k1), for the parts the direct launch left (all of them when kall < 0).
+template <typename T, bool INNER>
+__global__ void __launch_bounds__(256) k_diffuse(Dims d, Geo G, Phy P, SIn<T> q, SOut<T> qo, double scale,
+                                                 int final_stage, int k0, int k1, int kall)
+{
+    using R = typename Compute<T>::R;
+    const int nk = k1 - k0;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)d.nx * d.ny * nk) return;
-    const int l = (int)(t % nk);
-    const int k = l < nlo ? k0 + l : kt + (l - nlo);
+    const int k = k0 + (int)(t % nk);
     const int64_t col = t / nk;
     const int j = (int)(col % d.ny), i = (int)(col / d.ny);
     const int64_t c = col * d.nzs + k;
+    const int nz = d.nz;
     const bool diff = P.kdh != 0.0 || P.kdv != 0.0;
-    // the flux-form launch takes the interior form too where the column band tops show every cell and
-    // point within two of the centre regular (most columns away from the terrain)
-    bool inner = FAST;
-    if (!FAST && diff && k >= 2 && k <= d.nz - 3) {
-        const int64_t nc = (int64_t)d.nx * d.ny;
-        auto top = [&](int ii, int jj) {
-            const int64_t cc = (int64_t)wrap(ii, d.nx) * d.ny + wrap(jj, d.ny);
-            return max(G.colk[cc], G.colk[nc + cc]);
-        };
-        inner = k - 2 >= top(i, j) && k >= top(i - 1, j) && k >= top(i - 2, j) && k >= top(i + 1, j) &&
-                k >= top(i + 2, j) && k >= top(i, j - 1) && k >= top(i, j - 2) && k >= top(i, j + 1) &&
-                k >= top(i, j + 2);
-    }
-    int64_t xm[2], xp[2], ym[2], yp[2];
-    if (inner) {
-        xm[0] = cidx(d, i - 1, j, k); xm[1] = cidx(d, i - 2, j, k);
-        xp[0] = cidx(d, i + 1, j, k); xp[1] = cidx(d, i + 2, j, k);
-        ym[0] = cidx(d, i, j - 1, k); ym[1] = cidx(d, i, j - 2, k);
-        yp[0] = cidx(d, i, j + 1, k); yp[1] = cidx(d, i, j + 2, k);
-    }
-    // ---- scalars at a group master ----
+    bool ic = false, ip = false;
+    if (diff && kall >= 0) direct_parts(d, G, i, j, k, kall, ic, ip);
     const int8_t cl = G.cls[c];
+    const bool master = cl == CC_OPEN || cl == CC_ORPHAN, pred = G.vcls[c] == CC_PRED;
     const double tau_c = sponge_tau(P, d.z0 + (k + 0.5) * d.dz);
-    if ((cl == CC_OPEN || cl == CC_ORPHAN) && (diff || tau_c != 0.0)) {
+    const double tau_p = sponge_tau(P, d.z0 + k * d.dz);
+    if (INNER) {
+        if (!ic && !(ip && pred)) return;
+        int64_t xm[2], xp[2], ym[2], yp[2];
+        if (i >= 2 && i + 2 < d.nx && j >= 2 && j + 2 < d.ny) {  // no periodic wrap: plain strides
+            const int64_t sx = (int64_t)d.ny * d.nzs, sy = d.nzs;
+            xm[0] = c - sx; xm[1] = c - 2 * sx; xp[0] = c + sx; xp[1] = c + 2 * sx;
+            ym[0] = c - sy; ym[1] = c - 2 * sy; yp[0] = c + sy; yp[1] = c + 2 * sy;
+        } else {
+            xm[0] = cidx(d, i - 1, j, k); xm[1] = cidx(d, i - 2, j, k);
+            xp[0] = cidx(d, i + 1, j, k); xp[1] = cidx(d, i + 2, j, k);
+            ym[0] = cidx(d, i, j - 1, k); ym[1] = cidx(d, i, j - 2, k);
+            yp[0] = cidx(d, i, j + 1, k); yp[1] = cidx(d, i, j + 2, k);
+        }
+        auto d4h = [&](auto v) {
+            const R v0 = v(c);
+            const R dx4 = (((v(xp[1]) - (R)4 * v(xp[0])) + (R)6 * v0) - (R)4 * v(xm[0])) + v(xm[1]);
+            const R dy4 = (((v(yp[1]) - (R)4 * v(yp[0])) + (R)6 * v0) - (R)4 * v(ym[0])) + v(ym[1]);
+            return dx4 + dy4;
+        };
+        if (ic) {  // a regular cell: its own master, V = 1, open faces
+            R Dv[2];
+            const T *f2[2] = {q.rho, q.rth};
+            for (int w = 0; w < 2; ++w) {
+                const T *f = f2[w];
+                auto v = [&](int64_t p) { return (R)f[p]; };
+                // z flux through the face at level ff (between ff-1 and ff); none through ground and lid
+                auto Fz = [&](int ff) -> R {
+                    if (ff <= 0 || ff >= nz) return (R)0;
+                    const int64_t u = c + (ff - k), l = u - 1;
+                    if (ff - 2 >= 0 && ff + 1 < nz) return (((R)f[u + 1] - (R)3 * (R)f[u]) + (R)3 * (R)f[l]) - (R)f[l - 1];
+                    return (R)-4 * ((R)f[u] - (R)f[l]);
+                };
+                Dv[w] = -((R)P.kdh * d4h(v) + (R)P.kdv * (Fz(k + 1) - Fz(k)));
+            }
+            double D1 = (double)Dv[1];
+            if (tau_c != 0.0) D1 += -tau_c * (double)q.rth[c];
+            apply_scalars<T>(qo, c, scale, final_stage, (double)Dv[0], D1);
+        }
+        if (ip && pred) {
+            const int64_t c0 = (int64_t)i * d.ny + j;
+            const int kl = G.colk[(int64_t)d.nx * d.ny + c0];
+            auto pk = [&](int K) { return K >= kl && K <= nz - 1; };  // predicted points of the column
+            T *mo[3] = {qo.mu, qo.mv, qo.mw};
+            for (int cc = 0; cc < 3; ++cc) {
+                auto m = [&](int64_t p, int K) { return (R)mom_pert(P, q, p, K, cc); };
+                auto v = [&](int64_t p) { return m(p, k); };
+                // z flux between the points at levels ff and ff+1 of the column
+                auto Gz = [&](int ff) -> R {
+                    if (!pk(ff) || !pk(ff + 1)) return (R)0;
+                    const int64_t a = c + (ff - k);
+                    if (pk(ff - 1) && pk(ff + 2))
+                        return ((m(a + 2, ff + 2) - (R)3 * m(a + 1, ff + 1)) + (R)3 * m(a, ff)) - m(a - 1, ff - 1);
+                    return (R)-4 * (m(a + 1, ff + 1) - m(a, ff));
+                };
+                double S = (double)(-((R)P.kdh * d4h(v) + (R)P.kdv * (Gz(k) - Gz(k - 1))));
+                if (tau_p != 0.0) S += -tau_p * mom_pert(P, q, c, k, cc);
+                mo[cc][c] = (T)((double)mo[cc][c] + scale * S);
+            }
+        }
+        return;
+    }
+    // ---- flux form: scalars at a group master ----
+    if (!ic && master && (diff || tau_c != 0.0)) {
         double D0 = 0.0, D1 = 0.0;
-        if (inner) {
-            D0 = interior_d4(P, [&](int64_t p, int) { return (double)q.rho[p]; }, c, xm, xp, ym, yp);
-            D1 = interior_d4(P, [&](int64_t p, int) { return (double)q.rth[p]; }, c, xm, xp, ym, yp);
-        } else if (diff) {
+        if (diff) {
             double acc[2] = {0.0, 0.0};
             int64_t mem = c;
             for (int guard = 0; mem >= 0 && guard <= CC_MAX_GROUP; ++guard) {
@@ -189,41 +268,19 @@ __global__ void __launch_bounds__(256) k_diffuse(Dims d, Geo G, Phy P, SIn<T> q,
             D1 = -acc[1] / vg;
         }
         if (tau_c != 0.0) D1 += -tau_c * (double)q.rth[c];
-        double x0 = (double)qo.rho[c], x1 = (double)qo.rth[c];
-        const bool lo = final_stage && qo.rho_lo;
-        if (lo) {
-            x0 += (double)qo.rho_lo[c];
-            x1 += (double)qo.rth_lo[c];
-        }
-        x0 = x0 + scale * D0;
-        x1 = x1 + scale * D1;
-        const T a = (T)x0, b = (T)x1;
-        qo.rho[c] = a;
-        qo.rth[c] = b;
-        if (lo) {
-            qo.rho_lo[c] = (T)(x0 - (double)a);
-            qo.rth_lo[c] = (T)(x1 - (double)b);
-        }
+        apply_scalars<T>(qo, c, scale, final_stage, D0, D1);
     }
-    // ---- momentum at a predicted point ----
-    const double tau_p = sponge_tau(P, d.z0 + k * d.dz);
-    if (G.vcls[c] == CC_PRED && (diff || tau_p != 0.0)) {
-        double S[3] = {0.0, 0.0, 0.0};
-        if (inner) {
-            for (int cc = 0; cc < 3; ++cc)
-                S[cc] = interior_d4(P, [&](int64_t p, int dk) { return mom_pert(P, q, p, k + dk, cc); }, c, xm, xp,
-                                    ym, yp);
-        } else if (diff) {
-            double acc[3] = {0.0, 0.0, 0.0};
-            for (int a = 0; a < 3; ++a) {
-                const double kr = a == 2 ? P.kdv : P.kdh;
-                double Fp[3], Fm[3];
-                lattice_diff_flux<T>(d, G, P, q, a, i, j, k, Fp);
-                lattice_diff_flux<T>(d, G, P, q, a, i - (a == 0), j - (a == 1), k - (a == 2), Fm);
-                for (int cc = 0; cc < 3; ++cc) acc[cc] += kr * (Fp[cc] - Fm[cc]);
-            }
-            for (int cc = 0; cc < 3; ++cc) S[cc] = -acc[cc];
+    // ---- flux form: momentum at a predicted point ----
+    if (!ip && pred && (diff || tau_p != 0.0)) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; diff && a < 3; ++a) {
+            const double kr = a == 2 ? P.kdv : P.kdh;
+            double Fp[3], Fm[3];
+            lattice_diff_flux<T>(d, G, P, q, a, i, j, k, Fp);
+            lattice_diff_flux<T>(d, G, P, q, a, i - (a == 0), j - (a == 1), k - (a == 2), Fm);
+            for (int cc = 0; cc < 3; ++cc) acc[cc] += kr * (Fp[cc] - Fm[cc]);
         }
+        double S[3] = {-acc[0], -acc[1], -acc[2]};
         if (tau_p != 0.0)
             for (int cc = 0; cc < 3; ++cc) S[cc] += -tau_p * mom_pert(P, q, c, k, cc);
         qo.mu[c] = (T)((double)qo.mu[c] + scale * S[0]);
@@ -245,21 +302,17 @@ void launch_diffuse(const Dims &d, const Geo &G, const Phy &P, const cc_state *q
         const int kmin = kz <= 0.0 ? 0 : (kz >= d.nz ? d.nz : (int)kz);
         if (kmin >= d.nz) return;
         hipLaunchKernelGGL((k_diffuse<T, false>), dim3(blocks_for(nc * (d.nz - kmin), 256)), dim3(256), 0, s, d, G,
-                           P, sin_of<T>(qs), sout_of<T>(qo), scale, final_stage, kmin, d.nz, d.nz);
+                           P, sin_of<T>(qs), sout_of<T>(qo), scale, final_stage, kmin, d.nz, -1);
         return;
     }
-    // interior levels [kf, nz - 2) when the band height is known, the flux form below and above
-    int kf = d.nz, ke = d.nz;
-    if (G.kband >= 1 && G.kband <= d.nz && G.kband + 2 < d.nz - 2) {
-        kf = G.kband + 2;
-        ke = d.nz - 2;
-    }
-    if (kf < ke)
-        hipLaunchKernelGGL((k_diffuse<T, true>), dim3(blocks_for(nc * (ke - kf), 256)), dim3(256), 0, s, d, G, P,
-                           sin_of<T>(qs), sout_of<T>(qo), scale, final_stage, kf, ke, ke);
-    const int nslow = kf + (d.nz - ke);
-    hipLaunchKernelGGL((k_diffuse<T, false>), dim3(blocks_for(nc * nslow, 256)), dim3(256), 0, s, d, G, P,
-                       sin_of<T>(qs), sout_of<T>(qo), scale, final_stage, 0, kf, ke);
+    // the direct stencils over every level (every column from two levels above the band height, below
+    // it where the column band tops allow), then the flux form for what they left below that height
+    const int kall = (G.kband >= 1 && G.kband <= d.nz) ? G.kband + 2 : d.nz;
+    hipLaunchKernelGGL((k_diffuse<T, true>), dim3(blocks_for(nc * d.nz, 256)), dim3(256), 0, s, d, G, P,
+                       sin_of<T>(qs), sout_of<T>(qo), scale, final_stage, 0, d.nz, kall);
+    const int kb = kall < d.nz ? kall : d.nz;
+    hipLaunchKernelGGL((k_diffuse<T, false>), dim3(blocks_for(nc * kb, 256)), dim3(256), 0, s, d, G, P,
+                       sin_of<T>(qs), sout_of<T>(qo), scale, final_stage, 0, kb, kall);
 }
 
 template void launch_diffuse<float>(const Dims &, const Geo &, const Phy &, const cc_state *, cc_state *, double,
