@@ -42,7 +42,7 @@ TILE_TEMPLATE = {0: (8, 8, 8, 1, 1), 1: (4, 4, 16, 1, 1), 2: (8, 4, 16, 1, 1), 3
                  16: (8, 8, 2, 8, 4), 17: (4, 4, 8, 8, 2), 18: (8, 8, 4, 4, 2), 19: (8, 8, 4, 6, 4)}
 # tile ids a batch (ensemble or refined grid) accepts
 BATCH_TILES = (0, 1, 6, 7, 8, 9, 11, 12)
-BATCH_CANDIDATES = (0, 1, 6, 7, 9, 11, 12)
+BATCH_CANDIDATES = (0, 1, 6, 7, 9, 11, 12, 21, 22, 23, 24, 25, 26)  # streaming forms: whole grids only
 REFINED_CANDIDATES = (1, 6, 9, 11)
 
 

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "cc_kernels.hpp"
+#include "cc_stream.hpp"
 
 namespace cc {
 
@@ -280,9 +281,11 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 template <typename T>
 const BlockDesc<T> *descs(const cc_batch_s *b, int l) { return (const BlockDesc<T> *)(b->ws + b->lev[l].desc_off); }
 
-template <typename T, int TX, int TY, int TZ, int MINW>
-void launch_batch_stage(const cc_batch_s *b, int l, int rn, int rs, int ro, double cdt, int fin, int64_t *st,
-                        hipStream_t s)
+// the band points of a level on the side stream, `regular` (the regular-point launch) on s, then the
+// join
+template <typename T, typename F>
+void batch_stage_split(const cc_batch_s *b, int l, int rn, int rs, int ro, double cdt, int fin, int64_t *st,
+                       hipStream_t s, F regular)
 {
     const Level &L = b->lev[l];
     // the points below their column's band top, on the side stream beside the regular points (the
@@ -302,12 +305,21 @@ void launch_batch_stage(const cc_batch_s *b, int l, int rn, int rs, int ro, doub
             hipLaunchKernelGGL((k_stage_batch<T, 2, 2, 16, 0, 1, 2>), dim3(L.ntiles), dim3(64), 0, sb, descs<T>(b, l),
                                L.nblk, L.ntiles, rn, rs, ro, cdt, fin, st);
     }
-    if (L.ntilesr > 0)  // the points at or above their column's band top
-        hipLaunchKernelGGL((k_stage_batch<T, TX, TY, TZ, 0, MINW, 1>), dim3(L.ntilesr), dim3(TX * TY * TZ), 0, s,
-                           descs<T>(b, l), L.nblk, L.ntilesr, rn, rs, ro, cdt, fin, st);
+    if (L.ntilesr > 0) regular();  // the points at or above their column's band top
     // join: later work on s waits for the band launch (should the join fail, the host waits)
     if (sb != s && (hipEventRecord(b->join, sb) != hipSuccess || hipStreamWaitEvent(s, b->join, 0) != hipSuccess))
         (void)hipStreamSynchronize(sb);
+}
+
+template <typename T, int TX, int TY, int TZ, int MINW>
+void launch_batch_stage(const cc_batch_s *b, int l, int rn, int rs, int ro, double cdt, int fin, int64_t *st,
+                        hipStream_t s)
+{
+    const Level &L = b->lev[l];
+    batch_stage_split<T>(b, l, rn, rs, ro, cdt, fin, st, s, [&] {
+        hipLaunchKernelGGL((k_stage_batch<T, TX, TY, TZ, 0, MINW, 1>), dim3(L.ntilesr), dim3(TX * TY * TZ), 0, s,
+                           descs<T>(b, l), L.nblk, L.ntilesr, rn, rs, ro, cdt, fin, st);
+    });
 }
 
 // refill of level ld's ghost cells from level ls: nch chunks of the table at chunk offset ch, whose
@@ -328,7 +340,11 @@ void level_stage(cc_batch_s *b, int l, int rn, int rs, int ro, double cdt, int f
                  hipStream_t s)
 {
     const Level &L = b->lev[l];
-    switch (b->tile) {
+    if (b->tile >= STREAM_ID_MIN && b->tile <= STREAM_ID_MAX) {  // streaming form (whole grids only)
+        batch_stage_split<T>(b, l, rn, rs, ro, cdt, fin, st, s, [&] {
+            launch_stream_batch<T>(b->tile, descs<T>(b, l), L.nblk, L.ntilesr, rn, rs, ro, cdt, fin, st, s);
+        });
+    } else switch (b->tile) {
     case 1: launch_batch_stage<T, 4, 4, 16, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
     case 6: launch_batch_stage<T, 4, 4, 32, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
     case 11: launch_batch_stage<T, 4, 4, 16, 8>(b, l, rn, rs, ro, cdt, fin, st, s); break;
@@ -732,9 +748,11 @@ bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, i
     return true;
 }
 
-// tile shape of a batch: the requested one if every block holds a tile in x and y
-int batch_tile(const cc_block *B, int n, int tile, int &TX, int &TY, int &TZ)
+// tile shape of a batch: the requested one if every block holds a tile in x and y; a streaming form
+// (TX = its chunk of planes) for batches of whole grids when its planes fit in LDS
+int batch_tile(const cc_block *B, int n, int tile, bool own_range, int prec_bytes, int &TX, int &TY, int &TZ)
 {
+    if (!own_range && stream_shape(tile, prec_bytes, TY, TZ, TX)) return tile;
     auto fits = [&](int tx, int ty) {
         for (int m = 0; m < n; ++m)
             if (B[m].grid.nx < tx || B[m].grid.ny < ty) return false;
@@ -808,7 +826,7 @@ bool plan_batch(const cc_block *B, int n, cc_prec prec, int tile, bool own_range
                 Plan &plan, const char *what)
 {
     int TX, TY, TZ, BX, BY, BZ;
-    int id = batch_tile(B, n, tile, TX, TY, TZ);
+    int id = batch_tile(B, n, tile, own_range, prec == CC_F64 ? 8 : 4, TX, TY, TZ);
     int bid = band_tile(B, n, BX, BY, BZ);
     int nl = (int)t.members.size();
     std::vector<Level> lev(nl);

@@ -37,10 +37,12 @@ __device__ __forceinline__ void st_at(T *base, unsigned boff, T v)
 // stored, a barrier, its velocities, a barrier, then the update.  1: rings of 5 and 4 planes, the cells
 // of plane s+2 stored, one barrier, then the velocities of plane s+2 and the update of plane s (a
 // plane's velocities are formed one step before they are read).
-template <typename T, int TY, int TZ, int CH, int MINW, int NBAR>
-__global__ void __launch_bounds__(TY * TZ, MINW)
-    k_stage_stream(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn, SOut<T> qo, double cdt, int final_stage, int nby,
-                   int nbz, int64_t *st)
+// The streaming update of one workgroup: logical block lb of a grid with nby x nbz (j, k) tiles per
+// chunk of CH planes (k tile fastest, then j tile, then chunk).
+template <typename T, int TY, int TZ, int CH, int NBAR>
+__device__ __forceinline__ void stream_body(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &qs,
+                                            const SIn<T> &qn, const SOut<T> &qo, double cdt, int final_stage,
+                                            int nby, int nbz, int lb, int64_t *st)
 {
     using R = typename Compute<T>::R;
     constexpr int NT = TY * TZ;
@@ -62,16 +64,8 @@ __global__ void __launch_bounds__(TY * TZ, MINW)
     const unsigned pstride = (unsigned)ny * (unsigned)nzs;  // elements per x plane
     const R Ux = (R)P.ux, Vy = (R)P.vy;
 
-    // this workgroup's chunk, j-tile and k-tile, dealt to the XCDs in contiguous ranges
-    int ct, jt, kt;
-    {
-        const int b = blockIdx.x, n = gridDim.x;
-        const int xcd = b & 7, idx = b >> 3, per = n >> 3, rem = n & 7;
-        const int lb = xcd * per + (xcd < rem ? xcd : rem) + idx;
-        kt = lb % nbz;
-        jt = (lb / nbz) % nby;
-        ct = lb / (nbz * nby);
-    }
+    // this workgroup's chunk, j-tile and k-tile
+    const int kt = lb % nbz, jt = (lb / nbz) % nby, ct = lb / (nbz * nby);
     const int i_s = ct * CH, i_e = min(i_s + CH, nx);
     const int j0 = jt * TY, k0 = kt * TZ;
     const int tid = threadIdx.x;
@@ -448,6 +442,40 @@ __global__ void __launch_bounds__(TY * TZ, MINW)
     }
 }
 
+// one grid: workgroups dealt to the XCDs in contiguous ranges of logical blocks
+template <typename T, int TY, int TZ, int CH, int MINW, int NBAR>
+__global__ void __launch_bounds__(TY * TZ, MINW)
+    k_stage_stream(Dims d, Geo G, Phy P, SIn<T> qs, SIn<T> qn, SOut<T> qo, double cdt, int final_stage, int nby,
+                   int nbz, int64_t *st)
+{
+    const int b = blockIdx.x, n = gridDim.x;
+    const int xcd = b & 7, idx = b >> 3, per = n >> 3, rem = n & 7;
+    stream_body<T, TY, TZ, CH, NBAR>(d, G, P, qs, qn, qo, cdt, final_stage, nby, nbz,
+                                     xcd * per + (xcd < rem ? xcd : rem) + idx, st);
+}
+
+// a batch of independent grids (ensemble members): the logical blocks of all members in one launch,
+// XCD-aware over the whole batch; each workgroup finds its member by binary search over the members'
+// first logical blocks (tile0r, counted in the streaming decomposition)
+template <typename T, int TY, int TZ, int CH, int MINW, int NBAR>
+__global__ void __launch_bounds__(TY * TZ, MINW)
+    k_stage_stream_batch(const BlockDesc<T> *__restrict__ desc, int nblk, int ntiles, int rn, int rs, int ro,
+                         double cdt, int final_stage, int64_t *st)
+{
+    const int b = blockIdx.x;
+    const int xcd = b & 7, idx = b >> 3, per = ntiles >> 3, rem = ntiles & 7;
+    const int lb = xcd * per + (xcd < rem ? xcd : rem) + idx;
+    int lo = 0, hi = nblk - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (desc[mid].tile0r <= lb) lo = mid;
+        else hi = mid - 1;
+    }
+    const BlockDesc<T> &D = desc[lo];
+    stream_body<T, TY, TZ, CH, NBAR>(D.d, D.G, D.P, as_in(D.q[rs]), as_in(D.q[rn]), D.q[ro], cdt, final_stage,
+                                     D.nby, D.nbz, lb - D.tile0r, st);
+}
+
 // the number of workgroups of a launch over the grid
 static inline unsigned stream_blocks(const Dims &d, int TY, int TZ, int CH)
 {
@@ -494,6 +522,54 @@ bool launch_stream(int id, const Dims &d, const Geo &G, const Phy &P, const cc_s
     default: return false;
     }
 }
+
+bool stream_shape(int id, int prec_bytes, int &TY, int &TZ, int &CH)
+{
+    int ty, tz, ch;
+    switch (id) {
+    case 21: case 22: ty = 8; tz = 32; ch = 32; break;
+    case 23: case 26: ty = 8; tz = 16; ch = 32; break;
+    case 24: case 25: ty = 8; tz = 32; ch = 64; break;
+    default: return false;
+    }
+    const int nbar = (id == 22 || id == 23 || id == 25) ? 1 : 2;
+    const size_t RC = nbar == 1 ? 5 : 4, RV = nbar == 1 ? 4 : 3;
+    const size_t lds = (size_t)prec_bytes * (RC * (ty + 3) * (tz + 3) + RC * (ty + 2) * (tz + 2) +
+                                             RC * (ty + 1) * (tz + 1) + 3 * RV * (ty + 2) * (tz + 2) + 6 * (tz + 4));
+    if (lds > 65536) return false;
+    TY = ty; TZ = tz; CH = ch;
+    return true;
+}
+
+template <typename T, int TY, int TZ, int CH, int MINW, int NBAR>
+static void launch_stream_batch_t(const void *desc, int nblk, int ntiles, int rn, int rs, int ro, double cdt,
+                                  int final_stage, int64_t *st, hipStream_t s)
+{
+    if constexpr (stream_lds_bytes<typename Compute<T>::R, TY, TZ, NBAR>() <= 65536)
+        hipLaunchKernelGGL((k_stage_stream_batch<T, TY, TZ, CH, MINW, NBAR>), dim3(ntiles), dim3(TY * TZ), 0, s,
+                           (const BlockDesc<T> *)desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st);
+}
+
+template <typename T>
+void launch_stream_batch(int id, const void *desc, int nblk, int ntiles, int rn, int rs, int ro, double cdt,
+                         int final_stage, int64_t *st, hipStream_t s)
+{
+    constexpr int W = sizeof(T) == 4 ? 3 : 1;
+    switch (id) {
+    case 21: launch_stream_batch_t<T, 8, 32, 32, W, 2>(desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st, s); break;
+    case 22: launch_stream_batch_t<T, 8, 32, 32, W, 1>(desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st, s); break;
+    case 23: launch_stream_batch_t<T, 8, 16, 32, W, 1>(desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st, s); break;
+    case 24: launch_stream_batch_t<T, 8, 32, 64, W, 2>(desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st, s); break;
+    case 25: launch_stream_batch_t<T, 8, 32, 64, W, 1>(desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st, s); break;
+    case 26: launch_stream_batch_t<T, 8, 16, 32, W, 2>(desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st, s); break;
+    default: break;
+    }
+}
+
+template void launch_stream_batch<float>(int, const void *, int, int, int, int, int, double, int, int64_t *,
+                                         hipStream_t);
+template void launch_stream_batch<double>(int, const void *, int, int, int, int, int, double, int, int64_t *,
+                                          hipStream_t);
 
 template bool launch_stream<float>(int, const Dims &, const Geo &, const Phy &, const cc_state *, const cc_state *,
                                    cc_state *, double, int, int64_t *, hipStream_t);

@@ -17,4 +17,16 @@ template <typename T>
 bool launch_stream(int id, const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
                    cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s);
 
+// Shape of streaming form `id` (TY x TZ threads, chunks of CH planes); false when `id` is not a
+// streaming form or its planes do not fit in the LDS of a workgroup at prec_bytes per value.
+bool stream_shape(int id, int prec_bytes, int &TY, int &TZ, int &CH);
+
+// The regular points of a batch of whole grids (ensemble members) with streaming form `id`: desc is
+// the level's BlockDesc<T> table, whose tile0r / nby / nbz count the streaming decomposition
+// (CH-plane chunks x TY x TZ); ntiles workgroups in all.  Nothing is launched for a form that
+// stream_shape refuses.
+template <typename T>
+void launch_stream_batch(int id, const void *desc, int nblk, int ntiles, int rn, int rs, int ro, double cdt,
+                         int final_stage, int64_t *st, hipStream_t s);
+
 }  // namespace cc
