@@ -82,7 +82,7 @@ typedef struct {
     double dx, dy, dz;       /* spacings [m] */
     int32_t nsub;            /* sub-columns per cell edge for volumes/apertures, power of two */
     int32_t tile;            /* tile shape of the update kernel (0 = default; 1..20 three-dimensional
-                                tiles, 21..26 streaming forms, see the tuning table of the stage
+                                tiles, 21..29 streaming forms, see the tuning table of the stage
                                 kernels); results do not depend on it */
     double z0;               /* height of the grid's bottom face above the terrain datum [m]: 0 for
                                 a grid standing on the ground; > 0 for a block of a refined grid

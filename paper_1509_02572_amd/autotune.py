@@ -27,11 +27,12 @@ TILE_IDS = {1: (4, 4, 16), 2: (8, 4, 16), 3: (4, 8, 16), 4: (8, 8, 8), 5: (2, 4,
             7: (8, 8, 16), 8: (2, 2, 64), 9: (8, 8, 8), 10: (8, 8, 8), 11: (4, 4, 16), 12: (4, 8, 16),
             13: (8, 8, 16), 14: (8, 8, 16), 15: (8, 8, 8), 16: (8, 8, 8), 17: (4, 4, 16), 18: (8, 8, 8),
             19: (8, 8, 16), 20: (1, 1, 1),
-            21: (8, 32), 22: (8, 32), 23: (8, 16), 24: (8, 32), 25: (8, 32), 26: (8, 16)}
-# ids 21-26: streaming forms of the regular points, (TY, TZ) threads over a j-k cross-section
+            21: (8, 32), 22: (8, 32), 23: (8, 16), 24: (8, 32), 25: (8, 32), 26: (8, 16), 27: (16, 16),
+            28: (16, 16), 29: (16, 32)}
+# ids 21-29: streaming forms of the regular points, (TY, TZ) threads over a j-k cross-section
 # marching along x through chunks of STREAM_CHUNK planes with STREAM_NBAR barriers per plane
-STREAM_CHUNK = {21: 32, 22: 32, 23: 32, 24: 64, 25: 64, 26: 32}
-STREAM_NBAR = {21: 2, 22: 1, 23: 1, 24: 2, 25: 1, 26: 2}
+STREAM_CHUNK = {21: 32, 22: 32, 23: 32, 24: 64, 25: 64, 26: 32, 27: 32, 28: 32, 29: 32}
+STREAM_NBAR = {21: 2, 22: 1, 23: 1, 24: 2, 25: 1, 26: 2, 27: 1, 28: 2, 29: 2}
 TILE_MINW = {9: 6, 10: 8, 11: 8, 12: 6, 13: 4, 14: 6, 15: 6, 16: 8, 17: 8, 18: 4, 19: 6}
 # id -> template arguments of k_stage_tiled: threads per tile (TX, TY, TZ), minimum waves, points per
 # thread along k
@@ -42,7 +43,7 @@ TILE_TEMPLATE = {0: (8, 8, 8, 1, 1), 1: (4, 4, 16, 1, 1), 2: (8, 4, 16, 1, 1), 3
                  16: (8, 8, 2, 8, 4), 17: (4, 4, 8, 8, 2), 18: (8, 8, 4, 4, 2), 19: (8, 8, 4, 6, 4)}
 # tile ids a batch (ensemble or refined grid) accepts
 BATCH_TILES = (0, 1, 6, 7, 8, 9, 11, 12)
-BATCH_CANDIDATES = (0, 1, 6, 7, 9, 11, 12, 21, 22, 23, 24, 25, 26)  # streaming forms: whole grids only
+BATCH_CANDIDATES = (0, 1, 6, 7, 9, 11, 12, 21, 22, 23, 24, 25, 26, 27, 28, 29)  # streaming forms: whole grids only
 REFINED_CANDIDATES = (1, 6, 9, 11)
 
 
@@ -58,7 +59,7 @@ def kernel_names(tile: int, prec: str, small: bool = False):
     band = "4, 4, 4" if small else "8, 8, 1"
     if tile in STREAM_CHUNK:
         ty, tz = TILE_IDS[tile]
-        w = 3 if prec == "f32" else 1
+        w = 4 if prec == "f32" else 1
         return (f"cc::k_stage_stream<{t}, {ty}, {tz}, {STREAM_CHUNK[tile]}, {w}, {STREAM_NBAR[tile]}>",
                 f"cc::k_stage_tiled<{t}, {band}, 0, 1, 1, false, 2>")
     tx, ty, tz, w, kp = TILE_TEMPLATE[tile]

@@ -752,7 +752,12 @@ bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, i
 // (TX = its chunk of planes) for batches of whole grids when its planes fit in LDS
 int batch_tile(const cc_block *B, int n, int tile, bool own_range, int prec_bytes, int &TX, int &TY, int &TZ)
 {
-    if (!own_range && stream_shape(tile, prec_bytes, TY, TZ, TX)) return tile;
+    auto offsets_fit = [&] {
+        for (int m = 0; m < n; ++m)
+            if (!stream_offsets_fit(B[m].grid.nx, B[m].grid.ny, B[m].grid.nzs, prec_bytes)) return false;
+        return true;
+    };
+    if (!own_range && stream_shape(tile, prec_bytes, TY, TZ, TX) && offsets_fit()) return tile;
     auto fits = [&](int tx, int ty) {
         for (int m = 0; m < n; ++m)
             if (B[m].grid.nx < tx || B[m].grid.ny < ty) return false;

@@ -55,13 +55,18 @@ __device__ __forceinline__ void stream_body(const Dims &d, const Geo &G, const P
     constexpr int NB = TZ + 4;  // staged base levels k0-2 .. k0+TZ+1
     constexpr int IC = (NC + NT - 1) / NT, IH = (NH + NT - 1) / NT;
     constexpr int RC = NBAR == 1 ? 5 : 4, RV = NBAR == 1 ? 4 : 3;  // ring slots: cell planes, lattice planes
-    __shared__ R s_rho[RC][NC], s_rth[RC][NH], s_pp[RC][NPP];
-    __shared__ R s_u[RV][NH], s_v[RV][NH], s_w[RV][NH];
+    // one spare element at the end of each box takes the stores of staging entries outside it, so that
+    // the stores need no per-lane conditions
+    __shared__ R s_rho[RC][NC + 1], s_rth[RC][NH + 1], s_pp[RC][NPP + 1];
+    __shared__ R s_u[RV][NH + 1], s_v[RV][NH + 1], s_w[RV][NH + 1];
     __shared__ R s_b[6][NB];
 
     const int nx = d.nx, ny = d.ny, nz = d.nz, nzs = d.nzs;
     const unsigned ncol = (unsigned)(nx * ny);
     const unsigned pstride = (unsigned)ny * (unsigned)nzs;  // elements per x plane
+    // every global access below is the array's base plus a 32-bit byte offset (the launchers take this
+    // form only for grids whose arrays stay below 4 GiB), so that no per-plane 64-bit addresses are formed
+    const unsigned pbytes = pstride * (unsigned)sizeof(T);
     const R Ux = (R)P.ux, Vy = (R)P.vy;
 
     // this workgroup's chunk, j-tile and k-tile
@@ -87,9 +92,9 @@ __device__ __forceinline__ void stream_body(const Dims &d, const Geo &G, const P
         c_off[it] = c_ok[it] ? ((unsigned)jj * (unsigned)nzs + (unsigned)kk) * (unsigned)sizeof(T) : 0u;
         c_lev[it] = cc;  // staged base level of the cell
         const bool in_h = e < NC && r >= 1 && r <= TY + 2 && cc >= 1 && cc <= TZ + 2;
-        c_rth[it] = in_h ? (r - 1) * HW + (cc - 1) : -1;
+        c_rth[it] = in_h ? (r - 1) * HW + (cc - 1) : NH;
         const bool in_p = e < NC && r >= 1 && r <= TY + 1 && cc >= 1 && cc <= TZ + 1;
-        c_pp[it] = in_p ? (r - 1) * PW + (cc - 1) : -1;
+        c_pp[it] = in_p ? (r - 1) * PW + (cc - 1) : NPP;
     }
     // lattice elements: offset of the (clamped) lattice level within a plane, column index within a
     // plane, rho' slot of the cell (J-1, Kc-1) in the cell box, lid flag
@@ -130,21 +135,22 @@ __device__ __forceinline__ void stream_body(const Dims &d, const Geo &G, const P
     R p_rho[IC], p_rth[IC], p_m0[IH], p_m1[IH], p_m2[IH];
     int p_kb[IH];
     auto load_plane = [&](int ip) {
-        const unsigned base = (unsigned)wrap(ip, nx) * pstride;
-        const T *rho = qs.rho + base, *rth = qs.rth + base;
+        const unsigned ib = (unsigned)wrap(ip, nx);
+        const unsigned pb = ib * pbytes;
 #pragma unroll
         for (int it = 0; it < IC; ++it) {
-            p_rho[it] = c_ok[it] ? (R)ld_at(rho, c_off[it]) : (R)0;
-            p_rth[it] = c_ok[it] ? (R)ld_at(rth, c_off[it]) : (R)0;
+            const unsigned o = pb + c_off[it];
+            p_rho[it] = c_ok[it] ? (R)ld_at(qs.rho, o) : (R)0;
+            p_rth[it] = c_ok[it] ? (R)ld_at(qs.rth, o) : (R)0;
         }
-        const T *mu = qs.mu + base, *mv = qs.mv + base, *mw = qs.mw + base;
-        const int *kb = G.colk + ncol + (unsigned)wrap(ip, nx) * (unsigned)ny;
+        const unsigned kbo = (ncol + ib * (unsigned)ny) * (unsigned)sizeof(int);
 #pragma unroll
         for (int it = 0; it < IH; ++it) {
-            p_m0[it] = l_ok[it] ? (R)ld_at(mu, l_off[it]) : (R)0;
-            p_m1[it] = l_ok[it] ? (R)ld_at(mv, l_off[it]) : (R)0;
-            p_m2[it] = l_ok[it] ? (R)ld_at(mw, l_off[it]) : (R)0;
-            p_kb[it] = l_ok[it] ? ld_at(kb, l_col[it]) : 0;
+            const unsigned o = pb + l_off[it];
+            p_m0[it] = l_ok[it] ? (R)ld_at(qs.mu, o) : (R)0;
+            p_m1[it] = l_ok[it] ? (R)ld_at(qs.mv, o) : (R)0;
+            p_m2[it] = l_ok[it] ? (R)ld_at(qs.mw, o) : (R)0;
+            p_kb[it] = l_ok[it] ? ld_at(G.colk, kbo + l_col[it]) : 0;
         }
     };
     // rho', (rho theta)' and p' of the loaded plane into ring slot sl
@@ -152,28 +158,24 @@ __device__ __forceinline__ void stream_body(const Dims &d, const Geo &G, const P
 #pragma unroll
         for (int it = 0; it < IC; ++it) {
             const int e = tid + it * NT;
-            if (e < NC) s_rho[sl][e] = p_rho[it];
-            if (c_rth[it] >= 0) s_rth[sl][c_rth[it]] = p_rth[it];
-            if (c_pp[it] >= 0) {
-                const int kk = k0 - 2 + c_lev[it];
-                R pp = (R)0;
-                if (kk >= 0 && kk < nz) pp = eos_staged<R>(p_rth[it], s_b[3][c_lev[it]], s_b[2][c_lev[it]], P);
-                s_pp[sl][c_pp[it]] = pp;
-            }
+            s_rho[sl][e < NC ? e : NC] = p_rho[it];
+            s_rth[sl][c_rth[it]] = p_rth[it];
+            R pp = (R)0;  // zero outside the grid in k
+            if (c_ok[it]) pp = eos_staged<R>(p_rth[it], s_b[3][c_lev[it]], s_b[2][c_lev[it]], P);
+            s_pp[sl][c_pp[it]] = pp;
         }
     };
     // velocities of lattice plane ip (cells of the old plane ring slot so and the new one sn) into
     // velocity slot sv; the momentum of the plane is in the load registers
     auto store_vel = [&](int ip, int so, int sn, int sv) {
-        const unsigned base = (unsigned)wrap(ip, nx) * pstride;
+        const unsigned base = (unsigned)wrap(ip, nx) * pstride;  // vcls holds one byte per cell
 #pragma unroll
         for (int it = 0; it < IH; ++it) {
             const int e = tid + it * NT;
-            if (e >= NH) continue;
             R u0 = (R)0, u1 = (R)0, u2 = (R)0;
             if (l_ok[it]) {
                 const int Kc = l_kc[it];
-                const bool pred = Kc >= p_kb[it] || G.vcls[base + l_off[it] / (unsigned)sizeof(T)] == CC_PRED;
+                const bool pred = Kc >= p_kb[it] || ld_at(G.vcls, base + l_off[it] / (unsigned)sizeof(T)) == CC_PRED;
                 if (pred) {
                     const R *ro = s_rho[so] + l_rho[it], *rn = s_rho[sn] + l_rho[it];
                     R sm = ((ro[0] + rn[0]) + (ro[CW] + rn[CW])) + ((ro[1] + rn[1]) + (ro[CW + 1] + rn[CW + 1]));
@@ -189,15 +191,19 @@ __device__ __forceinline__ void stream_body(const Dims &d, const Geo &G, const P
                 }
                 if (l_lid[it]) u2 = (R)0;
             }
-            s_u[sv][e] = u0;
-            s_v[sv][e] = u1;
-            s_w[sv][e] = u2;
+            const int eh = e < NH ? e : NH;
+            s_u[sv][eh] = u0;
+            s_v[sv][eh] = u1;
+            s_w[sv][eh] = u2;
         }
     };
 
-    // ring slots of cell plane p and lattice plane p (p >= i_s - 2)
+    // ring slots of cell plane p and lattice plane p (p >= i_s - 2); inside the loop the slots advance
+    // by one per plane
     auto cslot = [&](int p) { return (p - i_s + 2 * RC) % RC; };
     auto vslot = [&](int p) { return (p - i_s + 2 * RV) % RV; };
+    auto cnext = [](int x) { return x + 1 == RC ? 0 : x + 1; };
+    auto vnext = [](int x) { return x + 1 == RV ? 0 : x + 1; };
     // ---- prologue: cell planes i_s-2 .. i_s (i_s+1 with one barrier per plane), their lattice planes
     // from i_s-1, and the loads of the next plane in flight ----
     load_plane(i_s - 2);
@@ -224,30 +230,33 @@ __device__ __forceinline__ void stream_body(const Dims &d, const Geo &G, const P
     const R ix = (R)P.idx, iy = (R)P.idy, iz = (R)P.idz;
     // x-face fluxes carried from the previous plane: scalars (rho', (rho theta)') and momentum
     R cm0 = (R)0, cm1 = (R)0, cmx[3] = {(R)0, (R)0, (R)0};
+    int c_first = cslot(i_s - 1), v_first = vslot(i_s - 1);  // slots of plane s-1
 
     for (int s = i_s; s < i_e; ++s) {
-        const int sm1 = cslot(s - 1), s0 = cslot(s), sp1 = cslot(s + 1);
-        const int vm1 = vslot(s - 1), v0 = vslot(s), vp1 = vslot(s + 1);
+        const int sm1 = c_first, s0 = cnext(sm1), sp1 = cnext(s0), sp2 = cnext(sp1);
+        const int vm1 = v_first, v0 = vnext(vm1), vp1 = vnext(v0), vp2 = vnext(vp1);
+        c_first = s0;
+        v_first = v0;
         // q_n at this thread's point of plane s and its column's band tops: loaded first, so that they
         // arrive while the rings are filled
         const int i = s;  // s < i_e <= nx
-        const unsigned c = (j * (unsigned)nzs + (unsigned)k) * (unsigned)sizeof(T);  // within the plane
-        const unsigned pbase = (unsigned)i * pstride;
+        // byte offset of this thread's point (i, j, k)
+        const unsigned c = (unsigned)i * pbytes + (j * (unsigned)nzs + (unsigned)k) * (unsigned)sizeof(T);
         T n_rho = (T)0, n_rth = (T)0, n_rlo = (T)0, n_tlo = (T)0, n_mu = (T)0, n_mv = (T)0, n_mw = (T)0;
         int kcell = 0, klat = 0;
         if (inside) {
-            const int *ck = G.colk + (unsigned)i * (unsigned)ny;
-            kcell = ld_at(ck, (unsigned)j * 4u);
-            klat = ld_at(ck + ncol, (unsigned)j * 4u);
-            n_rho = ld_at(qn.rho + pbase, c);
-            n_rth = ld_at(qn.rth + pbase, c);
+            const unsigned co = ((unsigned)i * (unsigned)ny + (unsigned)j) * (unsigned)sizeof(int);
+            kcell = ld_at(G.colk, co);
+            klat = ld_at(G.colk, co + ncol * (unsigned)sizeof(int));
+            n_rho = ld_at(qn.rho, c);
+            n_rth = ld_at(qn.rth, c);
             if (final_stage && qo.rho_lo && qn.rho_lo) {
-                n_rlo = ld_at(qn.rho_lo + pbase, c);
-                n_tlo = ld_at(qn.rth_lo + pbase, c);
+                n_rlo = ld_at(qn.rho_lo, c);
+                n_tlo = ld_at(qn.rth_lo, c);
             }
-            n_mu = ld_at(qn.mu + pbase, c);
-            n_mv = ld_at(qn.mv + pbase, c);
-            n_mw = ld_at(qn.mw + pbase, c);
+            n_mu = ld_at(qn.mu, c);
+            n_mv = ld_at(qn.mv, c);
+            n_mw = ld_at(qn.mw, c);
         }
         if constexpr (NBAR == 2) {
             // the loaded plane s+1 into the rings, a barrier, its lattice velocities, a barrier
@@ -260,9 +269,9 @@ __device__ __forceinline__ void stream_body(const Dims &d, const Geo &G, const P
         } else {
             // the loaded plane s+2 into the rings, a barrier, its lattice velocities (read from the next
             // step on), the loads of plane s+3, then the update of plane s
-            if (s + 2 <= i_e) store_cells(cslot(s + 2));
+            if (s + 2 <= i_e) store_cells(sp2);
             __syncthreads();
-            if (s + 2 <= i_e) store_vel(s + 2, sp1, cslot(s + 2), vslot(s + 2));
+            if (s + 2 <= i_e) store_vel(s + 2, sp1, sp2, vp2);
             if (s + 3 <= i_e) load_plane(s + 3);
         }
         const bool mine = inside && k >= band_top(kcell, klat);
@@ -408,7 +417,6 @@ __device__ __forceinline__ void stream_body(const Dims &d, const Geo &G, const P
 
         // ---- the stage update of cell (i,j,k) and lattice point (i,j,k) ----
         if (mine) {
-            const unsigned pb = pbase;
             bool bad;
             {
                 double x0 = (double)n_rho, x1 = (double)n_rth;
@@ -420,11 +428,11 @@ __device__ __forceinline__ void stream_body(const Dims &d, const Geo &G, const P
                 x1 = fmaR(cdt, L1, x1);
                 const T a = (T)x0, bb = (T)x1;
                 bad = !isfinite(a) || !isfinite(bb);
-                st_at(qo.rho + pb, c, a);
-                st_at(qo.rth + pb, c, bb);
+                st_at(qo.rho, c, a);
+                st_at(qo.rth, c, bb);
                 if (final_stage && qo.rho_lo) {
-                    st_at(qo.rho_lo + pb, c, (T)(x0 - (double)a));
-                    st_at(qo.rth_lo + pb, c, (T)(x1 - (double)bb));
+                    st_at(qo.rho_lo, c, (T)(x0 - (double)a));
+                    st_at(qo.rth_lo, c, (T)(x1 - (double)bb));
                 }
             }
             if (k >= 1) {
@@ -433,9 +441,9 @@ __device__ __forceinline__ void stream_body(const Dims &d, const Geo &G, const P
                 const T bb = (T)fmaR(cd, Lm[1], (R)n_mv);
                 const T e = (T)fmaR(cd, Lm[2], (R)n_mw);
                 bad = bad || !isfinite(a) || !isfinite(bb) || !isfinite(e);
-                st_at(qo.mu + pb, c, a);
-                st_at(qo.mv + pb, c, bb);
-                st_at(qo.mw + pb, c, e);
+                st_at(qo.mu, c, a);
+                st_at(qo.mv, c, bb);
+                st_at(qo.mw, c, e);
             }
             if (bad) count_status(st, ST_NONFINITE);
         }
@@ -476,6 +484,12 @@ __global__ void __launch_bounds__(TY * TZ, MINW)
                                      D.nby, D.nbz, lb - D.tile0r, st);
 }
 
+// the streaming kernels address every array with 32-bit byte offsets
+bool stream_offsets_fit(int nx, int ny, int nzs, int prec_bytes)
+{
+    return (uint64_t)nx * (uint64_t)ny * (uint64_t)nzs * (uint64_t)prec_bytes <= (uint64_t)UINT32_MAX;
+}
+
 // the number of workgroups of a launch over the grid
 static inline unsigned stream_blocks(const Dims &d, int TY, int TZ, int CH)
 {
@@ -488,8 +502,8 @@ template <typename R, int TY, int TZ, int NBAR>
 constexpr size_t stream_lds_bytes()
 {
     constexpr size_t RC = NBAR == 1 ? 5 : 4, RV = NBAR == 1 ? 4 : 3;
-    return sizeof(R) * (RC * (size_t)(TY + 3) * (TZ + 3) + RC * (size_t)(TY + 2) * (TZ + 2) +
-                        RC * (size_t)(TY + 1) * (TZ + 1) + 3 * RV * (size_t)(TY + 2) * (TZ + 2) +
+    return sizeof(R) * (RC * ((size_t)(TY + 3) * (TZ + 3) + 1) + RC * ((size_t)(TY + 2) * (TZ + 2) + 1) +
+                        RC * ((size_t)(TY + 1) * (TZ + 1) + 1) + 3 * RV * ((size_t)(TY + 2) * (TZ + 2) + 1) +
                         6 * (size_t)(TZ + 4));
 }
 
@@ -500,6 +514,7 @@ static bool launch_stream_t(const Dims &d, const Geo &G, const Phy &P, const cc_
     if constexpr (stream_lds_bytes<typename Compute<T>::R, TY, TZ, NBAR>() > 65536) {
         return false;
     } else {
+        if (!stream_offsets_fit(d.nx, d.ny, d.nzs, (int)sizeof(T))) return false;
         const int nby = (d.ny + TY - 1) / TY, nbz = (d.nz + TZ - 1) / TZ;
         hipLaunchKernelGGL((k_stage_stream<T, TY, TZ, CH, MINW, NBAR>), dim3(stream_blocks(d, TY, TZ, CH)), dim3(TY * TZ), 0,
                            s, d, G, P, sin_of<T>(qs), sin_of<T>(qn), sout_of<T>(qo), cdt, final_stage, nby, nbz, st);
@@ -511,7 +526,8 @@ template <typename T>
 bool launch_stream(int id, const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, const cc_state *qn,
                    cc_state *qo, double cdt, int final_stage, int64_t *st, hipStream_t s)
 {
-    constexpr int W = sizeof(T) == 4 ? 3 : 1;  // float: registers capped for 3 waves per SIMD
+    // float: registers capped for 4 waves per SIMD
+    constexpr int W = sizeof(T) == 4 ? 4 : 1;
     switch (id) {
     case 21: return launch_stream_t<T, 8, 32, 32, W, 2>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
     case 22: return launch_stream_t<T, 8, 32, 32, W, 1>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
@@ -519,6 +535,9 @@ bool launch_stream(int id, const Dims &d, const Geo &G, const Phy &P, const cc_s
     case 24: return launch_stream_t<T, 8, 32, 64, W, 2>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
     case 25: return launch_stream_t<T, 8, 32, 64, W, 1>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
     case 26: return launch_stream_t<T, 8, 16, 32, W, 2>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
+    case 27: return launch_stream_t<T, 16, 16, 32, W, 1>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
+    case 28: return launch_stream_t<T, 16, 16, 32, W, 2>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
+    case 29: return launch_stream_t<T, 16, 32, 32, W, 2>(d, G, P, qs, qn, qo, cdt, final_stage, st, s);
     default: return false;
     }
 }
@@ -530,12 +549,15 @@ bool stream_shape(int id, int prec_bytes, int &TY, int &TZ, int &CH)
     case 21: case 22: ty = 8; tz = 32; ch = 32; break;
     case 23: case 26: ty = 8; tz = 16; ch = 32; break;
     case 24: case 25: ty = 8; tz = 32; ch = 64; break;
+    case 27: case 28: ty = 16; tz = 16; ch = 32; break;
+    case 29: ty = 16; tz = 32; ch = 32; break;
     default: return false;
     }
-    const int nbar = (id == 22 || id == 23 || id == 25) ? 1 : 2;
+    const int nbar = (id == 22 || id == 23 || id == 25 || id == 27) ? 1 : 2;
     const size_t RC = nbar == 1 ? 5 : 4, RV = nbar == 1 ? 4 : 3;
-    const size_t lds = (size_t)prec_bytes * (RC * (ty + 3) * (tz + 3) + RC * (ty + 2) * (tz + 2) +
-                                             RC * (ty + 1) * (tz + 1) + 3 * RV * (ty + 2) * (tz + 2) + 6 * (tz + 4));
+    const size_t lds = (size_t)prec_bytes * (RC * ((ty + 3) * (tz + 3) + 1) + RC * ((ty + 2) * (tz + 2) + 1) +
+                                             RC * ((ty + 1) * (tz + 1) + 1) + 3 * RV * ((ty + 2) * (tz + 2) + 1) +
+                                             6 * (tz + 4));
     if (lds > 65536) return false;
     TY = ty; TZ = tz; CH = ch;
     return true;
@@ -554,7 +576,7 @@ template <typename T>
 void launch_stream_batch(int id, const void *desc, int nblk, int ntiles, int rn, int rs, int ro, double cdt,
                          int final_stage, int64_t *st, hipStream_t s)
 {
-    constexpr int W = sizeof(T) == 4 ? 3 : 1;
+    constexpr int W = sizeof(T) == 4 ? 4 : 1;
     switch (id) {
     case 21: launch_stream_batch_t<T, 8, 32, 32, W, 2>(desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st, s); break;
     case 22: launch_stream_batch_t<T, 8, 32, 32, W, 1>(desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st, s); break;
@@ -562,6 +584,9 @@ void launch_stream_batch(int id, const void *desc, int nblk, int ntiles, int rn,
     case 24: launch_stream_batch_t<T, 8, 32, 64, W, 2>(desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st, s); break;
     case 25: launch_stream_batch_t<T, 8, 32, 64, W, 1>(desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st, s); break;
     case 26: launch_stream_batch_t<T, 8, 16, 32, W, 2>(desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st, s); break;
+    case 27: launch_stream_batch_t<T, 16, 16, 32, W, 1>(desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st, s); break;
+    case 28: launch_stream_batch_t<T, 16, 16, 32, W, 2>(desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st, s); break;
+    case 29: launch_stream_batch_t<T, 16, 32, 32, W, 2>(desc, nblk, ntiles, rn, rs, ro, cdt, final_stage, st, s); break;
     default: break;
     }
 }

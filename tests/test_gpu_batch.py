@@ -48,7 +48,7 @@ def test_small_batch_matches_single_domains_bitwise(prec):
     cfgs = _small_ensemble()
     print("case small ensemble", prec, [(c.nx, c.ny, c.nz) for c in cfgs], flush=True)
     doms, states = _members(cfgs, prec)
-    for tile in (0, 1, 6, 7, 8, 9, 11, 12, 21, 22, 23, 24, 25, 26):
+    for tile in (0, 1, 6, 7, 8, 9, 11, 12, 21, 22, 23, 24, 25, 26, 27, 28, 29):
         batch = CC.Batch(doms, states, tile=tile)
         batch.step(cfgs[0].dt, 3)
         torch.cuda.synchronize()
