@@ -1170,13 +1170,15 @@ __device__ bool plane_family(const Dims &d, const Geo &G, const Phy &P, const SI
         }
         w[m][0] = (1.0 - a) * (1.0 - b); w[m][1] = a * (1.0 - b); w[m][2] = (1.0 - a) * b; w[m][3] = a * b;
     }
-    // classes of the valid planes' corners (every corner index of a valid plane is in range)
+    // classes of the valid planes' corners of nonzero weight (every corner index of a valid plane is
+    // in range; a corner of zero weight does not enter the mean, whatever its class)
     int8_t vc[3][4];
 #pragma unroll
     for (int m = 0; m < 3; ++m)
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-            vc[m][s] = valid[m] ? G.vcls[cidx(d, P4[m][s][0], P4[m][s][1], P4[m][s][2])] : (int8_t)CC_GROUND;
+            vc[m][s] = valid[m] && w[m][s] != 0.0 ? G.vcls[cidx(d, P4[m][s][0], P4[m][s][1], P4[m][s][2])]
+                                                  : (int8_t)CC_GROUND;
     int pick = -1;
     for (int m = 0; m < 3 && pick < 0; ++m) {
         if (!valid[m]) {
@@ -1196,13 +1198,12 @@ __device__ bool plane_family(const Dims &d, const Geo &G, const Phy &P, const SI
         for (int e = 0; e < 3; ++e) C4[s][e] = pick == 0 ? P4[0][s][e] : (pick == 1 ? P4[1][s][e] : P4[2][s][e]);
         wp[s] = pick == 0 ? w[0][s] : (pick == 1 ? w[1][s] : w[2][s]);
     }
-    R v[4][3];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) lat_vel_pred<T>(d, P, q, C4[s][0], C4[s][1], C4[s][2] > 1 ? C4[s][2] : 1, v[s]);
     R acc[3] = {(R)0, (R)0, (R)0};
     for (int s = 0; s < 4; ++s) {
-        if (wp[s] == 0.0) continue;
-        for (int cc = 0; cc < 3; ++cc) acc[cc] += (R)wp[s] * v[s][cc];
+        if (wp[s] == 0.0) continue;  // only corners of nonzero weight are read
+        R v[3];
+        lat_vel_pred<T>(d, P, q, C4[s][0], C4[s][1], C4[s][2] > 1 ? C4[s][2] : 1, v);
+        for (int cc = 0; cc < 3; ++cc) acc[cc] += (R)wp[s] * v[cc];
     }
     ut[0] = acc[0]; ut[1] = acc[1]; ut[2] = acc[2];
     return true;
