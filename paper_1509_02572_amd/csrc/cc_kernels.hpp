@@ -1320,6 +1320,20 @@ struct DiagCol {
     double zlo, zhi;
 };
 
+// Run f(b) for the member b of each lane: with the wave-uniform member (read through scalar loads)
+// when every lane of the wave has the same one, as is the case away from the members' boundaries.
+template <typename VIEWS, typename F>
+__device__ __forceinline__ void with_member(int b, F &&f)
+{
+    if constexpr (VIEWS::MULTI) {
+        const int bu = __builtin_amdgcn_readfirstlane(b);
+        if (__all(b == bu)) f(bu);
+        else f(b);
+    } else {
+        f(b);
+    }
+}
+
 template <typename T, typename VIEWS>
 __device__ __forceinline__ void diagnose_block(const VIEWS &views, int64_t *st)
 {
@@ -1332,49 +1346,56 @@ __device__ __forceinline__ void diagnose_block(const VIEWS &views, int64_t *st)
     if (tid == 0) s_kmax = 0;
     __syncthreads();
     const DiagCol col = views.column(slot);
-    const Dims &d = views.dims(col.b);
-    const Geo &G = views.geo(col.b);
-    const Phy &P = views.phy(col.b);
-    const SOut<T> &qw = views.state(col.b);
     DiagLevel<R> early;
     early.mode = 0;
-    const int top = col.valid ? G.colk[2 * (int64_t)d.nx * d.ny + col.t] : 0;
-    if (grp == 0) {
-        if (col.valid) {
-            R ub[3];
-            boundary_velocity<T>(d, G, P, qw, col.t, st, col.zlo, col.zhi, ub);
-            s_ub[0][slot] = ub[0]; s_ub[1][slot] = ub[1]; s_ub[2][slot] = ub[2];
+    int top = 0;
+    with_member<VIEWS>(col.b, [&](int b) {
+        const Dims &d = views.dims(b);
+        const Geo &G = views.geo(b);
+        const Phy &P = views.phy(b);
+        const SOut<T> &qw = views.state(b);
+        top = col.valid ? G.colk[2 * (int64_t)d.nx * d.ny + col.t] : 0;
+        if (grp == 0) {
+            if (col.valid) {
+                R ub[3];
+                boundary_velocity<T>(d, G, P, qw, col.t, st, col.zlo, col.zhi, ub);
+                s_ub[0][slot] = ub[0]; s_ub[1][slot] = ub[1]; s_ub[2][slot] = ub[2];
+            }
+        } else if (grp - 1 < top) {
+            diagnose_level_pre<T>(d, G, P, qw, col.t, grp - 1, early);
         }
+    });
+    if (grp == 0) {
         s_top[slot] = top;
         s_b[slot] = col.b;
         s_t[slot] = col.t;
         atomicMax(&s_kmax, top);
-    } else if (grp - 1 < top) {
-        diagnose_level_pre<T>(d, G, P, qw, col.t, grp - 1, early);
     }
     __syncthreads();
     if (early.mode != 0) {
         const R ub[3] = {s_ub[0][slot], s_ub[1][slot], s_ub[2][slot]};
-        diagnose_level_post<T>(d, qw, col.t, grp - 1, early, ub);
+        with_member<VIEWS>(col.b, [&](int b) { diagnose_level_post<T>(views.dims(b), views.state(b), col.t, grp - 1, early, ub); });
     }
     const int n = (s_kmax - DIAG_EARLY) * DIAG_COLS;
     for (int it = tid; it < n; it += DIAG_THREADS) {
         const int sl = it % DIAG_COLS, K = DIAG_EARLY + it / DIAG_COLS;
         if (K >= s_top[sl]) continue;
-        const int b = s_b[sl];
         const int64_t t = s_t[sl];
-        const Dims &d2 = views.dims(b);
-        const SOut<T> &q2 = views.state(b);
-        DiagLevel<R> o;
-        diagnose_level_pre<T>(d2, views.geo(b), views.phy(b), q2, t, K, o);
         const R ub[3] = {s_ub[0][sl], s_ub[1][sl], s_ub[2][sl]};
-        diagnose_level_post<T>(d2, q2, t, K, o, ub);
+        with_member<VIEWS>(s_b[sl], [&](int b) {
+            const Dims &d2 = views.dims(b);
+            const SOut<T> &q2 = views.state(b);
+            DiagLevel<R> o;
+            diagnose_level_pre<T>(d2, views.geo(b), views.phy(b), q2, t, K, o);
+            diagnose_level_post<T>(d2, q2, t, K, o, ub);
+        });
     }
 }
 
 // views of a single grid: slot s of block b is corner b DIAG_COLS + s
 template <typename T>
 struct GridDiagViews {
+    static constexpr bool MULTI = false;
     const Dims &d;
     const Geo &G;
     const Phy &P;
@@ -1401,8 +1422,10 @@ __global__ void __launch_bounds__(DIAG_THREADS) k_diagnose(Dims d, Geo G, Phy P,
 // own levels, the others (ghost layers, which go stale) never
 template <typename T>
 struct BatchDiagViews {
+    static constexpr bool MULTI = true;
     const BlockDesc<T> *desc;
     int nblk, ncols, ro;
+    // the block holding column t (the last whose first column is at or before t)
     __device__ int block_of(int t) const
     {
         int lo = 0, hi = nblk - 1;
@@ -1415,9 +1438,12 @@ struct BatchDiagViews {
     }
     __device__ DiagCol column(int slot) const
     {
-        const int t = blockIdx.x * DIAG_COLS + slot;
+        // one search for the workgroup's first column (uniform), then forward to each lane's block
+        const int t0 = blockIdx.x * DIAG_COLS;
+        const int t = t0 + slot;
         if (t >= ncols) return DiagCol{false, 0, 0, 0.0, 0.0};
-        const int b = block_of(t);
+        int b = block_of(t0);
+        while (b + 1 < nblk && desc[b + 1].col0 <= t) ++b;
         const BlockDesc<T> &D = desc[b];
         const int wy = D.rhi[1] - D.rlo[1];
         const int r = t - D.col0;
