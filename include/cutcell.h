@@ -95,12 +95,16 @@ typedef struct {
     double theta0, bvn;   /* sea-level potential temperature [K], Brunt-Vaisala frequency [1/s] */
     double u0, v0;        /* uniform inflow (reference velocity of the perturbation form) */
     double kdh, kdv;      /* rates [1/s] of the fourth-order artificial diffusion in x, y and in z
-                             (Sec. 2.1 D terms; 0: none; single grids only).  The 2-dx mode of a field
-                             decays at 16 kdh per horizontal direction (16 kdv vertically); the
-                             explicit stage needs dt (32 kdh + 16 kdv) below about 2.5 */
+                             (Sec. 2.1 D terms; 0: none).  The 2-dx mode of a field decays at 16 kdh
+                             per horizontal direction (16 kdv vertically); the explicit stage needs
+                             dt (32 kdh + 16 kdv) below about 2.5.  In a batch or refined grid every
+                             block applies it in flux form over its update range; the stencil reaches
+                             two cells, so a refined level's stale ghost layers advance two per stage
+                             (ghost width 12 covers two fine steps), and the coarse-fine flux
+                             matching covers the advective fluxes only */
     double zsp, rsp;      /* sponge layer below the lid (Sec. 3, absorbing layer after Klemp & Lilly):
                              bottom height zsp [m, same datum as z0] and damping rate rsp [1/s] at the
-                             lid (0: none; single grids only).  Rayleigh damping -tau(z) (q - q_ref)
+                             lid (0: none; single grids only: a batch refuses it).  Rayleigh damping -tau(z) (q - q_ref)
                              with tau = rsp sin^2(pi/2 (z - zsp)/(ztop - zsp)) above zsp, ztop =
                              z0 + nz dz, on (rho theta)' at group masters (cell-centre height) and on
                              rho u - rhobar_c (u0, v0, 0) at predicted points (lattice height); rho'

@@ -24,6 +24,7 @@
 #include <numeric>
 #include <vector>
 
+#include "cc_diffuse.hpp"
 #include "cc_kernels.hpp"
 #include "cc_stream.hpp"
 
@@ -263,6 +264,7 @@ struct cc_batch_s {
     cc_prec prec;
     int tile = 0;
     int btile = 0;  // band-point tiles: 0 8x8x1, 1 4x4x4, 2 2x2x16
+    bool diffuse = false;  // some block has a non-zero artificial-diffusion rate
     char *ws = nullptr;  // caller workspace: descriptors, refill tables, flux registers
     std::vector<Level> lev;
     hipStream_t cap = nullptr;  // private stream used only for graph capture
@@ -354,6 +356,9 @@ void level_stage(cc_batch_s *b, int l, int rn, int rs, int ro, double cdt, int f
     case 12: launch_batch_stage<T, 4, 8, 16, 6>(b, l, rn, rs, ro, cdt, fin, st, s); break;
     default: launch_batch_stage<T, 8, 8, 8, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
     }
+    // the artificial diffusion of the stage input, after the update as on a single grid (the flux
+    // matching below covers the advective fluxes)
+    if (b->diffuse) launch_diffuse_batch<T>(descs<T>(b, l), L.nblk, L.ncols, rs, ro, cdt, fin, s);
     if (fin) {
         if (l > 0 && b->lev[l - 1].nslot > 0) {  // this level is the fine side of level l-1's interfaces
             const Level &C = b->lev[l - 1];
@@ -700,9 +705,8 @@ bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, i
         const cc_block &b = B[ids[m]];
         Dims d; Geo G; Phy P;
         if (!make_views(what, &b.grid, &b.phys, &b.geom, b.base, prec, d, G, P)) return false;
-        if (P.kdh != 0.0 || P.kdv != 0.0 || P.rsp != 0.0) {
-            set_error("%s: block %d: the artificial diffusion and the sponge run on single grids only", what,
-                      ids[m]);
+        if (P.rsp != 0.0) {
+            set_error("%s: block %d: the sponge runs on single grids only", what, ids[m]);
             return false;
         }
         for (int r = 0; r < 3; ++r) {
@@ -876,6 +880,8 @@ bool plan_batch(const cc_block *B, int n, cc_prec prec, int tile, bool own_range
         b->tile = id;
         b->btile = bid;
         b->lev = lev;
+        b->diffuse = false;
+        for (int m = 0; m < n; ++m) b->diffuse = b->diffuse || B[m].phys.kdh != 0.0 || B[m].phys.kdv != 0.0;
     }
     return true;
 }

@@ -158,16 +158,12 @@ __device__ __forceinline__ void apply_scalars(const SOut<T> &qo, int64_t c, doub
 // ground and the lid shorten it), in the compute precision.  Otherwise the flux form over levels
 // [k0, k1), for the parts the direct launch left (all of them when kall < 0).
 template <typename T, bool INNER>
-__global__ void __launch_bounds__(256) k_diffuse(Dims d, Geo G, Phy P, SIn<T> q, SOut<T> qo, double scale,
-                                                 int final_stage, int k0, int k1, int kall)
+__device__ __forceinline__ void diffuse_point(const Dims &d, const Geo &G, const Phy &P, const SIn<T> &q,
+                                              const SOut<T> &qo, double scale, int final_stage, int i, int j, int k,
+                                              int kall)
 {
     using R = typename Compute<T>::R;
-    const int nk = k1 - k0;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)d.nx * d.ny * nk) return;
-    const int k = k0 + (int)(t % nk);
-    const int64_t col = t / nk;
-    const int j = (int)(col % d.ny), i = (int)(col / d.ny);
+    const int64_t col = (int64_t)i * d.ny + j;
     const int64_t c = col * d.nzs + k;
     const int nz = d.nz;
     const bool diff = P.kdh != 0.0 || P.kdv != 0.0;
@@ -288,6 +284,56 @@ __global__ void __launch_bounds__(256) k_diffuse(Dims d, Geo G, Phy P, SIn<T> q,
         qo.mw[c] = (T)((double)qo.mw[c] + scale * S[2]);
     }
 }
+
+template <typename T, bool INNER>
+__global__ void __launch_bounds__(256) k_diffuse(Dims d, Geo G, Phy P, SIn<T> q, SOut<T> qo, double scale,
+                                                 int final_stage, int k0, int k1, int kall)
+{
+    const int nk = k1 - k0;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)d.nx * d.ny * nk) return;
+    const int k = k0 + (int)(t % nk);
+    const int64_t col = t / nk;
+    diffuse_point<T, INNER>(d, G, P, q, qo, scale, final_stage, (int)(col / d.ny), (int)(col % d.ny), k, kall);
+}
+
+// Blocks of a batch: the diffusion in flux form over each block's update range [rlo, rhi), whose
+// columns are numbered from the block's col0 as for the batched diagnostics; DIFF_KS threads share a
+// column, each taking every DIFF_KS-th level.
+constexpr int DIFF_KS = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_diffuse_batch(const BlockDesc<T> *__restrict__ desc, int nblk, int ncols,
+                                                       int rs, int ro, double scale, int final_stage)
+{
+    const int t = blockIdx.x * (256 / DIFF_KS) + (int)(threadIdx.x / DIFF_KS);
+    const int ks = threadIdx.x % DIFF_KS;
+    if (t >= ncols) return;
+    int lo = 0, hi = nblk - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (desc[mid].col0 <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const BlockDesc<T> &D = desc[lo];
+    const int wy = D.rhi[1] - D.rlo[1], r = t - D.col0;
+    const int i = D.rlo[0] + r / wy, j = D.rlo[1] + r % wy;
+    const SIn<T> q = as_in(D.q[rs]);
+    for (int k = D.rlo[2] + ks; k < D.rhi[2]; k += DIFF_KS)
+        diffuse_point<T, false>(D.d, D.G, D.P, q, D.q[ro], scale, final_stage, i, j, k, -1);
+}
+
+template <typename T>
+void launch_diffuse_batch(const void *desc, int nblk, int ncols, int rs, int ro, double scale, int final_stage,
+                          hipStream_t s)
+{
+    if (ncols <= 0) return;
+    hipLaunchKernelGGL(k_diffuse_batch<T>, dim3(blocks_for(ncols, 256 / DIFF_KS)), dim3(256), 0, s,
+                       (const BlockDesc<T> *)desc, nblk, ncols, rs, ro, scale, final_stage);
+}
+
+template void launch_diffuse_batch<float>(const void *, int, int, int, int, double, int, hipStream_t);
+template void launch_diffuse_batch<double>(const void *, int, int, int, int, double, int, hipStream_t);
 
 template <typename T>
 void launch_diffuse(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, cc_state *qo, double scale,

@@ -22,11 +22,22 @@ the sponge (Rayleigh damping rising as sin^2 from 10 km to a rate of 0.01 1/s at
 evaluation region (every lattice point above the hilltop height, up to the lid, over the whole
 horizontal domain).
 
+* ``refined``: the refined-grid experiment of Sec. 3.2.  Flow over the hemisphere of Sec. 3.1.2
+  (radius 1 km at (32, 16) km) on cubes of 20^3 cells: level 0 alone (400 m, 64 cubes), levels 0-1
+  (148 cubes, 200 m around the hill) and levels 0-2 (232 cubes, 100 m nearest the hill), against the
+  uniform 100 m grid (4096 cubes) as reference; w is compared on the x-z section through the hill
+  centre and on the horizontal slices at z = 1200 m and 2400 m, per region of the level-2 layout.
+  Every run carries the artificial diffusion of the other studies (1e-3 1/s); the batched block path
+  has no sponge, so none of the four runs has one here (the lid reflects what reaches it in every
+  run alike), and the refined layouts keep 12 ghost layers, which the diffusion's reach of two cells
+  per stage needs over two fine steps.
+
 Both run with the three-stage Runge-Kutta scheme of the (rho theta)' form, or with ``--scheme lf``
 with the paper's leap-frog and Robert-Asselin filter in p' form (filter weight ``--nu``).
 
 Usage:  python -m paper_1509_02572_amd.studies convergence [--t-end 3600] [--scheme rk3|lf] [--out FILE]
         python -m paper_1509_02572_amd.studies lee-wave [--delta 100] [--t-end 3600] [--scheme rk3|lf] [--out FILE]
+        python -m paper_1509_02572_amd.studies refined [--t-end 3600] [--out FILE]
 """
 from __future__ import annotations
 
@@ -95,6 +106,8 @@ def integrate(cfg: W.Config, prec: str = "f64", every: float = 30.0, scheme: str
             dom.lf_step(c, a, b, cfg.dt, nu, first=(n == 0))
             c, a, b = a, b, c
         if (n + 1) % 200 == 0:
+            if (n + 1) % 1600 == 0 and dom.check()[2]:  # stop at the first non-finite value
+                raise RuntimeError(f"{cfg.name}: non-finite values by step {n + 1} (t = {(n + 1) * cfg.dt:.0f} s)")
             torch.cuda.synchronize()
             now = time.perf_counter()
             if now - last >= every:
@@ -268,6 +281,175 @@ def lee_wave(delta: float = 100.0, t_end: float = 3600.0, prec: str = "f64", out
     return res
 
 
+# ---- the refined-grid experiment (Sec. 3.2) ----
+
+def trilinear(arr: np.ndarray, p: np.ndarray) -> np.ndarray:
+    """Values of arr (nx, ny, nz) at fractional indices p (N, 3); every p + 1 lies inside arr."""
+    i0 = np.floor(p + 1e-9).astype(np.int64)
+    w = p - i0
+    out = np.zeros(len(p))
+    for c in range(8):
+        o = np.array([(c >> 2) & 1, (c >> 1) & 1, c & 1])
+        wt = np.prod(np.where(o[None, :] == 1, w, 1.0 - w), axis=1)
+        idx = i0 + o[None, :]
+        out += wt * arr[idx[:, 0], idx[:, 1], idx[:, 2]]
+    return out
+
+
+def sample_blocks(blocks, targets: np.ndarray, delta0: float) -> np.ndarray:
+    """Lattice values at target positions (N, 3) [m] from blocks given as (level, own_lo, own_hi,
+    box_org, arr): own range and box origin in level-l global lattice indices, arr the box's lattice
+    values.  Each target takes the finest block whose own range holds it (trilinear within the box);
+    NaN where none does."""
+    out = np.full(len(targets), np.nan)
+    done = np.zeros(len(targets), dtype=bool)
+    for lev in sorted({b[0] for b in blocks}, reverse=True):
+        g = targets / (delta0 / (1 << lev))
+        for level, lo, hi, org, arr in blocks:
+            if level != lev:
+                continue
+            m = ~done & np.all((g >= np.array(lo) - 1e-9) & (g < np.array(hi) - 1e-9), axis=1)
+            if not m.any():
+                continue
+            out[m] = trilinear(arr, g[m] - np.array(org, dtype=np.float64)[None, :])
+            done |= m
+    return out
+
+
+def uniform_as_block(arr: np.ndarray) -> tuple:
+    """A periodic uniform grid's lattice values as one level-0 block (padded by one lattice point in x
+    and y with the periodic copies, so interpolation reaches the far side)."""
+    pad = np.concatenate([arr, arr[:1]], axis=0)
+    pad = np.concatenate([pad, pad[:, :1]], axis=1)
+    return (0, (0, 0, 0), arr.shape, (0, 0, 0), pad)
+
+
+def refined_targets(delta: float = 100.0, zmax: float = 10000.0) -> Dict[str, np.ndarray]:
+    """Comparison points: the x-z section through the hill centre (y = 16 km, 0 < z <= zmax) and the
+    horizontal slices at z = 1200 m and 2400 m, on the reference lattice."""
+    x = np.arange(int(round(LX / delta))) * delta
+    y = np.arange(int(round(LY / delta))) * delta
+    z = np.arange(1, int(round(zmax / delta)) + 1) * delta
+    X, Z = np.meshgrid(x, z, indexing="ij")
+    xz = np.stack([X.ravel(), np.full(X.size, LY / 2), Z.ravel()], axis=1)
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    sl = {f"z{int(h)}": np.stack([X.ravel(), Y.ravel(), np.full(X.size, h)], axis=1) for h in (1200.0, 2400.0)}
+    return {"xz": xz, **sl}
+
+
+def region_of(targets: np.ndarray, levels: int = 3) -> np.ndarray:
+    """Finest level of the ``levels``-level layout covering each target (0, 1, 2)."""
+    reg = np.zeros(len(targets), dtype=np.int64)
+    cube0 = W.CBCM_CUBE * 400.0
+    for lev, ((x0, x1), (y0, y1), (z0, z1)) in enumerate(W.cbcm_regions(levels)):
+        c = cube0 / (1 << lev)
+        m = ((targets[:, 0] >= x0 * c) & (targets[:, 0] < x1 * c) & (targets[:, 1] >= y0 * c)
+             & (targets[:, 1] < y1 * c) & (targets[:, 2] >= z0 * c) & (targets[:, 2] < z1 * c))
+        reg[m] = lev + 1
+    return reg
+
+
+def diff_norms(w: np.ndarray, wref: np.ndarray, reg: np.ndarray) -> Dict[str, object]:
+    """RMS and maximum of w - wref, over all points and per region (finest level of the level-2
+    layout there), with the RMS of wref for scale."""
+    out = {}
+    for name, m in (("all", np.ones(len(w), dtype=bool)), ("L0", reg == 0), ("L1", reg == 1), ("L2", reg == 2)):
+        if not m.any():
+            continue
+        d = w[m] - wref[m]
+        out[name] = {"rms": float(np.sqrt(np.mean(d * d))), "max": float(np.abs(d).max()),
+                     "ref_rms": float(np.sqrt(np.mean(wref[m] ** 2))), "points": int(m.sum())}
+    return out
+
+
+def integrate_refined(layout, prec: str = "f64", t_end: float = 3600.0, chunk: int = 25, every: float = 30.0):
+    """Run a refined layout for t_end (level-0 steps of layout.base.dt, chunk steps per graph launch)."""
+    import torch
+    from . import autotune
+    from . import cutcell as CC
+    tile = autotune.tune_refined(layout, prec, path=None)["tile"]
+    h = CC.Hierarchy(layout, prec, "cuda:0", tile=tile)
+    n0 = int(round(t_end / layout.base.dt))
+    torch.cuda.synchronize()
+    t0 = last = time.perf_counter()
+    done = 0
+    while done < n0:
+        k = min(chunk, n0 - done)
+        h.step(k, use_graph=True)
+        done += k
+        if done % (8 * chunk) == 0 and h.check()[2]:  # stop at the first non-finite own value
+            raise RuntimeError(f"refined layout: non-finite values by level-0 step {done}")
+        torch.cuda.synchronize()
+        now = time.perf_counter()
+        if now - last >= every:
+            log(f"  refined {len(layout.blocks)} cubes: level-0 step {done}/{n0} ({now - t0:.0f} s wall)")
+            last = now
+    secs = time.perf_counter() - t0
+    st = h.check()
+    if st[:6].any():
+        raise RuntimeError(f"refined layout: device status counters set: {st}")
+    info = {"cubes": len(layout.blocks), "levels": layout.levels, "tile": tile, "level0_steps": n0,
+            "dt0": layout.base.dt, "own_cells": layout.cells(), "wall_s": round(secs, 2)}
+    log(f"  refined {len(layout.blocks)} cubes: {n0} level-0 steps in {secs:.1f} s")
+    return h, info
+
+
+def hierarchy_blocks(h) -> list:
+    """The lattice w of every block of a hierarchy as sample_blocks entries."""
+    out = []
+    for m, (b, q) in enumerate(zip(h.layout.blocks, h.current())):
+        org, size, gb, gt = h.layout.box(b)
+        w = lattice_velocity(h.doms[m], q)["w"]
+        out.append((b.level, b.org, tuple(o + s for o, s in zip(b.org, b.size)), org, w))
+    return out
+
+
+def refined(t_end: float = 3600.0, prec: str = "f64", out: Optional[str] = None) -> dict:
+    import torch
+    from . import cutcell as CC
+    log(f"refined-grid experiment: hemisphere, t_end {t_end} s, {prec}")
+    tg = refined_targets()
+    reg = {k: region_of(v) for k, v in tg.items()}
+    res = {"case": "hemisphere r=1 km at (32,16) km, 64x32x16 km, U=10 m/s, N=0.01 1/s, cubes of 20^3 cells, "
+                   f"diffusion {KD} 1/s, no sponge", "t_end_s": t_end, "prec": prec, "kd_per_s": KD, "runs": {}}
+    # reference: uniform 100 m
+    base = W.cbcm_hemisphere(1).base.replace(kdh=KD, kdv=KD)
+    ref_cfg = base.replace(name="cbcm_uniform100", nx=640, ny=320, nz=160, dx=100.0, dy=100.0, dz=100.0,
+                           dt=0.125, nsteps=int(round(t_end / 0.125)), H=None)
+    dom, q, info = integrate(ref_cfg, prec)
+    blk = [uniform_as_block(lattice_velocity(dom, q)["w"])]
+    wref = {k: sample_blocks(blk, v, 100.0) for k, v in tg.items()}
+    res["reference"] = dict(info, cubes=4096)
+    del dom, q, blk
+    torch.cuda.empty_cache()
+    # level 0 alone: the uniform 400 m grid (one level of cubes steps like the uniform grid, bitwise)
+    c0 = base.replace(name="cbcm_level0", nsteps=int(round(t_end / base.dt)), H=None)
+    dom, q, info = integrate(c0, prec)
+    blk = [uniform_as_block(lattice_velocity(dom, q)["w"])]
+    info = dict(info, cubes=64)
+    info["w"] = {k: diff_norms(sample_blocks(blk, v, 400.0), wref[k], reg[k]) for k, v in tg.items()}
+    res["runs"]["level0"] = info
+    del dom, q, blk
+    torch.cuda.empty_cache()
+    for levels in (2, 3):
+        lay = W.cbcm_hemisphere(levels, ghost=12)
+        lay.base = lay.base.replace(kdh=KD, kdv=KD)
+        h, info = integrate_refined(lay, prec, t_end)
+        blk = hierarchy_blocks(h)
+        info["w"] = {k: diff_norms(sample_blocks(blk, v, 400.0), wref[k], reg[k]) for k, v in tg.items()}
+        res["runs"][f"level{levels - 1}"] = info
+        h.close()
+        del h, blk
+        torch.cuda.empty_cache()
+    for name, r in res["runs"].items():
+        log(f"  {name}: " + "; ".join(f"{k} rms {v['all']['rms']:.3e} (L0 {v.get('L0', {}).get('rms', 0):.2e}, "
+                                      f"L1 {v.get('L1', {}).get('rms', 0):.2e}, L2 {v.get('L2', {}).get('rms', 0):.2e})"
+                                      for k, v in r["w"].items()))
+    if out:
+        json.dump(res, open(out, "w"), indent=1)
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -286,7 +468,15 @@ def main(argv=None):
     lw.add_argument("--out", default=None)
     lw.add_argument("--scheme", default="rk3", choices=["rk3", "lf"])
     lw.add_argument("--nu", type=float, default=NU)
+    rf = sub.add_parser("refined")
+    rf.add_argument("--t-end", type=float, default=3600.0)
+    rf.add_argument("--prec", default="f64", choices=["f32", "f64"])
+    rf.add_argument("--out", default=None)
     a = ap.parse_args(argv)
+    if a.cmd == "refined":
+        r = refined(a.t_end, a.prec, a.out)
+        print(json.dumps({k: v for k, v in r.items()}))
+        return
     if a.cmd == "convergence":
         r = convergence(tuple(float(x) for x in a.deltas.split(",")), a.ref, a.t_end, a.prec, a.out, a.scheme,
                         a.nu)

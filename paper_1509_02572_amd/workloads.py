@@ -319,8 +319,8 @@ class AmrLayout:
     def box(self, b: AmrBlock):
         """Padded box of block b: (origin in level-l global cells, size, ghost below, ghost above)."""
         nzl = self.base.nz << b.level
-        gb = self.ghost if b.org[2] > 0 else 0
-        gt = self.ghost if b.org[2] + b.size[2] < nzl else 0
+        gb = min(self.ghost, b.org[2])  # the box stops at the ground and at the lid
+        gt = min(self.ghost, nzl - (b.org[2] + b.size[2]))
         org = (b.org[0] - self.ghost, b.org[1] - self.ghost, b.org[2] - gb)
         size = (b.size[0] + 2 * self.ghost, b.size[1] + 2 * self.ghost, b.size[2] + gb + gt)
         return org, size, gb, gt
@@ -475,3 +475,46 @@ def amr_hemisphere(target_blocks: int = 2000, seed: int = 0) -> AmrLayout:
         else:
             hi = mid
     return best
+
+
+# --------------------------------------------------------------------------------------------
+# The refined-grid experiment of Sec. 3.2: cubes of 20^3 cells over the 64 x 32 x 16 km domain.
+# --------------------------------------------------------------------------------------------
+
+CBCM_CUBE = 20  # cells per cube edge at every level (Sec. 3.2)
+
+
+def cbcm_regions(levels: int):
+    """Cubes each level refines in the Sec. 3.2 layouts, as index ranges of that level's cubes
+    ((x0, x1), (y0, y1), (z0, z1)), half-open.  The paper gives the cube counts (64, 148, 232) and
+    the spacings, not the criterion; the counts fix 12 refined cubes per level, read here as the
+    3 x 2 x 2 cubes around the hill and one cube downstream of it: level 0 (8 x 4 x 2 cubes of
+    8 km) refines x 24-48 km, y 8-24 km, z 0-16 km; level 1 (4 km cubes) refines x 28-40 km,
+    y 12-20 km, z 0-8 km."""
+    return [((3, 6), (1, 3), (0, 2)), ((7, 10), (3, 5), (0, 2))][: levels - 1]
+
+
+def cbcm_hemisphere(levels: int = 3, ghost: int = 6) -> AmrLayout:
+    """The grids of Sec. 3.2 over the hemisphere of Sec. 3.1.2 (radius 1 km at (32, 16) km, U = 10 m/s,
+    N = 0.01 1/s, theta_0 = 300 K): level 0 is 160 x 80 x 40 cells at 400 m (8 x 4 x 2 cubes of
+    20^3 cells); ``levels`` = 2 and 3 add the 200 m and 100 m cubes of ``cbcm_regions`` (148 and 232
+    cubes in all; the uniform 100 m grid holds 4096).  Every cube is one block; dt(0) = 0.5 s
+    (dt = delta / 800 s at every level)."""
+    base = Config("cbcm_hemi", 160, 80, 40, 400.0, 400.0, 400.0, Hill("hemisphere", 0.0, 1000.0), u0=10.0,
+                  v0=0.0, bvn=0.01, theta0=300.0, dt=0.5, nsteps=7200)
+    n = CBCM_CUBE
+    regions = cbcm_regions(levels)
+    cubes = {(x, y, z) for x in range(base.nx // n) for y in range(base.ny // n) for z in range(base.nz // n)}
+    blocks = []
+    for lev in range(levels):
+        nxt = set()
+        if lev < len(regions):
+            (x0, x1), (y0, y1), (z0, z1) = regions[lev]
+            for x in range(x0, x1):
+                for y in range(y0, y1):
+                    for z in range(z0, z1):
+                        cubes.discard((x, y, z))
+                        nxt.update((2 * x + a, 2 * y + b, 2 * z + c) for a in (0, 1) for b in (0, 1) for c in (0, 1))
+        blocks += [AmrBlock(lev, (x * n, y * n, z * n), (n, n, n)) for (x, y, z) in sorted(cubes)]
+        cubes = nxt
+    return AmrLayout(base, levels, n, ghost, [], blocks)

@@ -90,6 +90,39 @@ def test_three_levels_against_oracle():
     assert not h.check()[:6].any()
 
 
+def test_three_levels_with_diffusion_against_oracle():
+    # every block applies the artificial diffusion over its update range; the oracle steps each
+    # box with the uniform-grid oracle, whose stage carries the diffusion.  The diffusion reaches two
+    # cells per stage, so the stale ghost layers advance two per stage: 12 layers keep them away from
+    # the own cells over two fine steps (with 6 they reach the own cells, where the box-edge values
+    # they carry differ between the two sides by rounding only, but at their own large magnitude)
+    base = small_layout().base.replace(kdh=0.05, kdv=0.05)
+    lay = W.amr_layout(base, levels=3, brick=8, ghost=12, d_fine=300.0, band=400.0, seed=1)
+    print("case three levels diffusion", len(lay.blocks), flush=True)
+    steps = 2
+    h = CC.Hierarchy(lay, "f64")
+    h.step(steps)
+    torch.cuda.synchronize()
+    a = A.AmrOracle(lay)
+    a.step(steps)
+    plain = A.AmrOracle(W.amr_layout(small_layout().base, levels=3, brick=8, ghost=12, d_fine=300.0, band=400.0,
+                                     seed=1))
+    plain.step(steps)
+    scale = {f: max(np.abs(a.own_cells(m)[f]).max() for m in range(len(lay.blocks))) for f in A.FIELDS}
+    err = {f: 0.0 for f in A.FIELDS}
+    moved = 0.0
+    for m, qb in enumerate(h.current()):
+        got, ref = h.own_cells(m, qb), a.own_cells(m)
+        for f in A.FIELDS:
+            err[f] = max(err[f], float(np.abs(got[f] - ref[f]).max()) / scale[f])
+        moved = max(moved, float(np.abs(ref["mw"] - plain.own_cells(m)["mw"]).max()) / scale["mw"])
+    print("errors", err, "diffusion effect", moved, flush=True)
+    for f, e in err.items():
+        assert e <= 1e-12, (f, err)
+    assert moved > 1e-9
+    assert not h.check()[:6].any()
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_three_levels_conserve_mass(prec):
     lay = small_layout()

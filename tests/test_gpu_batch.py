@@ -122,6 +122,35 @@ def test_full_ensemble_members_bitwise_and_conservative(prec):
     batch.close()
 
 
+def test_batch_with_diffusion_matches_single_domains():
+    # the batched diffusion (flux form over each member) against single-domain runs (direct stencils
+    # where the points are regular, flux form elsewhere): the same terms up to rounding order, so the
+    # bar is 1e-12 of each field's total magnitude (base state included for the perturbation scalars,
+    # the largest momentum component for every component)
+    cfgs = [c.replace(kdh=0.02, kdv=0.01) for c in _small_ensemble(count=3)]
+    print("case batch diffusion", [(c.nx, c.ny, c.nz) for c in cfgs], flush=True)
+    doms, states = _members(cfgs, "f64")
+    batch = CC.Batch(doms, states, tile=0)
+    batch.step(cfgs[0].dt, 4)
+    torch.cuda.synchronize()
+    plain = [CC.Domain(c.replace(kdh=0.0, kdv=0.0), "f64", side_stream=False) for c in cfgs]
+    for m, (d, q) in enumerate(zip(doms, states)):
+        ref = d.state_numpy(d.run(q, cfgs[0].dt, 4))
+        got = d.state_numpy(batch.current()[m])
+        nod = plain[m].state_numpy(plain[m].run(plain[m].init_state(W.theta_noise(
+            cfgs[m].replace(noise_sigma=0.01, seed=7 + m))), cfgs[0].dt, 4))
+        nz = cfgs[m].nz
+        mom = max(np.abs(ref[f]).max() for f in ("mu", "mv", "mw"))
+        base = {"rho": d.base[:nz].abs().max().item(), "rth": d.base[nz:2 * nz].abs().max().item()}
+        for f in CC.FIELDS:
+            scale = np.abs(ref[f]).max() + base[f] if f in base else mom
+            assert np.abs(got[f] - ref[f]).max() <= 1e-12 * scale, (m, f)
+        # the diffusion acted
+        assert max(np.abs(ref[f] - nod[f]).max() / np.abs(ref[f]).max() for f in ("rth", "mw")) > 1e-9
+    assert not batch.check()[:5].any()
+    batch.close()
+
+
 def test_batch_rejects_bad_arguments():
     cfg = W.get("bell32")
     d64 = CC.Domain(cfg, "f64")
@@ -139,3 +168,7 @@ def test_batch_rejects_bad_arguments():
     ws = torch.zeros(CC.amr_batch_workspace_bytes(1, CC.CC_F64), dtype=torch.uint8, device="cuda:0")
     with pytest.raises(RuntimeError, match="level"):
         CC.amr_batch_create([blk], CC.CC_F64, 0, ws)
+    # the sponge runs on single grids only
+    ds = CC.Domain(cfg.replace(zsp=2000.0, rsp=0.01), "f64")
+    with pytest.raises(RuntimeError, match="sponge"):
+        CC.Batch([ds], [ds.init_state()])
