@@ -104,11 +104,14 @@ typedef struct {
                              matching covers the advective fluxes only */
     double zsp, rsp;      /* sponge layer below the lid (Sec. 3, absorbing layer after Klemp & Lilly):
                              bottom height zsp [m, same datum as z0] and damping rate rsp [1/s] at the
-                             lid (0: none; single grids only: a batch refuses it).  Rayleigh damping -tau(z) (q - q_ref)
-                             with tau = rsp sin^2(pi/2 (z - zsp)/(ztop - zsp)) above zsp, ztop =
-                             z0 + nz dz, on (rho theta)' at group masters (cell-centre height) and on
-                             rho u - rhobar_c (u0, v0, 0) at predicted points (lattice height); rho'
-                             is not damped, so mass stays conserved.  Needs dt rsp below about 2.5 */
+                             lid (0: none).  Rayleigh damping -tau(z) (q - q_ref) with tau = rsp
+                             sin^2(pi/2 (z - zsp)/(ztop - zsp)) above zsp, on (rho theta)' at group
+                             masters (cell-centre height) and on rho u - rhobar_c (u0, v0, 0) at
+                             predicted points (lattice height); rho' is not damped, so mass stays
+                             conserved.  Needs dt rsp below about 2.5 */
+    double ztop;          /* height of the domain's lid [m, same datum as z0] for the sponge: 0 for
+                             the grid's own top z0 + nz dz; a block of a refined grid that ends below
+                             the lid passes the domain's (not below its own top, else CC_EINVAL) */
 } cc_phys;
 
 /* Geometry and merge map (device arrays, caller-allocated). */

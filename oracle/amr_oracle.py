@@ -17,9 +17,11 @@ The step, in the paper's order:
   * after the level-l step, ghost cells of level l covered by level l+1 take the mean of the eight
     fine cells (momentum: the coincident fine lattice point), and ghost cells of level l+1 covered
     by level l take the coarse cell's values (the coarse lattice point at the halved index).
-Reading (the paper leaves it open): the values moved between levels are the prognostic variables
-as stored, i.e. the perturbations rho', (rho theta)' from each level's own base state and the
-momentum rho u.
+Reading (the paper leaves it open): the values moved between levels are perturbations, each from
+the level's own reference: rho' and (rho theta)' from the level's base state, and at predicted
+lattice points the momentum rho u - rhobar_c(K) (u0, v0, 0) from the level's reference flow (the
+base density of a lattice level depends on the level's spacing, so moving the total rho u would put
+a vertical staircase of size d rhobar_c/dz dz U into the fine ghost cells at every transfer).
 """
 from __future__ import annotations
 
@@ -185,6 +187,24 @@ class AmrOracle:
                     fields = FIELDS
                 for f in fields:
                     dst.a[f].ravel()[di] = src.a[f].ravel()[si]
+                if kind != "same":
+                    self._momentum_reference(m, sm, dst, di, si)
+
+    def _momentum_reference(self, m, sm, dst, di, si):
+        """Moved momenta at predicted lattice points keep their perturbation from the reference flow
+        rhobar_c(K) (u0, v0): add (rhobar_c of the destination level - that of the source) U."""
+        od, os_ = self.boxes[m], self.boxes[sm]
+        pred = (od.vcls.ravel()[di] == O.PRED) & (os_.vcls.ravel()[si] == O.PRED)
+        if not pred.any():
+            return
+        kd, ks = di[pred] % od.shape[2], si[pred] % os_.shape[2]
+
+        def rbc(o, k):  # mean base density of the levels k-1 and k (k >= 1 at predicted points)
+            return 0.5 * (o.rhob[k - 1] + o.rhob[k])
+
+        dr = rbc(od, kd) - rbc(os_, ks)
+        for f, u in (("mu", od.cfg.u0), ("mv", od.cfg.v0)):
+            dst.a[f].ravel()[di[pred]] += dr * u
 
     def sync(self):
         for l in range(self.nl):

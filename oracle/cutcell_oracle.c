@@ -30,7 +30,7 @@ typedef struct { int32_t nx, ny, nz, nsub; double dx, dy, dz, z0; } or_grid;  /*
 /* kdh, kdv: rates [1/s] of the fourth-order artificial diffusion in the horizontal and the vertical
  * (0: none); zsp, rsp: bottom height [m] of the sponge layer and its damping rate [1/s] at the lid
  * (rsp = 0: none) */
-typedef struct { double g, rd, cp, p0, theta0, bvn, u0, v0, kdh, kdv, zsp, rsp; } or_phys;
+typedef struct { double g, rd, cp, p0, theta0, bvn, u0, v0, kdh, kdv, zsp, rsp, ztop; } or_phys;
 
 /* cell classes, merge directions and lattice-point classes (numeric codes are an interface) */
 enum { OR_SOLID = 0, OR_OPEN = 1, OR_ABSORBED = 2, OR_ORPHAN = 3 };
@@ -903,7 +903,7 @@ static void diffusion_point(const or_ctx *x, int I, int J, int K, double D[3])
 /* ------------------------------------------------------------------------------------------ */
 static double sponge_rate(const or_grid *g, const or_phys *ph, double z)
 {
-    double ztop = g->z0 + g->nz * g->dz;
+    double ztop = ph->ztop != 0.0 ? ph->ztop : g->z0 + g->nz * g->dz;  /* the domain's lid */
     if (ph->rsp == 0.0 || z <= ph->zsp || ph->zsp >= ztop) return 0.0;
     double s = sin(0.5 * 3.14159265358979323846 * (z - ph->zsp) / (ztop - ph->zsp));
     return ph->rsp * (s * s);

@@ -39,7 +39,7 @@ class _Grid(C.Structure):
 
 class _Phys(C.Structure):
     _fields_ = [(n, C.c_double)
-                for n in ("g", "rd", "cp", "p0", "theta0", "bvn", "u0", "v0", "kdh", "kdv", "zsp", "rsp")]
+                for n in ("g", "rd", "cp", "p0", "theta0", "bvn", "u0", "v0", "kdh", "kdv", "zsp", "rsp", "ztop")]
 
 
 _DP = C.POINTER(C.c_double)
@@ -139,7 +139,7 @@ class Oracle:
         self.shape = (nx, ny, nz)
         self.grid = _Grid(nx, ny, nz, cfg.nsub, cfg.dx, cfg.dy, cfg.dz, cfg.z0)
         self.phys = _Phys(cfg.g, cfg.rd, cfg.cp, cfg.p0, cfg.theta0, cfg.bvn, cfg.u0, cfg.v0, cfg.kdh, cfg.kdv,
-                           cfg.zsp, cfg.rsp)
+                           cfg.zsp, cfg.rsp, cfg.ztop)
         self.rhob, self.rthb, self.pb, self.thb = (np.zeros(nz) for _ in range(4))
         lib().or_base_state(C.byref(self.phys), nz, cfg.dz, cfg.z0, _p(self.rhob), _p(self.rthb), _p(self.pb),
                             _p(self.thb))

@@ -72,9 +72,11 @@ __device__ __forceinline__ double get_scalar(const SOut<T> &q, int64_t i, int w)
 }
 
 // One ghost cell and the lattice point that shares its index.  Copies within a level move the
-// stored values as they are.  Between levels the scalars (perturbations from each level's base
-// state) move as they are, and momentum at predicted points keeps its total value: the float form
-// stores rho u - rhobar_c(K) U, so the base term of the two levels' lattice levels is exchanged.
+// stored values as they are.  Between levels every value moves as a perturbation from its level's
+// reference: the scalars from each level's base state, and the momentum at predicted points from the
+// reference flow rhobar_c(K) U of each level's lattice level (whose base density depends on the
+// spacing).  The float form stores those perturbations; FP64 stores the total momentum, so there the
+// reference terms of the two lattice levels are exchanged.
 template <typename T>
 __global__ void __launch_bounds__(256) k_ghost_fill(const BlockDesc<T> *__restrict__ dd, int rd,
                                                     const BlockDesc<T> *__restrict__ sd, int rs,
@@ -112,11 +114,11 @@ __global__ void __launch_bounds__(256) k_ghost_fill(const BlockDesc<T> *__restri
         }
     }
     T mu = qs.mu[si], mv = qs.mv[si], mw = qs.mw[si];
-    if (mode != FILL_COPY && sizeof(T) == 4 && D.G.vcls[di] == CC_PRED && S.G.vcls[si] == CC_PRED) {
+    if (mode != FILL_COPY && sizeof(T) == 8 && D.G.vcls[di] == CC_PRED && S.G.vcls[si] == CC_PRED) {
         const int kd = (int)(di % D.d.nzs), ks = (int)(si % S.d.nzs);
-        const double dr = S.P.rhobc[ks] - D.P.rhobc[kd];
-        mu = (T)((double)mu + dr * S.P.ux);
-        mv = (T)((double)mv + dr * S.P.vy);
+        const double dr = D.P.rhobc[kd] - S.P.rhobc[ks];
+        mu = (T)((double)mu + dr * S.P.u0);
+        mv = (T)((double)mv + dr * S.P.v0);
     }
     qd.mu[di] = mu;
     qd.mv[di] = mv;
@@ -264,7 +266,7 @@ struct cc_batch_s {
     cc_prec prec;
     int tile = 0;
     int btile = 0;  // band-point tiles: 0 8x8x1, 1 4x4x4, 2 2x2x16
-    bool diffuse = false;  // some block has a non-zero artificial-diffusion rate
+    bool diffuse = false;  // some block has a non-zero artificial-diffusion or sponge rate
     char *ws = nullptr;  // caller workspace: descriptors, refill tables, flux registers
     std::vector<Level> lev;
     hipStream_t cap = nullptr;  // private stream used only for graph capture
@@ -356,8 +358,8 @@ void level_stage(cc_batch_s *b, int l, int rn, int rs, int ro, double cdt, int f
     case 12: launch_batch_stage<T, 4, 8, 16, 6>(b, l, rn, rs, ro, cdt, fin, st, s); break;
     default: launch_batch_stage<T, 8, 8, 8, 1>(b, l, rn, rs, ro, cdt, fin, st, s); break;
     }
-    // the artificial diffusion of the stage input, after the update as on a single grid (the flux
-    // matching below covers the advective fluxes)
+    // the artificial diffusion and the sponge of the stage input, after the update as on a single
+    // grid (the flux matching below covers the advective fluxes)
     if (b->diffuse) launch_diffuse_batch<T>(descs<T>(b, l), L.nblk, L.ncols, rs, ro, cdt, fin, s);
     if (fin) {
         if (l > 0 && b->lev[l - 1].nslot > 0) {  // this level is the fine side of level l-1's interfaces
@@ -705,10 +707,6 @@ bool build_descs(const cc_block *B, const std::vector<int> &ids, cc_prec prec, i
         const cc_block &b = B[ids[m]];
         Dims d; Geo G; Phy P;
         if (!make_views(what, &b.grid, &b.phys, &b.geom, b.base, prec, d, G, P)) return false;
-        if (P.rsp != 0.0) {
-            set_error("%s: block %d: the sponge runs on single grids only", what, ids[m]);
-            return false;
-        }
         for (int r = 0; r < 3; ++r) {
             if (!state_ok(what, &b.q[r])) return false;
             if (sizeof(T) == 4 && (!b.q[r].rho_lo || !b.q[r].rth_lo)) {
@@ -881,7 +879,8 @@ bool plan_batch(const cc_block *B, int n, cc_prec prec, int tile, bool own_range
         b->btile = bid;
         b->lev = lev;
         b->diffuse = false;
-        for (int m = 0; m < n; ++m) b->diffuse = b->diffuse || B[m].phys.kdh != 0.0 || B[m].phys.kdv != 0.0;
+        for (int m = 0; m < n; ++m)
+            b->diffuse = b->diffuse || B[m].phys.kdh != 0.0 || B[m].phys.kdv != 0.0 || B[m].phys.rsp != 0.0;
     }
     return true;
 }

@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(256) k_diffuse(Dims d, Geo G, Phy P, SIn<T> q,
     diffuse_point<T, INNER>(d, G, P, q, qo, scale, final_stage, (int)(col / d.ny), (int)(col % d.ny), k, kall);
 }
 
-// Blocks of a batch: the diffusion in flux form over each block's update range [rlo, rhi), whose
+// Blocks of a batch: the diffusion in flux form and the sponge over each block's update range [rlo, rhi), whose
 // columns are numbered from the block's col0 as for the batched diagnostics; DIFF_KS threads share a
 // column, each taking every DIFF_KS-th level.
 constexpr int DIFF_KS = 4;

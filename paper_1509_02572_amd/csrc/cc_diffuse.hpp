@@ -14,9 +14,9 @@ template <typename T>
 void launch_diffuse(const Dims &d, const Geo &G, const Phy &P, const cc_state *qs, cc_state *qo, double scale,
                     int final_stage, hipStream_t s);
 
-// The diffusion (flux form) of a batch's blocks: scale x D(q_s) added to q_out over every block's update
-// range, desc being the level's BlockDesc<T> table whose col0 number the range's columns (ncols in
-// all), rs / ro the state slots of q_s and q_out.  The blocks' sponge rates must be zero.
+// The diffusion (flux form) and the sponge of a batch's blocks: scale x (D(q_s) + S(q_s)) added to
+// q_out over every block's update range, desc being the level's BlockDesc<T> table whose col0 number
+// the range's columns (ncols in all), rs / ro the state slots of q_s and q_out.
 template <typename T>
 void launch_diffuse_batch(const void *desc, int nblk, int ncols, int rs, int ro, double scale, int final_stage,
                           hipStream_t s);

@@ -1489,7 +1489,15 @@ inline bool make_views(const char *what, const cc_grid *grid, const cc_phys *phy
     P.vy = prec == CC_F32_PERT ? phys->v0 : 0.0;
     P.u0 = phys->u0; P.v0 = phys->v0; P.kdh = phys->kdh; P.kdv = phys->kdv;
     if (!(P.kdh >= 0.0 && P.kdv >= 0.0)) { set_error("%s: negative diffusion rate", what); return false; }
-    P.zsp = phys->zsp; P.rsp = phys->rsp; P.ztop = d.z0 + d.nz * d.dz;
+    P.zsp = phys->zsp; P.rsp = phys->rsp;
+    P.ztop = d.z0 + d.nz * d.dz;
+    if (phys->ztop != 0.0) {
+        if (!(phys->ztop >= P.ztop * (1.0 - 1e-12)) || !std::isfinite(phys->ztop)) {
+            set_error("%s: lid height %g below the grid's top %g", what, phys->ztop, P.ztop);
+            return false;
+        }
+        P.ztop = phys->ztop;
+    }
     if (!(P.rsp >= 0.0) || !std::isfinite(P.rsp) || (P.rsp != 0.0 && !std::isfinite(P.zsp))) {
         set_error("%s: invalid sponge (rate %g, bottom %g)", what, P.rsp, P.zsp);
         return false;

@@ -34,7 +34,7 @@ class cc_grid(C.Structure):
 
 class cc_phys(C.Structure):
     _fields_ = [(n, C.c_double)
-                for n in ("g", "rd", "cp", "p0", "theta0", "bvn", "u0", "v0", "kdh", "kdv", "zsp", "rsp")]
+                for n in ("g", "rd", "cp", "p0", "theta0", "bvn", "u0", "v0", "kdh", "kdv", "zsp", "rsp", "ztop")]
 
 
 class cc_geom(C.Structure):
@@ -341,7 +341,7 @@ class Domain:
         self.n = nx * ny * self.nzs
         self.grid = cc_grid(nx, ny, nz, self.nzs, cfg.dx, cfg.dy, cfg.dz, cfg.nsub, tile, cfg.z0)
         self.phys = cc_phys(cfg.g, cfg.rd, cfg.cp, cfg.p0, cfg.theta0, cfg.bvn, cfg.u0, cfg.v0, cfg.kdh, cfg.kdv,
-                            cfg.zsp, cfg.rsp)
+                            cfg.zsp, cfg.rsp, cfg.ztop)
         Hn = workloads.terrain(cfg) if H is None else H
         d, f64, i8, i32 = self.dev, torch.float64, torch.int8, torch.int32
         nc = nx * ny

@@ -27,17 +27,16 @@ horizontal domain).
   (148 cubes, 200 m around the hill) and levels 0-2 (232 cubes, 100 m nearest the hill), against the
   uniform 100 m grid (4096 cubes) as reference; w is compared on the x-z section through the hill
   centre and on the horizontal slices at z = 1200 m and 2400 m, per region of the level-2 layout.
-  Every run carries the artificial diffusion of the other studies (1e-3 1/s); the batched block path
-  has no sponge, so none of the four runs has one here (the lid reflects what reaches it in every
-  run alike), and the refined layouts keep 12 ghost layers, which the diffusion's reach of two cells
-  per stage needs over two fine steps.
+  Every run carries the artificial diffusion (``--kd``, 1e-3 1/s by default) and the sponge of the
+  other studies (above 10 km), and the refined layouts keep 12 ghost layers, which the diffusion's
+  reach of two cells per stage needs over two fine steps.
 
 Both run with the three-stage Runge-Kutta scheme of the (rho theta)' form, or with ``--scheme lf``
 with the paper's leap-frog and Robert-Asselin filter in p' form (filter weight ``--nu``).
 
 Usage:  python -m paper_1509_02572_amd.studies convergence [--t-end 3600] [--scheme rk3|lf] [--out FILE]
         python -m paper_1509_02572_amd.studies lee-wave [--delta 100] [--t-end 3600] [--scheme rk3|lf] [--out FILE]
-        python -m paper_1509_02572_amd.studies refined [--t-end 3600] [--out FILE]
+        python -m paper_1509_02572_amd.studies refined [--t-end 3600] [--kd 1e-3] [--max-level 2] [--out FILE]
 """
 from __future__ import annotations
 
@@ -404,36 +403,50 @@ def hierarchy_blocks(h) -> list:
     return out
 
 
-def refined(t_end: float = 3600.0, prec: str = "f64", out: Optional[str] = None) -> dict:
+def refined(t_end: float = 3600.0, prec: str = "f64", out: Optional[str] = None, kd: float = KD,
+            max_level: int = 2, min_level: int = 0, ref_file: Optional[str] = None) -> dict:
+    """The runs of levels min_level .. max_level against the uniform 100 m reference; ref_file (npz)
+    keeps the reference's samples for later calls with the same t_end and kd."""
     import torch
     from . import cutcell as CC
     log(f"refined-grid experiment: hemisphere, t_end {t_end} s, {prec}")
     tg = refined_targets()
     reg = {k: region_of(v) for k, v in tg.items()}
     res = {"case": "hemisphere r=1 km at (32,16) km, 64x32x16 km, U=10 m/s, N=0.01 1/s, cubes of 20^3 cells, "
-                   f"diffusion {KD} 1/s, no sponge", "t_end_s": t_end, "prec": prec, "kd_per_s": KD, "runs": {}}
+                   f"diffusion {kd} 1/s, sponge above {ZSP:.0f} m", "t_end_s": t_end, "prec": prec, "kd_per_s": kd,
+           "sponge": {"bottom_m": ZSP, "rate_per_s": RSP}, "runs": {}}
     # reference: uniform 100 m
-    base = W.cbcm_hemisphere(1).base.replace(kdh=KD, kdv=KD)
+    base = W.cbcm_hemisphere(1).base.replace(kdh=kd, kdv=kd, zsp=ZSP, rsp=RSP)
     ref_cfg = base.replace(name="cbcm_uniform100", nx=640, ny=320, nz=160, dx=100.0, dy=100.0, dz=100.0,
                            dt=0.125, nsteps=int(round(t_end / 0.125)), H=None)
-    dom, q, info = integrate(ref_cfg, prec)
-    blk = [uniform_as_block(lattice_velocity(dom, q)["w"])]
-    wref = {k: sample_blocks(blk, v, 100.0) for k, v in tg.items()}
-    res["reference"] = dict(info, cubes=4096)
-    del dom, q, blk
-    torch.cuda.empty_cache()
-    # level 0 alone: the uniform 400 m grid (one level of cubes steps like the uniform grid, bitwise)
-    c0 = base.replace(name="cbcm_level0", nsteps=int(round(t_end / base.dt)), H=None)
-    dom, q, info = integrate(c0, prec)
-    blk = [uniform_as_block(lattice_velocity(dom, q)["w"])]
-    info = dict(info, cubes=64)
-    info["w"] = {k: diff_norms(sample_blocks(blk, v, 400.0), wref[k], reg[k]) for k, v in tg.items()}
-    res["runs"]["level0"] = info
-    del dom, q, blk
-    torch.cuda.empty_cache()
-    for levels in (2, 3):
+    import os
+    if ref_file and os.path.exists(ref_file):
+        z = np.load(ref_file)
+        assert float(z["t_end"]) == t_end and float(z["kd"]) == kd, "reference of another run"
+        wref = {k: z[k] for k in tg}
+        res["reference"] = json.loads(str(z["info"]))
+    else:
+        dom, q, info = integrate(ref_cfg, prec)
+        blk = [uniform_as_block(lattice_velocity(dom, q)["w"])]
+        wref = {k: sample_blocks(blk, v, 100.0) for k, v in tg.items()}
+        res["reference"] = dict(info, cubes=4096)
+        if ref_file:
+            np.savez(ref_file, t_end=t_end, kd=kd, info=json.dumps(res["reference"]), **wref)
+        del dom, q, blk
+        torch.cuda.empty_cache()
+    if min_level == 0:
+        # level 0 alone: the uniform 400 m grid (one level of cubes steps like the uniform grid, bitwise)
+        c0 = base.replace(name="cbcm_level0", nsteps=int(round(t_end / base.dt)), H=None)
+        dom, q, info = integrate(c0, prec)
+        blk = [uniform_as_block(lattice_velocity(dom, q)["w"])]
+        info = dict(info, cubes=64)
+        info["w"] = {k: diff_norms(sample_blocks(blk, v, 400.0), wref[k], reg[k]) for k, v in tg.items()}
+        res["runs"]["level0"] = info
+        del dom, q, blk
+        torch.cuda.empty_cache()
+    for levels in range(max(2, min_level + 1), max_level + 2):
         lay = W.cbcm_hemisphere(levels, ghost=12)
-        lay.base = lay.base.replace(kdh=KD, kdv=KD)
+        lay.base = lay.base.replace(kdh=kd, kdv=kd, zsp=ZSP, rsp=RSP)
         h, info = integrate_refined(lay, prec, t_end)
         blk = hierarchy_blocks(h)
         info["w"] = {k: diff_norms(sample_blocks(blk, v, 400.0), wref[k], reg[k]) for k, v in tg.items()}
@@ -472,9 +485,13 @@ def main(argv=None):
     rf.add_argument("--t-end", type=float, default=3600.0)
     rf.add_argument("--prec", default="f64", choices=["f32", "f64"])
     rf.add_argument("--out", default=None)
+    rf.add_argument("--kd", type=float, default=KD)
+    rf.add_argument("--max-level", type=int, default=2, choices=[0, 1, 2])
+    rf.add_argument("--min-level", type=int, default=0, choices=[0, 1, 2])
+    rf.add_argument("--ref-file", default=None, help="npz keeping the reference's samples between calls")
     a = ap.parse_args(argv)
     if a.cmd == "refined":
-        r = refined(a.t_end, a.prec, a.out)
+        r = refined(a.t_end, a.prec, a.out, a.kd, a.max_level, a.min_level, a.ref_file)
         print(json.dumps({k: v for k, v in r.items()}))
         return
     if a.cmd == "convergence":

@@ -83,6 +83,7 @@ class Config:
     redraws: int = 0  # ensemble members: hill sets redrawn before this one was accepted
     zsp: float = 0.0  # bottom height of the sponge layer below the lid [m]
     rsp: float = 0.0  # damping rate of the sponge at the lid [1/s] (0: none)
+    ztop: float = 0.0  # height of the domain's lid for the sponge [m] (0: the grid's own top)
 
     @property
     def ncells(self) -> int:
@@ -337,7 +338,7 @@ class AmrLayout:
         z0 = org[2] * dz
         H = terrain_at(c, I * dx, J * dy) - z0
         return c.replace(name=f"{c.name}-L{b.level}-{b.org}", nx=size[0], ny=size[1], nz=size[2], dx=dx, dy=dy,
-                         dz=dz, H=np.ascontiguousarray(H), z0=z0, dt=c.dt / f)
+                         dz=dz, H=np.ascontiguousarray(H), z0=z0, dt=c.dt / f, ztop=c.ztop or c.nz * c.dz)
 
 
 def _leaf_of(leaves, lev, p, nb):

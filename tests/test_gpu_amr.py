@@ -91,13 +91,15 @@ def test_three_levels_against_oracle():
 
 
 def test_three_levels_with_diffusion_against_oracle():
-    # every block applies the artificial diffusion over its update range; the oracle steps each
-    # box with the uniform-grid oracle, whose stage carries the diffusion.  The diffusion reaches two
+    # every block applies the artificial diffusion and the sponge (rate from the domain's lid height)
+    # over its update range; the oracle steps each box with the uniform-grid oracle, whose stage
+    # carries both.  The diffusion reaches two
     # cells per stage, so the stale ghost layers advance two per stage: 12 layers keep them away from
     # the own cells over two fine steps (with 6 they reach the own cells, where the box-edge values
     # they carry differ between the two sides by rounding only, but at their own large magnitude)
-    base = small_layout().base.replace(kdh=0.05, kdv=0.05)
+    base = small_layout().base.replace(kdh=0.05, kdv=0.05, zsp=2400.0, rsp=0.05)
     lay = W.amr_layout(base, levels=3, brick=8, ghost=12, d_fine=300.0, band=400.0, seed=1)
+    assert {lay.block_config(b).ztop for b in lay.blocks} == {base.nz * base.dz}
     print("case three levels diffusion", len(lay.blocks), flush=True)
     steps = 2
     h = CC.Hierarchy(lay, "f64")

@@ -168,7 +168,7 @@ def test_batch_rejects_bad_arguments():
     ws = torch.zeros(CC.amr_batch_workspace_bytes(1, CC.CC_F64), dtype=torch.uint8, device="cuda:0")
     with pytest.raises(RuntimeError, match="level"):
         CC.amr_batch_create([blk], CC.CC_F64, 0, ws)
-    # the sponge runs on single grids only
-    ds = CC.Domain(cfg.replace(zsp=2000.0, rsp=0.01), "f64")
-    with pytest.raises(RuntimeError, match="sponge"):
-        CC.Batch([ds], [ds.init_state()])
+    # a lid height below the grid's own top is refused
+    with pytest.raises(RuntimeError, match="lid height"):
+        ds = CC.Domain(cfg.replace(zsp=500.0, rsp=0.01, ztop=100.0), "f64")
+        ds.step(ds.init_state(), ds.new_state(), ds.new_state(), cfg.dt)

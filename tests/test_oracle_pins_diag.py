@@ -313,7 +313,11 @@ def test_refills_between_levels_carry_linear_fields():
     level l covered by level l+1 then take the eight-point mean of their children, which for a
     linear field is the value at the coarse centre; ghost cells of level l+1 covered by level l take
     the coarse cell's value (the value at the parent's centre); momenta take the value at the
-    coincident fine lattice point, or at the coarse lattice point at the halved index."""
+    coincident fine lattice point, or at the coarse lattice point at the halved index.  At predicted
+    points the momentum holds its level's reference flow rhobar_c(K) U on top of the linear part
+    (rhobar_c of the box's own base state, which differs between levels at the same height): what
+    moves is the linear part, the perturbation from each level's reference, so the destination
+    holds the source's linear value plus its own reference flow."""
     lay = _amr_small()
     a = A.AmrOracle(lay)
     coef = {"rho": (1e-3, 2e-7, -3e-7, 5e-7), "rth": (0.2, -1e-5, 4e-5, 2e-5),
@@ -338,13 +342,22 @@ def test_refills_between_levels_carry_linear_fields():
         gz = oz + np.arange(nz)
         return ((gx + off) * d[0])[:, None, None], ((gy + off) * d[1])[None, :, None], ((gz + off) * d[2])[None, None, :]
 
+    U = {"mu": lay.base.u0, "mv": lay.base.v0, "mw": 0.0}
+    assert U["mu"] != 0.0
+
+    def ref_flow(o, f):
+        """rhobar_c(K) U of box o at its predicted lattice points, 0 elsewhere."""
+        rbc = np.zeros(o.shape[2])
+        rbc[1:] = 0.5 * (o.rhob[:-1] + o.rhob[1:])
+        return np.where(o.vcls == O.PRED, rbc[None, None, :] * U[f], 0.0)
+
     for m, o in enumerate(a.boxes):
         xc, yc, zc = positions(m, True)
         xl, yl, zl = positions(m, False)
         for f in ("rho", "rth"):
             a.q[m].a[f][...] = lin(f, xc, yc, zc)
         for f in ("mu", "mv", "mw"):
-            a.q[m].a[f][...] = lin(f, xl, yl, zl)
+            a.q[m].a[f][...] = lin(f, xl, yl, zl) + ref_flow(o, f)
     # refill targets start as NaN so that every one is seen written
     targets = {}
     for m, b in enumerate(lay.blocks):
@@ -352,9 +365,9 @@ def test_refills_between_levels_carry_linear_fields():
             if kind in ("fine", "coarse"):
                 for f in O.FIELDS:
                     a.q[m].a[f].ravel()[di] = np.nan
-                targets.setdefault(m, []).append((kind, sm, di))
-    assert any(k == "fine" for v in targets.values() for k, _, _ in v)
-    assert any(k == "coarse" for v in targets.values() for k, _, _ in v)
+                targets.setdefault(m, []).append((kind, sm, di, si))
+    assert any(k == "fine" for v in targets.values() for k, _, _, _ in v)
+    assert any(k == "coarse" for v in targets.values() for k, _, _, _ in v)
     for l in range(lay.levels):
         a._fill(l, a.q, ("fine", "coarse"))
     n = 0
@@ -364,7 +377,7 @@ def test_refills_between_levels_carry_linear_fields():
         xc, yc, zc = positions(m, True)
         xl, yl, zl = positions(m, False)
         shape = o.shape
-        for kind, sm, di in lst:
+        for kind, sm, di, si in lst:
             i, j, k = np.unravel_index(di, shape)
             if kind == "fine":  # restriction: the coarse ghost's own centre / lattice point
                 px, py, pz = xc[i, 0, 0], yc[0, j, 0], zc[0, 0, k]
@@ -381,9 +394,15 @@ def test_refills_between_levels_carry_linear_fields():
                 want = lin(f, px, py, pz)
                 got = a.q[m].a[f][i, j, k]
                 assert np.all(np.abs(got - want) <= 1e-13 * np.abs(want)), (kind, m, f)
+            # both ends predicted: the linear part moves, the destination adds its own reference
+            # flow; otherwise the stored value moves as it is
+            both = (o.vcls.ravel()[di] == O.PRED) & (a.boxes[sm].vcls.ravel()[si] == O.PRED)
             for f in ("mu", "mv", "mw"):
-                want = lin(f, lx, ly, lz)
+                src_ref = ref_flow(a.boxes[sm], f).ravel()[si]
+                want = lin(f, lx, ly, lz) + np.where(both, ref_flow(o, f).ravel()[di], src_ref)
                 got = a.q[m].a[f][i, j, k]
                 assert np.all(np.abs(got - want) <= 1e-13 * np.abs(want)), (kind, m, f)
+            if kind == "coarse":
+                assert both.any()
             n += len(di)
     assert n > 100

@@ -75,6 +75,31 @@ def test_uniform_shear_decays_by_rk3_factor():
     assert tau[-1] < RSP
 
 
+def test_lid_height_of_a_block_below_the_lid():
+    # a grid that ends below the domain's lid (a block of a refined grid) takes the rate from the
+    # domain's lid height: at z = zsp + f (ztop - zsp) the rate is rsp sin^2(pi f / 2), here
+    # sin^2(pi/12) = (1 - sqrt(3)/2)/2 at f = 1/6 and sin^2(pi/8) = (1 - sqrt(2)/2)/2 at f = 1/4
+    ztop = 4800.0
+    cfg = _flat(ztop=ztop)
+    o = O.Oracle(cfg).merge()
+    q0 = o.init_state()
+    pred = o.vcls == O.PRED
+    K = np.broadcast_to(np.arange(NZ)[None, None, :], o.shape)
+    q0.a["mv"][pred] = (1e-2 * (1.0 + K / NZ))[pred]
+    n = 4
+    q = o.run(q0, cfg.dt, n)
+    ratio = (q.a["mv"][pred] / q0.a["mv"][pred]).reshape(cfg.nx, cfg.ny, NZ - 1)
+    tau = {Kl: _rk3_rate(ratio[0, 0, Kl - 1] ** (1.0 / n), cfg.dt) for Kl in (18, 21)}
+    assert abs(tau[18] - RSP * (1.0 - np.sqrt(3.0) / 2.0) / 2.0) <= 1e-9 * RSP, tau
+    assert abs(tau[21] - RSP * (1.0 - np.sqrt(2.0) / 2.0) / 2.0) <= 1e-9 * RSP, tau
+    # the grid's own top as lid height is the default
+    a = O.Oracle(_flat(ztop=NZ * DZ)).merge()
+    b = O.Oracle(_flat()).merge()
+    qa, qb = a.run(a.init_state(), cfg.dt, 2), b.run(b.init_state(), cfg.dt, 2)
+    for f in O.FIELDS:
+        assert np.array_equal(qa.a[f], qb.a[f])
+
+
 def test_sponge_term_is_minus_tau_times_perturbation():
     cfg = W.get("hemi_tiny").replace(zsp=700.0, rsp=RSP)
     o = O.Oracle(cfg).merge()
