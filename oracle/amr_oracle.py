@@ -16,8 +16,14 @@ The step, in the paper's order:
     steps; in the coarse final stage that sum replaces dt x the coarse flux through the face;
   * after the level-l step, ghost cells of level l covered by level l+1 take the mean of the eight
     fine cells (momentum: the coincident fine lattice point), and ghost cells of level l+1 covered
-    by level l take the coarse cell's values (the coarse lattice point at the halved index).
-Reading (the paper leaves it open): the values moved between levels are perturbations, each from
+    by level l take the coarse field at their own position: linear interpolation between the coarse
+    cell centres (weights 3/4 and 1/4 along each axis) and between the coarse lattice points (1/2 and
+    1/2 along each axis where the fine lattice index is odd); where the coarse stencil holds a solid
+    cell, a lattice point that is not predicted, or would reach below the ground or above the lid,
+    the fine ghost takes the coarse cell's own values (the coarse lattice point at the halved index).
+Readings (the paper leaves them open): the coarse-to-fine transfer interpolates linearly (the paper
+gives the coarse value; a piecewise-constant field in the fine ghosts forces the fine level at its
+grid scale at every coarse step).  The values moved between levels are perturbations, each from
 the level's own reference: rho' and (rho theta)' from the level's base state, and at predicted
 lattice points the momentum rho u - rhobar_c(K) (u0, v0, 0) from the level's reference flow (the
 base density of a lattice level depends on the level's spacing, so moving the total rho u would put
@@ -189,6 +195,8 @@ class AmrOracle:
                     dst.a[f].ravel()[di] = src.a[f].ravel()[si]
                 if kind != "same":
                     self._momentum_reference(m, sm, dst, di, si)
+                if kind == "coarse":
+                    self._prolong(m, sm, dst, src, di, si)
 
     def _momentum_reference(self, m, sm, dst, di, si):
         """Moved momenta at predicted lattice points keep their perturbation from the reference flow
@@ -205,6 +213,62 @@ class AmrOracle:
         dr = rbc(od, kd) - rbc(os_, ks)
         for f, u in (("mu", od.cfg.u0), ("mv", od.cfg.v0)):
             dst.a[f].ravel()[di[pred]] += dr * u
+
+    def _prolong(self, m, sm, dst, src, di, si):
+        """Linear interpolation of the coarse fields to the fine ghost cells (centres) and lattice
+        points di of block m from the coarse box sm (parents at si); entries whose stencil fails keep
+        the parent's values already written."""
+        od, os_ = self.boxes[m], self.boxes[sm]
+        nx, ny, nz = od.shape
+        i, j, k = np.unravel_index(di, od.shape)
+        ox, oy, oz = self.org[m]
+        N = self.N[self.blocks[m].level]
+        par = [np.mod(ox + i, N[0]) & 1, np.mod(oy + j, N[1]) & 1, (oz + k) & 1]
+        sny, snz = os_.shape[1], os_.shape[2]
+        st = (sny * snz, snz, 1)
+        ks = si % snz
+        # scalars: the fine centre lies a quarter of a coarse cell from the parent's centre, towards
+        # the neighbour on the child's side (upper for an odd fine index)
+        sg = [np.where(p == 1, 1, -1) for p in par]
+        zin = (ks + sg[2] >= 0) & (ks + sg[2] < snz)
+        ok = np.ones(len(di), dtype=bool)
+        acc = {f: np.zeros(len(di)) for f in ("rho", "rth")}
+        V = os_.V.ravel()
+        for c in range(8):
+            a, b, e = c >> 2, (c >> 1) & 1, c & 1
+            p = si + a * sg[0] * st[0] + b * sg[1] * st[1] + e * np.where(zin, sg[2], 0)
+            w = (0.75 if a == 0 else 0.25) * (0.75 if b == 0 else 0.25) * np.where(zin, 0.75 if e == 0 else 0.25, 0.5)
+            ok &= V[p] > 0.0
+            for f in acc:
+                acc[f] += w * src.a[f].ravel()[p]
+        for f in acc:
+            dst.a[f].ravel()[di[ok]] = acc[f][ok]
+        # momentum: average of the coarse lattice points around the fine one (odd fine index: the
+        # point at the halved index and the next one), as perturbations from each level's reference
+        zup = (par[2] == 1) & (ks + 1 < snz)
+        odd = [par[0] == 1, par[1] == 1, zup]
+        pred_s = os_.vcls.ravel() == O.PRED
+        okm = od.vcls.ravel()[di] == O.PRED
+        pts = []
+        for c in range(8):
+            a, b, e = c >> 2, (c >> 1) & 1, c & 1
+            use = (odd[0] | (a == 0)) & (odd[1] | (b == 0)) & (odd[2] | (e == 0))
+            p = si + a * st[0] + b * st[1] + e
+            p = np.where(use, p, si)
+            okm &= ~use | pred_s[p]
+            pts.append((use, p))
+        n = (1 + odd[0]) * (1 + odd[1]) * (1 + odd[2])
+
+        def rbc(o, kk):
+            return 0.5 * (o.rhob[np.maximum(kk - 1, 0)] + o.rhob[kk])
+
+        kd = di % nz
+        for f, u in (("mu", od.cfg.u0), ("mv", od.cfg.v0), ("mw", 0.0)):
+            s = np.zeros(len(di))
+            for use, p in pts:
+                s += np.where(use, src.a[f].ravel()[p] - rbc(os_, p % snz) * u, 0.0)
+            val = s / n + rbc(od, kd) * u
+            dst.a[f].ravel()[di[okm]] = val[okm]
 
     def sync(self):
         for l in range(self.nl):

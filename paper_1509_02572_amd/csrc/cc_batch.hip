@@ -32,7 +32,11 @@ namespace cc {
 
 // ghost-cell refill: destination block / box index, source block / box index (block numbers
 // within their levels)
-struct GhostEnt { int32_t dblk, didx, sblk, sidx; };
+struct GhostEnt { int32_t dblk, didx, sblk, sidx, par = 0; };  // par: injection's fine-index parities
+// an injection entry's destination index carries the parities (x, y, z in bits 0-2) of the fine
+// cell's global index above bit GHOST_PAR_SHIFT (block boxes hold fewer than 2^28 slots)
+constexpr int GHOST_PAR_SHIFT = 28;
+constexpr int32_t GHOST_IDX_MASK = (1 << GHOST_PAR_SHIFT) - 1;
 // on the device the refill lists are packed by (destination, source) block pair: chunks of at most
 // 64 entries of one pair (one wavefront each, so the pair's descriptors are read once per wave), and
 // the entries' destination and source box indices
@@ -93,7 +97,8 @@ __global__ void __launch_bounds__(256) k_ghost_fill(const BlockDesc<T> *__restri
     const GhostPair g = pr[first + lane];
     const BlockDesc<T> &D = dd[dblk], &S = sd[sblk];
     const SOut<T> qd = D.q[rd], qs = S.q[rs];
-    const int64_t di = g.didx, si = g.sidx;
+    const int64_t di = g.didx & GHOST_IDX_MASK, si = g.sidx;
+    const unsigned par = (unsigned)g.didx >> GHOST_PAR_SHIFT;
     if (mode == FILL_RESTRICT) {
         const int64_t sx = (int64_t)S.d.ny * S.d.nzs, sy = S.d.nzs;
         double v[2];
@@ -119,6 +124,48 @@ __global__ void __launch_bounds__(256) k_ghost_fill(const BlockDesc<T> *__restri
         const double dr = D.P.rhobc[kd] - S.P.rhobc[ks];
         mu = (T)((double)mu + dr * S.P.u0);
         mv = (T)((double)mv + dr * S.P.v0);
+    }
+    if (mode == FILL_INJECT) {
+        // the coarse field at the fine ghost's own position, where the coarse stencil allows
+        const int64_t sx = (int64_t)S.d.ny * S.d.nzs, sy = S.d.nzs;
+        const int ks = (int)(si % S.d.nzs);
+        // scalars: a quarter cell from the parent's centre towards the child's side (weights 3/4, 1/4)
+        const int64_t ox = (par & 1) ? sx : -sx, oy = (par & 2) ? sy : -sy, oz = (par & 4) ? 1 : -1;
+        const bool zin = ks + oz >= 0 && ks + oz < S.d.nz;
+        double a0 = 0.0, a1 = 0.0;
+        bool ok = true;
+        for (int c = 0; c < 8; ++c) {
+            const int a = c >> 2, b = (c >> 1) & 1, e = c & 1;
+            const int64_t p = si + a * ox + b * oy + (zin ? e * oz : 0);
+            const double w = ((a ? 0.25 : 0.75) * (b ? 0.25 : 0.75)) * (zin ? (e ? 0.25 : 0.75) : 0.5);
+            ok = ok && S.G.V[p] > 0.0;
+            a0 += w * get_scalar(qs, p, 0);
+            a1 += w * get_scalar(qs, p, 1);
+        }
+        if (ok) put_scalar(qd, di, a0, a1);
+        // momentum: the mean of the coarse lattice points around the fine one (the point at the halved
+        // index, and the next one along every axis where the fine index is odd), as perturbations
+        const bool oddx = par & 1, oddy = par & 2, oddz = (par & 4) && ks + 1 < S.d.nz;
+        bool okm = D.G.vcls[di] == CC_PRED;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        int n = 0;
+        for (int c = 0; c < 8; ++c) {
+            const int a = c >> 2, b = (c >> 1) & 1, e = c & 1;
+            if ((a && !oddx) || (b && !oddy) || (e && !oddz)) continue;
+            const int64_t p = si + a * sx + b * sy + e;
+            okm = okm && S.G.vcls[p] == CC_PRED;
+            const double ref = sizeof(T) == 8 ? S.P.rhobc[ks + e] : 0.0;  // FP64 stores the total
+            s0 += (double)qs.mu[p] - ref * S.P.u0;
+            s1 += (double)qs.mv[p] - ref * S.P.v0;
+            s2 += (double)qs.mw[p];
+            ++n;
+        }
+        if (okm) {
+            const double rd = sizeof(T) == 8 ? D.P.rhobc[(int)(di % D.d.nzs)] : 0.0;
+            mu = (T)(s0 / n + rd * S.P.u0);
+            mv = (T)(s1 / n + rd * S.P.v0);
+            mw = (T)(s2 / n);
+        }
     }
     qd.mu[di] = mu;
     qd.mv[di] = mv;
@@ -497,6 +544,11 @@ bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, co
     int nl = 0;
     for (int m = 0; m < n; ++m) {
         if (B[m].level < 0 || B[m].level > 12) { set_error("%s: block %d has level %d", what, m, B[m].level); return false; }
+        if ((int64_t)B[m].grid.nx * B[m].grid.ny * B[m].grid.nzs > GHOST_IDX_MASK) {
+            set_error("%s: block %d: a box of %lld slots exceeds the 2^28 of a refill entry", what, m,
+                      (long long)B[m].grid.nx * B[m].grid.ny * B[m].grid.nzs);
+            return false;
+        }
         nl = std::max(nl, B[m].level + 1);
     }
     t.members.assign(nl, {});
@@ -601,7 +653,8 @@ bool build_tables(const cc_block *B, int n, const int32_t dom0[3], Tables &t, co
                             int64_t gc[3] = {g[0] >> 1, g[1] >> 1, g[2] >> 1};
                             int oc = om[l - 1].at(gc[0], gc[1], gc[2]);
                             if (oc >= 0) {
-                                t.inj[l].push_back({t.local[m], didx, oc, box_index(t.members[l - 1][oc], l - 1, gc)});
+                                const int32_t par = (int32_t)((g[0] & 1) | ((g[1] & 1) << 1) | ((g[2] & 1) << 2));
+                                t.inj[l].push_back({t.local[m], didx, oc, box_index(t.members[l - 1][oc], l - 1, gc), par});
                                 grow(m, i, j, k);
                                 mark(i, j, k);
                                 continue;
@@ -812,7 +865,7 @@ static Packed pack(const std::vector<GhostEnt> &v, size_t nfirst)
             size_t z = a;
             while (z < e.size() && z - a < (size_t)FILL_CHUNK && e[z].dblk == e[a].dblk && e[z].sblk == e[a].sblk) ++z;
             p.chunks.push_back({e[a].dblk, e[a].sblk, (int32_t)p.pairs.size(), (int32_t)(z - a)});
-            for (size_t q = a; q < z; ++q) p.pairs.push_back({e[q].didx, e[q].sidx});
+            for (size_t q = a; q < z; ++q) p.pairs.push_back({e[q].didx | (e[q].par << GHOST_PAR_SHIFT), e[q].sidx});
             a = z;
         }
     };

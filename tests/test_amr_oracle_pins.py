@@ -80,5 +80,5 @@ def test_flux_matching_conserves_mass(match):
     drift = max(abs(m1[0] - m0[0]), abs(m1[1] - m0[1]) / 300.0) / m0[2]
     if match:
         assert drift <= 1e-12, drift
-    else:
-        assert drift > 1e-9, drift
+    else:  # a hundred times the matched bound
+        assert drift > 1e-10, drift
