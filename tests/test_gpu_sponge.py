@@ -103,8 +103,23 @@ def test_f32_with_sponge_after_100_steps():
     assert abs(r1[0] - r0[0]) <= 1e-12 * r0[2]
 
 
-def test_batch_refuses_sponge():
+def test_batch_runs_the_sponge():
     cfg = CASES["hemi_tiny_700"]()
+    print("case batch sponge", flush=True)
+    # a batch of one member runs the sponge (and diffusion) in flux form over the whole grid: the
+    # same terms as the single grid up to rounding order (bar: 1e-12 of each field's total magnitude)
     dom = CC.Domain(cfg, "f64", side_stream=False)
-    with pytest.raises(RuntimeError, match="single grids"):
-        CC.Batch([dom], [dom.init_state()])
+    q0 = dom.init_state(W.theta_noise(cfg.replace(noise_sigma=0.5, seed=9)))
+    batch = CC.Batch([dom], [q0])
+    batch.step(cfg.dt, 4)
+    torch.cuda.synchronize()
+    ref = dom.state_numpy(dom.run(q0, cfg.dt, 4))
+    got = dom.state_numpy(batch.current()[0])
+    nz = cfg.nz
+    mom = max(np.abs(ref[f]).max() for f in ("mu", "mv", "mw"))
+    base = {"rho": dom.base[:nz].abs().max().item(), "rth": dom.base[nz:2 * nz].abs().max().item()}
+    for f in CC.FIELDS:
+        scale = np.abs(ref[f]).max() + base[f] if f in base else mom
+        assert np.abs(got[f] - ref[f]).max() <= 1e-12 * scale, f
+    assert not batch.check()[:5].any()
+    batch.close()
