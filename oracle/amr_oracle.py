@@ -20,7 +20,9 @@ The step, in the paper's order:
     cell centres (weights 3/4 and 1/4 along each axis) and between the coarse lattice points (1/2 and
     1/2 along each axis where the fine lattice index is odd); where the coarse stencil holds a solid
     cell, a lattice point that is not predicted, or would reach below the ground or above the lid,
-    the fine ghost takes the coarse cell's own values (the coarse lattice point at the halved index).
+    the fine ghost takes the coarse cell's own values (the coarse lattice point at the halved index;
+    for an odd fine lattice level over a coarse level that is not predicted, as at the ground, the
+    coarse level above it, so that a predicted fine point never takes a diagnosed ground value).
 Readings (the paper leaves them open): the coarse-to-fine transfer interpolates linearly (the paper
 gives the coarse value; a piecewise-constant field in the fine ghosts forces the fine level at its
 grid scale at every coarse step).  The values moved between levels are perturbations, each from
@@ -246,23 +248,33 @@ class AmrOracle:
         # momentum: average of the coarse lattice points around the fine one (odd fine index: the
         # point at the halved index and the next one), as perturbations from each level's reference
         zup = (par[2] == 1) & (ks + 1 < snz)
-        odd = [par[0] == 1, par[1] == 1, zup]
         pred_s = os_.vcls.ravel() == O.PRED
-        okm = od.vcls.ravel()[di] == O.PRED
-        pts = []
-        for c in range(8):
-            a, b, e = c >> 2, (c >> 1) & 1, c & 1
-            use = (odd[0] | (a == 0)) & (odd[1] | (b == 0)) & (odd[2] | (e == 0))
-            p = si + a * st[0] + b * st[1] + e
-            p = np.where(use, p, si)
-            okm &= ~use | pred_s[p]
-            pts.append((use, p))
-        n = (1 + odd[0]) * (1 + odd[1]) * (1 + odd[2])
+        pred_d = od.vcls.ravel()[di] == O.PRED
+        # an odd fine level above a coarse level whose point is not predicted (the ground) takes the
+        # coarse level above it alone
+        shift = zup & ~pred_s[si] & pred_s[np.minimum(si + 1, len(pred_s) - 1)]
+        base = si + shift
+        odd = [par[0] == 1, par[1] == 1, zup & ~shift]
 
         def rbc(o, kk):
             return 0.5 * (o.rhob[np.maximum(kk - 1, 0)] + o.rhob[kk])
 
         kd = di % nz
+        if shift.any():  # the fallback of a shifted point: the coarse point above, as a perturbation
+            sh = shift & pred_d
+            for f, u in (("mu", od.cfg.u0), ("mv", od.cfg.v0), ("mw", 0.0)):
+                v = src.a[f].ravel()[base] - rbc(os_, base % snz) * u + rbc(od, kd) * u
+                dst.a[f].ravel()[di[sh]] = v[sh]
+        okm = pred_d.copy()
+        pts = []
+        for c in range(8):
+            a, b, e = c >> 2, (c >> 1) & 1, c & 1
+            use = (odd[0] | (a == 0)) & (odd[1] | (b == 0)) & (odd[2] | (e == 0))
+            p = base + a * st[0] + b * st[1] + e
+            p = np.where(use, p, base)
+            okm &= ~use | pred_s[p]
+            pts.append((use, p))
+        n = (1 + odd[0]) * (1 + odd[1]) * (1 + odd[2])
         for f, u in (("mu", od.cfg.u0), ("mv", od.cfg.v0), ("mw", 0.0)):
             s = np.zeros(len(di))
             for use, p in pts:

@@ -144,24 +144,36 @@ __global__ void __launch_bounds__(256) k_ghost_fill(const BlockDesc<T> *__restri
         }
         if (ok) put_scalar(qd, di, a0, a1);
         // momentum: the mean of the coarse lattice points around the fine one (the point at the halved
-        // index, and the next one along every axis where the fine index is odd), as perturbations
-        const bool oddx = par & 1, oddy = par & 2, oddz = (par & 4) && ks + 1 < S.d.nz;
-        bool okm = D.G.vcls[di] == CC_PRED;
+        // index, and the next one along every axis where the fine index is odd), as perturbations; an
+        // odd fine level over a coarse level that is not predicted (the ground) takes the level above
+        const bool zup = (par & 4) && ks + 1 < S.d.nz;
+        const bool predd = D.G.vcls[di] == CC_PRED;
+        const bool shift = zup && S.G.vcls[si] != CC_PRED && S.G.vcls[si + 1] == CC_PRED;
+        const int64_t base = si + (shift ? 1 : 0);
+        const int kb = ks + (shift ? 1 : 0);
+        const double rd = sizeof(T) == 8 ? D.P.rhobc[(int)(di % D.d.nzs)] : 0.0;
+        if (shift && predd) {  // the fallback: the coarse point above, as a perturbation
+            const double rb = sizeof(T) == 8 ? S.P.rhobc[kb] : 0.0;
+            mu = (T)((double)qs.mu[base] - rb * S.P.u0 + rd * S.P.u0);
+            mv = (T)((double)qs.mv[base] - rb * S.P.v0 + rd * S.P.v0);
+            mw = qs.mw[base];
+        }
+        const bool oddx = par & 1, oddy = par & 2, oddz = zup && !shift;
+        bool okm = predd;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         int n = 0;
         for (int c = 0; c < 8; ++c) {
             const int a = c >> 2, b = (c >> 1) & 1, e = c & 1;
             if ((a && !oddx) || (b && !oddy) || (e && !oddz)) continue;
-            const int64_t p = si + a * sx + b * sy + e;
+            const int64_t p = base + a * sx + b * sy + e;
             okm = okm && S.G.vcls[p] == CC_PRED;
-            const double ref = sizeof(T) == 8 ? S.P.rhobc[ks + e] : 0.0;  // FP64 stores the total
+            const double ref = sizeof(T) == 8 ? S.P.rhobc[kb + e] : 0.0;  // FP64 stores the total
             s0 += (double)qs.mu[p] - ref * S.P.u0;
             s1 += (double)qs.mv[p] - ref * S.P.v0;
             s2 += (double)qs.mw[p];
             ++n;
         }
         if (okm) {
-            const double rd = sizeof(T) == 8 ? D.P.rhobc[(int)(di % D.d.nzs)] : 0.0;
             mu = (T)(s0 / n + rd * S.P.u0);
             mv = (T)(s1 / n + rd * S.P.v0);
             mw = (T)(s2 / n);
