@@ -82,3 +82,33 @@ def test_flux_matching_conserves_mass(match):
         assert drift <= 1e-12, drift
     else:  # a hundred times the matched bound
         assert drift > 1e-10, drift
+
+
+def test_uniform_flow_over_flat_ground_stays_uniform_across_levels():
+    """Uniform inflow over flat ground is a steady state of every level on its own, so the transfers
+    between levels must keep it: two steps of a two-level layout whose fine bricks sit on the ground
+    (coarse-fine faces reaching down to it) leave w at zero and u at the inflow in every own cell, to
+    well below the size of a transfer error: w within 1e-4 m/s and u, v within 1e-5 of the inflow
+    (the diagnosed boundary rows of the two levels leave a residual of a few 1e-6 m/s; a fine lattice
+    level 1 filled from the coarse ground row, which holds diagnosed velocities instead of momentum,
+    gave 0.1 m/s within two steps)."""
+    base = W.Config("flat2", 16, 16, 16, 200.0, 200.0, 200.0, W.Hill("flat"), dt=0.2, u0=10.0, v0=2.0)
+    # level 0: bricks of 8 cells; the brick at the origin replaced by eight level-1 bricks, so
+    # coarse-fine faces run up from the ground on four sides
+    blocks = [W.AmrBlock(0, (8 * x, 8 * y, 8 * z), (8, 8, 8)) for x in range(2) for y in range(2) for z in range(2)
+              if (x, y, z) != (0, 0, 0)]
+    blocks += [W.AmrBlock(1, (8 * x, 8 * y, 8 * z), (8, 8, 8)) for x in range(2) for y in range(2) for z in range(2)]
+    lay = W.AmrLayout(base, 2, 8, 6, [], blocks)
+    a = A.AmrOracle(lay)
+    a.step(2)
+    for m, b in enumerate(lay.blocks):
+        own = a.own_cells(m)
+        o = a.boxes[m]
+        (i0, j0, k0), (i1, j1, k1) = a.own[m]
+        pred = (o.vcls == O.PRED)[i0:i1, j0:j1, k0:k1]
+        rbc = np.zeros(o.shape[2])
+        rbc[1:] = 0.5 * (o.rhob[:-1] + o.rhob[1:])
+        rbc = rbc[None, None, k0:k1]
+        assert np.abs(own["mw"][pred]).max() <= 1e-4, (m, b.level)
+        assert np.abs((own["mu"] - rbc * base.u0)[pred]).max() <= 1e-5 * base.u0, (m, b.level)
+        assert np.abs((own["mv"] - rbc * base.v0)[pred]).max() <= 1e-5 * base.u0, (m, b.level)
