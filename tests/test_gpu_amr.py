@@ -126,6 +126,28 @@ def test_three_levels_with_diffusion_against_oracle():
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_uniform_flow_over_flat_ground_stays_uniform(prec):
+    # every level keeps uniform inflow over flat ground on its own; the transfers between levels must
+    # too, where the fine bricks stand on the ground (coarse-fine faces reaching down to it)
+    base = W.Config("flat2", 16, 16, 16, 200.0, 200.0, 200.0, W.Hill("flat"), dt=0.2, u0=10.0, v0=2.0)
+    blocks = [W.AmrBlock(0, (8 * x, 8 * y, 8 * z), (8, 8, 8)) for x in range(2) for y in range(2) for z in range(2)
+              if (x, y, z) != (0, 0, 0)]
+    blocks += [W.AmrBlock(1, (8 * x, 8 * y, 8 * z), (8, 8, 8)) for x in range(2) for y in range(2) for z in range(2)]
+    lay = W.AmrLayout(base, 2, 8, 6, [], blocks)
+    print("case flat two levels", prec, flush=True)
+    h = CC.Hierarchy(lay, prec)
+    h.step(2)
+    torch.cuda.synchronize()
+    for m, (b, qb) in enumerate(zip(lay.blocks, h.current())):
+        d = h.doms[m]
+        (i0, j0, k0), (i1, j1, k1) = h.own[m]
+        own = h.own_cells(m, qb)
+        pred = (d.unpad(d.g["vcls"]) == O.PRED)[i0:i1, j0:j1, k0:k1]
+        assert np.abs(own["mw"][pred]).max() <= 1e-4, (m, b.level)
+    assert not h.check()[:6].any()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_three_levels_conserve_mass(prec):
     lay = small_layout()
     print("case mass", prec, flush=True)
