@@ -112,3 +112,22 @@ def test_stage_workspace_layout(lib):
         g = CC.cc_grid(nx, ny, nz, nzs, 100.0, 100.0, 50.0, 16, 0)
         for prec, esz in ((CC.CC_F64, 8), (CC.CC_F32_PERT, 4)):
             assert L.cutcell_stage_workspace_bytes(ctypes.byref(g), prec) == expected(nx, ny, nz, nzs, esz)
+
+
+def test_hierarchy_block_checks_on_host(lib):
+    """A block's lid height (for the sponge) below its own top is refused, and so is a block box too
+    large for the refill entries (2^28 slots)."""
+    from paper_1509_02572_amd import cutcell as CC
+    from paper_1509_02572_amd import workloads as W
+    base = W.Config("amr_test", 16, 16, 24, 200.0, 200.0, 200.0, W.Hill("hemisphere", 0.0, 600.0), dt=0.2)
+    lay = W.amr_layout(base, levels=3, brick=8, ghost=6, d_fine=300.0, band=400.0, seed=1)
+    dom0 = (base.nx, base.ny, base.nz)
+    blocks = _fake_blocks(CC, lay)
+    blocks[0].phys.zsp, blocks[0].phys.rsp, blocks[0].phys.ztop = 100.0, 0.01, 1.0
+    with pytest.raises(RuntimeError, match="lid height"):
+        CC.amr_hierarchy_workspace_bytes(blocks, CC.CC_F64, dom0)
+    blocks = _fake_blocks(CC, lay)
+    g = blocks[0].grid
+    g.nx, g.ny, g.nz, g.nzs = 1024, 1024, 300, 304  # 2^28 and more slots in one box
+    with pytest.raises(RuntimeError, match="2\\^28"):
+        CC.amr_hierarchy_workspace_bytes(blocks, CC.CC_F64, dom0)
