@@ -89,7 +89,9 @@ def test_uniform_flow_over_flat_ground_stays_uniform_across_levels():
     between levels must keep it: two steps of a two-level layout whose fine bricks sit on the ground
     (coarse-fine faces reaching down to it) leave w at zero and u at the inflow in every own cell, to
     well below the size of a transfer error: w within 1e-4 m/s and u, v within 1e-5 of the inflow
-    (the diagnosed boundary rows of the two levels leave a residual of a few 1e-6 m/s; a fine lattice
+    (the flux matching leaves a residual of a few 1e-6 m/s: the fine base density at the fine cell
+    centres differs from the coarse one at second order, so the matched face flux of uniform flow
+    differs from the coarse one by that much; a fine lattice
     level 1 filled from the coarse ground row, which holds diagnosed velocities instead of momentum,
     gave 0.1 m/s within two steps)."""
     base = W.Config("flat2", 16, 16, 16, 200.0, 200.0, 200.0, W.Hill("flat"), dt=0.2, u0=10.0, v0=2.0)
