@@ -320,14 +320,21 @@ cc_status cutcell_reduce_noalloc(const cc_grid *grid, const cc_phys *phys, const
  *    grid.z0).  Own cells of one level do not overlap; own cells of all levels tile the domain
  *    except buried regions; a coarse cell's eight children lie in one fine block.  Ghost cells are
  *    integrated on like own cells and refilled: after every stage from same-level blocks (copy);
- *    after every level-l step, level-l ghosts owned by level l+1 get the eight-point average and
- *    level-(l+1) ghosts owned by level l get the coarse value (momentum keeps its total value
- *    across levels, scalars their perturbation from each level's base state).  A level-l step
- *    follows two level-(l+1) steps (fine first).  Flux matching: the fine fluxes through a
- *    coarse-fine face, summed over the two fine final stages (x dt_fine), replace dt x the coarse
- *    flux in the coarse final stage, which conserves mass exactly.  The ghost width must cover the
- *    stages between refills and the diagnostic reach (6 cells: 2 fine steps x 3 stages); coarse-fine
- *    interfaces must stay clear of cut and merged cells (counted into dev_status[5] otherwise).
+ *    after every level-l step, level-l ghosts owned by level l+1 get the eight-point average (momentum:
+ *    the coincident fine lattice point) and level-(l+1) ghosts owned by level l get the coarse field
+ *    interpolated linearly to their own centre and lattice point (the parent's values where the
+ *    coarse stencil meets terrain, the ground or the lid; an odd fine lattice level over a coarse
+ *    level that is not predicted takes the coarse level above).  Values cross levels as
+ *    perturbations from each level's reference: the scalars from its base state, the momentum at
+ *    predicted points from its reference flow rhobar_c(K) (u0, v0, 0).  A level-l step follows two
+ *    level-(l+1) steps (fine first).  Flux matching: the fine advective fluxes through a coarse-fine
+ *    face, summed over the two fine final stages (x dt_fine), replace dt x the coarse flux in the
+ *    coarse final stage, which conserves mass exactly (the diffusive fluxes are not matched).  The
+ *    ghost width must cover the stages between refills and the diagnostic reach (6 cells: 2 fine
+ *    steps x 3 stages; 12 with the artificial diffusion, whose stencil reaches two cells); a block
+ *    box holds fewer than 2^28 slots; coarse-fine interfaces must stay clear of cut and merged cells
+ *    (counted into dev_status[5] otherwise).  Diffusion and sponge act on every block (the sponge
+ *    from the domain's lid height, cc_phys.ztop).
  * ------------------------------------------------------------------------------------------- */
 typedef struct {
     cc_grid grid;
