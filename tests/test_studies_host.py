@@ -168,3 +168,17 @@ def test_regions_of_the_level_two_layout():
     n = S.diff_norms(np.array([1.0, 2.0, 3.0]), np.array([1.0, 1.0, 1.0]), np.array([0, 2, 2]))
     assert n["L0"]["rms"] == 0.0 and n["L2"]["max"] == 2.0 and "L1" not in n
     assert math.isclose(n["all"]["rms"], math.sqrt(5.0 / 3.0))
+
+
+def test_block_boxes_stop_at_ground_and_lid():
+    # with 12 ghost layers a 20-cell cube above the ground has 12 below it, the bottom cubes none, and
+    # no box reaches above the lid; laterally the ghost layers wrap periodically
+    lay = W.cbcm_hemisphere(3, ghost=12)
+    for b in lay.blocks:
+        org, size, gb, gt = lay.box(b)
+        nzl = lay.base.nz << b.level
+        assert gb == min(12, b.org[2]) and gt == min(12, nzl - b.org[2] - b.size[2])
+        assert org[2] >= 0 and org[2] + size[2] <= nzl
+        assert org[0] == b.org[0] - 12 and size[0] == b.size[0] + 24
+        c = lay.block_config(b)
+        assert c.z0 == org[2] * c.dz and c.ztop == lay.base.nz * lay.base.dz
